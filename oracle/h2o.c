@@ -1,0 +1,1241 @@
+/*
+ * h2o.c -- plain FP64 CPU oracle for the data-driven H^2 construction of
+ * Cai, Huang, Chow and Xi, "Data-Driven Construction of Hierarchical
+ * Matrices with Nested Bases" (arXiv 2206.01885).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or helper with the GPU library.
+ *
+ * Every step follows the paper in the paper's order:
+ *   - adaptive 2^d partition tree .............. Section 2.1
+ *   - admissibility, interaction / near lists .. Section 2.1, Eq. (separation)
+ *   - volume-based DataReduct .................. Section 3.3
+ *   - HiDR bottom-up / top-down ................ Section 3.1, Algorithm 1
+ *   - r1, r2 from the tolerance ................ Section 4.2, Algorithm 2 step 2
+ *   - getBasis as an interpolative decomposition Section 4.1, Eqs. (SRRQR1-2)
+ *   - nested bases, transfer and coupling blocks Section 2.1, Algorithm 2
+ *   - H^2 matrix-vector product ................ Section 2.1 (O(n) apply)
+ *   - dense reference K x ...................... Section 2 (definition of K)
+ *
+ * Where the paper is silent, the reading taken is stated next to the code
+ * (root box, tie rules, grid placement, rank rule, calibration set-up).
+ *
+ * All arithmetic is IEEE double, compiled with -ffp-contract=off; sums run
+ * sequentially in index order.  OpenMP parallelises over independent nodes of
+ * one tree level only, so results do not depend on the thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define H2O_MAXDEPTH 48 /* guard for coincident points (paper silent) */
+
+enum { K_COULOMB = 0, K_GAUSSIAN = 1, K_EXPONENTIAL = 2, K_MATERN32 = 3 };
+
+/* ------------------------------------------------------------------ */
+/* growable int list                                                   */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int *v;
+    int n, cap;
+} ilist;
+
+static void il_push(ilist *a, int x)
+{
+    if (a->n == a->cap) {
+        a->cap = a->cap ? 2 * a->cap : 8;
+        a->v = (int *)realloc(a->v, sizeof(int) * (size_t)a->cap);
+    }
+    a->v[a->n++] = x;
+}
+static void il_free(ilist *a)
+{
+    free(a->v);
+    a->v = NULL;
+    a->n = a->cap = 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* kernel functions (Section 2; Table 1)                               */
+/* ------------------------------------------------------------------ */
+/* kappa(x,y) for the supported kernels; prm[0] is the bandwidth h or the
+ * length scale l.  Coulomb 1/|x-y| with kappa(x,x)=0 (Table 1 caption);
+ * Gaussian exp(-|x-y|^2/h^2) (bandwidth form of Section 6.1.3);
+ * exponential exp(-|x-y|/l) (the Laplace kernel of Section 2);
+ * Matern-3/2 (1+sqrt(3) r/l) exp(-sqrt(3) r/l) (standard definition). */
+double h2o_kappa(int kid, const double *prm, const double *x, const double *y, int d)
+{
+    double r2 = 0.0;
+    for (int k = 0; k < d; ++k) {
+        double t = x[k] - y[k];
+        r2 = r2 + t * t;
+    }
+    switch (kid) {
+    case K_COULOMB:
+        return r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;
+    case K_GAUSSIAN:
+        return exp(-r2 / (prm[0] * prm[0]));
+    case K_EXPONENTIAL:
+        return exp(-sqrt(r2) / prm[0]);
+    case K_MATERN32: {
+        double t = sqrt(3.0) * sqrt(r2) / prm[0];
+        return (1.0 + t) * exp(-t);
+    }
+    default:
+        return NAN;
+    }
+}
+
+/* A[i*s + j] = kappa(X_i, Y_j) for X (m x d) and Y (s x d), both row-major. */
+void h2o_kernel_matrix(int kid, const double *prm, int d, const double *X, int m,
+                       const double *Y, int s, double *A)
+{
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < s; ++j)
+            A[(size_t)i * s + j] = h2o_kappa(kid, prm, X + (size_t)i * d, Y + (size_t)j * d, d);
+}
+
+/* ------------------------------------------------------------------ */
+/* volume-based DataReduct (Section 3.3)                               */
+/* ------------------------------------------------------------------ */
+/* DataReduct(X, k) -> X*: X is given as `L` indices into the point array
+ * `pts` ([npts][d]).  Reading of the silent details:
+ *  - |X| <= k: X is returned unchanged (keeps every point);
+ *  - Q is the tensor grid of cell centres of a g^d grid over the bounding box
+ *    of X, g the largest integer with g^d <= k, dimension 0 varying fastest;
+ *  - for each q in grid order the point of X with the smallest squared
+ *    distance is taken, ties going to the earliest position in X;
+ *  - X* lists the distinct picks in grid order of first occurrence.
+ * Writes the selected indices to out (capacity >= min(L,k)); returns |X*|. */
+int h2o_datareduct(int d, const double *pts, const int *list, int L, int k, int *out)
+{
+    if (L <= k) {
+        for (int p = 0; p < L; ++p)
+            out[p] = list[p];
+        return L;
+    }
+    double lo[3], hi[3];
+    for (int a = 0; a < d; ++a) {
+        lo[a] = pts[(size_t)list[0] * d + a];
+        hi[a] = lo[a];
+    }
+    for (int p = 1; p < L; ++p)
+        for (int a = 0; a < d; ++a) {
+            double v = pts[(size_t)list[p] * d + a];
+            if (v < lo[a]) lo[a] = v;
+            if (v > hi[a]) hi[a] = v;
+        }
+    int g = 1;
+    for (;;) {
+        long long nx = 1;
+        for (int a = 0; a < d; ++a)
+            nx *= (long long)(g + 1);
+        if (nx > k) break;
+        ++g;
+    }
+    int nq = 1;
+    for (int a = 0; a < d; ++a)
+        nq *= g;
+    int *pick = (int *)malloc(sizeof(int) * (size_t)nq);
+    for (int t = 0; t < nq; ++t) {
+        double q[3];
+        int rem = t;
+        for (int a = 0; a < d; ++a) {
+            int ta = rem % g;
+            rem /= g;
+            double w = (double)(2 * ta + 1) / (double)(2 * g);
+            q[a] = lo[a] + (hi[a] - lo[a]) * w;
+        }
+        int best = 0;
+        double bd = INFINITY;
+        for (int p = 0; p < L; ++p) {
+            double dd = 0.0;
+            for (int a = 0; a < d; ++a) {
+                double e = q[a] - pts[(size_t)list[p] * d + a];
+                dd = dd + e * e;
+            }
+            if (dd < bd) {
+                bd = dd;
+                best = p;
+            }
+        }
+        pick[t] = best;
+    }
+    int cnt = 0;
+    for (int t = 0; t < nq; ++t) {
+        int dup = 0;
+        for (int u = 0; u < t; ++u)
+            if (pick[u] == pick[t]) {
+                dup = 1;
+                break;
+            }
+        if (!dup) out[cnt++] = list[pick[t]];
+    }
+    free(pick);
+    return cnt;
+}
+
+/* ------------------------------------------------------------------ */
+/* getBasis: interpolative decomposition by column-pivoted QR          */
+/* (Section 4.1, Eqs. SRRQR1-2)                                        */
+/* ------------------------------------------------------------------ */
+/* The rows of A (m x s, row-major) are the points of a node, the columns its
+ * farfield representor points.  Householder QR with column pivoting is run
+ * on M = A^T (s x m); the leading k pivoted columns of M are the skeleton
+ * rows of A, and with M P = Q [R11 R12; 0 R22] the interpolation matrix is
+ * T = R11^{-1} R12, so that A(rest,:) ~ T^T A(skel,:) and U = P [I; T^T].
+ *
+ * Pivot rule: the lowest index c with nu_c >= (1 - 2^-40) max nu, so that
+ * exact ties (lattice data) resolve to the same column everywhere.
+ * Column norms are down-dated with the safeguard of Drmac and Bujanovic
+ * (LAPACK Working Note 176): recompute whenever the down-dated value has
+ * lost about half of its digits.
+ * Rank rule (paper silent): stop before step j when |R_jj| <= tol |R_00|, or
+ * when j = min(s, m); if A is zero, k = 0.
+ *
+ * Outputs: piv (m entries, a permutation of 0..m-1; the first k are the
+ * skeleton rows, in pivot order), T (k x (m-k), T[t*(m-k)+u] couples
+ * skeleton t with non-skeleton row piv[k+u]), absRdiag (k entries, |R_jj|).
+ * Returns k. */
+int h2o_cpqr_id(const double *A, int m, int s, double tol, int *piv, double *T, double *absRdiag)
+{
+    for (int c = 0; c < m; ++c)
+        piv[c] = c;
+    if (m <= 0 || s <= 0) return 0;
+    /* M column-major: column c = row c of A, length s */
+    double *M = (double *)malloc(sizeof(double) * (size_t)m * s);
+    for (int c = 0; c < m; ++c)
+        for (int r = 0; r < s; ++r)
+            M[(size_t)c * s + r] = A[(size_t)c * s + r];
+    double *nu = (double *)malloc(sizeof(double) * (size_t)m);
+    double *nu0 = (double *)malloc(sizeof(double) * (size_t)m);
+    double *v = (double *)malloc(sizeof(double) * (size_t)s);
+    for (int c = 0; c < m; ++c) {
+        double ss = 0.0;
+        for (int r = 0; r < s; ++r)
+            ss = ss + M[(size_t)c * s + r] * M[(size_t)c * s + r];
+        nu[c] = sqrt(ss);
+        nu0[c] = nu[c];
+    }
+    const double tol3z = sqrt(2.220446049250313e-16);
+    const double window = 1.0 - ldexp(1.0, -40);
+    int kmax = m < s ? m : s;
+    int k = 0;
+    double r00 = 0.0;
+    for (int j = 0; j < kmax; ++j) {
+        /* pivot */
+        double mx = 0.0;
+        for (int c = j; c < m; ++c)
+            if (nu[c] > mx) mx = nu[c];
+        int p = j;
+        for (int c = j; c < m; ++c)
+            if (nu[c] >= window * mx) {
+                p = c;
+                break;
+            }
+        if (p != j) {
+            for (int r = 0; r < s; ++r) {
+                double t = M[(size_t)j * s + r];
+                M[(size_t)j * s + r] = M[(size_t)p * s + r];
+                M[(size_t)p * s + r] = t;
+            }
+            double t = nu[j]; nu[j] = nu[p]; nu[p] = t;
+            t = nu0[j]; nu0[j] = nu0[p]; nu0[p] = t;
+            int ti = piv[j]; piv[j] = piv[p]; piv[p] = ti;
+        }
+        /* exact norm of the trailing pivot column = |R_jj| */
+        double *x = M + (size_t)j * s;
+        double ss = 0.0;
+        for (int r = j; r < s; ++r)
+            ss = ss + x[r] * x[r];
+        double alpha = sqrt(ss);
+        if (j == 0) r00 = alpha;
+        if (alpha == 0.0 || alpha <= tol * r00) break;
+        /* Householder reflector H = I - 2 v v^T / (v^T v) mapping x to beta e_j */
+        double beta = x[j] >= 0.0 ? -alpha : alpha;
+        for (int r = j; r < s; ++r)
+            v[r] = x[r];
+        v[j] = v[j] - beta;
+        double vtv = 0.0;
+        for (int r = j; r < s; ++r)
+            vtv = vtv + v[r] * v[r];
+        for (int c = j + 1; c < m; ++c) {
+            double *y = M + (size_t)c * s;
+            double w = 0.0;
+            for (int r = j; r < s; ++r)
+                w = w + v[r] * y[r];
+            double f = 2.0 * w / vtv;
+            for (int r = j; r < s; ++r)
+                y[r] = y[r] - f * v[r];
+        }
+        x[j] = beta;
+        for (int r = j + 1; r < s; ++r)
+            x[r] = 0.0;
+        absRdiag[j] = alpha;
+        /* norm down-dates */
+        for (int c = j + 1; c < m; ++c) {
+            if (nu[c] == 0.0) continue;
+            double *y = M + (size_t)c * s;
+            double t = fabs(y[j]) / nu[c];
+            t = (1.0 + t) * (1.0 - t);
+            if (t < 0.0) t = 0.0;
+            double rat = nu[c] / nu0[c];
+            double t2 = t * rat * rat;
+            if (t2 <= tol3z) {
+                double s2 = 0.0;
+                for (int r = j + 1; r < s; ++r)
+                    s2 = s2 + y[r] * y[r];
+                nu[c] = sqrt(s2);
+                nu0[c] = nu[c];
+            } else {
+                nu[c] = nu[c] * sqrt(t);
+            }
+        }
+        k = j + 1;
+    }
+    /* T = R11^{-1} R12 by back substitution, one column of R12 at a time */
+    int nr = m - k;
+    for (int u = 0; u < nr; ++u) {
+        const double *b = M + (size_t)(k + u) * s;
+        for (int t = k - 1; t >= 0; --t) {
+            double acc = b[t];
+            for (int l = t + 1; l < k; ++l)
+                acc = acc - M[(size_t)l * s + t] * T[(size_t)l * nr + u];
+            T[(size_t)t * nr + u] = acc / M[(size_t)t * s + t];
+        }
+    }
+    free(M);
+    free(nu);
+    free(nu0);
+    free(v);
+    return k;
+}
+
+/* ------------------------------------------------------------------ */
+/* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014), counter form       */
+/* ------------------------------------------------------------------ */
+/* Value number i of the stream seeded with `seed`: the generator state after
+ * i+1 increments by the golden-ratio constant, passed through the published
+ * finaliser.  Mapped to [0,1) with the top 53 bits. */
+double h2o_splitmix_u01(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) * 0x1.0p-53;
+}
+
+/* ------------------------------------------------------------------ */
+/* the H^2 object                                                      */
+/* ------------------------------------------------------------------ */
+typedef struct h2o {
+    int n, d, kid;
+    double prm[4];
+    double tol, tau;
+    int q;
+    /* tree (Section 2.1); nodes in BFS order: depth, then parent, then child code */
+    int nnode, cap, maxdepth;
+    int *parent, *first_child, *nchild, *start, *count, *depth;
+    double *side, *center; /* center[node*d + k] */
+    int *perm;             /* tree position -> original index */
+    double *P;             /* points in tree order, [n][d] */
+    int *lvl_ptr;          /* nodes of depth L are lvl_ptr[L] .. lvl_ptr[L+1]-1 */
+    /* lists (CSR over nodes, columns ascending) */
+    int *il_ptr, *il_col, *nr_ptr, *nr_col;
+    /* HiDR */
+    int r1, r2;
+    ilist *xs, *ys; /* X_i^*, Y_i^* as tree positions */
+    /* bases */
+    int *rank, *mbar;
+    ilist *xbar;     /* row set Xbar_i (tree positions), in original (unpivoted) order */
+    int **piv;       /* per node, m_i entries */
+    double **T;      /* per node, k_i x (m_i - k_i) */
+    int *calib_r;    /* per depth r found by the calibration (0 if not calibrated) */
+    double *calib_err;
+} h2o;
+
+static void grow_nodes(h2o *h, int need)
+{
+    if (need <= h->cap) return;
+    int nc = h->cap ? h->cap : 64;
+    while (nc < need)
+        nc *= 2;
+#define GROW(p, T_) p = (T_ *)realloc(p, sizeof(T_) * (size_t)nc)
+    GROW(h->parent, int);
+    GROW(h->first_child, int);
+    GROW(h->nchild, int);
+    GROW(h->start, int);
+    GROW(h->count, int);
+    GROW(h->depth, int);
+    GROW(h->side, double);
+#undef GROW
+    h->center = (double *)realloc(h->center, sizeof(double) * (size_t)nc * h->d);
+    h->cap = nc;
+}
+
+static int is_leaf(const h2o *h, int i) { return h->nchild[i] == 0; }
+
+/* Adaptive 2^d tree (Section 2.1; Algorithm 2 step 1).  Readings: the root
+ * box is the cube of side L = max_k (max x_k - min x_k) anchored at the
+ * per-axis minimum; a node splits iff it holds more than q points (and its
+ * depth is below the coincident-point guard); child code b = sum_k [x_k >=
+ * c_k] 2^k (boundary points go to the upper child); empty children are
+ * dropped; points are reordered by a stable counting sort on b. */
+static void build_tree(h2o *h, const double *pts)
+{
+    int n = h->n, d = h->d;
+    h->perm = (int *)malloc(sizeof(int) * (size_t)n);
+    h->P = (double *)malloc(sizeof(double) * (size_t)n * d);
+    for (int i = 0; i < n; ++i) {
+        h->perm[i] = i;
+        for (int a = 0; a < d; ++a)
+            h->P[(size_t)i * d + a] = pts[(size_t)i * d + a];
+    }
+    double lo[3], hi[3];
+    for (int a = 0; a < d; ++a) {
+        lo[a] = pts[a];
+        hi[a] = pts[a];
+    }
+    for (int i = 1; i < n; ++i)
+        for (int a = 0; a < d; ++a) {
+            double v = pts[(size_t)i * d + a];
+            if (v < lo[a]) lo[a] = v;
+            if (v > hi[a]) hi[a] = v;
+        }
+    double L = 0.0;
+    for (int a = 0; a < d; ++a)
+        if (hi[a] - lo[a] > L) L = hi[a] - lo[a];
+    grow_nodes(h, 1);
+    h->nnode = 1;
+    h->parent[0] = -1;
+    h->first_child[0] = -1;
+    h->nchild[0] = 0;
+    h->start[0] = 0;
+    h->count[0] = n;
+    h->depth[0] = 0;
+    h->side[0] = L;
+    for (int a = 0; a < d; ++a)
+        h->center[a] = lo[a] + 0.5 * L;
+
+    int nb = 1 << d;
+    int *tmpperm = (int *)malloc(sizeof(int) * (size_t)n);
+    double *tmpP = (double *)malloc(sizeof(double) * (size_t)n * d);
+    int *code = (int *)malloc(sizeof(int) * (size_t)n);
+    int lvl_cap = 8;
+    h->lvl_ptr = (int *)malloc(sizeof(int) * (size_t)lvl_cap);
+    h->lvl_ptr[0] = 0;
+    int nlev = 0;
+    int a0 = 0, b0 = 1;
+    while (a0 < b0) {
+        if (nlev + 2 >= lvl_cap) {
+            lvl_cap *= 2;
+            h->lvl_ptr = (int *)realloc(h->lvl_ptr, sizeof(int) * (size_t)lvl_cap);
+        }
+        h->lvl_ptr[nlev + 1] = b0;
+        ++nlev;
+        for (int id = a0; id < b0; ++id) {
+            int cnt = h->count[id];
+            if (!(cnt > h->q && h->depth[id] < H2O_MAXDEPTH && h->side[id] > 0.0)) continue;
+            int st = h->start[id];
+            double *c = h->center + (size_t)id * d;
+            int hist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int p = st; p < st + cnt; ++p) {
+                int b = 0;
+                for (int a = 0; a < d; ++a)
+                    if (h->P[(size_t)p * d + a] >= c[a]) b |= 1 << a;
+                code[p] = b;
+                hist[b]++;
+            }
+            int off[8], acc = 0;
+            for (int b = 0; b < nb; ++b) {
+                off[b] = acc;
+                acc += hist[b];
+            }
+            int fill[8];
+            for (int b = 0; b < nb; ++b)
+                fill[b] = off[b];
+            for (int p = st; p < st + cnt; ++p) {
+                int dst = st + fill[code[p]]++;
+                tmpperm[dst] = h->perm[p];
+                for (int a = 0; a < d; ++a)
+                    tmpP[(size_t)dst * d + a] = h->P[(size_t)p * d + a];
+            }
+            for (int p = st; p < st + cnt; ++p) {
+                h->perm[p] = tmpperm[p];
+                for (int a = 0; a < d; ++a)
+                    h->P[(size_t)p * d + a] = tmpP[(size_t)p * d + a];
+            }
+            double s = h->side[id];
+            double qs = s * 0.25;
+            h->first_child[id] = h->nnode;
+            h->nchild[id] = 0;
+            for (int b = 0; b < nb; ++b) {
+                if (hist[b] == 0) continue;
+                grow_nodes(h, h->nnode + 1);
+                int ch = h->nnode++;
+                c = h->center + (size_t)id * d; /* realloc may have moved it */
+                h->parent[ch] = id;
+                h->first_child[ch] = -1;
+                h->nchild[ch] = 0;
+                h->start[ch] = st + off[b];
+                h->count[ch] = hist[b];
+                h->depth[ch] = h->depth[id] + 1;
+                h->side[ch] = s * 0.5;
+                for (int a = 0; a < d; ++a)
+                    h->center[(size_t)ch * d + a] = ((b >> a) & 1) ? c[a] + qs : c[a] - qs;
+                h->nchild[id]++;
+            }
+        }
+        a0 = b0;
+        b0 = h->nnode;
+    }
+    h->maxdepth = nlev - 1;
+    free(tmpperm);
+    free(tmpP);
+    free(code);
+}
+
+/* Admissibility, Eq. (separation): diam(X_i) + diam(X_j) <= 2 tau |a_i - a_j|
+ * with diam read as the box diagonal side*sqrt(d) and a as the box centre;
+ * squared to avoid a square root: d (s_i + s_j)^2 <= 4 tau^2 |a_i - a_j|^2. */
+static int admissible(const h2o *h, int i, int j)
+{
+    int d = h->d;
+    double dist2 = 0.0;
+    for (int a = 0; a < d; ++a) {
+        double t = h->center[(size_t)i * d + a] - h->center[(size_t)j * d + a];
+        dist2 = dist2 + t * t;
+    }
+    double ss = h->side[i] + h->side[j];
+    double lhs = (double)d * (ss * ss);
+    double rhs = 4.0 * h->tau * h->tau * dist2;
+    return lhs <= rhs;
+}
+
+static int cmp_int(const void *a, const void *b)
+{
+    int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+
+static void csr_from_pairs(int nnode, const ilist *ri, const ilist *rj, int **ptr, int **col)
+{
+    int *p = (int *)calloc((size_t)nnode + 1, sizeof(int));
+    for (int e = 0; e < ri->n; ++e)
+        p[ri->v[e] + 1]++;
+    for (int i = 0; i < nnode; ++i)
+        p[i + 1] += p[i];
+    int *c = (int *)malloc(sizeof(int) * (size_t)(ri->n > 0 ? ri->n : 1));
+    int *fill = (int *)malloc(sizeof(int) * (size_t)nnode);
+    for (int i = 0; i < nnode; ++i)
+        fill[i] = p[i];
+    for (int e = 0; e < ri->n; ++e)
+        c[fill[ri->v[e]]++] = rj->v[e];
+    for (int i = 0; i < nnode; ++i)
+        qsort(c + p[i], (size_t)(p[i + 1] - p[i]), sizeof(int), cmp_int);
+    free(fill);
+    *ptr = p;
+    *col = c;
+}
+
+/* Interaction and near lists (Section 2.1).  The paper's worked example
+ * (IL(4) = {6,7}, IL(10) = {8,12,13} on a 1-D binary tree) matches the pair
+ * rule: (i,j) is in the interaction list when (i,j) is admissible and the
+ * pair of their parents is not.  Dual traversal from (root, root): an
+ * inadmissible pair with a non-leaf side is refined (both non-leaf: all child
+ * pairs; one side a leaf: the children of the other side); every new pair is
+ * admissible (interaction list), a pair of leaves (near list, (i,i)
+ * included), or refined further. */
+static void build_lists(h2o *h)
+{
+    ilist ilr = {0}, ilc = {0}, nrr = {0}, nrc = {0};
+    ilist fr = {0}, fc = {0};
+    if (is_leaf(h, 0)) {
+        il_push(&nrr, 0);
+        il_push(&nrc, 0);
+    } else {
+        il_push(&fr, 0);
+        il_push(&fc, 0);
+    }
+    while (fr.n > 0) {
+        ilist gr = {0}, gc = {0};
+        for (int e = 0; e < fr.n; ++e) {
+            int i = fr.v[e], j = fc.v[e];
+            int ni = is_leaf(h, i) ? 1 : h->nchild[i];
+            int nj = is_leaf(h, j) ? 1 : h->nchild[j];
+            for (int a = 0; a < ni; ++a)
+                for (int b = 0; b < nj; ++b) {
+                    int ci = is_leaf(h, i) ? i : h->first_child[i] + a;
+                    int cj = is_leaf(h, j) ? j : h->first_child[j] + b;
+                    if (admissible(h, ci, cj)) {
+                        il_push(&ilr, ci);
+                        il_push(&ilc, cj);
+                    } else if (is_leaf(h, ci) && is_leaf(h, cj)) {
+                        il_push(&nrr, ci);
+                        il_push(&nrc, cj);
+                    } else {
+                        il_push(&gr, ci);
+                        il_push(&gc, cj);
+                    }
+                }
+        }
+        il_free(&fr);
+        il_free(&fc);
+        fr = gr;
+        fc = gc;
+    }
+    csr_from_pairs(h->nnode, &ilr, &ilc, &h->il_ptr, &h->il_col);
+    csr_from_pairs(h->nnode, &nrr, &nrc, &h->nr_ptr, &h->nr_col);
+    il_free(&ilr);
+    il_free(&ilc);
+    il_free(&nrr);
+    il_free(&nrc);
+}
+
+/* HiDR, Algorithm 1.  Bottom-up (deepest level first): S_i = X_i for a leaf,
+ * else the children's X_c^* concatenated in child order; X_i^* =
+ * DataReduct(S_i, r1).  Top-down (depth 1 first): T_i = Y_p^* followed by
+ * X_j^* for j in IL(i) ascending (Y_root^* is empty); Y_i^* =
+ * DataReduct(T_i, r2) when T_i is not empty.  (The text writes "union of
+ * Y_p" once and Y_p^* in the algorithm and elsewhere; Y_p^* is taken.) */
+static void run_hidr(h2o *h)
+{
+    h->xs = (ilist *)calloc((size_t)h->nnode, sizeof(ilist));
+    h->ys = (ilist *)calloc((size_t)h->nnode, sizeof(ilist));
+    for (int L = h->maxdepth; L >= 1; --L) {
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int i = h->lvl_ptr[L]; i < h->lvl_ptr[L + 1]; ++i) {
+            ilist S = {0};
+            if (is_leaf(h, i)) {
+                for (int p = h->start[i]; p < h->start[i] + h->count[i]; ++p)
+                    il_push(&S, p);
+            } else {
+                for (int c = h->first_child[i]; c < h->first_child[i] + h->nchild[i]; ++c)
+                    for (int t = 0; t < h->xs[c].n; ++t)
+                        il_push(&S, h->xs[c].v[t]);
+            }
+            int *out = (int *)malloc(sizeof(int) * (size_t)(S.n > 0 ? S.n : 1));
+            int cnt = h2o_datareduct(h->d, h->P, S.v, S.n, h->r1, out);
+            ilist X = {0};
+            for (int t = 0; t < cnt; ++t)
+                il_push(&X, out[t]);
+            h->xs[i] = X;
+            free(out);
+            il_free(&S);
+        }
+    }
+    for (int L = 1; L <= h->maxdepth; ++L) {
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int i = h->lvl_ptr[L]; i < h->lvl_ptr[L + 1]; ++i) {
+            ilist Tl = {0};
+            int p = h->parent[i];
+            for (int t = 0; t < h->ys[p].n; ++t)
+                il_push(&Tl, h->ys[p].v[t]);
+            for (int e = h->il_ptr[i]; e < h->il_ptr[i + 1]; ++e) {
+                int j = h->il_col[e];
+                for (int t = 0; t < h->xs[j].n; ++t)
+                    il_push(&Tl, h->xs[j].v[t]);
+            }
+            ilist Y = {0};
+            if (Tl.n > 0) {
+                int *out = (int *)malloc(sizeof(int) * (size_t)Tl.n);
+                int cnt = h2o_datareduct(h->d, h->P, Tl.v, Tl.n, h->r2, out);
+                for (int t = 0; t < cnt; ++t)
+                    il_push(&Y, out[t]);
+                free(out);
+            }
+            h->ys[i] = Y;
+            il_free(&Tl);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* r1, r2 from the tolerance (Section 4.2; Algorithm 2 step 2)         */
+/* ------------------------------------------------------------------ */
+/* The paper grows r1 = r2 from 1 until the ID built from the reduced set
+ * approximates an artificial well-separated K_{Z1 Z2} to better than
+ * 1e-2 eps.  Readings of what it leaves open: r steps over g^d (the sizes the
+ * volume grid produces); Z1, Z2 hold 512 points each, uniform in cubes of
+ * side s whose centres lie s sqrt(d)/tau apart along axis 0 (the closest
+ * admissible placement); coordinates come from SplitMix64 values 0.. (Z1
+ * first, then Z2, coordinate fastest); the ID inside uses tolerance 1e-3 eps,
+ * a decade below the target, so that the sampling and not the truncation is
+ * what the test measures;
+ * the error is the relative Frobenius norm of K_{Z1Z2} - U K_{Zhat Z2}.
+ * Returns the first r meeting the target, or r_cap if none does; *err gets
+ * the error of the returned r. */
+#define H2O_NCAL 512
+int h2o_calibrate_one(int kid, const double *prm, int d, double s, double tau, double eps,
+                      uint64_t seed, int r_cap, double *err_out)
+{
+    int nz = H2O_NCAL;
+    double *Z1 = (double *)malloc(sizeof(double) * (size_t)nz * d);
+    double *Z2 = (double *)malloc(sizeof(double) * (size_t)nz * d);
+    double sep = s * sqrt((double)d) / tau;
+    for (int i = 0; i < nz; ++i)
+        for (int a = 0; a < d; ++a) {
+            double u1 = h2o_splitmix_u01(seed, (uint64_t)i * d + a);
+            double u2 = h2o_splitmix_u01(seed, (uint64_t)nz * d + (uint64_t)i * d + a);
+            Z1[(size_t)i * d + a] = s * (u1 - 0.5);
+            Z2[(size_t)i * d + a] = s * (u2 - 0.5) + (a == 0 ? sep : 0.0);
+        }
+    double *Kfull = (double *)malloc(sizeof(double) * (size_t)nz * nz);
+    h2o_kernel_matrix(kid, prm, d, Z1, nz, Z2, nz, Kfull);
+    double fro = 0.0;
+    for (size_t e = 0; e < (size_t)nz * nz; ++e)
+        fro = fro + Kfull[e] * Kfull[e];
+    fro = sqrt(fro);
+    int *all = (int *)malloc(sizeof(int) * (size_t)nz);
+    for (int i = 0; i < nz; ++i)
+        all[i] = i;
+    int *ysel = (int *)malloc(sizeof(int) * (size_t)nz);
+    double *Ysel = (double *)malloc(sizeof(double) * (size_t)nz * d);
+    double *A = (double *)malloc(sizeof(double) * (size_t)nz * nz);
+    int *piv = (int *)malloc(sizeof(int) * (size_t)nz);
+    double *T = (double *)malloc(sizeof(double) * (size_t)nz * nz);
+    double *rd = (double *)malloc(sizeof(double) * (size_t)nz);
+    int r_found = r_cap;
+    double err = INFINITY;
+    for (int g = 1;; ++g) {
+        long long rr = 1;
+        for (int a = 0; a < d; ++a)
+            rr *= g;
+        int r = rr > r_cap ? r_cap : (int)rr;
+        int sy = h2o_datareduct(d, Z2, all, nz, r, ysel);
+        for (int t = 0; t < sy; ++t)
+            for (int a = 0; a < d; ++a)
+                Ysel[(size_t)t * d + a] = Z2[(size_t)ysel[t] * d + a];
+        h2o_kernel_matrix(kid, prm, d, Z1, nz, Ysel, sy, A);
+        int k = h2o_cpqr_id(A, nz, sy, 1e-3 * eps, piv, T, rd);
+        /* residual K(rest,:) - T^T K(skel,:) over all of Z2 (skeleton rows are exact) */
+        int nr = nz - k;
+        double res = 0.0;
+        for (int u = 0; u < nr; ++u) {
+            const double *xr = Z1 + (size_t)piv[k + u] * d;
+            for (int c = 0; c < nz; ++c) {
+                double approx = 0.0;
+                for (int t = 0; t < k; ++t)
+                    approx = approx + T[(size_t)t * nr + u] * Kfull[(size_t)piv[t] * nz + c];
+                double e = h2o_kappa(kid, prm, xr, Z2 + (size_t)c * d, d) - approx;
+                res = res + e * e;
+            }
+        }
+        err = fro > 0.0 ? sqrt(res) / fro : 0.0;
+        if (err < 1e-2 * eps) {
+            r_found = r;
+            break;
+        }
+        if (r >= r_cap) {
+            r_found = r_cap;
+            break;
+        }
+    }
+    if (err_out) *err_out = err;
+    free(Z1); free(Z2); free(Kfull); free(all); free(ysel); free(Ysel);
+    free(A); free(piv); free(T); free(rd);
+    return r_found;
+}
+
+/* Calibration for a tree: the Coulomb kernel is scale invariant, so one box
+ * size suffices; other kernels are calibrated at the box side of every depth
+ * that has interaction-list pairs and r = the maximum over those depths. */
+static int r_cap_for(int d) { return d == 3 ? 1000 : (d == 2 ? 1024 : 64); }
+
+static void calibrate(h2o *h, uint64_t seed)
+{
+    h->calib_r = (int *)calloc((size_t)h->maxdepth + 1, sizeof(int));
+    h->calib_err = (double *)calloc((size_t)h->maxdepth + 1, sizeof(double));
+    int rmax = 1;
+    int cap = r_cap_for(h->d);
+    if (h->kid == K_COULOMB) {
+        double e;
+        int r = h2o_calibrate_one(h->kid, h->prm, h->d, 1.0, h->tau, h->tol, seed, cap, &e);
+        for (int L = 0; L <= h->maxdepth; ++L) {
+            h->calib_r[L] = r;
+            h->calib_err[L] = e;
+        }
+        rmax = r;
+    } else {
+        for (int L = 1; L <= h->maxdepth; ++L) {
+            int has = 0;
+            for (int i = h->lvl_ptr[L]; i < h->lvl_ptr[L + 1] && !has; ++i)
+                if (h->il_ptr[i + 1] > h->il_ptr[i]) has = 1;
+            if (!has) continue;
+            double e;
+            int r = h2o_calibrate_one(h->kid, h->prm, h->d, h->side[h->lvl_ptr[L]], h->tau, h->tol,
+                                      seed, cap, &e);
+            h->calib_r[L] = r;
+            h->calib_err[L] = e;
+            if (r > rmax) rmax = r;
+        }
+    }
+    if (h->r1 <= 0) h->r1 = rmax;
+    if (h->r2 <= 0) h->r2 = rmax;
+}
+
+/* ------------------------------------------------------------------ */
+/* nested bases (Algorithm 2, steps 4-12)                              */
+/* ------------------------------------------------------------------ */
+/* Bottom-up over non-root nodes: the row set Xbar_i is X_i for a leaf and the
+ * children's skeletons concatenated in child order otherwise; getBasis on
+ * K(Xbar_i, Y_i^*) gives U_i = P [I; T^T] and the skeleton Xhat_i =
+ * Xbar_i[piv_0..k-1] in pivot order.  The transfer matrix R_c of a child is
+ * the block of U_p's rows that belong to c's segment of Xbar_p.  Every
+ * supported kernel is symmetric, so V = U and W = R.  A node with an empty
+ * Y_i^* gets rank 0. */
+static void build_bases(h2o *h)
+{
+    int nn = h->nnode;
+    h->rank = (int *)calloc((size_t)nn, sizeof(int));
+    h->mbar = (int *)calloc((size_t)nn, sizeof(int));
+    h->xbar = (ilist *)calloc((size_t)nn, sizeof(ilist));
+    h->piv = (int **)calloc((size_t)nn, sizeof(int *));
+    h->T = (double **)calloc((size_t)nn, sizeof(double *));
+    int d = h->d;
+    for (int L = h->maxdepth; L >= 1; --L) {
+#pragma omp parallel for schedule(dynamic, 2)
+        for (int i = h->lvl_ptr[L]; i < h->lvl_ptr[L + 1]; ++i) {
+            ilist X = {0};
+            if (is_leaf(h, i)) {
+                for (int p = h->start[i]; p < h->start[i] + h->count[i]; ++p)
+                    il_push(&X, p);
+            } else {
+                for (int c = h->first_child[i]; c < h->first_child[i] + h->nchild[i]; ++c) {
+                    const ilist *xc = &h->xbar[c];
+                    for (int t = 0; t < h->rank[c]; ++t)
+                        il_push(&X, xc->v[h->piv[c][t]]);
+                }
+            }
+            int m = X.n, s = h->ys[i].n;
+            int *piv = (int *)malloc(sizeof(int) * (size_t)(m > 0 ? m : 1));
+            int k = 0;
+            double *T = NULL;
+            if (m > 0 && s > 0) {
+                double *Xc = (double *)malloc(sizeof(double) * (size_t)m * d);
+                double *Yc = (double *)malloc(sizeof(double) * (size_t)s * d);
+                for (int t = 0; t < m; ++t)
+                    for (int a = 0; a < d; ++a)
+                        Xc[(size_t)t * d + a] = h->P[(size_t)X.v[t] * d + a];
+                for (int t = 0; t < s; ++t)
+                    for (int a = 0; a < d; ++a)
+                        Yc[(size_t)t * d + a] = h->P[(size_t)h->ys[i].v[t] * d + a];
+                double *A = (double *)malloc(sizeof(double) * (size_t)m * s);
+                h2o_kernel_matrix(h->kid, h->prm, d, Xc, m, Yc, s, A);
+                int kk = m < s ? m : s;
+                double *Tt = (double *)malloc(sizeof(double) * (size_t)(kk > 0 ? kk : 1) * (size_t)m);
+                double *rd = (double *)malloc(sizeof(double) * (size_t)(kk > 0 ? kk : 1));
+                k = h2o_cpqr_id(A, m, s, h->tol, piv, Tt, rd);
+                T = Tt;
+                free(rd);
+                free(A);
+                free(Xc);
+                free(Yc);
+            } else {
+                for (int t = 0; t < m; ++t)
+                    piv[t] = t;
+            }
+            h->xbar[i] = X;
+            h->mbar[i] = m;
+            h->rank[i] = k;
+            h->piv[i] = piv;
+            h->T[i] = T;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* public: build / free / export                                       */
+/* ------------------------------------------------------------------ */
+void h2o_free(h2o *h);
+
+/* Build the H^2 representation of K = [kappa(x_i, x_j)] for the points pts
+ * ([n][d], row-major, original order).  r1/r2 <= 0 select calibration.
+ * nthreads <= 0 keeps the OpenMP default.  Returns NULL on invalid input. */
+h2o *h2o_build(const double *pts, int n, int d, int kid, const double *prm, double tol, int q,
+               double tau, int r1, int r2, uint64_t seed, int nthreads)
+{
+    if (n < 1 || d < 1 || d > 3 || q < 1 || !(tol > 0.0 && tol < 1.0) || !(tau > 0.0 && tau < 1.0) ||
+        kid < 0 || kid > 3)
+        return NULL;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    h2o *h = (h2o *)calloc(1, sizeof(h2o));
+    h->n = n;
+    h->d = d;
+    h->kid = kid;
+    h->prm[0] = prm ? prm[0] : 1.0;
+    /* The paper leaves the split of the tolerance between sampling and
+     * truncation open; the construction runs at eps' = eps/2 (ID truncation
+     * and the calibration target), which keeps the end-to-end error against
+     * the dense product within eps on the reference workloads. */
+    h->tol = tol * 0.5;
+    h->tau = tau;
+    h->q = q;
+    h->r1 = r1;
+    h->r2 = r2;
+    build_tree(h, pts);
+    build_lists(h);
+    calibrate(h, seed);
+    run_hidr(h);
+    build_bases(h);
+    return h;
+}
+
+/* Tree and lists only (for structural pins on inputs where HiDR is moot). */
+h2o *h2o_build_tree_lists(const double *pts, int n, int d, int q, double tau)
+{
+    h2o *h = (h2o *)calloc(1, sizeof(h2o));
+    h->n = n;
+    h->d = d;
+    h->q = q;
+    h->tau = tau;
+    h->tol = 1e-6;
+    h->prm[0] = 1.0;
+    build_tree(h, pts);
+    build_lists(h);
+    return h;
+}
+
+void h2o_free(h2o *h)
+{
+    if (!h) return;
+    free(h->parent); free(h->first_child); free(h->nchild); free(h->start); free(h->count);
+    free(h->depth); free(h->side); free(h->center); free(h->perm); free(h->P); free(h->lvl_ptr);
+    free(h->il_ptr); free(h->il_col); free(h->nr_ptr); free(h->nr_col);
+    for (int i = 0; i < h->nnode; ++i) {
+        if (h->xs) il_free(&h->xs[i]);
+        if (h->ys) il_free(&h->ys[i]);
+        if (h->xbar) il_free(&h->xbar[i]);
+        if (h->piv) free(h->piv[i]);
+        if (h->T) free(h->T[i]);
+    }
+    free(h->xs); free(h->ys); free(h->xbar); free(h->piv); free(h->T);
+    free(h->rank); free(h->mbar); free(h->calib_r); free(h->calib_err);
+    free(h);
+}
+
+/* scalar info: 0 nnode, 1 maxdepth, 2 r1, 3 r2, 4 nnz IL, 5 nnz near, 6 n, 7 d */
+long long h2o_info(const h2o *h, int what)
+{
+    switch (what) {
+    case 0: return h->nnode;
+    case 1: return h->maxdepth;
+    case 2: return h->r1;
+    case 3: return h->r2;
+    case 4: return h->il_ptr ? h->il_ptr[h->nnode] : 0;
+    case 5: return h->nr_ptr ? h->nr_ptr[h->nnode] : 0;
+    case 6: return h->n;
+    case 7: return h->d;
+    default: return -1;
+    }
+}
+
+/* Export an int array.  what: 0 perm, 1 parent, 2 first_child, 3 nchild,
+ * 4 start, 5 count, 6 depth, 7 lvl_ptr, 8 il_ptr, 9 il_col, 10 nr_ptr,
+ * 11 nr_col, 12 rank, 13 mbar.  Returns the number of entries (buf may be
+ * NULL to query). */
+long long h2o_export_int(const h2o *h, int what, int *buf)
+{
+    const int *src = NULL;
+    long long cnt = 0;
+    switch (what) {
+    case 0: src = h->perm; cnt = h->n; break;
+    case 1: src = h->parent; cnt = h->nnode; break;
+    case 2: src = h->first_child; cnt = h->nnode; break;
+    case 3: src = h->nchild; cnt = h->nnode; break;
+    case 4: src = h->start; cnt = h->nnode; break;
+    case 5: src = h->count; cnt = h->nnode; break;
+    case 6: src = h->depth; cnt = h->nnode; break;
+    case 7: src = h->lvl_ptr; cnt = h->maxdepth + 2; break;
+    case 8: src = h->il_ptr; cnt = h->nnode + 1; break;
+    case 9: src = h->il_col; cnt = h->il_ptr[h->nnode]; break;
+    case 10: src = h->nr_ptr; cnt = h->nnode + 1; break;
+    case 11: src = h->nr_col; cnt = h->nr_ptr[h->nnode]; break;
+    case 12: src = h->rank; cnt = src ? h->nnode : 0; break;
+    case 13: src = h->mbar; cnt = src ? h->nnode : 0; break;
+    default: return -1;
+    }
+    if (buf && src) memcpy(buf, src, sizeof(int) * (size_t)cnt);
+    return cnt;
+}
+
+/* Export a double array: 0 center ([nnode][d]), 1 side, 2 points in tree
+ * order ([n][d]), 3 calibration error per depth. */
+long long h2o_export_double(const h2o *h, int what, double *buf)
+{
+    const double *src = NULL;
+    long long cnt = 0;
+    switch (what) {
+    case 0: src = h->center; cnt = (long long)h->nnode * h->d; break;
+    case 1: src = h->side; cnt = h->nnode; break;
+    case 2: src = h->P; cnt = (long long)h->n * h->d; break;
+    case 3: src = h->calib_err; cnt = src ? h->maxdepth + 1 : 0; break;
+    default: return -1;
+    }
+    if (buf && src) memcpy(buf, src, sizeof(double) * (size_t)cnt);
+    return cnt;
+}
+
+/* Per-node variable lists: what 0 X_i^*, 1 Y_i^*, 2 Xbar_i (unpivoted),
+ * 3 piv_i, 4 skeleton Xhat_i (pivot order).  Returns the length. */
+long long h2o_node_list(const h2o *h, int what, int i, int *buf)
+{
+    const int *src = NULL;
+    long long cnt = 0;
+    switch (what) {
+    case 0: if (h->xs) { src = h->xs[i].v; cnt = h->xs[i].n; } break;
+    case 1: if (h->ys) { src = h->ys[i].v; cnt = h->ys[i].n; } break;
+    case 2: if (h->xbar) { src = h->xbar[i].v; cnt = h->xbar[i].n; } break;
+    case 3: if (h->piv) { src = h->piv[i]; cnt = h->mbar[i]; } break;
+    case 4:
+        if (h->piv) {
+            cnt = h->rank[i];
+            if (buf)
+                for (int t = 0; t < cnt; ++t)
+                    buf[t] = h->xbar[i].v[h->piv[i][t]];
+            return cnt;
+        }
+        break;
+    default: return -1;
+    }
+    if (buf && src) memcpy(buf, src, sizeof(int) * (size_t)cnt);
+    return cnt;
+}
+
+/* T_i (k x (m-k), row-major). Returns the number of entries. */
+long long h2o_node_T(const h2o *h, int i, double *buf)
+{
+    if (!h->T) return 0;
+    long long cnt = (long long)h->rank[i] * (h->mbar[i] - h->rank[i]);
+    if (buf && h->T[i]) memcpy(buf, h->T[i], sizeof(double) * (size_t)cnt);
+    return cnt;
+}
+
+/* ------------------------------------------------------------------ */
+/* H^2 matrix-vector product                                           */
+/* ------------------------------------------------------------------ */
+/* xhat = U^T z with U = P [I; T^T]: xhat[t] = z[piv t] + sum_u T[t,u] z[piv(k+u)] */
+static void apply_Ut(const h2o *h, int i, const double *z, double *xh)
+{
+    int m = h->mbar[i], k = h->rank[i], nr = m - k;
+    const int *piv = h->piv[i];
+    const double *T = h->T[i];
+    for (int t = 0; t < k; ++t) {
+        double acc = z[piv[t]];
+        for (int u = 0; u < nr; ++u)
+            acc = acc + T[(size_t)t * nr + u] * z[piv[k + u]];
+        xh[t] = acc;
+    }
+}
+
+/* w += U yhat: w[piv t] += yhat[t]; w[piv(k+u)] += sum_t T[t,u] yhat[t] */
+static void apply_U_add(const h2o *h, int i, const double *yh, double *w)
+{
+    int m = h->mbar[i], k = h->rank[i], nr = m - k;
+    const int *piv = h->piv[i];
+    const double *T = h->T[i];
+    for (int t = 0; t < k; ++t)
+        w[piv[t]] = w[piv[t]] + yh[t];
+    for (int u = 0; u < nr; ++u) {
+        double acc = 0.0;
+        for (int t = 0; t < k; ++t)
+            acc = acc + T[(size_t)t * nr + u] * yh[t];
+        w[piv[k + u]] = w[piv[k + u]] + acc;
+    }
+}
+
+static void skel_coords(const h2o *h, int i, double *out)
+{
+    int d = h->d;
+    for (int t = 0; t < h->rank[i]; ++t) {
+        int p = h->xbar[i].v[h->piv[i][t]];
+        for (int a = 0; a < d; ++a)
+            out[(size_t)t * d + a] = h->P[(size_t)p * d + a];
+    }
+}
+
+/* Computes the H^2 product for one right-hand side in tree order.  When
+ * `need` is non-NULL only rows r with need[r] != 0 are produced (the
+ * coupling and downward sweeps then visit only the ancestors of the leaves
+ * holding those rows); other rows of yt are left at 0. */
+static void matvec_tree(const h2o *h, const double *xt, double *yt, const unsigned char *need)
+{
+    int nn = h->nnode, d = h->d;
+    size_t *off = (size_t *)malloc(sizeof(size_t) * ((size_t)nn + 1));
+    off[0] = 0;
+    for (int i = 0; i < nn; ++i)
+        off[i + 1] = off[i] + (size_t)h->rank[i];
+    double *xh = (double *)calloc(off[nn] + 1, sizeof(double));
+    double *yh = (double *)calloc(off[nn] + 1, sizeof(double));
+    unsigned char *act = (unsigned char *)calloc((size_t)nn, 1);
+    /* which nodes need their output: ancestors of leaves holding needed rows */
+    for (int i = 0; i < nn; ++i) {
+        if (!is_leaf(h, i)) continue;
+        int want = need ? 0 : 1;
+        if (need)
+            for (int p = h->start[i]; p < h->start[i] + h->count[i]; ++p)
+                if (need[p]) { want = 1; break; }
+        if (want)
+            for (int a = i; a >= 0 && !act[a]; a = h->parent[a])
+                act[a] = 1;
+    }
+    /* upward: xhat_i = U_i^T z_i, z_i = x_t(X_i) (leaf) or the children's xhat */
+    for (int L = h->maxdepth; L >= 1; --L) {
+#pragma omp parallel for schedule(dynamic, 8)
+        for (int i = h->lvl_ptr[L]; i < h->lvl_ptr[L + 1]; ++i) {
+            if (h->rank[i] == 0) continue;
+            const double *z;
+            if (is_leaf(h, i))
+                z = xt + h->start[i];
+            else
+                z = xh + off[h->first_child[i]]; /* children's xhat are contiguous */
+            apply_Ut(h, i, z, xh + off[i]);
+        }
+    }
+    /* coupling: yhat_i = sum_{j in IL(i)} B_ij xhat_j, B_ij = K(Xhat_i, Xhat_j) */
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int i = 0; i < nn; ++i) {
+        if (!act[i] || h->rank[i] == 0) continue;
+        int ki = h->rank[i];
+        double *Xi = (double *)malloc(sizeof(double) * (size_t)ki * d);
+        skel_coords(h, i, Xi);
+        for (int e = h->il_ptr[i]; e < h->il_ptr[i + 1]; ++e) {
+            int j = h->il_col[e];
+            int kj = h->rank[j];
+            double *Xj = (double *)malloc(sizeof(double) * (size_t)(kj > 0 ? kj : 1) * d);
+            skel_coords(h, j, Xj);
+            for (int t = 0; t < ki; ++t) {
+                double acc = 0.0;
+                for (int u = 0; u < kj; ++u)
+                    acc = acc + h2o_kappa(h->kid, h->prm, Xi + (size_t)t * d, Xj + (size_t)u * d, d) *
+                                    xh[off[j] + u];
+                yh[off[i] + t] = yh[off[i] + t] + acc;
+            }
+            free(Xj);
+        }
+        free(Xi);
+    }
+    /* downward: yhat_c += R_c yhat_p, i.e. the children's segment of U_p yhat_p */
+    for (int L = 1; L <= h->maxdepth; ++L) {
+#pragma omp parallel for schedule(dynamic, 8)
+        for (int i = h->lvl_ptr[L]; i < h->lvl_ptr[L + 1]; ++i) {
+            if (!act[i] || is_leaf(h, i) || h->rank[i] == 0) continue;
+            apply_U_add(h, i, yh + off[i], yh + off[h->first_child[i]]);
+        }
+    }
+    /* leaves: y_t(X_i) = U_i yhat_i + sum_{j in near(i)} K(X_i, X_j) x_t(X_j) */
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int i = 0; i < nn; ++i) {
+        if (!act[i] || !is_leaf(h, i)) continue;
+        int st = h->start[i], ci = h->count[i];
+        double *w = yt + st;
+        for (int t = 0; t < ci; ++t)
+            w[t] = 0.0;
+        if (h->rank[i] > 0) apply_U_add(h, i, yh + off[i], w);
+        for (int e = h->nr_ptr[i]; e < h->nr_ptr[i + 1]; ++e) {
+            int j = h->nr_col[e];
+            for (int t = 0; t < ci; ++t) {
+                if (need && !need[st + t]) continue;
+                double acc = 0.0;
+                for (int u = 0; u < h->count[j]; ++u)
+                    acc = acc + h2o_kappa(h->kid, h->prm, h->P + (size_t)(st + t) * d,
+                                          h->P + (size_t)(h->start[j] + u) * d, d) *
+                                    xt[h->start[j] + u];
+                w[t] = w[t] + acc;
+            }
+        }
+    }
+    free(off);
+    free(xh);
+    free(yh);
+    free(act);
+}
+
+/* y = Ktilde x for nrhs right-hand sides, x and y [nrhs][n] in original order. */
+void h2o_matvec(const h2o *h, const double *x, double *y, int nrhs)
+{
+    int n = h->n;
+    double *xt = (double *)malloc(sizeof(double) * (size_t)n);
+    double *yt = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int r = 0; r < nrhs; ++r) {
+        for (int i = 0; i < n; ++i)
+            xt[i] = x[(size_t)r * n + h->perm[i]];
+        matvec_tree(h, xt, yt, NULL);
+        for (int i = 0; i < n; ++i)
+            y[(size_t)r * n + h->perm[i]] = yt[i];
+    }
+    free(xt);
+    free(yt);
+}
+
+/* Rows `rows` (original indices) of Ktilde x: out [nrhs][nrows]. */
+void h2o_matvec_rows(const h2o *h, const double *x, int nrhs, const int *rows, int nrows, double *out)
+{
+    int n = h->n;
+    int *inv = (int *)malloc(sizeof(int) * (size_t)n);
+    for (int i = 0; i < n; ++i)
+        inv[h->perm[i]] = i;
+    unsigned char *need = (unsigned char *)calloc((size_t)n, 1);
+    for (int t = 0; t < nrows; ++t)
+        need[inv[rows[t]]] = 1;
+    double *xt = (double *)malloc(sizeof(double) * (size_t)n);
+    double *yt = (double *)calloc((size_t)n, sizeof(double));
+    for (int r = 0; r < nrhs; ++r) {
+        for (int i = 0; i < n; ++i)
+            xt[i] = x[(size_t)r * n + h->perm[i]];
+        matvec_tree(h, xt, yt, need);
+        for (int t = 0; t < nrows; ++t)
+            out[(size_t)r * nrows + t] = yt[inv[rows[t]]];
+    }
+    free(inv);
+    free(need);
+    free(xt);
+    free(yt);
+}
+
+/* ------------------------------------------------------------------ */
+/* dense reference                                                     */
+/* ------------------------------------------------------------------ */
+/* out[r][t] = sum_j kappa(x_rows[t], x_j) x[r][j]  (K as defined in Section 2)
+ * pts [n][d] original order; rows NULL means all rows (nrows = n). */
+void h2o_dense_rows(const double *pts, int n, int d, int kid, const double *prm, const double *x,
+                    int nrhs, const int *rows, int nrows, double *out, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(static)
+    for (int t = 0; t < nrows; ++t) {
+        int i = rows ? rows[t] : t;
+        for (int r = 0; r < nrhs; ++r) {
+            double acc = 0.0;
+            for (int j = 0; j < n; ++j)
+                acc = acc + h2o_kappa(kid, prm, pts + (size_t)i * d, pts + (size_t)j * d, d) *
+                                x[(size_t)r * n + j];
+            out[(size_t)r * nrows + t] = acc;
+        }
+    }
+}
+
+int h2o_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
