@@ -263,9 +263,9 @@ int h2o_cpqr_id(const double *A, int m, int s, double tol, int *piv, double *T, 
         for (int r = j; r < s; ++r)
             v[r] = x[r];
         v[j] = v[j] - beta;
-        double vtv = 0.0;
-        for (int r = j; r < s; ++r)
-            vtv = vtv + v[r] * v[r];
+        /* |v|^2 in closed form: v_j = x_j - beta with beta = -sign(x_j) alpha,
+         * so |v|^2 = (|x_j| + alpha)^2 + (alpha^2 - x_j^2) = 2 alpha (alpha + |x_j|) */
+        double vtv = 2.0 * alpha * (alpha + fabs(x[j]));
         for (int c = j + 1; c < m; ++c) {
             double *y = M + (size_t)c * s;
             double w = 0.0;
