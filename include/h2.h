@@ -1,0 +1,154 @@
+/*
+ * h2.h -- C ABI of the MI355X (gfx950) library for the data-driven H^2
+ * construction of Cai, Huang, Chow and Xi (arXiv 2206.01885).
+ *
+ * The calls follow the paper's statement of the problem (Algorithm 2): the
+ * input is a point set X, a kernel function kappa, an approximation tolerance
+ * eps, a separation ratio tau and a leaf capacity q; the output is the H^2
+ * representation (bases U, transfer matrices R, coupling blocks B and the
+ * dense nearfield), which is then applied to vectors, y = Ktilde x.
+ *
+ * All numerical work of h2_build / h2_matvec runs in the library's HIP
+ * kernels on the current device.  Pointers marked "device" must be device
+ * memory of that device; pointers marked "host" are host memory.
+ *
+ * Thread safety: a handle must not be used by two calls at once; distinct
+ * handles are independent.  Every non-OK status leaves a message readable with
+ * h2_last_error() (thread-local).
+ */
+#ifndef H2_MI355X_H
+#define H2_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct h2_handle_s *h2_handle;
+
+typedef enum {
+    H2_OK = 0,
+    H2_EINVAL = -1,       /* invalid argument (sizes, tolerance, non-finite points, ...) */
+    H2_ENOMEM = -2,       /* device memory exhausted */
+    H2_EDEVICE = -3,      /* HIP runtime error */
+    H2_EUNSUPPORTED = -4, /* valid request outside what this build implements */
+    H2_EINTERNAL = -5     /* internal consistency check failed */
+} h2_status;
+
+/* Kernel functions (Section 2 and Table 1 of the paper); params[0] is the
+ * bandwidth h or the length scale l:
+ *   H2_COULOMB      1/|x-y|, with kappa(x,x) = 0
+ *   H2_GAUSSIAN     exp(-|x-y|^2 / h^2)
+ *   H2_EXPONENTIAL  exp(-|x-y| / l)
+ *   H2_MATERN32     (1 + sqrt(3)|x-y|/l) exp(-sqrt(3)|x-y|/l)            */
+typedef enum { H2_COULOMB = 0, H2_GAUSSIAN = 1, H2_EXPONENTIAL = 2, H2_MATERN32 = 3 } h2_kernel_id;
+
+/* Build options (h2_options_default fills the defaults).
+ *   tau            separation ratio of Eq. (separation), 0 < tau < 1; default 0.7
+ *   r1, r2         maximum sizes of X_i^* and Y_i^* (Algorithm 1); 0 = choose
+ *                  them from the tolerance (Section 4.2); > 0 = use as given
+ *   precision      64: FP64 throughout (the only value accepted by this build)
+ *   store_coupling 1: store the coupling and nearfield blocks (default)
+ *   calib_seed     seed of the random points used to choose r1, r2          */
+typedef struct {
+    double tau;
+    int r1, r2;
+    int precision;
+    int store_coupling;
+    uint64_t calib_seed;
+} h2_options;
+
+void h2_options_default(h2_options *opt);
+
+/* h2_build: Algorithm 2 of the paper.
+ *   points     device, FP64, SoA layout [dim][n] (points[k*n + i] is
+ *              coordinate k of point i), original order.  Read during the
+ *              call only; the library keeps its own permuted copy.
+ *   n          number of points, n >= 1 (and n < 2^31)
+ *   dim        1, 2 or 3
+ *   kernel_id  an h2_kernel_id
+ *   params     host, params[0] = bandwidth / length scale (ignored for Coulomb,
+ *              may then be NULL); must be finite and > 0 when used
+ *   tol        approximation tolerance eps, 0 < tol < 1
+ *   leaf_size  maximum number of points q of a leaf, >= 1
+ *   out        receives the handle; set to NULL on failure (nothing leaks)
+ * The call synchronises the current stream (level sizes are read back).   */
+h2_status h2_build(const double *points, int64_t n, int dim, int kernel_id, const double *params,
+                   double tol, int leaf_size, h2_handle *out);
+
+/* As h2_build, with options (NULL = defaults) and a HIP stream (NULL = the
+ * default stream) on which all work is ordered.                          */
+h2_status h2_build_ex(const double *points, int64_t n, int dim, int kernel_id, const double *params,
+                      double tol, int leaf_size, const h2_options *opt, void *hip_stream, h2_handle *out);
+
+/* h2_matvec: y = Ktilde x with the H^2 representation (upward, coupling,
+ * downward and nearfield sweeps).
+ *   x, y   device, FP64, [nrhs][n] (x[r*n + i] is entry i of right-hand side
+ *          r), original point order; x and y must not overlap
+ *   nrhs   number of right-hand sides, 1 <= nrhs <= 256
+ * Stream-ordered on the handle's stream; returns without synchronising
+ * except on the first call with a larger nrhs (workspace allocation).    */
+h2_status h2_matvec(h2_handle h, const double *x, double *y, int nrhs);
+h2_status h2_matvec_ex(h2_handle h, const double *x, double *y, int nrhs, void *hip_stream);
+
+/* Summary of a built representation (all host values). */
+typedef struct {
+    int64_t n;
+    int dim, kernel_id;
+    int nnode, maxdepth, nleaf;
+    int r1, r2;
+    int64_t nnz_il, nnz_near; /* interaction-list and near-list entries */
+    int max_rank;
+    int64_t sum_rank;
+    int64_t bytes_U, bytes_B, bytes_D; /* stored interpolation, coupling, nearfield */
+    double t_tree, t_lists, t_calib, t_hidr, t_basis, t_blocks; /* seconds */
+} h2_info;
+
+h2_status h2_query(h2_handle h, h2_info *info);
+
+/* h2_export: copy one internal array to host memory for inspection and
+ * parity tests.  `what` selects the array (H2_EXP_*); for the per-node
+ * variable-length lists, `node` selects the node, otherwise it is ignored.
+ * Point indices are tree positions (perm maps them to original indices).
+ * If host_buf is NULL only the element count is returned in *count.
+ * Otherwise `bytes` must hold the whole array.                            */
+enum {
+    H2_EXP_PERM = 0,        /* int32 [n] tree position -> original index */
+    H2_EXP_PARENT = 1,      /* int32 [nnode] */
+    H2_EXP_FIRST_CHILD = 2, /* int32 [nnode] (-1 for leaves) */
+    H2_EXP_NCHILD = 3,      /* int32 [nnode] */
+    H2_EXP_START = 4,       /* int32 [nnode] first tree position */
+    H2_EXP_COUNT = 5,       /* int32 [nnode] */
+    H2_EXP_DEPTH = 6,       /* int32 [nnode] */
+    H2_EXP_CENTER = 7,      /* double [nnode][dim] */
+    H2_EXP_SIDE = 8,        /* double [nnode] */
+    H2_EXP_IL_PTR = 9,      /* int32 [nnode+1] */
+    H2_EXP_IL_COL = 10,     /* int32 [nnz_il] */
+    H2_EXP_NEAR_PTR = 11,   /* int32 [nnode+1] */
+    H2_EXP_NEAR_COL = 12,   /* int32 [nnz_near] */
+    H2_EXP_XSTAR = 13,      /* int32 list of node `node` */
+    H2_EXP_YSTAR = 14,      /* int32 list of node `node` */
+    H2_EXP_RANK = 15,       /* int32 [nnode] */
+    H2_EXP_MBAR = 16,       /* int32 [nnode] rows of the node's ID problem */
+    H2_EXP_PIV = 17,        /* int32 list of node `node` (mbar entries) */
+    H2_EXP_SKEL = 18,       /* int32 list of node `node` (rank entries) */
+    H2_EXP_T = 19,          /* double, node `node`: rank x (mbar-rank) row-major */
+    H2_EXP_POINTS = 20,     /* double [dim][n] SoA, tree order */
+    H2_EXP_B = 21,          /* double, IL entry `node` (CSR index): rank_i x rank_j row-major */
+    H2_EXP_CALIB_R = 22     /* int32 [maxdepth+1] r chosen per depth (0 if not calibrated) */
+};
+h2_status h2_export(h2_handle h, int what, int node, void *host_buf, size_t bytes, int64_t *count);
+
+/* Release a handle and all its device memory.  NULL is accepted. */
+h2_status h2_destroy(h2_handle h);
+
+/* Message of the last non-OK status returned on this thread. */
+const char *h2_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* H2_MI355X_H */

@@ -1,0 +1,224 @@
+// Internal declarations shared by the HIP sources of the H^2 library.
+// Nothing here is part of the public C ABI (see include/h2.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/h2.h"
+
+namespace h2 {
+
+// ------------------------------------------------------------------ errors
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define H2_HIP(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            throw ::h2::Error{H2_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define H2_LAUNCH_CHECK() H2_HIP(hipGetLastError())
+
+inline void fail(int code, const std::string& m) { throw Error{code, m}; }
+
+// ------------------------------------------------------------------ device memory
+// A plain owning device buffer.  Allocation failures surface as H2_ENOMEM.
+template <class T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    ~DBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    // (Re)allocate to hold at least cnt elements; contents are not kept.
+    void ensure(size_t cnt)
+    {
+        if (cnt <= n && p) return;
+        release();
+        size_t bytes = (cnt ? cnt : 1) * sizeof(T);
+        if (hipMalloc((void**)&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            fail(H2_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        }
+        n = cnt ? cnt : 1;
+    }
+    // Grow to at least cnt elements keeping the first `keep` elements.
+    void grow_keep(size_t cnt, size_t keep, hipStream_t s)
+    {
+        if (cnt <= n && p) return;
+        size_t nc = n ? n : 16;
+        while (nc < cnt) nc *= 2;
+        T* q = nullptr;
+        if (hipMalloc((void**)&q, nc * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(H2_ENOMEM, "device allocation of " + std::to_string(nc * sizeof(T)) + " bytes failed");
+        }
+        if (p && keep) H2_HIP(hipMemcpyAsync(q, p, keep * sizeof(T), hipMemcpyDeviceToDevice, s));
+        H2_HIP(hipStreamSynchronize(s));
+        release();
+        p = q;
+        n = nc;
+    }
+};
+
+template <class T>
+inline T read_scalar(const T* dptr, hipStream_t s)
+{
+    T v;
+    H2_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+    H2_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+template <class T>
+inline std::vector<T> read_vec(const T* dptr, size_t cnt, hipStream_t s)
+{
+    std::vector<T> v(cnt);
+    if (cnt) {
+        H2_HIP(hipMemcpyAsync(v.data(), dptr, cnt * sizeof(T), hipMemcpyDeviceToHost, s));
+        H2_HIP(hipStreamSynchronize(s));
+    }
+    return v;
+}
+
+inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// ------------------------------------------------------------------ scan (scan.hip)
+// Exclusive prefix sums.  out has cnt+1 entries; out[cnt] is the total.
+// `tmp` is scratch resized as needed.  Deterministic (integer arithmetic).
+void scan_excl_i32(const int* in, int* out, int64_t cnt, DBuf<int>& tmp, hipStream_t s);
+void scan_excl_i64(const int64_t* in, int64_t* out, int64_t cnt, DBuf<int64_t>& tmp, hipStream_t s);
+
+// ------------------------------------------------------------------ handle
+struct Handle {
+    // problem
+    int64_t n = 0;
+    int d = 0, kid = 0;
+    double prm = 1.0;
+    double tol = 1e-6;      // user tolerance eps
+    double tol_int = 5e-7;  // construction tolerance eps' = eps / 2
+    double tau = 0.7;
+    int q = 64;
+    int r1 = 0, r2 = 0;
+    int precision = 64;
+    int store_coupling = 1;
+    uint64_t calib_seed = 0x5EED;
+    hipStream_t stream = nullptr;
+
+    // tree: nodes in BFS order (depth, parent, child code)
+    int nnode = 0, maxdepth = 0;
+    std::vector<int> lvl_ptr;  // host copy: nodes of depth L are lvl_ptr[L]..lvl_ptr[L+1]-1
+    DBuf<int> parent, first_child, nchild, start, count, depth;
+    DBuf<double> center;  // [cap][d]
+    DBuf<double> side;
+    DBuf<double> pts;  // [d][n] SoA, tree order
+    DBuf<int> perm;    // tree position -> original index
+    std::vector<int> h_nchild, h_first_child, h_start, h_count, h_parent;  // host mirrors (small)
+
+    // lists (CSR, columns ascending)
+    int64_t nil = 0, nnear = 0;
+    DBuf<int> il_ptr, il_col, nr_ptr, nr_col;
+    std::vector<int> h_il_ptr, h_nr_ptr;
+
+    // HiDR representor sets, fixed stride per node
+    DBuf<int> xs_cnt, xs_idx;  // stride r1
+    DBuf<int> ys_cnt, ys_idx;  // stride r2
+    std::vector<int> calib_r;
+    std::vector<double> calib_err;
+
+    // bases
+    DBuf<int> rank, mbar;
+    std::vector<int> h_rank, h_mbar;
+    DBuf<int> skel;         // stride r2: skeleton tree positions in pivot order
+    DBuf<int64_t> piv_off;  // per node offset into piv
+    DBuf<int> piv;          // per node m_i entries
+    DBuf<int64_t> T_off;    // per node offset into T (row-major k x (m-k))
+    DBuf<double> T;
+    std::vector<int64_t> h_piv_off, h_T_off;
+
+    // coupling and nearfield blocks
+    DBuf<int64_t> B_off;  // per IL entry (CSR order), size nil+1
+    DBuf<double> B;
+    DBuf<int64_t> D_off;  // per near entry, size nnear+1
+    DBuf<double> D;
+    DBuf<int64_t> xh_off;  // per node offset (in units of rank) into xhat/yhat
+    DBuf<int> leaves;      // leaf node ids
+    int64_t sum_rank = 0;
+
+    // matvec workspace (sized for the largest nrhs seen)
+    int mv_nrhs = 0;
+    DBuf<double> xt, yt, xh, yh;
+
+    // diagnostics
+    double t_tree = 0, t_lists = 0, t_calib = 0, t_hidr = 0, t_basis = 0, t_blocks = 0;
+    int64_t bytes_B = 0, bytes_D = 0, bytes_T = 0;
+
+    // scratch
+    DBuf<int> tmp_i32;
+    DBuf<int64_t> tmp_i64;
+};
+
+// ------------------------------------------------------------------ phases
+void build_tree(Handle& h, const double* pts_in);                // tree.hip
+void build_lists(Handle& h);                                      // lists.hip
+void run_calibration(Handle& h);                                  // calib.hip
+void run_hidr(Handle& h);                                         // hidr.hip
+void build_bases(Handle& h);                                      // basis.hip
+void build_blocks(Handle& h);                                     // blocks.hip
+void matvec(Handle& h, const double* x, double* y, int nrhs, hipStream_t s);  // matvec.hip
+
+// DataReduct over materialised index lists (hidr.hip); used by HiDR and by
+// the calibration.  For each of `nlist` lists (indices into the SoA point
+// array pts with leading dimension ld), writes up to k selected indices to
+// out[list * out_stride ...] and the count to out_cnt[list].
+void datareduct_lists(const double* pts, int64_t ld, int d, const int64_t* list_off, const int* list_idx,
+                      int nlist, int k, int* out, int out_stride, int* out_cnt, hipStream_t s);
+
+// Batched ID (basis.hip): one problem per entry.  Problem p has rows X
+// (m_p indices into pts) and columns Y (s_p indices into pts2); the kernel
+// matrix is evaluated and compressed with the column-pivoted QR rule.
+struct IdBatch {
+    int nprob = 0;
+    const int* m = nullptr;          // [nprob]
+    const int* s = nullptr;          // [nprob]
+    const int64_t* x_off = nullptr;  // [nprob] offsets into x_idx
+    const int* x_idx = nullptr;
+    const int64_t* y_off = nullptr;
+    const int* y_idx = nullptr;
+    const double* xpts = nullptr;  // SoA [d][xld]
+    int64_t xld = 0;
+    const double* ypts = nullptr;  // SoA [d][yld]
+    int64_t yld = 0;
+    const int64_t* M_off = nullptr;  // workspace offsets (s_p * m_p doubles each)
+    double* M = nullptr;
+    double* nu = nullptr;            // workspace, 2*m_p doubles per problem at nu_off
+    const int64_t* nu_off = nullptr;
+    double tol = 0;
+    int* rank_out = nullptr;         // [nprob]
+    int* piv_out = nullptr;          // at piv_off[p], m_p entries
+    const int64_t* piv_off = nullptr;
+    double* T_out = nullptr;         // at T_off[p]
+    const int64_t* T_off = nullptr;
+    int* skel_out = nullptr;         // at p*skel_stride, k_p entries (x indices)
+    int skel_stride = 0;
+};
+void batched_id(const IdBatch& b, int d, int kid, double prm, hipStream_t s);
+
+}  // namespace h2

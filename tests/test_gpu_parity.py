@@ -1,0 +1,208 @@
+"""Parity of the HIP library (through the C ABI) with the CPU oracle.
+
+Integer and index results (tree, permutation, lists, representor sets,
+ranks, pivots, skeletons) must be bit-identical; geometry (box centres and
+sides) too.  Floating point: the FP64 H^2 product agrees to 1e-10 relative,
+and the product against the dense K x to the tolerance of the build.
+
+The interpolation matrices T = R11^{-1} R12 are bit-identical for Coulomb
+(every kernel entry is a correctly rounded sqrt and division on both sides,
+and the QR runs in the oracle's operation order).  For the exp-based kernels
+the device and host exp differ in the last bit; the triangular solve
+amplifies that by cond(R11) <~ |R_00|/|R_kk| < 1/tol', so T is compared to
+10 u / tol' relative (u = 2^-53 * 2, tol' the construction tolerance).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2206_01885_amd import workloads as W
+
+U_ROUND = 2.220446049250313e-16
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_01885_amd import h2
+    h2.lib()
+    return h2
+
+
+def _build(H, P, kernel, prm, tol, leaf, r=0, oracle=True):
+    g = H.H2Matrix(P, kernel, prm, tol, leaf, r1=r, r2=r)
+    o = O.H2Oracle(P, kernel, prm, tol=tol, leaf=leaf, r1=r, r2=r) if oracle else None
+    return g, o
+
+
+def _compare_structure(g, o):
+    d = g.d
+    for name in ("perm", "parent", "first_child", "nchild", "start", "count", "depth", "il_ptr",
+                 "il_col", "near_ptr", "near_col"):
+        a, b = g.export(name), o.get(name)
+        assert np.array_equal(a, b), name
+    assert np.array_equal(g.export("center").reshape(-1, d), o.get("center"))
+    assert np.array_equal(g.export("side"), o.get("side"))
+    pts = g.export("points").reshape(d, -1).T
+    assert np.array_equal(pts, o.get("points"))
+
+
+def _compare_reduction_and_bases(g, o, t_rtol=None, tol=1e-6):
+    if t_rtol is None:
+        t_rtol = 10.0 * U_ROUND / (0.5 * tol)
+    gi, oi = g.info(), o.info()
+    assert (gi["r1"], gi["r2"]) == (oi["r1"], oi["r2"])
+    nn = oi["nnode"]
+    bad = {"xstar": 0, "ystar": 0, "rank": 0, "piv": 0, "skel": 0}
+    for i in range(1, nn):
+        for name in ("xstar", "ystar"):
+            if not np.array_equal(g.export(name, i), o.node_list(name, i)):
+                bad[name] += 1
+    grank, orank = g.export("rank"), o.get("rank")
+    bad["rank"] = int(np.sum(grank != orank))
+    assert np.array_equal(g.export("mbar"), o.get("mbar"))
+    tmax = 0.0
+    for i in range(1, nn):
+        if grank[i] != orank[i]:
+            continue
+        if not np.array_equal(g.export("piv", i), o.node_list("piv", i)):
+            bad["piv"] += 1
+            continue
+        if not np.array_equal(g.export("skel", i), o.node_list("skel", i)):
+            bad["skel"] += 1
+        Tg, To = g.export("T", i), o.node_T(i).ravel()
+        if To.size:
+            tmax = max(tmax, np.max(np.abs(Tg - To)) / max(np.max(np.abs(To)), 1e-300))
+    _say(f"mismatching nodes: {bad}, max rel |T diff| {tmax:.3e}")
+    assert all(v == 0 for v in bad.values()), bad
+    assert tmax <= t_rtol
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_small_coulomb_full_parity(H):
+    """n = 4096 uniform in [0,1]^3, Coulomb, leaf 64, tol 1e-6."""
+    c = W.config_small_coulomb()
+    _say("cube3d-coulomb-n4096 build")
+    g, o = _build(H, c["points"], c["kernel"], c["prm"], c["tol"], c["leaf"])
+    _compare_structure(g, o)
+    _compare_reduction_and_bases(g, o, t_rtol=0.0)
+    _say("cube3d-coulomb-n4096 matvec")
+    yg = g.matvec(c["x"]).cpu().numpy()
+    yo = o.matvec(c["x"])
+    ref = O.dense_rows(c["points"], c["kernel"], c["prm"], c["x"])
+    e_or, e_de = _rel(yg, yo), _rel(yg, ref)
+    _say(f"e_oracle {e_or:.3e} e_dense {e_de:.3e}")
+    assert e_or <= 1e-10
+    assert e_de <= c["tol"]
+
+
+def test_gaussian_2d_parity(H):
+    """n = 65536 uniform in [0,1]^2, Gaussian h = 0.1, leaf 128, tol 1e-8, 16 RHS."""
+    c = W.config_gaussian_2d()
+    _say("square2d-gaussian-n65536 build")
+    g, o = _build(H, c["points"], c["kernel"], c["prm"], c["tol"], c["leaf"])
+    _compare_structure(g, o)
+    _compare_reduction_and_bases(g, o, tol=c["tol"])
+    _say("square2d-gaussian-n65536 matvec x16")
+    yg = g.matvec(c["x"]).cpu().numpy()
+    yo = o.matvec(c["x"])
+    worst = max(_rel(yg[r], yo[r]) for r in range(16))
+    _say(f"max e_oracle over RHS {worst:.3e}")
+    assert worst <= 1e-10
+    rows = c["rows"]
+    ref = O.dense_rows(c["points"], c["kernel"], c["prm"], c["x"], rows=rows)
+    e_de = max(_rel(yg[r, rows], ref[r]) for r in range(16))
+    _say(f"max e_dense on 1000 sampled rows {e_de:.3e}")
+
+
+@pytest.mark.parametrize("d,kernel,prm,n,leaf", [
+    (3, "coulomb", 1.0, 3333, 32), (3, "exponential", 0.2, 2500, 40), (3, "matern32", 0.2, 2049, 64),
+    (2, "gaussian", 0.1, 5000, 50), (2, "coulomb", 1.0, 1777, 17), (1, "exponential", 0.3, 3001, 16),
+    (1, "coulomb", 1.0, 1000, 1),
+])
+def test_kernels_and_dimensions(H, d, kernel, prm, n, leaf):
+    rng = np.random.default_rng(n + d)
+    P = rng.random((n, d)) ** 1.5  # non-uniform density: adaptive tree, mixed-level lists
+    x = rng.standard_normal((3, n))
+    _say(f"{kernel}-d{d}-n{n}-leaf{leaf}")
+    g, o = _build(H, P, kernel, prm, 1e-6, leaf)
+    _compare_structure(g, o)
+    _compare_reduction_and_bases(g, o)
+    yg = g.matvec(x).cpu().numpy()
+    assert _rel(yg, o.matvec(x)) <= 1e-10
+
+
+def test_exact_limit_against_dense(H):
+    """r1 = r2 >= n and a rounding-level tolerance: the GPU H^2 product equals
+    the dense product."""
+    rng = np.random.default_rng(7)
+    n = 1500
+    P = rng.random((n, 3))
+    x = rng.standard_normal((2, n))
+    _say("exact-limit coulomb n1500")
+    g = H.H2Matrix(P, "coulomb", 1.0, 1e-15, 24, r1=n, r2=n)
+    y = g.matvec(x).cpu().numpy()
+    assert _rel(y, O.dense_rows(P, "coulomb", 1.0, x)) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["n1", "root_leaf", "duplicates", "collinear", "two_clusters"])
+def test_degenerate_inputs(H, case):
+    rng = np.random.default_rng(11)
+    if case == "n1":
+        P = rng.random((1, 3))
+    elif case == "root_leaf":
+        P = rng.random((50, 3))
+    elif case == "duplicates":
+        P = np.vstack([rng.random((200, 3)), np.repeat(rng.random((1, 3)), 100, axis=0)])
+    elif case == "collinear":
+        t = rng.random(2000)
+        P = np.stack([t, np.zeros_like(t), np.zeros_like(t)], axis=1)
+    else:
+        P = np.vstack([rng.random((1000, 3)) * 1e-3, rng.random((1000, 3)) * 1e-3 + 5.0])
+    n = len(P)
+    x = rng.standard_normal((1, n))
+    _say(f"degenerate {case} n{n}")
+    g, o = _build(H, P, "coulomb", 1.0, 1e-6, 8 if case != "root_leaf" else 64)
+    _compare_structure(g, o)
+    _compare_reduction_and_bases(g, o)
+    yg = g.matvec(x).cpu().numpy()
+    yo = o.matvec(x)
+    if np.linalg.norm(yo) == 0:
+        assert np.linalg.norm(yg) == 0
+    else:
+        assert _rel(yg, yo) <= 1e-10
+
+
+def test_deterministic_rebuild(H):
+    c = W.config_small_coulomb()
+    g1 = H.H2Matrix(c["points"], "coulomb", 1.0, 1e-6, 64)
+    g2 = H.H2Matrix(c["points"], "coulomb", 1.0, 1e-6, 64)
+    for name in ("perm", "il_col", "near_col", "rank"):
+        assert np.array_equal(g1.export(name), g2.export(name))
+    y1 = g1.matvec(c["x"]).cpu().numpy()
+    y2 = g2.matvec(c["x"]).cpu().numpy()
+    assert _rel(y1, y2) <= 1e-14
+
+
+def test_invalid_points_rejected(H):
+    import torch
+    P = np.random.default_rng(3).random((100, 3))
+    P[17, 1] = np.nan
+    with pytest.raises(H.H2Error) as ei:
+        H.H2Matrix(P, "coulomb", 1.0, 1e-6, 16)
+    assert ei.value.status == H.H2_EINVAL
+    torch.cuda.synchronize()

@@ -1,0 +1,64 @@
+"""The C-ABI library builds, loads and exports every symbol of include/h2.h;
+argument validation rejects bad input before any device work.  No GPU needed."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "h2.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(h2_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("h2_build", "h2_build_ex", "h2_matvec", "h2_matvec_ex", "h2_query", "h2_export",
+                 "h2_destroy", "h2_last_error", "h2_options_default"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2206_01885_amd import h2
+    L = h2.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert sorted(h2.SYMBOLS) == declared_functions()
+
+
+def test_validation_without_device_work():
+    from paper_2206_01885_amd import h2
+    L = h2.lib()
+    out = C.c_void_p(123)
+    dummy = C.c_void_p(8)  # never dereferenced: validation fails first
+    prm = (C.c_double * 1)(0.1)
+    cases = [
+        (dummy, 0, 3, 0, prm, 1e-6, 64),      # n < 1
+        (dummy, 10, 4, 0, prm, 1e-6, 64),     # dim
+        (dummy, 10, 3, 7, prm, 1e-6, 64),     # kernel id
+        (dummy, 10, 3, 0, prm, 0.0, 64),      # tol
+        (dummy, 10, 3, 0, prm, 1.5, 64),      # tol
+        (dummy, 10, 3, 0, prm, 1e-6, 0),      # leaf
+        (None, 10, 3, 0, prm, 1e-6, 64),      # NULL points
+        (dummy, 10, 3, 1, None, 1e-6, 64),    # Gaussian without params
+    ]
+    for args in cases:
+        st = L.h2_build(*args, C.byref(out))
+        assert st == h2.H2_EINVAL, args
+        assert out.value is None
+        assert len(L.h2_last_error()) > 0
+    bad = (C.c_double * 1)(float("nan"))
+    assert L.h2_build(dummy, 10, 3, 1, bad, 1e-6, 64, C.byref(out)) == h2.H2_EINVAL
+    opt = h2.h2_options_default()
+    assert opt.tau == 0.7 and opt.precision == 64 and opt.r1 == 0
+    opt.tau = 1.0
+    assert L.h2_build_ex(dummy, 10, 3, 0, prm, 1e-6, 64, C.byref(opt), None, C.byref(out)) == h2.H2_EINVAL
+    opt.tau, opt.precision = 0.7, 16
+    assert L.h2_build_ex(dummy, 10, 3, 0, prm, 1e-6, 64, C.byref(opt), None, C.byref(out)) == h2.H2_EUNSUPPORTED
+    assert L.h2_matvec(None, dummy, dummy, 1) == h2.H2_EINVAL
+    assert L.h2_destroy(None) == h2.H2_OK
