@@ -51,13 +51,16 @@ typedef enum { H2_COULOMB = 0, H2_GAUSSIAN = 1, H2_EXPONENTIAL = 2, H2_MATERN32 
  *                  them from the tolerance (Section 4.2); > 0 = use as given
  *   precision      64: FP64 throughout (the only value accepted by this build)
  *   store_coupling 1: store the coupling and nearfield blocks (default)
- *   calib_seed     seed of the random points used to choose r1, r2          */
+ *   calib_seed     seed of the random points used to choose r1, r2
+ *   profile        1: h2_matvec records HIP events around each of its sweeps on
+ *                  its stream; h2_query then reports the last apply's times  */
 typedef struct {
     double tau;
     int r1, r2;
     int precision;
     int store_coupling;
     uint64_t calib_seed;
+    int profile;
 } h2_options;
 
 void h2_options_default(h2_options *opt);
@@ -104,6 +107,10 @@ typedef struct {
     int64_t sum_rank;
     int64_t bytes_U, bytes_B, bytes_D; /* stored interpolation, coupling, nearfield */
     double t_tree, t_lists, t_calib, t_hidr, t_basis, t_blocks; /* seconds */
+    /* last h2_matvec with options.profile = 1 (milliseconds, HIP events on the
+     * apply's stream; h2_query waits for that apply to finish); 0 otherwise */
+    double mv_gather, mv_upward, mv_coupling, mv_downward, mv_leaves, mv_scatter;
+    int mv_nrhs;
 } h2_info;
 
 h2_status h2_query(h2_handle h, h2_info *info);

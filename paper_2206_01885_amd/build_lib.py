@@ -14,7 +14,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Sources whose arithmetic must round exactly as written (geometry, the ID,
 # block evaluation) are compiled without FMA contraction.
 EXACT = {"tree.hip", "lists.hip", "hidr.hip", "basis.hip", "calib.hip", "blocks.hip"}
-SOURCES = ["scan.hip", "tree.hip", "lists.hip", "hidr.hip", "calib.hip", "basis.hip", "blocks.hip",
+SOURCES = ["alloc.hip", "scan.hip", "tree.hip", "lists.hip", "hidr.hip", "calib.hip", "basis.hip", "blocks.hip",
            "matvec.hip", "api.hip"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

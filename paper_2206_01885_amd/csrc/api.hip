@@ -30,7 +30,7 @@ double now_s()
 template <class T>
 void upload_vec(h2::DBuf<T>& dst, const std::vector<T>& src, hipStream_t s)
 {
-    dst.ensure(src.size());
+    dst.ensure(src.size(), s);
     if (!src.empty())
         H2_HIP(hipMemcpyAsync(dst.p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
     H2_HIP(hipStreamSynchronize(s));
@@ -49,6 +49,7 @@ void h2_options_default(h2_options* opt)
     opt->precision = 64;
     opt->store_coupling = 1;
     opt->calib_seed = 0x5EED;
+    opt->profile = 0;
 }
 
 const char* h2_last_error(void) { return g_last_error.c_str(); }
@@ -100,6 +101,7 @@ h2_status h2_build_ex(const double* points, int64_t n, int dim, int kernel_id, c
     h.precision = opt.precision;
     h.store_coupling = opt.store_coupling;
     h.calib_seed = opt.calib_seed;
+    h.profile = opt.profile;
     h.stream = (hipStream_t)hip_stream;
     try {
         double t0 = now_s();
@@ -167,7 +169,7 @@ h2_status h2_matvec_ex(h2_handle hd, const double* x, double* y, int nrhs, void*
 h2_status h2_query(h2_handle hd, h2_info* info)
 {
     if (!hd || !info) return set_err(H2_EINVAL, "NULL argument");
-    const h2::Handle& h = hd->h;
+    h2::Handle& h = hd->h;
     std::memset(info, 0, sizeof(*info));
     info->n = h.n;
     info->dim = h.d;
@@ -195,6 +197,20 @@ h2_status h2_query(h2_handle hd, h2_info* info)
     info->t_hidr = h.t_hidr;
     info->t_basis = h.t_basis;
     info->t_blocks = h.t_blocks;
+    if (h.prof_valid) {
+        float ms[6];
+        if (hipEventSynchronize(h.ev[6]) != hipSuccess) return set_err(H2_EDEVICE, "event wait failed");
+        for (int e = 0; e < 6; ++e)
+            if (hipEventElapsedTime(&ms[e], h.ev[e], h.ev[e + 1]) != hipSuccess)
+                return set_err(H2_EDEVICE, "event timing failed");
+        info->mv_gather = ms[0];
+        info->mv_upward = ms[1];
+        info->mv_coupling = ms[2];
+        info->mv_downward = ms[3];
+        info->mv_leaves = ms[4];
+        info->mv_scatter = ms[5];
+        info->mv_nrhs = h.prof_nrhs;
+    }
     return H2_OK;
 }
 
@@ -287,6 +303,8 @@ h2_status h2_destroy(h2_handle hd)
 {
     if (!hd) return H2_OK;
     (void)hipStreamSynchronize(hd->h.stream);
+    for (auto& e : hd->h.ev)
+        if (e) (void)hipEventDestroy(e);
     delete hd;
     return H2_OK;
 }

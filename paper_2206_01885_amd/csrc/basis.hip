@@ -223,7 +223,7 @@ void batched_id(const IdBatch& b, int d, int kid, double prm, hipStream_t s)
 template <class T>
 static void upload(DBuf<T>& dst, const std::vector<T>& src, hipStream_t s)
 {
-    dst.ensure(src.size());
+    dst.ensure(src.size(), s);
     if (!src.empty())
         H2_HIP(hipMemcpyAsync(dst.p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
@@ -233,11 +233,11 @@ void build_bases(Handle& h)
     hipStream_t s = h.stream;
     const int nn = h.nnode;
     if (h.r2 > MAXS) fail(H2_EUNSUPPORTED, "r2 above 4096");
-    h.rank.ensure((size_t)nn);
-    h.mbar.ensure((size_t)nn);
-    h.skel.ensure((size_t)nn * h.r2);
-    h.piv_off.ensure((size_t)nn + 1);
-    h.T_off.ensure((size_t)nn + 1);
+    h.rank.ensure((size_t)nn, s);
+    h.mbar.ensure((size_t)nn, s);
+    h.skel.ensure((size_t)nn * h.r2, s);
+    h.piv_off.ensure((size_t)nn + 1, s);
+    h.T_off.ensure((size_t)nn + 1, s);
     H2_HIP(hipMemsetAsync(h.rank.p, 0, sizeof(int) * nn, s));
     H2_HIP(hipMemsetAsync(h.mbar.p, 0, sizeof(int) * nn, s));
     std::vector<int> ys_cnt = read_vec(h.ys_cnt.p, nn, s);
@@ -308,9 +308,9 @@ void build_bases(Handle& h)
             upload(d_nuoff, nuoff, s);
             upload(d_pivoff, pivoff, s);
             upload(d_Toff, Toff, s);
-            d_xidx.ensure((size_t)std::max<int64_t>(xo, 1));
-            Mws.ensure((size_t)std::max<int64_t>(ws, 1));
-            nuws.ensure((size_t)std::max<int64_t>(no, 1));
+            d_xidx.ensure((size_t)std::max<int64_t>(xo, 1), s);
+            Mws.ensure((size_t)std::max<int64_t>(ws, 1), s);
+            nuws.ensure((size_t)std::max<int64_t>(no, 1), s);
             k_xbar_fill<<<np, TB, 0, s>>>(c0, h.nchild.p, h.first_child.p, h.start.p, h.count.p, h.rank.p, h.skel.p,
                                           h.r2, d_xoff.p, d_xidx.p);
             H2_LAUNCH_CHECK();

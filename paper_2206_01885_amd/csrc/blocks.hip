@@ -71,16 +71,16 @@ void build_blocks(Handle& h)
 {
     hipStream_t s = h.stream;
     const int nn = h.nnode;
-    h.B_off.ensure((size_t)h.nil + 1);
-    h.D_off.ensure((size_t)h.nnear + 1);
+    h.B_off.ensure((size_t)h.nil + 1, s);
+    h.D_off.ensure((size_t)h.nnear + 1, s);
     DBuf<int64_t> sz;
-    sz.ensure((size_t)std::max<int64_t>(std::max(h.nil, h.nnear), 1));
+    sz.ensure((size_t)std::max<int64_t>(std::max(h.nil, h.nnear), 1), s);
     // coupling
     k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, h.il_col.p, h.rank.p, sz.p);
     H2_LAUNCH_CHECK();
     scan_excl_i64(sz.p, h.B_off.p, h.nil, h.tmp_i64, s);
     int64_t nB = read_scalar(h.B_off.p + h.nil, s);
-    h.B.ensure((size_t)std::max<int64_t>(nB, 1));
+    h.B.ensure((size_t)std::max<int64_t>(nB, 1), s);
     h.bytes_B = nB * (int64_t)sizeof(double);
     k_coupling<<<nn, TB, 0, s>>>(h.pts.p, h.n, h.d, h.kid, h.prm, h.il_ptr.p, h.il_col.p, h.rank.p, h.skel.p, h.r2,
                                  h.B_off.p, h.B.p);
@@ -90,7 +90,7 @@ void build_blocks(Handle& h)
     H2_LAUNCH_CHECK();
     scan_excl_i64(sz.p, h.D_off.p, h.nnear, h.tmp_i64, s);
     int64_t nD = read_scalar(h.D_off.p + h.nnear, s);
-    h.D.ensure((size_t)std::max<int64_t>(nD, 1));
+    h.D.ensure((size_t)std::max<int64_t>(nD, 1), s);
     h.bytes_D = nD * (int64_t)sizeof(double);
     k_near<<<nn, TB, 0, s>>>(h.pts.p, h.n, h.d, h.kid, h.prm, h.nr_ptr.p, h.nr_col.p, h.start.p, h.count.p,
                              h.D_off.p, h.D.p);

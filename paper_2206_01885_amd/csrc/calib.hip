@@ -147,10 +147,10 @@ void run_calibration(Handle& h)
     int rmax = 1;
     if (nset > 0) {
         DBuf<double> dsides, Z;
-        dsides.ensure(nset);
+        dsides.ensure(nset, s);
         H2_HIP(hipMemcpyAsync(dsides.p, sides.data(), sizeof(double) * nset, hipMemcpyHostToDevice, s));
         const int64_t ld = (int64_t)nset * 2 * NZ;
-        Z.ensure((size_t)d * ld);
+        Z.ensure((size_t)d * ld, s);
         k_points<<<blocks_for(ld, TB), TB, 0, s>>>(nset, dsides.p, d, h.tau, h.calib_seed, Z.p);
         H2_LAUNCH_CHECK();
 
@@ -168,18 +168,18 @@ void run_calibration(Handle& h)
                 if (open[t]) sets.push_back(t);
             if (sets.empty()) break;
             const int np = (int)sets.size();
-            set_of.ensure(np);
+            set_of.ensure(np, s);
             H2_HIP(hipMemcpyAsync(set_of.p, sets.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
-            z2idx.ensure((size_t)np * NZ);
-            z1idx.ensure((size_t)np * NZ);
-            zoff.ensure((size_t)np + 1);
-            xoff.ensure((size_t)np + 1);
-            mm.ensure(np);
+            z2idx.ensure((size_t)np * NZ, s);
+            z1idx.ensure((size_t)np * NZ, s);
+            zoff.ensure((size_t)np + 1, s);
+            xoff.ensure((size_t)np + 1, s);
+            mm.ensure(np, s);
             k_lists<<<np, TB, 0, s>>>(np, set_of.p, zoff.p, z2idx.p, z1idx.p, xoff.p, mm.p);
             H2_LAUNCH_CHECK();
             const int rs = std::min(r, NZ);  // |Y*| <= min(r, 512)
-            ycnt.ensure(np);
-            yidx.ensure((size_t)np * rs);
+            ycnt.ensure(np, s);
+            yidx.ensure((size_t)np * rs, s);
             datareduct_lists(Z.p, ld, d, zoff.p, z2idx.p, np, r, yidx.p, rs, ycnt.p, s);
             // ID workspaces
             std::vector<int64_t> h_yoff(np), h_Moff(np), h_nuoff(np), h_pivoff(np), h_Toff(np);
@@ -191,7 +191,7 @@ void run_calibration(Handle& h)
                 h_Toff[p] = (int64_t)p * rs * NZ;
             }
             auto up = [&](DBuf<int64_t>& dst, const std::vector<int64_t>& src) {
-                dst.ensure(src.size());
+                dst.ensure(src.size(), s);
                 H2_HIP(hipMemcpyAsync(dst.p, src.data(), sizeof(int64_t) * src.size(), hipMemcpyHostToDevice, s));
             };
             up(yoff, h_yoff);
@@ -199,13 +199,13 @@ void run_calibration(Handle& h)
             up(nuoff, h_nuoff);
             up(pivoff, h_pivoff);
             up(Toff, h_Toff);
-            M.ensure((size_t)np * rs * NZ);
-            nu.ensure((size_t)np * 3 * NZ);
-            T.ensure((size_t)np * rs * NZ);
-            rank.ensure(np);
-            piv.ensure((size_t)np * NZ);
-            skel.ensure((size_t)np * rs);
-            err.ensure(np);
+            M.ensure((size_t)np * rs * NZ, s);
+            nu.ensure((size_t)np * 3 * NZ, s);
+            T.ensure((size_t)np * rs * NZ, s);
+            rank.ensure(np, s);
+            piv.ensure((size_t)np * NZ, s);
+            skel.ensure((size_t)np * rs, s);
+            err.ensure(np, s);
             IdBatch b;
             b.nprob = np;
             b.m = mm.p;

@@ -31,48 +31,55 @@ struct Error {
 inline void fail(int code, const std::string& m) { throw Error{code, m}; }
 
 // ------------------------------------------------------------------ device memory
-// A plain owning device buffer.  Allocation failures surface as H2_ENOMEM.
+// Device allocations go through a small caching layer (alloc.hip): large
+// blocks are kept after release and handed out again to a request of a
+// similar size, so that repeated builds do not pay for mapping ~100 GB of
+// HBM each time.  On allocation failure the cache is emptied and the
+// allocation retried once; a second failure surfaces as H2_ENOMEM.
+void* dev_alloc(size_t bytes);
+// Returns a block; `s` is the stream whose work may still use it (waited for
+// before the block can be handed out again).
+void dev_free(void* p, size_t bytes, hipStream_t s);
+// Releases every cached block back to the runtime.
+void dev_cache_trim();
+
+// A plain owning device buffer.
 template <class T>
 struct DBuf {
     T* p = nullptr;
     size_t n = 0;
+    hipStream_t s = nullptr;
     DBuf() = default;
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
     ~DBuf() { release(); }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) dev_free(p, n * sizeof(T), s);
         p = nullptr;
         n = 0;
     }
     // (Re)allocate to hold at least cnt elements; contents are not kept.
-    void ensure(size_t cnt)
+    void ensure(size_t cnt, hipStream_t stream = nullptr)
     {
         if (cnt <= n && p) return;
         release();
-        size_t bytes = (cnt ? cnt : 1) * sizeof(T);
-        if (hipMalloc((void**)&p, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-            fail(H2_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-        }
-        n = cnt ? cnt : 1;
+        s = stream;
+        size_t c = cnt ? cnt : 1;
+        p = (T*)dev_alloc(c * sizeof(T));
+        n = c;
     }
     // Grow to at least cnt elements keeping the first `keep` elements.
-    void grow_keep(size_t cnt, size_t keep, hipStream_t s)
+    void grow_keep(size_t cnt, size_t keep, hipStream_t stream)
     {
         if (cnt <= n && p) return;
         size_t nc = n ? n : 16;
         while (nc < cnt) nc *= 2;
-        T* q = nullptr;
-        if (hipMalloc((void**)&q, nc * sizeof(T)) != hipSuccess) {
-            (void)hipGetLastError();
-            fail(H2_ENOMEM, "device allocation of " + std::to_string(nc * sizeof(T)) + " bytes failed");
-        }
-        if (p && keep) H2_HIP(hipMemcpyAsync(q, p, keep * sizeof(T), hipMemcpyDeviceToDevice, s));
-        H2_HIP(hipStreamSynchronize(s));
+        T* q = (T*)dev_alloc(nc * sizeof(T));
+        if (p && keep) H2_HIP(hipMemcpyAsync(q, p, keep * sizeof(T), hipMemcpyDeviceToDevice, stream));
+        H2_HIP(hipStreamSynchronize(stream));
         release();
+        s = stream;
         p = q;
         n = nc;
     }
@@ -165,6 +172,12 @@ struct Handle {
     // matvec workspace (sized for the largest nrhs seen)
     int mv_nrhs = 0;
     DBuf<double> xt, yt, xh, yh;
+
+    // optional per-sweep events of the last apply
+    int profile = 0;
+    bool prof_valid = false;
+    int prof_nrhs = 0;
+    hipEvent_t ev[7] = {};
 
     // diagnostics
     double t_tree = 0, t_lists = 0, t_calib = 0, t_hidr = 0, t_basis = 0, t_blocks = 0;

@@ -311,24 +311,24 @@ void run_hidr(Handle& h)
 {
     hipStream_t s = h.stream;
     const int nn = h.nnode;
-    h.xs_cnt.ensure((size_t)nn);
-    h.ys_cnt.ensure((size_t)nn);
-    h.xs_idx.ensure((size_t)nn * h.r1);
-    h.ys_idx.ensure((size_t)nn * h.r2);
+    h.xs_cnt.ensure((size_t)nn, s);
+    h.ys_cnt.ensure((size_t)nn, s);
+    h.xs_idx.ensure((size_t)nn * h.r1, s);
+    h.ys_idx.ensure((size_t)nn * h.r2, s);
     H2_HIP(hipMemsetAsync(h.xs_cnt.p, 0, sizeof(int) * nn, s));
     H2_HIP(hipMemsetAsync(h.ys_cnt.p, 0, sizeof(int) * nn, s));
     DBuf<int64_t> sz, off;
     DBuf<int> list;
     for (int L = h.maxdepth; L >= 1; --L) {
         int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
-        sz.ensure((size_t)nl);
-        off.ensure((size_t)nl + 1);
+        sz.ensure((size_t)nl, s);
+        off.ensure((size_t)nl + 1, s);
         k_up_sizes<<<blocks_for(nl, TB), TB, 0, s>>>(lo, nl, h.nchild.p, h.first_child.p, h.count.p, h.xs_cnt.p,
                                                      sz.p);
         H2_LAUNCH_CHECK();
         scan_excl_i64(sz.p, off.p, nl, h.tmp_i64, s);
         int64_t tot = read_scalar(off.p + nl, s);
-        list.ensure((size_t)std::max<int64_t>(tot, 1));
+        list.ensure((size_t)std::max<int64_t>(tot, 1), s);
         k_up_fill<<<nl, TB, 0, s>>>(lo, h.nchild.p, h.first_child.p, h.start.p, h.count.p, h.xs_cnt.p, h.xs_idx.p,
                                     h.r1, off.p, list.p);
         H2_LAUNCH_CHECK();
@@ -337,14 +337,14 @@ void run_hidr(Handle& h)
     }
     for (int L = 1; L <= h.maxdepth; ++L) {
         int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
-        sz.ensure((size_t)nl);
-        off.ensure((size_t)nl + 1);
+        sz.ensure((size_t)nl, s);
+        off.ensure((size_t)nl + 1, s);
         k_down_sizes<<<blocks_for(nl, TB), TB, 0, s>>>(lo, nl, h.parent.p, h.il_ptr.p, h.il_col.p, h.xs_cnt.p,
                                                        h.ys_cnt.p, sz.p);
         H2_LAUNCH_CHECK();
         scan_excl_i64(sz.p, off.p, nl, h.tmp_i64, s);
         int64_t tot = read_scalar(off.p + nl, s);
-        list.ensure((size_t)std::max<int64_t>(tot, 1));
+        list.ensure((size_t)std::max<int64_t>(tot, 1), s);
         k_down_fill<<<nl, TB, 0, s>>>(lo, h.parent.p, h.il_ptr.p, h.il_col.p, h.xs_cnt.p, h.xs_idx.p, h.r1,
                                       h.ys_cnt.p, h.ys_idx.p, h.r2, off.p, list.p);
         H2_LAUNCH_CHECK();

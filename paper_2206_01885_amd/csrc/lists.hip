@@ -164,13 +164,13 @@ void to_csr(Handle& h, PairList& pl, DBuf<int>& ptr, DBuf<int>& col)
     hipStream_t s = h.stream;
     int nn = h.nnode;
     DBuf<int> rowcnt;
-    rowcnt.ensure((size_t)nn);
+    rowcnt.ensure((size_t)nn, s);
     H2_HIP(hipMemsetAsync(rowcnt.p, 0, sizeof(int) * nn, s));
     if (pl.n) k_row_count<<<blocks_for(pl.n, TB), TB, 0, s>>>(pl.i.p, pl.n, rowcnt.p);
     H2_LAUNCH_CHECK();
-    ptr.ensure((size_t)nn + 1);
+    ptr.ensure((size_t)nn + 1, s);
     scan_excl_i32(rowcnt.p, ptr.p, nn, h.tmp_i32, s);
-    col.ensure((size_t)std::max<int64_t>(pl.n, 1));
+    col.ensure((size_t)std::max<int64_t>(pl.n, 1), s);
     H2_HIP(hipMemsetAsync(rowcnt.p, 0, sizeof(int) * nn, s));
     if (pl.n) k_row_fill<<<blocks_for(pl.n, TB), TB, 0, s>>>(pl.i.p, pl.j.p, pl.n, ptr.p, rowcnt.p, col.p);
     H2_LAUNCH_CHECK();
@@ -201,16 +201,16 @@ void build_lists(Handle& h)
     DBuf<int> cnt, off, ci, cj, flags, pos;
     while (fr.n > 0) {
         int64_t nf = fr.n;
-        cnt.ensure((size_t)nf);
-        off.ensure((size_t)nf + 1);
+        cnt.ensure((size_t)nf, s);
+        off.ensure((size_t)nf + 1, s);
         k_pair_count<<<blocks_for(nf, TB), TB, 0, s>>>(fr.i.p, fr.j.p, nf, h.nchild.p, cnt.p);
         H2_LAUNCH_CHECK();
         scan_excl_i32(cnt.p, off.p, nf, h.tmp_i32, s);
         int64_t nc = read_scalar(off.p + nf, s);
-        ci.ensure((size_t)nc);
-        cj.ensure((size_t)nc);
-        flags.ensure((size_t)nc * 3);
-        pos.ensure((size_t)nc * 3 + 3);
+        ci.ensure((size_t)nc, s);
+        cj.ensure((size_t)nc, s);
+        flags.ensure((size_t)nc * 3, s);
+        pos.ensure((size_t)nc * 3 + 3, s);
         k_pair_expand<<<blocks_for(nf, TB), TB, 0, s>>>(fr.i.p, fr.j.p, nf, off.p, h.nchild.p, h.first_child.p,
                                                         h.center.p, h.side.p, h.d, h.tau, ci.p, cj.p, flags.p, nc);
         H2_LAUNCH_CHECK();

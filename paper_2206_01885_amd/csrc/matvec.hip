@@ -168,35 +168,52 @@ void matvec(Handle& h, const double* x, double* y, int nrhs, hipStream_t s)
     const int64_t n = h.n;
     if (nrhs > h.mv_nrhs) {
         H2_HIP(hipStreamSynchronize(s));
-        h.xt.ensure((size_t)n * nrhs);
-        h.yt.ensure((size_t)n * nrhs);
-        h.xh.ensure((size_t)std::max<int64_t>(h.sum_rank, 1) * nrhs);
-        h.yh.ensure((size_t)std::max<int64_t>(h.sum_rank, 1) * nrhs);
+        h.xt.ensure((size_t)n * nrhs, s);
+        h.yt.ensure((size_t)n * nrhs, s);
+        h.xh.ensure((size_t)std::max<int64_t>(h.sum_rank, 1) * nrhs, s);
+        h.yh.ensure((size_t)std::max<int64_t>(h.sum_rank, 1) * nrhs, s);
         h.mv_nrhs = nrhs;
     }
+    const bool prof = h.profile != 0;
+    auto mark = [&](int e) {
+        if (prof) H2_HIP(hipEventRecord(h.ev[e], s));
+    };
+    if (prof && !h.ev[0])
+        for (auto& e : h.ev) H2_HIP(hipEventCreate(&e));
+    mark(0);
     k_gather<<<blocks_for(n * nrhs, TB), TB, 0, s>>>(x, n, nrhs, h.perm.p, h.xt.p);
     H2_LAUNCH_CHECK();
+    mark(1);
     for (int L = h.maxdepth; L >= 1; --L) {
         int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
         k_upward<<<nl, TB, 0, s>>>(lo, nrhs, h.nchild.p, h.first_child.p, h.start.p, h.rank.p, h.mbar.p,
                                    h.piv_off.p, h.piv.p, h.T_off.p, h.T.p, h.xh_off.p, h.xt.p, h.xh.p);
         H2_LAUNCH_CHECK();
     }
+    mark(2);
     k_coupling_mv<<<h.nnode, TB, 0, s>>>(nrhs, h.il_ptr.p, h.il_col.p, h.rank.p, h.B_off.p, h.B.p, h.xh_off.p,
                                          h.xh.p, h.yh.p);
     H2_LAUNCH_CHECK();
+    mark(3);
     for (int L = 1; L < h.maxdepth; ++L) {
         int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
         k_downward<<<nl, TB, 0, s>>>(lo, nrhs, h.nchild.p, h.first_child.p, h.rank.p, h.mbar.p, h.piv_off.p,
                                      h.piv.p, h.T_off.p, h.T.p, h.xh_off.p, h.yh.p);
         H2_LAUNCH_CHECK();
     }
+    mark(4);
     k_leaves<<<(unsigned)h.leaves.n, TB, 0, s>>>(nrhs, h.leaves.p, h.start.p, h.count.p, h.rank.p, h.piv_off.p,
                                                  h.piv.p, h.T_off.p, h.T.p, h.xh_off.p, h.yh.p, h.nr_ptr.p,
                                                  h.nr_col.p, h.D_off.p, h.D.p, h.xt.p, h.yt.p);
     H2_LAUNCH_CHECK();
+    mark(5);
     k_scatter<<<blocks_for(n * nrhs, TB), TB, 0, s>>>(h.yt.p, n, nrhs, h.perm.p, y);
     H2_LAUNCH_CHECK();
+    mark(6);
+    if (prof) {
+        h.prof_valid = true;
+        h.prof_nrhs = nrhs;
+    }
 }
 
 }  // namespace h2

@@ -90,7 +90,7 @@ void scan_impl(const T* in, T* out, int64_t cnt, DBuf<T>& tmp, hipStream_t s)
         H2_HIP(hipMemsetAsync(out, 0, sizeof(T), s));
         return;
     }
-    tmp.ensure((size_t)nt + 1);
+    tmp.ensure((size_t)nt + 1, s);
     tile_sums<T><<<(unsigned)nt, SCAN_BLOCK, 0, s>>>(in, cnt, tmp.p);
     H2_LAUNCH_CHECK();
     scan_sums<T><<<1, SCAN_BLOCK, 0, s>>>(tmp.p, nt, out + cnt);

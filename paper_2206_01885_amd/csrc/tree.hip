@@ -222,17 +222,17 @@ void build_tree(Handle& h, const double* pts_in)
     const int d = h.d;
     const int nb = 1 << d;
 
-    h.pts.ensure((size_t)d * n);
-    h.perm.ensure((size_t)n);
+    h.pts.ensure((size_t)d * n, s);
+    h.perm.ensure((size_t)n, s);
     DBuf<double> pts2;
-    pts2.ensure((size_t)d * n);
+    pts2.ensure((size_t)d * n, s);
     DBuf<int> perm2, node_a, node_b, code, flags, pre;
-    perm2.ensure((size_t)n);
-    node_a.ensure((size_t)n);
-    node_b.ensure((size_t)n);
-    code.ensure((size_t)n);
-    flags.ensure((size_t)nb * n);
-    pre.ensure((size_t)nb * (n + 1));
+    perm2.ensure((size_t)n, s);
+    node_a.ensure((size_t)n, s);
+    node_b.ensure((size_t)n, s);
+    code.ensure((size_t)n, s);
+    flags.ensure((size_t)nb * n, s);
+    pre.ensure((size_t)nb * (n + 1), s);
 
     // node arrays, grown as levels are added
     size_t cap = 1024;
@@ -255,9 +255,9 @@ void build_tree(Handle& h, const double* pts_in)
     // root box and finiteness check
     int nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + TB - 1) / TB));
     DBuf<double> part;
-    part.ensure((size_t)nblk * 6);
+    part.ensure((size_t)nblk * 6, s);
     DBuf<int> bad;
-    bad.ensure(1);
+    bad.ensure(1, s);
     H2_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
     k_bbox<<<nblk, TB, 0, s>>>(pts_in, n, d, part.p, bad.p);
     H2_LAUNCH_CHECK();
@@ -279,11 +279,11 @@ void build_tree(Handle& h, const double* pts_in)
         H2_LAUNCH_CHECK();
         for (int b = 0; b < nb; ++b)
             scan_excl_i32(flags.p + (int64_t)b * n, pre.p + (int64_t)b * (n + 1), n, h.tmp_i32, s);
-        ccnt.ensure((size_t)nl * 8);
-        nch.ensure((size_t)nl);
-        nch_off.ensure((size_t)nl + 1);
-        coff.ensure((size_t)nl * 8);
-        cid.ensure((size_t)nl * 8);
+        ccnt.ensure((size_t)nl * 8, s);
+        nch.ensure((size_t)nl, s);
+        nch_off.ensure((size_t)nl + 1, s);
+        coff.ensure((size_t)nl * 8, s);
+        cid.ensure((size_t)nl * 8, s);
         k_child_counts<<<blocks_for(nl, TB), TB, 0, s>>>(lo_node, nl, d, n, h.start.p, h.count.p, h.depth.p,
                                                          h.side.p, h.q, pre.p, ccnt.p, nch.p);
         H2_LAUNCH_CHECK();

@@ -37,7 +37,7 @@ class H2Error(RuntimeError):
 
 class h2_options(C.Structure):
     _fields_ = [("tau", C.c_double), ("r1", C.c_int), ("r2", C.c_int), ("precision", C.c_int),
-                ("store_coupling", C.c_int), ("calib_seed", C.c_uint64)]
+                ("store_coupling", C.c_int), ("calib_seed", C.c_uint64), ("profile", C.c_int)]
 
 
 class h2_info(C.Structure):
@@ -47,7 +47,9 @@ class h2_info(C.Structure):
                 ("sum_rank", C.c_int64), ("bytes_U", C.c_int64), ("bytes_B", C.c_int64),
                 ("bytes_D", C.c_int64), ("t_tree", C.c_double), ("t_lists", C.c_double),
                 ("t_calib", C.c_double), ("t_hidr", C.c_double), ("t_basis", C.c_double),
-                ("t_blocks", C.c_double)]
+                ("t_blocks", C.c_double), ("mv_gather", C.c_double), ("mv_upward", C.c_double),
+                ("mv_coupling", C.c_double), ("mv_downward", C.c_double), ("mv_leaves", C.c_double),
+                ("mv_scatter", C.c_double), ("mv_nrhs", C.c_int)]
 
 
 SYMBOLS = ["h2_options_default", "h2_build", "h2_build_ex", "h2_matvec", "h2_matvec_ex", "h2_query",
