@@ -11,9 +11,10 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libh2.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# Sources whose arithmetic must round exactly as written (geometry, the ID,
-# block evaluation) are compiled without FMA contraction.
-EXACT = {"tree.hip", "lists.hip", "hidr.hip", "basis.hip", "calib.hip", "blocks.hip"}
+# Sources whose arithmetic must round exactly as written (geometry,
+# DataReduct, the ID and its calibration) are compiled without FMA
+# contraction.
+EXACT = {"tree.hip", "lists.hip", "hidr.hip", "basis.hip", "calib.hip"}
 SOURCES = ["alloc.hip", "scan.hip", "tree.hip", "lists.hip", "hidr.hip", "calib.hip", "basis.hip", "blocks.hip",
            "matvec.hip", "api.hip"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",

@@ -127,6 +127,7 @@ h2_status h2_build_ex(const double* points, int64_t n, int dim, int kernel_id, c
         std::vector<int64_t> xo((size_t)h.nnode + 1, 0);
         for (int i = 0; i < h.nnode; ++i) xo[i + 1] = xo[i] + h.h_rank[i];
         upload_vec(h.xh_off, xo, h.stream);
+        h2::prepare_apply(h);
         h.t_tree = t1 - t0;
         h.t_lists = t2 - t1;
         h.t_calib = t3 - t2;

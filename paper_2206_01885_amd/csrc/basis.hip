@@ -26,7 +26,7 @@ namespace h2 {
 namespace {
 
 constexpr int TB = 256;
-constexpr int MAXS = 4096;
+constexpr int MAXS = 4096;  // largest s (r2)
 
 __device__ inline double wave_max(double v)
 {
@@ -38,43 +38,55 @@ __device__ inline int wave_min_i(int v)
     for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
     return v;
 }
+template <int NT>
 __device__ inline double block_max(double v, double* sh)
 {
     v = wave_max(v);
+    if (NT == 64) return v;
     int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) sh[w] = v;
     __syncthreads();
-    double r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    double r = sh[0];
+    for (int q = 1; q < NT / 64; ++q) r = fmax(r, sh[q]);
     __syncthreads();
     return r;
 }
+template <int NT>
 __device__ inline int block_min_i(int v, int* sh)
 {
     v = wave_min_i(v);
+    if (NT == 64) return v;
     int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) sh[w] = v;
     __syncthreads();
-    int r = min(min(sh[0], sh[1]), min(sh[2], sh[3]));
+    int r = sh[0];
+    for (int q = 1; q < NT / 64; ++q) r = min(r, sh[q]);
     __syncthreads();
     return r;
 }
 
-__global__ __launch_bounds__(TB) void k_batched_id(IdBatch b, int d, int kid, double prm)
+// NT = 64 (one wavefront, for row sets of at most 64 points) or 256 lanes.
+// LDSM: the s x m block lives in LDS (dynamic shared memory after the
+// reflector), otherwise in the global workspace.  The arithmetic is the same.
+template <int NT, bool LDSM>
+__global__ __launch_bounds__(NT) void k_batched_id(IdBatch b, const int* __restrict__ order, int d, int kid,
+                                                   double prm)
 {
-    __shared__ double v[MAXS];
+    extern __shared__ double dyn[];
     __shared__ double redd[4];
     __shared__ int redi[4];
     __shared__ double sh_alpha;
 
-    const int p = blockIdx.x;
+    const int p = order[blockIdx.x];
     const int m = b.m[p], s = b.s[p];
     int* piv = b.piv_out + b.piv_off[p];
-    for (int c = threadIdx.x; c < m; c += TB) piv[c] = c;
+    for (int c = threadIdx.x; c < m; c += NT) piv[c] = c;
     if (m == 0 || s == 0) {
         if (threadIdx.x == 0) b.rank_out[p] = 0;
         return;
     }
-    double* M = b.M + b.M_off[p];
+    double* v = dyn;
+    double* M = LDSM ? dyn + s : b.M + b.M_off[p];
     double* nu = b.nu + b.nu_off[p];
     double* nu0 = nu + m;
     double* ss = nu + 2 * m;
@@ -82,13 +94,13 @@ __global__ __launch_bounds__(TB) void k_batched_id(IdBatch b, int d, int kid, do
     const int* yi = b.y_idx + b.y_off[p];
 
     // kernel block: M[r][c] = kappa(x_c, y_r)
-    for (int64_t e = threadIdx.x; e < (int64_t)s * m; e += TB) {
+    for (int64_t e = threadIdx.x; e < (int64_t)s * m; e += NT) {
         int r = (int)(e / m), c = (int)(e - (int64_t)r * m);
         double r2 = dist2(b.xpts, b.xld, xi[c], b.ypts, b.yld, yi[r], d);
         M[e] = kappa_r2(kid, prm, r2);
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < m; c += TB) {
+    for (int c = threadIdx.x; c < m; c += NT) {
         double acc = 0.0;
         for (int r = 0; r < s; ++r) acc = acc + M[(int64_t)r * m + c] * M[(int64_t)r * m + c];
         ss[c] = acc;
@@ -105,17 +117,17 @@ __global__ __launch_bounds__(TB) void k_batched_id(IdBatch b, int d, int kid, do
     for (int j = 0; j < kmax; ++j) {
         // pivot: lowest index within the window of the largest partial norm
         double mx = 0.0;
-        for (int c = j + threadIdx.x; c < m; c += TB) mx = fmax(mx, nu[c]);
-        mx = block_max(mx, redd);
+        for (int c = j + threadIdx.x; c < m; c += NT) mx = fmax(mx, nu[c]);
+        mx = block_max<NT>(mx, redd);
         int cand = 0x7fffffff;
-        for (int c = j + threadIdx.x; c < m; c += TB)
+        for (int c = j + threadIdx.x; c < m; c += NT)
             if (nu[c] >= window * mx) {
                 cand = c;
                 break;
             }
-        int pc = block_min_i(cand, redi);
+        int pc = block_min_i<NT>(cand, redi);
         if (pc != j) {
-            for (int r = threadIdx.x; r < s; r += TB) {
+            for (int r = threadIdx.x; r < s; r += NT) {
                 double t = M[(int64_t)r * m + j];
                 M[(int64_t)r * m + j] = M[(int64_t)r * m + pc];
                 M[(int64_t)r * m + pc] = t;
@@ -135,12 +147,12 @@ __global__ __launch_bounds__(TB) void k_batched_id(IdBatch b, int d, int kid, do
         if (alpha == 0.0 || alpha <= b.tol * r00) break;
         const double xj = M[(int64_t)j * m + j];
         const double beta = xj >= 0.0 ? -alpha : alpha;
-        for (int r = j + threadIdx.x; r < s; r += TB) v[r] = M[(int64_t)r * m + j];
+        for (int r = j + threadIdx.x; r < s; r += NT) v[r] = M[(int64_t)r * m + j];
         __syncthreads();
         if (threadIdx.x == 0) v[j] = v[j] - beta;
         __syncthreads();
         const double vtv = 2.0 * alpha * (alpha + fabs(xj));
-        for (int c = j + 1 + threadIdx.x; c < m; c += TB) {
+        for (int c = j + 1 + threadIdx.x; c < m; c += NT) {
             double w = 0.0;
             for (int r = j; r < s; ++r) w = w + v[r] * M[(int64_t)r * m + c];
             double f = 2.0 * w / vtv;
@@ -177,14 +189,14 @@ __global__ __launch_bounds__(TB) void k_batched_id(IdBatch b, int d, int kid, do
     // T = R11^{-1} R12 by back substitution, one column of R12 per lane
     const int nr = m - k;
     double* T = b.T_out + b.T_off[p];
-    for (int u = threadIdx.x; u < nr; u += TB) {
+    for (int u = threadIdx.x; u < nr; u += NT) {
         for (int t = k - 1; t >= 0; --t) {
             double acc = M[(int64_t)t * m + (k + u)];
             for (int l = t + 1; l < k; ++l) acc = acc - M[(int64_t)t * m + l] * T[(int64_t)l * nr + u];
             T[(int64_t)t * nr + u] = acc / M[(int64_t)t * m + t];
         }
     }
-    for (int t = threadIdx.x; t < k; t += TB) b.skel_out[(int64_t)p * b.skel_stride + t] = xi[piv[t]];
+    for (int t = threadIdx.x; t < k; t += NT) b.skel_out[(int64_t)p * b.skel_stride + t] = xi[piv[t]];
     if (threadIdx.x == 0) b.rank_out[p] = k;
 }
 
@@ -213,11 +225,49 @@ __global__ __launch_bounds__(TB) void k_xbar_fill(int lo, const int* __restrict_
 
 }  // namespace
 
-void batched_id(const IdBatch& b, int d, int kid, double prm, hipStream_t s)
+void batched_id(const IdBatch& b, const std::vector<int>& m_host, const std::vector<int>& s_host, int d, int kid,
+                double prm, hipStream_t s)
 {
     if (b.nprob <= 0) return;
-    k_batched_id<<<b.nprob, TB, 0, s>>>(b, d, kid, prm);
-    H2_LAUNCH_CHECK();
+    // class 0: one wavefront, block in LDS; 1: one wavefront, global block;
+    // 2: four wavefronts, global block
+    const int LDS_DOUBLES = 8192;  // 64 KiB per workgroup
+    std::vector<int> cls(b.nprob);
+    for (int p = 0; p < b.nprob; ++p) {
+        int64_t need = (int64_t)s_host[p] * (m_host[p] + 1);
+        cls[p] = m_host[p] <= 64 ? (need <= LDS_DOUBLES ? 0 : 1) : 2;
+    }
+    std::vector<int> order;
+    order.reserve(b.nprob);
+    int cnt[3] = {0, 0, 0};
+    size_t lds[3] = {8, 8, 8};
+    for (int c = 0; c < 3; ++c)
+        for (int p = 0; p < b.nprob; ++p)
+            if (cls[p] == c) {
+                order.push_back(p);
+                ++cnt[c];
+                size_t need = (size_t)s_host[p] * (c == 0 ? m_host[p] + 1 : 1) * sizeof(double);
+                lds[c] = std::max(lds[c], need);
+            }
+    DBuf<int> d_order;
+    d_order.ensure(order.size(), s);
+    H2_HIP(hipMemcpyAsync(d_order.p, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    int o = 0;
+    if (cnt[0] > 0) {
+        k_batched_id<64, true><<<cnt[0], 64, lds[0], s>>>(b, d_order.p + o, d, kid, prm);
+        H2_LAUNCH_CHECK();
+    }
+    o += cnt[0];
+    if (cnt[1] > 0) {
+        k_batched_id<64, false><<<cnt[1], 64, lds[1], s>>>(b, d_order.p + o, d, kid, prm);
+        H2_LAUNCH_CHECK();
+    }
+    o += cnt[1];
+    if (cnt[2] > 0) {
+        k_batched_id<TB, false><<<cnt[2], TB, lds[2], s>>>(b, d_order.p + o, d, kid, prm);
+        H2_LAUNCH_CHECK();
+    }
+    H2_HIP(hipStreamSynchronize(s));
 }
 
 template <class T>
@@ -338,7 +388,7 @@ void build_bases(Handle& h)
             b.T_off = d_Toff.p;
             b.skel_out = h.skel.p + (int64_t)c0 * h.r2;
             b.skel_stride = h.r2;
-            batched_id(b, h.d, h.kid, h.prm, s);
+            batched_id(b, mv, sv, h.d, h.kid, h.prm, s);
             std::vector<int> rk = read_vec(h.rank.p + c0, np, s);
             for (int t = 0; t < np; ++t) h.h_rank[c0 + t] = rk[t];
             c0 = c1;

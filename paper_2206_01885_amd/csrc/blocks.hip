@@ -1,10 +1,11 @@
 // Coupling and nearfield blocks of Algorithm 2:
 //   B_ij = K(Xhat_i, Xhat_j)   for (i, j) in the interaction lists,
 //   D_ij = K(X_i, X_j)         for (i, j) in the near lists (leaf pairs).
-// Blocks are stored row-major (rank_i x rank_j, resp. count_i x count_j) in
-// CSR order of the lists; offsets come from a device scan over the block
-// sizes.  One workgroup per row i; consecutive lanes write consecutive
-// entries of a block row.
+// Blocks are stored column-major (rank_i x rank_j, resp. count_i x count_j)
+// in CSR order of the lists; offsets come from a device scan over the block
+// sizes.  One workgroup per list row i.  These entries feed only the apply,
+// so they use the fast kernel evaluation (an ulp or two from the correctly
+// rounded form that the ID uses).
 #include "common.h"
 #include "kappa.h"
 
@@ -22,45 +23,84 @@ __global__ __launch_bounds__(TB) void k_block_sizes(int nrow, const int* __restr
     for (int e = ptr[i]; e < ptr[i + 1]; ++e) out[e] = a * sz_node[col[e]];
 }
 
-// Coupling blocks: rows/cols are skeleton points (tree positions) skel[i*stride + t].
-__global__ __launch_bounds__(TB) void k_coupling(const double* __restrict__ pts, int64_t n, int d, int kid,
-                                                 double prm, const int* __restrict__ ptr, const int* __restrict__ col,
-                                                 const int* __restrict__ rank, const int* __restrict__ skel,
-                                                 int stride, const int64_t* __restrict__ off, double* __restrict__ B)
+// Skeleton coordinates gathered into node order (SoA [d][sum k]) so that a
+// block's column points are one coalesced load.
+__global__ __launch_bounds__(TB) void k_skel_coords(int nn, const double* __restrict__ pts, int64_t n, int d,
+                                                    const int* __restrict__ rank, const int* __restrict__ skel,
+                                                    int stride, const int64_t* __restrict__ xoff, int64_t sumk,
+                                                    double* __restrict__ skc)
 {
     const int i = blockIdx.x;
-    const int ki = rank[i];
-    if (ki == 0) return;
-    const int* si = skel + (int64_t)i * stride;
-    for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
-        const int j = col[e];
-        const int kj = rank[j];
-        const int* sj = skel + (int64_t)j * stride;
-        double* o = B + off[e];
-        const int64_t tot = (int64_t)ki * kj;
-        for (int64_t q = threadIdx.x; q < tot; q += TB) {
-            int t = (int)(q / kj), u = (int)(q - (int64_t)t * kj);
-            o[q] = kappa_r2(kid, prm, dist2(pts, n, si[t], pts, n, sj[u], d));
-        }
+    const int k = rank[i];
+    for (int t = threadIdx.x; t < k; t += TB) {
+        const int p = skel[(int64_t)i * stride + t];
+        for (int a = 0; a < d; ++a) skc[a * sumk + xoff[i] + t] = pts[a * n + p];
     }
 }
 
-// Nearfield blocks between leaves: rows/cols are the leaves' points.
-__global__ __launch_bounds__(TB) void k_near(const double* __restrict__ pts, int64_t n, int d, int kid, double prm,
-                                             const int* __restrict__ ptr, const int* __restrict__ col,
-                                             const int* __restrict__ start, const int* __restrict__ count,
-                                             const int64_t* __restrict__ off, double* __restrict__ D)
+// Row of every list entry (CSR expansion).
+__global__ __launch_bounds__(TB) void k_entry_rows(int nrow, const int* __restrict__ ptr, int* __restrict__ row)
 {
-    const int i = blockIdx.x;
-    const int ci = count[i], s0 = start[i];
-    for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
-        const int j = col[e];
-        const int cj = count[j], s1 = start[j];
-        double* o = D + off[e];
-        const int64_t tot = (int64_t)ci * cj;
-        for (int64_t q = threadIdx.x; q < tot; q += TB) {
-            int t = (int)(q / cj), u = (int)(q - (int64_t)t * cj);
-            o[q] = kappa_r2(kid, prm, dist2(pts, n, s0 + t, pts, n, s1 + u, d));
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= nrow) return;
+    for (int e = ptr[i]; e < ptr[i + 1]; ++e) row[e] = i;
+}
+
+// One wavefront per block (list entry e = (i, j)), four blocks per
+// workgroup.  Row points X_i (rows_i of them, contiguous in `xs` from xo[i])
+// and column points (cols_j from xo[j]) are loaded once, one per lane, and the
+// column point of each block column is broadcast with a lane shuffle.  The
+// block is column-major (entry (t,u) at u*rows_i + t); with rows_i <= 32 the
+// two half-waves fill two columns per pass.
+__global__ __launch_bounds__(TB) void k_blocks_eval(int64_t nent, const int* __restrict__ erow,
+                                                    const int* __restrict__ col, const int* __restrict__ cnt,
+                                                    const double* __restrict__ xs, int64_t ld,
+                                                    const int64_t* __restrict__ xo, int d, int kid, double prm,
+                                                    const int64_t* __restrict__ off, double* __restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6);
+    if (e >= nent) return;
+    const int lane = threadIdx.x & 63;
+    const int i = erow[e], j = col[e];
+    const int ki = cnt[i], kj = cnt[j];
+    if (ki == 0 || kj == 0) return;
+    double* o = out + off[e];
+    const int64_t bi = xo[i], bj = xo[j];
+    for (int t0 = 0; t0 < ki; t0 += 64) {
+        const bool half = ki - t0 <= 32;  // two columns per pass
+        const int t = half ? t0 + (lane & 31) : t0 + lane;
+        const int du = half ? (lane >> 5) : 0;
+        const int su = half ? 2 : 1;
+        double xi0 = 0.0, xi1 = 0.0, xi2 = 0.0;
+        if (t < ki) {
+            xi0 = xs[bi + t];
+            if (d > 1) xi1 = xs[ld + bi + t];
+            if (d > 2) xi2 = xs[2 * ld + bi + t];
+        }
+        for (int u0 = 0; u0 < kj; u0 += 64) {
+            const int uc = min(64, kj - u0);
+            double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+            if (lane < uc) {
+                y0 = xs[bj + u0 + lane];
+                if (d > 1) y1 = xs[ld + bj + u0 + lane];
+                if (d > 2) y2 = xs[2 * ld + bj + u0 + lane];
+            }
+            // wave-uniform trip count: every lane takes part in every shuffle
+            for (int ub = 0; ub < uc; ub += su) {
+                const int uu = ub + du;
+                const int src = uu < uc ? uu : uc - 1;
+                const double a0 = __shfl(y0, src, 64) - xi0;
+                double r2 = a0 * a0;
+                if (d > 1) {
+                    const double a1 = __shfl(y1, src, 64) - xi1;
+                    r2 += a1 * a1;
+                }
+                if (d > 2) {
+                    const double a2 = __shfl(y2, src, 64) - xi2;
+                    r2 += a2 * a2;
+                }
+                if (t < ki && uu < uc) o[(int64_t)(u0 + uu) * ki + t] = kappa_fast(kid, prm, r2);
+            }
         }
     }
 }
@@ -74,7 +114,21 @@ void build_blocks(Handle& h)
     h.B_off.ensure((size_t)h.nil + 1, s);
     h.D_off.ensure((size_t)h.nnear + 1, s);
     DBuf<int64_t> sz;
-    sz.ensure((size_t)std::max<int64_t>(std::max(h.nil, h.nnear), 1), s);
+    DBuf<int> erow;
+    const int64_t nmax = std::max<int64_t>(std::max(h.nil, h.nnear), 1);
+    sz.ensure((size_t)nmax, s);
+    erow.ensure((size_t)nmax, s);
+    // skeleton coordinates in node order
+    std::vector<int64_t> xo((size_t)nn + 1, 0);
+    for (int i = 0; i < nn; ++i) xo[i + 1] = xo[i] + h.h_rank[i];
+    const int64_t sumk = std::max<int64_t>(xo[nn], 1);
+    DBuf<int64_t> d_xo;
+    d_xo.ensure(xo.size(), s);
+    H2_HIP(hipMemcpyAsync(d_xo.p, xo.data(), xo.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    DBuf<double> skc;
+    skc.ensure((size_t)h.d * sumk, s);
+    k_skel_coords<<<nn, TB, 0, s>>>(nn, h.pts.p, h.n, h.d, h.rank.p, h.skel.p, h.r2, d_xo.p, sumk, skc.p);
+    H2_LAUNCH_CHECK();
     // coupling
     k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, h.il_col.p, h.rank.p, sz.p);
     H2_LAUNCH_CHECK();
@@ -82,19 +136,32 @@ void build_blocks(Handle& h)
     int64_t nB = read_scalar(h.B_off.p + h.nil, s);
     h.B.ensure((size_t)std::max<int64_t>(nB, 1), s);
     h.bytes_B = nB * (int64_t)sizeof(double);
-    k_coupling<<<nn, TB, 0, s>>>(h.pts.p, h.n, h.d, h.kid, h.prm, h.il_ptr.p, h.il_col.p, h.rank.p, h.skel.p, h.r2,
-                                 h.B_off.p, h.B.p);
-    H2_LAUNCH_CHECK();
-    // nearfield
+    if (h.nil > 0) {
+        k_entry_rows<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, erow.p);
+        H2_LAUNCH_CHECK();
+        k_blocks_eval<<<blocks_for(h.nil, TB / 64), TB, 0, s>>>(h.nil, erow.p, h.il_col.p, h.rank.p, skc.p, sumk,
+                                                                 d_xo.p, h.d, h.kid, h.prm, h.B_off.p, h.B.p);
+        H2_LAUNCH_CHECK();
+    }
+    // nearfield: the leaves' points are contiguous in tree order
     k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.nr_ptr.p, h.nr_col.p, h.count.p, sz.p);
     H2_LAUNCH_CHECK();
     scan_excl_i64(sz.p, h.D_off.p, h.nnear, h.tmp_i64, s);
     int64_t nD = read_scalar(h.D_off.p + h.nnear, s);
     h.D.ensure((size_t)std::max<int64_t>(nD, 1), s);
     h.bytes_D = nD * (int64_t)sizeof(double);
-    k_near<<<nn, TB, 0, s>>>(h.pts.p, h.n, h.d, h.kid, h.prm, h.nr_ptr.p, h.nr_col.p, h.start.p, h.count.p,
-                             h.D_off.p, h.D.p);
-    H2_LAUNCH_CHECK();
+    if (h.nnear > 0) {
+        std::vector<int64_t> st(h.h_start.begin(), h.h_start.end());
+        DBuf<int64_t> d_st;
+        d_st.ensure(st.size(), s);
+        H2_HIP(hipMemcpyAsync(d_st.p, st.data(), st.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        k_entry_rows<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.nr_ptr.p, erow.p);
+        H2_LAUNCH_CHECK();
+        k_blocks_eval<<<blocks_for(h.nnear, TB / 64), TB, 0, s>>>(h.nnear, erow.p, h.nr_col.p, h.count.p, h.pts.p,
+                                                                   h.n, d_st.p, h.d, h.kid, h.prm, h.D_off.p, h.D.p);
+        H2_LAUNCH_CHECK();
+        H2_HIP(hipStreamSynchronize(s));
+    }
     H2_HIP(hipStreamSynchronize(s));
 }
 

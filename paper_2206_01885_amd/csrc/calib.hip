@@ -73,44 +73,68 @@ __global__ void k_lists(int nprob, const int* __restrict__ set_of, int64_t* __re
     }
 }
 
-// Relative Frobenius error of K(Z1,Z2) - U K(Zhat,Z2) over all of Z2.
-__global__ __launch_bounds__(TB) void k_err(const double* __restrict__ Z, int64_t ld, int d, int kid, double prm,
-                                            const int* __restrict__ set_of, const int* __restrict__ rank,
-                                            const int* __restrict__ piv, const double* __restrict__ T,
-                                            int64_t T_stride, double* __restrict__ err)
+// Squared Frobenius norms for the calibration error, spread over the grid:
+// workgroup (p, cb) owns 8 columns c of Z2; it stages K(Zhat, c) in LDS and
+// each lane forms rows u of K(Z1 rest, c) - T^T K(Zhat, c).  Partial sums go
+// to part[(p*64 + cb)*2 + {0,1}] (residual, full norm) and are reduced in a
+// fixed order by k_err_final, so the result does not depend on scheduling.
+constexpr int ECOLS = 8;
+constexpr int ECB = NZ / ECOLS;
+__global__ __launch_bounds__(TB) void k_err_part(const double* __restrict__ Z, int64_t ld, int d, int kid,
+                                                 double prm, const int* __restrict__ set_of,
+                                                 const int* __restrict__ rank, const int* __restrict__ piv,
+                                                 const double* __restrict__ T, int64_t T_stride,
+                                                 double* __restrict__ part)
 {
-    __shared__ double sh_res[TB], sh_fro[TB];
-    const int p = blockIdx.x;
+    __shared__ double ks[NZ * ECOLS];  // K(Zhat_t, c) for t < k <= 512
+    __shared__ double red_r[TB], red_f[TB];
+    const int p = blockIdx.x / ECB, cb = blockIdx.x % ECB;
     const int base = set_of[p] * 2 * NZ;
     const int k = rank[p], nr = NZ - k;
     const int* pv = piv + (int64_t)p * NZ;
     const double* Tp = T + (int64_t)p * T_stride;
+    const int cl = threadIdx.x % ECOLS, ul = threadIdx.x / ECOLS;  // 8 columns x 32 row lanes
+    const int c = cb * ECOLS + cl;
+    for (int t = ul; t < k; t += TB / ECOLS)
+        ks[t * ECOLS + cl] = kappa_r2(kid, prm, dist2(Z, ld, base + pv[t], Z, ld, base + NZ + c, d));
+    __syncthreads();
     double res = 0.0, fro = 0.0;
-    for (int q = threadIdx.x; q < NZ * NZ; q += TB) {
-        int i = q / NZ, c = q - i * NZ;
+    for (int i = ul; i < NZ; i += TB / ECOLS) {
         double kv = kappa_r2(kid, prm, dist2(Z, ld, base + i, Z, ld, base + NZ + c, d));
         fro += kv * kv;
     }
-    for (int q = threadIdx.x; q < nr * NZ; q += TB) {
-        int u = q / NZ, c = q - u * NZ;
+    for (int u = ul; u < nr; u += TB / ECOLS) {
         double approx = 0.0;
-        for (int t = 0; t < k; ++t)
-            approx = approx + Tp[(int64_t)t * nr + u] *
-                                  kappa_r2(kid, prm, dist2(Z, ld, base + pv[t], Z, ld, base + NZ + c, d));
+        for (int t = 0; t < k; ++t) approx = approx + Tp[(int64_t)t * nr + u] * ks[t * ECOLS + cl];
         double e = kappa_r2(kid, prm, dist2(Z, ld, base + pv[k + u], Z, ld, base + NZ + c, d)) - approx;
         res += e * e;
     }
-    sh_res[threadIdx.x] = res;
-    sh_fro[threadIdx.x] = fro;
+    red_r[threadIdx.x] = res;
+    red_f[threadIdx.x] = fro;
     __syncthreads();
     for (int off = TB / 2; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) {
-            sh_res[threadIdx.x] += sh_res[threadIdx.x + off];
-            sh_fro[threadIdx.x] += sh_fro[threadIdx.x + off];
+            red_r[threadIdx.x] += red_r[threadIdx.x + off];
+            red_f[threadIdx.x] += red_f[threadIdx.x + off];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) err[p] = sh_fro[0] > 0.0 ? sqrt(sh_res[0]) / sqrt(sh_fro[0]) : 0.0;
+    if (threadIdx.x == 0) {
+        part[(int64_t)blockIdx.x * 2] = red_r[0];
+        part[(int64_t)blockIdx.x * 2 + 1] = red_f[0];
+    }
+}
+
+__global__ void k_err_final(int np, const double* __restrict__ part, double* __restrict__ err)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    double r = 0.0, f = 0.0;
+    for (int cb = 0; cb < ECB; ++cb) {
+        r += part[((int64_t)p * ECB + cb) * 2];
+        f += part[((int64_t)p * ECB + cb) * 2 + 1];
+    }
+    err[p] = f > 0.0 ? sqrt(r) / sqrt(f) : 0.0;
 }
 
 }  // namespace
@@ -158,7 +182,7 @@ void run_calibration(Handle& h)
         std::vector<double> result_err(nset, 0.0);
         DBuf<int> set_of, z2idx, z1idx, mm, ycnt, yidx, rank, piv, skel;
         DBuf<int64_t> zoff, xoff, yoff, Moff, nuoff, pivoff, Toff;
-        DBuf<double> M, nu, T, err;
+        DBuf<double> M, nu, T, err, part;
         for (int g = 1;; ++g) {
             long long rr = 1;
             for (int a = 0; a < d; ++a) rr *= g;
@@ -230,8 +254,13 @@ void run_calibration(Handle& h)
             b.T_off = Toff.p;
             b.skel_out = skel.p;
             b.skel_stride = rs;
-            batched_id(b, d, h.kid, h.prm, s);
-            k_err<<<np, TB, 0, s>>>(Z.p, ld, d, h.kid, h.prm, set_of.p, rank.p, piv.p, T.p, (int64_t)rs * NZ, err.p);
+            std::vector<int> ys_h = read_vec(ycnt.p, np, s);
+            batched_id(b, std::vector<int>(np, NZ), ys_h, d, h.kid, h.prm, s);
+            part.ensure((size_t)np * ECB * 2, s);
+            k_err_part<<<np * ECB, TB, 0, s>>>(Z.p, ld, d, h.kid, h.prm, set_of.p, rank.p, piv.p, T.p,
+                                               (int64_t)rs * NZ, part.p);
+            H2_LAUNCH_CHECK();
+            k_err_final<<<blocks_for(np, 64), 64, 0, s>>>(np, part.p, err.p);
             H2_LAUNCH_CHECK();
             std::vector<double> e = read_vec(err.p, np, s);
             for (int p = 0; p < np; ++p) {

@@ -169,6 +169,15 @@ struct Handle {
     DBuf<int> leaves;      // leaf node ids
     int64_t sum_rank = 0;
 
+    // apply task lists: (node, first row) of every 32-row chunk of a block
+    // row, split by whether the chunk holds one or two 16-row tiles
+    struct Tasks {
+        DBuf<int> node, r0;
+        int n = 0;
+    };
+    Tasks cp_t1, cp_t2, nr_t1, nr_t2;
+    DBuf<int64_t> start64;  // start[] widened, row offsets of the leaves in x_t / y_t
+
     // matvec workspace (sized for the largest nrhs seen)
     int mv_nrhs = 0;
     DBuf<double> xt, yt, xh, yh;
@@ -195,6 +204,7 @@ void run_calibration(Handle& h);                                  // calib.hip
 void run_hidr(Handle& h);                                         // hidr.hip
 void build_bases(Handle& h);                                      // basis.hip
 void build_blocks(Handle& h);                                     // blocks.hip
+void prepare_apply(Handle& h);                                   // matvec.hip
 void matvec(Handle& h, const double* x, double* y, int nrhs, hipStream_t s);  // matvec.hip
 
 // DataReduct over materialised index lists (hidr.hip); used by HiDR and by
@@ -232,6 +242,7 @@ struct IdBatch {
     int* skel_out = nullptr;         // at p*skel_stride, k_p entries (x indices)
     int skel_stride = 0;
 };
-void batched_id(const IdBatch& b, int d, int kid, double prm, hipStream_t s);
+void batched_id(const IdBatch& b, const std::vector<int>& m_host, const std::vector<int>& s_host, int d, int kid,
+                double prm, hipStream_t s);
 
 }  // namespace h2

@@ -23,6 +23,35 @@ __device__ __forceinline__ double kappa_r2(int kid, double prm, double r2)
     }
 }
 
+// 1/sqrt(r2) for r2 > 0: the hardware estimate refined by two Newton steps
+// y <- y (3 - r2 y^2) / 2 (each roughly doubles the correct bits).
+__device__ __forceinline__ double rsqrt_nr(double r2)
+{
+    double y = __builtin_amdgcn_rsq(r2);
+    double h = 0.5 * r2;
+    y = y * (1.5 - h * y * y);
+    y = y * (1.5 - h * y * y);
+    return y;
+}
+
+// Same functions with the refined reciprocal square root (an ulp or two);
+// used where the entries are not compared bit for bit.
+__device__ __forceinline__ double kappa_fast(int kid, double prm, double r2)
+{
+    switch (kid) {
+    case H2_COULOMB:
+        return r2 > 0.0 ? rsqrt_nr(r2) : 0.0;
+    case H2_GAUSSIAN:
+        return exp(-r2 / (prm * prm));
+    case H2_EXPONENTIAL:
+        return exp(-sqrt(r2) / prm);
+    default: {
+        double t = sqrt(3.0) * sqrt(r2) / prm;
+        return (1.0 + t) * exp(-t);
+    }
+    }
+}
+
 // Squared distance accumulated in coordinate order from 0 (as the oracle does).
 __device__ __forceinline__ double dist2(const double* __restrict__ xa, int64_t xld, int64_t xi,
                                         const double* __restrict__ ya, int64_t yld, int64_t yi, int d)
