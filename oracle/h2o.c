@@ -106,32 +106,27 @@ void h2o_kernel_matrix(int kid, const double *prm, int d, const double *X, int m
 /* volume-based DataReduct (Section 3.3)                               */
 /* ------------------------------------------------------------------ */
 /* DataReduct(X, k) -> X*: X is given as `L` indices into the point array
- * `pts` ([npts][d]).  Reading of the silent details:
+ * `pts` ([npts][d]), split into `nseg` consecutive segments seg[0..nseg]
+ * (seg[0] = 0, seg[nseg] = L).  Reading of the silent details:
  *  - |X| <= k: X is returned unchanged (keeps every point);
- *  - Q is the tensor grid of cell centres of a g^d grid over the bounding box
- *    of X, g the largest integer with g^d <= k, dimension 0 varying fastest;
- *  - for each q in grid order the point of X with the smallest squared
+ *  - the reference set Q is, for every non-empty segment in order, the
+ *    tensor grid of cell centres of a g^d grid over that segment's bounding
+ *    box (g the largest integer with g^d <= k, dimension 0 varying fastest);
+ *    a list built from one set has one segment, the farfield list T_i of
+ *    HiDR has two (the parent's Y_p^* and the interaction-list part);
+ *  - for each q in Q order the point of the whole X with the smallest squared
  *    distance is taken, ties going to the earliest position in X;
- *  - X* lists the distinct picks in grid order of first occurrence.
- * Writes the selected indices to out (capacity >= min(L,k)); returns |X*|. */
-int h2o_datareduct(int d, const double *pts, const int *list, int L, int k, int *out)
+ *  - X* lists the distinct picks in Q order of first occurrence.
+ * Writes the selected indices to out (capacity >= min(L, nseg*k)); returns
+ * |X*|. */
+int h2o_datareduct_seg(int d, const double *pts, const int *list, int L, const int *seg, int nseg, int k,
+                       int *out)
 {
     if (L <= k) {
         for (int p = 0; p < L; ++p)
             out[p] = list[p];
         return L;
     }
-    double lo[3], hi[3];
-    for (int a = 0; a < d; ++a) {
-        lo[a] = pts[(size_t)list[0] * d + a];
-        hi[a] = lo[a];
-    }
-    for (int p = 1; p < L; ++p)
-        for (int a = 0; a < d; ++a) {
-            double v = pts[(size_t)list[p] * d + a];
-            if (v < lo[a]) lo[a] = v;
-            if (v > hi[a]) hi[a] = v;
-        }
     int g = 1;
     for (;;) {
         long long nx = 1;
@@ -140,33 +135,49 @@ int h2o_datareduct(int d, const double *pts, const int *list, int L, int k, int 
         if (nx > k) break;
         ++g;
     }
-    int nq = 1;
+    int nq1 = 1;
     for (int a = 0; a < d; ++a)
-        nq *= g;
-    int *pick = (int *)malloc(sizeof(int) * (size_t)nq);
-    for (int t = 0; t < nq; ++t) {
-        double q[3];
-        int rem = t;
+        nq1 *= g;
+    int *pick = (int *)malloc(sizeof(int) * (size_t)nq1 * (size_t)nseg);
+    int nq = 0;
+    for (int sg = 0; sg < nseg; ++sg) {
+        int b0 = seg[sg], b1 = seg[sg + 1];
+        if (b1 <= b0) continue;
+        double lo[3], hi[3];
         for (int a = 0; a < d; ++a) {
-            int ta = rem % g;
-            rem /= g;
-            double w = (double)(2 * ta + 1) / (double)(2 * g);
-            q[a] = lo[a] + (hi[a] - lo[a]) * w;
+            lo[a] = pts[(size_t)list[b0] * d + a];
+            hi[a] = lo[a];
         }
-        int best = 0;
-        double bd = INFINITY;
-        for (int p = 0; p < L; ++p) {
-            double dd = 0.0;
+        for (int p = b0 + 1; p < b1; ++p)
             for (int a = 0; a < d; ++a) {
-                double e = q[a] - pts[(size_t)list[p] * d + a];
-                dd = dd + e * e;
+                double v = pts[(size_t)list[p] * d + a];
+                if (v < lo[a]) lo[a] = v;
+                if (v > hi[a]) hi[a] = v;
             }
-            if (dd < bd) {
-                bd = dd;
-                best = p;
+        for (int t = 0; t < nq1; ++t) {
+            double q[3];
+            int rem = t;
+            for (int a = 0; a < d; ++a) {
+                int ta = rem % g;
+                rem /= g;
+                double w = (double)(2 * ta + 1) / (double)(2 * g);
+                q[a] = lo[a] + (hi[a] - lo[a]) * w;
             }
+            int best = 0;
+            double bd = INFINITY;
+            for (int p = 0; p < L; ++p) {
+                double dd = 0.0;
+                for (int a = 0; a < d; ++a) {
+                    double e = q[a] - pts[(size_t)list[p] * d + a];
+                    dd = dd + e * e;
+                }
+                if (dd < bd) {
+                    bd = dd;
+                    best = p;
+                }
+            }
+            pick[nq++] = best;
         }
-        pick[t] = best;
     }
     int cnt = 0;
     for (int t = 0; t < nq; ++t) {
@@ -180,6 +191,13 @@ int h2o_datareduct(int d, const double *pts, const int *list, int L, int k, int 
     }
     free(pick);
     return cnt;
+}
+
+/* DataReduct of a single set (one segment). */
+int h2o_datareduct(int d, const double *pts, const int *list, int L, int k, int *out)
+{
+    int seg[2] = {0, L};
+    return h2o_datareduct_seg(d, pts, list, L, seg, 1, k, out);
 }
 
 /* ------------------------------------------------------------------ */
@@ -604,7 +622,9 @@ static void build_lists(h2o *h)
  * else the children's X_c^* concatenated in child order; X_i^* =
  * DataReduct(S_i, r1).  Top-down (depth 1 first): T_i = Y_p^* followed by
  * X_j^* for j in IL(i) ascending (Y_root^* is empty); Y_i^* =
- * DataReduct(T_i, r2) when T_i is not empty.  (The text writes "union of
+ * DataReduct(T_i, r2) when T_i is not empty, with the two parts of T_i as
+ * the segments of the volume reference set, so each part is sampled on a
+ * grid of its own extent and |Y_i^*| <= 2 r2.  (The text writes "union of
  * Y_p" once and Y_p^* in the algorithm and elsewhere; Y_p^* is taken.) */
 static void run_hidr(h2o *h)
 {
@@ -647,7 +667,8 @@ static void run_hidr(h2o *h)
             ilist Y = {0};
             if (Tl.n > 0) {
                 int *out = (int *)malloc(sizeof(int) * (size_t)Tl.n);
-                int cnt = h2o_datareduct(h->d, h->P, Tl.v, Tl.n, h->r2, out);
+                int seg[3] = {0, h->ys[p].n, Tl.n};
+                int cnt = h2o_datareduct_seg(h->d, h->P, Tl.v, Tl.n, seg, 2, h->r2, out);
                 for (int t = 0; t < cnt; ++t)
                     il_push(&Y, out[t]);
                 free(out);

@@ -49,6 +49,8 @@ def lib():
         L.h2o_kernel_matrix.argtypes = [C.c_int, dp, C.c_int, dp, C.c_int, dp, C.c_int, dp]
         L.h2o_datareduct.restype = C.c_int
         L.h2o_datareduct.argtypes = [C.c_int, dp, ip, C.c_int, C.c_int, ip]
+        L.h2o_datareduct_seg.restype = C.c_int
+        L.h2o_datareduct_seg.argtypes = [C.c_int, dp, ip, C.c_int, ip, C.c_int, C.c_int, ip]
         L.h2o_cpqr_id.restype = C.c_int
         L.h2o_cpqr_id.argtypes = [dp, C.c_int, C.c_int, C.c_double, ip, dp, dp]
         L.h2o_splitmix_u01.restype = C.c_double
@@ -124,6 +126,17 @@ def datareduct(pts, idx, k) -> np.ndarray:
     idx = _i32(idx)
     out = np.empty(max(1, min(len(idx), k)), dtype=np.int32)
     cnt = lib().h2o_datareduct(pts.shape[1], _d(pts), _i(idx), len(idx), int(k), _i(out))
+    return out[:cnt].copy()
+
+
+def datareduct_seg(pts, idx, seg, k) -> np.ndarray:
+    """DataReduct with one reference grid per segment [seg[s], seg[s+1])."""
+    pts = _f64(pts)
+    idx = _i32(idx)
+    seg = _i32(seg)
+    out = np.empty(max(1, min(len(idx), k * (len(seg) - 1))), dtype=np.int32)
+    cnt = lib().h2o_datareduct_seg(pts.shape[1], _d(pts), _i(idx), len(idx), _i(seg), len(seg) - 1, int(k),
+                                   _i(out))
     return out[:cnt].copy()
 
 

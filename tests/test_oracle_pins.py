@@ -214,6 +214,47 @@ def test_datareduct_nearest_by_kdtree(d, k):
     assert len(out) == len(set(out))
 
 
+def test_datareduct_segments_closed_form():
+    """Two segments, each containing the cell centres of the g^d grid over its
+    own bounding box: every lattice point of both is picked, the first
+    segment's grid first, even though the second lies far away."""
+    g, d = 3, 2
+    lat = _lattice(g, d)
+    A = np.vstack([lat, np.zeros((1, d)), np.ones((1, d))])
+    B = A * 0.25 + 7.0
+    P = np.vstack([A, B])
+    idx = np.arange(len(P))
+    out = O.datareduct_seg(P, idx, [0, len(A), len(P)], g**d)
+    assert len(out) == 2 * g**d
+    assert np.all(out[:g**d] < len(A)) and np.all(out[g**d:] >= len(A))
+    np.testing.assert_array_equal(np.sort(P[out[:g**d]], axis=0), np.sort(lat, axis=0))
+    # one segment reproduces the plain DataReduct
+    assert np.array_equal(O.datareduct_seg(P, idx, [0, len(P)], 20), O.datareduct(P, idx, 20))
+
+
+def test_datareduct_segments_nearest_over_whole_list():
+    """Each reference point of a segment's grid takes its nearest point among
+    all segments (cKDTree over the whole list)."""
+    rng = np.random.default_rng(9)
+    A = rng.random((300, 3))
+    B = rng.random((200, 3)) * 0.3 + 0.8  # overlaps A's bounding box
+    P = np.vstack([A, B])
+    idx = rng.permutation(len(P))
+    cut = 250
+    seg = [0, cut, len(P)]
+    k = 27
+    out = O.datareduct_seg(P, idx, seg, k)
+    tree = cKDTree(P[idx])
+    want = []
+    for s0, s1 in ((0, cut), (cut, len(P))):
+        lo, hi = P[idx[s0:s1]].min(0), P[idx[s0:s1]].max(0)
+        ax = [lo[a] + (hi[a] - lo[a]) * ((2 * np.arange(3) + 1) / 6) for a in range(3)]
+        Q = np.stack(np.meshgrid(*ax, indexing="ij"), -1).transpose(2, 1, 0, 3).reshape(-1, 3)
+        want += list(idx[tree.query(Q)[1]])
+    assert set(out) == set(want)
+    assert list(out) == list(dict.fromkeys(want))  # first-occurrence order
+
+
 # --------------------------------------------------------------- CPQR-ID
 @pytest.mark.parametrize("m,s,seed", [(40, 60, 0), (60, 40, 1), (33, 33, 2), (200, 90, 3)])
 def test_cpqr_pivots_match_lapack(m, s, seed):
@@ -279,7 +320,8 @@ def _ancestors(parent, i):
 
 @pytest.mark.parametrize("d,n,q,r", [(2, 3000, 20, 16), (3, 4000, 30, 27)])
 def test_hidr_bounds_and_farfield(d, n, q, r):
-    """Theorem 3.1 bounds |X_i^*| <= r1, |Y_i^*| <= r2; X_i^* lies in X_i;
+    """Theorem 3.1 bounds |X_i^*| <= r1, |Y_i^*| <= 2 r2 (one reference grid for
+    each of the two parts of T_i); X_i^* lies in X_i;
     every point of Y_i^* lies in a node admissible to i or to an ancestor of
     i (it belongs to the farfield)."""
     rng = np.random.default_rng(20 + d)
@@ -296,7 +338,7 @@ def test_hidr_bounds_and_farfield(d, n, q, r):
     for i in range(1, len(start)):
         xs = h.node_list("xstar", i)
         ys = h.node_list("ystar", i)
-        assert len(xs) <= r and len(ys) <= r
+        assert len(xs) <= r and len(ys) <= 2 * r  # two reference grids for T_i
         assert np.all((xs >= start[i]) & (xs < start[i] + count[i]))
         if nch[i] > 0:
             S = sum(len(h.node_list("xstar", c)) for c in range(fc[i], fc[i] + nch[i]))
