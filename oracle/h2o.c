@@ -215,8 +215,9 @@ int h2o_datareduct(int d, const double *pts, const int *list, int L, int k, int 
  * Column norms are down-dated with the safeguard of Drmac and Bujanovic
  * (LAPACK Working Note 176): recompute whenever the down-dated value has
  * lost about half of its digits.
- * Rank rule (paper silent): stop before step j when |R_jj| <= tol |R_00|, or
- * when j = min(s, m); if A is zero, k = 0.
+ * Rank rule (paper silent): stop before step j when |R_jj| <= tol |R_00| for
+ * the column step j would pivot in (which is then left in place), or when
+ * j = min(s, m); if A is zero, k = 0.
  *
  * Outputs: piv (m entries, a permutation of 0..m-1; the first k are the
  * skeleton rows, in pivot order), T (k x (m-k), T[t*(m-k)+u] couples
@@ -258,6 +259,14 @@ int h2o_cpqr_id(const double *A, int m, int s, double tol, int *piv, double *T, 
                 p = c;
                 break;
             }
+        /* exact norm of the trailing pivot column = |R_jj|; the step that
+         * stops leaves the columns in place */
+        double ss = 0.0;
+        for (int r = j; r < s; ++r)
+            ss = ss + M[(size_t)p * s + r] * M[(size_t)p * s + r];
+        double alpha = sqrt(ss);
+        if (j == 0) r00 = alpha;
+        if (alpha == 0.0 || alpha <= tol * r00) break;
         if (p != j) {
             for (int r = 0; r < s; ++r) {
                 double t = M[(size_t)j * s + r];
@@ -268,14 +277,7 @@ int h2o_cpqr_id(const double *A, int m, int s, double tol, int *piv, double *T, 
             t = nu0[j]; nu0[j] = nu0[p]; nu0[p] = t;
             int ti = piv[j]; piv[j] = piv[p]; piv[p] = ti;
         }
-        /* exact norm of the trailing pivot column = |R_jj| */
         double *x = M + (size_t)j * s;
-        double ss = 0.0;
-        for (int r = j; r < s; ++r)
-            ss = ss + x[r] * x[r];
-        double alpha = sqrt(ss);
-        if (j == 0) r00 = alpha;
-        if (alpha == 0.0 || alpha <= tol * r00) break;
         /* Householder reflector H = I - 2 v v^T / (v^T v) mapping x to beta e_j */
         double beta = x[j] >= 0.0 ? -alpha : alpha;
         for (int r = j; r < s; ++r)

@@ -75,8 +75,8 @@ h2_status h2_build_ex(const double* points, int64_t n, int dim, int kernel_id, c
     if (!(tol > 0.0 && tol < 1.0)) return set_err(H2_EINVAL, "tol must be in (0, 1)");
     if (leaf_size < 1) return set_err(H2_EINVAL, "leaf_size must be >= 1");
     if (!(opt.tau > 0.0 && opt.tau < 1.0)) return set_err(H2_EINVAL, "tau must be in (0, 1)");
-    if (opt.r1 < 0 || opt.r2 < 0 || opt.r1 > 4096 || opt.r2 > 4096)
-        return set_err(H2_EINVAL, "r1, r2 must be in [0, 4096]");
+    if (opt.r1 < 0 || opt.r2 < 0 || opt.r1 > 2048 || opt.r2 > 2048)
+        return set_err(H2_EINVAL, "r1, r2 must be in [0, 2048]");
     if (opt.precision != 64) return set_err(H2_EUNSUPPORTED, "only precision 64 is implemented");
     if (opt.store_coupling != 1) return set_err(H2_EUNSUPPORTED, "only stored coupling blocks are implemented");
     double prm = 1.0;
@@ -248,7 +248,7 @@ h2_status h2_export(h2_handle hd, int what, int node, void* host_buf, size_t byt
         case H2_EXP_YSTAR:
             if (!node_ok()) return set_err(H2_EINVAL, "node out of range");
             cnt = h2::read_scalar(h.ys_cnt.p + node, s);
-            src = h.ys_idx.p + (int64_t)node * h.r2;
+            src = h.ys_idx.p + (int64_t)node * h.ys_stride;
             break;
         case H2_EXP_RANK: src = h.rank.p; cnt = h.nnode; break;
         case H2_EXP_MBAR: src = h.mbar.p; cnt = h.nnode; break;
@@ -260,7 +260,7 @@ h2_status h2_export(h2_handle hd, int what, int node, void* host_buf, size_t byt
         case H2_EXP_SKEL:
             if (!node_ok()) return set_err(H2_EINVAL, "node out of range");
             cnt = h.h_rank[node];
-            src = h.skel.p + (int64_t)node * h.r2;
+            src = h.skel.p + (int64_t)node * h.ys_stride;
             break;
         case H2_EXP_T:
             if (!node_ok()) return set_err(H2_EINVAL, "node out of range");

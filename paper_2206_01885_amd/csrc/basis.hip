@@ -11,7 +11,8 @@
 // Rules (identical to the oracle's): pivot = lowest index whose partial norm
 // is within a factor (1 - 2^-40) of the largest; norms down-dated with the
 // LAWN 176 safeguard (recompute once a down-date has lost half the digits);
-// stop before step j when |R_jj| <= tol |R_00| (or j = min(s, m)).
+// stop before step j when |R_jj| <= tol |R_00| for the column it would pivot
+// in, leaving the columns in place (or j = min(s, m)).
 //
 // One workgroup per node; lane c owns columns c, c+256, ...  Each lane runs
 // its columns' dot products, updates and squared tail sums sequentially in row
@@ -26,7 +27,6 @@ namespace h2 {
 namespace {
 
 constexpr int TB = 256;
-constexpr int MAXS = 4096;  // largest s (r2)
 
 __device__ inline double wave_max(double v)
 {
@@ -126,6 +126,12 @@ __global__ __launch_bounds__(NT) void k_batched_id(IdBatch b, const int* __restr
                 break;
             }
         int pc = block_min_i<NT>(cand, redi);
+        // |R_jj| of the candidate; the step that stops swaps nothing
+        if (threadIdx.x == 0) sh_alpha = sqrt(ss[pc]);
+        __syncthreads();
+        const double alpha = sh_alpha;
+        if (j == 0) r00 = alpha;
+        if (alpha == 0.0 || alpha <= b.tol * r00) break;
         if (pc != j) {
             for (int r = threadIdx.x; r < s; r += NT) {
                 double t = M[(int64_t)r * m + j];
@@ -140,11 +146,6 @@ __global__ __launch_bounds__(NT) void k_batched_id(IdBatch b, const int* __restr
             }
         }
         __syncthreads();
-        if (threadIdx.x == 0) sh_alpha = sqrt(ss[j]);
-        __syncthreads();
-        const double alpha = sh_alpha;
-        if (j == 0) r00 = alpha;
-        if (alpha == 0.0 || alpha <= b.tol * r00) break;
         const double xj = M[(int64_t)j * m + j];
         const double beta = xj >= 0.0 ? -alpha : alpha;
         for (int r = j + threadIdx.x; r < s; r += NT) v[r] = M[(int64_t)r * m + j];
@@ -282,10 +283,9 @@ void build_bases(Handle& h)
 {
     hipStream_t s = h.stream;
     const int nn = h.nnode;
-    if (h.r2 > MAXS) fail(H2_EUNSUPPORTED, "r2 above 4096");
     h.rank.ensure((size_t)nn, s);
     h.mbar.ensure((size_t)nn, s);
-    h.skel.ensure((size_t)nn * h.r2, s);
+    h.skel.ensure((size_t)nn * h.ys_stride, s);
     h.piv_off.ensure((size_t)nn + 1, s);
     h.T_off.ensure((size_t)nn + 1, s);
     H2_HIP(hipMemsetAsync(h.rank.p, 0, sizeof(int) * nn, s));
@@ -331,7 +331,7 @@ void build_bases(Handle& h)
                 mv.push_back(m);
                 sv.push_back(sy);
                 xoff.push_back(xo);
-                yoff.push_back((int64_t)i * h.r2);
+                yoff.push_back((int64_t)i * h.ys_stride);
                 Moff.push_back(ws);
                 nuoff.push_back(no);
                 pivoff.push_back(piv_total);
@@ -362,7 +362,7 @@ void build_bases(Handle& h)
             Mws.ensure((size_t)std::max<int64_t>(ws, 1), s);
             nuws.ensure((size_t)std::max<int64_t>(no, 1), s);
             k_xbar_fill<<<np, TB, 0, s>>>(c0, h.nchild.p, h.first_child.p, h.start.p, h.count.p, h.rank.p, h.skel.p,
-                                          h.r2, d_xoff.p, d_xidx.p);
+                                          h.ys_stride, d_xoff.p, d_xidx.p);
             H2_LAUNCH_CHECK();
             IdBatch b;
             b.nprob = np;
@@ -386,8 +386,8 @@ void build_bases(Handle& h)
             b.piv_off = d_pivoff.p;
             b.T_out = h.T.p;
             b.T_off = d_Toff.p;
-            b.skel_out = h.skel.p + (int64_t)c0 * h.r2;
-            b.skel_stride = h.r2;
+            b.skel_out = h.skel.p + (int64_t)c0 * h.ys_stride;
+            b.skel_stride = h.ys_stride;
             batched_id(b, mv, sv, h.d, h.kid, h.prm, s);
             std::vector<int> rk = read_vec(h.rank.p + c0, np, s);
             for (int t = 0; t < np; ++t) h.h_rank[c0 + t] = rk[t];

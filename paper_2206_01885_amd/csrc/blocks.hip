@@ -127,7 +127,7 @@ void build_blocks(Handle& h)
     H2_HIP(hipMemcpyAsync(d_xo.p, xo.data(), xo.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
     DBuf<double> skc;
     skc.ensure((size_t)h.d * sumk, s);
-    k_skel_coords<<<nn, TB, 0, s>>>(nn, h.pts.p, h.n, h.d, h.rank.p, h.skel.p, h.r2, d_xo.p, sumk, skc.p);
+    k_skel_coords<<<nn, TB, 0, s>>>(nn, h.pts.p, h.n, h.d, h.rank.p, h.skel.p, h.ys_stride, d_xo.p, sumk, skc.p);
     H2_LAUNCH_CHECK();
     // coupling
     k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, h.il_col.p, h.rank.p, sz.p);

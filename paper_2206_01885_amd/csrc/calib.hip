@@ -204,7 +204,7 @@ void run_calibration(Handle& h)
             const int rs = std::min(r, NZ);  // |Y*| <= min(r, 512)
             ycnt.ensure(np, s);
             yidx.ensure((size_t)np * rs, s);
-            datareduct_lists(Z.p, ld, d, zoff.p, z2idx.p, np, r, yidx.p, rs, ycnt.p, s);
+            datareduct_lists(Z.p, ld, d, zoff.p, z2idx.p, nullptr, np, r, yidx.p, rs, ycnt.p, s);
             // ID workspaces
             std::vector<int64_t> h_yoff(np), h_Moff(np), h_nuoff(np), h_pivoff(np), h_Toff(np);
             for (int p = 0; p < np; ++p) {

@@ -146,14 +146,15 @@ struct Handle {
 
     // HiDR representor sets, fixed stride per node
     DBuf<int> xs_cnt, xs_idx;  // stride r1
-    DBuf<int> ys_cnt, ys_idx;  // stride r2
+    DBuf<int> ys_cnt, ys_idx;  // stride ys_stride = 2*r2 (two reference grids)
+    int ys_stride = 0;
     std::vector<int> calib_r;
     std::vector<double> calib_err;
 
     // bases
     DBuf<int> rank, mbar;
     std::vector<int> h_rank, h_mbar;
-    DBuf<int> skel;         // stride r2: skeleton tree positions in pivot order
+    DBuf<int> skel;         // stride ys_stride: skeleton tree positions in pivot order
     DBuf<int64_t> piv_off;  // per node offset into piv
     DBuf<int> piv;          // per node m_i entries
     DBuf<int64_t> T_off;    // per node offset into T (row-major k x (m-k))
@@ -211,8 +212,10 @@ void matvec(Handle& h, const double* x, double* y, int nrhs, hipStream_t s);  //
 // the calibration.  For each of `nlist` lists (indices into the SoA point
 // array pts with leading dimension ld), writes up to k selected indices to
 // out[list * out_stride ...] and the count to out_cnt[list].
+// `split` (may be NULL) gives, per list, the length of its first part: the
+// reference set then holds one grid per non-empty part.
 void datareduct_lists(const double* pts, int64_t ld, int d, const int64_t* list_off, const int* list_idx,
-                      int nlist, int k, int* out, int out_stride, int* out_cnt, hipStream_t s);
+                      const int* split, int nlist, int k, int* out, int out_stride, int* out_cnt, hipStream_t s);
 
 // Batched ID (basis.hip): one problem per entry.  Problem p has rows X
 // (m_p indices into pts) and columns Y (s_p indices into pts2); the kernel
