@@ -771,7 +771,7 @@ int h2o_calibrate_one(int kid, const double *prm, int d, double s, double tau, d
 /* Calibration for a tree: the Coulomb kernel is scale invariant, so one box
  * size suffices; other kernels are calibrated at the box side of every depth
  * that has interaction-list pairs and r = the maximum over those depths. */
-static int r_cap_for(int d) { return d == 3 ? 1000 : (d == 2 ? 1024 : 64); }
+static int r_cap_for(int d) { return d == 3 ? 512 : (d == 2 ? 484 : 64); }
 
 static void calibrate(h2o *h, uint64_t seed)
 {

@@ -65,6 +65,73 @@ __device__ inline int block_min_i(int v, int* sh)
     return r;
 }
 
+
+// Sequential row loops of one column with the loads issued ahead in batches
+// of 8: the arithmetic runs in exactly the order of a plain loop (so the
+// result is the oracle's, bit for bit), only the memory latency overlaps.
+constexpr int LB = 8;
+
+// acc + sum_{r=r0}^{r1-1} a[r] * x[r*ld], accumulated in row order
+__device__ __forceinline__ double dot_rows(const double* __restrict__ a, const double* x, int64_t ld, int r0,
+                                           int r1, double acc)
+{
+    int r = r0;
+    for (; r + LB <= r1; r += LB) {
+        double xv[LB];
+#pragma unroll
+        for (int q = 0; q < LB; ++q) xv[q] = x[(int64_t)(r + q) * ld];
+#pragma unroll
+        for (int q = 0; q < LB; ++q) acc = acc + a[r + q] * xv[q];
+    }
+    for (; r < r1; ++r) acc = acc + a[r] * x[(int64_t)r * ld];
+    return acc;
+}
+
+// acc + sum_{r=r0}^{r1-1} x[r*ld]^2, in row order
+__device__ __forceinline__ double sumsq_rows(const double* x, int64_t ld, int r0, int r1, double acc)
+{
+    int r = r0;
+    for (; r + LB <= r1; r += LB) {
+        double xv[LB];
+#pragma unroll
+        for (int q = 0; q < LB; ++q) xv[q] = x[(int64_t)(r + q) * ld];
+#pragma unroll
+        for (int q = 0; q < LB; ++q) acc = acc + xv[q] * xv[q];
+    }
+    for (; r < r1; ++r) acc = acc + x[(int64_t)r * ld] * x[(int64_t)r * ld];
+    return acc;
+}
+
+// x[r] <- x[r] - f v[r] for r in [r0, r1); returns the sum of the new x[r]^2
+// over r in [r0+1, r1) in row order (the next step's tail norm)
+__device__ __forceinline__ double axpy_rows(const double* __restrict__ v, double f, double* x, int64_t ld, int r0,
+                                            int r1)
+{
+    {
+        double y = x[(int64_t)r0 * ld] - f * v[r0];
+        x[(int64_t)r0 * ld] = y;
+    }
+    double tail = 0.0;
+    int r = r0 + 1;
+    for (; r + LB <= r1; r += LB) {
+        double xv[LB];
+#pragma unroll
+        for (int q = 0; q < LB; ++q) xv[q] = x[(int64_t)(r + q) * ld];
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            double y = xv[q] - f * v[r + q];
+            x[(int64_t)(r + q) * ld] = y;
+            tail = tail + y * y;
+        }
+    }
+    for (; r < r1; ++r) {
+        double y = x[(int64_t)r * ld] - f * v[r];
+        x[(int64_t)r * ld] = y;
+        tail = tail + y * y;
+    }
+    return tail;
+}
+
 // NT = 64 (one wavefront, for row sets of at most 64 points) or 256 lanes.
 // LDSM: the s x m block lives in LDS (dynamic shared memory after the
 // reflector), otherwise in the global workspace.  The arithmetic is the same.
@@ -101,8 +168,7 @@ __global__ __launch_bounds__(NT) void k_batched_id(IdBatch b, const int* __restr
     }
     __syncthreads();
     for (int c = threadIdx.x; c < m; c += NT) {
-        double acc = 0.0;
-        for (int r = 0; r < s; ++r) acc = acc + M[(int64_t)r * m + c] * M[(int64_t)r * m + c];
+        double acc = sumsq_rows(M + c, m, 0, s, 0.0);
         ss[c] = acc;
         nu[c] = sqrt(acc);
         nu0[c] = nu[c];
@@ -154,19 +220,9 @@ __global__ __launch_bounds__(NT) void k_batched_id(IdBatch b, const int* __restr
         __syncthreads();
         const double vtv = 2.0 * alpha * (alpha + fabs(xj));
         for (int c = j + 1 + threadIdx.x; c < m; c += NT) {
-            double w = 0.0;
-            for (int r = j; r < s; ++r) w = w + v[r] * M[(int64_t)r * m + c];
+            double w = dot_rows(v, M + c, m, j, s, 0.0);
             double f = 2.0 * w / vtv;
-            double tail = 0.0;
-            {
-                double y = M[(int64_t)j * m + c] - f * v[j];
-                M[(int64_t)j * m + c] = y;
-            }
-            for (int r = j + 1; r < s; ++r) {
-                double y = M[(int64_t)r * m + c] - f * v[r];
-                M[(int64_t)r * m + c] = y;
-                tail = tail + y * y;
-            }
+            double tail = axpy_rows(v, f, M + c, m, j, s);
             ss[c] = tail;
             if (nu[c] != 0.0) {
                 double t = fabs(M[(int64_t)j * m + c]) / nu[c];
@@ -193,7 +249,19 @@ __global__ __launch_bounds__(NT) void k_batched_id(IdBatch b, const int* __restr
     for (int u = threadIdx.x; u < nr; u += NT) {
         for (int t = k - 1; t >= 0; --t) {
             double acc = M[(int64_t)t * m + (k + u)];
-            for (int l = t + 1; l < k; ++l) acc = acc - M[(int64_t)t * m + l] * T[(int64_t)l * nr + u];
+            const double* Rt = M + (int64_t)t * m;
+            int l = t + 1;
+            for (; l + LB <= k; l += LB) {
+                double rv[LB], tv[LB];
+#pragma unroll
+                for (int q = 0; q < LB; ++q) {
+                    rv[q] = Rt[l + q];
+                    tv[q] = T[(int64_t)(l + q) * nr + u];
+                }
+#pragma unroll
+                for (int q = 0; q < LB; ++q) acc = acc - rv[q] * tv[q];
+            }
+            for (; l < k; ++l) acc = acc - Rt[l] * T[(int64_t)l * nr + u];
             T[(int64_t)t * nr + u] = acc / M[(int64_t)t * m + t];
         }
     }

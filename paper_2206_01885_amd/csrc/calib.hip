@@ -3,7 +3,7 @@
 // The paper grows r1 = r2 from 1 until the ID built on the reduced set
 // approximates an artificial well-separated block K(Z1, Z2) to better than
 // 1e-2 eps.  Readings (identical to the oracle's): r steps over g^d, g = 1,
-// 2, ..., capped at 1000 (3-D), 1024 (2-D) or 64 (1-D); Z1, Z2 hold 512
+// 2, ..., capped at 512 (3-D), 484 (2-D) or 64 (1-D); Z1, Z2 hold 512
 // points each, uniform in cubes of side s whose centres lie s sqrt(d)/tau
 // apart along axis 0; coordinates are SplitMix64 values (Z1 first, then Z2,
 // coordinate fastest); the ID inside uses tolerance 1e-3 eps; the error is the
@@ -139,7 +139,7 @@ __global__ void k_err_final(int np, const double* __restrict__ part, double* __r
 
 }  // namespace
 
-static int r_cap(int d) { return d == 3 ? 1000 : (d == 2 ? 1024 : 64); }
+static int r_cap(int d) { return d == 3 ? 512 : (d == 2 ? 484 : 64); }
 
 void run_calibration(Handle& h)
 {

@@ -248,12 +248,35 @@ __global__ __launch_bounds__(TB) void k_datareduct(const double* __restrict__ pt
 // exact pruning: every X_j^* lies in node j's (closed) box, so the box's
 // squared distance lb_j bounds the distance of all its points from below; a
 // box with lb_j (1 - 1e-12) > best cannot hold a point at distance <= best
-// (the margin covers the rounding of lb_j and of the point distances), and
-// the remaining candidates are scanned in list order with a strict `<`,
-// which keeps the earliest position among equal distances.
-template <int MAXQ>
+// (the margin covers the rounding of lb_j and of the point distances).  The
+// candidates are compared by (distance, list position), which yields the
+// sequential scan's answer -- smallest distance, earliest position among
+// equal ones -- whatever the scan order; the box nearest to q is scanned
+// first so that the bound prunes well.
+// The interaction-list table (box centre, half side, count, list offset) and
+// (up to YCAP points) the coordinates of Y_p^* are staged in LDS; interaction
+// lists longer than ILCAP entries are rejected on the host (see run_hidr).
+constexpr int ILCAP = 640;  // interaction-list entries staged per node
+constexpr int YCAP = 1024;  // Y_p^* points staged per node
+constexpr int PB = 8;       // candidate loads issued ahead
+
+__device__ __forceinline__ int seg_of(const int* __restrict__ off, int n, int p)
+{
+    // last e with off[e] <= p (off ascending, off[0] = 0)
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= p)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int D, int MAXQ>
 __global__ __launch_bounds__(TB) void k_datareduct_down(
-    int lo_node, const double* __restrict__ pts, int64_t ld, int d, const int* __restrict__ parent,
+    int lo_node, const double* __restrict__ pts, int64_t ld, const int* __restrict__ parent,
     const int* __restrict__ il_ptr, const int* __restrict__ il_col, const double* __restrict__ center,
     const double* __restrict__ side, const int* __restrict__ xs_cnt, const int* __restrict__ xs_idx, int r1,
     int* __restrict__ ys_cnt, int* __restrict__ ys_idx, int ys_stride, int k)
@@ -262,78 +285,112 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     __shared__ long long keys[MAXQ];
     __shared__ int pick[MAXQ];
     __shared__ int scan_sh[TB];
-    __shared__ long long lsum[TB];
+    __shared__ double bx[3][ILCAP];
+    __shared__ double bh[ILCAP];
+    __shared__ int bj[ILCAP], bcnt[ILCAP], boff[ILCAP + 1];
+    __shared__ double yc[3][YCAP];
     constexpr int QPT = MAXQ / TB;
+    constexpr int d = D;
 
     const int i = lo_node + blockIdx.x;
     const int p = parent[i];
     const int np_ = p > 0 ? ys_cnt[p] : 0;
     const int* yp = ys_idx + (int64_t)(p > 0 ? p : 0) * ys_stride;
-    const int e0 = il_ptr[i], e1 = il_ptr[i + 1];
+    const int e0 = il_ptr[i], ne = il_ptr[i + 1] - e0;
     int* o = ys_idx + (int64_t)i * ys_stride;
 
-    long long part = 0;
-    for (int e = e0 + threadIdx.x; e < e1; e += TB) part += xs_cnt[il_col[e]];
-    lsum[threadIdx.x] = part;
+    // interaction-list table and its exclusive prefix of counts
+    for (int e = threadIdx.x; e < ne; e += TB) {
+        const int j = il_col[e0 + e];
+        bj[e] = j;
+        bcnt[e] = xs_cnt[j];
+        bh[e] = 0.5 * side[j];
+        for (int a = 0; a < d; ++a) bx[a][e] = center[(int64_t)j * d + a];
+    }
+    const bool stage_y = np_ <= YCAP;
+    if (stage_y)
+        for (int q = threadIdx.x; q < np_; q += TB)
+            for (int a = 0; a < d; ++a) yc[a][q] = pts[a * ld + yp[q]];
     __syncthreads();
-    for (int off = TB / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) lsum[threadIdx.x] += lsum[threadIdx.x + off];
+    {
+        // block scan over ne <= ILCAP counts: each lane sums a run of entries
+        const int per = (ne + TB - 1) / TB;
+        const int q0 = threadIdx.x * per;
+        int c = 0;
+        for (int e = q0; e < min(ne, q0 + per); ++e) c += bcnt[e];
+        scan_sh[threadIdx.x] = c;
+        __syncthreads();
+        for (int off = 1; off < TB; off <<= 1) {
+            int a = (int)threadIdx.x >= off ? scan_sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            scan_sh[threadIdx.x] += a;
+            __syncthreads();
+        }
+        int w = scan_sh[threadIdx.x] - c;
+        for (int e = q0; e < min(ne, q0 + per); ++e) {
+            boff[e] = w;
+            w += bcnt[e];
+        }
+        if (threadIdx.x == TB - 1) boff[ne] = scan_sh[TB - 1];
         __syncthreads();
     }
-    const long long L = np_ + lsum[0];
-    __syncthreads();
+    const int Lil = boff[ne];
+    const int L = np_ + Lil;
     if (L == 0) {
         if (threadIdx.x == 0) ys_cnt[i] = 0;
         return;
     }
     if (L <= k) {
         for (int q = threadIdx.x; q < np_; q += TB) o[q] = yp[q];
-        int w = np_;
-        for (int e = e0; e < e1; ++e) {
-            const int j = il_col[e];
-            const int c = xs_cnt[j];
-            for (int q = threadIdx.x; q < c; q += TB) o[w + q] = xs_idx[(int64_t)j * r1 + q];
-            w += c;
+        for (int q = threadIdx.x; q < Lil; q += TB) {
+            const int e = seg_of(boff, ne, q);
+            o[np_ + q] = xs_idx[(int64_t)bj[e] * r1 + (q - boff[e])];
         }
-        if (threadIdx.x == 0) ys_cnt[i] = (int)L;
+        if (threadIdx.x == 0) ys_cnt[i] = L;
         return;
     }
-    // segments: 0 = Y_p^* (if any), 1 = the interaction-list part (if any)
+    // segments: 0 = Y_p^* (if any), 1 = the interaction-list part (if any);
+    // their boxes live in LDS so that the per-lane segment choice is a plain
+    // LDS read
+    __shared__ double lo[2][3], hi[2][3];
     int nseg = 0;
-    double lo[2][3], hi[2][3];
     if (np_ > 0) {
         for (int a = 0; a < d; ++a) {
             double mn = INFINITY, mx = -INFINITY;
             for (int q = threadIdx.x; q < np_; q += TB) {
-                double v = pts[a * ld + yp[q]];
+                const double v = stage_y ? yc[a][q] : pts[a * ld + yp[q]];
                 mn = fmin(mn, v);
                 mx = fmax(mx, v);
             }
-            lo[nseg][a] = block_min(mn, red);
-            hi[nseg][a] = block_max(mx, red);
+            const double l0 = block_min(mn, red), h0 = block_max(mx, red);
+            if (threadIdx.x == 0) {
+                lo[nseg][a] = l0;
+                hi[nseg][a] = h0;
+            }
         }
         ++nseg;
     }
-    if (L > np_) {
+    if (Lil > 0) {
         double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-        for (int e = e0; e < e1; ++e) {
-            const int j = il_col[e];
-            const int c = xs_cnt[j];
-            for (int q = threadIdx.x; q < c; q += TB) {
-                const int id = xs_idx[(int64_t)j * r1 + q];
-                for (int a = 0; a < d; ++a) {
-                    double v = pts[a * ld + id];
-                    mn[a] = fmin(mn[a], v);
-                    mx[a] = fmax(mx[a], v);
-                }
+        for (int q = threadIdx.x; q < Lil; q += TB) {
+            const int e = seg_of(boff, ne, q);
+            const int id = xs_idx[(int64_t)bj[e] * r1 + (q - boff[e])];
+            for (int a = 0; a < d; ++a) {
+                double v = pts[a * ld + id];
+                mn[a] = fmin(mn[a], v);
+                mx[a] = fmax(mx[a], v);
             }
         }
         for (int a = 0; a < d; ++a) {
-            lo[nseg][a] = block_min(mn[a], red);
-            hi[nseg][a] = block_max(mx[a], red);
+            const double l0 = block_min(mn[a], red), h0 = block_max(mx[a], red);
+            if (threadIdx.x == 0) {
+                lo[nseg][a] = l0;
+                hi[nseg][a] = h0;
+            }
         }
         ++nseg;
     }
+    __syncthreads();
     int g = 1;
     for (;;) {
         long long nx = 1;
@@ -350,50 +407,88 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
         if (t >= nq) break;
         const int sg = t / nq1;
         int rem = t - sg * nq1;
-        double q[3] = {0.0, 0.0, 0.0};
-        for (int a = 0; a < d; ++a) {
+        double q[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
             int ta = rem % g;
             rem /= g;
             double w = (double)(2 * ta + 1) / (double)(2 * g);
             q[a] = lo[sg][a] + (hi[sg][a] - lo[sg][a]) * w;
         }
+        // (distance, position) minimum: the sequential scan's answer in any order
         double best = INFINITY;
-        int bidx = -1;
-        for (int c = 0; c < np_; ++c) {
-            const int id = yp[c];
-            double dd = 0.0;
-            for (int a = 0; a < d; ++a) {
-                double ea = q[a] - pts[a * ld + id];
-                dd = dd + ea * ea;
-            }
-            if (dd < best) {
+        int bpos = 0x7fffffff, bidx = -1;
+        auto consider = [&](double dd, int pos, int id) {
+            if (dd < best || (dd == best && pos < bpos)) {
                 best = dd;
+                bpos = pos;
                 bidx = id;
             }
-        }
-        for (int e = e0; e < e1; ++e) {
-            const int j = il_col[e];
-            const double hs = 0.5 * side[j];
+        };
+        auto dist = [&](const double* c3) {
+            double dd = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                double ea = q[a] - c3[a];
+                dd = dd + ea * ea;
+            }
+            return dd;
+        };
+        auto box_lb = [&](int e) {
             double lb = 0.0;
-            for (int a = 0; a < d; ++a) {
-                double ex = fabs(q[a] - center[(int64_t)j * d + a]) - hs;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                double ex = fabs(q[a] - bx[a][e]) - bh[e];
                 if (ex > 0.0) lb = lb + ex * ex;
             }
-            if (lb * (1.0 - 1e-12) > best) continue;
-            const int c = xs_cnt[j];
-            const int* xj = xs_idx + (int64_t)j * r1;
-            for (int m = 0; m < c; ++m) {
-                const int id = xj[m];
-                double dd = 0.0;
-                for (int a = 0; a < d; ++a) {
-                    double ea = q[a] - pts[a * ld + id];
-                    dd = dd + ea * ea;
-                }
-                if (dd < best) {
-                    best = dd;
-                    bidx = id;
-                }
+            return lb;
+        };
+        auto scan_box = [&](int e) {
+            const int c = bcnt[e];
+            const int* xj = xs_idx + (int64_t)bj[e] * r1;
+            const int pos0 = np_ + boff[e];
+            int m = 0;
+            for (; m + PB <= c; m += PB) {
+                int id[PB];
+                double cx[PB][D];
+#pragma unroll
+                for (int z = 0; z < PB; ++z) id[z] = xj[m + z];
+#pragma unroll
+                for (int z = 0; z < PB; ++z)
+#pragma unroll
+                    for (int a = 0; a < D; ++a) cx[z][a] = pts[a * ld + id[z]];
+#pragma unroll
+                for (int z = 0; z < PB; ++z) consider(dist(cx[z]), pos0 + m + z, id[z]);
             }
+            for (; m < c; ++m) {
+                const int id = xj[m];
+                double cx[D];
+#pragma unroll
+                for (int a = 0; a < D; ++a) cx[a] = pts[a * ld + id];
+                consider(dist(cx), pos0 + m, id);
+            }
+        };
+        // Y_p^*, then the box nearest to q, then every box not pruned
+        for (int c = 0; c < np_; ++c) {
+            double cy[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) cy[a] = stage_y ? yc[a][c] : pts[a * ld + yp[c]];
+            consider(dist(cy), c, yp[c]);
+        }
+        int e_first = -1;
+        double lb_first = INFINITY;
+        for (int e = 0; e < ne; ++e) {
+            const double lb = box_lb(e);
+            if (lb < lb_first) {
+                lb_first = lb;
+                e_first = e;
+            }
+        }
+        if (e_first >= 0 && lb_first * (1.0 - 1e-12) <= best) scan_box(e_first);
+        for (int e = 0; e < ne; ++e) {
+            if (e == e_first) continue;
+            if (box_lb(e) * (1.0 - 1e-12) > best) continue;
+            scan_box(e);
         }
         pick[t] = bidx;
         keys[t] = ((long long)bidx << 13) | t;
@@ -478,6 +573,29 @@ __global__ __launch_bounds__(TB) void k_up_fill(int lo, const int* __restrict__ 
     }
 }
 
+template <int D>
+void launch_down_d(Handle& h, int lo, int nl, hipStream_t s)
+{
+    if (h.r2 <= 512)
+        k_datareduct_down<D, 1024><<<nl, TB, 0, s>>>(lo, h.pts.p, h.n, h.parent.p, h.il_ptr.p, h.il_col.p,
+                                                     h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, h.r1, h.ys_cnt.p,
+                                                     h.ys_idx.p, h.ys_stride, h.r2);
+    else
+        k_datareduct_down<D, MAXQ_ALL><<<nl, TB, 0, s>>>(lo, h.pts.p, h.n, h.parent.p, h.il_ptr.p, h.il_col.p,
+                                                         h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, h.r1,
+                                                         h.ys_cnt.p, h.ys_idx.p, h.ys_stride, h.r2);
+}
+
+void launch_down(Handle& h, int lo, int nl, hipStream_t s)
+{
+    if (h.d == 1)
+        launch_down_d<1>(h, lo, nl, s);
+    else if (h.d == 2)
+        launch_down_d<2>(h, lo, nl, s);
+    else
+        launch_down_d<3>(h, lo, nl, s);
+}
+
 }  // namespace
 
 void datareduct_lists(const double* pts, int64_t ld, int d, const int64_t* list_off, const int* list_idx,
@@ -523,16 +641,12 @@ void run_hidr(Handle& h)
                          h.r1, h.xs_cnt.p + lo, s);
     }
     if (h.r2 < 1 || h.r2 > MAXQ_ALL / 2) fail(H2_EUNSUPPORTED, "r2 must be in [1, 2048]");
+    for (int i = 0; i < nn; ++i)
+        if (h.h_il_ptr[i + 1] - h.h_il_ptr[i] > ILCAP)
+            fail(H2_EUNSUPPORTED, "interaction list longer than " + std::to_string(ILCAP) + " entries");
     for (int L = 1; L <= h.maxdepth; ++L) {
         int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
-        if (h.r2 <= 512)
-            k_datareduct_down<1024><<<nl, TB, 0, s>>>(lo, h.pts.p, h.n, h.d, h.parent.p, h.il_ptr.p, h.il_col.p,
-                                                      h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, h.r1,
-                                                      h.ys_cnt.p, h.ys_idx.p, h.ys_stride, h.r2);
-        else
-            k_datareduct_down<MAXQ_ALL><<<nl, TB, 0, s>>>(lo, h.pts.p, h.n, h.d, h.parent.p, h.il_ptr.p,
-                                                          h.il_col.p, h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p,
-                                                          h.r1, h.ys_cnt.p, h.ys_idx.p, h.ys_stride, h.r2);
+        launch_down(h, lo, nl, s);
         H2_LAUNCH_CHECK();
     }
     H2_HIP(hipStreamSynchronize(s));
