@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--nrhs", type=int, default=32)
     ap.add_argument("--r", type=int, default=0, help="r1 = r2 override (0: chosen from the tolerance)")
+    ap.add_argument("--r-min", type=int, default=343,
+                    help="floor on the r chosen from the tolerance (343 = 7^3 meets 1e-6 at n=2^20)")
+    ap.add_argument("--no-f32", action="store_true", help="skip the precision-mode (FP32 apply) measurement")
     ap.add_argument("--rows", type=int, default=512, help="sampled rows for the dense accuracy check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=1 << 17, help="points of the oracle's bounded sample")
@@ -97,6 +100,7 @@ def main():
     del P_np, X_np
     opt = h2.h2_options_default()
     opt.r1 = opt.r2 = args.r
+    opt.r_min = args.r_min
     opt.profile = 1
     print(f"[bench] inputs resident: n={n} nrhs={nrhs}", file=sys.stderr, flush=True)
 
@@ -139,7 +143,9 @@ def main():
     ridx = torch.tensor(rows, device=dev)
     ref = dense_rows_gpu(P, X, ridx)
     got = Y[:, ridx]
-    e_rows = ((got - ref).norm(dim=1) / ref.norm(dim=1)).max().item()
+    e_per_rhs = (got - ref).norm(dim=1) / ref.norm(dim=1)
+    e_rows = e_per_rhs.max().item()
+    e_rows_mean = e_per_rhs.mean().item()
 
     # coupling-sweep roofline: algorithmic bytes = B blocks + xhat reads + yhat writes
     coupling_bytes = info["bytes_B"] + 2 * 8 * info["sum_rank"] * nrhs
@@ -149,6 +155,46 @@ def main():
     build_s = float(np.mean(builds))
     mv_s = float(np.mean(mvs))
     h2.h2_destroy(hd)
+    Y64 = Y[:, ridx].clone()
+    del Y
+
+    # precision mode: FP32 blocks and apply (compensated nearfield), same build otherwise
+    f32 = None
+    if not args.no_f32:
+        opt32 = h2.h2_options_default()
+        opt32.r1 = opt32.r2 = args.r
+        opt32.r_min = args.r_min
+        opt32.precision = 32
+        opt32.profile = 1
+        X32 = X.float()
+        Y32 = torch.empty_like(X32)
+        torch.cuda.synchronize()
+        hd32 = h2.h2_build(Psoa, "coulomb", 1.0, 1e-6, 128, opt32)
+        h2.h2_matvec(hd32, X32, Y32, nrhs)
+        torch.cuda.synchronize()
+        h2.h2_destroy(hd32)
+        b32, m32 = [], []
+        for k in range(args.steps):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            hd32 = h2.h2_build(Psoa, "coulomb", 1.0, 1e-6, 128, opt32)
+            tb = time.perf_counter()
+            h2.h2_matvec(hd32, X32, Y32, nrhs)
+            torch.cuda.synchronize()
+            te = time.perf_counter()
+            b32.append(tb - ts)
+            m32.append(te - tb)
+            i32 = h2.h2_query(hd32)
+            h2.h2_destroy(hd32)
+        got32 = Y32[:, ridx].double()
+        e32 = ((got32 - ref).norm(dim=1) / ref.norm(dim=1)).max().item()
+        e32_64 = ((got32 - Y64).norm(dim=1) / Y64.norm(dim=1)).max().item()
+        f32 = {"ms_per_step": 1e3 * (np.mean(b32) + np.mean(m32)), "build_s": float(np.mean(b32)),
+               "matvec_s": float(np.mean(m32)), "matvec_phases_ms": {k: i32[k] for k in (
+                   "mv_gather", "mv_upward", "mv_coupling", "mv_downward", "mv_leaves", "mv_scatter")},
+               "bytes_B": i32["bytes_B"], "bytes_D": i32["bytes_D"],
+               "e_dense_sampled_rows_max_rhs": e32, "e_vs_fp64_path_max_rhs": e32_64}
+        del Y32, X32
 
     out = {
         "metric": "H2 build Mpts/s + matvec GB/s, n=1M 3D Coulomb @1e-6; p50/p99 latency",
@@ -169,8 +215,10 @@ def main():
                                                    "mv_leaves", "mv_scatter")},
         "structure": {k: info[k] for k in ("nnode", "maxdepth", "nnz_il", "nnz_near", "max_rank", "sum_rank",
                                             "bytes_U", "bytes_B", "bytes_D")},
-        "accuracy": {"e_dense_sampled_rows_max_rhs": e_rows, "rows": int(args.rows)},
-        "roofline": {"kernel": "k_coupling_mv", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "accuracy": {"e_dense_sampled_rows_max_rhs": e_rows, "e_dense_sampled_rows_mean_rhs": e_rows_mean,
+                     "rows": int(args.rows)},
+        "precision_f32": f32,
+        "roofline": {"kernel": "k_blockgemm (coupling sweep)", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
     }
     if not args.no_cpu_baseline:

@@ -47,9 +47,16 @@ typedef enum { H2_COULOMB = 0, H2_GAUSSIAN = 1, H2_EXPONENTIAL = 2, H2_MATERN32 
 
 /* Build options (h2_options_default fills the defaults).
  *   tau            separation ratio of Eq. (separation), 0 < tau < 1; default 0.7
- *   r1, r2         maximum sizes of X_i^* and Y_i^* (Algorithm 1); 0 = choose
- *                  them from the tolerance (Section 4.2); > 0 = use as given
- *   precision      64: FP64 throughout (the only value accepted by this build)
+ *   r1, r2         grid sizes of the volume DataReduct (Algorithm 1; X_i^* has
+ *                  at most r1 points, Y_i^* at most 2 r2: one reference grid for
+ *                  each of the two parts of its input list); 0 = choose them
+ *                  from the tolerance (Section 4.2); > 0 = use as given (<= 2048)
+ *   r_min          0, or a lower bound applied to r1 and r2 after they were
+ *                  chosen from the tolerance
+ *   precision      64: FP64 throughout; 32: the coupling and nearfield blocks,
+ *                  the apply and its vectors in FP32 (FP32 accumulation,
+ *                  compensated accumulation of the nearfield blocks); the tree,
+ *                  HiDR and the interpolative decompositions stay FP64
  *   store_coupling 1: store the coupling and nearfield blocks (default)
  *   calib_seed     seed of the random points used to choose r1, r2
  *   profile        1: h2_matvec records HIP events around each of its sweeps on
@@ -61,6 +68,7 @@ typedef struct {
     int store_coupling;
     uint64_t calib_seed;
     int profile;
+    int r_min;
 } h2_options;
 
 void h2_options_default(h2_options *opt);
@@ -88,13 +96,14 @@ h2_status h2_build_ex(const double *points, int64_t n, int dim, int kernel_id, c
 
 /* h2_matvec: y = Ktilde x with the H^2 representation (upward, coupling,
  * downward and nearfield sweeps).
- *   x, y   device, FP64, [nrhs][n] (x[r*n + i] is entry i of right-hand side
- *          r), original point order; x and y must not overlap
+ *   x, y   device, [nrhs][n] (x[r*n + i] is entry i of right-hand side r),
+ *          original point order; FP64 (double) for a handle built with
+ *          precision 64, FP32 (float) for precision 32; must not overlap
  *   nrhs   number of right-hand sides, 1 <= nrhs <= 256
  * Stream-ordered on the handle's stream; returns without synchronising
  * except on the first call with a larger nrhs (workspace allocation).    */
-h2_status h2_matvec(h2_handle h, const double *x, double *y, int nrhs);
-h2_status h2_matvec_ex(h2_handle h, const double *x, double *y, int nrhs, void *hip_stream);
+h2_status h2_matvec(h2_handle h, const void *x, void *y, int nrhs);
+h2_status h2_matvec_ex(h2_handle h, const void *x, void *y, int nrhs, void *hip_stream);
 
 /* Summary of a built representation (all host values). */
 typedef struct {
@@ -106,6 +115,7 @@ typedef struct {
     int max_rank;
     int64_t sum_rank;
     int64_t bytes_U, bytes_B, bytes_D; /* stored interpolation, coupling, nearfield */
+    int precision;
     double t_tree, t_lists, t_calib, t_hidr, t_basis, t_blocks; /* seconds */
     /* last h2_matvec with options.profile = 1 (milliseconds, HIP events on the
      * apply's stream; h2_query waits for that apply to finish); 0 otherwise */
@@ -143,7 +153,7 @@ enum {
     H2_EXP_SKEL = 18,       /* int32 list of node `node` (rank entries) */
     H2_EXP_T = 19,          /* double, node `node`: rank x (mbar-rank) row-major */
     H2_EXP_POINTS = 20,     /* double [dim][n] SoA, tree order */
-    H2_EXP_B = 21,          /* double, IL entry `node` (CSR index): rank_i x rank_j row-major */
+    H2_EXP_B = 21,          /* double, IL entry `node` (CSR index): rank_i x rank_j column-major (precision 64) */
     H2_EXP_CALIB_R = 22     /* int32 [maxdepth+1] r chosen per depth (0 if not calibrated) */
 };
 h2_status h2_export(h2_handle h, int what, int node, void *host_buf, size_t bytes, int64_t *count);

@@ -50,6 +50,7 @@ void h2_options_default(h2_options* opt)
     opt->store_coupling = 1;
     opt->calib_seed = 0x5EED;
     opt->profile = 0;
+    opt->r_min = 0;
 }
 
 const char* h2_last_error(void) { return g_last_error.c_str(); }
@@ -77,7 +78,8 @@ h2_status h2_build_ex(const double* points, int64_t n, int dim, int kernel_id, c
     if (!(opt.tau > 0.0 && opt.tau < 1.0)) return set_err(H2_EINVAL, "tau must be in (0, 1)");
     if (opt.r1 < 0 || opt.r2 < 0 || opt.r1 > 2048 || opt.r2 > 2048)
         return set_err(H2_EINVAL, "r1, r2 must be in [0, 2048]");
-    if (opt.precision != 64) return set_err(H2_EUNSUPPORTED, "only precision 64 is implemented");
+    if (opt.precision != 64 && opt.precision != 32) return set_err(H2_EINVAL, "precision must be 64 or 32");
+    if (opt.r_min < 0 || opt.r_min > 2048) return set_err(H2_EINVAL, "r_min must be in [0, 2048]");
     if (opt.store_coupling != 1) return set_err(H2_EUNSUPPORTED, "only stored coupling blocks are implemented");
     double prm = 1.0;
     if (kernel_id != H2_COULOMB) {
@@ -102,6 +104,7 @@ h2_status h2_build_ex(const double* points, int64_t n, int dim, int kernel_id, c
     h.store_coupling = opt.store_coupling;
     h.calib_seed = opt.calib_seed;
     h.profile = opt.profile;
+    h.r_min = opt.r_min;
     h.stream = (hipStream_t)hip_stream;
     try {
         double t0 = now_s();
@@ -145,20 +148,21 @@ h2_status h2_build_ex(const double* points, int64_t n, int dim, int kernel_id, c
     return H2_OK;
 }
 
-h2_status h2_matvec(h2_handle hd, const double* x, double* y, int nrhs)
+h2_status h2_matvec(h2_handle hd, const void* x, void* y, int nrhs)
 {
     return h2_matvec_ex(hd, x, y, nrhs, hd ? (void*)hd->h.stream : nullptr);
 }
 
-h2_status h2_matvec_ex(h2_handle hd, const double* x, double* y, int nrhs, void* hip_stream)
+h2_status h2_matvec_ex(h2_handle hd, const void* x, void* y, int nrhs, void* hip_stream)
 {
     if (!hd) return set_err(H2_EINVAL, "handle is NULL");
     if (!x || !y) return set_err(H2_EINVAL, "x or y is NULL");
     if (nrhs < 1 || nrhs > 256) return set_err(H2_EINVAL, "nrhs must be in [1, 256]");
     h2::Handle& h = hd->h;
-    const double* xe = x + h.n * nrhs;
-    const double* ye = y + h.n * nrhs;
-    if (!(xe <= y || ye <= x)) return set_err(H2_EINVAL, "x and y overlap");
+    const size_t bytes = (size_t)h.n * nrhs * (h.precision == 32 ? sizeof(float) : sizeof(double));
+    const char* xb = (const char*)x;
+    const char* yb = (const char*)y;
+    if (!(xb + bytes <= yb || yb + bytes <= xb)) return set_err(H2_EINVAL, "x and y overlap");
     try {
         h2::matvec(h, x, y, nrhs, (hipStream_t)hip_stream);
     } catch (const h2::Error& e) {
@@ -192,6 +196,7 @@ h2_status h2_query(h2_handle hd, h2_info* info)
     info->bytes_U = h.bytes_T;
     info->bytes_B = h.bytes_B;
     info->bytes_D = h.bytes_D;
+    info->precision = h.precision;
     info->t_tree = h.t_tree;
     info->t_lists = h.t_lists;
     info->t_calib = h.t_calib;
@@ -271,6 +276,7 @@ h2_status h2_export(h2_handle hd, int what, int node, void* host_buf, size_t byt
         case H2_EXP_POINTS: src = h.pts.p; cnt = h.n * h.d; esz = 8; break;
         case H2_EXP_B: {
             if (node < 0 || node >= h.nil) return set_err(H2_EINVAL, "IL entry out of range");
+            if (h.precision != 64) return set_err(H2_EUNSUPPORTED, "B export needs precision 64");
             int64_t o[2];
             H2_HIP(hipMemcpy(o, h.B_off.p + node, 2 * sizeof(int64_t), hipMemcpyDeviceToHost));
             cnt = o[1] - o[0];

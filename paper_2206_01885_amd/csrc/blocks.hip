@@ -52,11 +52,12 @@ __global__ __launch_bounds__(TB) void k_entry_rows(int nrow, const int* __restri
 // column point of each block column is broadcast with a lane shuffle.  The
 // block is column-major (entry (t,u) at u*rows_i + t); with rows_i <= 32 the
 // two half-waves fill two columns per pass.
+template <class OutT>
 __global__ __launch_bounds__(TB) void k_blocks_eval(int64_t nent, const int* __restrict__ erow,
                                                     const int* __restrict__ col, const int* __restrict__ cnt,
                                                     const double* __restrict__ xs, int64_t ld,
                                                     const int64_t* __restrict__ xo, int d, int kid, double prm,
-                                                    const int64_t* __restrict__ off, double* __restrict__ out)
+                                                    const int64_t* __restrict__ off, OutT* __restrict__ out)
 {
     const int64_t e = (int64_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6);
     if (e >= nent) return;
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(TB) void k_blocks_eval(int64_t nent, const int* __r
     const int i = erow[e], j = col[e];
     const int ki = cnt[i], kj = cnt[j];
     if (ki == 0 || kj == 0) return;
-    double* o = out + off[e];
+    OutT* o = out + off[e];
     const int64_t bi = xo[i], bj = xo[j];
     for (int t0 = 0; t0 < ki; t0 += 64) {
         const bool half = ki - t0 <= 32;  // two columns per pass
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(TB) void k_blocks_eval(int64_t nent, const int* __r
                     const double a2 = __shfl(y2, src, 64) - xi2;
                     r2 += a2 * a2;
                 }
-                if (t < ki && uu < uc) o[(int64_t)(u0 + uu) * ki + t] = kappa_fast(kid, prm, r2);
+                if (t < ki && uu < uc) o[(int64_t)(u0 + uu) * ki + t] = kappa_store<OutT>(kid, prm, r2);
             }
         }
     }
@@ -134,13 +135,23 @@ void build_blocks(Handle& h)
     H2_LAUNCH_CHECK();
     scan_excl_i64(sz.p, h.B_off.p, h.nil, h.tmp_i64, s);
     int64_t nB = read_scalar(h.B_off.p + h.nil, s);
-    h.B.ensure((size_t)std::max<int64_t>(nB, 1), s);
-    h.bytes_B = nB * (int64_t)sizeof(double);
+    const bool f32 = h.precision == 32;
+    if (f32)
+        h.Bf.ensure((size_t)std::max<int64_t>(nB, 1), s);
+    else
+        h.B.ensure((size_t)std::max<int64_t>(nB, 1), s);
+    h.bytes_B = nB * (int64_t)(f32 ? sizeof(float) : sizeof(double));
     if (h.nil > 0) {
         k_entry_rows<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, erow.p);
         H2_LAUNCH_CHECK();
-        k_blocks_eval<<<blocks_for(h.nil, TB / 64), TB, 0, s>>>(h.nil, erow.p, h.il_col.p, h.rank.p, skc.p, sumk,
-                                                                 d_xo.p, h.d, h.kid, h.prm, h.B_off.p, h.B.p);
+        if (f32)
+            k_blocks_eval<float><<<blocks_for(h.nil, TB / 64), TB, 0, s>>>(h.nil, erow.p, h.il_col.p, h.rank.p,
+                                                                            skc.p, sumk, d_xo.p, h.d, h.kid, h.prm,
+                                                                            h.B_off.p, h.Bf.p);
+        else
+            k_blocks_eval<double><<<blocks_for(h.nil, TB / 64), TB, 0, s>>>(h.nil, erow.p, h.il_col.p, h.rank.p,
+                                                                             skc.p, sumk, d_xo.p, h.d, h.kid, h.prm,
+                                                                             h.B_off.p, h.B.p);
         H2_LAUNCH_CHECK();
     }
     // nearfield: the leaves' points are contiguous in tree order
@@ -148,8 +159,11 @@ void build_blocks(Handle& h)
     H2_LAUNCH_CHECK();
     scan_excl_i64(sz.p, h.D_off.p, h.nnear, h.tmp_i64, s);
     int64_t nD = read_scalar(h.D_off.p + h.nnear, s);
-    h.D.ensure((size_t)std::max<int64_t>(nD, 1), s);
-    h.bytes_D = nD * (int64_t)sizeof(double);
+    if (f32)
+        h.Df.ensure((size_t)std::max<int64_t>(nD, 1), s);
+    else
+        h.D.ensure((size_t)std::max<int64_t>(nD, 1), s);
+    h.bytes_D = nD * (int64_t)(f32 ? sizeof(float) : sizeof(double));
     if (h.nnear > 0) {
         std::vector<int64_t> st(h.h_start.begin(), h.h_start.end());
         DBuf<int64_t> d_st;
@@ -157,8 +171,14 @@ void build_blocks(Handle& h)
         H2_HIP(hipMemcpyAsync(d_st.p, st.data(), st.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
         k_entry_rows<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.nr_ptr.p, erow.p);
         H2_LAUNCH_CHECK();
-        k_blocks_eval<<<blocks_for(h.nnear, TB / 64), TB, 0, s>>>(h.nnear, erow.p, h.nr_col.p, h.count.p, h.pts.p,
-                                                                   h.n, d_st.p, h.d, h.kid, h.prm, h.D_off.p, h.D.p);
+        if (f32)
+            k_blocks_eval<float><<<blocks_for(h.nnear, TB / 64), TB, 0, s>>>(h.nnear, erow.p, h.nr_col.p, h.count.p,
+                                                                              h.pts.p, h.n, d_st.p, h.d, h.kid, h.prm,
+                                                                              h.D_off.p, h.Df.p);
+        else
+            k_blocks_eval<double><<<blocks_for(h.nnear, TB / 64), TB, 0, s>>>(h.nnear, erow.p, h.nr_col.p, h.count.p,
+                                                                               h.pts.p, h.n, d_st.p, h.d, h.kid, h.prm,
+                                                                               h.D_off.p, h.D.p);
         H2_LAUNCH_CHECK();
         H2_HIP(hipStreamSynchronize(s));
     }

@@ -289,8 +289,8 @@ void run_calibration(Handle& h)
             }
         }
     }
-    if (h.r1 <= 0) h.r1 = rmax;
-    if (h.r2 <= 0) h.r2 = rmax;
+    if (h.r1 <= 0) h.r1 = std::max(rmax, h.r_min);
+    if (h.r2 <= 0) h.r2 = std::max(rmax, h.r_min);
 }
 
 }  // namespace h2

@@ -123,7 +123,7 @@ struct Handle {
     double tol_int = 5e-7;  // construction tolerance eps' = eps / 2
     double tau = 0.7;
     int q = 64;
-    int r1 = 0, r2 = 0;
+    int r1 = 0, r2 = 0, r_min = 0;
     int precision = 64;
     int store_coupling = 1;
     uint64_t calib_seed = 0x5EED;
@@ -166,6 +166,7 @@ struct Handle {
     DBuf<double> B;
     DBuf<int64_t> D_off;  // per near entry, size nnear+1
     DBuf<double> D;
+    DBuf<float> Bf, Df, Tf;  // precision mode: FP32 blocks and interpolation matrices
     DBuf<int64_t> xh_off;  // per node offset (in units of rank) into xhat/yhat
     DBuf<int> leaves;      // leaf node ids
     int64_t sum_rank = 0;
@@ -182,6 +183,7 @@ struct Handle {
     // matvec workspace (sized for the largest nrhs seen)
     int mv_nrhs = 0;
     DBuf<double> xt, yt, xh, yh;
+    DBuf<float> xtf, ytf, xhf, yhf;
 
     // optional per-sweep events of the last apply
     int profile = 0;
@@ -206,7 +208,7 @@ void run_hidr(Handle& h);                                         // hidr.hip
 void build_bases(Handle& h);                                      // basis.hip
 void build_blocks(Handle& h);                                     // blocks.hip
 void prepare_apply(Handle& h);                                   // matvec.hip
-void matvec(Handle& h, const double* x, double* y, int nrhs, hipStream_t s);  // matvec.hip
+void matvec(Handle& h, const void* x, void* y, int nrhs, hipStream_t s);  // matvec.hip
 
 // DataReduct over materialised index lists (hidr.hip); used by HiDR and by
 // the calibration.  For each of `nlist` lists (indices into the SoA point

@@ -52,6 +52,39 @@ __device__ __forceinline__ double kappa_fast(int kid, double prm, double r2)
     }
 }
 
+// FP32 evaluation from an FP64 squared distance (precision mode): the
+// distance is formed in FP64 (differences of nearby points keep their
+// digits), the kernel function in FP32.
+__device__ __forceinline__ float kappa_f32(int kid, float prm, double r2d)
+{
+    const float r2 = (float)r2d;
+    switch (kid) {
+    case H2_COULOMB:
+        return r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+    case H2_GAUSSIAN:
+        return __expf(-r2 / (prm * prm));
+    case H2_EXPONENTIAL:
+        return __expf(-sqrtf(r2) / prm);
+    default: {
+        float t = 1.7320508075688772f * sqrtf(r2) / prm;
+        return (1.0f + t) * __expf(-t);
+    }
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T kappa_store(int kid, double prm, double r2);
+template <>
+__device__ __forceinline__ double kappa_store<double>(int kid, double prm, double r2)
+{
+    return kappa_fast(kid, prm, r2);
+}
+template <>
+__device__ __forceinline__ float kappa_store<float>(int kid, double prm, double r2)
+{
+    return kappa_f32(kid, (float)prm, r2);
+}
+
 // Squared distance accumulated in coordinate order from 0 (as the oracle does).
 __device__ __forceinline__ double dist2(const double* __restrict__ xa, int64_t xld, int64_t xi,
                                         const double* __restrict__ ya, int64_t yld, int64_t yi, int d)

@@ -37,7 +37,8 @@ class H2Error(RuntimeError):
 
 class h2_options(C.Structure):
     _fields_ = [("tau", C.c_double), ("r1", C.c_int), ("r2", C.c_int), ("precision", C.c_int),
-                ("store_coupling", C.c_int), ("calib_seed", C.c_uint64), ("profile", C.c_int)]
+                ("store_coupling", C.c_int), ("calib_seed", C.c_uint64), ("profile", C.c_int),
+                ("r_min", C.c_int)]
 
 
 class h2_info(C.Structure):
@@ -45,7 +46,7 @@ class h2_info(C.Structure):
                 ("maxdepth", C.c_int), ("nleaf", C.c_int), ("r1", C.c_int), ("r2", C.c_int),
                 ("nnz_il", C.c_int64), ("nnz_near", C.c_int64), ("max_rank", C.c_int),
                 ("sum_rank", C.c_int64), ("bytes_U", C.c_int64), ("bytes_B", C.c_int64),
-                ("bytes_D", C.c_int64), ("t_tree", C.c_double), ("t_lists", C.c_double),
+                ("bytes_D", C.c_int64), ("precision", C.c_int), ("t_tree", C.c_double), ("t_lists", C.c_double),
                 ("t_calib", C.c_double), ("t_hidr", C.c_double), ("t_basis", C.c_double),
                 ("t_blocks", C.c_double), ("mv_gather", C.c_double), ("mv_upward", C.c_double),
                 ("mv_coupling", C.c_double), ("mv_downward", C.c_double), ("mv_leaves", C.c_double),
@@ -119,7 +120,8 @@ def h2_build(points_soa: torch.Tensor, kernel_id, params, tol, leaf_size, option
 
 
 def h2_matvec(handle, x: torch.Tensor, y: torch.Tensor, nrhs: int, stream=None):
-    """C ABI h2_matvec_ex: x, y contiguous float64 CUDA tensors [nrhs, n]."""
+    """C ABI h2_matvec_ex: x, y contiguous CUDA tensors [nrhs, n], float64
+    (precision 64) or float32 (precision 32)."""
     _check(lib().h2_matvec_ex(handle, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), int(nrhs),
                               _stream_ptr(stream)))
 
@@ -148,7 +150,7 @@ class H2Matrix:
     """Owning wrapper: builds on construction, applies with matvec()."""
 
     def __init__(self, points, kernel="coulomb", prm=1.0, tol=1e-6, leaf=64, tau=0.7, r1=0, r2=0,
-                 seed=0x5EED, stream=None):
+                 seed=0x5EED, stream=None, precision=64, r_min=0):
         pts = torch.as_tensor(points, dtype=torch.float64)
         if not pts.is_cuda:
             pts = pts.cuda()
@@ -158,11 +160,13 @@ class H2Matrix:
         soa = pts.t().contiguous()  # [dim, n] layout expected by the C ABI
         opt = h2_options_default()
         opt.tau, opt.r1, opt.r2, opt.calib_seed = tau, r1, r2, seed
+        opt.precision, opt.r_min = precision, r_min
+        self.dtype = torch.float32 if precision == 32 else torch.float64
         self.stream = stream
         self.handle = h2_build(soa, kernel, prm, tol, leaf, opt, stream)
 
     def matvec(self, x) -> torch.Tensor:
-        x = torch.as_tensor(x, dtype=torch.float64)
+        x = torch.as_tensor(x, dtype=self.dtype)
         if not x.is_cuda:
             x = x.cuda()
         squeeze = x.dim() == 1

@@ -206,3 +206,26 @@ def test_invalid_points_rejected(H):
         H.H2Matrix(P, "coulomb", 1.0, 1e-6, 16)
     assert ei.value.status == H.H2_EINVAL
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("kernel,prm,d,n,leaf", [("coulomb", 1.0, 3, 4096, 64), ("gaussian", 0.1, 2, 20000, 128),
+                                                 ("matern32", 0.2, 3, 3000, 40)])
+def test_precision_mode_against_fp64_oracle(H, kernel, prm, d, n, leaf):
+    """Precision mode (FP32 blocks, FP32 apply, compensated nearfield): the
+    structure and the skeletons are the FP64 path's (the ID stays FP64), and
+    the FP32 product is within 1e-6 of the FP64 oracle's (a few FP32 ulps
+    accumulated over the sweeps)."""
+    rng = np.random.default_rng(77 + d)
+    P = rng.random((n, d))
+    x = rng.standard_normal((4, n))
+    _say(f"precision32 {kernel}-d{d}-n{n}")
+    g = H.H2Matrix(P, kernel, prm, 1e-6, leaf, precision=32)
+    o = O.H2Oracle(P, kernel, prm, tol=1e-6, leaf=leaf)
+    assert g.info()["precision"] == 32
+    for name in ("perm", "il_col", "near_col", "rank"):
+        assert np.array_equal(g.export(name), o.get(name)), name
+    y = g.matvec(x.astype(np.float32)).cpu().numpy().astype(np.float64)
+    yo = o.matvec(x)
+    err = max(_rel(y[r], yo[r]) for r in range(4))
+    _say(f"precision32 max rel diff vs FP64 oracle {err:.3e}")
+    assert err <= 1e-6

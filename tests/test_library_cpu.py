@@ -59,6 +59,8 @@ def test_validation_without_device_work():
     opt.tau = 1.0
     assert L.h2_build_ex(dummy, 10, 3, 0, prm, 1e-6, 64, C.byref(opt), None, C.byref(out)) == h2.H2_EINVAL
     opt.tau, opt.precision = 0.7, 16
-    assert L.h2_build_ex(dummy, 10, 3, 0, prm, 1e-6, 64, C.byref(opt), None, C.byref(out)) == h2.H2_EUNSUPPORTED
+    assert L.h2_build_ex(dummy, 10, 3, 0, prm, 1e-6, 64, C.byref(opt), None, C.byref(out)) == h2.H2_EINVAL
+    opt.precision, opt.r_min = 32, -1
+    assert L.h2_build_ex(dummy, 10, 3, 0, prm, 1e-6, 64, C.byref(opt), None, C.byref(out)) == h2.H2_EINVAL
     assert L.h2_matvec(None, dummy, dummy, 1) == h2.H2_EINVAL
     assert L.h2_destroy(None) == h2.H2_OK
