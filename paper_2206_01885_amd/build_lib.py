@@ -15,6 +15,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # DataReduct, the ID and its calibration) are compiled without FMA
 # contraction.
 EXACT = {"tree.hip", "lists.hip", "hidr.hip", "basis.hip", "calib.hip"}
+# Sources whose matrix-core loops keep their accumulators in VGPRs: with the
+# default AGPR form the compiler copies every accumulator out and back at
+# each loop iteration.
+MFMA_VGPR = {"matvec.hip"}
 SOURCES = ["alloc.hip", "scan.hip", "tree.hip", "lists.hip", "hidr.hip", "calib.hip", "basis.hip", "blocks.hip",
            "matvec.hip", "api.hip"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
@@ -26,6 +30,8 @@ def _compile(src: str, outdir: str) -> str:
     obj = os.path.join(outdir, src.replace(".hip", ".o"))
     flags = list(COMMON)
     flags.append("-ffp-contract=off" if src in EXACT else "-ffp-contract=fast")
+    if src in MFMA_VGPR:
+        flags += ["-mllvm", "-amdgpu-mfma-vgpr-form"]
     cmd = [HIPCC, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -136,10 +136,15 @@ void build_blocks(Handle& h)
     scan_excl_i64(sz.p, h.B_off.p, h.nil, h.tmp_i64, s);
     int64_t nB = read_scalar(h.B_off.p + h.nil, s);
     const bool f32 = h.precision == 32;
-    if (f32)
-        h.Bf.ensure((size_t)std::max<int64_t>(nB, 1), s);
-    else
-        h.B.ensure((size_t)std::max<int64_t>(nB, 1), s);
+    // BLK_PAD zeros after the last block (read by row tiles of the apply
+    // that run past a block's last row)
+    if (f32) {
+        h.Bf.ensure((size_t)(nB + BLK_PAD), s);
+        H2_HIP(hipMemsetAsync(h.Bf.p + nB, 0, BLK_PAD * sizeof(float), s));
+    } else {
+        h.B.ensure((size_t)(nB + BLK_PAD), s);
+        H2_HIP(hipMemsetAsync(h.B.p + nB, 0, BLK_PAD * sizeof(double), s));
+    }
     h.bytes_B = nB * (int64_t)(f32 ? sizeof(float) : sizeof(double));
     if (h.nil > 0) {
         k_entry_rows<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, erow.p);
@@ -159,10 +164,13 @@ void build_blocks(Handle& h)
     H2_LAUNCH_CHECK();
     scan_excl_i64(sz.p, h.D_off.p, h.nnear, h.tmp_i64, s);
     int64_t nD = read_scalar(h.D_off.p + h.nnear, s);
-    if (f32)
-        h.Df.ensure((size_t)std::max<int64_t>(nD, 1), s);
-    else
-        h.D.ensure((size_t)std::max<int64_t>(nD, 1), s);
+    if (f32) {
+        h.Df.ensure((size_t)(nD + BLK_PAD), s);
+        H2_HIP(hipMemsetAsync(h.Df.p + nD, 0, BLK_PAD * sizeof(float), s));
+    } else {
+        h.D.ensure((size_t)(nD + BLK_PAD), s);
+        H2_HIP(hipMemsetAsync(h.D.p + nD, 0, BLK_PAD * sizeof(double), s));
+    }
     h.bytes_D = nD * (int64_t)(f32 ? sizeof(float) : sizeof(double));
     if (h.nnear > 0) {
         std::vector<int64_t> st(h.h_start.begin(), h.h_start.end());

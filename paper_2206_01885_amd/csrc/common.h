@@ -114,6 +114,10 @@ void scan_excl_i32(const int* in, int* out, int64_t cnt, DBuf<int>& tmp, hipStre
 void scan_excl_i64(const int64_t* in, int64_t* out, int64_t cnt, DBuf<int64_t>& tmp, hipStream_t s);
 
 // ------------------------------------------------------------------ handle
+// Elements kept (zeroed) after the last coupling / nearfield block: a row
+// tile of the apply reads up to 15 elements past the end of a block column.
+constexpr int64_t BLK_PAD = 64;
+
 struct Handle {
     // problem
     int64_t n = 0;
@@ -173,15 +177,21 @@ struct Handle {
 
     // apply task lists: (node, first row) of every 32-row chunk of a block
     // row, split by whether the chunk holds one or two 16-row tiles
-    struct Tasks {
-        DBuf<int> node, r0;
-        int n = 0;
+    // A block sweep of the apply: tasks (node, first row) grouped by their
+    // number of 16-row tiles (1..4), and per-entry metadata of the list.
+    struct Sweep {
+        DBuf<int> node[4], r0[4];
+        int n[4] = {0, 0, 0, 0};
+        DBuf<int> ek;       // per list entry: columns of the block
+        DBuf<int64_t> ex;   // per list entry: first input row of the block
+        DBuf<int> steps;    // per node: sum over its entries of max(1, ceil(columns / 4))
     };
-    Tasks cp_t1, cp_t2, nr_t1, nr_t2;
+    Sweep cp, nr;
+    DBuf<double> zeros;     // 64 zeros, read by masked lanes of the sweeps
     DBuf<int64_t> start64;  // start[] widened, row offsets of the leaves in x_t / y_t
 
     // matvec workspace (sized for the largest nrhs seen)
-    int mv_nrhs = 0;
+    int mv_ld = 0;  // column stride the apply buffers are sized for
     DBuf<double> xt, yt, xh, yh;
     DBuf<float> xtf, ytf, xhf, yhf;
 

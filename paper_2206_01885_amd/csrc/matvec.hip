@@ -3,11 +3,14 @@
 // matrix-core products per block, compensated (Kahan) accumulation of the
 // block products and FP64 accumulation of the interpolation sums.
 //
-// Vectors live in tree order as [n][nrhs] (right-hand sides fastest); the
-// node coefficients xhat_i, yhat_i as [rank_i][nrhs] blocks laid out in node
-// id order, so the children of a node (consecutive ids) own one contiguous
-// block: the input rows z_p of a parent's interpolation step are exactly its
-// children's xhat concatenated, as in the row set Xbar_p of Algorithm 2.
+// Vectors live in tree order as [n][ld] (right-hand sides fastest, ld =
+// nrhs rounded up to 32); the node coefficients xhat_i, yhat_i as
+// [rank_i][ld] blocks laid out in node id order, so the children of a node
+// (consecutive ids) own one contiguous block: the input rows z_p of a
+// parent's interpolation step are exactly its children's xhat concatenated,
+// as in the row set Xbar_p of Algorithm 2.  Columns nrhs .. ld-1 are never
+// initialised: every product below is column-independent, so whatever they
+// hold reaches only columns nrhs .. ld-1 of the results, which are never read.
 //
 //   gather    x_t = x[perm]
 //   upward    xhat_i = U_i^T z_i, z_i = x_t(X_i) (leaf) or children's xhat;
@@ -45,30 +48,45 @@ struct Mfma<float> {
     __device__ static int row(int r, int k4) { return 4 * k4 + r; }
 };
 
+// n contiguous values loaded as one (unaligned) vector access
+template <class T, int N>
+struct Vec {
+    T v[N];
+};
+template <class T, int N>
+__device__ __forceinline__ Vec<T, N> vload(const T* p)
+{
+    Vec<T, N> r;
+    __builtin_memcpy(&r, p, sizeof(r));
+    return r;
+}
+
 template <class T>
-__global__ __launch_bounds__(TB) void k_gather(const T* __restrict__ x, int64_t n, int nrhs, const int* __restrict__ perm,
-                                               T* __restrict__ xt)
+__global__ __launch_bounds__(TB) void k_gather(const T* __restrict__ x, int64_t n, int nrhs, int ld,
+                                               const int* __restrict__ perm, T* __restrict__ xt)
 {
     int64_t q = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (q >= n * nrhs) return;
     int64_t i = q / nrhs;
     int r = (int)(q - i * nrhs);
-    xt[q] = x[(int64_t)r * n + perm[i]];
+    xt[i * ld + r] = x[(int64_t)r * n + perm[i]];
 }
 
 template <class T>
-__global__ __launch_bounds__(TB) void k_scatter(const T* __restrict__ yt, int64_t n, int nrhs,
+__global__ __launch_bounds__(TB) void k_scatter(const T* __restrict__ yt, int64_t n, int nrhs, int ld,
                                                 const int* __restrict__ perm, T* __restrict__ y)
 {
     int64_t q = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (q >= n * nrhs) return;
     int64_t i = q / nrhs;
     int r = (int)(q - i * nrhs);
-    y[(int64_t)r * n + perm[i]] = yt[q];
+    y[(int64_t)r * n + perm[i]] = yt[i * ld + r];
 }
 
+// The interpolation sums (up to a few hundred terms) accumulate in FP64 in
+// both modes; the FP32 mode stores and loads FP32 operands only.
 template <class T>
-__global__ __launch_bounds__(TB) void k_upward(int lo, int nrhs, const int* __restrict__ nchild,
+__global__ __launch_bounds__(TB) void k_upward(int lo, int nrhs, int ld, const int* __restrict__ nchild,
                                                const int* __restrict__ first_child, const int* __restrict__ start,
                                                const int* __restrict__ rank, const int* __restrict__ mbar,
                                                const int64_t* __restrict__ piv_off, const int* __restrict__ piv,
@@ -80,40 +98,53 @@ __global__ __launch_bounds__(TB) void k_upward(int lo, int nrhs, const int* __re
     const int k = rank[i];
     if (k == 0) return;
     const int m = mbar[i], nr = m - k;
-    const T* z = nchild[i] == 0 ? xt + (int64_t)start[i] * nrhs : xh + xh_off[first_child[i]] * nrhs;
+    const T* z = nchild[i] == 0 ? xt + (int64_t)start[i] * ld : xh + xh_off[first_child[i]] * ld;
     const int* pv = piv + piv_off[i];
     const T* Ti = Tm + T_off[i];
-    T* o = xh + xh_off[i] * nrhs;
+    T* o = xh + xh_off[i] * ld;
     for (int q = threadIdx.x; q < k * nrhs; q += TB) {
         int t = q / nrhs, r = q - t * nrhs;
-        double acc = z[(int64_t)pv[t] * nrhs + r];
+        double acc = z[(int64_t)pv[t] * ld + r];
         const T* Tr = Ti + (int64_t)t * nr;
-        for (int u = 0; u < nr; ++u) acc += (double)Tr[u] * (double)z[(int64_t)pv[k + u] * nrhs + r];
-        o[q] = (T)acc;
+        for (int u = 0; u < nr; ++u) acc += (double)Tr[u] * (double)z[(int64_t)pv[k + u] * ld + r];
+        o[(int64_t)t * ld + r] = (T)acc;
     }
 }
 
 // Batched block products Y[rows of i] (+)= sum_{e in row i} Blk_e X[rows of j_e]
 // for the coupling sweep (Blk = B, X = xhat, Y = yhat) and the nearfield
-// sweep (Blk = D, X = x_t, Y = y_t).  One wavefront per task (node i, 32-row
-// chunk): MT 16-row tiles x 2 16-column tiles of 16x16x4 matrix-core steps,
-// the K loop walking the list entries four rows of X at a time.  Blocks are
-// column-major, so each 16-lane group of an A load reads 16 contiguous
-// values, and X rows are nrhs-contiguous, so B loads are contiguous as well.
-// The operands of the next K step are loaded before the current step's
-// matrix-core instructions issue.  Workgroup ids are remapped so that each
-// XCD (ids round-robin over 8) runs a contiguous range of tasks, keeping the
-// shared X rows of neighbouring nodes in one L2.
+// sweep (Blk = D, X = x_t, Y = y_t).  The blocks of one list row are stored
+// back to back, each column-major with leading dimension rows_i, so row i's
+// blocks together are one rows_i x (sum of columns) column-major matrix and
+// the sweep over a row is one long K loop.
+//
+// One wavefront per task (node i, rows r0 .. r0 + 16 MT - 1, 32 columns of
+// X per pass): MT 16-row tiles x 2 16-column tiles of 16x16x4 matrix-core
+// steps, four columns of the row matrix (four rows of X) per step.  The
+// tiles are interleaved so that every lane's operands are contiguous: lane
+// (q, g) = (l%16, l/16) loads rows r0 + MT q .. r0 + MT q + MT - 1 of column
+// g of the step (tile mt takes row MT q + mt) and columns 2q, 2q+1 of row g
+// of X (tile nt takes column 2q + nt), each as one vector access.  Rows past
+// the block (the last tile of a node) compute values that are never stored;
+// columns past a block's last column (its last step) read zeros from `zero`.
+// The addresses move by one scalar offset per step.  Loads run P steps ahead
+// of the matrix-core instructions through a register ring, across block
+// boundaries; the next entry's metadata (columns, first input row) is read
+// one entry ahead.  The loop runs a multiple of P steps; the surplus steps
+// read zeros.  Workgroup ids are remapped so that each XCD (ids round-robin
+// over 8) runs a contiguous range of tasks, keeping the X rows shared by
+// neighbouring nodes in one L2.
 // COMP: every block's product is formed on its own and added to the running
 // sum with Kahan compensation (precision mode).
-template <int MT, class T, bool COMP>
-__global__ __launch_bounds__(64) void k_blockgemm(int ntask, const int* __restrict__ task_node,
-                                                  const int* __restrict__ task_r0, const int* __restrict__ ptr,
-                                                  const int* __restrict__ col, const int* __restrict__ krow,
-                                                  const int64_t* __restrict__ blk_off, const T* __restrict__ blk,
-                                                  const int64_t* __restrict__ in_off, const T* __restrict__ X,
-                                                  const int64_t* __restrict__ out_off, T* __restrict__ Y, int nrhs,
-                                                  int accumulate)
+template <int MT, class T, bool COMP, int P>
+__global__ __launch_bounds__(64) void k_sweep(int ntask, const int* __restrict__ task_node,
+                                              const int* __restrict__ task_r0, const int* __restrict__ ptr,
+                                              const int* __restrict__ ek, const int64_t* __restrict__ ex,
+                                              const int* __restrict__ nsteps, const int* __restrict__ krow,
+                                              const int64_t* __restrict__ blk_off, const T* __restrict__ blk,
+                                              const T* __restrict__ X, const int64_t* __restrict__ out_off,
+                                              T* __restrict__ Y, int nchunk, int ld, int accumulate,
+                                              const T* __restrict__ zero)
 {
     typedef typename Mfma<T>::V V;
     const int per = (ntask + 7) / 8;
@@ -121,106 +152,156 @@ __global__ __launch_bounds__(64) void k_blockgemm(int ntask, const int* __restri
     if (task >= ntask) return;
     const int i = task_node[task], r0 = task_r0[task];
     const int ki = krow[i];
-    const int lane = threadIdx.x, l16 = lane & 15, k4 = lane >> 4;
+    const int lane = threadIdx.x, q = lane & 15, g = lane >> 4;
     const int e0 = ptr[i], e1 = ptr[i + 1];
-    for (int c0 = 0; c0 < nrhs; c0 += 32) {
-        V acc[MT][2], cmp[MT][2];
+    const int S = nsteps[i];
+    const int SP = (S + P - 1) / P * P;
+    // lane bases: column g of the row matrix at row r0 + MT q; row g of X
+    const T* baseA = blk + (e0 < e1 ? blk_off[e0] : 0) + (int64_t)g * ki + r0 + MT * q;
+    for (int c = 0; c < nchunk; ++c) {
+        const T* baseX = X + (int64_t)g * ld + 32 * c + 2 * q;
+        V acc[MT][2], cmp[MT][2], bacc[MT][2];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) {
                 acc[mt][nt] = (V){0, 0, 0, 0};
                 cmp[mt][nt] = (V){0, 0, 0, 0};
+                bacc[mt][nt] = (V){0, 0, 0, 0};
             }
-        for (int e = e0; e < e1; ++e) {
-            const int j = col[e];
-            const int kj = krow[j];
-            const T* Bb = blk + blk_off[e];
-            const T* Xj = X + in_off[j] * nrhs;
-            V blkacc[MT][2];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt) blkacc[mt][nt] = COMP ? (V){0, 0, 0, 0} : acc[mt][nt];
-            T av[MT], bv[2];
-            auto load = [&](int u0) {
-                const int u = u0 + k4;
-                const bool uv = u < kj;
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
-                    const int t = r0 + 16 * mt + l16;
-                    av[mt] = (uv && t < ki) ? Bb[(int64_t)u * ki + t] : (T)0;
+        // loader state (wave-uniform): entry le, column lu within it, its
+        // column count lk and first input row lx, first column lkst of the
+        // entry in the row matrix; nk, nx: metadata of entry le + 1.  An entry
+        // without columns (a partner of rank 0) takes one all-zero step.
+        int le = e0, lu = 0, lk = 0, nk = 0;
+        int64_t lx = 0, nx = 0, lkst = 0;
+        if (e0 < e1) {
+            lk = ek[e0];
+            lx = ex[e0];
+        }
+        if (e0 + 1 < e1) {
+            nk = ek[e0 + 1];
+            nx = ex[e0 + 1];
+        }
+        Vec<T, MT> av[P];
+        Vec<T, 2> bv[P];
+        bool last[P];
+        auto load = [&](Vec<T, MT>& a, Vec<T, 2>& b, bool& lst) {
+            const bool uv = lu + g < lk;
+            const T* pa = baseA + (lkst + lu) * ki;
+            const T* px = baseX + (lx + lu) * ld;
+            a = vload<T, MT>(uv ? pa : zero);
+            b = vload<T, 2>(uv ? px : zero);
+            lu += 4;
+            lst = le < e1 && lu >= lk;
+            if (lst) {
+                lkst += lk;
+                lu = 0;
+                ++le;
+                lk = nk;
+                lx = nx;
+                if (le + 1 < e1) {
+                    nk = ek[le + 1];
+                    nx = ex[le + 1];
+                } else {
+                    nk = 0;
                 }
+            }
+        };
 #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) {
-                    const int c = c0 + 16 * nt + l16;
-                    bv[nt] = (uv && c < nrhs) ? Xj[(int64_t)u * nrhs + c] : (T)0;
-                }
-            };
-            load(0);
-            for (int u0 = 0; u0 < kj; u0 += 4) {
-                T a_cur[MT], b_cur[2];
+        for (int p = 0; p < P; ++p) load(av[p], bv[p], last[p]);
+        for (int s0 = 0; s0 < SP; s0 += P) {
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) a_cur[mt] = av[mt];
-                b_cur[0] = bv[0];
-                b_cur[1] = bv[1];
-                if (u0 + 4 < kj) load(u0 + 4);
+            for (int p = 0; p < P; ++p) {
+                // consume slot p, then refill it (the old operands die at
+                // their matrix-core instructions, so the refill reuses their
+                // registers)
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int nt = 0; nt < 2; ++nt) blkacc[mt][nt] = Mfma<T>::step(a_cur[mt], b_cur[nt], blkacc[mt][nt]);
-            }
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt) {
-                    if (COMP) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            T yk = blkacc[mt][nt][r] - cmp[mt][nt][r];
-                            T tk = acc[mt][nt][r] + yk;
-                            cmp[mt][nt][r] = (tk - acc[mt][nt][r]) - yk;
-                            acc[mt][nt][r] = tk;
-                        }
-                    } else {
-                        acc[mt][nt] = blkacc[mt][nt];
+                    for (int nt = 0; nt < 2; ++nt) {
+                        if (COMP)
+                            bacc[mt][nt] = Mfma<T>::step(av[p].v[mt], bv[p].v[nt], bacc[mt][nt]);
+                        else
+                            acc[mt][nt] = Mfma<T>::step(av[p].v[mt], bv[p].v[nt], acc[mt][nt]);
                     }
+                const bool lst = last[p];
+                load(av[p], bv[p], last[p]);
+                if (COMP && lst) {
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int nt = 0; nt < 2; ++nt) {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                T yk = bacc[mt][nt][r] - cmp[mt][nt][r];
+                                T tk = acc[mt][nt][r] + yk;
+                                cmp[mt][nt][r] = (tk - acc[mt][nt][r]) - yk;
+                                acc[mt][nt][r] = tk;
+                            }
+                            bacc[mt][nt] = (V){0, 0, 0, 0};
+                        }
                 }
+            }
         }
-        T* Yi = Y + out_off[i] * nrhs;
+        // tile (mt, nt) row w, column q = node row r0 + MT w + mt, column 2q + nt
+        T* Yi = Y + out_off[i] * ld + 32 * c + 2 * q;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt)
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + MT * Mfma<T>::row(r, g) + mt;
+                if (row < ki) {
+                    Vec<T, 2> v;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = r0 + 16 * mt + Mfma<T>::row(r, k4);
-                    const int c = c0 + 16 * nt + l16;
-                    if (row < ki && c < nrhs) {
-                        T* dst = Yi + (int64_t)row * nrhs + c;
-                        T v = COMP ? acc[mt][nt][r] - cmp[mt][nt][r] : acc[mt][nt][r];
-                        *dst = accumulate ? *dst + v : v;
+                    for (int nt = 0; nt < 2; ++nt)
+                        v.v[nt] = COMP ? acc[mt][nt][r] - cmp[mt][nt][r] : acc[mt][nt][r];
+                    T* dst = Yi + (int64_t)row * ld;
+                    if (accumulate) {
+                        const Vec<T, 2> o = vload<T, 2>(dst);
+                        v.v[0] += o.v[0];
+                        v.v[1] += o.v[1];
                     }
+                    __builtin_memcpy(dst, &v, sizeof(v));
                 }
+            }
     }
 }
 
-// The interpolation sums (up to a few hundred terms) accumulate in FP64 in
-// both modes; the FP32 mode stores and loads FP32 operands only.
+// Per-entry metadata of a list (columns, first input row) and per-node
+// step counts of the sweep (an entry without columns takes one step).
+__global__ __launch_bounds__(TB) void k_sweep_meta(int nrow, const int* __restrict__ ptr, const int* __restrict__ col,
+                                                   const int* __restrict__ kcol, const int64_t* __restrict__ in_off,
+                                                   int* __restrict__ ek, int64_t* __restrict__ ex,
+                                                   int* __restrict__ nsteps)
+{
+    const int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= nrow) return;
+    int st = 0;
+    for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+        const int j = col[e];
+        const int k = kcol[j];
+        ek[e] = k;
+        ex[e] = in_off[j];
+        st += k > 0 ? (k + 3) / 4 : 1;
+    }
+    nsteps[i] = st;
+}
+
 // w[piv pos] (+)= (U yhat)[pos]: pos < k -> yhat[pos]; else sum_t T[t, pos-k] yhat[t]
 template <class T>
-__device__ inline T u_times(int pos, int k, int nr, int r, int nrhs, const T* __restrict__ Ti,
+__device__ inline T u_times(int pos, int k, int nr, int r, int ld, const T* __restrict__ Ti,
                             const T* __restrict__ yhat)
 {
-    if (pos < k) return yhat[(int64_t)pos * nrhs + r];
+    if (pos < k) return yhat[(int64_t)pos * ld + r];
     int u = pos - k;
     double acc = 0;
-    for (int t = 0; t < k; ++t) acc += (double)Ti[(int64_t)t * nr + u] * (double)yhat[(int64_t)t * nrhs + r];
+    for (int t = 0; t < k; ++t) acc += (double)Ti[(int64_t)t * nr + u] * (double)yhat[(int64_t)t * ld + r];
     return (T)acc;
 }
 
 template <class T>
-__global__ __launch_bounds__(TB) void k_downward(int lo, int nrhs, const int* __restrict__ nchild,
+__global__ __launch_bounds__(TB) void k_downward(int lo, int nrhs, int ld, const int* __restrict__ nchild,
                                                  const int* __restrict__ first_child, const int* __restrict__ rank,
                                                  const int* __restrict__ mbar, const int64_t* __restrict__ piv_off,
                                                  const int* __restrict__ piv, const int64_t* __restrict__ T_off,
@@ -233,18 +314,18 @@ __global__ __launch_bounds__(TB) void k_downward(int lo, int nrhs, const int* __
     const int m = mbar[i], nr = m - k;
     const int* pv = piv + piv_off[i];
     const T* Ti = Tm + T_off[i];
-    const T* yi = yh + xh_off[i] * nrhs;
-    T* yc = yh + xh_off[first_child[i]] * nrhs;
+    const T* yi = yh + xh_off[i] * ld;
+    T* yc = yh + xh_off[first_child[i]] * ld;
     for (int q = threadIdx.x; q < m * nrhs; q += TB) {
         int pos = q / nrhs, r = q - pos * nrhs;
-        yc[(int64_t)pv[pos] * nrhs + r] += u_times(pos, k, nr, r, nrhs, Ti, yi);
+        yc[(int64_t)pv[pos] * ld + r] += u_times(pos, k, nr, r, ld, Ti, yi);
     }
 }
 
 // Far part of the leaves: y_t(X_i) = U_i yhat_i (zero when the leaf has no
 // farfield); the nearfield sweep then accumulates into the same rows.
 template <class T>
-__global__ __launch_bounds__(TB) void k_leaves_far(int nrhs, const int* __restrict__ leaves,
+__global__ __launch_bounds__(TB) void k_leaves_far(int nrhs, int ld, const int* __restrict__ leaves,
                                                    const int* __restrict__ start, const int* __restrict__ count,
                                                    const int* __restrict__ rank, const int64_t* __restrict__ piv_off,
                                                    const int* __restrict__ piv, const int64_t* __restrict__ T_off,
@@ -254,17 +335,20 @@ __global__ __launch_bounds__(TB) void k_leaves_far(int nrhs, const int* __restri
     const int i = leaves[blockIdx.x];
     const int k = rank[i];
     const int m = count[i], nr = m - k;
-    T* yo = yt + (int64_t)start[i] * nrhs;
+    T* yo = yt + (int64_t)start[i] * ld;
     if (k > 0) {
         const int* pv = piv + piv_off[i];
         const T* Ti = Tm + T_off[i];
-        const T* yi = yh + xh_off[i] * nrhs;
+        const T* yi = yh + xh_off[i] * ld;
         for (int q = threadIdx.x; q < m * nrhs; q += TB) {
             int pos = q / nrhs, r = q - pos * nrhs;
-            yo[(int64_t)pv[pos] * nrhs + r] = u_times(pos, k, nr, r, nrhs, Ti, yi);
+            yo[(int64_t)pv[pos] * ld + r] = u_times(pos, k, nr, r, ld, Ti, yi);
         }
     } else {
-        for (int q = threadIdx.x; q < m * nrhs; q += TB) yo[q] = (T)0;
+        for (int q = threadIdx.x; q < m * nrhs; q += TB) {
+            int pos = q / nrhs, r = q - pos * nrhs;
+            yo[(int64_t)pos * ld + r] = (T)0;
+        }
     }
 }
 
@@ -274,23 +358,28 @@ __global__ __launch_bounds__(TB) void k_to_f32(const double* __restrict__ a, int
     if (q < n) b[q] = (float)a[q];
 }
 
-template <class T, bool COMP>
-void launch_gemm(const Handle::Tasks& t1, const Handle::Tasks& t2, const int* ptr, const int* col, const int* krow,
-                 const int64_t* blk_off, const T* blk, const int64_t* in_off, const T* X, const int64_t* out_off,
-                 T* Y, int nrhs, int accumulate, hipStream_t s)
+template <int MT, class T, bool COMP>
+void launch_sweep_mt(const Handle::Sweep& w, const int* ptr, const int* krow, const int64_t* blk_off, const T* blk,
+                     const T* X, const int64_t* out_off, T* Y, int ld, int accumulate, const T* zero, hipStream_t s)
 {
-    if (t1.n > 0) {
-        unsigned grid = (unsigned)(8 * ((t1.n + 7) / 8));
-        k_blockgemm<1, T, COMP><<<grid, 64, 0, s>>>(t1.n, t1.node.p, t1.r0.p, ptr, col, krow, blk_off, blk, in_off,
-                                                    X, out_off, Y, nrhs, accumulate);
-        H2_LAUNCH_CHECK();
-    }
-    if (t2.n > 0) {
-        unsigned grid = (unsigned)(8 * ((t2.n + 7) / 8));
-        k_blockgemm<2, T, COMP><<<grid, 64, 0, s>>>(t2.n, t2.node.p, t2.r0.p, ptr, col, krow, blk_off, blk, in_off,
-                                                    X, out_off, Y, nrhs, accumulate);
-        H2_LAUNCH_CHECK();
-    }
+    const int nt = w.n[MT - 1];
+    if (nt == 0) return;
+    constexpr int P = MT <= 2 ? 4 : 3;
+    const unsigned grid = (unsigned)(8 * ((nt + 7) / 8));
+    k_sweep<MT, T, COMP, P><<<grid, 64, 0, s>>>(nt, w.node[MT - 1].p, w.r0[MT - 1].p, ptr, w.ek.p, w.ex.p,
+                                                w.steps.p, krow, blk_off, blk, X, out_off, Y, ld / 32, ld,
+                                                accumulate, zero);
+    H2_LAUNCH_CHECK();
+}
+
+template <class T, bool COMP>
+void launch_sweep(const Handle::Sweep& w, const int* ptr, const int* krow, const int64_t* blk_off, const T* blk,
+                  const T* X, const int64_t* out_off, T* Y, int ld, int accumulate, const T* zero, hipStream_t s)
+{
+    launch_sweep_mt<4, T, COMP>(w, ptr, krow, blk_off, blk, X, out_off, Y, ld, accumulate, zero, s);
+    launch_sweep_mt<3, T, COMP>(w, ptr, krow, blk_off, blk, X, out_off, Y, ld, accumulate, zero, s);
+    launch_sweep_mt<2, T, COMP>(w, ptr, krow, blk_off, blk, X, out_off, Y, ld, accumulate, zero, s);
+    launch_sweep_mt<1, T, COMP>(w, ptr, krow, blk_off, blk, X, out_off, Y, ld, accumulate, zero, s);
 }
 
 template <class T>
@@ -321,19 +410,21 @@ void matvec_t(Handle& h, const T* x, T* y, int nrhs, hipStream_t s)
 {
     typedef ApplyBufs<T> AB;
     const int64_t n = h.n;
-    if (nrhs > h.mv_nrhs) {
+    const int ld = (nrhs + 31) / 32 * 32;
+    if (ld > h.mv_ld) {
         H2_HIP(hipStreamSynchronize(s));
-        AB::xt(h).ensure((size_t)n * nrhs, s);
-        AB::yt(h).ensure((size_t)n * nrhs, s);
-        AB::xh(h).ensure((size_t)std::max<int64_t>(h.sum_rank, 1) * nrhs, s);
-        AB::yh(h).ensure((size_t)std::max<int64_t>(h.sum_rank, 1) * nrhs, s);
-        h.mv_nrhs = nrhs;
+        AB::xt(h).ensure((size_t)n * ld, s);
+        AB::yt(h).ensure((size_t)n * ld, s);
+        AB::xh(h).ensure((size_t)std::max<int64_t>(h.sum_rank, 1) * ld, s);
+        AB::yh(h).ensure((size_t)std::max<int64_t>(h.sum_rank, 1) * ld, s);
+        h.mv_ld = ld;
     }
     T* xt = AB::xt(h).p;
     T* yt = AB::yt(h).p;
     T* xh = AB::xh(h).p;
     T* yh = AB::yh(h).p;
     const T* Tm = AB::Tm(h);
+    const T* zero = (const T*)h.zeros.p;
     const bool prof = h.profile != 0;
     auto mark = [&](int e) {
         if (prof) H2_HIP(hipEventRecord(h.ev[e], s));
@@ -341,12 +432,12 @@ void matvec_t(Handle& h, const T* x, T* y, int nrhs, hipStream_t s)
     if (prof && !h.ev[0])
         for (auto& e : h.ev) H2_HIP(hipEventCreate(&e));
     mark(0);
-    k_gather<T><<<blocks_for(n * nrhs, TB), TB, 0, s>>>(x, n, nrhs, h.perm.p, xt);
+    k_gather<T><<<blocks_for(n * nrhs, TB), TB, 0, s>>>(x, n, nrhs, ld, h.perm.p, xt);
     H2_LAUNCH_CHECK();
     mark(1);
     for (int L = h.maxdepth; L >= 1; --L) {
         int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
-        k_upward<T><<<nl, TB, 0, s>>>(lo, nrhs, h.nchild.p, h.first_child.p, h.start.p, h.rank.p, h.mbar.p,
+        k_upward<T><<<nl, TB, 0, s>>>(lo, nrhs, ld, h.nchild.p, h.first_child.p, h.start.p, h.rank.p, h.mbar.p,
                                       h.piv_off.p, h.piv.p, h.T_off.p, Tm, h.xh_off.p, xt, xh);
         H2_LAUNCH_CHECK();
     }
@@ -354,24 +445,23 @@ void matvec_t(Handle& h, const T* x, T* y, int nrhs, hipStream_t s)
     // the precision mode adds each block product (one interaction) to the
     // row sums with compensation: FP32 recursion over the ~10^4 terms of an
     // interaction list would lose about sqrt(10^4) ulps
-    launch_gemm<T, sizeof(T) == 4>(h.cp_t1, h.cp_t2, h.il_ptr.p, h.il_col.p, h.rank.p, h.B_off.p, AB::B(h), h.xh_off.p, xh,
-                          h.xh_off.p, yh, nrhs, 0, s);
+    launch_sweep<T, sizeof(T) == 4>(h.cp, h.il_ptr.p, h.rank.p, h.B_off.p, AB::B(h), xh, h.xh_off.p, yh, ld, 0,
+                                    zero, s);
     mark(3);
     for (int L = 1; L < h.maxdepth; ++L) {
         int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
-        k_downward<T><<<nl, TB, 0, s>>>(lo, nrhs, h.nchild.p, h.first_child.p, h.rank.p, h.mbar.p, h.piv_off.p,
-                                        h.piv.p, h.T_off.p, Tm, h.xh_off.p, yh);
+        k_downward<T><<<nl, TB, 0, s>>>(lo, nrhs, ld, h.nchild.p, h.first_child.p, h.rank.p, h.mbar.p,
+                                        h.piv_off.p, h.piv.p, h.T_off.p, Tm, h.xh_off.p, yh);
         H2_LAUNCH_CHECK();
     }
     mark(4);
-    k_leaves_far<T><<<(unsigned)h.leaves.n, TB, 0, s>>>(nrhs, h.leaves.p, h.start.p, h.count.p, h.rank.p,
+    k_leaves_far<T><<<(unsigned)h.leaves.n, TB, 0, s>>>(nrhs, ld, h.leaves.p, h.start.p, h.count.p, h.rank.p,
                                                         h.piv_off.p, h.piv.p, h.T_off.p, Tm, h.xh_off.p, yh, yt);
     H2_LAUNCH_CHECK();
-    // the precision mode accumulates the nearfield blocks with compensation
-    launch_gemm<T, sizeof(T) == 4>(h.nr_t1, h.nr_t2, h.nr_ptr.p, h.nr_col.p, h.count.p, h.D_off.p, AB::D(h),
-                                   h.start64.p, xt, h.start64.p, yt, nrhs, 1, s);
+    launch_sweep<T, sizeof(T) == 4>(h.nr, h.nr_ptr.p, h.count.p, h.D_off.p, AB::D(h), xt, h.start64.p, yt, ld, 1,
+                                    zero, s);
     mark(5);
-    k_scatter<T><<<blocks_for(n * nrhs, TB), TB, 0, s>>>(yt, n, nrhs, h.perm.p, y);
+    k_scatter<T><<<blocks_for(n * nrhs, TB), TB, 0, s>>>(yt, n, nrhs, ld, h.perm.p, y);
     H2_LAUNCH_CHECK();
     mark(6);
     if (prof) {
@@ -382,50 +472,60 @@ void matvec_t(Handle& h, const T* x, T* y, int nrhs, hipStream_t s)
 
 }  // namespace
 
-// Task lists of the two block sweeps, built once per handle; in the
-// precision mode also the FP32 copy of the interpolation matrices.
+// Task lists and list metadata of the two block sweeps, built once per
+// handle; in the precision mode also the FP32 copy of the interpolation
+// matrices.  A node's rows are cut into chunks of at most 64 rows (4 tiles).
 void prepare_apply(Handle& h)
 {
     hipStream_t s = h.stream;
-    auto make = [&](const std::vector<int>& rows_of, const std::vector<int>& ptr, bool need_rank,
-                    Handle::Tasks& t1, Handle::Tasks& t2) {
-        std::vector<int> n1, r1, n2, r2;
+    auto make = [&](const std::vector<int>& rows_of, const std::vector<int>& ptr, bool need_rank, Handle::Sweep& w) {
+        std::vector<int> nd[4], rr[4];
         for (int i = 0; i < h.nnode; ++i) {
-            int rows = rows_of[i];
+            const int rows = rows_of[i];
             if (rows == 0) continue;
             if (!need_rank && ptr[i + 1] == ptr[i]) continue;
-            for (int r0 = 0; r0 < rows; r0 += 32) {
-                if (rows - r0 > 16) {
-                    n2.push_back(i);
-                    r2.push_back(r0);
-                } else {
-                    n1.push_back(i);
-                    r1.push_back(r0);
-                }
+            for (int r0 = 0; r0 < rows; r0 += 64) {
+                const int mt = (std::min(64, rows - r0) + 15) / 16;
+                nd[mt - 1].push_back(i);
+                rr[mt - 1].push_back(r0);
             }
         }
         auto up = [&](DBuf<int>& d, const std::vector<int>& v) {
             d.ensure(std::max<size_t>(v.size(), 1), s);
             if (!v.empty()) H2_HIP(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, s));
         };
-        up(t1.node, n1);
-        up(t1.r0, r1);
-        up(t2.node, n2);
-        up(t2.r0, r2);
-        t1.n = (int)n1.size();
-        t2.n = (int)n2.size();
+        for (int c = 0; c < 4; ++c) {
+            up(w.node[c], nd[c]);
+            up(w.r0[c], rr[c]);
+            w.n[c] = (int)nd[c].size();
+        }
         H2_HIP(hipStreamSynchronize(s));
     };
+    // zero source of the masked lanes of the block sweeps (FP64 and FP32)
+    h.zeros.ensure(64, s);
+    H2_HIP(hipMemsetAsync(h.zeros.p, 0, 64 * sizeof(double), s));
+    std::vector<int64_t> st(h.h_start.begin(), h.h_start.end());
+    h.start64.ensure(std::max<size_t>(st.size(), 1), s);
+    H2_HIP(hipMemcpyAsync(h.start64.p, st.data(), st.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
     // coupling: every node with a basis writes its yhat (zero without IL)
-    make(h.h_rank, h.h_il_ptr, true, h.cp_t1, h.cp_t2);
+    make(h.h_rank, h.h_il_ptr, true, h.cp);
+    h.cp.ek.ensure(std::max<int64_t>(h.nil, 1), s);
+    h.cp.ex.ensure(std::max<int64_t>(h.nil, 1), s);
+    h.cp.steps.ensure(std::max(h.nnode, 1), s);
+    k_sweep_meta<<<blocks_for(h.nnode, TB), TB, 0, s>>>(h.nnode, h.il_ptr.p, h.il_col.p, h.rank.p, h.xh_off.p,
+                                                        h.cp.ek.p, h.cp.ex.p, h.cp.steps.p);
+    H2_LAUNCH_CHECK();
     // nearfield: leaves with near entries (a leaf's own block is one)
     std::vector<int> leaf_rows(h.nnode, 0);
     for (int i = 0; i < h.nnode; ++i)
         if (h.h_nchild[i] == 0) leaf_rows[i] = h.h_count[i];
-    make(leaf_rows, h.h_nr_ptr, false, h.nr_t1, h.nr_t2);
-    std::vector<int64_t> st(h.h_start.begin(), h.h_start.end());
-    h.start64.ensure(std::max<size_t>(st.size(), 1), s);
-    H2_HIP(hipMemcpyAsync(h.start64.p, st.data(), st.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    make(leaf_rows, h.h_nr_ptr, false, h.nr);
+    h.nr.ek.ensure(std::max<int64_t>(h.nnear, 1), s);
+    h.nr.ex.ensure(std::max<int64_t>(h.nnear, 1), s);
+    h.nr.steps.ensure(std::max(h.nnode, 1), s);
+    k_sweep_meta<<<blocks_for(h.nnode, TB), TB, 0, s>>>(h.nnode, h.nr_ptr.p, h.nr_col.p, h.count.p, h.start64.p,
+                                                        h.nr.ek.p, h.nr.ex.p, h.nr.steps.p);
+    H2_LAUNCH_CHECK();
     if (h.precision == 32) {
         const int64_t nt = std::max<int64_t>(h.h_T_off[h.nnode], 1);
         h.Tf.ensure((size_t)nt, s);
