@@ -54,9 +54,10 @@ typedef enum { H2_COULOMB = 0, H2_GAUSSIAN = 1, H2_EXPONENTIAL = 2, H2_MATERN32 
  *   r_min          0, or a lower bound applied to r1 and r2 after they were
  *                  chosen from the tolerance
  *   precision      64: FP64 throughout; 32: the coupling and nearfield blocks,
- *                  the apply and its vectors in FP32 (FP32 accumulation,
- *                  compensated accumulation of the nearfield blocks); the tree,
- *                  HiDR and the interpolative decompositions stay FP64
+ *                  the apply and its vectors in FP32 (FP32 products per block,
+ *                  compensated accumulation of the block products, FP64
+ *                  interpolation sums); the tree, HiDR and the interpolative
+ *                  decompositions stay FP64
  *   store_coupling 1: store the coupling and nearfield blocks (default)
  *   calib_seed     seed of the random points used to choose r1, r2
  *   profile        1: h2_matvec records HIP events around each of its sweeps on
@@ -93,6 +94,28 @@ h2_status h2_build(const double *points, int64_t n, int dim, int kernel_id, cons
  * default stream) on which all work is ordered.                          */
 h2_status h2_build_ex(const double *points, int64_t n, int dim, int kernel_id, const double *params,
                       double tol, int leaf_size, const h2_options *opt, void *hip_stream, h2_handle *out);
+
+/* h2_build_batched: Algorithm 2 for nprob independent problems in one call.
+ * Each problem is built exactly as h2_build_ex would build it alone (same
+ * tree, lists, r1/r2, HiDR, bases and blocks), but two steps run over all
+ * problems together: the choice of r1, r2 (Section 4.2; identical
+ * calibration sets of different problems are evaluated once, and all sets
+ * share each round's launches), and the nested-basis step -- kernel-block
+ * evaluation and pivoted-QR ID of Section 4.1 -- level by level: round t
+ * takes depth maxdepth_p - t of every problem p, and all its nodes go into
+ * one batched launch.
+ *   points     host array of nprob device pointers, each as in h2_build
+ *   n, dim, kernel_id, tol, leaf_size   host arrays [nprob], as in h2_build
+ *   params     host array [nprob]: params[p] is problem p's params[0]
+ *              (ignored for Coulomb)
+ *   opt        options shared by all problems (NULL = defaults)
+ *   hip_stream stream of all work and of the returned handles (NULL = default)
+ *   out        host array [nprob] of handles; all NULL on failure, and the
+ *              message of h2_last_error() names the problem that failed a check.
+ * Synchronises the stream.                                                */
+h2_status h2_build_batched(int nprob, const double *const *points, const int64_t *n, const int *dim,
+                           const int *kernel_id, const double *params, const double *tol, const int *leaf_size,
+                           const h2_options *opt, void *hip_stream, h2_handle *out);
 
 /* h2_matvec: y = Ktilde x with the H^2 representation (upward, coupling,
  * downward and nearfield sweeps).

@@ -1,4 +1,12 @@
 // Caching device allocator behind DBuf (see common.h).
+//
+// Every freed block is kept for reuse: blocks below LARGE bytes in power-of-
+// two size classes, larger ones reused best-fit within 25 % waste.  A block
+// remembers the stream it was last used on and an event recorded there when
+// it was freed; reusing it on another stream makes that stream wait for the
+// event (no host synchronisation, no device-wide hipFree on the hot path).
+// When hipMalloc fails the cache is released (after each block's event) and
+// the allocation retried.
 #include <mutex>
 #include <vector>
 
@@ -7,15 +15,27 @@
 namespace h2 {
 namespace {
 
-constexpr size_t CACHE_MIN = (size_t)64 << 20;  // blocks from 64 MiB up are cached
+constexpr size_t LARGE = (size_t)32 << 20;
+constexpr size_t MIN_CLASS = 512;
 
 struct Block {
     void* p;
     size_t bytes;
+    hipStream_t s;
+    hipEvent_t ev;
 };
 
 std::mutex g_mu;
 std::vector<Block> g_cache;
+std::vector<hipEvent_t> g_events;
+
+size_t class_bytes(size_t bytes)
+{
+    if (bytes >= LARGE) return bytes;
+    size_t c = MIN_CLASS;
+    while (c < bytes) c <<= 1;
+    return c;
+}
 
 void* raw_alloc(size_t bytes)
 {
@@ -27,52 +47,85 @@ void* raw_alloc(size_t bytes)
     return p;
 }
 
+hipEvent_t take_event()
+{
+    if (!g_events.empty()) {
+        hipEvent_t e = g_events.back();
+        g_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
 }  // namespace
 
-void* dev_alloc(size_t bytes)
+void* dev_alloc(size_t bytes, hipStream_t s)
 {
-    if (bytes >= CACHE_MIN) {
+    const size_t cb = class_bytes(bytes);
+    {
         std::lock_guard<std::mutex> lk(g_mu);
-        // smallest cached block that fits without wasting more than a quarter
         int best = -1;
-        for (int i = 0; i < (int)g_cache.size(); ++i)
-            if (g_cache[i].bytes >= bytes && g_cache[i].bytes <= bytes + bytes / 4 &&
-                (best < 0 || g_cache[i].bytes < g_cache[best].bytes))
+        for (int i = (int)g_cache.size() - 1; i >= 0; --i) {
+            const size_t b = g_cache[i].bytes;
+            const bool fits = cb < LARGE ? b == cb : (b >= cb && b <= cb + cb / 4);
+            if (fits && (best < 0 || b < g_cache[best].bytes)) {
                 best = i;
+                if (cb < LARGE) break;
+            }
+        }
         if (best >= 0) {
-            void* p = g_cache[best].p;
+            Block blk = g_cache[best];
             g_cache.erase(g_cache.begin() + best);
-            return p;
+            if (blk.ev) {
+                if (blk.s != s) H2_HIP(hipStreamWaitEvent(s, blk.ev, 0));
+                g_events.push_back(blk.ev);
+            }
+            return blk.p;
         }
     }
-    void* p = raw_alloc(bytes);
+    void* p = raw_alloc(cb);
     if (!p) {
         dev_cache_trim();
-        p = raw_alloc(bytes);
+        p = raw_alloc(cb);
     }
-    if (!p) fail(H2_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    if (!p) fail(H2_ENOMEM, "device allocation of " + std::to_string(cb) + " bytes failed");
     return p;
 }
 
 void dev_free(void* p, size_t bytes, hipStream_t s)
 {
     if (!p) return;
-    if (bytes >= CACHE_MIN) {
-        // work queued on s may still read or write the block
-        if (hipStreamSynchronize(s) == hipSuccess) {
-            std::lock_guard<std::mutex> lk(g_mu);
-            g_cache.push_back({p, bytes});
-            return;
-        }
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipEvent_t e = take_event();
+    if (e && hipEventRecord(e, s) != hipSuccess) {
+        (void)hipGetLastError();
+        g_events.push_back(e);
+        e = nullptr;
+    }
+    if (!e) {
+        // no event: wait here so that the block is idle when reused
+        (void)hipStreamSynchronize(s);
         (void)hipGetLastError();
     }
-    (void)hipFree(p);
+    g_cache.push_back({p, class_bytes(bytes), s, e});
 }
 
 void dev_cache_trim()
 {
     std::lock_guard<std::mutex> lk(g_mu);
-    for (auto& b : g_cache) (void)hipFree(b.p);
+    for (auto& b : g_cache) {
+        if (b.ev) {
+            (void)hipEventSynchronize(b.ev);
+            g_events.push_back(b.ev);
+        }
+        (void)hipFree(b.p);
+    }
+    (void)hipGetLastError();
     g_cache.clear();
 }
 

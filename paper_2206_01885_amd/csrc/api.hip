@@ -4,7 +4,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <exception>
+#include <mutex>
 #include <new>
+#include <thread>
 
 #include "common.h"
 
@@ -34,6 +37,101 @@ void upload_vec(h2::DBuf<T>& dst, const std::vector<T>& src, hipStream_t s)
     if (!src.empty())
         H2_HIP(hipMemcpyAsync(dst.p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
     H2_HIP(hipStreamSynchronize(s));
+}
+
+
+// Worker streams of the batched build: created once, kept for the life of
+// the process (buffers allocated on them remember them), default priority,
+// not synchronising with the null stream.
+constexpr int NWORK = 8;
+hipStream_t worker_stream(int w)
+{
+    static std::mutex mu;
+    static hipStream_t st[NWORK] = {};
+    std::lock_guard<std::mutex> lk(mu);
+    if (!st[w]) H2_HIP(hipStreamCreateWithFlags(&st[w], hipStreamNonBlocking));
+    return st[w];
+}
+
+// Argument checks and the handle's problem parameters (h2_build_ex and
+// h2_build_batched).
+h2_status check_and_init(h2::Handle& h, const double* points, int64_t n, int dim, int kernel_id,
+                         const double* params, double tol, int leaf_size, const h2_options& opt, hipStream_t s)
+{
+    if (!points) return set_err(H2_EINVAL, "points is NULL");
+    if (n < 1 || n > (int64_t)INT32_MAX) return set_err(H2_EINVAL, "n must be in [1, 2^31)");
+    if (dim < 1 || dim > 3) return set_err(H2_EINVAL, "dim must be 1, 2 or 3");
+    if (kernel_id < H2_COULOMB || kernel_id > H2_MATERN32) return set_err(H2_EINVAL, "unknown kernel_id");
+    if (!(tol > 0.0 && tol < 1.0)) return set_err(H2_EINVAL, "tol must be in (0, 1)");
+    if (leaf_size < 1) return set_err(H2_EINVAL, "leaf_size must be >= 1");
+    if (!(opt.tau > 0.0 && opt.tau < 1.0)) return set_err(H2_EINVAL, "tau must be in (0, 1)");
+    if (opt.r1 < 0 || opt.r2 < 0 || opt.r1 > 2048 || opt.r2 > 2048)
+        return set_err(H2_EINVAL, "r1, r2 must be in [0, 2048]");
+    if (opt.precision != 64 && opt.precision != 32) return set_err(H2_EINVAL, "precision must be 64 or 32");
+    if (opt.r_min < 0 || opt.r_min > 2048) return set_err(H2_EINVAL, "r_min must be in [0, 2048]");
+    if (opt.store_coupling != 1) return set_err(H2_EUNSUPPORTED, "only stored coupling blocks are implemented");
+    double prm = 1.0;
+    if (kernel_id != H2_COULOMB) {
+        if (!params) return set_err(H2_EINVAL, "params is NULL");
+        prm = params[0];
+        if (!(std::isfinite(prm) && prm > 0.0)) return set_err(H2_EINVAL, "params[0] must be finite and > 0");
+    }
+    h.n = n;
+    h.d = dim;
+    h.kid = kernel_id;
+    h.prm = prm;
+    h.tol = tol;
+    h.tol_int = 0.5 * tol;  // eps' = eps/2 for truncation and calibration
+    h.tau = opt.tau;
+    h.q = leaf_size;
+    h.r1 = opt.r1;
+    h.r2 = opt.r2;
+    h.precision = opt.precision;
+    h.store_coupling = opt.store_coupling;
+    h.calib_seed = opt.calib_seed;
+    h.profile = opt.profile;
+    h.r_min = opt.r_min;
+    h.stream = s;
+    return H2_OK;
+}
+
+// Algorithm 2, first steps: tree and lists.
+void build_tree_lists(h2::Handle& h, const double* points)
+{
+    double t0 = now_s();
+    h2::build_tree(h, points);
+    H2_HIP(hipStreamSynchronize(h.stream));
+    double t1 = now_s();
+    h2::build_lists(h);
+    H2_HIP(hipStreamSynchronize(h.stream));
+    double t2 = now_s();
+    h.t_tree = t1 - t0;
+    h.t_lists = t2 - t1;
+}
+
+// HiDR (after r1, r2 are known).
+void build_hidr(h2::Handle& h)
+{
+    double t0 = now_s();
+    h2::run_hidr(h);
+    h.t_hidr = now_s() - t0;
+}
+
+// After the nested bases: coupling and nearfield blocks, apply preparation.
+void build_back(h2::Handle& h)
+{
+    double t5 = now_s();
+    h2::build_blocks(h);
+    double t6 = now_s();
+    std::vector<int> leaves;
+    for (int i = 0; i < h.nnode; ++i)
+        if (h.h_nchild[i] == 0) leaves.push_back(i);
+    upload_vec(h.leaves, leaves, h.stream);
+    std::vector<int64_t> xo((size_t)h.nnode + 1, 0);
+    for (int i = 0; i < h.nnode; ++i) xo[i + 1] = xo[i] + h.h_rank[i];
+    upload_vec(h.xh_off, xo, h.stream);
+    h2::prepare_apply(h);
+    h.t_blocks = t6 - t5;
 }
 
 }  // namespace
@@ -69,74 +167,24 @@ h2_status h2_build_ex(const double* points, int64_t n, int dim, int kernel_id, c
     h2_options opt;
     h2_options_default(&opt);
     if (opt_in) opt = *opt_in;
-    if (!points) return set_err(H2_EINVAL, "points is NULL");
-    if (n < 1 || n > (int64_t)INT32_MAX) return set_err(H2_EINVAL, "n must be in [1, 2^31)");
-    if (dim < 1 || dim > 3) return set_err(H2_EINVAL, "dim must be 1, 2 or 3");
-    if (kernel_id < H2_COULOMB || kernel_id > H2_MATERN32) return set_err(H2_EINVAL, "unknown kernel_id");
-    if (!(tol > 0.0 && tol < 1.0)) return set_err(H2_EINVAL, "tol must be in (0, 1)");
-    if (leaf_size < 1) return set_err(H2_EINVAL, "leaf_size must be >= 1");
-    if (!(opt.tau > 0.0 && opt.tau < 1.0)) return set_err(H2_EINVAL, "tau must be in (0, 1)");
-    if (opt.r1 < 0 || opt.r2 < 0 || opt.r1 > 2048 || opt.r2 > 2048)
-        return set_err(H2_EINVAL, "r1, r2 must be in [0, 2048]");
-    if (opt.precision != 64 && opt.precision != 32) return set_err(H2_EINVAL, "precision must be 64 or 32");
-    if (opt.r_min < 0 || opt.r_min > 2048) return set_err(H2_EINVAL, "r_min must be in [0, 2048]");
-    if (opt.store_coupling != 1) return set_err(H2_EUNSUPPORTED, "only stored coupling blocks are implemented");
-    double prm = 1.0;
-    if (kernel_id != H2_COULOMB) {
-        if (!params) return set_err(H2_EINVAL, "params is NULL");
-        prm = params[0];
-        if (!(std::isfinite(prm) && prm > 0.0)) return set_err(H2_EINVAL, "params[0] must be finite and > 0");
-    }
     h2_handle_s* hs = new (std::nothrow) h2_handle_s();
     if (!hs) return set_err(H2_ENOMEM, "host allocation failed");
     h2::Handle& h = hs->h;
-    h.n = n;
-    h.d = dim;
-    h.kid = kernel_id;
-    h.prm = prm;
-    h.tol = tol;
-    h.tol_int = 0.5 * tol;  // eps' = eps/2 for truncation and calibration
-    h.tau = opt.tau;
-    h.q = leaf_size;
-    h.r1 = opt.r1;
-    h.r2 = opt.r2;
-    h.precision = opt.precision;
-    h.store_coupling = opt.store_coupling;
-    h.calib_seed = opt.calib_seed;
-    h.profile = opt.profile;
-    h.r_min = opt.r_min;
-    h.stream = (hipStream_t)hip_stream;
+    h2_status st = check_and_init(h, points, n, dim, kernel_id, params, tol, leaf_size, opt, (hipStream_t)hip_stream);
+    if (st != H2_OK) {
+        delete hs;
+        return st;
+    }
     try {
+        build_tree_lists(h, points);
         double t0 = now_s();
-        h2::build_tree(h, points);
-        H2_HIP(hipStreamSynchronize(h.stream));
-        double t1 = now_s();
-        h2::build_lists(h);
-        H2_HIP(hipStreamSynchronize(h.stream));
-        double t2 = now_s();
         h2::run_calibration(h);
-        double t3 = now_s();
-        h2::run_hidr(h);
-        double t4 = now_s();
+        h.t_calib = now_s() - t0;
+        build_hidr(h);
+        t0 = now_s();
         h2::build_bases(h);
-        double t5 = now_s();
-        h2::build_blocks(h);
-        double t6 = now_s();
-        // leaves and coefficient offsets for the apply
-        std::vector<int> leaves;
-        for (int i = 0; i < h.nnode; ++i)
-            if (h.h_nchild[i] == 0) leaves.push_back(i);
-        upload_vec(h.leaves, leaves, h.stream);
-        std::vector<int64_t> xo((size_t)h.nnode + 1, 0);
-        for (int i = 0; i < h.nnode; ++i) xo[i + 1] = xo[i] + h.h_rank[i];
-        upload_vec(h.xh_off, xo, h.stream);
-        h2::prepare_apply(h);
-        h.t_tree = t1 - t0;
-        h.t_lists = t2 - t1;
-        h.t_calib = t3 - t2;
-        h.t_hidr = t4 - t3;
-        h.t_basis = t5 - t4;
-        h.t_blocks = t6 - t5;
+        h.t_basis = now_s() - t0;
+        build_back(h);
     } catch (const h2::Error& e) {
         delete hs;
         return set_err(e.code, e.msg);
@@ -145,6 +193,102 @@ h2_status h2_build_ex(const double* points, int64_t n, int dim, int kernel_id, c
         return set_err(H2_ENOMEM, "host allocation failed");
     }
     *out = hs;
+    return H2_OK;
+}
+
+h2_status h2_build_batched(int nprob, const double* const* points, const int64_t* n, const int* dim,
+                           const int* kernel_id, const double* params, const double* tol, const int* leaf_size,
+                           const h2_options* opt_in, void* hip_stream, h2_handle* out)
+{
+    if (!out) return set_err(H2_EINVAL, "out is NULL");
+    if (nprob < 1) return set_err(H2_EINVAL, "nprob must be >= 1");
+    for (int p = 0; p < nprob; ++p) out[p] = nullptr;
+    if (!points || !n || !dim || !kernel_id || !params || !tol || !leaf_size)
+        return set_err(H2_EINVAL, "an argument array is NULL");
+    h2_options opt;
+    h2_options_default(&opt);
+    if (opt_in) opt = *opt_in;
+    std::vector<h2_handle_s*> hs(nprob, nullptr);
+    auto cleanup = [&]() {
+        for (auto* x : hs) delete x;
+    };
+    for (int p = 0; p < nprob; ++p) {
+        hs[p] = new (std::nothrow) h2_handle_s();
+        if (!hs[p]) {
+            cleanup();
+            return set_err(H2_ENOMEM, "host allocation failed");
+        }
+        h2_status st = check_and_init(hs[p]->h, points[p], n[p], dim[p], kernel_id[p], params + p, tol[p],
+                                      leaf_size[p], opt, (hipStream_t)hip_stream);
+        if (st != H2_OK) {
+            std::string msg = "problem " + std::to_string(p) + ": " + g_last_error;
+            cleanup();
+            return set_err(st, msg);
+        }
+    }
+    try {
+        const hipStream_t us = (hipStream_t)hip_stream;
+        std::vector<h2::Handle*> hv(nprob);
+        for (int p = 0; p < nprob; ++p) hv[p] = &hs[p]->h;
+        // the per-problem steps (many small launches and read-backs each) run
+        // concurrently: problem p on worker p % W, each worker with its own
+        // stream, ordered after the caller's stream; the shared steps run on
+        // the caller's stream after all workers finished
+        const int W = std::min(nprob, NWORK);
+        std::vector<hipStream_t> ws(W);
+        for (int w = 0; w < W; ++w) ws[w] = worker_stream(w);
+        hipEvent_t ready = nullptr;
+        H2_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        H2_HIP(hipEventRecord(ready, us));
+        for (int w = 0; w < W; ++w) H2_HIP(hipStreamWaitEvent(ws[w], ready, 0));
+        H2_HIP(hipEventSynchronize(ready));
+        (void)hipEventDestroy(ready);
+        auto parallel = [&](auto&& fn) {
+            int dev = 0;
+            H2_HIP(hipGetDevice(&dev));
+            std::vector<std::exception_ptr> errs(W);
+            std::vector<std::thread> th;
+            for (int w = 0; w < W; ++w)
+                th.emplace_back([&, w]() {
+                    try {
+                        H2_HIP(hipSetDevice(dev));
+                        for (int p = w; p < nprob; p += W) {
+                            hv[p]->stream = ws[w];
+                            fn(p);
+                        }
+                        H2_HIP(hipStreamSynchronize(ws[w]));
+                    } catch (...) {
+                        errs[w] = std::current_exception();
+                    }
+                });
+            for (auto& t : th) t.join();
+            for (int p = 0; p < nprob; ++p) hv[p]->stream = us;
+            for (auto& e : errs)
+                if (e) std::rethrow_exception(e);
+        };
+        parallel([&](int p) { build_tree_lists(*hv[p], points[p]); });
+        double t0 = now_s();
+        h2::run_calibration_multi(hv, us);
+        const double tc = now_s() - t0;
+        parallel([&](int p) {
+            hv[p]->t_calib = tc;
+            build_hidr(*hv[p]);
+        });
+        t0 = now_s();
+        h2::build_bases_multi(hv, us);
+        const double tb = now_s() - t0;
+        parallel([&](int p) {
+            hv[p]->t_basis = tb;
+            build_back(*hv[p]);
+        });
+    } catch (const h2::Error& e) {
+        cleanup();
+        return set_err(e.code, e.msg);
+    } catch (const std::bad_alloc&) {
+        cleanup();
+        return set_err(H2_ENOMEM, "host allocation failed");
+    }
+    for (int p = 0; p < nprob; ++p) out[p] = hs[p];
     return H2_OK;
 }
 
@@ -164,7 +308,10 @@ h2_status h2_matvec_ex(h2_handle hd, const void* x, void* y, int nrhs, void* hip
     const char* yb = (const char*)y;
     if (!(xb + bytes <= yb || yb + bytes <= xb)) return set_err(H2_EINVAL, "x and y overlap");
     try {
-        h2::matvec(h, x, y, nrhs, (hipStream_t)hip_stream);
+        hipStream_t ms = (hipStream_t)hip_stream;
+        if (ms != h.stream && std::find(h.mv_streams.begin(), h.mv_streams.end(), ms) == h.mv_streams.end())
+            h.mv_streams.push_back(ms);
+        h2::matvec(h, x, y, nrhs, ms);
     } catch (const h2::Error& e) {
         return set_err(e.code, e.msg);
     }
@@ -310,6 +457,7 @@ h2_status h2_destroy(h2_handle hd)
 {
     if (!hd) return H2_OK;
     (void)hipStreamSynchronize(hd->h.stream);
+    for (hipStream_t ms : hd->h.mv_streams) (void)hipStreamSynchronize(ms);
     for (auto& e : hd->h.ev)
         if (e) (void)hipEventDestroy(e);
     delete hd;

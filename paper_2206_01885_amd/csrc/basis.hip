@@ -136,34 +136,36 @@ __device__ __forceinline__ double axpy_rows(const double* __restrict__ v, double
 // LDSM: the s x m block lives in LDS (dynamic shared memory after the
 // reflector), otherwise in the global workspace.  The arithmetic is the same.
 template <int NT, bool LDSM>
-__global__ __launch_bounds__(NT) void k_batched_id(IdBatch b, const int* __restrict__ order, int d, int kid,
-                                                   double prm)
+__global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ tasks, const int* __restrict__ order)
 {
     extern __shared__ double dyn[];
     __shared__ double redd[4];
     __shared__ int redi[4];
     __shared__ double sh_alpha;
 
-    const int p = order[blockIdx.x];
-    const int m = b.m[p], s = b.s[p];
-    int* piv = b.piv_out + b.piv_off[p];
+    const IdTask& tk = tasks[order[blockIdx.x]];
+    const int m = tk.m, s = tk.s, d = tk.d, kid = tk.kid;
+    const double prm = tk.prm, tol = tk.tol;
+    int* piv = tk.piv;
     for (int c = threadIdx.x; c < m; c += NT) piv[c] = c;
     if (m == 0 || s == 0) {
-        if (threadIdx.x == 0) b.rank_out[p] = 0;
+        if (threadIdx.x == 0) *tk.rank = 0;
         return;
     }
     double* v = dyn;
-    double* M = LDSM ? dyn + s : b.M + b.M_off[p];
-    double* nu = b.nu + b.nu_off[p];
+    double* M = LDSM ? dyn + s : tk.M;
+    double* nu = tk.nu;
     double* nu0 = nu + m;
     double* ss = nu + 2 * m;
-    const int* xi = b.x_idx + b.x_off[p];
-    const int* yi = b.y_idx + b.y_off[p];
+    const int* xi = tk.x_idx;
+    const int* yi = tk.y_idx;
+    const double* pts = tk.pts;
+    const int64_t ld = tk.ld;
 
     // kernel block: M[r][c] = kappa(x_c, y_r)
     for (int64_t e = threadIdx.x; e < (int64_t)s * m; e += NT) {
         int r = (int)(e / m), c = (int)(e - (int64_t)r * m);
-        double r2 = dist2(b.xpts, b.xld, xi[c], b.ypts, b.yld, yi[r], d);
+        double r2 = dist2(pts, ld, xi[c], pts, ld, yi[r], d);
         M[e] = kappa_r2(kid, prm, r2);
     }
     __syncthreads();
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(NT) void k_batched_id(IdBatch b, const int* __restr
         __syncthreads();
         const double alpha = sh_alpha;
         if (j == 0) r00 = alpha;
-        if (alpha == 0.0 || alpha <= b.tol * r00) break;
+        if (alpha == 0.0 || alpha <= tol * r00) break;
         if (pc != j) {
             for (int r = threadIdx.x; r < s; r += NT) {
                 double t = M[(int64_t)r * m + j];
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(NT) void k_batched_id(IdBatch b, const int* __restr
     }
     // T = R11^{-1} R12 by back substitution, one column of R12 per lane
     const int nr = m - k;
-    double* T = b.T_out + b.T_off[p];
+    double* T = tk.T;
     for (int u = threadIdx.x; u < nr; u += NT) {
         for (int t = k - 1; t >= 0; --t) {
             double acc = M[(int64_t)t * m + (k + u)];
@@ -265,8 +267,8 @@ __global__ __launch_bounds__(NT) void k_batched_id(IdBatch b, const int* __restr
             T[(int64_t)t * nr + u] = acc / M[(int64_t)t * m + t];
         }
     }
-    for (int t = threadIdx.x; t < k; t += NT) b.skel_out[(int64_t)p * b.skel_stride + t] = xi[piv[t]];
-    if (threadIdx.x == 0) b.rank_out[p] = k;
+    for (int t = threadIdx.x; t < k; t += NT) tk.skel[t] = xi[piv[t]];
+    if (threadIdx.x == 0) *tk.rank = k;
 }
 
 // Row set of every node of a level: the leaf's points, or the children's
@@ -294,46 +296,49 @@ __global__ __launch_bounds__(TB) void k_xbar_fill(int lo, const int* __restrict_
 
 }  // namespace
 
-void batched_id(const IdBatch& b, const std::vector<int>& m_host, const std::vector<int>& s_host, int d, int kid,
-                double prm, hipStream_t s)
+void batched_id(const std::vector<IdTask>& tasks, hipStream_t s)
 {
-    if (b.nprob <= 0) return;
+    const int np = (int)tasks.size();
+    if (np <= 0) return;
     // class 0: one wavefront, block in LDS; 1: one wavefront, global block;
     // 2: four wavefronts, global block
     const int LDS_DOUBLES = 8192;  // 64 KiB per workgroup
-    std::vector<int> cls(b.nprob);
-    for (int p = 0; p < b.nprob; ++p) {
-        int64_t need = (int64_t)s_host[p] * (m_host[p] + 1);
-        cls[p] = m_host[p] <= 64 ? (need <= LDS_DOUBLES ? 0 : 1) : 2;
+    std::vector<int> cls(np);
+    for (int p = 0; p < np; ++p) {
+        int64_t need = (int64_t)tasks[p].s * (tasks[p].m + 1);
+        cls[p] = tasks[p].m <= 64 ? (need <= LDS_DOUBLES ? 0 : 1) : 2;
     }
     std::vector<int> order;
-    order.reserve(b.nprob);
+    order.reserve(np);
     int cnt[3] = {0, 0, 0};
     size_t lds[3] = {8, 8, 8};
     for (int c = 0; c < 3; ++c)
-        for (int p = 0; p < b.nprob; ++p)
+        for (int p = 0; p < np; ++p)
             if (cls[p] == c) {
                 order.push_back(p);
                 ++cnt[c];
-                size_t need = (size_t)s_host[p] * (c == 0 ? m_host[p] + 1 : 1) * sizeof(double);
+                size_t need = (size_t)tasks[p].s * (c == 0 ? tasks[p].m + 1 : 1) * sizeof(double);
                 lds[c] = std::max(lds[c], need);
             }
+    DBuf<IdTask> d_tasks;
     DBuf<int> d_order;
+    d_tasks.ensure(tasks.size(), s);
     d_order.ensure(order.size(), s);
+    H2_HIP(hipMemcpyAsync(d_tasks.p, tasks.data(), tasks.size() * sizeof(IdTask), hipMemcpyHostToDevice, s));
     H2_HIP(hipMemcpyAsync(d_order.p, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s));
     int o = 0;
     if (cnt[0] > 0) {
-        k_batched_id<64, true><<<cnt[0], 64, lds[0], s>>>(b, d_order.p + o, d, kid, prm);
+        k_batched_id<64, true><<<cnt[0], 64, lds[0], s>>>(d_tasks.p, d_order.p + o);
         H2_LAUNCH_CHECK();
     }
     o += cnt[0];
     if (cnt[1] > 0) {
-        k_batched_id<64, false><<<cnt[1], 64, lds[1], s>>>(b, d_order.p + o, d, kid, prm);
+        k_batched_id<64, false><<<cnt[1], 64, lds[1], s>>>(d_tasks.p, d_order.p + o);
         H2_LAUNCH_CHECK();
     }
     o += cnt[1];
     if (cnt[2] > 0) {
-        k_batched_id<TB, false><<<cnt[2], TB, lds[2], s>>>(b, d_order.p + o, d, kid, prm);
+        k_batched_id<TB, false><<<cnt[2], TB, lds[2], s>>>(d_tasks.p, d_order.p + o);
         H2_LAUNCH_CHECK();
     }
     H2_HIP(hipStreamSynchronize(s));
@@ -347,130 +352,164 @@ static void upload(DBuf<T>& dst, const std::vector<T>& src, hipStream_t s)
         H2_HIP(hipMemcpyAsync(dst.p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
-void build_bases(Handle& h)
+// Nested bases of several independent problems at once: round t handles
+// depth maxdepth - t of every problem (a node's children were done in the
+// round before), and all nodes of a round go into one batched ID launch
+// (several only when the workspace cap splits it).  piv and T offsets are
+// assigned per problem in processing order (deepest level first).
+void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
 {
-    hipStream_t s = h.stream;
-    const int nn = h.nnode;
-    h.rank.ensure((size_t)nn, s);
-    h.mbar.ensure((size_t)nn, s);
-    h.skel.ensure((size_t)nn * h.ys_stride, s);
-    h.piv_off.ensure((size_t)nn + 1, s);
-    h.T_off.ensure((size_t)nn + 1, s);
-    H2_HIP(hipMemsetAsync(h.rank.p, 0, sizeof(int) * nn, s));
-    H2_HIP(hipMemsetAsync(h.mbar.p, 0, sizeof(int) * nn, s));
-    std::vector<int> ys_cnt = read_vec(h.ys_cnt.p, nn, s);
-    h.h_rank.assign(nn, 0);
-    h.h_mbar.assign(nn, 0);
-    h.h_piv_off.assign((size_t)nn + 1, 0);
-    h.h_T_off.assign((size_t)nn + 1, 0);
-
-    // piv and T offsets for all nodes need the ranks of the level below, so
-    // they are assigned level by level; nodes are laid out in id order, with
-    // the root (never compressed) at offset 0 with size 0.
-    int64_t piv_total = 0, T_total = 0;
-    std::vector<int> mv, sv;
-    std::vector<int64_t> xoff, yoff, Moff, nuoff, pivoff, Toff;
-    DBuf<int> d_m, d_s, d_xidx;
-    DBuf<int64_t> d_xoff, d_yoff, d_Moff, d_nuoff, d_pivoff, d_Toff;
-    DBuf<double> Mws, nuws;
+    struct St {
+        std::vector<int> ys_cnt;
+        int64_t piv_total = 0, T_total = 0;
+    };
+    const int np = (int)hs.size();
+    std::vector<St> st(np);
+    int maxd = 0;
+    for (int p = 0; p < np; ++p) {
+        Handle& h = *hs[p];
+        const int nn = h.nnode;
+        h.rank.ensure((size_t)nn, s);
+        h.mbar.ensure((size_t)nn, s);
+        h.skel.ensure((size_t)nn * h.ys_stride, s);
+        h.piv_off.ensure((size_t)nn + 1, s);
+        h.T_off.ensure((size_t)nn + 1, s);
+        H2_HIP(hipMemsetAsync(h.rank.p, 0, sizeof(int) * nn, s));
+        H2_HIP(hipMemsetAsync(h.mbar.p, 0, sizeof(int) * nn, s));
+        st[p].ys_cnt = read_vec(h.ys_cnt.p, nn, s);
+        h.h_rank.assign(nn, 0);
+        h.h_mbar.assign(nn, 0);
+        h.h_piv_off.assign((size_t)nn + 1, 0);
+        h.h_T_off.assign((size_t)nn + 1, 0);
+        maxd = std::max(maxd, h.maxdepth);
+    }
     const int64_t WS_CAP = (int64_t)1 << 28;  // doubles of ID workspace per launch
-
-    // offsets of deeper levels come first in memory; compute per level
-    for (int L = h.maxdepth; L >= 1; --L) {
-        const int lo = h.lvl_ptr[L], hi = h.lvl_ptr[L + 1];
-        int c0 = lo;
-        while (c0 < hi) {
-            // chunk [c0, c1) with bounded workspace
-            int c1 = c0;
-            int64_t ws = 0;
-            mv.clear(); sv.clear(); xoff.clear(); yoff.clear(); Moff.clear(); nuoff.clear();
-            pivoff.clear(); Toff.clear();
-            int64_t xo = 0, no = 0;
-            while (c1 < hi) {
-                int i = c1;
+    DBuf<int> d_xidx;
+    DBuf<int64_t> d_xoff;
+    DBuf<double> Mws, nuws;
+    for (int t = 0; t < maxd; ++t) {
+        // problems and levels of this round; grow piv / T first (the task
+        // pointers must see the final buffers)
+        std::vector<int> lvl(np, 0);
+        int64_t xtot = 0;
+        std::vector<int64_t> xbase(np, 0);
+        for (int p = 0; p < np; ++p) {
+            Handle& h = *hs[p];
+            const int L = h.maxdepth - t;
+            lvl[p] = L;
+            if (L < 1) continue;
+            xbase[p] = xtot;
+            const int64_t keep_piv = st[p].piv_total, keep_T = st[p].T_total;
+            for (int i = h.lvl_ptr[L]; i < h.lvl_ptr[L + 1]; ++i) {
                 int m = 0;
                 if (h.h_nchild[i] == 0)
                     m = h.h_count[i];
                 else
                     for (int c = h.h_first_child[i]; c < h.h_first_child[i] + h.h_nchild[i]; ++c) m += h.h_rank[c];
-                int sy = ys_cnt[i];
-                int64_t need = (int64_t)m * sy;
-                if (c1 > c0 && ws + need > WS_CAP) break;
-                mv.push_back(m);
-                sv.push_back(sy);
-                xoff.push_back(xo);
-                yoff.push_back((int64_t)i * h.ys_stride);
-                Moff.push_back(ws);
-                nuoff.push_back(no);
-                pivoff.push_back(piv_total);
-                Toff.push_back(T_total);
-                h.h_piv_off[i] = piv_total;
-                h.h_T_off[i] = T_total;
                 h.h_mbar[i] = m;
-                xo += m;
-                no += 3 * (int64_t)m;
-                ws += need;
-                piv_total += m;
-                T_total += (int64_t)m * std::min(m, sy);
-                ++c1;
+                h.h_piv_off[i] = st[p].piv_total;
+                h.h_T_off[i] = st[p].T_total;
+                st[p].piv_total += m;
+                st[p].T_total += (int64_t)m * std::min(m, st[p].ys_cnt[i]);
+                xtot += m;
             }
-            int np = c1 - c0;
-            xoff.push_back(xo);
-            h.piv.grow_keep((size_t)std::max<int64_t>(piv_total, 1), (size_t)(piv_total - xo), s);
-            h.T.grow_keep((size_t)std::max<int64_t>(T_total, 1), (size_t)Toff[0], s);
-            upload(d_m, mv, s);
-            upload(d_s, sv, s);
-            upload(d_xoff, xoff, s);
-            upload(d_yoff, yoff, s);
-            upload(d_Moff, Moff, s);
-            upload(d_nuoff, nuoff, s);
-            upload(d_pivoff, pivoff, s);
-            upload(d_Toff, Toff, s);
-            d_xidx.ensure((size_t)std::max<int64_t>(xo, 1), s);
-            Mws.ensure((size_t)std::max<int64_t>(ws, 1), s);
-            nuws.ensure((size_t)std::max<int64_t>(no, 1), s);
-            k_xbar_fill<<<np, TB, 0, s>>>(c0, h.nchild.p, h.first_child.p, h.start.p, h.count.p, h.rank.p, h.skel.p,
+            h.piv.grow_keep((size_t)std::max<int64_t>(st[p].piv_total, 1), (size_t)keep_piv, s);
+            h.T.grow_keep((size_t)std::max<int64_t>(st[p].T_total, 1), (size_t)keep_T, s);
+        }
+        if (xtot == 0) continue;
+        // row sets of the round
+        d_xidx.ensure((size_t)xtot, s);
+        for (int p = 0; p < np; ++p) {
+            Handle& h = *hs[p];
+            const int L = lvl[p];
+            if (L < 1) continue;
+            const int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
+            std::vector<int64_t> xo((size_t)nl + 1, 0);
+            for (int q = 0; q < nl; ++q) xo[q + 1] = xo[q] + h.h_mbar[lo + q];
+            for (auto& v : xo) v += xbase[p];
+            d_xoff.ensure(xo.size(), s);
+            H2_HIP(hipMemcpyAsync(d_xoff.p, xo.data(), xo.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+            k_xbar_fill<<<nl, TB, 0, s>>>(lo, h.nchild.p, h.first_child.p, h.start.p, h.count.p, h.rank.p, h.skel.p,
                                           h.ys_stride, d_xoff.p, d_xidx.p);
             H2_LAUNCH_CHECK();
-            IdBatch b;
-            b.nprob = np;
-            b.m = d_m.p;
-            b.s = d_s.p;
-            b.x_off = d_xoff.p;
-            b.x_idx = d_xidx.p;
-            b.y_off = d_yoff.p;
-            b.y_idx = h.ys_idx.p;
-            b.xpts = h.pts.p;
-            b.xld = h.n;
-            b.ypts = h.pts.p;
-            b.yld = h.n;
-            b.M_off = d_Moff.p;
-            b.M = Mws.p;
-            b.nu = nuws.p;
-            b.nu_off = d_nuoff.p;
-            b.tol = h.tol_int;
-            b.rank_out = h.rank.p + c0;
-            b.piv_out = h.piv.p;
-            b.piv_off = d_pivoff.p;
-            b.T_out = h.T.p;
-            b.T_off = d_Toff.p;
-            b.skel_out = h.skel.p + (int64_t)c0 * h.ys_stride;
-            b.skel_stride = h.ys_stride;
-            batched_id(b, mv, sv, h.d, h.kid, h.prm, s);
-            std::vector<int> rk = read_vec(h.rank.p + c0, np, s);
-            for (int t = 0; t < np; ++t) h.h_rank[c0 + t] = rk[t];
-            c0 = c1;
+            H2_HIP(hipStreamSynchronize(s));  // d_xoff is reused by the next problem
+        }
+        // tasks, launched in chunks of bounded workspace
+        std::vector<IdTask> tasks;
+        std::vector<int64_t> Moff, nuoff;
+        int64_t ws = 0, no = 0;
+        auto flush = [&]() {
+            if (tasks.empty()) return;
+            Mws.ensure((size_t)std::max<int64_t>(ws, 1), s);
+            nuws.ensure((size_t)std::max<int64_t>(no, 1), s);
+            for (size_t q = 0; q < tasks.size(); ++q) {
+                tasks[q].M = Mws.p + Moff[q];
+                tasks[q].nu = nuws.p + nuoff[q];
+            }
+            batched_id(tasks, s);
+            tasks.clear();
+            Moff.clear();
+            nuoff.clear();
+            ws = 0;
+            no = 0;
+        };
+        for (int p = 0; p < np; ++p) {
+            Handle& h = *hs[p];
+            const int L = lvl[p];
+            if (L < 1) continue;
+            int64_t xo = xbase[p];
+            for (int i = h.lvl_ptr[L]; i < h.lvl_ptr[L + 1]; ++i) {
+                const int m = h.h_mbar[i], sy = st[p].ys_cnt[i];
+                const int64_t need = (int64_t)m * sy;
+                if (!tasks.empty() && ws + need > WS_CAP) flush();
+                IdTask tk;
+                tk.pts = h.pts.p;
+                tk.ld = h.n;
+                tk.x_idx = d_xidx.p + xo;
+                tk.y_idx = h.ys_idx.p + (int64_t)i * h.ys_stride;
+                tk.piv = h.piv.p + h.h_piv_off[i];
+                tk.T = h.T.p + h.h_T_off[i];
+                tk.skel = h.skel.p + (int64_t)i * h.ys_stride;
+                tk.rank = h.rank.p + i;
+                tk.prm = h.prm;
+                tk.tol = h.tol_int;
+                tk.m = m;
+                tk.s = sy;
+                tk.d = h.d;
+                tk.kid = h.kid;
+                tasks.push_back(tk);
+                Moff.push_back(ws);
+                nuoff.push_back(no);
+                ws += need;
+                no += 3 * (int64_t)m;
+                xo += m;
+            }
+        }
+        flush();
+        for (int p = 0; p < np; ++p) {
+            Handle& h = *hs[p];
+            const int L = lvl[p];
+            if (L < 1) continue;
+            const int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
+            std::vector<int> rk = read_vec(h.rank.p + lo, nl, s);
+            for (int q = 0; q < nl; ++q) h.h_rank[lo + q] = rk[q];
         }
     }
-    h.h_piv_off[nn] = piv_total;
-    h.h_T_off[nn] = T_total;
-    upload(h.mbar, h.h_mbar, s);
-    upload(h.piv_off, h.h_piv_off, s);
-    upload(h.T_off, h.h_T_off, s);
-    h.sum_rank = 0;
-    for (int i = 0; i < nn; ++i) h.sum_rank += h.h_rank[i];
-    h.bytes_T = T_total * (int64_t)sizeof(double);
+    for (int p = 0; p < np; ++p) {
+        Handle& h = *hs[p];
+        const int nn = h.nnode;
+        h.h_piv_off[nn] = st[p].piv_total;
+        h.h_T_off[nn] = st[p].T_total;
+        upload(h.mbar, h.h_mbar, s);
+        upload(h.piv_off, h.h_piv_off, s);
+        upload(h.T_off, h.h_T_off, s);
+        h.sum_rank = 0;
+        for (int i = 0; i < nn; ++i) h.sum_rank += h.h_rank[i];
+        h.bytes_T = st[p].T_total * (int64_t)sizeof(double);
+    }
     H2_HIP(hipStreamSynchronize(s));
 }
+
+void build_bases(Handle& h) { build_bases_multi({&h}, h.stream); }
 
 }  // namespace h2

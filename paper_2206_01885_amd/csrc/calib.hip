@@ -14,6 +14,9 @@
 // Every candidate round runs on the device: point generation, DataReduct,
 // the batched ID and the error reduction; all still-open depths of a round
 // share one launch of each.
+#include <map>
+#include <tuple>
+
 #include "common.h"
 #include "kappa.h"
 
@@ -80,8 +83,9 @@ __global__ void k_lists(int nprob, const int* __restrict__ set_of, int64_t* __re
 // fixed order by k_err_final, so the result does not depend on scheduling.
 constexpr int ECOLS = 8;
 constexpr int ECB = NZ / ECOLS;
-__global__ __launch_bounds__(TB) void k_err_part(const double* __restrict__ Z, int64_t ld, int d, int kid,
-                                                 double prm, const int* __restrict__ set_of,
+__global__ __launch_bounds__(TB) void k_err_part(const double* __restrict__ Z, int64_t ld, int d,
+                                                 const int* __restrict__ set_kid, const double* __restrict__ set_prm,
+                                                 const int* __restrict__ set_of,
                                                  const int* __restrict__ rank, const int* __restrict__ piv,
                                                  const double* __restrict__ T, int64_t T_stride,
                                                  double* __restrict__ part)
@@ -90,6 +94,8 @@ __global__ __launch_bounds__(TB) void k_err_part(const double* __restrict__ Z, i
     __shared__ double red_r[TB], red_f[TB];
     const int p = blockIdx.x / ECB, cb = blockIdx.x % ECB;
     const int base = set_of[p] * 2 * NZ;
+    const int kid = set_kid[set_of[p]];
+    const double prm = set_prm[set_of[p]];
     const int k = rank[p], nr = NZ - k;
     const int* pv = piv + (int64_t)p * NZ;
     const double* Tp = T + (int64_t)p * T_stride;
@@ -141,156 +147,212 @@ __global__ void k_err_final(int np, const double* __restrict__ part, double* __r
 
 static int r_cap(int d) { return d == 3 ? 512 : (d == 2 ? 484 : 64); }
 
-void run_calibration(Handle& h)
+// Calibration of a list of sets that share d, tau and the seed; set t has
+// kernel kid[t] with parameter prm[t], box side side[t] and tolerance eps[t].
+// Returns, per set, the first r = g^d whose error is below 1e-2 eps (or the
+// cap) and that error.
+static void calibrate_sets(int d, double tau, uint64_t seed, const std::vector<double>& sides,
+                           const std::vector<int>& kids, const std::vector<double>& prms,
+                           const std::vector<double>& epss, int cap, std::vector<int>& result,
+                           std::vector<double>& result_err, hipStream_t s)
 {
-    hipStream_t s = h.stream;
-    const int d = h.d;
-    const double eps = h.tol_int;
-    const int cap = r_cap(d);
-    h.calib_r.assign((size_t)h.maxdepth + 1, 0);
-    h.calib_err.assign((size_t)h.maxdepth + 1, 0.0);
-    if (h.r1 > 0 && h.r2 > 0) return;
-
-    // the calibration sets: (depth, side)
-    std::vector<int> depths;
-    std::vector<double> sides;
-    std::vector<double> hside = read_vec(h.side.p, (size_t)h.nnode, s);
-    if (h.kid == H2_COULOMB) {
-        depths.push_back(-1);
-        sides.push_back(1.0);
-    } else {
-        for (int L = 1; L <= h.maxdepth; ++L) {
-            bool has = false;
-            for (int i = h.lvl_ptr[L]; i < h.lvl_ptr[L + 1] && !has; ++i) has = h.h_il_ptr[i + 1] > h.h_il_ptr[i];
-            if (!has) continue;
-            depths.push_back(L);
-            sides.push_back(hside[h.lvl_ptr[L]]);
+    const int nset = (int)sides.size();
+    result.assign(nset, cap);
+    result_err.assign(nset, 0.0);
+    if (nset == 0) return;
+    DBuf<double> dsides, Z, dprm;
+    DBuf<int> dkid;
+    dsides.ensure(nset, s);
+    dprm.ensure(nset, s);
+    dkid.ensure(nset, s);
+    H2_HIP(hipMemcpyAsync(dsides.p, sides.data(), sizeof(double) * nset, hipMemcpyHostToDevice, s));
+    H2_HIP(hipMemcpyAsync(dprm.p, prms.data(), sizeof(double) * nset, hipMemcpyHostToDevice, s));
+    H2_HIP(hipMemcpyAsync(dkid.p, kids.data(), sizeof(int) * nset, hipMemcpyHostToDevice, s));
+    const int64_t ld = (int64_t)nset * 2 * NZ;
+    Z.ensure((size_t)d * ld, s);
+    k_points<<<blocks_for(ld, TB), TB, 0, s>>>(nset, dsides.p, d, tau, seed, Z.p);
+    H2_LAUNCH_CHECK();
+    std::vector<int> open(nset, 1);
+    DBuf<int> set_of, z2idx, z1idx, mm, ycnt, yidx, rank, piv, skel;
+    DBuf<int64_t> zoff, xoff;
+    DBuf<double> M, nu, T, err, part;
+    for (int g = 1;; ++g) {
+        long long rr = 1;
+        for (int a = 0; a < d; ++a) rr *= g;
+        const int r = rr > cap ? cap : (int)rr;
+        std::vector<int> sets;
+        for (int t = 0; t < nset; ++t)
+            if (open[t]) sets.push_back(t);
+        if (sets.empty()) break;
+        const int np = (int)sets.size();
+        set_of.ensure(np, s);
+        H2_HIP(hipMemcpyAsync(set_of.p, sets.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
+        z2idx.ensure((size_t)np * NZ, s);
+        z1idx.ensure((size_t)np * NZ, s);
+        zoff.ensure((size_t)np + 1, s);
+        xoff.ensure((size_t)np + 1, s);
+        mm.ensure(np, s);
+        k_lists<<<np, TB, 0, s>>>(np, set_of.p, zoff.p, z2idx.p, z1idx.p, xoff.p, mm.p);
+        H2_LAUNCH_CHECK();
+        const int rs = std::min(r, NZ);  // |Y*| <= min(r, 512)
+        ycnt.ensure(np, s);
+        yidx.ensure((size_t)np * rs, s);
+        datareduct_lists(Z.p, ld, d, zoff.p, z2idx.p, nullptr, np, r, yidx.p, rs, ycnt.p, s);
+        M.ensure((size_t)np * rs * NZ, s);
+        nu.ensure((size_t)np * 3 * NZ, s);
+        T.ensure((size_t)np * rs * NZ, s);
+        rank.ensure(np, s);
+        piv.ensure((size_t)np * NZ, s);
+        skel.ensure((size_t)np * rs, s);
+        err.ensure(np, s);
+        std::vector<int> ys_h = read_vec(ycnt.p, np, s);
+        std::vector<IdTask> tasks(np);
+        for (int p = 0; p < np; ++p) {
+            IdTask& t = tasks[p];
+            t.pts = Z.p;
+            t.ld = ld;
+            t.x_idx = z1idx.p + (int64_t)p * NZ;
+            t.y_idx = yidx.p + (int64_t)p * rs;
+            t.M = M.p + (int64_t)p * rs * NZ;
+            t.nu = nu.p + (int64_t)p * 3 * NZ;
+            t.piv = piv.p + (int64_t)p * NZ;
+            t.T = T.p + (int64_t)p * rs * NZ;
+            t.skel = skel.p + (int64_t)p * rs;
+            t.rank = rank.p + p;
+            t.prm = prms[sets[p]];
+            t.tol = 1e-3 * epss[sets[p]];
+            t.m = NZ;
+            t.s = ys_h[p];
+            t.d = d;
+            t.kid = kids[sets[p]];
+        }
+        batched_id(tasks, s);
+        part.ensure((size_t)np * ECB * 2, s);
+        k_err_part<<<np * ECB, TB, 0, s>>>(Z.p, ld, d, dkid.p, dprm.p, set_of.p, rank.p, piv.p, T.p,
+                                           (int64_t)rs * NZ, part.p);
+        H2_LAUNCH_CHECK();
+        k_err_final<<<blocks_for(np, 64), 64, 0, s>>>(np, part.p, err.p);
+        H2_LAUNCH_CHECK();
+        std::vector<double> e = read_vec(err.p, np, s);
+        for (int p = 0; p < np; ++p) {
+            int t = sets[p];
+            if (e[p] < 1e-2 * epss[t]) {
+                result[t] = r;
+                result_err[t] = e[p];
+                open[t] = 0;
+            } else if (r >= cap) {
+                result[t] = cap;
+                result_err[t] = e[p];
+                open[t] = 0;
+            }
         }
     }
-    const int nset = (int)depths.size();
-    int rmax = 1;
-    if (nset > 0) {
-        DBuf<double> dsides, Z;
-        dsides.ensure(nset, s);
-        H2_HIP(hipMemcpyAsync(dsides.p, sides.data(), sizeof(double) * nset, hipMemcpyHostToDevice, s));
-        const int64_t ld = (int64_t)nset * 2 * NZ;
-        Z.ensure((size_t)d * ld, s);
-        k_points<<<blocks_for(ld, TB), TB, 0, s>>>(nset, dsides.p, d, h.tau, h.calib_seed, Z.p);
-        H2_LAUNCH_CHECK();
+}
 
-        std::vector<int> open(nset, 1), result(nset, cap);
-        std::vector<double> result_err(nset, 0.0);
-        DBuf<int> set_of, z2idx, z1idx, mm, ycnt, yidx, rank, piv, skel;
-        DBuf<int64_t> zoff, xoff, yoff, Moff, nuoff, pivoff, Toff;
-        DBuf<double> M, nu, T, err, part;
-        for (int g = 1;; ++g) {
-            long long rr = 1;
-            for (int a = 0; a < d; ++a) rr *= g;
-            const int r = rr > cap ? cap : (int)rr;
-            std::vector<int> sets;
-            for (int t = 0; t < nset; ++t)
-                if (open[t]) sets.push_back(t);
-            if (sets.empty()) break;
-            const int np = (int)sets.size();
-            set_of.ensure(np, s);
-            H2_HIP(hipMemcpyAsync(set_of.p, sets.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
-            z2idx.ensure((size_t)np * NZ, s);
-            z1idx.ensure((size_t)np * NZ, s);
-            zoff.ensure((size_t)np + 1, s);
-            xoff.ensure((size_t)np + 1, s);
-            mm.ensure(np, s);
-            k_lists<<<np, TB, 0, s>>>(np, set_of.p, zoff.p, z2idx.p, z1idx.p, xoff.p, mm.p);
-            H2_LAUNCH_CHECK();
-            const int rs = std::min(r, NZ);  // |Y*| <= min(r, 512)
-            ycnt.ensure(np, s);
-            yidx.ensure((size_t)np * rs, s);
-            datareduct_lists(Z.p, ld, d, zoff.p, z2idx.p, nullptr, np, r, yidx.p, rs, ycnt.p, s);
-            // ID workspaces
-            std::vector<int64_t> h_yoff(np), h_Moff(np), h_nuoff(np), h_pivoff(np), h_Toff(np);
-            for (int p = 0; p < np; ++p) {
-                h_yoff[p] = (int64_t)p * rs;
-                h_Moff[p] = (int64_t)p * rs * NZ;
-                h_nuoff[p] = (int64_t)p * 3 * NZ;
-                h_pivoff[p] = (int64_t)p * NZ;
-                h_Toff[p] = (int64_t)p * rs * NZ;
-            }
-            auto up = [&](DBuf<int64_t>& dst, const std::vector<int64_t>& src) {
-                dst.ensure(src.size(), s);
-                H2_HIP(hipMemcpyAsync(dst.p, src.data(), sizeof(int64_t) * src.size(), hipMemcpyHostToDevice, s));
-            };
-            up(yoff, h_yoff);
-            up(Moff, h_Moff);
-            up(nuoff, h_nuoff);
-            up(pivoff, h_pivoff);
-            up(Toff, h_Toff);
-            M.ensure((size_t)np * rs * NZ, s);
-            nu.ensure((size_t)np * 3 * NZ, s);
-            T.ensure((size_t)np * rs * NZ, s);
-            rank.ensure(np, s);
-            piv.ensure((size_t)np * NZ, s);
-            skel.ensure((size_t)np * rs, s);
-            err.ensure(np, s);
-            IdBatch b;
-            b.nprob = np;
-            b.m = mm.p;
-            b.s = ycnt.p;
-            b.x_off = xoff.p;
-            b.x_idx = z1idx.p;
-            b.y_off = yoff.p;
-            b.y_idx = yidx.p;
-            b.xpts = Z.p;
-            b.xld = ld;
-            b.ypts = Z.p;
-            b.yld = ld;
-            b.M_off = Moff.p;
-            b.M = M.p;
-            b.nu = nu.p;
-            b.nu_off = nuoff.p;
-            b.tol = 1e-3 * eps;
-            b.rank_out = rank.p;
-            b.piv_out = piv.p;
-            b.piv_off = pivoff.p;
-            b.T_out = T.p;
-            b.T_off = Toff.p;
-            b.skel_out = skel.p;
-            b.skel_stride = rs;
-            std::vector<int> ys_h = read_vec(ycnt.p, np, s);
-            batched_id(b, std::vector<int>(np, NZ), ys_h, d, h.kid, h.prm, s);
-            part.ensure((size_t)np * ECB * 2, s);
-            k_err_part<<<np * ECB, TB, 0, s>>>(Z.p, ld, d, h.kid, h.prm, set_of.p, rank.p, piv.p, T.p,
-                                               (int64_t)rs * NZ, part.p);
-            H2_LAUNCH_CHECK();
-            k_err_final<<<blocks_for(np, 64), 64, 0, s>>>(np, part.p, err.p);
-            H2_LAUNCH_CHECK();
-            std::vector<double> e = read_vec(err.p, np, s);
-            for (int p = 0; p < np; ++p) {
-                int t = sets[p];
-                if (e[p] < 1e-2 * eps) {
-                    result[t] = r;
-                    result_err[t] = e[p];
-                    open[t] = 0;
-                } else if (r >= cap) {
-                    result[t] = cap;
-                    result_err[t] = e[p];
-                    open[t] = 0;
-                }
+// r1, r2 of several problems at once.  Each problem's sets (Coulomb: one set
+// of side 1; otherwise one per depth holding interaction-list pairs) are
+// pooled; identical sets (same d, tau, seed, kernel, parameter, side and
+// tolerance: e.g. every Coulomb problem at one tolerance) are calibrated once,
+// and all sets of one (d, tau, seed) share each round's launches.  Each
+// problem gets exactly the r it would get alone.
+void run_calibration_multi(const std::vector<Handle*>& hs, hipStream_t s)
+{
+    struct Key {
+        int d, kid;
+        double tau, prm, side, eps;
+        uint64_t seed;
+        bool operator<(const Key& o) const
+        {
+            return std::tie(d, tau, seed, kid, prm, side, eps) <
+                   std::tie(o.d, o.tau, o.seed, o.kid, o.prm, o.side, o.eps);
+        }
+    };
+    std::map<Key, int> uniq;
+    std::vector<Key> keys;
+    std::vector<std::vector<std::pair<int, int>>> uses;  // (depth, set) per problem
+    uses.resize(hs.size());
+    for (size_t p = 0; p < hs.size(); ++p) {
+        Handle& h = *hs[p];
+        h.calib_r.assign((size_t)h.maxdepth + 1, 0);
+        h.calib_err.assign((size_t)h.maxdepth + 1, 0.0);
+        if (h.r1 > 0 && h.r2 > 0) continue;
+        std::vector<std::pair<int, double>> ds;
+        if (h.kid == H2_COULOMB) {
+            ds.push_back({-1, 1.0});
+        } else {
+            std::vector<double> hside = read_vec(h.side.p, (size_t)h.nnode, s);
+            for (int L = 1; L <= h.maxdepth; ++L) {
+                bool has = false;
+                for (int i = h.lvl_ptr[L]; i < h.lvl_ptr[L + 1] && !has; ++i)
+                    has = h.h_il_ptr[i + 1] > h.h_il_ptr[i];
+                if (has) ds.push_back({L, hside[h.lvl_ptr[L]]});
             }
         }
-        for (int t = 0; t < nset; ++t) {
-            rmax = std::max(rmax, result[t]);
-            if (depths[t] < 0) {
+        for (auto& x : ds) {
+            Key k{h.d, h.kid, h.tau, h.kid == H2_COULOMB ? 1.0 : h.prm, x.second, h.tol_int, h.calib_seed};
+            auto it = uniq.find(k);
+            int id;
+            if (it == uniq.end()) {
+                id = (int)keys.size();
+                uniq[k] = id;
+                keys.push_back(k);
+            } else {
+                id = it->second;
+            }
+            uses[p].push_back({x.first, id});
+        }
+    }
+    std::vector<int> res(keys.size(), 0);
+    std::vector<double> res_err(keys.size(), 0.0);
+    // one calibration per (d, tau, seed) group
+    std::vector<int> done(keys.size(), 0);
+    for (size_t t0 = 0; t0 < keys.size(); ++t0) {
+        if (done[t0]) continue;
+        std::vector<int> grp;
+        for (size_t t = t0; t < keys.size(); ++t)
+            if (!done[t] && keys[t].d == keys[t0].d && keys[t].tau == keys[t0].tau && keys[t].seed == keys[t0].seed) {
+                grp.push_back((int)t);
+                done[t] = 1;
+            }
+        std::vector<double> sides, prms, epss;
+        std::vector<int> kids;
+        for (int t : grp) {
+            sides.push_back(keys[t].side);
+            prms.push_back(keys[t].prm);
+            epss.push_back(keys[t].eps);
+            kids.push_back(keys[t].kid);
+        }
+        std::vector<int> r;
+        std::vector<double> e;
+        calibrate_sets(keys[t0].d, keys[t0].tau, keys[t0].seed, sides, kids, prms, epss, r_cap(keys[t0].d), r, e,
+                       s);
+        for (size_t q = 0; q < grp.size(); ++q) {
+            res[grp[q]] = r[q];
+            res_err[grp[q]] = e[q];
+        }
+    }
+    for (size_t p = 0; p < hs.size(); ++p) {
+        Handle& h = *hs[p];
+        if (h.r1 > 0 && h.r2 > 0) continue;
+        int rmax = 1;
+        for (auto& u : uses[p]) {
+            const int r = res[u.second];
+            rmax = std::max(rmax, r);
+            if (u.first < 0) {
                 for (int L = 0; L <= h.maxdepth; ++L) {
-                    h.calib_r[L] = result[t];
-                    h.calib_err[L] = result_err[t];
+                    h.calib_r[L] = r;
+                    h.calib_err[L] = res_err[u.second];
                 }
             } else {
-                h.calib_r[depths[t]] = result[t];
-                h.calib_err[depths[t]] = result_err[t];
+                h.calib_r[u.first] = r;
+                h.calib_err[u.first] = res_err[u.second];
             }
         }
+        if (h.r1 <= 0) h.r1 = std::max(rmax, h.r_min);
+        if (h.r2 <= 0) h.r2 = std::max(rmax, h.r_min);
     }
-    if (h.r1 <= 0) h.r1 = std::max(rmax, h.r_min);
-    if (h.r2 <= 0) h.r2 = std::max(rmax, h.r_min);
 }
+
+void run_calibration(Handle& h) { run_calibration_multi({&h}, h.stream); }
 
 }  // namespace h2

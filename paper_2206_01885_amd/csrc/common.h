@@ -31,12 +31,16 @@ struct Error {
 inline void fail(int code, const std::string& m) { throw Error{code, m}; }
 
 // ------------------------------------------------------------------ device memory
-// Device allocations go through a small caching layer (alloc.hip): large
-// blocks are kept after release and handed out again to a request of a
-// similar size, so that repeated builds do not pay for mapping ~100 GB of
-// HBM each time.  On allocation failure the cache is emptied and the
-// allocation retried once; a second failure surfaces as H2_ENOMEM.
-void* dev_alloc(size_t bytes);
+// Device allocations go through a caching layer (alloc.hip): released
+// blocks are kept and handed out again (small ones per power-of-two class,
+// large ones to a request of a similar size), so that repeated builds pay
+// neither for mapping ~100 GB of HBM nor for the device-wide
+// synchronisation of hipFree.  A block reused on another stream than the one
+// that released it is ordered after that stream's work by an event.  On
+// allocation failure the cache is emptied and the allocation retried once; a
+// second failure surfaces as H2_ENOMEM.  `s` is the stream that will use the
+// block.
+void* dev_alloc(size_t bytes, hipStream_t s);
 // Returns a block; `s` is the stream whose work may still use it (waited for
 // before the block can be handed out again).
 void dev_free(void* p, size_t bytes, hipStream_t s);
@@ -66,7 +70,7 @@ struct DBuf {
         release();
         s = stream;
         size_t c = cnt ? cnt : 1;
-        p = (T*)dev_alloc(c * sizeof(T));
+        p = (T*)dev_alloc(c * sizeof(T), stream);
         n = c;
     }
     // Grow to at least cnt elements keeping the first `keep` elements.
@@ -75,7 +79,7 @@ struct DBuf {
         if (cnt <= n && p) return;
         size_t nc = n ? n : 16;
         while (nc < cnt) nc *= 2;
-        T* q = (T*)dev_alloc(nc * sizeof(T));
+        T* q = (T*)dev_alloc(nc * sizeof(T), stream);
         if (p && keep) H2_HIP(hipMemcpyAsync(q, p, keep * sizeof(T), hipMemcpyDeviceToDevice, stream));
         H2_HIP(hipStreamSynchronize(stream));
         release();
@@ -192,6 +196,7 @@ struct Handle {
 
     // matvec workspace (sized for the largest nrhs seen)
     int mv_ld = 0;  // column stride the apply buffers are sized for
+    std::vector<hipStream_t> mv_streams;  // other streams the apply ran on (waited for at destroy)
     DBuf<double> xt, yt, xh, yh;
     DBuf<float> xtf, ytf, xhf, yhf;
 
@@ -214,8 +219,10 @@ struct Handle {
 void build_tree(Handle& h, const double* pts_in);                // tree.hip
 void build_lists(Handle& h);                                      // lists.hip
 void run_calibration(Handle& h);                                  // calib.hip
+void run_calibration_multi(const std::vector<Handle*>& hs, hipStream_t s);  // calib.hip
 void run_hidr(Handle& h);                                         // hidr.hip
 void build_bases(Handle& h);                                      // basis.hip
+void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s);  // basis.hip
 void build_blocks(Handle& h);                                     // blocks.hip
 void prepare_apply(Handle& h);                                   // matvec.hip
 void matvec(Handle& h, const void* x, void* y, int nrhs, hipStream_t s);  // matvec.hip
@@ -232,32 +239,24 @@ void datareduct_lists(const double* pts, int64_t ld, int d, const int64_t* list_
 // Batched ID (basis.hip): one problem per entry.  Problem p has rows X
 // (m_p indices into pts) and columns Y (s_p indices into pts2); the kernel
 // matrix is evaluated and compressed with the column-pivoted QR rule.
-struct IdBatch {
-    int nprob = 0;
-    const int* m = nullptr;          // [nprob]
-    const int* s = nullptr;          // [nprob]
-    const int64_t* x_off = nullptr;  // [nprob] offsets into x_idx
-    const int* x_idx = nullptr;
-    const int64_t* y_off = nullptr;
-    const int* y_idx = nullptr;
-    const double* xpts = nullptr;  // SoA [d][xld]
-    int64_t xld = 0;
-    const double* ypts = nullptr;  // SoA [d][yld]
-    int64_t yld = 0;
-    const int64_t* M_off = nullptr;  // workspace offsets (s_p * m_p doubles each)
-    double* M = nullptr;
-    double* nu = nullptr;            // workspace, 2*m_p doubles per problem at nu_off
-    const int64_t* nu_off = nullptr;
-    double tol = 0;
-    int* rank_out = nullptr;         // [nprob]
-    int* piv_out = nullptr;          // at piv_off[p], m_p entries
-    const int64_t* piv_off = nullptr;
-    double* T_out = nullptr;         // at T_off[p]
-    const int64_t* T_off = nullptr;
-    int* skel_out = nullptr;         // at p*skel_stride, k_p entries (x indices)
-    int skel_stride = 0;
+// One ID problem (a node of a level, or a calibration set): the candidate
+// points x_idx[0..m) and reference points y_idx[0..s) index the SoA point
+// array pts ([d][ld]); outputs go to absolute device addresses, so one batch
+// may hold nodes of many independent problems.
+struct IdTask {
+    const double* pts = nullptr;
+    int64_t ld = 0;
+    const int* x_idx = nullptr;  // m entries
+    const int* y_idx = nullptr;  // s entries
+    double* M = nullptr;         // workspace, s*m doubles (unless the block fits LDS)
+    double* nu = nullptr;        // workspace, 3*m doubles
+    int* piv = nullptr;          // m entries
+    double* T = nullptr;         // k*(m-k) entries
+    int* skel = nullptr;         // k entries (x indices)
+    int* rank = nullptr;         // 1 entry
+    double prm = 1.0, tol = 0.0;
+    int m = 0, s = 0, d = 0, kid = 0;
 };
-void batched_id(const IdBatch& b, const std::vector<int>& m_host, const std::vector<int>& s_host, int d, int kid,
-                double prm, hipStream_t s);
+void batched_id(const std::vector<IdTask>& tasks, hipStream_t s);
 
 }  // namespace h2

@@ -53,8 +53,8 @@ class h2_info(C.Structure):
                 ("mv_scatter", C.c_double), ("mv_nrhs", C.c_int)]
 
 
-SYMBOLS = ["h2_options_default", "h2_build", "h2_build_ex", "h2_matvec", "h2_matvec_ex", "h2_query",
-           "h2_export", "h2_destroy", "h2_last_error"]
+SYMBOLS = ["h2_options_default", "h2_build", "h2_build_ex", "h2_build_batched", "h2_matvec", "h2_matvec_ex",
+           "h2_query", "h2_export", "h2_destroy", "h2_last_error"]
 
 _lib = None
 
@@ -74,6 +74,10 @@ def lib():
         L.h2_build_ex.restype = C.c_int
         L.h2_build_ex.argtypes = [vp, C.c_int64, C.c_int, C.c_int, dp, C.c_double, C.c_int,
                                   C.POINTER(h2_options), vp, C.POINTER(vp)]
+        ip = C.POINTER(C.c_int)
+        L.h2_build_batched.restype = C.c_int
+        L.h2_build_batched.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(C.c_int64), ip, ip, dp, dp, ip,
+                                       C.POINTER(h2_options), vp, C.POINTER(vp)]
         L.h2_matvec.restype = C.c_int
         L.h2_matvec.argtypes = [vp, vp, vp, C.c_int]
         L.h2_matvec_ex.restype = C.c_int
@@ -117,6 +121,26 @@ def h2_build(points_soa: torch.Tensor, kernel_id, params, tol, leaf_size, option
     _check(lib().h2_build_ex(C.c_void_p(points_soa.data_ptr()), n, dim, kid, prm, float(tol), int(leaf_size),
                              C.byref(opt), _stream_ptr(stream), C.byref(out)))
     return out
+
+
+def h2_build_batched(points_list, kernels, params, tols, leaf_sizes, options=None, stream=None):
+    """C ABI h2_build_batched: one contiguous float64 CUDA tensor [dim, n] per
+    problem; kernels, params, tols, leaf_sizes are per-problem sequences.
+    Returns the list of handles."""
+    k = len(points_list)
+    for P in points_list:
+        assert P.is_cuda and P.dtype == torch.float64 and P.is_contiguous()
+    ptrs = (C.c_void_p * k)(*[P.data_ptr() for P in points_list])
+    ns = (C.c_int64 * k)(*[P.shape[1] for P in points_list])
+    dims = (C.c_int * k)(*[P.shape[0] for P in points_list])
+    kids = (C.c_int * k)(*[KERNELS[x] if isinstance(x, str) else int(x) for x in kernels])
+    prms = (C.c_double * k)(*[float(x) for x in params])
+    tl = (C.c_double * k)(*[float(x) for x in tols])
+    lf = (C.c_int * k)(*[int(x) for x in leaf_sizes])
+    opt = options if options is not None else h2_options_default()
+    out = (C.c_void_p * k)()
+    _check(lib().h2_build_batched(k, ptrs, ns, dims, kids, prms, tl, lf, C.byref(opt), _stream_ptr(stream), out))
+    return [C.c_void_p(out[i]) for i in range(k)]
 
 
 def h2_matvec(handle, x: torch.Tensor, y: torch.Tensor, nrhs: int, stream=None):

@@ -229,3 +229,51 @@ def test_precision_mode_against_fp64_oracle(H, kernel, prm, d, n, leaf):
     err = max(_rel(y[r], yo[r]) for r in range(4))
     _say(f"precision32 max rel diff vs FP64 oracle {err:.3e}")
     assert err <= 1e-6
+
+
+def test_batched_build_equals_solo(H):
+    """h2_build_batched (nested bases of all problems in shared per-level
+    launches) gives every problem exactly what h2_build gives it alone, and
+    the solo result matches the oracle."""
+    import torch
+    rng = np.random.default_rng(2024)
+    specs = [(3000, 3, "coulomb", 1.0, "cube"), (5000, 3, "exponential", 0.2, "sphere"),
+             (2048, 2, "gaussian", 0.1, "cube"), (4000, 3, "matern32", 0.2, "cube"), (1, 3, "coulomb", 1.0, "cube"),
+             (700, 1, "exponential", 0.3, "cube")]
+    pts = []
+    for n, d, _, _, geo in specs:
+        P = rng.random((n, d))
+        if geo == "sphere":
+            v = rng.standard_normal((n, d))
+            P = v / np.linalg.norm(v, axis=1, keepdims=True)
+        pts.append(P)
+    soa = [torch.tensor(P.T.copy(), device="cuda") for P in pts]
+    _say("batched build of %d problems" % len(specs))
+    hs = H.h2_build_batched(soa, [s[2] for s in specs], [s[3] for s in specs], [1e-6] * len(specs),
+                            [64] * len(specs))
+    try:
+        for (n, d, k, prm, _), P, hb in zip(specs, pts, hs):
+            _say(f"batched vs solo {k}-d{d}-n{n}")
+            g = H.H2Matrix(P, k, prm, 1e-6, 64)
+            for name in ("perm", "il_col", "near_col", "rank", "mbar"):
+                a, b = H.h2_export(hb, name), g.export(name)
+                assert a.shape == b.shape and np.array_equal(a, b), name
+            for i in range(len(g.export("parent"))):
+                for name in ("piv", "skel", "T", "xstar", "ystar"):
+                    a, b = H.h2_export(hb, name, i), g.export(name, i)
+                    assert a.shape == b.shape and np.array_equal(a, b), (name, i)
+            nil = len(g.export("il_col"))
+            for e in range(0, nil, max(1, nil // 150)):
+                assert np.array_equal(H.h2_export(hb, "B", e), g.export("B", e)), ("B", e)
+            x = torch.tensor(rng.standard_normal((2, n)), device="cuda")
+            yb = torch.empty_like(x)
+            H.h2_matvec(hb, x, yb, 2)
+            yg = g.matvec(x)
+            torch.cuda.synchronize()
+            assert torch.equal(yb, yg)
+            if n == 3000:
+                o = O.H2Oracle(P, k, prm, tol=1e-6, leaf=64)
+                assert _rel(yg.cpu().numpy()[0], o.matvec(x.cpu().numpy()[0])) <= 1e-10
+    finally:
+        for hb in hs:
+            H.h2_destroy(hb)

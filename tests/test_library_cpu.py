@@ -64,3 +64,28 @@ def test_validation_without_device_work():
     assert L.h2_build_ex(dummy, 10, 3, 0, prm, 1e-6, 64, C.byref(opt), None, C.byref(out)) == h2.H2_EINVAL
     assert L.h2_matvec(None, dummy, dummy, 1) == h2.H2_EINVAL
     assert L.h2_destroy(None) == h2.H2_OK
+
+
+def test_batched_validation_without_device_work():
+    from paper_2206_01885_amd import h2
+    L = h2.lib()
+    k = 3
+    dummy = C.c_void_p(8)  # never dereferenced: validation fails first
+    pts = (C.c_void_p * k)(8, 16, 24)
+    ns = (C.c_int64 * k)(10, 20, 30)
+    dims = (C.c_int * k)(3, 3, 3)
+    kids = (C.c_int * k)(0, 1, 2)
+    prms = (C.c_double * k)(1.0, 0.1, 0.2)
+    tols = (C.c_double * k)(1e-6, 1e-6, 1e-6)
+    leaf = (C.c_int * k)(64, 64, 64)
+    out = (C.c_void_p * k)(1, 2, 3)
+    assert L.h2_build_batched(0, pts, ns, dims, kids, prms, tols, leaf, None, None, out) == h2.H2_EINVAL
+    tols[1] = 2.0  # problem 1 invalid
+    assert L.h2_build_batched(k, pts, ns, dims, kids, prms, tols, leaf, None, None, out) == h2.H2_EINVAL
+    assert all(v is None for v in out)
+    assert b"problem 1" in L.h2_last_error()
+    tols[1] = 1e-6
+    prms[2] = float("nan")
+    assert L.h2_build_batched(k, pts, ns, dims, kids, prms, tols, leaf, None, None, out) == h2.H2_EINVAL
+    assert b"problem 2" in L.h2_last_error()
+    assert L.h2_build_batched(k, None, ns, dims, kids, prms, tols, leaf, None, None, out) == h2.H2_EINVAL
