@@ -42,8 +42,11 @@ def parse():
     ap.add_argument("--rows", type=int, default=512, help="sampled rows for the dense accuracy check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=1 << 17, help="points of the oracle's bounded sample")
-    ap.add_argument("--workload", choices=["cube1m", "batched"], default="cube1m",
-                    help="cube1m: the headline n=2^20 Coulomb step; batched: 256 independent problems")
+    ap.add_argument("--workload", choices=["cube1m", "batched", "serving"], default="cube1m",
+                    help="cube1m: the headline n=2^20 Coulomb step; batched: 256 independent problems; "
+                         "serving: Poisson request stream")
+    ap.add_argument("--nreq", type=int, default=64, help="requests of the serving workload")
+    ap.add_argument("--load", type=float, default=0.5, help="serving: offered load as a fraction of saturation")
     ap.add_argument("--nprob", type=int, default=256, help="problems of the batched workload")
     return ap.parse_args()
 
@@ -140,6 +143,75 @@ def cpu_baseline(n, nrhs):
             "build_s": t1 - t0, "matvec_s": t2 - t1}
 
 
+def bench_serving(args):
+    """Request stream (n log-uniform in [1024, 2^20], 2-D or 3-D, cube or
+    Gaussian mixture, Coulomb / Gaussian 0.1 / exponential 0.2, tol 1e-6,
+    8 right-hand sides, FP32 precision mode), served by serving.Server:
+    (1) the plain path -- one FP64 h2_build + h2_matvec per request, one after
+    the other; (2) saturation -- all requests at t = 0; (3) Poisson arrivals at
+    `load` x the saturation rate.  Reports p50/p99 latency and solves/s."""
+    import torch
+    from paper_2206_01885_amd import h2, serving, workloads
+    torch.cuda.set_device(0)
+    cfg = workloads.serving_requests(nreq=args.nreq)
+    ntot = sum(int(c["points"].shape[0]) for c in cfg)
+    print(f"[bench] serving: {len(cfg)} requests, {ntot} points", file=sys.stderr, flush=True)
+
+    def fresh():
+        return [serving.Request(i, c["points"], c["kernel"], c["prm"], c["tol"], c["leaf"], c["x"])
+                for i, c in enumerate(cfg)]
+
+    # warm-up
+    serving.Server(max_batch=4, keep_outputs=False).run(fresh()[:4])
+    # (1) plain FP64 path, sequential
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat_plain = []
+    for c in cfg:
+        ts = time.perf_counter()
+        P = torch.tensor(np.ascontiguousarray(c["points"].T), device="cuda")
+        X = torch.tensor(c["x"], device="cuda")
+        hd = h2.h2_build(P, c["kernel"], c["prm"], c["tol"], c["leaf"])
+        Y = torch.empty_like(X)
+        h2.h2_matvec(hd, X, Y, X.shape[0])
+        torch.cuda.synchronize()
+        h2.h2_destroy(hd)
+        lat_plain.append(time.perf_counter() - ts)
+    wall_plain = time.perf_counter() - t0
+    print(f"[bench] plain FP64 loop {wall_plain:.2f} s", file=sys.stderr, flush=True)
+    # (2) saturation
+    reqs = fresh()
+    t0 = time.perf_counter()
+    serving.Server(keep_outputs=False).run(reqs)
+    wall_sat = time.perf_counter() - t0
+    sat = serving.summarize(reqs, wall_sat)
+    print(f"[bench] saturation {wall_sat:.2f} s", file=sys.stderr, flush=True)
+    # (3) Poisson arrivals at load x saturation
+    rate = args.load * sat["requests_per_s"]
+    rng = np.random.default_rng(1005)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(cfg))).tolist()
+    reqs = fresh()
+    t0 = time.perf_counter()
+    serving.Server(keep_outputs=False).run(reqs, arrivals)
+    wall_p = time.perf_counter() - t0
+    poi = serving.summarize(reqs, wall_p)
+    print(f"[bench] poisson {wall_p:.2f} s", file=sys.stderr, flush=True)
+    nrhs = sum(int(c["x"].shape[0]) for c in cfg)
+    out = {
+        "metric": "H2 serving: p50/p99 request latency and solves/s (build + 8-RHS apply per request)",
+        "value": sat["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1e3 * wall_sat, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serving-{len(cfg)}-requests-n1024-1048576-d2or3-tol1e-6-8rhs", "points": ntot},
+        "plain_fp64_loop": {"wall_s": wall_plain, "solves_per_s": nrhs / wall_plain,
+                            "p50_s": float(np.percentile(lat_plain, 50)),
+                            "p99_s": float(np.percentile(lat_plain, 99))},
+        "saturation": sat,
+        "poisson": dict(poi, offered_load=args.load, offered_requests_per_s=rate),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -148,6 +220,9 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "serving":
+        bench_serving(args)
         return
     import torch
     from paper_2206_01885_amd import h2

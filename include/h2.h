@@ -181,7 +181,9 @@ enum {
 };
 h2_status h2_export(h2_handle h, int what, int node, void *host_buf, size_t bytes, int64_t *count);
 
-/* Release a handle and all its device memory.  NULL is accepted. */
+/* Release a handle and all its device memory.  NULL is accepted.  Waits for
+ * the handle's last h2_matvec (on whatever stream it ran) to finish, not for
+ * other work on those streams; the memory returns to the library's cache. */
 h2_status h2_destroy(h2_handle h);
 
 /* Message of the last non-OK status returned on this thread. */

@@ -97,10 +97,18 @@ void* dev_alloc(size_t bytes, hipStream_t s)
     return p;
 }
 
+thread_local int g_idle = 0;
+IdleFree::IdleFree() { ++g_idle; }
+IdleFree::~IdleFree() { --g_idle; }
+
 void dev_free(void* p, size_t bytes, hipStream_t s)
 {
     if (!p) return;
     std::lock_guard<std::mutex> lk(g_mu);
+    if (g_idle) {
+        g_cache.push_back({p, class_bytes(bytes), nullptr, nullptr});
+        return;
+    }
     hipEvent_t e = take_event();
     if (e && hipEventRecord(e, s) != hipSuccess) {
         (void)hipGetLastError();

@@ -309,9 +309,9 @@ h2_status h2_matvec_ex(h2_handle hd, const void* x, void* y, int nrhs, void* hip
     if (!(xb + bytes <= yb || yb + bytes <= xb)) return set_err(H2_EINVAL, "x and y overlap");
     try {
         hipStream_t ms = (hipStream_t)hip_stream;
-        if (ms != h.stream && std::find(h.mv_streams.begin(), h.mv_streams.end(), ms) == h.mv_streams.end())
-            h.mv_streams.push_back(ms);
         h2::matvec(h, x, y, nrhs, ms);
+        if (!h.mv_done) H2_HIP(hipEventCreateWithFlags(&h.mv_done, hipEventDisableTiming));
+        H2_HIP(hipEventRecord(h.mv_done, ms));
     } catch (const h2::Error& e) {
         return set_err(e.code, e.msg);
     }
@@ -456,11 +456,18 @@ h2_status h2_export(h2_handle hd, int what, int node, void* host_buf, size_t byt
 h2_status h2_destroy(h2_handle hd)
 {
     if (!hd) return H2_OK;
-    (void)hipStreamSynchronize(hd->h.stream);
-    for (hipStream_t ms : hd->h.mv_streams) (void)hipStreamSynchronize(ms);
+    // the build finished before it returned; wait for the last apply only
+    // (not for whatever else its stream is running), then release the
+    // buffers as idle
+    if (hd->h.mv_done) (void)hipEventSynchronize(hd->h.mv_done);
     for (auto& e : hd->h.ev)
         if (e) (void)hipEventDestroy(e);
-    delete hd;
+    hipEvent_t md = hd->h.mv_done;
+    {
+        h2::IdleFree idle;
+        delete hd;
+    }
+    if (md) (void)hipEventDestroy(md);
     return H2_OK;
 }
 

@@ -46,6 +46,13 @@ void* dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void* p, size_t bytes, hipStream_t s);
 // Releases every cached block back to the runtime.
 void dev_cache_trim();
+// While an IdleFree object lives on this thread, dev_free takes the released
+// blocks as idle (the caller has waited for all work on them): they are
+// reused without ordering against the stream that allocated them.
+struct IdleFree {
+    IdleFree();
+    ~IdleFree();
+};
 
 // A plain owning device buffer.
 template <class T>
@@ -196,7 +203,7 @@ struct Handle {
 
     // matvec workspace (sized for the largest nrhs seen)
     int mv_ld = 0;  // column stride the apply buffers are sized for
-    std::vector<hipStream_t> mv_streams;  // other streams the apply ran on (waited for at destroy)
+    hipEvent_t mv_done = nullptr;  // recorded after every apply (waited for at destroy)
     DBuf<double> xt, yt, xh, yh;
     DBuf<float> xtf, ytf, xhf, yhf;
 

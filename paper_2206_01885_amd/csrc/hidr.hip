@@ -254,8 +254,10 @@ __global__ __launch_bounds__(TB) void k_datareduct(const double* __restrict__ pt
 // equal ones -- whatever the scan order; the box nearest to q is scanned
 // first so that the bound prunes well.
 // The interaction-list table (box centre, half side, count, list offset) and
-// (up to YCAP points) the coordinates of Y_p^* are staged in LDS; interaction
-// lists longer than ILCAP entries are rejected on the host (see run_hidr).
+// (up to YCAP points) the coordinates of Y_p^* are staged in LDS; nodes with
+// more than ILCAP interaction-list entries are skipped here and reduced from
+// their materialised T_i by k_datareduct (same reference set, distances, tie
+// rule and output).
 constexpr int ILCAP = 640;  // interaction-list entries staged per node
 constexpr int YCAP = 1024;  // Y_p^* points staged per node
 constexpr int PB = 8;       // candidate loads issued ahead
@@ -297,6 +299,7 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     const int np_ = p > 0 ? ys_cnt[p] : 0;
     const int* yp = ys_idx + (int64_t)(p > 0 ? p : 0) * ys_stride;
     const int e0 = il_ptr[i], ne = il_ptr[i + 1] - e0;
+    if (ne > ILCAP) return;  // handled by the materialised path
     int* o = ys_idx + (int64_t)i * ys_stride;
 
     // interaction-list table and its exclusive prefix of counts
@@ -536,6 +539,55 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     if (threadIdx.x == TB - 1) ys_cnt[i] = scan_sh[TB - 1];
 }
 
+// ---- T_i = Y_p^* ++ X_j^* (j in IL(i)) materialised for the nodes with long
+// interaction lists; split = |Y_p^*| marks the two parts
+__global__ __launch_bounds__(TB) void k_down_sizes(int nl, const int* __restrict__ nodes, const int* __restrict__ parent,
+                                                   const int* __restrict__ il_ptr, const int* __restrict__ il_col,
+                                                   const int* __restrict__ xs_cnt, const int* __restrict__ ys_cnt,
+                                                   int64_t* __restrict__ sz, int* __restrict__ split)
+{
+    int t = blockIdx.x * TB + threadIdx.x;
+    if (t >= nl) return;
+    const int i = nodes[t], p = parent[i];
+    const int np_ = p > 0 ? ys_cnt[p] : 0;
+    int64_t v = np_;
+    for (int e = il_ptr[i]; e < il_ptr[i + 1]; ++e) v += xs_cnt[il_col[e]];
+    sz[t] = v;
+    split[t] = np_;
+}
+
+__global__ __launch_bounds__(TB) void k_down_fill(const int* __restrict__ nodes, const int* __restrict__ parent,
+                                                  const int* __restrict__ il_ptr, const int* __restrict__ il_col,
+                                                  const int* __restrict__ xs_cnt, const int* __restrict__ xs_idx,
+                                                  int r1, const int* __restrict__ ys_cnt,
+                                                  const int* __restrict__ ys_idx, int ys_stride,
+                                                  const int64_t* __restrict__ off, int* __restrict__ list)
+{
+    const int t = blockIdx.x;
+    const int i = nodes[t], p = parent[i];
+    int* o = list + off[t];
+    int64_t w = 0;
+    if (p > 0) {
+        const int np_ = ys_cnt[p];
+        for (int q = threadIdx.x; q < np_; q += TB) o[q] = ys_idx[(int64_t)p * ys_stride + q];
+        w = np_;
+    }
+    for (int e = il_ptr[i]; e < il_ptr[i + 1]; ++e) {
+        const int j = il_col[e], c = xs_cnt[j];
+        for (int q = threadIdx.x; q < c; q += TB) o[w + q] = xs_idx[(int64_t)j * r1 + q];
+        w += c;
+    }
+}
+
+__global__ __launch_bounds__(TB) void k_rows_scatter(const int* __restrict__ nodes, const int* __restrict__ cnt,
+                                                     const int* __restrict__ src, int stride, int* __restrict__ dst_cnt,
+                                                     int* __restrict__ dst)
+{
+    const int t = blockIdx.x, i = nodes[t], c = cnt[t];
+    for (int q = threadIdx.x; q < c; q += TB) dst[(int64_t)i * stride + q] = src[(int64_t)t * stride + q];
+    if (threadIdx.x == 0) dst_cnt[i] = c;
+}
+
 // ---- list materialisation for one level of HiDR
 __global__ __launch_bounds__(TB) void k_up_sizes(int lo, int nl, const int* __restrict__ nchild,
                                                  const int* __restrict__ first_child, const int* __restrict__ count,
@@ -641,12 +693,34 @@ void run_hidr(Handle& h)
                          h.r1, h.xs_cnt.p + lo, s);
     }
     if (h.r2 < 1 || h.r2 > MAXQ_ALL / 2) fail(H2_EUNSUPPORTED, "r2 must be in [1, 2048]");
-    for (int i = 0; i < nn; ++i)
-        if (h.h_il_ptr[i + 1] - h.h_il_ptr[i] > ILCAP)
-            fail(H2_EUNSUPPORTED, "interaction list longer than " + std::to_string(ILCAP) + " entries");
+    DBuf<int> lnodes, split, tmp, tmp_cnt;
     for (int L = 1; L <= h.maxdepth; ++L) {
         int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
         launch_down(h, lo, nl, s);
+        H2_LAUNCH_CHECK();
+        std::vector<int> longn;
+        for (int i = lo; i < lo + nl; ++i)
+            if (h.h_il_ptr[i + 1] - h.h_il_ptr[i] > ILCAP) longn.push_back(i);
+        if (longn.empty()) continue;
+        const int nlong = (int)longn.size();
+        lnodes.ensure((size_t)nlong, s);
+        H2_HIP(hipMemcpyAsync(lnodes.p, longn.data(), sizeof(int) * nlong, hipMemcpyHostToDevice, s));
+        sz.ensure((size_t)nlong, s);
+        off.ensure((size_t)nlong + 1, s);
+        split.ensure((size_t)nlong, s);
+        k_down_sizes<<<blocks_for(nlong, TB), TB, 0, s>>>(nlong, lnodes.p, h.parent.p, h.il_ptr.p, h.il_col.p,
+                                                          h.xs_cnt.p, h.ys_cnt.p, sz.p, split.p);
+        H2_LAUNCH_CHECK();
+        scan_excl_i64(sz.p, off.p, nlong, h.tmp_i64, s);
+        int64_t tot = read_scalar(off.p + nlong, s);
+        list.ensure((size_t)std::max<int64_t>(tot, 1), s);
+        k_down_fill<<<nlong, TB, 0, s>>>(lnodes.p, h.parent.p, h.il_ptr.p, h.il_col.p, h.xs_cnt.p, h.xs_idx.p, h.r1,
+                                         h.ys_cnt.p, h.ys_idx.p, h.ys_stride, off.p, list.p);
+        H2_LAUNCH_CHECK();
+        tmp.ensure((size_t)nlong * h.ys_stride, s);
+        tmp_cnt.ensure((size_t)nlong, s);
+        datareduct_lists(h.pts.p, h.n, h.d, off.p, list.p, split.p, nlong, h.r2, tmp.p, h.ys_stride, tmp_cnt.p, s);
+        k_rows_scatter<<<nlong, TB, 0, s>>>(lnodes.p, tmp_cnt.p, tmp.p, h.ys_stride, h.ys_cnt.p, h.ys_idx.p);
         H2_LAUNCH_CHECK();
     }
     H2_HIP(hipStreamSynchronize(s));

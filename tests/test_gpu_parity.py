@@ -277,3 +277,46 @@ def test_batched_build_equals_solo(H):
     finally:
         for hb in hs:
             H.h2_destroy(hb)
+
+
+def test_serving_mix_equals_solo(H):
+    """The serving loop (admission, batched builds of the requests that are
+    waiting, applies overlapped on a second stream) returns for every
+    request what a solo build + apply returns, within the FP32 tolerance."""
+    import torch
+    from paper_2206_01885_amd import serving, workloads
+    reqs_cfg = workloads.serving_requests(seed=77, nreq=6, nmin=1024, nmax=6000)
+    reqs = [serving.Request(i, c["points"], c["kernel"], c["prm"], c["tol"], c["leaf"], c["x"])
+            for i, c in enumerate(reqs_cfg)]
+    # small budget: forces admission to wait for memory part of the time
+    srv = serving.Server(hbm_budget=3 * serving.estimate_bytes(6000, 3), max_batch=4)
+    arrivals = [0.0, 0.0, 0.01, 0.02, 0.2, 0.21]
+    _say("serving 6 requests")
+    srv.run(reqs, arrivals)
+    for r in reqs:
+        assert r.t_done is not None and r.t_done >= r.t_arrive
+        g = H.H2Matrix(r.points, r.kernel, r.prm, r.tol, r.leaf, precision=32)
+        ys = g.matvec(r.x.astype(np.float32)).cpu().numpy()
+        g.close()
+        diff = np.linalg.norm(ys - r.y) / np.linalg.norm(ys)
+        _say(f"serving request {r.idx} n={r.points.shape[0]} diff vs solo {diff:.2e}")
+        assert diff <= 1e-6
+
+
+def test_long_interaction_lists(H):
+    """Clustered points (8-component Gaussian mixture, leaf 8) give nodes with
+    more than 640 interaction-list entries, which take the materialised HiDR
+    path: Y* stays identical to the oracle's and the product within 1e-10."""
+    from paper_2206_01885_amd import workloads as W
+    rng = np.random.default_rng(6)
+    P = W.gauss_mixture(rng, 30000, 3)
+    _say("long IL gauss-mixture n=30000 leaf 8")
+    g = H.H2Matrix(P, "coulomb", 1.0, 1e-6, 8, r1=27, r2=27)
+    o = O.H2Oracle(P, "coulomb", 1.0, tol=1e-6, leaf=8, r1=27, r2=27)
+    ptr = g.export("il_ptr")
+    longn = np.nonzero(np.diff(ptr) > 640)[0]
+    assert len(longn) > 0
+    for i in list(longn) + list(range(0, len(ptr) - 1, 97)):
+        assert np.array_equal(g.export("ystar", int(i)), o.node_list("ystar", int(i))), i
+    x = np.random.default_rng(1).standard_normal(30000)
+    assert _rel(g.matvec(x).cpu().numpy(), o.matvec(x)) <= 1e-10
