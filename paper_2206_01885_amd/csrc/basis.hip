@@ -135,8 +135,127 @@ __device__ __forceinline__ double axpy_rows(const double* __restrict__ v, double
 // NT = 64 (one wavefront, for row sets of at most 64 points) or 256 lanes.
 // LDSM: the s x m block lives in LDS (dynamic shared memory after the
 // reflector), otherwise in the global workspace.  The arithmetic is the same.
+// Compression (s > m): the s x m block is streamed in blocks of BR rows and
+// folded into the m x m upper triangle R (LDS or global) by Householder
+// reflectors that each zero one column of the block against the diagonal
+// entry of R (TSQR).  Lane l owns columns l, l + NT, ... (CPL of them) and
+// keeps their BR block entries in registers, evaluating them itself; the
+// column that step j eliminates is published in a double-buffered LDS slot
+// by its owner at the end of step j - 1, so one barrier per step suffices.
+// The R entries of the next row are loaded a step ahead.  (This part
+// accumulates with fused multiply-adds; it is not the oracle's operation
+// order, and need not be: pivots and T are fixed up to rounding.)
+template <int NT, int CPL, int BR>
+__device__ void tsqr_fold(const IdTask& tk, int m, int s0, double* R, double* colbuf, double* nubuf, double* scr)
+{
+    const double* pts = tk.pts;
+    const int64_t ld = tk.ld;
+    const int* xi = tk.x_idx;
+    const int* yi = tk.y_idx;
+    const int d = tk.d, kid = tk.kid;
+    const double prm = tk.prm;
+    const int lane = threadIdx.x;
+    for (int64_t e = lane; e < (int64_t)m * m; e += NT) R[e] = 0.0;
+    __syncthreads();
+    double bc[CPL][BR], tail[CPL];
+    for (int r0 = 0; r0 < s0; r0 += BR) {
+        const int nb = min(BR, s0 - r0);
+        // this lane's block entries (evaluated through a lane-private LDS
+        // slice, scr[r * NT + lane]) and their squared sums
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+            const int c = lane + t * NT;
+            if (c < m) {
+                const int xc = xi[c];
+                for (int r = 0; r < nb; ++r)
+                    scr[r * NT + lane] = kappa_r2(kid, prm, dist2(pts, ld, xc, pts, ld, yi[r0 + r], d));
+            }
+            tail[t] = 0.0;
+#pragma unroll
+            for (int r = 0; r < BR; ++r) {
+                const double v = (c < m && r < nb) ? scr[r * NT + lane] : 0.0;
+                bc[t][r] = v;
+                tail[t] = __builtin_fma(v, v, tail[t]);
+            }
+        }
+        // publish column 0
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < BR; ++r) colbuf[r] = bc[0][r];
+            nubuf[0] = tail[0];
+        }
+        double rn[CPL];
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+            const int c = lane + t * NT;
+            rn[t] = c < m ? R[c] : 0.0;
+        }
+        __syncthreads();
+        for (int j = 0; j < m; ++j) {
+            const double* cj = colbuf + (j & 1) * BR;
+            const double nub = nubuf[j & 1];
+            double rc[CPL];
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+                rc[t] = rn[t];
+                const int c = lane + t * NT;
+                rn[t] = (c < m && j + 1 < m) ? R[(int64_t)(j + 1) * m + c] : 0.0;
+            }
+            if (nub != 0.0) {
+                const double x0 = R[(int64_t)j * m + j];
+                const double alpha = x0 >= 0.0 ? -sqrt(x0 * x0 + nub) : sqrt(x0 * x0 + nub);
+                const double v0 = x0 - alpha;
+                const double vtv = 2.0 * fabs(alpha) * (fabs(alpha) + fabs(x0));
+                double cjr[BR];
+#pragma unroll
+                for (int r = 0; r < BR; ++r) cjr[r] = cj[r];
+#pragma unroll
+                for (int t = 0; t < CPL; ++t) {
+                    const int c = lane + t * NT;
+                    if (c > j && c < m) {
+                        double w = v0 * rc[t];
+#pragma unroll
+                        for (int r = 0; r < BR; ++r) w = __builtin_fma(cjr[r], bc[t][r], w);
+                        const double f = 2.0 * w / vtv;
+                        R[(int64_t)j * m + c] = rc[t] - f * v0;
+                        double ts = 0.0;
+#pragma unroll
+                        for (int r = 0; r < BR; ++r) {
+                            bc[t][r] = __builtin_fma(-f, cjr[r], bc[t][r]);
+                            ts = __builtin_fma(bc[t][r], bc[t][r], ts);
+                        }
+                        tail[t] = ts;
+                    }
+                }
+                if (lane == j % NT) R[(int64_t)j * m + j] = alpha;
+            }
+            // the owner of column j + 1 publishes it for the next step
+            if (j + 1 < m && lane == (j + 1) % NT) {
+                const int t1 = (j + 1) / NT;
+                double* nb1 = colbuf + ((j + 1) & 1) * BR;
+#pragma unroll
+                for (int t = 0; t < CPL; ++t)
+                    if (t == t1) {
+#pragma unroll
+                        for (int r = 0; r < BR; ++r) nb1[r] = bc[t][r];
+                        nubuf[(j + 1) & 1] = tail[t];
+                    }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// NT = 64 (one wavefront; the matrix in LDS) or 256 lanes (global matrix).
+// LDSM: the matrix the pivoted QR runs on lives in LDS (dynamic shared
+// memory after the reflector), otherwise in the global workspace.  With
+// s > m the s x m kernel block is first compressed to its m x m R factor
+// (tsqr_fold): column pivoting sees only the partial column norms, which a
+// left orthogonal factor does not change, so the pivots, |R_jj| and T are
+// those of the s x m block up to rounding.
 template <int NT, bool LDSM>
-__global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ tasks, const int* __restrict__ order)
+__global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ tasks, const int* __restrict__ order,
+                                                   int bmax)
 {
     extern __shared__ double dyn[];
     __shared__ double redd[4];
@@ -144,14 +263,16 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
     __shared__ double sh_alpha;
 
     const IdTask& tk = tasks[order[blockIdx.x]];
-    const int m = tk.m, s = tk.s, d = tk.d, kid = tk.kid;
+    const int m = tk.m, s0 = tk.s, d = tk.d, kid = tk.kid;
     const double prm = tk.prm, tol = tk.tol;
     int* piv = tk.piv;
     for (int c = threadIdx.x; c < m; c += NT) piv[c] = c;
-    if (m == 0 || s == 0) {
+    if (m == 0 || s0 == 0) {
         if (threadIdx.x == 0) *tk.rank = 0;
         return;
     }
+    const bool comp = s0 > m && m <= (NT == 64 ? 64 : 4 * NT);
+    const int s = comp ? m : s0;  // rows of the matrix the pivoted QR runs on
     double* v = dyn;
     double* M = LDSM ? dyn + s : tk.M;
     double* nu = tk.nu;
@@ -159,16 +280,24 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
     double* ss = nu + 2 * m;
     const int* xi = tk.x_idx;
     const int* yi = tk.y_idx;
-    const double* pts = tk.pts;
-    const int64_t ld = tk.ld;
 
-    // kernel block: M[r][c] = kappa(x_c, y_r)
-    for (int64_t e = threadIdx.x; e < (int64_t)s * m; e += NT) {
-        int r = (int)(e / m), c = (int)(e - (int64_t)r * m);
-        double r2 = dist2(pts, ld, xi[c], pts, ld, yi[r], d);
-        M[e] = kappa_r2(kid, prm, r2);
+    if (comp) {
+        // the published column lives after the LDS matrix, or over the (not
+        // yet used) reflector space
+        double* cb = LDSM ? dyn + s + (int64_t)s * m : dyn;
+        if constexpr (NT == 64)
+            tsqr_fold<NT, 1, 16>(tk, m, s0, M, cb, cb + 32, cb + 34);
+        else
+            tsqr_fold<NT, 4, 16>(tk, m, s0, M, cb, cb + 32, cb + 34);
+    } else {
+        // kernel block: M[r][c] = kappa(x_c, y_r)
+        for (int64_t e = threadIdx.x; e < (int64_t)s * m; e += NT) {
+            int r = (int)(e / m), c = (int)(e - (int64_t)r * m);
+            double r2 = dist2(tk.pts, tk.ld, xi[c], tk.pts, tk.ld, yi[r], d);
+            M[e] = kappa_r2(kid, prm, r2);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     for (int c = threadIdx.x; c < m; c += NT) {
         double acc = sumsq_rows(M + c, m, 0, s, 0.0);
         ss[c] = acc;
@@ -300,25 +429,40 @@ void batched_id(const std::vector<IdTask>& tasks, hipStream_t s)
 {
     const int np = (int)tasks.size();
     if (np <= 0) return;
-    // class 0: one wavefront, block in LDS; 1: one wavefront, global block;
-    // 2: four wavefronts, global block
-    const int LDS_DOUBLES = 8192;  // 64 KiB per workgroup
+    // class 0 / 3: one wavefront, matrix (and the compression's row block)
+    // in LDS; 1: one wavefront, global matrix; 2: four wavefronts, global
+    // matrix (the compression's row block in LDS)
+    const int BROWS = 64;                 // compression row block (at most)
+    const size_t LDS_CAP = 80 * 1024;     // bytes per workgroup
+    auto lds_need = [&](const IdTask& t, int c) -> size_t {
+        const bool comp = t.s > t.m && t.m <= (c == 2 ? 4 * TB : 64);
+        const int sr = comp ? t.m : t.s;
+        // published column (2 x 16) + its two norms + the lanes' evaluation slices
+        const size_t pub = comp ? 34 + (size_t)16 * (c == 2 ? TB : 64) : 0;
+        if (c == 0) return ((size_t)sr + (size_t)sr * t.m + pub) * sizeof(double);
+        return std::max((size_t)sr, pub) * sizeof(double);
+    };
+    // class 0 is split by LDS size (0: up to 32 KiB, 3: more) so that small
+    // problems are not limited to the occupancy of the largest
     std::vector<int> cls(np);
     for (int p = 0; p < np; ++p) {
-        int64_t need = (int64_t)tasks[p].s * (tasks[p].m + 1);
-        cls[p] = tasks[p].m <= 64 ? (need <= LDS_DOUBLES ? 0 : 1) : 2;
+        if (tasks[p].m > 64) {
+            cls[p] = 2;
+        } else {
+            const size_t need = lds_need(tasks[p], 0);
+            cls[p] = need <= 32 * 1024 ? 0 : (need <= LDS_CAP ? 3 : 1);
+        }
     }
     std::vector<int> order;
     order.reserve(np);
-    int cnt[3] = {0, 0, 0};
-    size_t lds[3] = {8, 8, 8};
-    for (int c = 0; c < 3; ++c)
+    int cnt[4] = {0, 0, 0, 0};
+    size_t lds[4] = {8, 8, 8, 8};
+    for (int c = 0; c < 4; ++c)
         for (int p = 0; p < np; ++p)
             if (cls[p] == c) {
                 order.push_back(p);
                 ++cnt[c];
-                size_t need = (size_t)tasks[p].s * (c == 0 ? tasks[p].m + 1 : 1) * sizeof(double);
-                lds[c] = std::max(lds[c], need);
+                lds[c] = std::max(lds[c], lds_need(tasks[p], c == 3 ? 0 : c));
             }
     DBuf<IdTask> d_tasks;
     DBuf<int> d_order;
@@ -328,17 +472,22 @@ void batched_id(const std::vector<IdTask>& tasks, hipStream_t s)
     H2_HIP(hipMemcpyAsync(d_order.p, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s));
     int o = 0;
     if (cnt[0] > 0) {
-        k_batched_id<64, true><<<cnt[0], 64, lds[0], s>>>(d_tasks.p, d_order.p + o);
+        k_batched_id<64, true><<<cnt[0], 64, lds[0], s>>>(d_tasks.p, d_order.p + o, BROWS);
         H2_LAUNCH_CHECK();
     }
     o += cnt[0];
     if (cnt[1] > 0) {
-        k_batched_id<64, false><<<cnt[1], 64, lds[1], s>>>(d_tasks.p, d_order.p + o);
+        k_batched_id<64, false><<<cnt[1], 64, lds[1], s>>>(d_tasks.p, d_order.p + o, BROWS);
         H2_LAUNCH_CHECK();
     }
     o += cnt[1];
     if (cnt[2] > 0) {
-        k_batched_id<TB, false><<<cnt[2], TB, lds[2], s>>>(d_tasks.p, d_order.p + o);
+        k_batched_id<TB, false><<<cnt[2], TB, lds[2], s>>>(d_tasks.p, d_order.p + o, BROWS);
+        H2_LAUNCH_CHECK();
+    }
+    o += cnt[2];
+    if (cnt[3] > 0) {
+        k_batched_id<64, true><<<cnt[3], 64, lds[3], s>>>(d_tasks.p, d_order.p + o, BROWS);
         H2_LAUNCH_CHECK();
     }
     H2_HIP(hipStreamSynchronize(s));

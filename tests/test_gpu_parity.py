@@ -99,7 +99,9 @@ def test_small_coulomb_full_parity(H):
     _say("cube3d-coulomb-n4096 build")
     g, o = _build(H, c["points"], c["kernel"], c["prm"], c["tol"], c["leaf"])
     _compare_structure(g, o)
-    _compare_reduction_and_bases(g, o, t_rtol=0.0)
+    # pivots, ranks and skeletons exactly; T up to the rounding of the
+    # compressed (m x m triangle) pivoted QR the GPU runs when s > m
+    _compare_reduction_and_bases(g, o)
     _say("cube3d-coulomb-n4096 matvec")
     yg = g.matvec(c["x"]).cpu().numpy()
     yo = o.matvec(c["x"])
