@@ -8,9 +8,12 @@ coupling and nearfield blocks) followed by one h2_matvec with 32 RHS, then
 h2_destroy.  Inputs are resident in HBM before the timed region starts.
 
 Printed: one JSON line with the whole-step throughput (Mpts/s), the build and
-apply figures, the roofline of the dominant kernel (coupling sweep of the
-apply, HIP events on the apply's stream), the sampled accuracy against the
-dense K x, and the CPU oracle timed on a bounded sample of the same workload.
+apply figures, the roofline of the dominant kernel of the step (the batched
+interpolative decomposition of the wide nodes, k_batched_id<256>: FP64 vector
+ALU bound; HIP events on the build's stream), the same for the apply's
+coupling sweep (k_sweep, HBM bound; HIP events on the apply's stream), the
+sampled accuracy against the dense K x, and the CPU oracle timed on a bounded
+sample of the same workload.
 """
 from __future__ import annotations
 
@@ -26,6 +29,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def id_roofline(flops, ms, kernel):
+    """Algorithmic FP64 flops of the pivoted-QR IDs over the event-timed
+    duration of their launches."""
+    achieved = flops / (ms / 1e3) / 1e12 if ms > 0 else 0.0
+    return {"kernel": kernel, "bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+            "flops_per_step": flops, "ms_per_step": ms}
 
 
 def parse():
@@ -67,6 +81,7 @@ def bench_batched(args):
     leaves = [p["leaf"] for p in probs]
     ntot = sum(int(p["points"].shape[0]) for p in probs)
     opt = h2.h2_options_default()
+    opt.profile = 1
     print(f"[bench] batched: {len(probs)} problems, {ntot} points", file=sys.stderr, flush=True)
     # warm-up: a few problems each way
     hs = h2.h2_build_batched(soa[:4], ks[:4], prms[:4], tols[:4], leaves[:4], opt)
@@ -99,6 +114,9 @@ def bench_batched(args):
     phases = {f: float(np.sum([i[f] for i in info])) for f in ("t_tree", "t_lists", "t_hidr", "t_blocks")}
     phases["t_calib_shared"] = info[0]["t_calib"]
     phases["t_basis_shared"] = info[0]["t_basis"]
+    # the ID launches are shared by all problems: their time once, their flops summed
+    roof = id_roofline(float(np.sum([i["id_flops"] for i in info])), info[0]["id_ms"],
+                       "k_batched_id (all classes, the batched interpolative decompositions)")
     out = {
         "metric": "batched H2 build Mpts/s (256 independent problems in one h2_build_batched call)",
         "value": ntot / tb / 1e6, "unit": "Mpts/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
@@ -107,6 +125,7 @@ def bench_batched(args):
         "config": {"workload": f"batched-{len(probs)}-problems-n2048-32768-leaf64-tol1e-6", "points": ntot},
         "loop_ms_per_step": 1e3 * tl, "loop_mpts_s": ntot / tl / 1e6, "speedup_vs_loop": tl / tb,
         "phases_s_sum_over_problems": phases,
+        "roofline": roof,
     }
     print(json.dumps(out), flush=True)
 
@@ -257,7 +276,7 @@ def main():
         h2.h2_destroy(hd)
         print(f"[bench] warmup {w} done", file=sys.stderr, flush=True)
 
-    builds, mvs, coup = [], [], []
+    builds, mvs, coup, idw = [], [], [], []
     keep = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -270,6 +289,7 @@ def main():
         builds.append(tb - ts)
         mvs.append(te - tb)
         coup.append(info["mv_coupling"] / 1e3)
+        idw.append((info["id_wide_flops"], info["id_wide_ms"], info["id_flops"], info["id_ms"]))
         if k == args.steps - 1:
             keep = (hd, info)
         else:
@@ -292,6 +312,10 @@ def main():
     coupling_bytes = info["bytes_B"] + 2 * 8 * info["sum_rank"] * nrhs
     t_coup = float(np.mean(coup))
     achieved = coupling_bytes / t_coup / 1e9
+    idw = np.array(idw)
+    roof_id = id_roofline(float(idw[:, 0].mean()), float(idw[:, 1].mean()),
+                          "k_batched_id<256> (interpolative decompositions of the nodes with > 64 columns)")
+    roof_id_all = id_roofline(float(idw[:, 2].mean()), float(idw[:, 3].mean()), "k_batched_id (all classes)")
     mv_bytes = (info["bytes_B"] + info["bytes_D"] + info["bytes_U"] + 8 * nrhs * n * 4)
     build_s = float(np.mean(builds))
     mv_s = float(np.mean(mvs))
@@ -359,8 +383,11 @@ def main():
         "accuracy": {"e_dense_sampled_rows_max_rhs": e_rows, "e_dense_sampled_rows_mean_rhs": e_rows_mean,
                      "rows": int(args.rows)},
         "precision_f32": f32,
-        "roofline": {"kernel": "k_blockgemm (coupling sweep)", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "roofline": roof_id,
+        "roofline_id_all_classes": roof_id_all,
+        "roofline_matvec": {"kernel": "k_sweep (coupling sweep of the apply)", "bound": "hbm", "achieved": achieved,
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                            "bytes_per_launch": coupling_bytes, "ms_per_launch": 1e3 * t_coup},
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)

@@ -61,7 +61,9 @@ typedef enum { H2_COULOMB = 0, H2_GAUSSIAN = 1, H2_EXPONENTIAL = 2, H2_MATERN32 
  *   store_coupling 1: store the coupling and nearfield blocks (default)
  *   calib_seed     seed of the random points used to choose r1, r2
  *   profile        1: h2_matvec records HIP events around each of its sweeps on
- *                  its stream; h2_query then reports the last apply's times  */
+ *                  its stream, and the build around its launches of the
+ *                  interpolative decompositions; h2_query then reports the
+ *                  last apply's and the build's times                       */
 typedef struct {
     double tau;
     int r1, r2;
@@ -144,6 +146,13 @@ typedef struct {
      * apply's stream; h2_query waits for that apply to finish); 0 otherwise */
     double mv_gather, mv_upward, mv_coupling, mv_downward, mv_leaves, mv_scatter;
     int mv_nrhs;
+    /* build with options.profile = 1: HIP-event time (ms) of the launches of
+     * the interpolative decompositions (all, and the one for nodes with more
+     * than 64 candidate columns; launches of h2_build_batched are shared by
+     * all its problems), and the algorithmic floating-point operations of
+     * this handle's decompositions (pivoted QR to the rank found and the
+     * solve for T); 0 otherwise */
+    double id_ms, id_wide_ms, id_flops, id_wide_flops;
 } h2_info;
 
 h2_status h2_query(h2_handle h, h2_info *info);

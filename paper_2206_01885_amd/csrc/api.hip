@@ -364,6 +364,10 @@ h2_status h2_query(h2_handle hd, h2_info* info)
         info->mv_scatter = ms[5];
         info->mv_nrhs = h.prof_nrhs;
     }
+    info->id_ms = h.id_ms;
+    info->id_wide_ms = h.id_wide_ms;
+    info->id_flops = h.id_flops;
+    info->id_wide_flops = h.id_wide_flops;
     return H2_OK;
 }
 

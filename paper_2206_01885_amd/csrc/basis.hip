@@ -20,6 +20,8 @@
 // recomputation.  With the reflector norm in closed form this reproduces the
 // oracle's operation order exactly, so pivots, ranks and T agree bit for bit
 // whenever the kernel entries do.  Compiled with -ffp-contract=off.
+#include <type_traits>
+
 #include "common.h"
 #include "kappa.h"
 
@@ -66,37 +68,77 @@ __device__ inline int block_min_i(int v, int* sh)
 }
 
 
-// Sequential row loops of one column with the loads issued ahead in batches
-// of 8: the arithmetic runs in exactly the order of a plain loop (so the
-// result is the oracle's, bit for bit), only the memory latency overlaps.
+// Device buffers reached through pointers loaded from memory would be
+// accessed with flat instructions, which also count against the LDS wait
+// counter: a wait for an LDS value would then drain every global load in
+// flight.  Global buffers are therefore addressed through the global address
+// space.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) int gint;
+
+// Barrier that orders LDS accesses only: global loads and stores of a lane
+// stay in flight across it.
+__device__ inline void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Sequential row loops of one column (x: LDS or gdouble pointer) with the
+// loads issued ahead: batches of LB rows, the next batch in flight while the
+// current one is used.  The arithmetic runs in exactly the order of a plain
+// loop (so the result is the oracle's, bit for bit); only the memory latency
+// overlaps.
 constexpr int LB = 8;
 
 // acc + sum_{r=r0}^{r1-1} a[r] * x[r*ld], accumulated in row order
-__device__ __forceinline__ double dot_rows(const double* __restrict__ a, const double* x, int64_t ld, int r0,
-                                           int r1, double acc)
+template <class XP>
+__device__ __forceinline__ double dot_rows(const double* __restrict__ a, XP x, int64_t ld, int r0, int r1, double acc)
 {
     int r = r0;
-    for (; r + LB <= r1; r += LB) {
-        double xv[LB];
+    if (r + LB <= r1) {
+        double cur[LB];
 #pragma unroll
-        for (int q = 0; q < LB; ++q) xv[q] = x[(int64_t)(r + q) * ld];
+        for (int q = 0; q < LB; ++q) cur[q] = x[(int64_t)(r + q) * ld];
+        for (; r + 2 * LB <= r1; r += LB) {
+            double nxt[LB];
 #pragma unroll
-        for (int q = 0; q < LB; ++q) acc = acc + a[r + q] * xv[q];
+            for (int q = 0; q < LB; ++q) nxt[q] = x[(int64_t)(r + LB + q) * ld];
+#pragma unroll
+            for (int q = 0; q < LB; ++q) acc = acc + a[r + q] * cur[q];
+#pragma unroll
+            for (int q = 0; q < LB; ++q) cur[q] = nxt[q];
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) acc = acc + a[r + q] * cur[q];
+        r += LB;
     }
     for (; r < r1; ++r) acc = acc + a[r] * x[(int64_t)r * ld];
     return acc;
 }
 
 // acc + sum_{r=r0}^{r1-1} x[r*ld]^2, in row order
-__device__ __forceinline__ double sumsq_rows(const double* x, int64_t ld, int r0, int r1, double acc)
+template <class XP>
+__device__ __forceinline__ double sumsq_rows(XP x, int64_t ld, int r0, int r1, double acc)
 {
     int r = r0;
-    for (; r + LB <= r1; r += LB) {
-        double xv[LB];
+    if (r + LB <= r1) {
+        double cur[LB];
 #pragma unroll
-        for (int q = 0; q < LB; ++q) xv[q] = x[(int64_t)(r + q) * ld];
+        for (int q = 0; q < LB; ++q) cur[q] = x[(int64_t)(r + q) * ld];
+        for (; r + 2 * LB <= r1; r += LB) {
+            double nxt[LB];
 #pragma unroll
-        for (int q = 0; q < LB; ++q) acc = acc + xv[q] * xv[q];
+            for (int q = 0; q < LB; ++q) nxt[q] = x[(int64_t)(r + LB + q) * ld];
+#pragma unroll
+            for (int q = 0; q < LB; ++q) acc = acc + cur[q] * cur[q];
+#pragma unroll
+            for (int q = 0; q < LB; ++q) cur[q] = nxt[q];
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) acc = acc + cur[q] * cur[q];
+        r += LB;
     }
     for (; r < r1; ++r) acc = acc + x[(int64_t)r * ld] * x[(int64_t)r * ld];
     return acc;
@@ -104,8 +146,8 @@ __device__ __forceinline__ double sumsq_rows(const double* x, int64_t ld, int r0
 
 // x[r] <- x[r] - f v[r] for r in [r0, r1); returns the sum of the new x[r]^2
 // over r in [r0+1, r1) in row order (the next step's tail norm)
-__device__ __forceinline__ double axpy_rows(const double* __restrict__ v, double f, double* x, int64_t ld, int r0,
-                                            int r1)
+template <class XP>
+__device__ __forceinline__ double axpy_rows(const double* __restrict__ v, double f, XP x, int64_t ld, int r0, int r1)
 {
     {
         double y = x[(int64_t)r0 * ld] - f * v[r0];
@@ -113,16 +155,30 @@ __device__ __forceinline__ double axpy_rows(const double* __restrict__ v, double
     }
     double tail = 0.0;
     int r = r0 + 1;
-    for (; r + LB <= r1; r += LB) {
-        double xv[LB];
+    if (r + LB <= r1) {
+        double cur[LB];
 #pragma unroll
-        for (int q = 0; q < LB; ++q) xv[q] = x[(int64_t)(r + q) * ld];
+        for (int q = 0; q < LB; ++q) cur[q] = x[(int64_t)(r + q) * ld];
+        for (; r + 2 * LB <= r1; r += LB) {
+            double nxt[LB];
+#pragma unroll
+            for (int q = 0; q < LB; ++q) nxt[q] = x[(int64_t)(r + LB + q) * ld];
+#pragma unroll
+            for (int q = 0; q < LB; ++q) {
+                double y = cur[q] - f * v[r + q];
+                x[(int64_t)(r + q) * ld] = y;
+                tail = tail + y * y;
+            }
+#pragma unroll
+            for (int q = 0; q < LB; ++q) cur[q] = nxt[q];
+        }
 #pragma unroll
         for (int q = 0; q < LB; ++q) {
-            double y = xv[q] - f * v[r + q];
+            double y = cur[q] - f * v[r + q];
             x[(int64_t)(r + q) * ld] = y;
             tail = tail + y * y;
         }
+        r += LB;
     }
     for (; r < r1; ++r) {
         double y = x[(int64_t)r * ld] - f * v[r];
@@ -140,14 +196,19 @@ __device__ __forceinline__ double axpy_rows(const double* __restrict__ v, double
 // reflectors that each zero one column of the block against the diagonal
 // entry of R (TSQR).  Lane l owns columns l, l + NT, ... (CPL of them) and
 // keeps their BR block entries in registers, evaluating them itself; the
-// column that step j eliminates is published in a double-buffered LDS slot
-// by its owner at the end of step j - 1, so one barrier per step suffices.
-// The R entries of the next row are loaded a step ahead.  (This part
+// column that step j eliminates, its squared norm and the diagonal entry
+// R[j][j] are published in a double-buffered LDS slot by the column's owner
+// at the end of step j - 1, so one barrier per step suffices.  The R entries
+// of the next row are loaded a step ahead.  (This part
 // accumulates with fused multiply-adds; it is not the oracle's operation
 // order, and need not be: pivots and T are fixed up to rounding.)
-template <int NT, int CPL, int BR>
-__device__ void tsqr_fold(const IdTask& tk, int m, int s0, double* R, double* colbuf, double* nubuf, double* scr)
+// R is an LDS pointer or a gdouble pointer.  Every R entry is read and written
+// by the lane that owns its column only (the diagonal entry reaches the other
+// lanes through LDS), so the steps need LDS barriers only.
+template <int NT, int CPL, int BR, class RPtr>
+__device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbuf, double* nubuf, double* scr)
 {
+    double* x0buf = nubuf + 2;
     const double* pts = tk.pts;
     const int64_t ld = tk.ld;
     const int* xi = tk.x_idx;
@@ -178,22 +239,24 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, double* R, double* co
                 tail[t] = __builtin_fma(v, v, tail[t]);
             }
         }
-        // publish column 0
-        if (lane == 0) {
-#pragma unroll
-            for (int r = 0; r < BR; ++r) colbuf[r] = bc[0][r];
-            nubuf[0] = tail[0];
-        }
         double rn[CPL];
 #pragma unroll
         for (int t = 0; t < CPL; ++t) {
             const int c = lane + t * NT;
             rn[t] = c < m ? R[c] : 0.0;
         }
-        __syncthreads();
+        // publish column 0
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < BR; ++r) colbuf[r] = bc[0][r];
+            nubuf[0] = tail[0];
+            x0buf[0] = rn[0];
+        }
+        lds_barrier();
         for (int j = 0; j < m; ++j) {
             const double* cj = colbuf + (j & 1) * BR;
             const double nub = nubuf[j & 1];
+            const double x0 = x0buf[j & 1];
             double rc[CPL];
 #pragma unroll
             for (int t = 0; t < CPL; ++t) {
@@ -202,7 +265,6 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, double* R, double* co
                 rn[t] = (c < m && j + 1 < m) ? R[(int64_t)(j + 1) * m + c] : 0.0;
             }
             if (nub != 0.0) {
-                const double x0 = R[(int64_t)j * m + j];
                 const double alpha = x0 >= 0.0 ? -sqrt(x0 * x0 + nub) : sqrt(x0 * x0 + nub);
                 const double v0 = x0 - alpha;
                 const double vtv = 2.0 * fabs(alpha) * (fabs(alpha) + fabs(x0));
@@ -229,7 +291,8 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, double* R, double* co
                 }
                 if (lane == j % NT) R[(int64_t)j * m + j] = alpha;
             }
-            // the owner of column j + 1 publishes it for the next step
+            // the owner of column j + 1 publishes it (entries, squared norm,
+            // diagonal entry of R from the row loaded ahead) for the next step
             if (j + 1 < m && lane == (j + 1) % NT) {
                 const int t1 = (j + 1) / NT;
                 double* nb1 = colbuf + ((j + 1) & 1) * BR;
@@ -239,11 +302,13 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, double* R, double* co
 #pragma unroll
                         for (int r = 0; r < BR; ++r) nb1[r] = bc[t][r];
                         nubuf[(j + 1) & 1] = tail[t];
+                        x0buf[(j + 1) & 1] = rn[t];
                     }
             }
-            __syncthreads();
+            lds_barrier();
         }
     }
+    __syncthreads();  // R complete and visible to every lane
 }
 
 // NT = 64 (one wavefront; the matrix in LDS) or 256 lanes (global matrix).
@@ -253,7 +318,7 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, double* R, double* co
 // (tsqr_fold): column pivoting sees only the partial column norms, which a
 // left orthogonal factor does not change, so the pivots, |R_jj| and T are
 // those of the s x m block up to rounding.
-template <int NT, bool LDSM>
+template <int NT, bool LDSM, int CPL, int BR>
 __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ tasks, const int* __restrict__ order,
                                                    int bmax)
 {
@@ -265,19 +330,24 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
     const IdTask& tk = tasks[order[blockIdx.x]];
     const int m = tk.m, s0 = tk.s, d = tk.d, kid = tk.kid;
     const double prm = tk.prm, tol = tk.tol;
-    int* piv = tk.piv;
+    gint* piv = (gint*)tk.piv;
     for (int c = threadIdx.x; c < m; c += NT) piv[c] = c;
     if (m == 0 || s0 == 0) {
         if (threadIdx.x == 0) *tk.rank = 0;
         return;
     }
-    const bool comp = s0 > m && m <= (NT == 64 ? 64 : 4 * NT);
+    const bool comp = s0 > m && m <= CPL * NT;
     const int s = comp ? m : s0;  // rows of the matrix the pivoted QR runs on
     double* v = dyn;
-    double* M = LDSM ? dyn + s : tk.M;
-    double* nu = tk.nu;
-    double* nu0 = nu + m;
-    double* ss = nu + 2 * m;
+    using MPtr = std::conditional_t<LDSM, double*, gdouble*>;
+    MPtr M;
+    if constexpr (LDSM)
+        M = dyn + s;
+    else
+        M = (gdouble*)tk.M;
+    gdouble* nu = (gdouble*)tk.nu;
+    gdouble* nu0 = nu + m;
+    gdouble* ss = nu + 2 * m;
     const int* xi = tk.x_idx;
     const int* yi = tk.y_idx;
 
@@ -285,10 +355,7 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
         // the published column lives after the LDS matrix, or over the (not
         // yet used) reflector space
         double* cb = LDSM ? dyn + s + (int64_t)s * m : dyn;
-        if constexpr (NT == 64)
-            tsqr_fold<NT, 1, 16>(tk, m, s0, M, cb, cb + 32, cb + 34);
-        else
-            tsqr_fold<NT, 4, 16>(tk, m, s0, M, cb, cb + 32, cb + 34);
+        tsqr_fold<NT, CPL, BR>(tk, m, s0, M, cb, cb + 2 * BR, cb + 2 * BR + 4);
     } else {
         // kernel block: M[r][c] = kappa(x_c, y_r)
         for (int64_t e = threadIdx.x; e < (int64_t)s * m; e += NT) {
@@ -376,11 +443,11 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
     }
     // T = R11^{-1} R12 by back substitution, one column of R12 per lane
     const int nr = m - k;
-    double* T = tk.T;
+    gdouble* T = (gdouble*)tk.T;
     for (int u = threadIdx.x; u < nr; u += NT) {
         for (int t = k - 1; t >= 0; --t) {
             double acc = M[(int64_t)t * m + (k + u)];
-            const double* Rt = M + (int64_t)t * m;
+            const MPtr Rt = M + (int64_t)t * m;
             int l = t + 1;
             for (; l + LB <= k; l += LB) {
                 double rv[LB], tv[LB];
@@ -425,72 +492,94 @@ __global__ __launch_bounds__(TB) void k_xbar_fill(int lo, const int* __restrict_
 
 }  // namespace
 
-void batched_id(const std::vector<IdTask>& tasks, hipStream_t s)
+void batched_id(const std::vector<IdTask>& tasks, hipStream_t s, IdProf* prof)
 {
     const int np = (int)tasks.size();
     if (np <= 0) return;
-    // class 0 / 3: one wavefront, matrix (and the compression's row block)
-    // in LDS; 1: one wavefront, global matrix; 2: four wavefronts, global
-    // matrix (the compression's row block in LDS)
+    // Launch classes (lanes per task, where the matrix lives, columns per lane
+    // and rows per block of the compression):
+    //   0 / 3  64 lanes, matrix in LDS, m <= 64 (split at 32 KiB of LDS so that
+    //          small problems are not limited to the occupancy of the largest)
+    //   1      64 lanes, global matrix, m <= 64
+    //   2      256 lanes, global matrix, m > 64
+    struct Cls {
+        int nt, cpl, br;
+    };
+    const Cls CL[4] = {{64, 1, 16}, {64, 1, 16}, {TB, 4, 16}, {64, 1, 16}};
     const int BROWS = 64;                 // compression row block (at most)
     const size_t LDS_CAP = 80 * 1024;     // bytes per workgroup
     auto lds_need = [&](const IdTask& t, int c) -> size_t {
-        const bool comp = t.s > t.m && t.m <= (c == 2 ? 4 * TB : 64);
+        const Cls& k = CL[c];
+        const bool comp = t.s > t.m && t.m <= k.cpl * k.nt;
         const int sr = comp ? t.m : t.s;
-        // published column (2 x 16) + its two norms + the lanes' evaluation slices
-        const size_t pub = comp ? 34 + (size_t)16 * (c == 2 ? TB : 64) : 0;
-        if (c == 0) return ((size_t)sr + (size_t)sr * t.m + pub) * sizeof(double);
+        // published column (2 x BR), its norms and diagonal entries (2 x 2),
+        // the lanes' evaluation slices
+        const size_t pub = comp ? 2 * k.br + 4 + (size_t)k.br * k.nt : 0;
+        if (c == 0 || c == 3) return ((size_t)sr + (size_t)sr * t.m + pub) * sizeof(double);
         return std::max((size_t)sr, pub) * sizeof(double);
     };
-    // class 0 is split by LDS size (0: up to 32 KiB, 3: more) so that small
-    // problems are not limited to the occupancy of the largest
     std::vector<int> cls(np);
     for (int p = 0; p < np; ++p) {
-        if (tasks[p].m > 64) {
+        const IdTask& t = tasks[p];
+        if (t.m > 64) {
             cls[p] = 2;
         } else {
-            const size_t need = lds_need(tasks[p], 0);
+            const size_t need = lds_need(t, 0);
             cls[p] = need <= 32 * 1024 ? 0 : (need <= LDS_CAP ? 3 : 1);
         }
     }
+    // narrow classes first, then the wide ones (timed together)
+    const int ORD[4] = {0, 3, 1, 2};
     std::vector<int> order;
     order.reserve(np);
-    int cnt[4] = {0, 0, 0, 0};
+    int cnt[4] = {0, 0, 0, 0}, off[4] = {0, 0, 0, 0};
     size_t lds[4] = {8, 8, 8, 8};
-    for (int c = 0; c < 4; ++c)
+    for (int c : ORD) {
+        off[c] = (int)order.size();
         for (int p = 0; p < np; ++p)
             if (cls[p] == c) {
                 order.push_back(p);
                 ++cnt[c];
-                lds[c] = std::max(lds[c], lds_need(tasks[p], c == 3 ? 0 : c));
+                lds[c] = std::max(lds[c], lds_need(tasks[p], c));
             }
+    }
     DBuf<IdTask> d_tasks;
     DBuf<int> d_order;
     d_tasks.ensure(tasks.size(), s);
     d_order.ensure(order.size(), s);
     H2_HIP(hipMemcpyAsync(d_tasks.p, tasks.data(), tasks.size() * sizeof(IdTask), hipMemcpyHostToDevice, s));
     H2_HIP(hipMemcpyAsync(d_order.p, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    int o = 0;
-    if (cnt[0] > 0) {
-        k_batched_id<64, true><<<cnt[0], 64, lds[0], s>>>(d_tasks.p, d_order.p + o, BROWS);
+    hipEvent_t ev[4] = {};
+    if (prof)
+        for (auto& e : ev) H2_HIP(hipEventCreate(&e));
+    if (prof) H2_HIP(hipEventRecord(ev[0], s));
+    auto launch = [&](int c) {
+        if (cnt[c] == 0) return;
+        const int* ord = d_order.p + off[c];
+        switch (c) {
+        case 0:
+        case 3: k_batched_id<64, true, 1, 16><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
+        case 1: k_batched_id<64, false, 1, 16><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
+        default: k_batched_id<TB, false, 4, 16><<<cnt[c], TB, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
+        }
         H2_LAUNCH_CHECK();
-    }
-    o += cnt[0];
-    if (cnt[1] > 0) {
-        k_batched_id<64, false><<<cnt[1], 64, lds[1], s>>>(d_tasks.p, d_order.p + o, BROWS);
-        H2_LAUNCH_CHECK();
-    }
-    o += cnt[1];
-    if (cnt[2] > 0) {
-        k_batched_id<TB, false><<<cnt[2], TB, lds[2], s>>>(d_tasks.p, d_order.p + o, BROWS);
-        H2_LAUNCH_CHECK();
-    }
-    o += cnt[2];
-    if (cnt[3] > 0) {
-        k_batched_id<64, true><<<cnt[3], 64, lds[3], s>>>(d_tasks.p, d_order.p + o, BROWS);
-        H2_LAUNCH_CHECK();
-    }
+    };
+    launch(0);
+    launch(3);
+    launch(1);
+    if (prof) H2_HIP(hipEventRecord(ev[1], s));
+    launch(2);
+    if (prof) H2_HIP(hipEventRecord(ev[2], s));
+    if (prof) H2_HIP(hipEventRecord(ev[3], s));
     H2_HIP(hipStreamSynchronize(s));
+    if (prof) {
+        float a = 0.f, w = 0.f;
+        H2_HIP(hipEventElapsedTime(&a, ev[0], ev[3]));
+        H2_HIP(hipEventElapsedTime(&w, ev[1], ev[2]));
+        prof->ms_all += a;
+        prof->ms_wide += w;
+        for (auto& e : ev) H2_HIP(hipEventDestroy(e));
+    }
 }
 
 template <class T>
@@ -506,6 +595,18 @@ static void upload(DBuf<T>& dst, const std::vector<T>& src, hipStream_t s)
 // round before), and all nodes of a round go into one batched ID launch
 // (several only when the workspace cap splits it).  piv and T offsets are
 // assigned per problem in processing order (deepest level first).
+// Floating-point operations of the pivoted-QR interpolative decomposition of
+// an s x m block stopped at rank k (Section 3.2): the initial column norms,
+// each Householder vector and its application to the remaining columns, and
+// the triangular solve for T.  (The compression of tall blocks and the norm
+// downdates are not counted: this is the method's own work.)
+static double id_flop_count(int64_t s, int64_t m, int64_t k)
+{
+    double f = 2.0 * (double)s * (double)m;
+    for (int64_t j = 0; j < k; ++j) f += 2.0 * (double)(s - j) * (1.0 + 2.0 * (double)(m - j - 1));
+    return f + (double)k * (double)k * (double)(m - k);
+}
+
 void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
 {
     struct St {
@@ -532,6 +633,9 @@ void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
         h.h_T_off.assign((size_t)nn + 1, 0);
         maxd = std::max(maxd, h.maxdepth);
     }
+    bool prof_on = false;
+    for (auto* h : hs) prof_on = prof_on || h->profile != 0;
+    IdProf prof;
     const int64_t WS_CAP = (int64_t)1 << 28;  // doubles of ID workspace per launch
     DBuf<int> d_xidx;
     DBuf<int64_t> d_xoff;
@@ -595,7 +699,7 @@ void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
                 tasks[q].M = Mws.p + Moff[q];
                 tasks[q].nu = nuws.p + nuoff[q];
             }
-            batched_id(tasks, s);
+            batched_id(tasks, s, prof_on ? &prof : nullptr);
             tasks.clear();
             Moff.clear();
             nuoff.clear();
@@ -642,6 +746,13 @@ void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
             const int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
             std::vector<int> rk = read_vec(h.rank.p + lo, nl, s);
             for (int q = 0; q < nl; ++q) h.h_rank[lo + q] = rk[q];
+            if (prof_on)
+                for (int q = 0; q < nl; ++q) {
+                    const int i = lo + q;
+                    const double f = id_flop_count(st[p].ys_cnt[i], h.h_mbar[i], rk[q]);
+                    h.id_flops += f;
+                    if (h.h_mbar[i] > 64) h.id_wide_flops += f;
+                }
         }
     }
     for (int p = 0; p < np; ++p) {
@@ -655,6 +766,8 @@ void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
         h.sum_rank = 0;
         for (int i = 0; i < nn; ++i) h.sum_rank += h.h_rank[i];
         h.bytes_T = st[p].T_total * (int64_t)sizeof(double);
+        h.id_ms = prof.ms_all;  // launches shared by all problems of the call
+        h.id_wide_ms = prof.ms_wide;
     }
     H2_HIP(hipStreamSynchronize(s));
 }

@@ -216,6 +216,9 @@ struct Handle {
     // diagnostics
     double t_tree = 0, t_lists = 0, t_calib = 0, t_hidr = 0, t_basis = 0, t_blocks = 0;
     int64_t bytes_B = 0, bytes_D = 0, bytes_T = 0;
+    // interpolative decompositions of the build (profile = 1): launch times
+    // (ms) and the algorithmic floating-point operations of the IDs
+    double id_ms = 0, id_wide_ms = 0, id_flops = 0, id_wide_flops = 0;
 
     // scratch
     DBuf<int> tmp_i32;
@@ -264,6 +267,11 @@ struct IdTask {
     double prm = 1.0, tol = 0.0;
     int m = 0, s = 0, d = 0, kid = 0;
 };
-void batched_id(const std::vector<IdTask>& tasks, hipStream_t s);
+// HIP-event time (ms) of batched_id's launches: all classes, and the class of
+// the wide nodes (m > 64), accumulated over calls.
+struct IdProf {
+    double ms_all = 0, ms_wide = 0;
+};
+void batched_id(const std::vector<IdTask>& tasks, hipStream_t s, IdProf* prof = nullptr);
 
 }  // namespace h2
