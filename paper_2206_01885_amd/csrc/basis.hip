@@ -318,7 +318,14 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbu
 // (tsqr_fold): column pivoting sees only the partial column norms, which a
 // left orthogonal factor does not change, so the pivots, |R_jj| and T are
 // those of the s x m block up to rounding.
-template <int NT, bool LDSM, int CPL, int BR>
+// The s x m block is compressed to its R factor when that removes a good
+// share of the rows (s > 1.5 m) and the lanes can hold its columns (m <= cap).
+__host__ __device__ inline bool compress_rows(int s, int m, int cap)
+{
+    return 2 * (int64_t)s > 3 * (int64_t)m && m <= cap;
+}
+
+template <int NT, bool LDSM, int CPL, int BR, bool PRE = false>
 __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ tasks, const int* __restrict__ order,
                                                    int bmax)
 {
@@ -336,8 +343,9 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
         if (threadIdx.x == 0) *tk.rank = 0;
         return;
     }
-    const bool comp = s0 > m && m <= CPL * NT;
-    const int s = comp ? m : s0;  // rows of the matrix the pivoted QR runs on
+    // PRE: the block was compressed to its m x m R factor by k_id_fold
+    const bool comp = !PRE && compress_rows(s0, m, CPL * NT);
+    const int s = (comp || PRE) ? m : s0;  // rows of the matrix the pivoted QR runs on
     double* v = dyn;
     using MPtr = std::conditional_t<LDSM, double*, gdouble*>;
     MPtr M;
@@ -351,7 +359,8 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
     const int* xi = tk.x_idx;
     const int* yi = tk.y_idx;
 
-    if (comp) {
+    if constexpr (PRE) {
+    } else if (comp) {
         // the published column lives after the LDS matrix, or over the (not
         // yet used) reflector space
         double* cb = LDSM ? dyn + s + (int64_t)s * m : dyn;
@@ -492,25 +501,173 @@ __global__ __launch_bounds__(TB) void k_xbar_fill(int lo, const int* __restrict_
 
 }  // namespace
 
-void batched_id(const std::vector<IdTask>& tasks, hipStream_t s, IdProf* prof)
+// ---------------------------------------------------------------------------
+// Wide nodes (m > 64) run as two launches: the compression of tall blocks
+// (k_id_fold) and the pivoted QR (k_id_qr).
+//
+// k_id_fold: the s x m block (s > m) is folded into its m x m R factor in the
+// task's workspace with the reflectors of tsqr_fold.  Lane l owns columns
+// l, l + 256, ... (CPL of them) and is the only lane to touch their R
+// entries, so a step synchronises through LDS only; the R rows a lane needs
+// are loaded D steps ahead into a register ring, and the block entries are
+// evaluated SL rows at a time through a lane-private LDS slice.
+template <int CPL, int BR, int D>
+__global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ tasks, const int* __restrict__ order)
 {
-    const int np = (int)tasks.size();
+    constexpr int NT = 256, SL = 8;
+    static_assert(BR % SL == 0 && BR % 4 == 0, "row block");
+    extern __shared__ double dyn[];
+    double* colbuf = dyn;          // 2 x BR: the column step j eliminates
+    double* nubuf = dyn + 2 * BR;  // 2: its squared norm
+    double* x0buf = nubuf + 2;     // 2: the diagonal entry R[j][j]
+    double* scr = x0buf + 2;       // SL x NT evaluation slices
+    const IdTask& tk = tasks[order[blockIdx.x]];
+    const int m = tk.m, s0 = tk.s, d = tk.d, kid = tk.kid;
+    const double prm = tk.prm;
+    const double* pts = tk.pts;
+    const int64_t ld = tk.ld;
+    const int* yi = tk.y_idx;
+    gdouble* R = (gdouble*)tk.M;
+    const int lane = threadIdx.x;
+    for (int64_t e = lane; e < (int64_t)m * m; e += NT) R[e] = 0.0;
+    int xc[CPL];
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) {
+        const int c = lane + t * NT;
+        xc[t] = c < m ? tk.x_idx[c] : 0;
+    }
+    __syncthreads();
+    double bc[CPL][BR], tail[CPL], rn[D][CPL];
+    for (int r0 = 0; r0 < s0; r0 += BR) {
+        const int nb = min(BR, s0 - r0);
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+            const int c = lane + t * NT;
+#pragma unroll
+            for (int k0 = 0; k0 < BR; k0 += SL) {
+                if (c < m)
+                    for (int r = 0; r < SL && k0 + r < nb; ++r)
+                        scr[r * NT + lane] =
+                            kappa_r2(kid, prm, dist2(pts, ld, xc[t], pts, ld, yi[r0 + k0 + r], d));
+#pragma unroll
+                for (int r = 0; r < SL; ++r) bc[t][k0 + r] = (c < m && k0 + r < nb) ? scr[r * NT + lane] : 0.0;
+            }
+            double t4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < BR; ++r) t4[r & 3] = __builtin_fma(bc[t][r], bc[t][r], t4[r & 3]);
+            tail[t] = (t4[0] + t4[1]) + (t4[2] + t4[3]);
+        }
+#pragma unroll
+        for (int q = 0; q < D; ++q)
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+                const int c = lane + t * NT;
+                rn[q][t] = (c < m && q < m) ? R[(int64_t)q * m + c] : 0.0;
+            }
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < BR; ++r) colbuf[r] = bc[0][r];
+            nubuf[0] = tail[0];
+            x0buf[0] = rn[0][0];
+        }
+        lds_barrier();
+        for (int j0 = 0; j0 < m; j0 += D) {
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+                const int j = j0 + q;
+                if (j < m) {
+                    const double* cj = colbuf + (j & 1) * BR;
+                    const double nub = nubuf[j & 1];
+                    const double x0 = x0buf[j & 1];
+                    double rc[CPL];
+#pragma unroll
+                    for (int t = 0; t < CPL; ++t) {
+                        rc[t] = rn[q][t];
+                        const int c = lane + t * NT;
+                        rn[q][t] = (c < m && j + D < m) ? R[(int64_t)(j + D) * m + c] : 0.0;
+                    }
+                    if (nub != 0.0) {
+                        const double alpha = x0 >= 0.0 ? -sqrt(x0 * x0 + nub) : sqrt(x0 * x0 + nub);
+                        const double v0 = x0 - alpha;
+                        const double vtv = 2.0 * fabs(alpha) * (fabs(alpha) + fabs(x0));
+#pragma unroll
+                        for (int t = 0; t < CPL; ++t) {
+                            const int c = lane + t * NT;
+                            // chunks wholly at or left of column j, or past m, are skipped
+                            if (t * NT + NT - 1 > j && t * NT < m && c > j && c < m) {
+                                // the published column is read from LDS in chunks of 8
+                                double w4[4] = {v0 * rc[t], 0.0, 0.0, 0.0};
+#pragma unroll
+                                for (int r0 = 0; r0 < BR; r0 += 8) {
+                                    double cv[8];
+#pragma unroll
+                                    for (int r = 0; r < 8; ++r) cv[r] = cj[r0 + r];
+#pragma unroll
+                                    for (int r = 0; r < 8; ++r)
+                                        w4[r & 3] = __builtin_fma(cv[r], bc[t][r0 + r], w4[r & 3]);
+                                }
+                                const double f = 2.0 * ((w4[0] + w4[1]) + (w4[2] + w4[3])) / vtv;
+                                R[(int64_t)j * m + c] = rc[t] - f * v0;
+                                double t4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                                for (int r0 = 0; r0 < BR; r0 += 8) {
+                                    double cv[8];
+#pragma unroll
+                                    for (int r = 0; r < 8; ++r) cv[r] = cj[r0 + r];
+#pragma unroll
+                                    for (int r = 0; r < 8; ++r) {
+                                        bc[t][r0 + r] = __builtin_fma(-f, cv[r], bc[t][r0 + r]);
+                                        t4[r & 3] = __builtin_fma(bc[t][r0 + r], bc[t][r0 + r], t4[r & 3]);
+                                    }
+                                }
+                                tail[t] = (t4[0] + t4[1]) + (t4[2] + t4[3]);
+                            }
+                        }
+                        if (lane == j % NT) R[(int64_t)j * m + j] = alpha;
+                    }
+                    // the owner of column j + 1 publishes it for the next step
+                    if (j + 1 < m && lane == (j + 1) % NT) {
+                        const int t1 = (j + 1) / NT;
+                        double* nb1 = colbuf + ((j + 1) & 1) * BR;
+#pragma unroll
+                        for (int t = 0; t < CPL; ++t)
+                            if (t == t1) {
+#pragma unroll
+                                for (int r = 0; r < BR; ++r) nb1[r] = bc[t][r];
+                                nubuf[(j + 1) & 1] = tail[t];
+                                x0buf[(j + 1) & 1] = rn[(q + 1) % D][t];
+                            }
+                    }
+                    lds_barrier();
+                }
+            }
+        }
+    }
+}
+
+void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof)
+{
+    const int np = (int)tasks_in.size();
     if (np <= 0) return;
+    std::vector<IdTask> tasks(tasks_in);
     // Launch classes (lanes per task, where the matrix lives, columns per lane
     // and rows per block of the compression):
     //   0 / 3  64 lanes, matrix in LDS, m <= 64 (split at 32 KiB of LDS so that
     //          small problems are not limited to the occupancy of the largest)
     //   1      64 lanes, global matrix, m <= 64
-    //   2      256 lanes, global matrix, m > 64
+    //   4      64 < m <= 1024 and s > m: compression by k_id_fold (many
+    //          tasks per CU), then the pivoted QR of the m x m factor
+    //   2      256 lanes, global matrix, the other wide nodes
     struct Cls {
         int nt, cpl, br;
     };
-    const Cls CL[4] = {{64, 1, 16}, {64, 1, 16}, {TB, 4, 16}, {64, 1, 16}};
+    const Cls CL[5] = {{64, 1, 16}, {64, 1, 16}, {TB, 4, 16}, {64, 1, 16}, {TB, 4, 16}};
     const int BROWS = 64;                 // compression row block (at most)
     const size_t LDS_CAP = 80 * 1024;     // bytes per workgroup
     auto lds_need = [&](const IdTask& t, int c) -> size_t {
+        if (c == 4) return (size_t)t.m * sizeof(double);
         const Cls& k = CL[c];
-        const bool comp = t.s > t.m && t.m <= k.cpl * k.nt;
+        const bool comp = compress_rows(t.s, t.m, k.cpl * k.nt);
         const int sr = comp ? t.m : t.s;
         // published column (2 x BR), its norms and diagonal entries (2 x 2),
         // the lanes' evaluation slices
@@ -522,18 +679,19 @@ void batched_id(const std::vector<IdTask>& tasks, hipStream_t s, IdProf* prof)
     for (int p = 0; p < np; ++p) {
         const IdTask& t = tasks[p];
         if (t.m > 64) {
-            cls[p] = 2;
+            cls[p] = compress_rows(t.s, t.m, 4 * TB) ? 4 : 2;
+            tasks[p].folded = cls[p] == 4 ? 1 : 0;
         } else {
             const size_t need = lds_need(t, 0);
             cls[p] = need <= 32 * 1024 ? 0 : (need <= LDS_CAP ? 3 : 1);
         }
     }
     // narrow classes first, then the wide ones (timed together)
-    const int ORD[4] = {0, 3, 1, 2};
+    const int ORD[5] = {0, 3, 1, 4, 2};
     std::vector<int> order;
     order.reserve(np);
-    int cnt[4] = {0, 0, 0, 0}, off[4] = {0, 0, 0, 0};
-    size_t lds[4] = {8, 8, 8, 8};
+    int cnt[5] = {0, 0, 0, 0, 0}, off[5] = {0, 0, 0, 0, 0};
+    size_t lds[5] = {8, 8, 8, 8, 8};
     for (int c : ORD) {
         off[c] = (int)order.size();
         for (int p = 0; p < np; ++p)
@@ -543,12 +701,25 @@ void batched_id(const std::vector<IdTask>& tasks, hipStream_t s, IdProf* prof)
                 lds[c] = std::max(lds[c], lds_need(tasks[p], c));
             }
     }
+    // the tall wide blocks to compress, grouped by columns per lane
+    std::vector<int> fold[3];
+    for (int q = off[4]; q < off[4] + cnt[4]; ++q) {
+        const IdTask& t = tasks[order[q]];
+        if (t.folded) fold[t.m <= 256 ? 0 : (t.m <= 512 ? 1 : 2)].push_back(order[q]);
+    }
+    int foff[3] = {0, 0, 0}, nfold = 0;
+    for (int g = 0; g < 3; ++g) {
+        foff[g] = (int)order.size() + nfold;
+        nfold += (int)fold[g].size();
+    }
+    std::vector<int> order_all(order);
+    for (auto& v : fold) order_all.insert(order_all.end(), v.begin(), v.end());
     DBuf<IdTask> d_tasks;
     DBuf<int> d_order;
     d_tasks.ensure(tasks.size(), s);
-    d_order.ensure(order.size(), s);
+    d_order.ensure(order_all.size(), s);
     H2_HIP(hipMemcpyAsync(d_tasks.p, tasks.data(), tasks.size() * sizeof(IdTask), hipMemcpyHostToDevice, s));
-    H2_HIP(hipMemcpyAsync(d_order.p, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    H2_HIP(hipMemcpyAsync(d_order.p, order_all.data(), order_all.size() * sizeof(int), hipMemcpyHostToDevice, s));
     hipEvent_t ev[4] = {};
     if (prof)
         for (auto& e : ev) H2_HIP(hipEventCreate(&e));
@@ -560,6 +731,7 @@ void batched_id(const std::vector<IdTask>& tasks, hipStream_t s, IdProf* prof)
         case 0:
         case 3: k_batched_id<64, true, 1, 16><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
         case 1: k_batched_id<64, false, 1, 16><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
+        case 4: k_batched_id<TB, false, 4, 16, true><<<cnt[c], TB, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
         default: k_batched_id<TB, false, 4, 16><<<cnt[c], TB, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
         }
         H2_LAUNCH_CHECK();
@@ -568,6 +740,17 @@ void batched_id(const std::vector<IdTask>& tasks, hipStream_t s, IdProf* prof)
     launch(3);
     launch(1);
     if (prof) H2_HIP(hipEventRecord(ev[1], s));
+    if (!fold[0].empty())
+        k_id_fold<1, 16, 1><<<(unsigned)fold[0].size(), 256, (2 * 16 + 4 + 8 * 256) * sizeof(double), s>>>(
+            d_tasks.p, d_order.p + foff[0]);
+    if (!fold[1].empty())
+        k_id_fold<2, 16, 1><<<(unsigned)fold[1].size(), 256, (2 * 16 + 4 + 8 * 256) * sizeof(double), s>>>(
+            d_tasks.p, d_order.p + foff[1]);
+    if (!fold[2].empty())
+        k_id_fold<4, 8, 1><<<(unsigned)fold[2].size(), 256, (2 * 8 + 4 + 8 * 256) * sizeof(double), s>>>(
+            d_tasks.p, d_order.p + foff[2]);
+    H2_LAUNCH_CHECK();
+    launch(4);
     launch(2);
     if (prof) H2_HIP(hipEventRecord(ev[2], s));
     if (prof) H2_HIP(hipEventRecord(ev[3], s));

@@ -266,6 +266,7 @@ struct IdTask {
     int* rank = nullptr;         // 1 entry
     double prm = 1.0, tol = 0.0;
     int m = 0, s = 0, d = 0, kid = 0;
+    int folded = 0;  // set by batched_id: M holds the m x m R factor of the block
 };
 // HIP-event time (ms) of batched_id's launches: all classes, and the class of
 // the wide nodes (m > 64), accumulated over calls.
