@@ -93,26 +93,26 @@ __device__ inline void lds_barrier()
 constexpr int LB = 8;
 
 // acc + sum_{r=r0}^{r1-1} a[r] * x[r*ld], accumulated in row order
-template <class XP>
+template <int BATCH = LB, class XP>
 __device__ __forceinline__ double dot_rows(const double* __restrict__ a, XP x, int64_t ld, int r0, int r1, double acc)
 {
     int r = r0;
-    if (r + LB <= r1) {
-        double cur[LB];
+    if (r + BATCH <= r1) {
+        double cur[BATCH];
 #pragma unroll
-        for (int q = 0; q < LB; ++q) cur[q] = x[(int64_t)(r + q) * ld];
-        for (; r + 2 * LB <= r1; r += LB) {
-            double nxt[LB];
+        for (int q = 0; q < BATCH; ++q) cur[q] = x[(int64_t)(r + q) * ld];
+        for (; r + 2 * BATCH <= r1; r += BATCH) {
+            double nxt[BATCH];
 #pragma unroll
-            for (int q = 0; q < LB; ++q) nxt[q] = x[(int64_t)(r + LB + q) * ld];
+            for (int q = 0; q < BATCH; ++q) nxt[q] = x[(int64_t)(r + BATCH + q) * ld];
 #pragma unroll
-            for (int q = 0; q < LB; ++q) acc = acc + a[r + q] * cur[q];
+            for (int q = 0; q < BATCH; ++q) acc = acc + a[r + q] * cur[q];
 #pragma unroll
-            for (int q = 0; q < LB; ++q) cur[q] = nxt[q];
+            for (int q = 0; q < BATCH; ++q) cur[q] = nxt[q];
         }
 #pragma unroll
-        for (int q = 0; q < LB; ++q) acc = acc + a[r + q] * cur[q];
-        r += LB;
+        for (int q = 0; q < BATCH; ++q) acc = acc + a[r + q] * cur[q];
+        r += BATCH;
     }
     for (; r < r1; ++r) acc = acc + a[r] * x[(int64_t)r * ld];
     return acc;
@@ -318,6 +318,271 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbu
 // (tsqr_fold): column pivoting sees only the partial column norms, which a
 // left orthogonal factor does not change, so the pivots, |R_jj| and T are
 // those of the s x m block up to rounding.
+template <int NT>
+__device__ inline double block_sum(double v, double* sh)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (NT == 64) return v;
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double r = sh[0];
+    for (int q = 1; q < NT / 64; ++q) r = r + sh[q];
+    __syncthreads();
+    return r;
+}
+
+// LDS doubles of cpqr_blocked: the reflector (s), the norms (2 m), the
+// panel's reflectors (s x nb) and scratch
+__host__ __device__ constexpr int64_t cpqr_blocked_lds(int64_t s, int64_t m, int nt, int nb)
+{
+    return s + 2 * m + s * nb + 4 * nb + (nt / 64) * nb + 2 * (nt / 64) + 2;
+}
+// The blocked form runs when the lanes can hold the F rows of their columns
+// and the panel fits the LDS budget.
+constexpr int64_t QR_LDS_MAX = 80 * 1024;
+__host__ __device__ inline bool use_blocked(int64_t s, int64_t m, int cols, int nt, int nb)
+{
+    return m <= cols && cpqr_blocked_lds(s, m, nt, nb) * 8 <= QR_LDS_MAX;
+}
+
+// Pivoted QR with delayed updates (the blocked form of LAPACK's QP3) of the
+// s x m matrix M (global, row-major).  Within a panel of NB steps only the
+// pivot column and the pivot row are brought up to date, from the panel's
+// Householder vectors V (kept below the diagonal of the factored columns)
+// and F, F[c][b] = 2 v_b^T a_c^(b) / (v_b^T v_b) (a_c^(b): column c after
+// the panel's first b reflectors), whose row c lives in the registers of the
+// lane that owns column c (c = lane + NT t); the trailing matrix is updated
+// once per panel.  That is one read pass over the trailing matrix per step
+// where the unblocked loop makes three.  Pivot rule, stopping rule and norm
+// downdates are those of the unblocked loop; a norm that has to be
+// recomputed ends the panel early (as LAPACK does): the panel update then
+// forms it from the up-to-date column.  Returns the rank; the pivot order is
+// in piv and R in the upper triangle of M.
+template <int NT, int CPL, int NB>
+__device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol, gint* piv, double* lds)
+{
+    constexpr int W = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double* v = lds;            // s: the reflector of the step
+    double* nu = v + s;         // m: partial column norms
+    double* nu0 = nu + m;       // m: their reference values
+    double* Vl = nu0 + m;       // s x NB: the panel's reflectors, Vl[r * NB + b]
+    double* fp = Vl + (int64_t)s * NB;  // NB: F row of the pivot column
+    double* fj = fp + NB;       // NB: F row of column j
+    double* vj = fj + NB;       // NB: row j of V
+    double* red = vj + NB;      // W x NB partial sums
+    double* redd = red + W * NB;  // W
+    int* redi = (int*)(redd + W);  // W
+    int* anyre = redi + W;         // 1: a norm of this step is to be recomputed
+    if (tid == 0) *anyre = 0;
+    for (int t = 0; t < CPL; ++t) {
+        const int c = tid + t * NT;
+        if (c < m) {
+            const double a = sumsq_rows(M + c, m, 0, s, 0.0);
+            nu[c] = sqrt(a);
+            nu0[c] = nu[c];
+        }
+    }
+    __syncthreads();
+    const double tol3z = sqrt(2.220446049250313e-16);
+    const double window = 1.0 - 0x1.0p-40;
+    const int kmax = m < s ? m : s;
+    double F[CPL][NB];
+#pragma unroll
+    for (int t = 0; t < CPL; ++t)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) F[t][b] = 0.0;
+    double r00 = 0.0;
+    int k = 0, j0 = 0;
+    for (int j = 0; j < kmax; ++j) {
+        const int jb = j - j0;
+        // pivot: lowest index within the window of the largest partial norm
+        double mx = 0.0;
+        for (int c = j + tid; c < m; c += NT) mx = fmax(mx, nu[c]);
+        mx = block_max<NT>(mx, redd);
+        int cand = 0x7fffffff;
+        for (int c = j + tid; c < m; c += NT)
+            if (nu[c] >= window * mx) {
+                cand = c;
+                break;
+            }
+        const int pc = block_min_i<NT>(cand, redi);
+        // F rows of the pivot column and of column j (their owners)
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+            const int c = tid + t * NT;
+            if (c == pc)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) fp[b] = F[t][b];
+            if (c == j)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) fj[b] = F[t][b];
+        }
+        __syncthreads();
+        // the pivot column brought up to date (rows >= j) and its norm, |R_jj|;
+        // row r >= j is handled by thread (r - j) mod NT in this step
+        double a2 = 0.0;
+        for (int r = j + tid; r < s; r += NT) {
+            double x = M[(int64_t)r * m + pc];
+            const double* Vr = Vl + (int64_t)r * NB;
+            for (int b = 0; b < jb; ++b) x = x - Vr[b] * fp[b];
+            v[r] = x;
+            a2 = a2 + x * x;
+        }
+        a2 = block_sum<NT>(a2, redd);
+        const double alpha = sqrt(a2);
+        if (j == 0) r00 = alpha;
+        // the step that stops swaps nothing
+        if (alpha == 0.0 || alpha <= tol * r00) break;
+        const double xj = v[j];
+        const double beta = xj >= 0.0 ? -alpha : alpha;
+        const double vd = xj - beta;  // first entry of the Householder vector
+        const double vtv = 2.0 * alpha * (alpha + fabs(xj));
+        // swap columns j and pc (every row), F rows and norms; the reflector
+        // below the diagonal of column j, R_jj
+        for (int r = j + tid; r < s; r += NT) {
+            if (pc != j) M[(int64_t)r * m + pc] = M[(int64_t)r * m + j];
+            M[(int64_t)r * m + j] = r == j ? beta : v[r];
+            if (r > j) Vl[(int64_t)r * NB + jb] = v[r];
+        }
+        if (pc != j) {
+            for (int r = tid; r < j; r += NT) {
+                const double a = M[(int64_t)r * m + j];
+                M[(int64_t)r * m + j] = M[(int64_t)r * m + pc];
+                M[(int64_t)r * m + pc] = a;
+            }
+#pragma unroll
+            for (int t = 0; t < CPL; ++t)
+                if (tid + t * NT == pc)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) F[t][b] = fj[b];
+            if (tid == 0) {
+                double tmp = nu[j]; nu[j] = nu[pc]; nu[pc] = tmp;
+                tmp = nu0[j]; nu0[j] = nu0[pc]; nu0[pc] = tmp;
+                const int ti = piv[j]; piv[j] = piv[pc]; piv[pc] = ti;
+            }
+        }
+        // y_b = v^T v_b over rows >= j (b < jb), row j of V
+        double yp[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) yp[b] = 0.0;
+        for (int r = j + tid; r < s; r += NT) {
+            const double vr = r == j ? vd : v[r];
+            const double* Vr = Vl + (int64_t)r * NB;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                if (b < jb) yp[b] = yp[b] + vr * Vr[b];
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            for (int off = 32; off > 0; off >>= 1) yp[b] += __shfl_xor(yp[b], off, 64);
+            if (lane == 0) red[wv * NB + b] = yp[b];
+        }
+        if (tid < jb) vj[tid] = Vl[(int64_t)j * NB + tid];
+        if (tid == 0) {
+            v[j] = vd;
+            vj[jb] = vd;
+        }
+        __syncthreads();
+        double yb[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            double a = 0.0;
+            for (int q = 0; q < W; ++q) a = a + red[q * NB + b];
+            yb[b] = a;
+        }
+        // this lane's columns c > j: F column jb, the pivot row, norm downdate
+        bool re[CPL];
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+            const int c = tid + t * NT;
+            re[t] = false;
+            if (c > j && c < m) {
+                const double w = dot_rows<16>(v, M + c, m, j, s, 0.0);
+                double corr = 0.0;
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    if (b < jb) corr = corr + yb[b] * F[t][b];
+                const double fn = 2.0 * (w - corr) / vtv;
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    if (b == jb) F[t][b] = fn;
+                double rj = M[(int64_t)j * m + c];
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    if (b <= jb) rj = rj - vj[b] * F[t][b];
+                M[(int64_t)j * m + c] = rj;
+                if (nu[c] != 0.0) {
+                    double tt = fabs(rj) / nu[c];
+                    tt = (1.0 + tt) * (1.0 - tt);
+                    if (tt < 0.0) tt = 0.0;
+                    const double rat = nu[c] / nu0[c];
+                    if (tt * rat * rat <= tol3z) {
+                        // recomputed from the up-to-date column by the panel update
+                        re[t] = true;
+                        *anyre = 1;
+                    } else {
+                        nu[c] = nu[c] * sqrt(tt);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        k = j + 1;
+        if ((jb + 1 == NB || *anyre) && k < kmax) {
+            // panel update of the trailing matrix (rows > j, this lane's
+            // columns > j; the panel's jb + 1 reflectors), with the norms
+            // that are to be recomputed
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+                const int c = tid + t * NT;
+                if (c > j && c < m) {
+                    constexpr int RB = 8;
+                    double tail = 0.0;
+                    int r = j + 1;
+                    for (; r + RB <= s; r += RB) {
+                        double x[RB];
+#pragma unroll
+                        for (int q = 0; q < RB; ++q) x[q] = M[(int64_t)(r + q) * m + c];
+#pragma unroll
+                        for (int q = 0; q < RB; ++q) {
+                            const double* Vr = Vl + (int64_t)(r + q) * NB;
+#pragma unroll
+                            for (int b = 0; b < NB; ++b)
+                                if (b <= jb) x[q] = x[q] - Vr[b] * F[t][b];
+                            M[(int64_t)(r + q) * m + c] = x[q];
+                            tail = tail + x[q] * x[q];
+                        }
+                    }
+                    for (; r < s; ++r) {
+                        double x = M[(int64_t)r * m + c];
+                        const double* Vr = Vl + (int64_t)r * NB;
+#pragma unroll
+                        for (int b = 0; b < NB; ++b)
+                            if (b <= jb) x = x - Vr[b] * F[t][b];
+                        M[(int64_t)r * m + c] = x;
+                        tail = tail + x * x;
+                    }
+                    if (re[t]) {
+                        nu[c] = sqrt(tail);
+                        nu0[c] = nu[c];
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < NB; ++b) F[t][b] = 0.0;
+            }
+            j0 = j + 1;
+            __syncthreads();
+            if (tid == 0) *anyre = 0;
+        }
+    }
+    return k;
+}
+
+constexpr int QR_NB = 8;  // steps per panel of the blocked pivoted QR
+constexpr int WNT = 512;  // lanes per wide task
+
 // The s x m block is compressed to its R factor when that removes a good
 // share of the rows (s > 1.5 m) and the lanes can hold its columns (m <= cap).
 __host__ __device__ inline bool compress_rows(int s, int m, int cap)
@@ -330,8 +595,8 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
                                                    int bmax)
 {
     extern __shared__ double dyn[];
-    __shared__ double redd[4];
-    __shared__ int redi[4];
+    __shared__ double redd[NT / 64];
+    __shared__ int redi[NT / 64];
     __shared__ double sh_alpha;
 
     const IdTask& tk = tasks[order[blockIdx.x]];
@@ -374,6 +639,16 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
         }
         __syncthreads();
     }
+    int k = 0;
+    bool blocked = false;
+    if constexpr (!LDSM) {
+        // global matrix: the blocked form when the lanes can hold the F rows
+        if (use_blocked(s, m, CPL * NT, NT, QR_NB)) {
+            k = cpqr_blocked<NT, CPL, QR_NB>(M, m, s, tol, piv, dyn);
+            blocked = true;
+        }
+    }
+    if (!blocked) {
     for (int c = threadIdx.x; c < m; c += NT) {
         double acc = sumsq_rows(M + c, m, 0, s, 0.0);
         ss[c] = acc;
@@ -386,7 +661,6 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
     const double window = 1.0 - 0x1.0p-40;
     const int kmax = m < s ? m : s;
     double r00 = 0.0;
-    int k = 0;
     for (int j = 0; j < kmax; ++j) {
         // pivot: lowest index within the window of the largest partial norm
         double mx = 0.0;
@@ -450,6 +724,8 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
         __syncthreads();
         k = j + 1;
     }
+    }
+    __syncthreads();
     // T = R11^{-1} R12 by back substitution, one column of R12 per lane
     const int nr = m - k;
     gdouble* T = (gdouble*)tk.T;
@@ -661,19 +937,21 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
     struct Cls {
         int nt, cpl, br;
     };
-    const Cls CL[5] = {{64, 1, 16}, {64, 1, 16}, {TB, 4, 16}, {64, 1, 16}, {TB, 4, 16}};
+    const Cls CL[5] = {{64, 1, 16}, {64, 1, 16}, {WNT, 2, 16}, {64, 1, 16}, {WNT, 2, 16}};
     const int BROWS = 64;                 // compression row block (at most)
     const size_t LDS_CAP = 80 * 1024;     // bytes per workgroup
     auto lds_need = [&](const IdTask& t, int c) -> size_t {
-        if (c == 4) return (size_t)t.m * sizeof(double);
         const Cls& k = CL[c];
-        const bool comp = compress_rows(t.s, t.m, k.cpl * k.nt);
+        const bool comp = c == 4 || compress_rows(t.s, t.m, k.cpl * k.nt);
         const int sr = comp ? t.m : t.s;
+        // the blocked pivoted QR keeps the norms and panel scratch in LDS
+        const size_t qr = use_blocked(sr, t.m, k.cpl * k.nt, k.nt, QR_NB) ? cpqr_blocked_lds(sr, t.m, k.nt, QR_NB) : 0;
+        if (c == 4) return std::max((size_t)sr, qr) * sizeof(double);
         // published column (2 x BR), its norms and diagonal entries (2 x 2),
         // the lanes' evaluation slices
         const size_t pub = comp ? 2 * k.br + 4 + (size_t)k.br * k.nt : 0;
         if (c == 0 || c == 3) return ((size_t)sr + (size_t)sr * t.m + pub) * sizeof(double);
-        return std::max((size_t)sr, pub) * sizeof(double);
+        return std::max(std::max((size_t)sr, qr), pub) * sizeof(double);
     };
     std::vector<int> cls(np);
     for (int p = 0; p < np; ++p) {
@@ -731,8 +1009,8 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
         case 0:
         case 3: k_batched_id<64, true, 1, 16><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
         case 1: k_batched_id<64, false, 1, 16><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
-        case 4: k_batched_id<TB, false, 4, 16, true><<<cnt[c], TB, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
-        default: k_batched_id<TB, false, 4, 16><<<cnt[c], TB, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
+        case 4: k_batched_id<WNT, false, 2, 16, true><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
+        default: k_batched_id<WNT, false, 2, 16><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
         }
         H2_LAUNCH_CHECK();
     };
