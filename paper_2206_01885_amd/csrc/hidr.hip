@@ -280,8 +280,9 @@ template <int D, int MAXQ>
 __global__ __launch_bounds__(TB) void k_datareduct_down(
     int lo_node, const double* __restrict__ pts, int64_t ld, const int* __restrict__ parent,
     const int* __restrict__ il_ptr, const int* __restrict__ il_col, const double* __restrict__ center,
-    const double* __restrict__ side, const int* __restrict__ xs_cnt, const int* __restrict__ xs_idx, int r1,
-    int* __restrict__ ys_cnt, int* __restrict__ ys_idx, int ys_stride, int k)
+    const double* __restrict__ side, const int* __restrict__ xs_cnt, const int* __restrict__ xs_idx,
+    const double* __restrict__ xs_pts, int r1, int* __restrict__ ys_cnt, int* __restrict__ ys_idx, int ys_stride,
+    int k)
 {
     __shared__ double red[TB];
     __shared__ long long keys[MAXQ];
@@ -418,14 +419,14 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
             double w = (double)(2 * ta + 1) / (double)(2 * g);
             q[a] = lo[sg][a] + (hi[sg][a] - lo[sg][a]) * w;
         }
-        // (distance, position) minimum: the sequential scan's answer in any order
+        // (distance, position) minimum: the sequential scan's answer in any
+        // order; the point index is looked up from the position at the end
         double best = INFINITY;
-        int bpos = 0x7fffffff, bidx = -1;
-        auto consider = [&](double dd, int pos, int id) {
+        int bpos = 0x7fffffff;
+        auto consider = [&](double dd, int pos) {
             if (dd < best || (dd == best && pos < bpos)) {
                 best = dd;
                 bpos = pos;
-                bidx = id;
             }
         };
         auto dist = [&](const double* c3) {
@@ -446,29 +447,26 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
             }
             return lb;
         };
+        // X_j^* coordinates are read from their contiguous per-node copy
         auto scan_box = [&](int e) {
             const int c = bcnt[e];
-            const int* xj = xs_idx + (int64_t)bj[e] * r1;
+            const double* xj = xs_pts + (int64_t)bj[e] * D * r1;
             const int pos0 = np_ + boff[e];
             int m = 0;
             for (; m + PB <= c; m += PB) {
-                int id[PB];
                 double cx[PB][D];
-#pragma unroll
-                for (int z = 0; z < PB; ++z) id[z] = xj[m + z];
 #pragma unroll
                 for (int z = 0; z < PB; ++z)
 #pragma unroll
-                    for (int a = 0; a < D; ++a) cx[z][a] = pts[a * ld + id[z]];
+                    for (int a = 0; a < D; ++a) cx[z][a] = xj[a * r1 + m + z];
 #pragma unroll
-                for (int z = 0; z < PB; ++z) consider(dist(cx[z]), pos0 + m + z, id[z]);
+                for (int z = 0; z < PB; ++z) consider(dist(cx[z]), pos0 + m + z);
             }
             for (; m < c; ++m) {
-                const int id = xj[m];
                 double cx[D];
 #pragma unroll
-                for (int a = 0; a < D; ++a) cx[a] = pts[a * ld + id];
-                consider(dist(cx), pos0 + m, id);
+                for (int a = 0; a < D; ++a) cx[a] = xj[a * r1 + m];
+                consider(dist(cx), pos0 + m);
             }
         };
         // Y_p^*, then the box nearest to q, then every box not pruned
@@ -476,7 +474,7 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
             double cy[D];
 #pragma unroll
             for (int a = 0; a < D; ++a) cy[a] = stage_y ? yc[a][c] : pts[a * ld + yp[c]];
-            consider(dist(cy), c, yp[c]);
+            consider(dist(cy), c);
         }
         int e_first = -1;
         double lb_first = INFINITY;
@@ -492,6 +490,14 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
             if (e == e_first) continue;
             if (box_lb(e) * (1.0 - 1e-12) > best) continue;
             scan_box(e);
+        }
+        int bidx;
+        if (bpos < np_) {
+            bidx = yp[bpos];
+        } else {
+            const int qq = bpos - np_;
+            const int e = seg_of(boff, ne, qq);
+            bidx = xs_idx[(int64_t)bj[e] * r1 + (qq - boff[e])];
         }
         pick[t] = bidx;
         keys[t] = ((long long)bidx << 13) | t;
@@ -626,26 +632,40 @@ __global__ __launch_bounds__(TB) void k_up_fill(int lo, const int* __restrict__ 
 }
 
 template <int D>
-void launch_down_d(Handle& h, int lo, int nl, hipStream_t s)
+void launch_down_d(Handle& h, int lo, int nl, const double* xs_pts, hipStream_t s)
 {
     if (h.r2 <= 512)
         k_datareduct_down<D, 1024><<<nl, TB, 0, s>>>(lo, h.pts.p, h.n, h.parent.p, h.il_ptr.p, h.il_col.p,
-                                                     h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, h.r1, h.ys_cnt.p,
-                                                     h.ys_idx.p, h.ys_stride, h.r2);
+                                                     h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, xs_pts, h.r1,
+                                                     h.ys_cnt.p, h.ys_idx.p, h.ys_stride, h.r2);
     else
         k_datareduct_down<D, MAXQ_ALL><<<nl, TB, 0, s>>>(lo, h.pts.p, h.n, h.parent.p, h.il_ptr.p, h.il_col.p,
-                                                         h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, h.r1,
+                                                         h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, xs_pts, h.r1,
                                                          h.ys_cnt.p, h.ys_idx.p, h.ys_stride, h.r2);
 }
 
-void launch_down(Handle& h, int lo, int nl, hipStream_t s)
+void launch_down(Handle& h, int lo, int nl, const double* xs_pts, hipStream_t s)
 {
     if (h.d == 1)
-        launch_down_d<1>(h, lo, nl, s);
+        launch_down_d<1>(h, lo, nl, xs_pts, s);
     else if (h.d == 2)
-        launch_down_d<2>(h, lo, nl, s);
+        launch_down_d<2>(h, lo, nl, xs_pts, s);
     else
-        launch_down_d<3>(h, lo, nl, s);
+        launch_down_d<3>(h, lo, nl, xs_pts, s);
+}
+
+// Coordinates of every node's X_i^* in a contiguous copy,
+// xs_pts[(i * d + a) * r1 + m] = coordinate a of point xs_idx[i * r1 + m].
+__global__ __launch_bounds__(TB) void k_xs_coords(const double* __restrict__ pts, int64_t ld, int d,
+                                                  const int* __restrict__ xs_cnt, const int* __restrict__ xs_idx,
+                                                  int r1, double* __restrict__ xs_pts)
+{
+    const int i = blockIdx.x;
+    const int c = xs_cnt[i];
+    for (int m = threadIdx.x; m < c; m += TB) {
+        const int id = xs_idx[(int64_t)i * r1 + m];
+        for (int a = 0; a < d; ++a) xs_pts[((int64_t)i * d + a) * r1 + m] = pts[a * ld + id];
+    }
 }
 
 }  // namespace
@@ -693,10 +713,14 @@ void run_hidr(Handle& h)
                          h.r1, h.xs_cnt.p + lo, s);
     }
     if (h.r2 < 1 || h.r2 > MAXQ_ALL / 2) fail(H2_EUNSUPPORTED, "r2 must be in [1, 2048]");
+    DBuf<double> xs_pts;
+    xs_pts.ensure((size_t)nn * h.d * h.r1, s);
+    k_xs_coords<<<nn, TB, 0, s>>>(h.pts.p, h.n, h.d, h.xs_cnt.p, h.xs_idx.p, h.r1, xs_pts.p);
+    H2_LAUNCH_CHECK();
     DBuf<int> lnodes, split, tmp, tmp_cnt;
     for (int L = 1; L <= h.maxdepth; ++L) {
         int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
-        launch_down(h, lo, nl, s);
+        launch_down(h, lo, nl, xs_pts.p, s);
         H2_LAUNCH_CHECK();
         std::vector<int> longn;
         for (int i = lo; i < lo + nl; ++i)
