@@ -8,12 +8,14 @@ coupling and nearfield blocks) followed by one h2_matvec with 32 RHS, then
 h2_destroy.  Inputs are resident in HBM before the timed region starts.
 
 Printed: one JSON line with the whole-step throughput (Mpts/s), the build and
-apply figures, the roofline of the dominant kernel of the step (the batched
-interpolative decomposition of the wide nodes, k_batched_id<256>: FP64 vector
-ALU bound; HIP events on the build's stream), the same for the apply's
-coupling sweep (k_sweep, HBM bound; HIP events on the apply's stream), the
-sampled accuracy against the dense K x, and the CPU oracle timed on a bounded
-sample of the same workload.
+apply figures, the roofline of the dominant kernel of the step (the top-down
+DataReduct of HiDR, k_datareduct_down: its candidate coordinates against the
+HBM bandwidth; HIP events on the build's stream), the same for the wide-node
+interpolative decompositions (FP64 ALU bound) and the apply's coupling sweep
+(k_sweep, HBM bound; HIP events on the apply's stream), the sampled accuracy
+against the dense K x, and the CPU oracle timed on a bounded sample of the
+same workload.  --copy-calibration instead runs a plain device copy of 1 GiB
+(the reference for scaling the HBM counters of a profile).
 """
 from __future__ import annotations
 
@@ -31,6 +33,23 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
 FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def recorded_traffic(profile, source):
+    """HBM bytes per launch recorded in a counter summary under profiles/ (the
+    FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy), or None when the
+    kernel's source has changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, "profiles", profile)).read()
+        rec = {ln.split(":")[0].strip(): ln.split(":")[1].split()[0] for ln in text.splitlines()
+               if ln.startswith(("traffic_bytes_per_launch:", "source_sha256_prefix:"))}
+        digest = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()[:16]
+        if rec.get("source_sha256_prefix") != digest:
+            return None
+        return float(rec["traffic_bytes_per_launch"])
+    except (OSError, KeyError, IndexError, ValueError):
+        return None
 
 
 def id_roofline(flops, ms, kernel):
@@ -62,6 +81,8 @@ def parse():
     ap.add_argument("--nreq", type=int, default=64, help="requests of the serving workload")
     ap.add_argument("--load", type=float, default=0.5, help="serving: offered load as a fraction of saturation")
     ap.add_argument("--nprob", type=int, default=256, help="problems of the batched workload")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device to device (5 times), the reference for HBM counters")
     return ap.parse_args()
 
 
@@ -237,6 +258,16 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part "
               "of this build", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 2 * src.numel() * 8, "read_bytes": src.numel() * 8,
+                          "write_bytes": src.numel() * 8, "launches": 5}), flush=True)
+        return
     if args.workload == "batched":
         bench_batched(args)
         return
@@ -289,7 +320,8 @@ def main():
         builds.append(tb - ts)
         mvs.append(te - tb)
         coup.append(info["mv_coupling"] / 1e3)
-        idw.append((info["id_wide_flops"], info["id_wide_ms"], info["id_flops"], info["id_ms"]))
+        idw.append((info["id_wide_flops"], info["id_wide_ms"], info["id_flops"], info["id_ms"],
+                    info["hidr_down_bytes"], info["hidr_down_ms"]))
         if k == args.steps - 1:
             keep = (hd, info)
         else:
@@ -314,8 +346,19 @@ def main():
     achieved = coupling_bytes / t_coup / 1e9
     idw = np.array(idw)
     roof_id = id_roofline(float(idw[:, 0].mean()), float(idw[:, 1].mean()),
-                          "k_batched_id<256> (interpolative decompositions of the nodes with > 64 columns)")
+                          "k_id_fold + k_batched_id<512> (interpolative decompositions of the nodes with "
+                          "more than 64 columns)")
     roof_id_all = id_roofline(float(idw[:, 2].mean()), float(idw[:, 3].mean()), "k_batched_id (all classes)")
+    # dominant kernel: the top-down DataReduct, one launch per tree level
+    dr_bytes, dr_ms = float(idw[:, 4].mean()), float(idw[:, 5].mean())
+    dr_launches = info["maxdepth"]
+    dr_achieved = dr_bytes / (dr_ms / 1e3) / 1e9 if dr_ms > 0 else 0.0
+    roof_dr = {"kernel": "k_datareduct_down<3,1024> (HiDR top-down DataReduct)", "bound": "hbm",
+               "achieved": dr_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dr_achieved / HBM_PEAK_GBS,
+               "traffic": recorded_traffic("k_datareduct_down_cube3d-coulomb-n1048576_hbm-counters.md",
+                                           "paper_2206_01885_amd/csrc/hidr.hip"),
+               "launches_per_step": dr_launches, "ms_per_launch": dr_ms / dr_launches,
+               "bytes_per_launch": dr_bytes / dr_launches}
     mv_bytes = (info["bytes_B"] + info["bytes_D"] + info["bytes_U"] + 8 * nrhs * n * 4)
     build_s = float(np.mean(builds))
     mv_s = float(np.mean(mvs))
@@ -383,7 +426,8 @@ def main():
         "accuracy": {"e_dense_sampled_rows_max_rhs": e_rows, "e_dense_sampled_rows_mean_rhs": e_rows_mean,
                      "rows": int(args.rows)},
         "precision_f32": f32,
-        "roofline": roof_id,
+        "roofline": roof_dr,
+        "roofline_id_wide": roof_id,
         "roofline_id_all_classes": roof_id_all,
         "roofline_matvec": {"kernel": "k_sweep (coupling sweep of the apply)", "bound": "hbm", "achieved": achieved,
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,

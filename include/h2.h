@@ -62,8 +62,9 @@ typedef enum { H2_COULOMB = 0, H2_GAUSSIAN = 1, H2_EXPONENTIAL = 2, H2_MATERN32 
  *   calib_seed     seed of the random points used to choose r1, r2
  *   profile        1: h2_matvec records HIP events around each of its sweeps on
  *                  its stream, and the build around its launches of the
- *                  interpolative decompositions; h2_query then reports the
- *                  last apply's and the build's times                       */
+ *                  interpolative decompositions and of the top-down
+ *                  DataReduct; h2_query then reports the last apply's and the
+ *                  build's times                                            */
 typedef struct {
     double tau;
     int r1, r2;
@@ -153,6 +154,10 @@ typedef struct {
      * this handle's decompositions (pivoted QR to the rank found and the
      * solve for T); 0 otherwise */
     double id_ms, id_wide_ms, id_flops, id_wide_flops;
+    /* build with options.profile = 1: HIP-event time (ms) of the top-down
+     * DataReduct launches of HiDR, and the bytes of the candidate coordinates
+     * they reduce (each farfield list T_i counted once); 0 otherwise */
+    double hidr_down_ms, hidr_down_bytes;
 } h2_info;
 
 h2_status h2_query(h2_handle h, h2_info *info);

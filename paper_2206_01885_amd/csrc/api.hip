@@ -368,6 +368,8 @@ h2_status h2_query(h2_handle hd, h2_info* info)
     info->id_wide_ms = h.id_wide_ms;
     info->id_flops = h.id_flops;
     info->id_wide_flops = h.id_wide_flops;
+    info->hidr_down_ms = h.hidr_down_ms;
+    info->hidr_down_bytes = h.hidr_down_bytes;
     return H2_OK;
 }
 

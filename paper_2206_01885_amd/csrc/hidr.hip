@@ -654,6 +654,23 @@ void launch_down(Handle& h, int lo, int nl, const double* xs_pts, hipStream_t s)
         launch_down_d<3>(h, lo, nl, xs_pts, s);
 }
 
+// |T_i| for the nodes the top-down kernel reduces (interaction lists of at
+// most ILCAP entries; 0 for the others), for the profile.
+__global__ __launch_bounds__(TB) void k_down_len(int nn, const int* __restrict__ parent, const int* __restrict__ il_ptr,
+                                                 const int* __restrict__ il_col, const int* __restrict__ xs_cnt,
+                                                 const int* __restrict__ ys_cnt, int64_t* __restrict__ len)
+{
+    const int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= nn) return;
+    const int e0 = il_ptr[i], ne = il_ptr[i + 1] - e0;
+    int64_t l = 0;
+    if (i > 0 && ne <= ILCAP) {
+        l = parent[i] > 0 ? ys_cnt[parent[i]] : 0;
+        for (int e = 0; e < ne; ++e) l += xs_cnt[il_col[e0 + e]];
+    }
+    len[i] = l;
+}
+
 // Coordinates of every node's X_i^* in a contiguous copy,
 // xs_pts[(i * d + a) * r1 + m] = coordinate a of point xs_idx[i * r1 + m].
 __global__ __launch_bounds__(TB) void k_xs_coords(const double* __restrict__ pts, int64_t ld, int d,
@@ -718,9 +735,16 @@ void run_hidr(Handle& h)
     k_xs_coords<<<nn, TB, 0, s>>>(h.pts.p, h.n, h.d, h.xs_cnt.p, h.xs_idx.p, h.r1, xs_pts.p);
     H2_LAUNCH_CHECK();
     DBuf<int> lnodes, split, tmp, tmp_cnt;
+    std::vector<hipEvent_t> ev;  // around each level's launch (profile)
+    if (h.profile) {
+        ev.resize(2 * (size_t)(h.maxdepth + 1));
+        for (auto& e : ev) H2_HIP(hipEventCreate(&e));
+    }
     for (int L = 1; L <= h.maxdepth; ++L) {
         int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
+        if (h.profile) H2_HIP(hipEventRecord(ev[2 * L], s));
         launch_down(h, lo, nl, xs_pts.p, s);
+        if (h.profile) H2_HIP(hipEventRecord(ev[2 * L + 1], s));
         H2_LAUNCH_CHECK();
         std::vector<int> longn;
         for (int i = lo; i < lo + nl; ++i)
@@ -746,6 +770,28 @@ void run_hidr(Handle& h)
         datareduct_lists(h.pts.p, h.n, h.d, off.p, list.p, split.p, nlong, h.r2, tmp.p, h.ys_stride, tmp_cnt.p, s);
         k_rows_scatter<<<nlong, TB, 0, s>>>(lnodes.p, tmp_cnt.p, tmp.p, h.ys_stride, h.ys_cnt.p, h.ys_idx.p);
         H2_LAUNCH_CHECK();
+    }
+    if (h.profile) {
+        // candidate bytes of the nodes the top-down kernel reduced:
+        // |T_i| = |Y_p^*| + sum over IL(i) of |X_j^*| coordinates of d doubles
+        DBuf<int64_t> len;
+        len.ensure((size_t)nn, s);
+        k_down_len<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.parent.p, h.il_ptr.p, h.il_col.p, h.xs_cnt.p, h.ys_cnt.p,
+                                                     len.p);
+        H2_LAUNCH_CHECK();
+        std::vector<int64_t> hl((size_t)nn);
+        H2_HIP(hipMemcpyAsync(hl.data(), len.p, sizeof(int64_t) * nn, hipMemcpyDeviceToHost, s));
+        H2_HIP(hipStreamSynchronize(s));
+        double tot = 0;
+        for (int64_t v : hl) tot += (double)v;
+        h.hidr_down_bytes = tot * h.d * sizeof(double);
+        h.hidr_down_ms = 0;
+        for (int L = 1; L <= h.maxdepth; ++L) {
+            float ms = 0.f;
+            H2_HIP(hipEventElapsedTime(&ms, ev[2 * L], ev[2 * L + 1]));
+            h.hidr_down_ms += ms;
+        }
+        for (auto& e : ev) H2_HIP(hipEventDestroy(e));
     }
     H2_HIP(hipStreamSynchronize(s));
 }

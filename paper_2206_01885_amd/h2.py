@@ -51,7 +51,8 @@ class h2_info(C.Structure):
                 ("t_blocks", C.c_double), ("mv_gather", C.c_double), ("mv_upward", C.c_double),
                 ("mv_coupling", C.c_double), ("mv_downward", C.c_double), ("mv_leaves", C.c_double),
                 ("mv_scatter", C.c_double), ("mv_nrhs", C.c_int), ("id_ms", C.c_double),
-                ("id_wide_ms", C.c_double), ("id_flops", C.c_double), ("id_wide_flops", C.c_double)]
+                ("id_wide_ms", C.c_double), ("id_flops", C.c_double), ("id_wide_flops", C.c_double),
+                ("hidr_down_ms", C.c_double), ("hidr_down_bytes", C.c_double)]
 
 
 SYMBOLS = ["h2_options_default", "h2_build", "h2_build_ex", "h2_build_batched", "h2_matvec", "h2_matvec_ex",
