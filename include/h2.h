@@ -120,6 +120,22 @@ h2_status h2_build_batched(int nprob, const double *const *points, const int64_t
                            const int *kernel_id, const double *params, const double *tol, const int *leaf_size,
                            const h2_options *opt, void *hip_stream, h2_handle *out);
 
+/* h2_rebuild: the representation of another kernel, kernel parameter or
+ * tolerance on the same points, from the representor sets already computed
+ * (Section 6, "HiDR once for all": HiDR depends on the points only, so a
+ * kernel family -- e.g. the bandwidths of a Gaussian-process search -- needs
+ * it once).  Keeps the tree, the lists, r1, r2 and every X_i^*, Y_i^*;
+ * recomputes Algorithm 2 from the kernel blocks on: interpolative
+ * decompositions, skeletons, coupling and nearfield blocks.  The result is
+ * what h2_build_ex would return for the new kernel and tolerance with the
+ * options r1, r2 set to this handle's values (r1, r2 are not recalibrated
+ * for the new kernel).
+ *   h          a built handle; its previous bases and blocks are replaced
+ *   kernel_id, params, tol   as in h2_build
+ * Waits for the handle's last apply; synchronises its stream.  On failure
+ * the handle is left unusable for h2_matvec (h2_destroy still works).     */
+h2_status h2_rebuild(h2_handle h, int kernel_id, const double *params, double tol);
+
 /* h2_matvec: y = Ktilde x with the H^2 representation (upward, coupling,
  * downward and nearfield sweeps).
  *   x, y   device, [nrhs][n] (x[r*n + i] is entry i of right-hand side r),

@@ -196,6 +196,43 @@ h2_status h2_build_ex(const double* points, int64_t n, int dim, int kernel_id, c
     return H2_OK;
 }
 
+h2_status h2_rebuild(h2_handle hd, int kernel_id, const double* params, double tol)
+{
+    if (!hd) return set_err(H2_EINVAL, "handle is NULL");
+    if (kernel_id < H2_COULOMB || kernel_id > H2_MATERN32) return set_err(H2_EINVAL, "unknown kernel_id");
+    if (!(tol > 0.0 && tol < 1.0)) return set_err(H2_EINVAL, "tol must be in (0, 1)");
+    double prm = 1.0;
+    if (kernel_id != H2_COULOMB) {
+        if (!params) return set_err(H2_EINVAL, "params is NULL");
+        prm = params[0];
+        if (!(std::isfinite(prm) && prm > 0.0)) return set_err(H2_EINVAL, "params[0] must be finite and > 0");
+    }
+    h2::Handle& h = hd->h;
+    try {
+        // the buffers an apply in flight reads are about to be replaced
+        if (h.mv_done) H2_HIP(hipEventSynchronize(h.mv_done));
+        H2_HIP(hipStreamSynchronize(h.stream));
+        h.ready = false;
+        h.kid = kernel_id;
+        h.prm = prm;
+        h.tol = tol;
+        h.tol_int = 0.5 * tol;
+        h.mv_ld = 0;  // the apply workspace follows the new ranks
+        h.prof_valid = false;
+        h.id_ms = h.id_wide_ms = h.id_flops = h.id_wide_flops = 0;
+        double t0 = now_s();
+        h2::build_bases(h);
+        h.t_basis = now_s() - t0;
+        build_back(h);
+        h.ready = true;
+    } catch (const h2::Error& e) {
+        return set_err(e.code, e.msg);
+    } catch (const std::bad_alloc&) {
+        return set_err(H2_ENOMEM, "host allocation failed");
+    }
+    return H2_OK;
+}
+
 h2_status h2_build_batched(int nprob, const double* const* points, const int64_t* n, const int* dim,
                            const int* kernel_id, const double* params, const double* tol, const int* leaf_size,
                            const h2_options* opt_in, void* hip_stream, h2_handle* out)
@@ -301,6 +338,7 @@ h2_status h2_matvec_ex(h2_handle hd, const void* x, void* y, int nrhs, void* hip
 {
     if (!hd) return set_err(H2_EINVAL, "handle is NULL");
     if (!x || !y) return set_err(H2_EINVAL, "x or y is NULL");
+    if (!hd->h.ready) return set_err(H2_EINVAL, "the handle holds no representation (a rebuild failed)");
     if (nrhs < 1 || nrhs > 256) return set_err(H2_EINVAL, "nrhs must be in [1, 256]");
     h2::Handle& h = hd->h;
     const size_t bytes = (size_t)h.n * nrhs * (h.precision == 32 ? sizeof(float) : sizeof(double));

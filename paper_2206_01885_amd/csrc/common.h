@@ -203,6 +203,7 @@ struct Handle {
 
     // matvec workspace (sized for the largest nrhs seen)
     int mv_ld = 0;  // column stride the apply buffers are sized for
+    bool ready = true;  // false while (or after a failed) h2_rebuild
     hipEvent_t mv_done = nullptr;  // recorded after every apply (waited for at destroy)
     DBuf<double> xt, yt, xh, yh;
     DBuf<float> xtf, ytf, xhf, yhf;

@@ -55,8 +55,8 @@ class h2_info(C.Structure):
                 ("hidr_down_ms", C.c_double), ("hidr_down_bytes", C.c_double)]
 
 
-SYMBOLS = ["h2_options_default", "h2_build", "h2_build_ex", "h2_build_batched", "h2_matvec", "h2_matvec_ex",
-           "h2_query", "h2_export", "h2_destroy", "h2_last_error"]
+SYMBOLS = ["h2_options_default", "h2_build", "h2_build_ex", "h2_build_batched", "h2_rebuild", "h2_matvec",
+           "h2_matvec_ex", "h2_query", "h2_export", "h2_destroy", "h2_last_error"]
 
 _lib = None
 
@@ -80,6 +80,8 @@ def lib():
         L.h2_build_batched.restype = C.c_int
         L.h2_build_batched.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(C.c_int64), ip, ip, dp, dp, ip,
                                        C.POINTER(h2_options), vp, C.POINTER(vp)]
+        L.h2_rebuild.restype = C.c_int
+        L.h2_rebuild.argtypes = [vp, C.c_int, dp, C.c_double]
         L.h2_matvec.restype = C.c_int
         L.h2_matvec.argtypes = [vp, vp, vp, C.c_int]
         L.h2_matvec_ex.restype = C.c_int
@@ -143,6 +145,14 @@ def h2_build_batched(points_list, kernels, params, tols, leaf_sizes, options=Non
     out = (C.c_void_p * k)()
     _check(lib().h2_build_batched(k, ptrs, ns, dims, kids, prms, tl, lf, C.byref(opt), _stream_ptr(stream), out))
     return [C.c_void_p(out[i]) for i in range(k)]
+
+
+def h2_rebuild(handle, kernel_id, params, tol):
+    """C ABI h2_rebuild: another kernel / parameter / tolerance on the same
+    representor sets (tree, lists, r1, r2, X*, Y* kept)."""
+    kid = KERNELS[kernel_id] if isinstance(kernel_id, str) else int(kernel_id)
+    prm = (C.c_double * 1)(float(params))
+    _check(lib().h2_rebuild(handle, kid, prm, float(tol)))
 
 
 def h2_matvec(handle, x: torch.Tensor, y: torch.Tensor, nrhs: int, stream=None):

@@ -305,6 +305,41 @@ def test_serving_mix_equals_solo(H):
         assert diff <= 1e-6
 
 
+def test_rebuild_reuses_representor_sets(H):
+    """h2_rebuild (HiDR once for all): a representation rebuilt for another
+    kernel, bandwidth and tolerance from the same representor sets equals a
+    fresh build of that kernel with the same r1, r2 (bit for bit), and its
+    product matches the oracle's within 1e-10."""
+    import torch
+    rng = np.random.default_rng(31)
+    n = 3000
+    P = rng.random((n, 3))
+    x = rng.standard_normal((2, n))
+    _say("rebuild: gaussian 0.1 -> exponential 0.2 -> gaussian 0.3")
+    g = H.H2Matrix(P, "gaussian", 0.1, 1e-6, 64)
+    r1, r2 = g.info()["r1"], g.info()["r2"]
+    xs0 = [g.export("xstar", i) for i in range(len(g.export("parent")))]
+    for kern, prm, tol in (("exponential", 0.2, 1e-7), ("gaussian", 0.3, 1e-5)):
+        H.h2_rebuild(g.handle, kern, prm, tol)
+        f = H.H2Matrix(P, kern, prm, tol, 64, r1=r1, r2=r2)
+        for name in ("perm", "il_col", "near_col", "rank", "mbar"):
+            a, b = g.export(name), f.export(name)
+            assert a.shape == b.shape and np.array_equal(a, b), name
+        for i in range(len(f.export("parent"))):
+            assert np.array_equal(g.export("xstar", i), xs0[i])
+            for name in ("piv", "skel", "T", "ystar"):
+                a, b = g.export(name, i), f.export(name, i)
+                assert a.shape == b.shape and np.array_equal(a, b), (kern, name, i)
+        yg = g.matvec(x).cpu().numpy()
+        yf = f.matvec(x).cpu().numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(yg, yf)
+        o = O.H2Oracle(P, kern, prm, tol=tol, leaf=64, r1=r1, r2=r2)
+        assert _rel(yg[0], o.matvec(x[0])[0]) <= 1e-10
+        f.close()
+    g.close()
+
+
 def test_long_interaction_lists(H):
     """Clustered points (8-component Gaussian mixture, leaf 8) give nodes with
     more than 640 interaction-list entries, which take the materialised HiDR

@@ -89,3 +89,16 @@ def test_batched_validation_without_device_work():
     assert L.h2_build_batched(k, pts, ns, dims, kids, prms, tols, leaf, None, None, out) == h2.H2_EINVAL
     assert b"problem 2" in L.h2_last_error()
     assert L.h2_build_batched(k, None, ns, dims, kids, prms, tols, leaf, None, None, out) == h2.H2_EINVAL
+
+
+def test_rebuild_validation_without_device_work():
+    from paper_2206_01885_amd import h2
+    L = h2.lib()
+    dummy = C.c_void_p(8)  # never dereferenced: validation fails first
+    prm = (C.c_double * 1)(0.1)
+    assert L.h2_rebuild(None, 1, prm, 1e-6) == h2.H2_EINVAL
+    assert L.h2_rebuild(dummy, 99, prm, 1e-6) == h2.H2_EINVAL
+    assert L.h2_rebuild(dummy, 1, prm, 2.0) == h2.H2_EINVAL
+    assert L.h2_rebuild(dummy, 1, None, 1e-6) == h2.H2_EINVAL
+    prm[0] = float("nan")
+    assert L.h2_rebuild(dummy, 1, prm, 1e-6) == h2.H2_EINVAL
