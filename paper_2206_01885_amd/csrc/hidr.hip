@@ -406,96 +406,138 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     for (int a = 0; a < d; ++a) nq1 *= g;
     const int nq = nq1 * nseg;
 
+    // A lane's reference points (t = lane + TB u) go through every phase
+    // together, so each candidate and each box is read once per lane.
+    double qv[QPT][D];
+    double best[QPT];
+    int bpos[QPT];
+    bool act[QPT];
+#pragma unroll
     for (int u = 0; u < QPT; ++u) {
         const int t = threadIdx.x + u * TB;
-        if (t >= nq) break;
-        const int sg = t / nq1;
-        int rem = t - sg * nq1;
-        double q[D];
+        act[u] = t < nq;
+        const int tq = act[u] ? t : 0;
+        const int sg = tq / nq1;
+        int rem = tq - sg * nq1;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             int ta = rem % g;
             rem /= g;
             double w = (double)(2 * ta + 1) / (double)(2 * g);
-            q[a] = lo[sg][a] + (hi[sg][a] - lo[sg][a]) * w;
+            qv[u][a] = lo[sg][a] + (hi[sg][a] - lo[sg][a]) * w;
         }
-        // (distance, position) minimum: the sequential scan's answer in any
-        // order; the point index is looked up from the position at the end
-        double best = INFINITY;
-        int bpos = 0x7fffffff;
-        auto consider = [&](double dd, int pos) {
-            if (dd < best || (dd == best && pos < bpos)) {
-                best = dd;
-                bpos = pos;
-            }
-        };
-        auto dist = [&](const double* c3) {
-            double dd = 0.0;
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                double ea = q[a] - c3[a];
-                dd = dd + ea * ea;
-            }
-            return dd;
-        };
-        auto box_lb = [&](int e) {
-            double lb = 0.0;
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                double ex = fabs(q[a] - bx[a][e]) - bh[e];
-                if (ex > 0.0) lb = lb + ex * ex;
-            }
-            return lb;
-        };
-        // X_j^* coordinates are read from their contiguous per-node copy
-        auto scan_box = [&](int e) {
-            const int c = bcnt[e];
-            const double* xj = xs_pts + (int64_t)bj[e] * D * r1;
-            const int pos0 = np_ + boff[e];
-            int m = 0;
-            for (; m + PB <= c; m += PB) {
-                double cx[PB][D];
-#pragma unroll
-                for (int z = 0; z < PB; ++z)
-#pragma unroll
-                    for (int a = 0; a < D; ++a) cx[z][a] = xj[a * r1 + m + z];
-#pragma unroll
-                for (int z = 0; z < PB; ++z) consider(dist(cx[z]), pos0 + m + z);
-            }
-            for (; m < c; ++m) {
-                double cx[D];
-#pragma unroll
-                for (int a = 0; a < D; ++a) cx[a] = xj[a * r1 + m];
-                consider(dist(cx), pos0 + m);
-            }
-        };
-        // Y_p^*, then the box nearest to q, then every box not pruned
-        for (int c = 0; c < np_; ++c) {
-            double cy[D];
-#pragma unroll
-            for (int a = 0; a < D; ++a) cy[a] = stage_y ? yc[a][c] : pts[a * ld + yp[c]];
-            consider(dist(cy), c);
+        best[u] = INFINITY;
+        bpos[u] = 0x7fffffff;
+    }
+    // (distance, position) minimum: the sequential scan's answer in any
+    // order; the point index is looked up from the position at the end
+    auto consider = [&](int u, double dd, int pos) {
+        if (dd < best[u] || (dd == best[u] && pos < bpos[u])) {
+            best[u] = dd;
+            bpos[u] = pos;
         }
-        int e_first = -1;
-        double lb_first = INFINITY;
-        for (int e = 0; e < ne; ++e) {
-            const double lb = box_lb(e);
-            if (lb < lb_first) {
-                lb_first = lb;
-                e_first = e;
+    };
+    auto dist = [&](int u, const double* c3) {
+        double dd = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            double ea = qv[u][a] - c3[a];
+            dd = dd + ea * ea;
+        }
+        return dd;
+    };
+    auto box_lb = [&](int u, const double* bc, double h) {
+        double lb = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            double ex = fabs(qv[u][a] - bc[a]) - h;
+            if (ex > 0.0) lb = lb + ex * ex;
+        }
+        return lb;
+    };
+    // box e for the reference points in mask (bit u); X_j^* coordinates are
+    // read from their contiguous per-node copy
+    auto scan_box = [&](int e, unsigned mask) {
+        const int c = bcnt[e];
+        const double* xj = xs_pts + (int64_t)bj[e] * D * r1;
+        const int pos0 = np_ + boff[e];
+        int m = 0;
+        for (; m + PB <= c; m += PB) {
+            double cx[PB][D];
+#pragma unroll
+            for (int z = 0; z < PB; ++z)
+#pragma unroll
+                for (int a = 0; a < D; ++a) cx[z][a] = xj[a * r1 + m + z];
+#pragma unroll
+            for (int u = 0; u < QPT; ++u)
+                if (mask & (1u << u))
+#pragma unroll
+                    for (int z = 0; z < PB; ++z) consider(u, dist(u, cx[z]), pos0 + m + z);
+        }
+        for (; m < c; ++m) {
+            double cx[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) cx[a] = xj[a * r1 + m];
+#pragma unroll
+            for (int u = 0; u < QPT; ++u)
+                if (mask & (1u << u)) consider(u, dist(u, cx), pos0 + m);
+        }
+    };
+    // Y_p^*
+    for (int c = 0; c < np_; ++c) {
+        double cy[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) cy[a] = stage_y ? yc[a][c] : pts[a * ld + yp[c]];
+#pragma unroll
+        for (int u = 0; u < QPT; ++u)
+            if (act[u]) consider(u, dist(u, cy), c);
+    }
+    // each reference point's nearest box first (it prunes best), then every
+    // box its bound admits
+    int e_first[QPT];
+    double lb_first[QPT];
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) {
+        e_first[u] = -1;
+        lb_first[u] = INFINITY;
+    }
+    for (int e = 0; e < ne; ++e) {
+        double bc[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) bc[a] = bx[a][e];
+        const double h = bh[e];
+#pragma unroll
+        for (int u = 0; u < QPT; ++u) {
+            const double lb = box_lb(u, bc, h);
+            if (lb < lb_first[u]) {
+                lb_first[u] = lb;
+                e_first[u] = e;
             }
         }
-        if (e_first >= 0 && lb_first * (1.0 - 1e-12) <= best) scan_box(e_first);
-        for (int e = 0; e < ne; ++e) {
-            if (e == e_first) continue;
-            if (box_lb(e) * (1.0 - 1e-12) > best) continue;
-            scan_box(e);
-        }
+    }
+#pragma unroll
+    for (int u = 0; u < QPT; ++u)
+        if (act[u] && e_first[u] >= 0 && lb_first[u] * (1.0 - 1e-12) <= best[u]) scan_box(e_first[u], 1u << u);
+    for (int e = 0; e < ne; ++e) {
+        double bc[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) bc[a] = bx[a][e];
+        const double h = bh[e];
+        unsigned mask = 0;
+#pragma unroll
+        for (int u = 0; u < QPT; ++u)
+            if (act[u] && e != e_first[u] && box_lb(u, bc, h) * (1.0 - 1e-12) <= best[u]) mask |= 1u << u;
+        if (mask) scan_box(e, mask);
+    }
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) {
+        if (!act[u]) continue;
+        const int t = threadIdx.x + u * TB;
         int bidx;
-        if (bpos < np_) {
-            bidx = yp[bpos];
+        if (bpos[u] < np_) {
+            bidx = yp[bpos[u]];
         } else {
-            const int qq = bpos - np_;
+            const int qq = bpos[u] - np_;
             const int e = seg_of(boff, ne, qq);
             bidx = xs_idx[(int64_t)bj[e] * r1 + (qq - boff[e])];
         }
