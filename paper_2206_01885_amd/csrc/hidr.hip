@@ -259,7 +259,7 @@ __global__ __launch_bounds__(TB) void k_datareduct(const double* __restrict__ pt
 // their materialised T_i by k_datareduct (same reference set, distances, tie
 // rule and output).
 constexpr int ILCAP = 640;  // interaction-list entries staged per node
-constexpr int YCAP = 1024;  // Y_p^* points staged per node
+constexpr int YCAP = 768;   // Y_p^* points staged per node
 constexpr int PB = 8;       // candidate loads issued ahead
 
 __device__ __forceinline__ int seg_of(const int* __restrict__ off, int n, int p)
@@ -285,13 +285,18 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     int k)
 {
     __shared__ double red[TB];
-    __shared__ long long keys[MAXQ];
-    __shared__ int pick[MAXQ];
     __shared__ int scan_sh[TB];
     __shared__ double bx[3][ILCAP];
     __shared__ double bh[ILCAP];
     __shared__ int bj[ILCAP], bcnt[ILCAP], boff[ILCAP + 1];
     __shared__ double yc[3][YCAP];
+    // the sort keys and picks reuse the staged Y_p^* once the searches are
+    // done (when they fit), which keeps three workgroups per CU
+    constexpr bool ALIAS = 3 * YCAP * sizeof(double) >= MAXQ * (sizeof(long long) + sizeof(int));
+    __shared__ long long keys_own[ALIAS ? 1 : MAXQ];
+    __shared__ int pick_own[ALIAS ? 1 : MAXQ];
+    long long* keys = ALIAS ? (long long*)&yc[0][0] : keys_own;
+    int* pick = ALIAS ? (int*)((long long*)&yc[0][0] + MAXQ) : pick_own;
     constexpr int QPT = MAXQ / TB;
     constexpr int d = D;
 
@@ -529,6 +534,7 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
             if (act[u] && e != e_first[u] && box_lb(u, bc, h) * (1.0 - 1e-12) <= best[u]) mask |= 1u << u;
         if (mask) scan_box(e, mask);
     }
+    __syncthreads();  // every lane is done with Y_p^* (keys and picks reuse it)
 #pragma unroll
     for (int u = 0; u < QPT; ++u) {
         if (!act[u]) continue;
