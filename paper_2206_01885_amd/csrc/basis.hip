@@ -937,7 +937,7 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
     struct Cls {
         int nt, cpl, br;
     };
-    const Cls CL[5] = {{64, 1, 16}, {64, 1, 16}, {WNT, 2, 16}, {64, 1, 16}, {WNT, 2, 16}};
+    const Cls CL[5] = {{64, 1, 32}, {64, 1, 16}, {WNT, 2, 16}, {64, 1, 32}, {WNT, 2, 16}};
     const int BROWS = 64;                 // compression row block (at most)
     const size_t LDS_CAP = 80 * 1024;     // bytes per workgroup
     auto lds_need = [&](const IdTask& t, int c) -> size_t {
@@ -1007,7 +1007,7 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
         const int* ord = d_order.p + off[c];
         switch (c) {
         case 0:
-        case 3: k_batched_id<64, true, 1, 16><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
+        case 3: k_batched_id<64, true, 1, 32><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
         case 1: k_batched_id<64, false, 1, 16><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
         case 4: k_batched_id<WNT, false, 2, 16, true><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
         default: k_batched_id<WNT, false, 2, 16><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
@@ -1019,7 +1019,7 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
     launch(1);
     if (prof) H2_HIP(hipEventRecord(ev[1], s));
     if (!fold[0].empty())
-        k_id_fold<1, 16, 1><<<(unsigned)fold[0].size(), 256, (2 * 16 + 4 + 8 * 256) * sizeof(double), s>>>(
+        k_id_fold<1, 32, 1><<<(unsigned)fold[0].size(), 256, (2 * 32 + 4 + 8 * 256) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[0]);
     if (!fold[1].empty())
         k_id_fold<2, 16, 1><<<(unsigned)fold[1].size(), 256, (2 * 16 + 4 + 8 * 256) * sizeof(double), s>>>(
