@@ -286,8 +286,11 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
 {
     __shared__ double red[TB];
     __shared__ int scan_sh[TB];
-    __shared__ double bx[3][ILCAP];
-    __shared__ double bh[ILCAP];
+    // box table in FP32, rounded outward (centre to nearest, half side up by
+    // the centre's rounding and one more ulp): every box it describes contains
+    // the true box, so its distance stays a lower bound and the pruning exact
+    __shared__ float bx[3][ILCAP];
+    __shared__ float bh[ILCAP];
     __shared__ int bj[ILCAP], bcnt[ILCAP], boff[ILCAP + 1];
     __shared__ double yc[3][YCAP];
     // the sort keys and picks reuse the staged Y_p^* once the searches are
@@ -313,8 +316,17 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
         const int j = il_col[e0 + e];
         bj[e] = j;
         bcnt[e] = xs_cnt[j];
-        bh[e] = 0.5 * side[j];
-        for (int a = 0; a < d; ++a) bx[a][e] = center[(int64_t)j * d + a];
+        double err = 0.0;
+        for (int a = 0; a < d; ++a) {
+            const double c = center[(int64_t)j * d + a];
+            const float cf = (float)c;
+            bx[a][e] = cf;
+            err = fmax(err, fabs(c - (double)cf));
+        }
+        const double hh = 0.5 * side[j] + err;
+        float hf = (float)hh;
+        if ((double)hf < hh) hf = nextafterf(hf, INFINITY);
+        bh[e] = nextafterf(hf, INFINITY);
     }
     const bool stage_y = np_ <= YCAP;
     if (stage_y)
@@ -509,8 +521,8 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     for (int e = 0; e < ne; ++e) {
         double bc[D];
 #pragma unroll
-        for (int a = 0; a < D; ++a) bc[a] = bx[a][e];
-        const double h = bh[e];
+        for (int a = 0; a < D; ++a) bc[a] = (double)bx[a][e];
+        const double h = (double)bh[e];
 #pragma unroll
         for (int u = 0; u < QPT; ++u) {
             const double lb = box_lb(u, bc, h);
@@ -526,8 +538,8 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     for (int e = 0; e < ne; ++e) {
         double bc[D];
 #pragma unroll
-        for (int a = 0; a < D; ++a) bc[a] = bx[a][e];
-        const double h = bh[e];
+        for (int a = 0; a < D; ++a) bc[a] = (double)bx[a][e];
+        const double h = (double)bh[e];
         unsigned mask = 0;
 #pragma unroll
         for (int u = 0; u < QPT; ++u)
