@@ -931,22 +931,23 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
     //   0 / 3  64 lanes, matrix in LDS, m <= 64 (split at 32 KiB of LDS so that
     //          small problems are not limited to the occupancy of the largest)
     //   1      64 lanes, global matrix, m <= 64
-    //   4      64 < m <= 1024 and s > m: compression by k_id_fold (many
-    //          tasks per CU), then the pivoted QR of the m x m factor
-    //   2      256 lanes, global matrix, the other wide nodes
+    //   4 / 5  64 < m <= 1024 and s > 1.5 m: compression by k_id_fold (many
+    //          tasks per CU), then the blocked pivoted QR of the m x m
+    //          factor on 512 lanes, or 256 when m <= 256 (two tasks per CU)
+    //   2      512 lanes, global matrix, the other wide nodes
     struct Cls {
         int nt, cpl, br;
     };
-    const Cls CL[5] = {{64, 1, 32}, {64, 1, 16}, {WNT, 2, 16}, {64, 1, 32}, {WNT, 2, 16}};
+    const Cls CL[6] = {{64, 1, 32}, {64, 1, 16}, {WNT, 2, 16}, {64, 1, 32}, {WNT, 2, 16}, {256, 1, 16}};
     const int BROWS = 64;                 // compression row block (at most)
     const size_t LDS_CAP = 80 * 1024;     // bytes per workgroup
     auto lds_need = [&](const IdTask& t, int c) -> size_t {
         const Cls& k = CL[c];
-        const bool comp = c == 4 || compress_rows(t.s, t.m, k.cpl * k.nt);
+        const bool comp = c == 4 || c == 5 || compress_rows(t.s, t.m, k.cpl * k.nt);
         const int sr = comp ? t.m : t.s;
         // the blocked pivoted QR keeps the norms and panel scratch in LDS
         const size_t qr = use_blocked(sr, t.m, k.cpl * k.nt, k.nt, QR_NB) ? cpqr_blocked_lds(sr, t.m, k.nt, QR_NB) : 0;
-        if (c == 4) return std::max((size_t)sr, qr) * sizeof(double);
+        if (c == 4 || c == 5) return std::max((size_t)sr, qr) * sizeof(double);
         // published column (2 x BR), its norms and diagonal entries (2 x 2),
         // the lanes' evaluation slices
         const size_t pub = comp ? 2 * k.br + 4 + (size_t)k.br * k.nt : 0;
@@ -957,19 +958,20 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
     for (int p = 0; p < np; ++p) {
         const IdTask& t = tasks[p];
         if (t.m > 64) {
-            cls[p] = compress_rows(t.s, t.m, 4 * TB) ? 4 : 2;
-            tasks[p].folded = cls[p] == 4 ? 1 : 0;
+            const bool comp = compress_rows(t.s, t.m, 4 * TB);
+            cls[p] = comp ? (t.m <= 256 ? 5 : 4) : 2;
+            tasks[p].folded = comp ? 1 : 0;
         } else {
             const size_t need = lds_need(t, 0);
             cls[p] = need <= 32 * 1024 ? 0 : (need <= LDS_CAP ? 3 : 1);
         }
     }
     // narrow classes first, then the wide ones (timed together)
-    const int ORD[5] = {0, 3, 1, 4, 2};
+    const int ORD[6] = {0, 3, 1, 5, 4, 2};
     std::vector<int> order;
     order.reserve(np);
-    int cnt[5] = {0, 0, 0, 0, 0}, off[5] = {0, 0, 0, 0, 0};
-    size_t lds[5] = {8, 8, 8, 8, 8};
+    int cnt[6] = {0, 0, 0, 0, 0, 0}, off[6] = {0, 0, 0, 0, 0, 0};
+    size_t lds[6] = {8, 8, 8, 8, 8, 8};
     for (int c : ORD) {
         off[c] = (int)order.size();
         for (int p = 0; p < np; ++p)
@@ -981,9 +983,9 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
     }
     // the tall wide blocks to compress, grouped by columns per lane
     std::vector<int> fold[3];
-    for (int q = off[4]; q < off[4] + cnt[4]; ++q) {
-        const IdTask& t = tasks[order[q]];
-        if (t.folded) fold[t.m <= 256 ? 0 : (t.m <= 512 ? 1 : 2)].push_back(order[q]);
+    for (int p = 0; p < np; ++p) {
+        const IdTask& t = tasks[p];
+        if (t.folded) fold[t.m <= 256 ? 0 : (t.m <= 512 ? 1 : 2)].push_back(p);
     }
     int foff[3] = {0, 0, 0}, nfold = 0;
     for (int g = 0; g < 3; ++g) {
@@ -1010,6 +1012,7 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
         case 3: k_batched_id<64, true, 1, 32><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
         case 1: k_batched_id<64, false, 1, 16><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
         case 4: k_batched_id<WNT, false, 2, 16, true><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
+        case 5: k_batched_id<256, false, 1, 16, true><<<cnt[c], 256, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
         default: k_batched_id<WNT, false, 2, 16><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
         }
         H2_LAUNCH_CHECK();
@@ -1028,6 +1031,7 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
         k_id_fold<4, 8, 1><<<(unsigned)fold[2].size(), 256, (2 * 8 + 4 + 8 * 256) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[2]);
     H2_LAUNCH_CHECK();
+    launch(5);
     launch(4);
     launch(2);
     if (prof) H2_HIP(hipEventRecord(ev[2], s));
