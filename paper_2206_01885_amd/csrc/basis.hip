@@ -188,23 +188,20 @@ __device__ __forceinline__ double axpy_rows(const double* __restrict__ v, double
     return tail;
 }
 
-// NT = 64 (one wavefront, for row sets of at most 64 points) or 256 lanes.
-// LDSM: the s x m block lives in LDS (dynamic shared memory after the
-// reflector), otherwise in the global workspace.  The arithmetic is the same.
-// Compression (s > m): the s x m block is streamed in blocks of BR rows and
-// folded into the m x m upper triangle R (LDS or global) by Householder
-// reflectors that each zero one column of the block against the diagonal
-// entry of R (TSQR).  Lane l owns columns l, l + NT, ... (CPL of them) and
+// Compression of a tall block (TSQR): the s x m block is streamed in blocks
+// of BR rows and folded into the m x m upper triangle R (LDS or global) by
+// Householder reflectors that each zero one column of the block against the
+// diagonal entry of R.  Lane l owns columns l, l + NT, ... (CPL of them) and
 // keeps their BR block entries in registers, evaluating them itself; the
 // column that step j eliminates, its squared norm and the diagonal entry
 // R[j][j] are published in a double-buffered LDS slot by the column's owner
 // at the end of step j - 1, so one barrier per step suffices.  The R entries
-// of the next row are loaded a step ahead.  (This part
-// accumulates with fused multiply-adds; it is not the oracle's operation
-// order, and need not be: pivots and T are fixed up to rounding.)
-// R is an LDS pointer or a gdouble pointer.  Every R entry is read and written
-// by the lane that owns its column only (the diagonal entry reaches the other
-// lanes through LDS), so the steps need LDS barriers only.
+// of the next row are loaded a step ahead.  (This part accumulates with fused
+// multiply-adds; it is not the oracle's operation order, and need not be:
+// pivots and T are fixed up to rounding.)  R is an LDS pointer or a gdouble
+// pointer.  Every R entry is read and written by the lane that owns its
+// column only (the diagonal entry reaches the other lanes through LDS), so
+// the steps need LDS barriers only.
 template <int NT, int CPL, int BR, class RPtr>
 __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbuf, double* nubuf, double* scr)
 {
@@ -311,13 +308,6 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbu
     __syncthreads();  // R complete and visible to every lane
 }
 
-// NT = 64 (one wavefront; the matrix in LDS) or 256 lanes (global matrix).
-// LDSM: the matrix the pivoted QR runs on lives in LDS (dynamic shared
-// memory after the reflector), otherwise in the global workspace.  With
-// s > m the s x m kernel block is first compressed to its m x m R factor
-// (tsqr_fold): column pivoting sees only the partial column norms, which a
-// left orthogonal factor does not change, so the pivots, |R_jj| and T are
-// those of the s x m block up to rounding.
 template <int NT>
 __device__ inline double block_sum(double v, double* sh)
 {
@@ -590,9 +580,16 @@ __host__ __device__ inline bool compress_rows(int s, int m, int cap)
     return 2 * (int64_t)s > 3 * (int64_t)m && m <= cap;
 }
 
+// One node per workgroup of NT lanes (64: one wavefront; 256 or 512 for
+// the wide nodes).  LDSM: the matrix the pivoted QR runs on lives in LDS
+// (dynamic shared memory after the reflector), otherwise in the global
+// workspace, where the blocked form runs when it fits.  When compress_rows
+// holds, the s x m kernel block is first compressed to its m x m R factor
+// (tsqr_fold; PRE: k_id_fold already did it): column pivoting sees only the
+// partial column norms, which a left orthogonal factor does not change, so
+// the pivots, |R_jj| and T are those of the s x m block up to rounding.
 template <int NT, bool LDSM, int CPL, int BR, bool PRE = false>
-__global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ tasks, const int* __restrict__ order,
-                                                   int bmax)
+__global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ tasks, const int* __restrict__ order)
 {
     extern __shared__ double dyn[];
     __shared__ double redd[NT / 64];
@@ -939,7 +936,6 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
         int nt, cpl, br;
     };
     const Cls CL[6] = {{64, 1, 32}, {64, 1, 16}, {WNT, 2, 16}, {64, 1, 32}, {WNT, 2, 16}, {256, 1, 16}};
-    const int BROWS = 64;                 // compression row block (at most)
     const size_t LDS_CAP = 80 * 1024;     // bytes per workgroup
     auto lds_need = [&](const IdTask& t, int c) -> size_t {
         const Cls& k = CL[c];
@@ -1009,11 +1005,11 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
         const int* ord = d_order.p + off[c];
         switch (c) {
         case 0:
-        case 3: k_batched_id<64, true, 1, 32><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
-        case 1: k_batched_id<64, false, 1, 16><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
-        case 4: k_batched_id<WNT, false, 2, 16, true><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
-        case 5: k_batched_id<256, false, 1, 16, true><<<cnt[c], 256, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
-        default: k_batched_id<WNT, false, 2, 16><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord, BROWS); break;
+        case 3: k_batched_id<64, true, 1, 32><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
+        case 1: k_batched_id<64, false, 1, 16><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
+        case 4: k_batched_id<WNT, false, 2, 16, true><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord); break;
+        case 5: k_batched_id<256, false, 1, 16, true><<<cnt[c], 256, lds[c], s>>>(d_tasks.p, ord); break;
+        default: k_batched_id<WNT, false, 2, 16><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord); break;
         }
         H2_LAUNCH_CHECK();
     };
