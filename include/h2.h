@@ -42,8 +42,18 @@ typedef enum {
  *   H2_COULOMB      1/|x-y|, with kappa(x,x) = 0
  *   H2_GAUSSIAN     exp(-|x-y|^2 / h^2)
  *   H2_EXPONENTIAL  exp(-|x-y| / l)
- *   H2_MATERN32     (1 + sqrt(3)|x-y|/l) exp(-sqrt(3)|x-y|/l)            */
-typedef enum { H2_COULOMB = 0, H2_GAUSSIAN = 1, H2_EXPONENTIAL = 2, H2_MATERN32 = 3 } h2_kernel_id;
+ *   H2_MATERN32     (1 + sqrt(3)|x-y|/l) exp(-sqrt(3)|x-y|/l)
+ *   H2_BUMP         exp(-1 / (1 - a|x-y|^2)), a = params[0] (kappa_4 of the
+ *                   paper's Table 1, where a = 0.1); defined where
+ *                   a|x-y|^2 < 1, which the caller's points must satisfy
+ *                   (the formula is evaluated as written)                 */
+typedef enum {
+    H2_COULOMB = 0,
+    H2_GAUSSIAN = 1,
+    H2_EXPONENTIAL = 2,
+    H2_MATERN32 = 3,
+    H2_BUMP = 4
+} h2_kernel_id;
 
 /* Build options (h2_options_default fills the defaults).
  *   tau            separation ratio of Eq. (separation), 0 < tau < 1; default 0.7

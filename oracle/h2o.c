@@ -37,7 +37,7 @@
 
 #define H2O_MAXDEPTH 48 /* guard for coincident points (paper silent) */
 
-enum { K_COULOMB = 0, K_GAUSSIAN = 1, K_EXPONENTIAL = 2, K_MATERN32 = 3 };
+enum { K_COULOMB = 0, K_GAUSSIAN = 1, K_EXPONENTIAL = 2, K_MATERN32 = 3, K_BUMP = 4 };
 
 /* ------------------------------------------------------------------ */
 /* growable int list                                                   */
@@ -69,7 +69,8 @@ static void il_free(ilist *a)
  * length scale l.  Coulomb 1/|x-y| with kappa(x,x)=0 (Table 1 caption);
  * Gaussian exp(-|x-y|^2/h^2) (bandwidth form of Section 6.1.3);
  * exponential exp(-|x-y|/l) (the Laplace kernel of Section 2);
- * Matern-3/2 (1+sqrt(3) r/l) exp(-sqrt(3) r/l) (standard definition). */
+ * Matern-3/2 (1+sqrt(3) r/l) exp(-sqrt(3) r/l) (standard definition);
+ * kappa_4 of Table 1, exp(-1/(1 - a r^2)) with a = prm[0] (0.1 there). */
 double h2o_kappa(int kid, const double *prm, const double *x, const double *y, int d)
 {
     double r2 = 0.0;
@@ -88,6 +89,8 @@ double h2o_kappa(int kid, const double *prm, const double *x, const double *y, i
         double t = sqrt(3.0) * sqrt(r2) / prm[0];
         return (1.0 + t) * exp(-t);
     }
+    case K_BUMP:
+        return exp(-1.0 / (1.0 - prm[0] * r2));
     default:
         return NAN;
     }
@@ -887,7 +890,7 @@ h2o *h2o_build(const double *pts, int n, int d, int kid, const double *prm, doub
                double tau, int r1, int r2, uint64_t seed, int nthreads)
 {
     if (n < 1 || d < 1 || d > 3 || q < 1 || !(tol > 0.0 && tol < 1.0) || !(tau > 0.0 && tau < 1.0) ||
-        kid < 0 || kid > 3)
+        kid < 0 || kid > 4)
         return NULL;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);

@@ -16,6 +16,8 @@ __device__ __forceinline__ double kappa_r2(int kid, double prm, double r2)
         return exp(-r2 / (prm * prm));
     case H2_EXPONENTIAL:
         return exp(-sqrt(r2) / prm);
+    case H2_BUMP:
+        return exp(-1.0 / (1.0 - prm * r2));
     default: {  // H2_MATERN32
         double t = sqrt(3.0) * sqrt(r2) / prm;
         return (1.0 + t) * exp(-t);
@@ -45,6 +47,8 @@ __device__ __forceinline__ double kappa_fast(int kid, double prm, double r2)
         return exp(-r2 / (prm * prm));
     case H2_EXPONENTIAL:
         return exp(-sqrt(r2) / prm);
+    case H2_BUMP:
+        return exp(-1.0 / (1.0 - prm * r2));
     default: {
         double t = sqrt(3.0) * sqrt(r2) / prm;
         return (1.0 + t) * exp(-t);
@@ -65,6 +69,8 @@ __device__ __forceinline__ float kappa_f32(int kid, float prm, double r2d)
         return __expf(-r2 / (prm * prm));
     case H2_EXPONENTIAL:
         return __expf(-sqrtf(r2) / prm);
+    case H2_BUMP:
+        return __expf(-1.0f / (1.0f - prm * r2));
     default: {
         float t = 1.7320508075688772f * sqrtf(r2) / prm;
         return (1.0f + t) * __expf(-t);

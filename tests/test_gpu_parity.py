@@ -134,7 +134,7 @@ def test_gaussian_2d_parity(H):
 @pytest.mark.parametrize("d,kernel,prm,n,leaf", [
     (3, "coulomb", 1.0, 3333, 32), (3, "exponential", 0.2, 2500, 40), (3, "matern32", 0.2, 2049, 64),
     (2, "gaussian", 0.1, 5000, 50), (2, "coulomb", 1.0, 1777, 17), (1, "exponential", 0.3, 3001, 16),
-    (1, "coulomb", 1.0, 1000, 1),
+    (1, "coulomb", 1.0, 1000, 1), (3, "bump", 0.1, 2800, 48),
 ])
 def test_kernels_and_dimensions(H, d, kernel, prm, n, leaf):
     rng = np.random.default_rng(n + d)
@@ -146,6 +146,28 @@ def test_kernels_and_dimensions(H, d, kernel, prm, n, leaf):
     _compare_reduction_and_bases(g, o)
     yg = g.matvec(x).cpu().numpy()
     assert _rel(yg, o.matvec(x)) <= 1e-10
+
+
+@pytest.mark.parametrize("kernel,prm", [("bump", 0.1), ("gaussian", 1.0)])
+def test_three_spheres_table1_kernels(H, kernel, prm):
+    """The paper's 3-sphere data (three unit spheres, centres on a triangle of
+    side 1) with kappa_4 and kappa_2 of Table 1: structure identical to the
+    oracle's, product within 1e-10 of it and within the tolerance of the
+    dense product."""
+    from paper_2206_01885_amd import workloads as W
+    rng = np.random.default_rng(1006)
+    n = 3000
+    P = W.three_spheres(rng, n)
+    x = rng.standard_normal((2, n))
+    _say(f"three spheres {kernel} {prm} n={n}")
+    g, o = _build(H, P, kernel, prm, 1e-6, 64)
+    _compare_structure(g, o)
+    _compare_reduction_and_bases(g, o)
+    yg = g.matvec(x).cpu().numpy()
+    assert _rel(yg, o.matvec(x)) <= 1e-10
+    ref = O.dense_rows(P, kernel, prm, x)
+    for r in range(2):
+        assert _rel(yg[r], ref[r]) <= 1e-6
 
 
 def test_exact_limit_against_dense(H):

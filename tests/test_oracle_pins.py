@@ -43,6 +43,24 @@ def test_kernels_match_library_definitions():
     assert O.kappa("coulomb", 1.0, [0, 0, 0], [3, 4, 0]) == 0.2
 
 
+def test_bump_kernel_special_values():
+    """kappa_4 of Table 1, exp(-1/(1 - a r^2)): e^-1 at r = 0, e^-2 where
+    a r^2 = 1/2, e^-4 where a r^2 = 3/4, symmetric, decreasing in r."""
+    a = 0.1
+    x = np.array([0.3, -0.2, 0.5])
+    assert O.kappa("bump", a, x, x) == pytest.approx(np.exp(-1.0), rel=1e-15)
+    e = np.array([1.0, 2.0, -2.0]) / 3.0  # unit vector
+    assert O.kappa("bump", a, x, x + np.sqrt(5.0) * e) == pytest.approx(np.exp(-2.0), rel=1e-13)
+    assert O.kappa("bump", a, x, x + np.sqrt(7.5) * e) == pytest.approx(np.exp(-4.0), rel=1e-13)
+    rng = np.random.default_rng(3)
+    X = rng.random((9, 3))
+    K = O.kernel_matrix("bump", a, X, X)
+    np.testing.assert_array_equal(K, K.T)
+    r = np.linspace(0.0, 3.0, 50)
+    v = [O.kappa("bump", a, [0.0, 0.0, 0.0], [t, 0.0, 0.0]) for t in r]
+    assert np.all(np.diff(v) < 0)
+
+
 def test_dense_rows_matches_library():
     rng = np.random.default_rng(1)
     P = rng.random((300, 3))
@@ -375,11 +393,14 @@ def _dense(P, kernel, prm):
         return RBF(length_scale=prm / np.sqrt(2.0))(P)
     if kernel == "exponential":
         return Matern(length_scale=prm, nu=0.5)(P)
+    if kernel == "bump":
+        return np.exp(-1.0 / (1.0 - prm * D * D))
     return Matern(length_scale=prm, nu=1.5)(P)
 
 
 @pytest.mark.parametrize("d,kernel,prm,q", [(3, "coulomb", 1.0, 16), (2, "gaussian", 0.3, 12),
                                             (3, "exponential", 0.2, 20), (1, "matern32", 0.1, 5),
+                                            (3, "bump", 0.1, 24),
                                             (2, "coulomb", 1.0, 1)])
 def test_matvec_exact_limit(d, kernel, prm, q):
     """With r1 = r2 >= n DataReduct is the identity, Y_i^* is the whole
