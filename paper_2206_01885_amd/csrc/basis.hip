@@ -188,6 +188,40 @@ __device__ __forceinline__ double axpy_rows(const double* __restrict__ v, double
     return tail;
 }
 
+// Coordinates of a lane's columns (c = lane + nt t) for the block
+// evaluation: held in registers when the lane owns one column, otherwise
+// read from global memory at each use.
+template <int CPL>
+struct XCoords {
+    const gdouble* p;
+    int64_t ld;
+    int idx[CPL];
+    __device__ XCoords(const double* pts, int64_t ld_, const int* xi, int lane, int nt, int m, int d) : ld(ld_)
+    {
+        (void)d;
+        p = (const gdouble*)pts;
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+            const int c = lane + t * nt;
+            idx[t] = c < m ? xi[c] : 0;
+        }
+    }
+    __device__ double get(int t, int a) const { return p[a * ld + idx[t]]; }
+};
+template <>
+struct XCoords<1> {
+    double x[3];
+    __device__ XCoords(const double* pts, int64_t ld, const int* xi, int lane, int nt, int m, int d)
+    {
+        (void)nt;
+        const int c = lane;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x[a] = (c < m && a < d) ? pts[a * ld + xi[c]] : 0.0;
+    }
+    // selects instead of an index, so that x stays in registers
+    __device__ double get(int, int a) const { return a == 0 ? x[0] : (a == 1 ? x[1] : x[2]); }
+};
+
 // Compression of a tall block (TSQR): the s x m block is streamed in blocks
 // of BR rows and folded into the m x m upper triangle R (LDS or global) by
 // Householder reflectors that each zero one column of the block against the
@@ -213,20 +247,34 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbu
     const int d = tk.d, kid = tk.kid;
     const double prm = tk.prm;
     const int lane = threadIdx.x;
+    double* ycrd = scr + BR * NT;  // 3 x BR: the row block's points
     for (int64_t e = lane; e < (int64_t)m * m; e += NT) R[e] = 0.0;
+    // this lane's column points: in registers for one column per lane,
+    // otherwise read where needed (L1 hits; registers kept for occupancy)
+    XCoords<CPL> xr(pts, ld, xi, lane, NT, m, d);
     __syncthreads();
     double bc[CPL][BR], tail[CPL];
     for (int r0 = 0; r0 < s0; r0 += BR) {
         const int nb = min(BR, s0 - r0);
+        // the row block's points, staged once in LDS for all lanes
+        if (lane < nb)
+            for (int a = 0; a < d; ++a) ycrd[a * BR + lane] = pts[a * ld + yi[r0 + lane]];
+        lds_barrier();
         // this lane's block entries (evaluated through a lane-private LDS
-        // slice, scr[r * NT + lane]) and their squared sums
+        // slice, scr[r * NT + lane]; squared distances accumulated in
+        // coordinate order as dist2 does) and their squared sums
 #pragma unroll
         for (int t = 0; t < CPL; ++t) {
             const int c = lane + t * NT;
             if (c < m) {
-                const int xc = xi[c];
-                for (int r = 0; r < nb; ++r)
-                    scr[r * NT + lane] = kappa_r2(kid, prm, dist2(pts, ld, xc, pts, ld, yi[r0 + r], d));
+                for (int r = 0; r < nb; ++r) {
+                    double r2 = 0.0;
+                    for (int a = 0; a < d; ++a) {
+                        const double ea = xr.get(t, a) - ycrd[a * BR + r];
+                        r2 = r2 + ea * ea;
+                    }
+                    scr[r * NT + lane] = kappa_r2(kid, prm, r2);
+                }
             }
             tail[t] = 0.0;
 #pragma unroll
@@ -794,6 +842,7 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
     double* nubuf = dyn + 2 * BR;  // 2: its squared norm
     double* x0buf = nubuf + 2;     // 2: the diagonal entry R[j][j]
     double* scr = x0buf + 2;       // SL x NT evaluation slices
+    double* ycrd = scr + SL * NT;  // 3 x BR: the row block's points
     const IdTask& tk = tasks[order[blockIdx.x]];
     const int m = tk.m, s0 = tk.s, d = tk.d, kid = tk.kid;
     const double prm = tk.prm;
@@ -803,25 +852,32 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
     gdouble* R = (gdouble*)tk.M;
     const int lane = threadIdx.x;
     for (int64_t e = lane; e < (int64_t)m * m; e += NT) R[e] = 0.0;
-    int xc[CPL];
-#pragma unroll
-    for (int t = 0; t < CPL; ++t) {
-        const int c = lane + t * NT;
-        xc[t] = c < m ? tk.x_idx[c] : 0;
-    }
+    // this lane's column points: in registers for one column per lane,
+    // otherwise read where needed (L1 hits; registers kept for occupancy)
+    XCoords<CPL> xr(pts, ld, tk.x_idx, lane, NT, m, d);
     __syncthreads();
     double bc[CPL][BR], tail[CPL], rn[D][CPL];
     for (int r0 = 0; r0 < s0; r0 += BR) {
         const int nb = min(BR, s0 - r0);
+        // the row block's points, staged once in LDS for all lanes
+        if (lane < nb)
+            for (int a = 0; a < d; ++a) ycrd[a * BR + lane] = pts[a * ld + yi[r0 + lane]];
+        lds_barrier();
 #pragma unroll
         for (int t = 0; t < CPL; ++t) {
             const int c = lane + t * NT;
 #pragma unroll
             for (int k0 = 0; k0 < BR; k0 += SL) {
                 if (c < m)
-                    for (int r = 0; r < SL && k0 + r < nb; ++r)
-                        scr[r * NT + lane] =
-                            kappa_r2(kid, prm, dist2(pts, ld, xc[t], pts, ld, yi[r0 + k0 + r], d));
+                    for (int r = 0; r < SL && k0 + r < nb; ++r) {
+                        // squared distance in coordinate order, as dist2
+                        double r2 = 0.0;
+                        for (int a = 0; a < d; ++a) {
+                            const double ea = xr.get(t, a) - ycrd[a * BR + k0 + r];
+                            r2 = r2 + ea * ea;
+                        }
+                        scr[r * NT + lane] = kappa_r2(kid, prm, r2);
+                    }
 #pragma unroll
                 for (int r = 0; r < SL; ++r) bc[t][k0 + r] = (c < m && k0 + r < nb) ? scr[r * NT + lane] : 0.0;
             }
@@ -945,8 +1001,8 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
         const size_t qr = use_blocked(sr, t.m, k.cpl * k.nt, k.nt, QR_NB) ? cpqr_blocked_lds(sr, t.m, k.nt, QR_NB) : 0;
         if (c == 4 || c == 5) return std::max((size_t)sr, qr) * sizeof(double);
         // published column (2 x BR), its norms and diagonal entries (2 x 2),
-        // the lanes' evaluation slices
-        const size_t pub = comp ? 2 * k.br + 4 + (size_t)k.br * k.nt : 0;
+        // the lanes' evaluation slices, the row block's points (3 x BR)
+        const size_t pub = comp ? 2 * k.br + 4 + (size_t)k.br * k.nt + 3 * k.br : 0;
         if (c == 0 || c == 3) return ((size_t)sr + (size_t)sr * t.m + pub) * sizeof(double);
         return std::max(std::max((size_t)sr, qr), pub) * sizeof(double);
     };
@@ -1018,13 +1074,13 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
     launch(1);
     if (prof) H2_HIP(hipEventRecord(ev[1], s));
     if (!fold[0].empty())
-        k_id_fold<1, 32, 1><<<(unsigned)fold[0].size(), 256, (2 * 32 + 4 + 8 * 256) * sizeof(double), s>>>(
+        k_id_fold<1, 32, 1><<<(unsigned)fold[0].size(), 256, (2 * 32 + 4 + 8 * 256 + 3 * 32) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[0]);
     if (!fold[1].empty())
-        k_id_fold<2, 16, 1><<<(unsigned)fold[1].size(), 256, (2 * 16 + 4 + 8 * 256) * sizeof(double), s>>>(
+        k_id_fold<2, 16, 1><<<(unsigned)fold[1].size(), 256, (2 * 16 + 4 + 8 * 256 + 3 * 16) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[1]);
     if (!fold[2].empty())
-        k_id_fold<4, 8, 1><<<(unsigned)fold[2].size(), 256, (2 * 8 + 4 + 8 * 256) * sizeof(double), s>>>(
+        k_id_fold<4, 8, 1><<<(unsigned)fold[2].size(), 256, (2 * 8 + 4 + 8 * 256 + 3 * 8) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[2]);
     H2_LAUNCH_CHECK();
     launch(5);
