@@ -676,11 +676,25 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
         double* cb = LDSM ? dyn + s + (int64_t)s * m : dyn;
         tsqr_fold<NT, CPL, BR>(tk, m, s0, M, cb, cb + 2 * BR, cb + 2 * BR + 4);
     } else {
-        // kernel block: M[r][c] = kappa(x_c, y_r)
-        for (int64_t e = threadIdx.x; e < (int64_t)s * m; e += NT) {
-            int r = (int)(e / m), c = (int)(e - (int64_t)r * m);
-            double r2 = dist2(tk.pts, tk.ld, xi[c], tk.pts, tk.ld, yi[r], d);
-            M[e] = kappa_r2(kid, prm, r2);
+        // kernel block: M[r][c] = kappa(x_c, y_r), a row per wavefront at a
+        // time (its point read once), the columns across the lanes
+        constexpr int W = NT / 64;
+        const int lane = threadIdx.x & 63;
+        const gdouble* gp = (const gdouble*)tk.pts;
+        const int64_t ld = tk.ld;
+        for (int r = threadIdx.x >> 6; r < s; r += W) {
+            const int yr = yi[r];
+            double yc[3] = {0.0, 0.0, 0.0};
+            for (int a = 0; a < d; ++a) yc[a] = gp[a * ld + yr];
+            for (int c = lane; c < m; c += 64) {
+                const int xc = xi[c];
+                double r2 = 0.0;  // coordinate order, as dist2
+                for (int a = 0; a < d; ++a) {
+                    const double t = gp[a * ld + xc] - (a == 0 ? yc[0] : (a == 1 ? yc[1] : yc[2]));
+                    r2 = r2 + t * t;
+                }
+                M[(int64_t)r * m + c] = kappa_r2(kid, prm, r2);
+            }
         }
         __syncthreads();
     }
