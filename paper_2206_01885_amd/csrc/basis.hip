@@ -394,9 +394,10 @@ __host__ __device__ inline bool use_blocked(int64_t s, int64_t m, int cols, int 
 // once per panel.  That is one read pass over the trailing matrix per step
 // where the unblocked loop makes three.  Pivot rule, stopping rule and norm
 // downdates are those of the unblocked loop; a norm that has to be
-// recomputed ends the panel early (as LAPACK does): the panel update then
-// forms it from the up-to-date column.  Returns the rank; the pivot order is
-// in piv and R in the upper triangle of M.
+// recomputed is formed from the up-to-date column, its panel update applied
+// on the fly (LAPACK ends the panel instead; with the fast-decaying spectra
+// of kernel blocks that would end nearly every panel).  Returns the rank;
+// the pivot order is in piv and R in the upper triangle of M.
 template <int NT, int CPL, int NB>
 __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol, gint* piv, double* lds)
 {
@@ -412,8 +413,6 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
     double* red = vj + NB;      // W x NB partial sums
     double* redd = red + W * NB;  // W
     int* redi = (int*)(redd + W);  // W
-    int* anyre = redi + W;         // 1: a norm of this step is to be recomputed
-    if (tid == 0) *anyre = 0;
     for (int t = 0; t < CPL; ++t) {
         const int c = tid + t * NT;
         if (c < m) {
@@ -531,11 +530,9 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
             yb[b] = a;
         }
         // this lane's columns c > j: F column jb, the pivot row, norm downdate
-        bool re[CPL];
 #pragma unroll
         for (int t = 0; t < CPL; ++t) {
             const int c = tid + t * NT;
-            re[t] = false;
             if (c > j && c < m) {
                 const double w = dot_rows<16>(v, M + c, m, j, s, 0.0);
                 double corr = 0.0;
@@ -557,9 +554,34 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
                     if (tt < 0.0) tt = 0.0;
                     const double rat = nu[c] / nu0[c];
                     if (tt * rat * rat <= tol3z) {
-                        // recomputed from the up-to-date column by the panel update
-                        re[t] = true;
-                        *anyre = 1;
+                        // recomputed from the up-to-date column (rows > j),
+                        // formed on the fly from the panel's reflectors
+                        double a = 0.0;
+                        constexpr int RB = 8;
+                        int r = j + 1;
+                        for (; r + RB <= s; r += RB) {
+                            double x[RB];
+#pragma unroll
+                            for (int q = 0; q < RB; ++q) x[q] = M[(int64_t)(r + q) * m + c];
+#pragma unroll
+                            for (int q = 0; q < RB; ++q) {
+                                const double* Vr = Vl + (int64_t)(r + q) * NB;
+#pragma unroll
+                                for (int b = 0; b < NB; ++b)
+                                    if (b <= jb) x[q] = x[q] - Vr[b] * F[t][b];
+                                a = a + x[q] * x[q];
+                            }
+                        }
+                        for (; r < s; ++r) {
+                            double x = M[(int64_t)r * m + c];
+                            const double* Vr = Vl + (int64_t)r * NB;
+#pragma unroll
+                            for (int b = 0; b < NB; ++b)
+                                if (b <= jb) x = x - Vr[b] * F[t][b];
+                            a = a + x * x;
+                        }
+                        nu[c] = sqrt(a);
+                        nu0[c] = nu[c];
                     } else {
                         nu[c] = nu[c] * sqrt(tt);
                     }
@@ -568,16 +590,14 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
         }
         __syncthreads();
         k = j + 1;
-        if ((jb + 1 == NB || *anyre) && k < kmax) {
+        if (jb + 1 == NB && k < kmax) {
             // panel update of the trailing matrix (rows > j, this lane's
-            // columns > j; the panel's jb + 1 reflectors), with the norms
-            // that are to be recomputed
+            // columns > j)
 #pragma unroll
             for (int t = 0; t < CPL; ++t) {
                 const int c = tid + t * NT;
                 if (c > j && c < m) {
                     constexpr int RB = 8;
-                    double tail = 0.0;
                     int r = j + 1;
                     for (; r + RB <= s; r += RB) {
                         double x[RB];
@@ -590,7 +610,6 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
                             for (int b = 0; b < NB; ++b)
                                 if (b <= jb) x[q] = x[q] - Vr[b] * F[t][b];
                             M[(int64_t)(r + q) * m + c] = x[q];
-                            tail = tail + x[q] * x[q];
                         }
                     }
                     for (; r < s; ++r) {
@@ -600,11 +619,6 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
                         for (int b = 0; b < NB; ++b)
                             if (b <= jb) x = x - Vr[b] * F[t][b];
                         M[(int64_t)r * m + c] = x;
-                        tail = tail + x * x;
-                    }
-                    if (re[t]) {
-                        nu[c] = sqrt(tail);
-                        nu0[c] = nu[c];
                     }
                 }
 #pragma unroll
@@ -612,7 +626,6 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
             }
             j0 = j + 1;
             __syncthreads();
-            if (tid == 0) *anyre = 0;
         }
     }
     return k;
