@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--rows", type=int, default=512, help="sampled rows for the dense accuracy check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=1 << 17, help="points of the oracle's bounded sample")
-    ap.add_argument("--workload", choices=["cube1m", "batched", "serving"], default="cube1m",
+    ap.add_argument("--workload", choices=["cube1m", "batched", "serving", "sphere3"], default="cube1m",
                     help="cube1m: the headline n=2^20 Coulomb step; batched: 256 independent problems; "
                          "serving: Poisson request stream")
     ap.add_argument("--nreq", type=int, default=64, help="requests of the serving workload")
@@ -151,17 +151,82 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def dense_rows_gpu(P, X, rows, chunk=64):
-    """Rows of K x on the GPU in FP64 (Coulomb, kappa(x,x)=0), exact distances."""
+def dense_rows_gpu(P, X, rows, chunk=64, kernel="coulomb", prm=1.0):
+    """Rows of K x on the GPU in FP64 (torch ops, exact distances): Coulomb
+    with kappa(x,x)=0, the Gaussian exp(-r^2/h^2) or the Table-1 bump
+    exp(-1/(1 - a r^2))."""
     import torch
     out = []
     for a in range(0, len(rows), chunk):
         r = rows[a:a + chunk]
         Pr = P[r]
-        D = ((Pr[:, None, :] - P[None, :, :]) ** 2).sum(-1).sqrt()
-        K = torch.where(D > 0, 1.0 / D, torch.zeros_like(D))
+        D2 = ((Pr[:, None, :] - P[None, :, :]) ** 2).sum(-1)
+        if kernel == "coulomb":
+            D = D2.sqrt()
+            K = torch.where(D > 0, 1.0 / D, torch.zeros_like(D))
+        elif kernel == "gaussian":
+            K = torch.exp(-D2 / (prm * prm))
+        elif kernel == "bump":
+            K = torch.exp(-1.0 / (1.0 - prm * D2))
+        else:
+            raise ValueError(kernel)
         out.append(K @ X.T)  # [chunk, nrhs]
     return torch.cat(out, 0).T  # [nrhs, rows]
+
+
+def bench_sphere3(args):
+    """The paper's kernel-scaling workload: n points on three unit spheres
+    (centres on a triangle of side 1), the Table-1 kernels kappa_4 (bump,
+    a = 0.1) and kappa_2 (Gaussian, h = 1), leaf 128, tol 1e-6, 32 RHS.  A
+    step is one build + one apply per kernel; value = points per second over
+    both kernels' steps."""
+    import torch
+    from paper_2206_01885_amd import h2, workloads
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    n, nrhs = args.n, args.nrhs
+    rng = np.random.default_rng(1006)
+    P = torch.tensor(workloads.three_spheres(rng, n), device=dev)
+    Psoa = P.t().contiguous()
+    X = torch.tensor(rng.standard_normal((nrhs, n)), device=dev)
+    Y = torch.empty_like(X)
+    rows = torch.tensor(np.sort(rng.choice(n, args.rows, replace=False)), device=dev)
+    opt = h2.h2_options_default()
+    opt.r_min = args.r_min
+    res = {}
+    total = 0.0
+    for kern, prm in (("bump", 0.1), ("gaussian", 1.0)):
+        times = []
+        for k in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hd = h2.h2_build(Psoa, kern, prm, 1e-6, 128, opt)
+            tb = time.perf_counter()
+            h2.h2_matvec(hd, X, Y, nrhs)
+            torch.cuda.synchronize()
+            te = time.perf_counter()
+            if k >= args.warmup:
+                times.append((tb - t0, te - tb))
+            info = h2.h2_query(hd)
+            h2.h2_destroy(hd)
+            print(f"[bench] sphere3 {kern} step {k}: build {tb - t0:.3f} s matvec {te - tb:.4f} s",
+                  file=sys.stderr, flush=True)
+        ref = dense_rows_gpu(P, X, rows, kernel=kern, prm=prm)
+        e = ((Y[:, rows] - ref).norm(dim=1) / ref.norm(dim=1)).max().item()
+        t = np.array(times)
+        total += float(t.sum(axis=1).mean())
+        res[kern] = {"prm": prm, "build_s": float(t[:, 0].mean()), "matvec_s": float(t[:, 1].mean()),
+                     "r1": info["r1"], "r2": info["r2"], "max_rank": info["max_rank"], "bytes_B": info["bytes_B"],
+                     "e_dense_sampled_rows_max_rhs": e}
+    out = {
+        "metric": "3-sphere H2 build + matvec Mpts/s (Table-1 kernels kappa_4 and kappa_2)",
+        "value": 2 * n / total / 1e6, "unit": "Mpts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / 2, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"sphere3-n{n}-bump0.1-gaussian1-leaf128-tol1e-6-nrhs{nrhs}", "n": n, "nrhs": nrhs},
+        "kernels": res,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(n, nrhs):
@@ -273,6 +338,9 @@ def main():
         return
     if args.workload == "serving":
         bench_serving(args)
+        return
+    if args.workload == "sphere3":
+        bench_sphere3(args)
         return
     import torch
     from paper_2206_01885_amd import h2
