@@ -46,13 +46,18 @@ typedef enum {
  *   H2_BUMP         exp(-1 / (1 - a|x-y|^2)), a = params[0] (kappa_4 of the
  *                   paper's Table 1, where a = 0.1); defined where
  *                   a|x-y|^2 < 1, which the caller's points must satisfy
- *                   (the formula is evaluated as written)                 */
+ *                   (the formula is evaluated as written)
+ *   H2_COSINE       cos(a x.y), a = params[0] (kappa_3 of Table 1, a = 1);
+ *                   not a function of |x-y|, so the calibration of r1, r2
+ *                   does not apply: options.r1 and options.r2 must be set
+ *                   (H2_EINVAL otherwise)                                  */
 typedef enum {
     H2_COULOMB = 0,
     H2_GAUSSIAN = 1,
     H2_EXPONENTIAL = 2,
     H2_MATERN32 = 3,
-    H2_BUMP = 4
+    H2_BUMP = 4,
+    H2_COSINE = 5
 } h2_kernel_id;
 
 /* Build options (h2_options_default fills the defaults).

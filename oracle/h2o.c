@@ -37,7 +37,7 @@
 
 #define H2O_MAXDEPTH 48 /* guard for coincident points (paper silent) */
 
-enum { K_COULOMB = 0, K_GAUSSIAN = 1, K_EXPONENTIAL = 2, K_MATERN32 = 3, K_BUMP = 4 };
+enum { K_COULOMB = 0, K_GAUSSIAN = 1, K_EXPONENTIAL = 2, K_MATERN32 = 3, K_BUMP = 4, K_COSINE = 5 };
 
 /* ------------------------------------------------------------------ */
 /* growable int list                                                   */
@@ -70,13 +70,15 @@ static void il_free(ilist *a)
  * Gaussian exp(-|x-y|^2/h^2) (bandwidth form of Section 6.1.3);
  * exponential exp(-|x-y|/l) (the Laplace kernel of Section 2);
  * Matern-3/2 (1+sqrt(3) r/l) exp(-sqrt(3) r/l) (standard definition);
- * kappa_4 of Table 1, exp(-1/(1 - a r^2)) with a = prm[0] (0.1 there). */
+ * kappa_4 of Table 1, exp(-1/(1 - a r^2)) with a = prm[0] (0.1 there);
+ * kappa_3 of Table 1, cos(a x.y) with a = prm[0] (1 there). */
 double h2o_kappa(int kid, const double *prm, const double *x, const double *y, int d)
 {
-    double r2 = 0.0;
+    double r2 = 0.0, xy = 0.0;
     for (int k = 0; k < d; ++k) {
         double t = x[k] - y[k];
         r2 = r2 + t * t;
+        xy = xy + x[k] * y[k];
     }
     switch (kid) {
     case K_COULOMB:
@@ -91,6 +93,8 @@ double h2o_kappa(int kid, const double *prm, const double *x, const double *y, i
     }
     case K_BUMP:
         return exp(-1.0 / (1.0 - prm[0] * r2));
+    case K_COSINE:
+        return cos(prm[0] * xy);
     default:
         return NAN;
     }
@@ -890,8 +894,10 @@ h2o *h2o_build(const double *pts, int n, int d, int kid, const double *prm, doub
                double tau, int r1, int r2, uint64_t seed, int nthreads)
 {
     if (n < 1 || d < 1 || d > 3 || q < 1 || !(tol > 0.0 && tol < 1.0) || !(tau > 0.0 && tau < 1.0) ||
-        kid < 0 || kid > 4)
+        kid < 0 || kid > 5)
         return NULL;
+    /* the cosine kernel is not a function of |x - y|: no calibration */
+    if (kid == K_COSINE && (r1 <= 0 || r2 <= 0)) return NULL;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "h2o.c")
 _LIB = os.path.join(_HERE, "libh2o.so")
 
-KERNELS = {"coulomb": 0, "gaussian": 1, "exponential": 2, "matern32": 3, "bump": 4}
+KERNELS = {"coulomb": 0, "gaussian": 1, "exponential": 2, "matern32": 3, "bump": 4, "cosine": 5}
 
 
 def build_library(force: bool = True) -> str:

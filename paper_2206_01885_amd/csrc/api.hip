@@ -61,7 +61,7 @@ h2_status check_and_init(h2::Handle& h, const double* points, int64_t n, int dim
     if (!points) return set_err(H2_EINVAL, "points is NULL");
     if (n < 1 || n > (int64_t)INT32_MAX) return set_err(H2_EINVAL, "n must be in [1, 2^31)");
     if (dim < 1 || dim > 3) return set_err(H2_EINVAL, "dim must be 1, 2 or 3");
-    if (kernel_id < H2_COULOMB || kernel_id > H2_BUMP) return set_err(H2_EINVAL, "unknown kernel_id");
+    if (kernel_id < H2_COULOMB || kernel_id > H2_COSINE) return set_err(H2_EINVAL, "unknown kernel_id");
     if (!(tol > 0.0 && tol < 1.0)) return set_err(H2_EINVAL, "tol must be in (0, 1)");
     if (leaf_size < 1) return set_err(H2_EINVAL, "leaf_size must be >= 1");
     if (!(opt.tau > 0.0 && opt.tau < 1.0)) return set_err(H2_EINVAL, "tau must be in (0, 1)");
@@ -70,6 +70,8 @@ h2_status check_and_init(h2::Handle& h, const double* points, int64_t n, int dim
     if (opt.precision != 64 && opt.precision != 32) return set_err(H2_EINVAL, "precision must be 64 or 32");
     if (opt.r_min < 0 || opt.r_min > 2048) return set_err(H2_EINVAL, "r_min must be in [0, 2048]");
     if (opt.store_coupling != 1) return set_err(H2_EUNSUPPORTED, "only stored coupling blocks are implemented");
+    if (kernel_id == H2_COSINE && (opt.r1 == 0 || opt.r2 == 0))
+        return set_err(H2_EINVAL, "the cosine kernel needs options.r1 and options.r2 (no calibration)");
     double prm = 1.0;
     if (kernel_id != H2_COULOMB) {
         if (!params) return set_err(H2_EINVAL, "params is NULL");
@@ -199,7 +201,7 @@ h2_status h2_build_ex(const double* points, int64_t n, int dim, int kernel_id, c
 h2_status h2_rebuild(h2_handle hd, int kernel_id, const double* params, double tol)
 {
     if (!hd) return set_err(H2_EINVAL, "handle is NULL");
-    if (kernel_id < H2_COULOMB || kernel_id > H2_BUMP) return set_err(H2_EINVAL, "unknown kernel_id");
+    if (kernel_id < H2_COULOMB || kernel_id > H2_COSINE) return set_err(H2_EINVAL, "unknown kernel_id");
     if (!(tol > 0.0 && tol < 1.0)) return set_err(H2_EINVAL, "tol must be in (0, 1)");
     double prm = 1.0;
     if (kernel_id != H2_COULOMB) {

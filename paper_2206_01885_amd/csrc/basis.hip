@@ -236,7 +236,7 @@ struct XCoords<1> {
 // pointer.  Every R entry is read and written by the lane that owns its
 // column only (the diagonal entry reaches the other lanes through LDS), so
 // the steps need LDS barriers only.
-template <int NT, int CPL, int BR, class RPtr>
+template <int NT, int CPL, int BR, bool COS, class RPtr>
 __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbuf, double* nubuf, double* scr)
 {
     double* x0buf = nubuf + 2;
@@ -268,12 +268,15 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbu
             const int c = lane + t * NT;
             if (c < m) {
                 for (int r = 0; r < nb; ++r) {
-                    double r2 = 0.0;
-                    for (int a = 0; a < d; ++a) {
-                        const double ea = xr.get(t, a) - ycrd[a * BR + r];
-                        r2 = r2 + ea * ea;
-                    }
-                    scr[r * NT + lane] = kappa_r2(kid, prm, r2);
+                    double r2 = 0.0, xy = 0.0;
+                    if constexpr (COS)
+                        for (int a = 0; a < d; ++a) xy = xy + xr.get(t, a) * ycrd[a * BR + r];
+                    else
+                        for (int a = 0; a < d; ++a) {
+                            const double ea = xr.get(t, a) - ycrd[a * BR + r];
+                            r2 = r2 + ea * ea;
+                        }
+                    scr[r * NT + lane] = kappa_rx<COS>(kid, prm, r2, xy);
                 }
             }
             tail[t] = 0.0;
@@ -649,7 +652,7 @@ __host__ __device__ inline bool compress_rows(int s, int m, int cap)
 // (tsqr_fold; PRE: k_id_fold already did it): column pivoting sees only the
 // partial column norms, which a left orthogonal factor does not change, so
 // the pivots, |R_jj| and T are those of the s x m block up to rounding.
-template <int NT, bool LDSM, int CPL, int BR, bool PRE = false>
+template <int NT, bool LDSM, int CPL, int BR, bool PRE, bool COS>
 __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ tasks, const int* __restrict__ order)
 {
     extern __shared__ double dyn[];
@@ -687,7 +690,7 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
         // the published column lives after the LDS matrix, or over the (not
         // yet used) reflector space
         double* cb = LDSM ? dyn + s + (int64_t)s * m : dyn;
-        tsqr_fold<NT, CPL, BR>(tk, m, s0, M, cb, cb + 2 * BR, cb + 2 * BR + 4);
+        tsqr_fold<NT, CPL, BR, COS>(tk, m, s0, M, cb, cb + 2 * BR, cb + 2 * BR + 4);
     } else {
         // kernel block: M[r][c] = kappa(x_c, y_r), a row per wavefront at a
         // time (its point read once), the columns across the lanes
@@ -701,12 +704,18 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
             for (int a = 0; a < d; ++a) yc[a] = gp[a * ld + yr];
             for (int c = lane; c < m; c += 64) {
                 const int xc = xi[c];
-                double r2 = 0.0;  // coordinate order, as dist2
+                double r2 = 0.0, xy = 0.0;  // coordinate order, as dist2
                 for (int a = 0; a < d; ++a) {
-                    const double t = gp[a * ld + xc] - (a == 0 ? yc[0] : (a == 1 ? yc[1] : yc[2]));
-                    r2 = r2 + t * t;
+                    const double xa = gp[a * ld + xc];
+                    const double ya = a == 0 ? yc[0] : (a == 1 ? yc[1] : yc[2]);
+                    if constexpr (COS) {
+                        xy = xy + xa * ya;
+                    } else {
+                        const double t = xa - ya;
+                        r2 = r2 + t * t;
+                    }
                 }
-                M[(int64_t)r * m + c] = kappa_r2(kid, prm, r2);
+                M[(int64_t)r * m + c] = kappa_rx<COS>(kid, prm, r2, xy);
             }
         }
         __syncthreads();
@@ -859,7 +868,7 @@ __global__ __launch_bounds__(TB) void k_xbar_fill(int lo, const int* __restrict_
 // entries, so a step synchronises through LDS only; the R rows a lane needs
 // are loaded D steps ahead into a register ring, and the block entries are
 // evaluated SL rows at a time through a lane-private LDS slice.
-template <int CPL, int BR, int D>
+template <int CPL, int BR, int D, bool COS>
 __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ tasks, const int* __restrict__ order)
 {
     constexpr int NT = 256, SL = 8;
@@ -898,12 +907,15 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
                 if (c < m)
                     for (int r = 0; r < SL && k0 + r < nb; ++r) {
                         // squared distance in coordinate order, as dist2
-                        double r2 = 0.0;
-                        for (int a = 0; a < d; ++a) {
-                            const double ea = xr.get(t, a) - ycrd[a * BR + k0 + r];
-                            r2 = r2 + ea * ea;
-                        }
-                        scr[r * NT + lane] = kappa_r2(kid, prm, r2);
+                        double r2 = 0.0, xy = 0.0;
+                        if constexpr (COS)
+                            for (int a = 0; a < d; ++a) xy = xy + xr.get(t, a) * ycrd[a * BR + k0 + r];
+                        else
+                            for (int a = 0; a < d; ++a) {
+                                const double ea = xr.get(t, a) - ycrd[a * BR + k0 + r];
+                                r2 = r2 + ea * ea;
+                            }
+                        scr[r * NT + lane] = kappa_rx<COS>(kid, prm, r2, xy);
                     }
 #pragma unroll
                 for (int r = 0; r < SL; ++r) bc[t][k0 + r] = (c < m && k0 + r < nb) ? scr[r * NT + lane] : 0.0;
@@ -1001,7 +1013,10 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
     }
 }
 
-void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof)
+namespace {
+
+template <bool COS>
+void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof)
 {
     const int np = (int)tasks_in.size();
     if (np <= 0) return;
@@ -1088,11 +1103,11 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
         const int* ord = d_order.p + off[c];
         switch (c) {
         case 0:
-        case 3: k_batched_id<64, true, 1, 32><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
-        case 1: k_batched_id<64, false, 1, 16><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
-        case 4: k_batched_id<WNT, false, 2, 16, true><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord); break;
-        case 5: k_batched_id<256, false, 1, 16, true><<<cnt[c], 256, lds[c], s>>>(d_tasks.p, ord); break;
-        default: k_batched_id<WNT, false, 2, 16><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord); break;
+        case 3: k_batched_id<64, true, 1, 32, false, COS><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
+        case 1: k_batched_id<64, false, 1, 16, false, COS><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
+        case 4: k_batched_id<WNT, false, 2, 16, true, COS><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord); break;
+        case 5: k_batched_id<256, false, 1, 16, true, COS><<<cnt[c], 256, lds[c], s>>>(d_tasks.p, ord); break;
+        default: k_batched_id<WNT, false, 2, 16, false, COS><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord); break;
         }
         H2_LAUNCH_CHECK();
     };
@@ -1101,13 +1116,13 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
     launch(1);
     if (prof) H2_HIP(hipEventRecord(ev[1], s));
     if (!fold[0].empty())
-        k_id_fold<1, 32, 1><<<(unsigned)fold[0].size(), 256, (2 * 32 + 4 + 8 * 256 + 3 * 32) * sizeof(double), s>>>(
+        k_id_fold<1, 32, 1, COS><<<(unsigned)fold[0].size(), 256, (2 * 32 + 4 + 8 * 256 + 3 * 32) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[0]);
     if (!fold[1].empty())
-        k_id_fold<2, 16, 1><<<(unsigned)fold[1].size(), 256, (2 * 16 + 4 + 8 * 256 + 3 * 16) * sizeof(double), s>>>(
+        k_id_fold<2, 16, 1, COS><<<(unsigned)fold[1].size(), 256, (2 * 16 + 4 + 8 * 256 + 3 * 16) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[1]);
     if (!fold[2].empty())
-        k_id_fold<4, 8, 1><<<(unsigned)fold[2].size(), 256, (2 * 8 + 4 + 8 * 256 + 3 * 8) * sizeof(double), s>>>(
+        k_id_fold<4, 8, 1, COS><<<(unsigned)fold[2].size(), 256, (2 * 8 + 4 + 8 * 256 + 3 * 8) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[2]);
     H2_LAUNCH_CHECK();
     launch(5);
@@ -1124,6 +1139,18 @@ void batched_id(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof
         prof->ms_wide += w;
         for (auto& e : ev) H2_HIP(hipEventDestroy(e));
     }
+}
+
+}  // namespace
+
+// The ID tasks of the radial kernels and of the cosine kernel run through
+// separately compiled launches (a batched build may mix both).
+void batched_id(const std::vector<IdTask>& tasks, hipStream_t s, IdProf* prof)
+{
+    std::vector<IdTask> fam[2];
+    for (const IdTask& t : tasks) fam[t.kid == H2_COSINE ? 1 : 0].push_back(t);
+    batched_id_family<false>(fam[0], s, prof);
+    batched_id_family<true>(fam[1], s, prof);
 }
 
 template <class T>

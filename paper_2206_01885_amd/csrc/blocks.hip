@@ -52,7 +52,7 @@ __global__ __launch_bounds__(TB) void k_entry_rows(int nrow, const int* __restri
 // column point of each block column is broadcast with a lane shuffle.  The
 // block is column-major (entry (t,u) at u*rows_i + t); with rows_i <= 32 the
 // two half-waves fill two columns per pass.
-template <class OutT>
+template <class OutT, bool COS>
 __global__ __launch_bounds__(TB) void k_blocks_eval(int64_t nent, const int* __restrict__ erow,
                                                     const int* __restrict__ col, const int* __restrict__ cnt,
                                                     const double* __restrict__ xs, int64_t ld,
@@ -90,20 +90,43 @@ __global__ __launch_bounds__(TB) void k_blocks_eval(int64_t nent, const int* __r
             for (int ub = 0; ub < uc; ub += su) {
                 const int uu = ub + du;
                 const int src = uu < uc ? uu : uc - 1;
-                const double a0 = __shfl(y0, src, 64) - xi0;
-                double r2 = a0 * a0;
-                if (d > 1) {
-                    const double a1 = __shfl(y1, src, 64) - xi1;
-                    r2 += a1 * a1;
+                const double s0 = __shfl(y0, src, 64);
+                const double s1 = d > 1 ? __shfl(y1, src, 64) : 0.0;
+                const double s2 = d > 2 ? __shfl(y2, src, 64) : 0.0;
+                double r2 = 0.0, xy = 0.0;  // xy: the cosine kernel's inner product
+                if constexpr (COS) {
+                    xy = xi0 * s0;
+                    if (d > 1) xy += xi1 * s1;
+                    if (d > 2) xy += xi2 * s2;
+                } else {
+                    const double a0 = s0 - xi0;
+                    r2 = a0 * a0;
+                    if (d > 1) {
+                        const double a1 = s1 - xi1;
+                        r2 += a1 * a1;
+                    }
+                    if (d > 2) {
+                        const double a2 = s2 - xi2;
+                        r2 += a2 * a2;
+                    }
                 }
-                if (d > 2) {
-                    const double a2 = __shfl(y2, src, 64) - xi2;
-                    r2 += a2 * a2;
-                }
-                if (t < ki && uu < uc) o[(int64_t)(u0 + uu) * ki + t] = kappa_store<OutT>(kid, prm, r2);
+                if (t < ki && uu < uc) o[(int64_t)(u0 + uu) * ki + t] = kappa_store<OutT, COS>(kid, prm, r2, xy);
             }
         }
     }
+}
+
+// The cosine kernel's blocks come from their own instance (see kappa_rx).
+template <class OutT>
+void launch_blocks_eval(int64_t nent, const int* erow, const int* col, const int* cnt, const double* xs, int64_t ld,
+                        const int64_t* xo, int d, int kid, double prm, const int64_t* off, OutT* out, hipStream_t s)
+{
+    const unsigned nb = (unsigned)blocks_for(nent, TB / 64);
+    if (kid == H2_COSINE)
+        k_blocks_eval<OutT, true><<<nb, TB, 0, s>>>(nent, erow, col, cnt, xs, ld, xo, d, kid, prm, off, out);
+    else
+        k_blocks_eval<OutT, false><<<nb, TB, 0, s>>>(nent, erow, col, cnt, xs, ld, xo, d, kid, prm, off, out);
+    H2_LAUNCH_CHECK();
 }
 
 }  // namespace
@@ -150,14 +173,11 @@ void build_blocks(Handle& h)
         k_entry_rows<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, erow.p);
         H2_LAUNCH_CHECK();
         if (f32)
-            k_blocks_eval<float><<<blocks_for(h.nil, TB / 64), TB, 0, s>>>(h.nil, erow.p, h.il_col.p, h.rank.p,
-                                                                            skc.p, sumk, d_xo.p, h.d, h.kid, h.prm,
-                                                                            h.B_off.p, h.Bf.p);
+            launch_blocks_eval(h.nil, erow.p, h.il_col.p, h.rank.p, skc.p, sumk, d_xo.p, h.d, h.kid, h.prm,
+                               h.B_off.p, h.Bf.p, s);
         else
-            k_blocks_eval<double><<<blocks_for(h.nil, TB / 64), TB, 0, s>>>(h.nil, erow.p, h.il_col.p, h.rank.p,
-                                                                             skc.p, sumk, d_xo.p, h.d, h.kid, h.prm,
-                                                                             h.B_off.p, h.B.p);
-        H2_LAUNCH_CHECK();
+            launch_blocks_eval(h.nil, erow.p, h.il_col.p, h.rank.p, skc.p, sumk, d_xo.p, h.d, h.kid, h.prm,
+                               h.B_off.p, h.B.p, s);
     }
     // nearfield: the leaves' points are contiguous in tree order
     k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.nr_ptr.p, h.nr_col.p, h.count.p, sz.p);
@@ -180,14 +200,11 @@ void build_blocks(Handle& h)
         k_entry_rows<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.nr_ptr.p, erow.p);
         H2_LAUNCH_CHECK();
         if (f32)
-            k_blocks_eval<float><<<blocks_for(h.nnear, TB / 64), TB, 0, s>>>(h.nnear, erow.p, h.nr_col.p, h.count.p,
-                                                                              h.pts.p, h.n, d_st.p, h.d, h.kid, h.prm,
-                                                                              h.D_off.p, h.Df.p);
+            launch_blocks_eval(h.nnear, erow.p, h.nr_col.p, h.count.p, h.pts.p, h.n, d_st.p, h.d, h.kid, h.prm,
+                               h.D_off.p, h.Df.p, s);
         else
-            k_blocks_eval<double><<<blocks_for(h.nnear, TB / 64), TB, 0, s>>>(h.nnear, erow.p, h.nr_col.p, h.count.p,
-                                                                               h.pts.p, h.n, d_st.p, h.d, h.kid, h.prm,
-                                                                               h.D_off.p, h.D.p);
-        H2_LAUNCH_CHECK();
+            launch_blocks_eval(h.nnear, erow.p, h.nr_col.p, h.count.p, h.pts.p, h.n, d_st.p, h.d, h.kid, h.prm,
+                               h.D_off.p, h.D.p, s);
         H2_HIP(hipStreamSynchronize(s));
     }
     H2_HIP(hipStreamSynchronize(s));

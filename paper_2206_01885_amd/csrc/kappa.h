@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace h2 {
 
 // kappa from the squared distance r2 = |x - y|^2.
@@ -23,6 +25,19 @@ __device__ __forceinline__ double kappa_r2(int kid, double prm, double r2)
         return (1.0 + t) * exp(-t);
     }
     }
+}
+
+// kappa from the squared distance r2 or the inner product xy = x.y.  The
+// cosine kernel (kappa_3 of Table 1) is the one that depends on xy; kernels
+// that evaluate it are compiled apart (COS = true), so that the radial
+// kernels' code does not carry the register cost of cos.
+template <bool COS>
+__device__ __forceinline__ double kappa_rx(int kid, double prm, double r2, double xy)
+{
+    if constexpr (COS)
+        return cos(prm * xy);
+    else
+        return kappa_r2(kid, prm, r2);
 }
 
 // 1/sqrt(r2) for r2 > 0: the hardware estimate refined by two Newton steps
@@ -78,17 +93,15 @@ __device__ __forceinline__ float kappa_f32(int kid, float prm, double r2d)
     }
 }
 
-template <class T>
-__device__ __forceinline__ T kappa_store(int kid, double prm, double r2);
-template <>
-__device__ __forceinline__ double kappa_store<double>(int kid, double prm, double r2)
+template <class T, bool COS>
+__device__ __forceinline__ T kappa_store(int kid, double prm, double r2, double xy)
 {
-    return kappa_fast(kid, prm, r2);
-}
-template <>
-__device__ __forceinline__ float kappa_store<float>(int kid, double prm, double r2)
-{
-    return kappa_f32(kid, (float)prm, r2);
+    if constexpr (COS)
+        return (T)cos(prm * xy);
+    else if constexpr (std::is_same_v<T, float>)
+        return kappa_f32(kid, (float)prm, r2);
+    else
+        return kappa_fast(kid, prm, r2);
 }
 
 // Squared distance accumulated in coordinate order from 0 (as the oracle does).

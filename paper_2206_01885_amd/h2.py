@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libh2.so")
 
 H2_OK, H2_EINVAL, H2_ENOMEM, H2_EDEVICE, H2_EUNSUPPORTED, H2_EINTERNAL = 0, -1, -2, -3, -4, -5
-KERNELS = {"coulomb": 0, "gaussian": 1, "exponential": 2, "matern32": 3, "bump": 4}
+KERNELS = {"coulomb": 0, "gaussian": 1, "exponential": 2, "matern32": 3, "bump": 4, "cosine": 5}
 
 EXPORTS = {"perm": (0, np.int32), "parent": (1, np.int32), "first_child": (2, np.int32),
            "nchild": (3, np.int32), "start": (4, np.int32), "count": (5, np.int32),

@@ -19,7 +19,7 @@ import math
 
 import numpy as np
 
-KERNEL_IDS = {"coulomb": 0, "gaussian": 1, "exponential": 2, "matern32": 3, "bump": 4}
+KERNEL_IDS = {"coulomb": 0, "gaussian": 1, "exponential": 2, "matern32": 3, "bump": 4, "cosine": 5}
 
 
 def cube(rng, n, d):

@@ -148,10 +148,11 @@ def test_kernels_and_dimensions(H, d, kernel, prm, n, leaf):
     assert _rel(yg, o.matvec(x)) <= 1e-10
 
 
-@pytest.mark.parametrize("kernel,prm", [("bump", 0.1), ("gaussian", 1.0)])
-def test_three_spheres_table1_kernels(H, kernel, prm):
+@pytest.mark.parametrize("kernel,prm,r", [("bump", 0.1, 0), ("gaussian", 1.0, 0), ("cosine", 1.0, 128)])
+def test_three_spheres_table1_kernels(H, kernel, prm, r):
     """The paper's 3-sphere data (three unit spheres, centres on a triangle of
-    side 1) with kappa_4 and kappa_2 of Table 1: structure identical to the
+    side 1) with kappa_4, kappa_2 and kappa_3 of Table 1 (the last with given
+    r1 = r2, since it has no calibration): structure identical to the
     oracle's, product within 1e-10 of it and within the tolerance of the
     dense product."""
     from paper_2206_01885_amd import workloads as W
@@ -160,7 +161,7 @@ def test_three_spheres_table1_kernels(H, kernel, prm):
     P = W.three_spheres(rng, n)
     x = rng.standard_normal((2, n))
     _say(f"three spheres {kernel} {prm} n={n}")
-    g, o = _build(H, P, kernel, prm, 1e-6, 64)
+    g, o = _build(H, P, kernel, prm, 1e-6, 64, r=r)
     _compare_structure(g, o)
     _compare_reduction_and_bases(g, o)
     yg = g.matvec(x).cpu().numpy()

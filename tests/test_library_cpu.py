@@ -46,6 +46,7 @@ def test_validation_without_device_work():
         (dummy, 10, 3, 0, prm, 1e-6, 0),      # leaf
         (None, 10, 3, 0, prm, 1e-6, 64),      # NULL points
         (dummy, 10, 3, 1, None, 1e-6, 64),    # Gaussian without params
+        (dummy, 10, 3, 5, prm, 1e-6, 64),     # cosine without r1, r2 (no calibration)
     ]
     for args in cases:
         st = L.h2_build(*args, C.byref(out))

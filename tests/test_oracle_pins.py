@@ -61,6 +61,29 @@ def test_bump_kernel_special_values():
     assert np.all(np.diff(v) < 0)
 
 
+def test_cosine_kernel_special_values():
+    """kappa_3 of Table 1, cos(a x.y): 1 for orthogonal points and at the
+    origin, 0 where a x.y = pi/2, -1 where a x.y = pi, symmetric, and (unlike
+    the radial kernels) changed by a common shift of both points."""
+    a = 1.0
+    x = np.array([0.6, 0.0, 0.8])  # unit vector
+    y = np.array([0.8, 0.0, -0.6])  # orthogonal to x
+    assert O.kappa("cosine", a, x, y) == 1.0
+    assert O.kappa("cosine", a, [0.0, 0.0, 0.0], [5.0, -3.0, 2.0]) == 1.0
+    assert abs(O.kappa("cosine", a, x, 0.5 * np.pi * x)) < 1e-15
+    assert O.kappa("cosine", a, x, np.pi * x) == pytest.approx(-1.0, abs=1e-15)
+    assert O.kappa("cosine", 2.0, x, 0.5 * np.pi * x) == pytest.approx(-1.0, abs=1e-15)
+    rng = np.random.default_rng(4)
+    X = rng.random((9, 3))
+    K = O.kernel_matrix("cosine", a, X, X)
+    np.testing.assert_array_equal(K, K.T)
+    t = np.array([0.3, 0.3, 0.3])
+    assert O.kappa("cosine", a, x + t, y + t) != pytest.approx(O.kappa("cosine", a, x, y))
+    # no calibration of r1, r2 for a kernel that is not a function of |x - y|
+    with pytest.raises(ValueError):
+        O.H2Oracle(X, "cosine", a, tol=1e-6, leaf=4)
+
+
 def test_dense_rows_matches_library():
     rng = np.random.default_rng(1)
     P = rng.random((300, 3))
@@ -395,12 +418,15 @@ def _dense(P, kernel, prm):
         return Matern(length_scale=prm, nu=0.5)(P)
     if kernel == "bump":
         return np.exp(-1.0 / (1.0 - prm * D * D))
+    if kernel == "cosine":
+        return np.cos(prm * (P @ P.T))
     return Matern(length_scale=prm, nu=1.5)(P)
 
 
 @pytest.mark.parametrize("d,kernel,prm,q", [(3, "coulomb", 1.0, 16), (2, "gaussian", 0.3, 12),
                                             (3, "exponential", 0.2, 20), (1, "matern32", 0.1, 5),
-                                            (3, "bump", 0.1, 24),
+                                            (3, "bump", 0.1, 24), (3, "cosine", 1.0, 24),
+                                            (2, "cosine", 3.0, 10),
                                             (2, "coulomb", 1.0, 1)])
 def test_matvec_exact_limit(d, kernel, prm, q):
     """With r1 = r2 >= n DataReduct is the identity, Y_i^* is the whole
