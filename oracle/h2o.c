@@ -37,7 +37,7 @@
 
 #define H2O_MAXDEPTH 48 /* guard for coincident points (paper silent) */
 
-enum { K_COULOMB = 0, K_GAUSSIAN = 1, K_EXPONENTIAL = 2, K_MATERN32 = 3, K_BUMP = 4, K_COSINE = 5 };
+enum { K_COULOMB = 0, K_GAUSSIAN = 1, K_EXPONENTIAL = 2, K_MATERN32 = 3, K_BUMP = 4, K_COSINE = 5, K_ADVECTION = 6 };
 
 /* ------------------------------------------------------------------ */
 /* growable int list                                                   */
@@ -71,7 +71,11 @@ static void il_free(ilist *a)
  * exponential exp(-|x-y|/l) (the Laplace kernel of Section 2);
  * Matern-3/2 (1+sqrt(3) r/l) exp(-sqrt(3) r/l) (standard definition);
  * kappa_4 of Table 1, exp(-1/(1 - a r^2)) with a = prm[0] (0.1 there);
- * kappa_3 of Table 1, cos(a x.y) with a = prm[0] (1 there). */
+ * kappa_3 of Table 1, cos(a x.y) with a = prm[0] (1 there);
+ * a non-symmetric kernel for the V != U path of Algorithm 2 (not in the
+ * paper): the Green's function of steady advection-diffusion with the drift
+ * along axis 0, exp(a((x-y)_0 - |x-y|)) / |x-y| with a = prm[0] and 0 at
+ * x = y (a = 0 gives Coulomb). */
 double h2o_kappa(int kid, const double *prm, const double *x, const double *y, int d)
 {
     double r2 = 0.0, xy = 0.0;
@@ -95,6 +99,11 @@ double h2o_kappa(int kid, const double *prm, const double *x, const double *y, i
         return exp(-1.0 / (1.0 - prm[0] * r2));
     case K_COSINE:
         return cos(prm[0] * xy);
+    case K_ADVECTION: {
+        if (!(r2 > 0.0)) return 0.0;
+        double r = sqrt(r2);
+        return exp(prm[0] * ((x[0] - y[0]) - r)) / r;
+    }
     default:
         return NAN;
     }
@@ -363,6 +372,15 @@ double h2o_splitmix_u01(uint64_t seed, uint64_t i)
 /* ------------------------------------------------------------------ */
 /* the H^2 object                                                      */
 /* ------------------------------------------------------------------ */
+/* One side of the nested bases: per node the rank, the row count of its ID
+ * problem, the row set, the pivots and T (U_i = P [I; T^T]). */
+typedef struct {
+    int *rank, *mbar;
+    ilist *xbar; /* row set Xbar_i (tree positions), in original (unpivoted) order */
+    int **piv;   /* per node, m_i entries */
+    double **T;  /* per node, k_i x (m_i - k_i) */
+} basis;
+
 typedef struct h2o {
     int n, d, kid;
     double prm[4];
@@ -380,11 +398,10 @@ typedef struct h2o {
     /* HiDR */
     int r1, r2;
     ilist *xs, *ys; /* X_i^*, Y_i^* as tree positions */
-    /* bases */
-    int *rank, *mbar;
-    ilist *xbar;     /* row set Xbar_i (tree positions), in original (unpivoted) order */
-    int **piv;       /* per node, m_i entries */
-    double **T;      /* per node, k_i x (m_i - k_i) */
+    /* bases: bu = U, R (row side); bv = V, W (column side), built only for a
+     * non-symmetric kernel (otherwise V = U) */
+    int nonsym;
+    basis bu, bv;
     int *calib_r;    /* per depth r found by the calibration (0 if not calibrated) */
     double *calib_err;
 } h2o;
@@ -819,17 +836,19 @@ static void calibrate(h2o *h, uint64_t seed)
  * children's skeletons concatenated in child order otherwise; getBasis on
  * K(Xbar_i, Y_i^*) gives U_i = P [I; T^T] and the skeleton Xhat_i =
  * Xbar_i[piv_0..k-1] in pivot order.  The transfer matrix R_c of a child is
- * the block of U_p's rows that belong to c's segment of Xbar_p.  Every
- * supported kernel is symmetric, so V = U and W = R.  A node with an empty
- * Y_i^* gets rank 0. */
-static void build_bases(h2o *h)
+ * the block of U_p's rows that belong to c's segment of Xbar_p.  The column
+ * side (side = 1) runs the same steps on K(Y_i^*, Xbar_i)^T, i.e. entries
+ * kappa(y, x), with its own row sets, and gives V_i, W_c and the column
+ * skeletons (Algorithm 2); for a symmetric kernel it equals the row side and
+ * is not built.  A node with an empty Y_i^* gets rank 0. */
+static void build_bases(h2o *h, basis *b, int side)
 {
     int nn = h->nnode;
-    h->rank = (int *)calloc((size_t)nn, sizeof(int));
-    h->mbar = (int *)calloc((size_t)nn, sizeof(int));
-    h->xbar = (ilist *)calloc((size_t)nn, sizeof(ilist));
-    h->piv = (int **)calloc((size_t)nn, sizeof(int *));
-    h->T = (double **)calloc((size_t)nn, sizeof(double *));
+    b->rank = (int *)calloc((size_t)nn, sizeof(int));
+    b->mbar = (int *)calloc((size_t)nn, sizeof(int));
+    b->xbar = (ilist *)calloc((size_t)nn, sizeof(ilist));
+    b->piv = (int **)calloc((size_t)nn, sizeof(int *));
+    b->T = (double **)calloc((size_t)nn, sizeof(double *));
     int d = h->d;
     for (int L = h->maxdepth; L >= 1; --L) {
 #pragma omp parallel for schedule(dynamic, 2)
@@ -840,9 +859,9 @@ static void build_bases(h2o *h)
                     il_push(&X, p);
             } else {
                 for (int c = h->first_child[i]; c < h->first_child[i] + h->nchild[i]; ++c) {
-                    const ilist *xc = &h->xbar[c];
-                    for (int t = 0; t < h->rank[c]; ++t)
-                        il_push(&X, xc->v[h->piv[c][t]]);
+                    const ilist *xc = &b->xbar[c];
+                    for (int t = 0; t < b->rank[c]; ++t)
+                        il_push(&X, xc->v[b->piv[c][t]]);
                 }
             }
             int m = X.n, s = h->ys[i].n;
@@ -850,16 +869,15 @@ static void build_bases(h2o *h)
             int k = 0;
             double *T = NULL;
             if (m > 0 && s > 0) {
-                double *Xc = (double *)malloc(sizeof(double) * (size_t)m * d);
-                double *Yc = (double *)malloc(sizeof(double) * (size_t)s * d);
-                for (int t = 0; t < m; ++t)
-                    for (int a = 0; a < d; ++a)
-                        Xc[(size_t)t * d + a] = h->P[(size_t)X.v[t] * d + a];
-                for (int t = 0; t < s; ++t)
-                    for (int a = 0; a < d; ++a)
-                        Yc[(size_t)t * d + a] = h->P[(size_t)h->ys[i].v[t] * d + a];
+                /* A[t][u] = kappa(xbar_t, y_u) (row side) or kappa(y_u, xbar_t) */
                 double *A = (double *)malloc(sizeof(double) * (size_t)m * s);
-                h2o_kernel_matrix(h->kid, h->prm, d, Xc, m, Yc, s, A);
+                for (int t = 0; t < m; ++t)
+                    for (int u = 0; u < s; ++u) {
+                        const double *xp = h->P + (size_t)X.v[t] * d;
+                        const double *yp = h->P + (size_t)h->ys[i].v[u] * d;
+                        A[(size_t)t * s + u] = side == 0 ? h2o_kappa(h->kid, h->prm, xp, yp, d)
+                                                         : h2o_kappa(h->kid, h->prm, yp, xp, d);
+                    }
                 int kk = m < s ? m : s;
                 double *Tt = (double *)malloc(sizeof(double) * (size_t)(kk > 0 ? kk : 1) * (size_t)m);
                 double *rd = (double *)malloc(sizeof(double) * (size_t)(kk > 0 ? kk : 1));
@@ -867,20 +885,31 @@ static void build_bases(h2o *h)
                 T = Tt;
                 free(rd);
                 free(A);
-                free(Xc);
-                free(Yc);
             } else {
                 for (int t = 0; t < m; ++t)
                     piv[t] = t;
             }
-            h->xbar[i] = X;
-            h->mbar[i] = m;
-            h->rank[i] = k;
-            h->piv[i] = piv;
-            h->T[i] = T;
+            b->xbar[i] = X;
+            b->mbar[i] = m;
+            b->rank[i] = k;
+            b->piv[i] = piv;
+            b->T[i] = T;
         }
     }
 }
+
+static void free_basis(basis *b, int nn)
+{
+    for (int i = 0; i < nn; ++i) {
+        if (b->xbar) il_free(&b->xbar[i]);
+        if (b->piv) free(b->piv[i]);
+        if (b->T) free(b->T[i]);
+    }
+    free(b->xbar); free(b->piv); free(b->T); free(b->rank); free(b->mbar);
+}
+
+/* the column basis V, W (the row basis when the kernel is symmetric) */
+static const basis *col_basis(const h2o *h) { return h->nonsym ? &h->bv : &h->bu; }
 
 /* ------------------------------------------------------------------ */
 /* public: build / free / export                                       */
@@ -894,10 +923,11 @@ h2o *h2o_build(const double *pts, int n, int d, int kid, const double *prm, doub
                double tau, int r1, int r2, uint64_t seed, int nthreads)
 {
     if (n < 1 || d < 1 || d > 3 || q < 1 || !(tol > 0.0 && tol < 1.0) || !(tau > 0.0 && tau < 1.0) ||
-        kid < 0 || kid > 5)
+        kid < 0 || kid > 6)
         return NULL;
-    /* the cosine kernel is not a function of |x - y|: no calibration */
-    if (kid == K_COSINE && (r1 <= 0 || r2 <= 0)) return NULL;
+    /* the calibration places its boxes along one axis and assumes a kernel
+     * of |x - y|: the cosine and advection kernels take given r1, r2 */
+    if ((kid == K_COSINE || kid == K_ADVECTION) && (r1 <= 0 || r2 <= 0)) return NULL;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -921,7 +951,9 @@ h2o *h2o_build(const double *pts, int n, int d, int kid, const double *prm, doub
     build_lists(h);
     calibrate(h, seed);
     run_hidr(h);
-    build_bases(h);
+    h->nonsym = kid == K_ADVECTION;
+    build_bases(h, &h->bu, 0);
+    if (h->nonsym) build_bases(h, &h->bv, 1);
     return h;
 }
 
@@ -949,12 +981,10 @@ void h2o_free(h2o *h)
     for (int i = 0; i < h->nnode; ++i) {
         if (h->xs) il_free(&h->xs[i]);
         if (h->ys) il_free(&h->ys[i]);
-        if (h->xbar) il_free(&h->xbar[i]);
-        if (h->piv) free(h->piv[i]);
-        if (h->T) free(h->T[i]);
     }
-    free(h->xs); free(h->ys); free(h->xbar); free(h->piv); free(h->T);
-    free(h->rank); free(h->mbar); free(h->calib_r); free(h->calib_err);
+    free_basis(&h->bu, h->nnode);
+    free_basis(&h->bv, h->nnode);
+    free(h->xs); free(h->ys); free(h->calib_r); free(h->calib_err);
     free(h);
 }
 
@@ -976,8 +1006,9 @@ long long h2o_info(const h2o *h, int what)
 
 /* Export an int array.  what: 0 perm, 1 parent, 2 first_child, 3 nchild,
  * 4 start, 5 count, 6 depth, 7 lvl_ptr, 8 il_ptr, 9 il_col, 10 nr_ptr,
- * 11 nr_col, 12 rank, 13 mbar.  Returns the number of entries (buf may be
- * NULL to query). */
+ * 11 nr_col, 12 rank, 13 mbar, 14 rank and 15 mbar of the column basis
+ * (the row basis' for a symmetric kernel).  Returns the number of entries
+ * (buf may be NULL to query). */
 long long h2o_export_int(const h2o *h, int what, int *buf)
 {
     const int *src = NULL;
@@ -995,8 +1026,10 @@ long long h2o_export_int(const h2o *h, int what, int *buf)
     case 9: src = h->il_col; cnt = h->il_ptr[h->nnode]; break;
     case 10: src = h->nr_ptr; cnt = h->nnode + 1; break;
     case 11: src = h->nr_col; cnt = h->nr_ptr[h->nnode]; break;
-    case 12: src = h->rank; cnt = src ? h->nnode : 0; break;
-    case 13: src = h->mbar; cnt = src ? h->nnode : 0; break;
+    case 12: src = h->bu.rank; cnt = src ? h->nnode : 0; break;
+    case 13: src = h->bu.mbar; cnt = src ? h->nnode : 0; break;
+    case 14: src = col_basis(h)->rank; cnt = src ? h->nnode : 0; break;
+    case 15: src = col_basis(h)->mbar; cnt = src ? h->nnode : 0; break;
     default: return -1;
     }
     if (buf && src) memcpy(buf, src, sizeof(int) * (size_t)cnt);
@@ -1021,49 +1054,49 @@ long long h2o_export_double(const h2o *h, int what, double *buf)
 }
 
 /* Per-node variable lists: what 0 X_i^*, 1 Y_i^*, 2 Xbar_i (unpivoted),
- * 3 piv_i, 4 skeleton Xhat_i (pivot order).  Returns the length. */
+ * 3 piv_i, 4 skeleton Xhat_i (pivot order); 5, 6, 7 the same three for the
+ * column basis.  Returns the length. */
 long long h2o_node_list(const h2o *h, int what, int i, int *buf)
 {
-    const int *src = NULL;
-    long long cnt = 0;
-    switch (what) {
-    case 0: if (h->xs) { src = h->xs[i].v; cnt = h->xs[i].n; } break;
-    case 1: if (h->ys) { src = h->ys[i].v; cnt = h->ys[i].n; } break;
-    case 2: if (h->xbar) { src = h->xbar[i].v; cnt = h->xbar[i].n; } break;
-    case 3: if (h->piv) { src = h->piv[i]; cnt = h->mbar[i]; } break;
-    case 4:
-        if (h->piv) {
-            cnt = h->rank[i];
-            if (buf)
-                for (int t = 0; t < cnt; ++t)
-                    buf[t] = h->xbar[i].v[h->piv[i][t]];
-            return cnt;
-        }
-        break;
-    default: return -1;
+    if (what == 0 || what == 1) {
+        const ilist *l = what == 0 ? h->xs : h->ys;
+        if (!l) return 0;
+        if (buf) memcpy(buf, l[i].v, sizeof(int) * (size_t)l[i].n);
+        return l[i].n;
     }
-    if (buf && src) memcpy(buf, src, sizeof(int) * (size_t)cnt);
+    if (what < 2 || what > 7) return -1;
+    const basis *b = what <= 4 ? &h->bu : col_basis(h);
+    int w = what <= 4 ? what : what - 3;
+    if (!b->piv) return 0;
+    long long cnt = w == 2 ? b->xbar[i].n : (w == 3 ? b->mbar[i] : b->rank[i]);
+    if (buf)
+        for (long long t = 0; t < cnt; ++t)
+            buf[t] = w == 2 ? b->xbar[i].v[t] : (w == 3 ? b->piv[i][t] : b->xbar[i].v[b->piv[i][t]]);
     return cnt;
 }
 
-/* T_i (k x (m-k), row-major). Returns the number of entries. */
-long long h2o_node_T(const h2o *h, int i, double *buf)
+/* T_i (k x (m-k), row-major) of the row basis (side 0) or of the column
+ * basis (side 1).  Returns the number of entries. */
+long long h2o_node_T_side(const h2o *h, int side, int i, double *buf)
 {
-    if (!h->T) return 0;
-    long long cnt = (long long)h->rank[i] * (h->mbar[i] - h->rank[i]);
-    if (buf && h->T[i]) memcpy(buf, h->T[i], sizeof(double) * (size_t)cnt);
+    const basis *b = side == 0 ? &h->bu : col_basis(h);
+    if (!b->T) return 0;
+    long long cnt = (long long)b->rank[i] * (b->mbar[i] - b->rank[i]);
+    if (buf && b->T[i]) memcpy(buf, b->T[i], sizeof(double) * (size_t)cnt);
     return cnt;
 }
+
+long long h2o_node_T(const h2o *h, int i, double *buf) { return h2o_node_T_side(h, 0, i, buf); }
 
 /* ------------------------------------------------------------------ */
 /* H^2 matrix-vector product                                           */
 /* ------------------------------------------------------------------ */
-/* xhat = U^T z with U = P [I; T^T]: xhat[t] = z[piv t] + sum_u T[t,u] z[piv(k+u)] */
-static void apply_Ut(const h2o *h, int i, const double *z, double *xh)
+/* xhat = V^T z with V = P [I; T^T] (of basis b): xhat[t] = z[piv t] + sum_u T[t,u] z[piv(k+u)] */
+static void apply_Ut(const basis *b, int i, const double *z, double *xh)
 {
-    int m = h->mbar[i], k = h->rank[i], nr = m - k;
-    const int *piv = h->piv[i];
-    const double *T = h->T[i];
+    int m = b->mbar[i], k = b->rank[i], nr = m - k;
+    const int *piv = b->piv[i];
+    const double *T = b->T[i];
     for (int t = 0; t < k; ++t) {
         double acc = z[piv[t]];
         for (int u = 0; u < nr; ++u)
@@ -1075,9 +1108,9 @@ static void apply_Ut(const h2o *h, int i, const double *z, double *xh)
 /* w += U yhat: w[piv t] += yhat[t]; w[piv(k+u)] += sum_t T[t,u] yhat[t] */
 static void apply_U_add(const h2o *h, int i, const double *yh, double *w)
 {
-    int m = h->mbar[i], k = h->rank[i], nr = m - k;
-    const int *piv = h->piv[i];
-    const double *T = h->T[i];
+    int m = h->bu.mbar[i], k = h->bu.rank[i], nr = m - k;
+    const int *piv = h->bu.piv[i];
+    const double *T = h->bu.T[i];
     for (int t = 0; t < k; ++t)
         w[piv[t]] = w[piv[t]] + yh[t];
     for (int u = 0; u < nr; ++u) {
@@ -1088,11 +1121,11 @@ static void apply_U_add(const h2o *h, int i, const double *yh, double *w)
     }
 }
 
-static void skel_coords(const h2o *h, int i, double *out)
+static void skel_coords(const h2o *h, const basis *b, int i, double *out)
 {
     int d = h->d;
-    for (int t = 0; t < h->rank[i]; ++t) {
-        int p = h->xbar[i].v[h->piv[i][t]];
+    for (int t = 0; t < b->rank[i]; ++t) {
+        int p = b->xbar[i].v[b->piv[i][t]];
         for (int a = 0; a < d; ++a)
             out[(size_t)t * d + a] = h->P[(size_t)p * d + a];
     }
@@ -1105,11 +1138,16 @@ static void skel_coords(const h2o *h, int i, double *out)
 static void matvec_tree(const h2o *h, const double *xt, double *yt, const unsigned char *need)
 {
     int nn = h->nnode, d = h->d;
+    const basis *bv = col_basis(h);
+    /* yhat in units of the row ranks, xhat in units of the column ranks */
     size_t *off = (size_t *)malloc(sizeof(size_t) * ((size_t)nn + 1));
-    off[0] = 0;
-    for (int i = 0; i < nn; ++i)
-        off[i + 1] = off[i] + (size_t)h->rank[i];
-    double *xh = (double *)calloc(off[nn] + 1, sizeof(double));
+    size_t *offv = (size_t *)malloc(sizeof(size_t) * ((size_t)nn + 1));
+    off[0] = offv[0] = 0;
+    for (int i = 0; i < nn; ++i) {
+        off[i + 1] = off[i] + (size_t)h->bu.rank[i];
+        offv[i + 1] = offv[i] + (size_t)bv->rank[i];
+    }
+    double *xh = (double *)calloc(offv[nn] + 1, sizeof(double));
     double *yh = (double *)calloc(off[nn] + 1, sizeof(double));
     unsigned char *act = (unsigned char *)calloc((size_t)nn, 1);
     /* which nodes need their output: ancestors of leaves holding needed rows */
@@ -1123,36 +1161,36 @@ static void matvec_tree(const h2o *h, const double *xt, double *yt, const unsign
             for (int a = i; a >= 0 && !act[a]; a = h->parent[a])
                 act[a] = 1;
     }
-    /* upward: xhat_i = U_i^T z_i, z_i = x_t(X_i) (leaf) or the children's xhat */
+    /* upward: xhat_i = V_i^T z_i, z_i = x_t(X_i) (leaf) or the children's xhat */
     for (int L = h->maxdepth; L >= 1; --L) {
 #pragma omp parallel for schedule(dynamic, 8)
         for (int i = h->lvl_ptr[L]; i < h->lvl_ptr[L + 1]; ++i) {
-            if (h->rank[i] == 0) continue;
+            if (bv->rank[i] == 0) continue;
             const double *z;
             if (is_leaf(h, i))
                 z = xt + h->start[i];
             else
-                z = xh + off[h->first_child[i]]; /* children's xhat are contiguous */
-            apply_Ut(h, i, z, xh + off[i]);
+                z = xh + offv[h->first_child[i]]; /* children's xhat are contiguous */
+            apply_Ut(bv, i, z, xh + offv[i]);
         }
     }
-    /* coupling: yhat_i = sum_{j in IL(i)} B_ij xhat_j, B_ij = K(Xhat_i, Xhat_j) */
+    /* coupling: yhat_i = sum_{j in IL(i)} B_ij xhat_j, B_ij = K(Xhat_i^(row), Xhat_j^(col)) */
 #pragma omp parallel for schedule(dynamic, 8)
     for (int i = 0; i < nn; ++i) {
-        if (!act[i] || h->rank[i] == 0) continue;
-        int ki = h->rank[i];
+        if (!act[i] || h->bu.rank[i] == 0) continue;
+        int ki = h->bu.rank[i];
         double *Xi = (double *)malloc(sizeof(double) * (size_t)ki * d);
-        skel_coords(h, i, Xi);
+        skel_coords(h, &h->bu, i, Xi);
         for (int e = h->il_ptr[i]; e < h->il_ptr[i + 1]; ++e) {
             int j = h->il_col[e];
-            int kj = h->rank[j];
+            int kj = bv->rank[j];
             double *Xj = (double *)malloc(sizeof(double) * (size_t)(kj > 0 ? kj : 1) * d);
-            skel_coords(h, j, Xj);
+            skel_coords(h, bv, j, Xj);
             for (int t = 0; t < ki; ++t) {
                 double acc = 0.0;
                 for (int u = 0; u < kj; ++u)
                     acc = acc + h2o_kappa(h->kid, h->prm, Xi + (size_t)t * d, Xj + (size_t)u * d, d) *
-                                    xh[off[j] + u];
+                                    xh[offv[j] + u];
                 yh[off[i] + t] = yh[off[i] + t] + acc;
             }
             free(Xj);
@@ -1163,7 +1201,7 @@ static void matvec_tree(const h2o *h, const double *xt, double *yt, const unsign
     for (int L = 1; L <= h->maxdepth; ++L) {
 #pragma omp parallel for schedule(dynamic, 8)
         for (int i = h->lvl_ptr[L]; i < h->lvl_ptr[L + 1]; ++i) {
-            if (!act[i] || is_leaf(h, i) || h->rank[i] == 0) continue;
+            if (!act[i] || is_leaf(h, i) || h->bu.rank[i] == 0) continue;
             apply_U_add(h, i, yh + off[i], yh + off[h->first_child[i]]);
         }
     }
@@ -1175,7 +1213,7 @@ static void matvec_tree(const h2o *h, const double *xt, double *yt, const unsign
         double *w = yt + st;
         for (int t = 0; t < ci; ++t)
             w[t] = 0.0;
-        if (h->rank[i] > 0) apply_U_add(h, i, yh + off[i], w);
+        if (h->bu.rank[i] > 0) apply_U_add(h, i, yh + off[i], w);
         for (int e = h->nr_ptr[i]; e < h->nr_ptr[i + 1]; ++e) {
             int j = h->nr_col[e];
             for (int t = 0; t < ci; ++t) {
@@ -1190,6 +1228,7 @@ static void matvec_tree(const h2o *h, const double *xt, double *yt, const unsign
         }
     }
     free(off);
+    free(offv);
     free(xh);
     free(yh);
     free(act);

@@ -20,7 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "h2o.c")
 _LIB = os.path.join(_HERE, "libh2o.so")
 
-KERNELS = {"coulomb": 0, "gaussian": 1, "exponential": 2, "matern32": 3, "bump": 4, "cosine": 5}
+KERNELS = {"coulomb": 0, "gaussian": 1, "exponential": 2, "matern32": 3, "bump": 4, "cosine": 5,
+           "advection": 6}
 
 
 def build_library(force: bool = True) -> str:
@@ -74,6 +75,8 @@ def lib():
         L.h2o_node_list.argtypes = [C.c_void_p, C.c_int, C.c_int, ip]
         L.h2o_node_T.restype = C.c_longlong
         L.h2o_node_T.argtypes = [C.c_void_p, C.c_int, dp]
+        L.h2o_node_T_side.restype = C.c_longlong
+        L.h2o_node_T_side.argtypes = [C.c_void_p, C.c_int, C.c_int, dp]
         L.h2o_matvec.argtypes = [C.c_void_p, dp, dp, C.c_int]
         L.h2o_matvec_rows.argtypes = [C.c_void_p, dp, C.c_int, ip, C.c_int, dp]
         L.h2o_dense_rows.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, ip, C.c_int, dp,
@@ -190,9 +193,10 @@ def max_threads() -> int:
 
 _INT_FIELDS = {"perm": 0, "parent": 1, "first_child": 2, "nchild": 3, "start": 4, "count": 5,
                "depth": 6, "lvl_ptr": 7, "il_ptr": 8, "il_col": 9, "near_ptr": 10, "near_col": 11,
-               "rank": 12, "mbar": 13}
+               "rank": 12, "mbar": 13, "rank_v": 14, "mbar_v": 15}
 _DBL_FIELDS = {"center": 0, "side": 1, "points": 2, "calib_err": 3}
-_LISTS = {"xstar": 0, "ystar": 1, "xbar": 2, "piv": 3, "skel": 4}
+# *_v: the column basis V, W (the row basis U, R for a symmetric kernel)
+_LISTS = {"xstar": 0, "ystar": 1, "xbar": 2, "piv": 3, "skel": 4, "xbar_v": 5, "piv_v": 6, "skel_v": 7}
 
 
 class H2Oracle:
@@ -255,12 +259,13 @@ class H2Oracle:
         lib().h2o_node_list(self._h, w, int(i), _i(buf))
         return buf[:cnt].copy()
 
-    def node_T(self, i):
-        cnt = lib().h2o_node_T(self._h, int(i), None)
+    def node_T(self, i, side=0):
+        """T_i of the row basis (side 0) or of the column basis (side 1)."""
+        cnt = lib().h2o_node_T_side(self._h, side, int(i), None)
         buf = np.empty(max(cnt, 1))
-        lib().h2o_node_T(self._h, int(i), _d(buf))
-        k = int(self.get("rank")[i])
-        m = int(self.get("mbar")[i])
+        lib().h2o_node_T_side(self._h, side, int(i), _d(buf))
+        k = int(self.get("rank_v" if side else "rank")[i])
+        m = int(self.get("mbar_v" if side else "mbar")[i])
         return buf[:cnt].reshape(k, m - k).copy()
 
     def matvec(self, x) -> np.ndarray:

@@ -84,6 +84,60 @@ def test_cosine_kernel_special_values():
         O.H2Oracle(X, "cosine", a, tol=1e-6, leaf=4)
 
 
+def test_advection_kernel_special_values():
+    """The non-symmetric kernel exp(a((x-y)_0 - r)) / r: Coulomb at a = 0,
+    1/t straight downstream, exp(-2at)/t upstream, exp(-at)/t across the
+    drift, 0 at x = y, kappa(y,x) = kappa(x,y) exp(-2a(x-y)_0); and, as the
+    Green's function of steady advection-diffusion with drift 2a along axis
+    0, Laplacian minus 2a d/dx_0 vanishes away from y (finite differences)."""
+    a = 1.5
+    x = np.array([0.3, -0.2, 0.5])
+    e0, e1 = np.array([1.0, 0.0, 0.0]), np.array([0.0, 0.6, 0.8])
+    t = 0.7
+    assert O.kappa("advection", a, x, x) == 0.0
+    assert O.kappa("advection", 0.0, x, x + t * e1) == O.kappa("coulomb", 1.0, x, x + t * e1)
+    assert O.kappa("advection", a, x, x - t * e0) == pytest.approx(1.0 / t, rel=1e-15)
+    assert O.kappa("advection", a, x, x + t * e0) == pytest.approx(np.exp(-2 * a * t) / t, rel=1e-14)
+    assert O.kappa("advection", a, x, x + t * e1) == pytest.approx(np.exp(-a * t) / t, rel=1e-14)
+    rng = np.random.default_rng(8)
+    X, Y = rng.random((6, 3)), rng.random((7, 3))
+    K = O.kernel_matrix("advection", a, X, Y)
+    Kt = O.kernel_matrix("advection", a, Y, X).T
+    scale = np.exp(-2 * a * (X[:, None, 0] - Y[None, :, 0]))
+    np.testing.assert_allclose(Kt, K * scale, rtol=1e-13)
+    y = np.array([0.1, 0.2, 0.3])
+    h = 1e-3
+    f = lambda p: O.kappa("advection", a, p, y)  # noqa: E731
+    for p in (np.array([0.9, 0.4, 0.1]), np.array([-0.5, 0.8, 0.6])):
+        lap = sum((f(p + h * u) - 2 * f(p) + f(p - h * u)) / h**2 for u in np.eye(3))
+        d0 = (f(p + h * e0) - f(p - h * e0)) / (2 * h)
+        assert abs(lap - 2 * a * d0) < 1e-5 * abs(lap)
+
+
+def test_nonsymmetric_bases():
+    """Algorithm 2 with a non-symmetric kernel builds a column basis of its
+    own: at a = 0 (Coulomb) it equals the row basis bit for bit; at a > 0
+    the column skeletons differ from the row skeletons and the product still
+    meets the tolerance against the dense product."""
+    rng = np.random.default_rng(52)
+    n = 1500
+    P = rng.random((n, 3))
+    x = rng.standard_normal((2, n))
+    h0 = O.H2Oracle(P, "advection", 0.0, tol=1e-6, leaf=32, r1=216, r2=216)
+    for i in range(1, h0.info()["nnode"]):
+        assert np.array_equal(h0.node_list("skel", i), h0.node_list("skel_v", i))
+        assert np.array_equal(h0.node_T(i), h0.node_T(i, side=1))
+    hc = O.H2Oracle(P, "coulomb", 1.0, tol=1e-6, leaf=32, r1=216, r2=216)
+    np.testing.assert_array_equal(h0.matvec(x), hc.matvec(x))
+    h1 = O.H2Oracle(P, "advection", 2.0, tol=1e-6, leaf=32, r1=216, r2=216)
+    nn = h1.info()["nnode"]
+    differ = sum(not np.array_equal(h1.node_list("skel", i), h1.node_list("skel_v", i)) for i in range(1, nn))
+    assert differ > nn // 4
+    ref = x @ _dense(P, "advection", 2.0).T
+    y = h1.matvec(x)
+    assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 1e-6
+
+
 def test_dense_rows_matches_library():
     rng = np.random.default_rng(1)
     P = rng.random((300, 3))
@@ -420,13 +474,18 @@ def _dense(P, kernel, prm):
         return np.exp(-1.0 / (1.0 - prm * D * D))
     if kernel == "cosine":
         return np.cos(prm * (P @ P.T))
+    if kernel == "advection":
+        diff = P[:, None, :] - P[None, :, :]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return np.where(D > 0, np.exp(prm * (diff[..., 0] - D)) / D, 0.0)
     return Matern(length_scale=prm, nu=1.5)(P)
 
 
 @pytest.mark.parametrize("d,kernel,prm,q", [(3, "coulomb", 1.0, 16), (2, "gaussian", 0.3, 12),
                                             (3, "exponential", 0.2, 20), (1, "matern32", 0.1, 5),
                                             (3, "bump", 0.1, 24), (3, "cosine", 1.0, 24),
-                                            (2, "cosine", 3.0, 10),
+                                            (2, "cosine", 3.0, 10), (3, "advection", 2.0, 24),
+                                            (2, "advection", 0.5, 8),
                                             (2, "coulomb", 1.0, 1)])
 def test_matvec_exact_limit(d, kernel, prm, q):
     """With r1 = r2 >= n DataReduct is the identity, Y_i^* is the whole
