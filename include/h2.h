@@ -50,14 +50,22 @@ typedef enum {
  *   H2_COSINE       cos(a x.y), a = params[0] (kappa_3 of Table 1, a = 1);
  *                   not a function of |x-y|, so the calibration of r1, r2
  *                   does not apply: options.r1 and options.r2 must be set
- *                   (H2_EINVAL otherwise)                                  */
+ *                   (H2_EINVAL otherwise)
+ *   H2_ADVECTION    exp(a((x-y)_0 - |x-y|)) / |x-y|, a = params[0] > 0, 0 at
+ *                   x = y: the Green's function of steady advection-diffusion
+ *                   with the drift along axis 0 (not in the paper).  Not
+ *                   symmetric: the build keeps a column basis V, W of its own
+ *                   (Algorithm 2, getBasis on K(Y_i*, Xbar_i)^T) beside U, R.
+ *                   Not a function of |x-y| either: options.r1 and
+ *                   options.r2 must be set (H2_EINVAL otherwise)          */
 typedef enum {
     H2_COULOMB = 0,
     H2_GAUSSIAN = 1,
     H2_EXPONENTIAL = 2,
     H2_MATERN32 = 3,
     H2_BUMP = 4,
-    H2_COSINE = 5
+    H2_COSINE = 5,
+    H2_ADVECTION = 6
 } h2_kernel_id;
 
 /* Build options (h2_options_default fills the defaults).
@@ -189,6 +197,12 @@ typedef struct {
      * DataReduct launches of HiDR, and the bytes of the candidate coordinates
      * they reduce (each farfield list T_i counted once); 0 otherwise */
     double hidr_down_ms, hidr_down_bytes;
+    /* column basis V, W: 1 when the kernel is not symmetric and V, W are
+     * built apart from U, R (max_rank, sum_rank and bytes_U describe U, R;
+     * these describe V, W and equal them for a symmetric kernel, except
+     * bytes_V = 0 there) */
+    int nonsymmetric, max_rank_v;
+    int64_t sum_rank_v, bytes_V;
 } h2_info;
 
 h2_status h2_query(h2_handle h, h2_info *info);
@@ -221,8 +235,14 @@ enum {
     H2_EXP_SKEL = 18,       /* int32 list of node `node` (rank entries) */
     H2_EXP_T = 19,          /* double, node `node`: rank x (mbar-rank) row-major */
     H2_EXP_POINTS = 20,     /* double [dim][n] SoA, tree order */
-    H2_EXP_B = 21,          /* double, IL entry `node` (CSR index): rank_i x rank_j column-major (precision 64) */
-    H2_EXP_CALIB_R = 22     /* int32 [maxdepth+1] r chosen per depth (0 if not calibrated) */
+    H2_EXP_B = 21,          /* double, IL entry `node` (CSR index): rank_i x rank_v_j column-major (precision 64) */
+    H2_EXP_CALIB_R = 22,    /* int32 [maxdepth+1] r chosen per depth (0 if not calibrated) */
+    /* the column basis V, W (the same arrays as U, R for a symmetric kernel) */
+    H2_EXP_RANK_V = 23,     /* int32 [nnode] */
+    H2_EXP_MBAR_V = 24,     /* int32 [nnode] */
+    H2_EXP_PIV_V = 25,      /* int32 list of node `node` */
+    H2_EXP_SKEL_V = 26,     /* int32 list of node `node` */
+    H2_EXP_T_V = 27         /* double, node `node`: rank_v x (mbar_v-rank_v) row-major */
 };
 h2_status h2_export(h2_handle h, int what, int node, void *host_buf, size_t bytes, int64_t *count);
 

@@ -61,7 +61,7 @@ h2_status check_and_init(h2::Handle& h, const double* points, int64_t n, int dim
     if (!points) return set_err(H2_EINVAL, "points is NULL");
     if (n < 1 || n > (int64_t)INT32_MAX) return set_err(H2_EINVAL, "n must be in [1, 2^31)");
     if (dim < 1 || dim > 3) return set_err(H2_EINVAL, "dim must be 1, 2 or 3");
-    if (kernel_id < H2_COULOMB || kernel_id > H2_COSINE) return set_err(H2_EINVAL, "unknown kernel_id");
+    if (kernel_id < H2_COULOMB || kernel_id > H2_ADVECTION) return set_err(H2_EINVAL, "unknown kernel_id");
     if (!(tol > 0.0 && tol < 1.0)) return set_err(H2_EINVAL, "tol must be in (0, 1)");
     if (leaf_size < 1) return set_err(H2_EINVAL, "leaf_size must be >= 1");
     if (!(opt.tau > 0.0 && opt.tau < 1.0)) return set_err(H2_EINVAL, "tau must be in (0, 1)");
@@ -70,8 +70,8 @@ h2_status check_and_init(h2::Handle& h, const double* points, int64_t n, int dim
     if (opt.precision != 64 && opt.precision != 32) return set_err(H2_EINVAL, "precision must be 64 or 32");
     if (opt.r_min < 0 || opt.r_min > 2048) return set_err(H2_EINVAL, "r_min must be in [0, 2048]");
     if (opt.store_coupling != 1) return set_err(H2_EUNSUPPORTED, "only stored coupling blocks are implemented");
-    if (kernel_id == H2_COSINE && (opt.r1 == 0 || opt.r2 == 0))
-        return set_err(H2_EINVAL, "the cosine kernel needs options.r1 and options.r2 (no calibration)");
+    if ((kernel_id == H2_COSINE || kernel_id == H2_ADVECTION) && (opt.r1 == 0 || opt.r2 == 0))
+        return set_err(H2_EINVAL, "the cosine and advection kernels need options.r1 and options.r2 (no calibration)");
     double prm = 1.0;
     if (kernel_id != H2_COULOMB) {
         if (!params) return set_err(H2_EINVAL, "params is NULL");
@@ -81,6 +81,7 @@ h2_status check_and_init(h2::Handle& h, const double* points, int64_t n, int dim
     h.n = n;
     h.d = dim;
     h.kid = kernel_id;
+    h.nonsym = kernel_id == H2_ADVECTION;
     h.prm = prm;
     h.tol = tol;
     h.tol_int = 0.5 * tol;  // eps' = eps/2 for truncation and calibration
@@ -129,9 +130,12 @@ void build_back(h2::Handle& h)
     for (int i = 0; i < h.nnode; ++i)
         if (h.h_nchild[i] == 0) leaves.push_back(i);
     upload_vec(h.leaves, leaves, h.stream);
-    std::vector<int64_t> xo((size_t)h.nnode + 1, 0);
-    for (int i = 0; i < h.nnode; ++i) xo[i + 1] = xo[i] + h.h_rank[i];
-    upload_vec(h.xh_off, xo, h.stream);
+    for (h2::Basis* b : {&h.bu, &h.bv}) {
+        if (b == &h.bv && !h.nonsym) break;
+        std::vector<int64_t> xo((size_t)h.nnode + 1, 0);
+        for (int i = 0; i < h.nnode; ++i) xo[i + 1] = xo[i] + b->h_rank[i];
+        upload_vec(b->xh_off, xo, h.stream);
+    }
     h2::prepare_apply(h);
     h.t_blocks = t6 - t5;
 }
@@ -201,7 +205,7 @@ h2_status h2_build_ex(const double* points, int64_t n, int dim, int kernel_id, c
 h2_status h2_rebuild(h2_handle hd, int kernel_id, const double* params, double tol)
 {
     if (!hd) return set_err(H2_EINVAL, "handle is NULL");
-    if (kernel_id < H2_COULOMB || kernel_id > H2_COSINE) return set_err(H2_EINVAL, "unknown kernel_id");
+    if (kernel_id < H2_COULOMB || kernel_id > H2_ADVECTION) return set_err(H2_EINVAL, "unknown kernel_id");
     if (!(tol > 0.0 && tol < 1.0)) return set_err(H2_EINVAL, "tol must be in (0, 1)");
     double prm = 1.0;
     if (kernel_id != H2_COULOMB) {
@@ -216,6 +220,7 @@ h2_status h2_rebuild(h2_handle hd, int kernel_id, const double* params, double t
         H2_HIP(hipStreamSynchronize(h.stream));
         h.ready = false;
         h.kid = kernel_id;
+        h.nonsym = kernel_id == H2_ADVECTION;
         h.prm = prm;
         h.tol = tol;
         h.tol_int = 0.5 * tol;
@@ -371,7 +376,7 @@ h2_status h2_query(h2_handle hd, h2_info* info)
     int nleaf = 0, maxr = 0;
     for (int i = 0; i < h.nnode; ++i) {
         nleaf += h.h_nchild[i] == 0;
-        maxr = std::max(maxr, h.h_rank[i]);
+        maxr = std::max(maxr, h.bu.h_rank[i]);
     }
     info->nleaf = nleaf;
     info->r1 = h.r1;
@@ -379,8 +384,12 @@ h2_status h2_query(h2_handle hd, h2_info* info)
     info->nnz_il = h.nil;
     info->nnz_near = h.nnear;
     info->max_rank = maxr;
-    info->sum_rank = h.sum_rank;
-    info->bytes_U = h.bytes_T;
+    info->sum_rank = h.bu.sum_rank;
+    info->bytes_U = h.bu.bytes_T;
+    info->nonsymmetric = h.nonsym ? 1 : 0;
+    for (int i = 0; i < h.nnode; ++i) info->max_rank_v = std::max(info->max_rank_v, h.col().h_rank[i]);
+    info->sum_rank_v = h.col().sum_rank;
+    info->bytes_V = h.nonsym ? h.bv.bytes_T : 0;
     info->bytes_B = h.bytes_B;
     info->bytes_D = h.bytes_D;
     info->precision = h.precision;
@@ -448,24 +457,35 @@ h2_status h2_export(h2_handle hd, int what, int node, void* host_buf, size_t byt
             cnt = h2::read_scalar(h.ys_cnt.p + node, s);
             src = h.ys_idx.p + (int64_t)node * h.ys_stride;
             break;
-        case H2_EXP_RANK: src = h.rank.p; cnt = h.nnode; break;
-        case H2_EXP_MBAR: src = h.mbar.p; cnt = h.nnode; break;
+        case H2_EXP_RANK:
+        case H2_EXP_RANK_V: src = (what == H2_EXP_RANK ? h.bu : h.col()).rank.p; cnt = h.nnode; break;
+        case H2_EXP_MBAR:
+        case H2_EXP_MBAR_V: src = (what == H2_EXP_MBAR ? h.bu : h.col()).mbar.p; cnt = h.nnode; break;
         case H2_EXP_PIV:
+        case H2_EXP_PIV_V: {
             if (!node_ok()) return set_err(H2_EINVAL, "node out of range");
-            cnt = h.h_mbar[node];
-            src = h.piv.p + h.h_piv_off[node];
+            const h2::Basis& b = what == H2_EXP_PIV ? h.bu : h.col();
+            cnt = b.h_mbar[node];
+            src = b.piv.p + b.h_piv_off[node];
             break;
+        }
         case H2_EXP_SKEL:
+        case H2_EXP_SKEL_V: {
             if (!node_ok()) return set_err(H2_EINVAL, "node out of range");
-            cnt = h.h_rank[node];
-            src = h.skel.p + (int64_t)node * h.ys_stride;
+            const h2::Basis& b = what == H2_EXP_SKEL ? h.bu : h.col();
+            cnt = b.h_rank[node];
+            src = b.skel.p + (int64_t)node * h.ys_stride;
             break;
+        }
         case H2_EXP_T:
+        case H2_EXP_T_V: {
             if (!node_ok()) return set_err(H2_EINVAL, "node out of range");
-            cnt = (int64_t)h.h_rank[node] * (h.h_mbar[node] - h.h_rank[node]);
-            src = h.T.p + h.h_T_off[node];
+            const h2::Basis& b = what == H2_EXP_T ? h.bu : h.col();
+            cnt = (int64_t)b.h_rank[node] * (b.h_mbar[node] - b.h_rank[node]);
+            src = b.T.p + b.h_T_off[node];
             esz = 8;
             break;
+        }
         case H2_EXP_POINTS: src = h.pts.p; cnt = h.n * h.d; esz = 8; break;
         case H2_EXP_B: {
             if (node < 0 || node >= h.nil) return set_err(H2_EINVAL, "IL entry out of range");

@@ -236,7 +236,7 @@ struct XCoords<1> {
 // pointer.  Every R entry is read and written by the lane that owns its
 // column only (the diagonal entry reaches the other lanes through LDS), so
 // the steps need LDS barriers only.
-template <int NT, int CPL, int BR, bool COS, class RPtr>
+template <int NT, int CPL, int BR, int FAM, class RPtr>
 __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbuf, double* nubuf, double* scr)
 {
     double* x0buf = nubuf + 2;
@@ -246,6 +246,7 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbu
     const int* yi = tk.y_idx;
     const int d = tk.d, kid = tk.kid;
     const double prm = tk.prm;
+    const double dsgn = tk.swap ? -1.0 : 1.0;  // column side: kappa(y, x)
     const int lane = threadIdx.x;
     double* ycrd = scr + BR * NT;  // 3 x BR: the row block's points
     for (int64_t e = lane; e < (int64_t)m * m; e += NT) R[e] = 0.0;
@@ -268,15 +269,16 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbu
             const int c = lane + t * NT;
             if (c < m) {
                 for (int r = 0; r < nb; ++r) {
-                    double r2 = 0.0, xy = 0.0;
-                    if constexpr (COS)
+                    double r2 = 0.0, xy = 0.0, e0 = 0.0;
+                    if constexpr (FAM == FAM_COSINE)
                         for (int a = 0; a < d; ++a) xy = xy + xr.get(t, a) * ycrd[a * BR + r];
                     else
                         for (int a = 0; a < d; ++a) {
                             const double ea = xr.get(t, a) - ycrd[a * BR + r];
+                            if (a == 0) e0 = ea;
                             r2 = r2 + ea * ea;
                         }
-                    scr[r * NT + lane] = kappa_rx<COS>(kid, prm, r2, xy);
+                    scr[r * NT + lane] = kappa_fam<FAM>(kid, prm, r2, xy, dsgn * e0);
                 }
             }
             tail[t] = 0.0;
@@ -652,7 +654,7 @@ __host__ __device__ inline bool compress_rows(int s, int m, int cap)
 // (tsqr_fold; PRE: k_id_fold already did it): column pivoting sees only the
 // partial column norms, which a left orthogonal factor does not change, so
 // the pivots, |R_jj| and T are those of the s x m block up to rounding.
-template <int NT, bool LDSM, int CPL, int BR, bool PRE, bool COS>
+template <int NT, bool LDSM, int CPL, int BR, bool PRE, int FAM>
 __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ tasks, const int* __restrict__ order)
 {
     extern __shared__ double dyn[];
@@ -690,7 +692,7 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
         // the published column lives after the LDS matrix, or over the (not
         // yet used) reflector space
         double* cb = LDSM ? dyn + s + (int64_t)s * m : dyn;
-        tsqr_fold<NT, CPL, BR, COS>(tk, m, s0, M, cb, cb + 2 * BR, cb + 2 * BR + 4);
+        tsqr_fold<NT, CPL, BR, FAM>(tk, m, s0, M, cb, cb + 2 * BR, cb + 2 * BR + 4);
     } else {
         // kernel block: M[r][c] = kappa(x_c, y_r), a row per wavefront at a
         // time (its point read once), the columns across the lanes
@@ -704,18 +706,19 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
             for (int a = 0; a < d; ++a) yc[a] = gp[a * ld + yr];
             for (int c = lane; c < m; c += 64) {
                 const int xc = xi[c];
-                double r2 = 0.0, xy = 0.0;  // coordinate order, as dist2
+                double r2 = 0.0, xy = 0.0, e0 = 0.0;  // coordinate order, as dist2
                 for (int a = 0; a < d; ++a) {
                     const double xa = gp[a * ld + xc];
                     const double ya = a == 0 ? yc[0] : (a == 1 ? yc[1] : yc[2]);
-                    if constexpr (COS) {
+                    if constexpr (FAM == FAM_COSINE) {
                         xy = xy + xa * ya;
                     } else {
                         const double t = xa - ya;
+                        if (a == 0) e0 = t;
                         r2 = r2 + t * t;
                     }
                 }
-                M[(int64_t)r * m + c] = kappa_rx<COS>(kid, prm, r2, xy);
+                M[(int64_t)r * m + c] = kappa_fam<FAM>(kid, prm, r2, xy, tk.swap ? -e0 : e0);
             }
         }
         __syncthreads();
@@ -868,7 +871,7 @@ __global__ __launch_bounds__(TB) void k_xbar_fill(int lo, const int* __restrict_
 // entries, so a step synchronises through LDS only; the R rows a lane needs
 // are loaded D steps ahead into a register ring, and the block entries are
 // evaluated SL rows at a time through a lane-private LDS slice.
-template <int CPL, int BR, int D, bool COS>
+template <int CPL, int BR, int D, int FAM>
 __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ tasks, const int* __restrict__ order)
 {
     constexpr int NT = 256, SL = 8;
@@ -882,6 +885,7 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
     const IdTask& tk = tasks[order[blockIdx.x]];
     const int m = tk.m, s0 = tk.s, d = tk.d, kid = tk.kid;
     const double prm = tk.prm;
+    const double dsgn = tk.swap ? -1.0 : 1.0;  // column side: kappa(y, x)
     const double* pts = tk.pts;
     const int64_t ld = tk.ld;
     const int* yi = tk.y_idx;
@@ -907,15 +911,16 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
                 if (c < m)
                     for (int r = 0; r < SL && k0 + r < nb; ++r) {
                         // squared distance in coordinate order, as dist2
-                        double r2 = 0.0, xy = 0.0;
-                        if constexpr (COS)
+                        double r2 = 0.0, xy = 0.0, e0 = 0.0;
+                        if constexpr (FAM == FAM_COSINE)
                             for (int a = 0; a < d; ++a) xy = xy + xr.get(t, a) * ycrd[a * BR + k0 + r];
                         else
                             for (int a = 0; a < d; ++a) {
                                 const double ea = xr.get(t, a) - ycrd[a * BR + k0 + r];
+                                if (a == 0) e0 = ea;
                                 r2 = r2 + ea * ea;
                             }
-                        scr[r * NT + lane] = kappa_rx<COS>(kid, prm, r2, xy);
+                        scr[r * NT + lane] = kappa_fam<FAM>(kid, prm, r2, xy, dsgn * e0);
                     }
 #pragma unroll
                 for (int r = 0; r < SL; ++r) bc[t][k0 + r] = (c < m && k0 + r < nb) ? scr[r * NT + lane] : 0.0;
@@ -1015,7 +1020,7 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
 
 namespace {
 
-template <bool COS>
+template <int FAM>
 void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof)
 {
     const int np = (int)tasks_in.size();
@@ -1103,11 +1108,11 @@ void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdPro
         const int* ord = d_order.p + off[c];
         switch (c) {
         case 0:
-        case 3: k_batched_id<64, true, 1, 32, false, COS><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
-        case 1: k_batched_id<64, false, 1, 16, false, COS><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
-        case 4: k_batched_id<WNT, false, 2, 16, true, COS><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord); break;
-        case 5: k_batched_id<256, false, 1, 16, true, COS><<<cnt[c], 256, lds[c], s>>>(d_tasks.p, ord); break;
-        default: k_batched_id<WNT, false, 2, 16, false, COS><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord); break;
+        case 3: k_batched_id<64, true, 1, 32, false, FAM><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
+        case 1: k_batched_id<64, false, 1, 16, false, FAM><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
+        case 4: k_batched_id<WNT, false, 2, 16, true, FAM><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord); break;
+        case 5: k_batched_id<256, false, 1, 16, true, FAM><<<cnt[c], 256, lds[c], s>>>(d_tasks.p, ord); break;
+        default: k_batched_id<WNT, false, 2, 16, false, FAM><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord); break;
         }
         H2_LAUNCH_CHECK();
     };
@@ -1116,13 +1121,13 @@ void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdPro
     launch(1);
     if (prof) H2_HIP(hipEventRecord(ev[1], s));
     if (!fold[0].empty())
-        k_id_fold<1, 32, 1, COS><<<(unsigned)fold[0].size(), 256, (2 * 32 + 4 + 8 * 256 + 3 * 32) * sizeof(double), s>>>(
+        k_id_fold<1, 32, 1, FAM><<<(unsigned)fold[0].size(), 256, (2 * 32 + 4 + 8 * 256 + 3 * 32) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[0]);
     if (!fold[1].empty())
-        k_id_fold<2, 16, 1, COS><<<(unsigned)fold[1].size(), 256, (2 * 16 + 4 + 8 * 256 + 3 * 16) * sizeof(double), s>>>(
+        k_id_fold<2, 16, 1, FAM><<<(unsigned)fold[1].size(), 256, (2 * 16 + 4 + 8 * 256 + 3 * 16) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[1]);
     if (!fold[2].empty())
-        k_id_fold<4, 8, 1, COS><<<(unsigned)fold[2].size(), 256, (2 * 8 + 4 + 8 * 256 + 3 * 8) * sizeof(double), s>>>(
+        k_id_fold<4, 8, 1, FAM><<<(unsigned)fold[2].size(), 256, (2 * 8 + 4 + 8 * 256 + 3 * 8) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[2]);
     H2_LAUNCH_CHECK();
     launch(5);
@@ -1143,14 +1148,15 @@ void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdPro
 
 }  // namespace
 
-// The ID tasks of the radial kernels and of the cosine kernel run through
-// separately compiled launches (a batched build may mix both).
+// The ID tasks of each kernel family run through their own instances of the
+// launches (a batched build may mix families).
 void batched_id(const std::vector<IdTask>& tasks, hipStream_t s, IdProf* prof)
 {
-    std::vector<IdTask> fam[2];
-    for (const IdTask& t : tasks) fam[t.kid == H2_COSINE ? 1 : 0].push_back(t);
-    batched_id_family<false>(fam[0], s, prof);
-    batched_id_family<true>(fam[1], s, prof);
+    std::vector<IdTask> fam[3];
+    for (const IdTask& t : tasks) fam[kernel_family(t.kid)].push_back(t);
+    batched_id_family<FAM_RADIAL>(fam[FAM_RADIAL], s, prof);
+    batched_id_family<FAM_COSINE>(fam[FAM_COSINE], s, prof);
+    batched_id_family<FAM_ADVECTION>(fam[FAM_ADVECTION], s, prof);
 }
 
 template <class T>
@@ -1178,30 +1184,49 @@ static double id_flop_count(int64_t s, int64_t m, int64_t k)
     return f + (double)k * (double)k * (double)(m - k);
 }
 
+// Nested bases of every problem of `hs`, level by level from the deepest,
+// all problems' nodes of a round in one batched ID.  A non-symmetric kernel
+// adds the column side: the same steps on K(Y_i*, Xbar_i)^T with row sets
+// from the column skeletons, in the same launches.
 void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
 {
-    struct St {
-        std::vector<int> ys_cnt;
-        int64_t piv_total = 0, T_total = 0;
+    // one unit per (problem, side)
+    struct Unit {
+        Handle* h;
+        Basis* b;
+        int swap;
+        const std::vector<int>* ys_cnt;
+        int64_t piv_total = 0, T_total = 0, xbase = 0;
+        int L = 0;
     };
     const int np = (int)hs.size();
-    std::vector<St> st(np);
+    std::vector<std::vector<int>> ys_cnt(np);
+    std::vector<Unit> units;
     int maxd = 0;
     for (int p = 0; p < np; ++p) {
         Handle& h = *hs[p];
         const int nn = h.nnode;
-        h.rank.ensure((size_t)nn, s);
-        h.mbar.ensure((size_t)nn, s);
-        h.skel.ensure((size_t)nn * h.ys_stride, s);
-        h.piv_off.ensure((size_t)nn + 1, s);
-        h.T_off.ensure((size_t)nn + 1, s);
-        H2_HIP(hipMemsetAsync(h.rank.p, 0, sizeof(int) * nn, s));
-        H2_HIP(hipMemsetAsync(h.mbar.p, 0, sizeof(int) * nn, s));
-        st[p].ys_cnt = read_vec(h.ys_cnt.p, nn, s);
-        h.h_rank.assign(nn, 0);
-        h.h_mbar.assign(nn, 0);
-        h.h_piv_off.assign((size_t)nn + 1, 0);
-        h.h_T_off.assign((size_t)nn + 1, 0);
+        ys_cnt[p] = read_vec(h.ys_cnt.p, nn, s);
+        for (int side = 0; side < (h.nonsym ? 2 : 1); ++side) {
+            Basis& b = side == 0 ? h.bu : h.bv;
+            b.rank.ensure((size_t)nn, s);
+            b.mbar.ensure((size_t)nn, s);
+            b.skel.ensure((size_t)nn * h.ys_stride, s);
+            b.piv_off.ensure((size_t)nn + 1, s);
+            b.T_off.ensure((size_t)nn + 1, s);
+            H2_HIP(hipMemsetAsync(b.rank.p, 0, sizeof(int) * nn, s));
+            H2_HIP(hipMemsetAsync(b.mbar.p, 0, sizeof(int) * nn, s));
+            b.h_rank.assign(nn, 0);
+            b.h_mbar.assign(nn, 0);
+            b.h_piv_off.assign((size_t)nn + 1, 0);
+            b.h_T_off.assign((size_t)nn + 1, 0);
+            Unit u;
+            u.h = &h;
+            u.b = &b;
+            u.swap = side;
+            u.ys_cnt = &ys_cnt[p];
+            units.push_back(u);
+        }
         maxd = std::max(maxd, h.maxdepth);
     }
     bool prof_on = false;
@@ -1212,51 +1237,49 @@ void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
     DBuf<int64_t> d_xoff;
     DBuf<double> Mws, nuws;
     for (int t = 0; t < maxd; ++t) {
-        // problems and levels of this round; grow piv / T first (the task
+        // units and levels of this round; grow piv / T first (the task
         // pointers must see the final buffers)
-        std::vector<int> lvl(np, 0);
         int64_t xtot = 0;
-        std::vector<int64_t> xbase(np, 0);
-        for (int p = 0; p < np; ++p) {
-            Handle& h = *hs[p];
-            const int L = h.maxdepth - t;
-            lvl[p] = L;
-            if (L < 1) continue;
-            xbase[p] = xtot;
-            const int64_t keep_piv = st[p].piv_total, keep_T = st[p].T_total;
-            for (int i = h.lvl_ptr[L]; i < h.lvl_ptr[L + 1]; ++i) {
+        for (Unit& u : units) {
+            Handle& h = *u.h;
+            Basis& b = *u.b;
+            u.L = h.maxdepth - t;
+            if (u.L < 1) continue;
+            u.xbase = xtot;
+            const int64_t keep_piv = u.piv_total, keep_T = u.T_total;
+            for (int i = h.lvl_ptr[u.L]; i < h.lvl_ptr[u.L + 1]; ++i) {
                 int m = 0;
                 if (h.h_nchild[i] == 0)
                     m = h.h_count[i];
                 else
-                    for (int c = h.h_first_child[i]; c < h.h_first_child[i] + h.h_nchild[i]; ++c) m += h.h_rank[c];
-                h.h_mbar[i] = m;
-                h.h_piv_off[i] = st[p].piv_total;
-                h.h_T_off[i] = st[p].T_total;
-                st[p].piv_total += m;
-                st[p].T_total += (int64_t)m * std::min(m, st[p].ys_cnt[i]);
+                    for (int c = h.h_first_child[i]; c < h.h_first_child[i] + h.h_nchild[i]; ++c) m += b.h_rank[c];
+                b.h_mbar[i] = m;
+                b.h_piv_off[i] = u.piv_total;
+                b.h_T_off[i] = u.T_total;
+                u.piv_total += m;
+                u.T_total += (int64_t)m * std::min(m, (*u.ys_cnt)[i]);
                 xtot += m;
             }
-            h.piv.grow_keep((size_t)std::max<int64_t>(st[p].piv_total, 1), (size_t)keep_piv, s);
-            h.T.grow_keep((size_t)std::max<int64_t>(st[p].T_total, 1), (size_t)keep_T, s);
+            b.piv.grow_keep((size_t)std::max<int64_t>(u.piv_total, 1), (size_t)keep_piv, s);
+            b.T.grow_keep((size_t)std::max<int64_t>(u.T_total, 1), (size_t)keep_T, s);
         }
         if (xtot == 0) continue;
         // row sets of the round
         d_xidx.ensure((size_t)xtot, s);
-        for (int p = 0; p < np; ++p) {
-            Handle& h = *hs[p];
-            const int L = lvl[p];
-            if (L < 1) continue;
-            const int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
+        for (Unit& u : units) {
+            Handle& h = *u.h;
+            Basis& b = *u.b;
+            if (u.L < 1) continue;
+            const int lo = h.lvl_ptr[u.L], nl = h.lvl_ptr[u.L + 1] - lo;
             std::vector<int64_t> xo((size_t)nl + 1, 0);
-            for (int q = 0; q < nl; ++q) xo[q + 1] = xo[q] + h.h_mbar[lo + q];
-            for (auto& v : xo) v += xbase[p];
+            for (int q = 0; q < nl; ++q) xo[q + 1] = xo[q] + b.h_mbar[lo + q];
+            for (auto& v : xo) v += u.xbase;
             d_xoff.ensure(xo.size(), s);
             H2_HIP(hipMemcpyAsync(d_xoff.p, xo.data(), xo.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
-            k_xbar_fill<<<nl, TB, 0, s>>>(lo, h.nchild.p, h.first_child.p, h.start.p, h.count.p, h.rank.p, h.skel.p,
+            k_xbar_fill<<<nl, TB, 0, s>>>(lo, h.nchild.p, h.first_child.p, h.start.p, h.count.p, b.rank.p, b.skel.p,
                                           h.ys_stride, d_xoff.p, d_xidx.p);
             H2_LAUNCH_CHECK();
-            H2_HIP(hipStreamSynchronize(s));  // d_xoff is reused by the next problem
+            H2_HIP(hipStreamSynchronize(s));  // d_xoff is reused by the next unit
         }
         // tasks, launched in chunks of bounded workspace
         std::vector<IdTask> tasks;
@@ -1277,13 +1300,13 @@ void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
             ws = 0;
             no = 0;
         };
-        for (int p = 0; p < np; ++p) {
-            Handle& h = *hs[p];
-            const int L = lvl[p];
-            if (L < 1) continue;
-            int64_t xo = xbase[p];
-            for (int i = h.lvl_ptr[L]; i < h.lvl_ptr[L + 1]; ++i) {
-                const int m = h.h_mbar[i], sy = st[p].ys_cnt[i];
+        for (Unit& u : units) {
+            Handle& h = *u.h;
+            Basis& b = *u.b;
+            if (u.L < 1) continue;
+            int64_t xo = u.xbase;
+            for (int i = h.lvl_ptr[u.L]; i < h.lvl_ptr[u.L + 1]; ++i) {
+                const int m = b.h_mbar[i], sy = (*u.ys_cnt)[i];
                 const int64_t need = (int64_t)m * sy;
                 if (!tasks.empty() && ws + need > WS_CAP) flush();
                 IdTask tk;
@@ -1291,16 +1314,17 @@ void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
                 tk.ld = h.n;
                 tk.x_idx = d_xidx.p + xo;
                 tk.y_idx = h.ys_idx.p + (int64_t)i * h.ys_stride;
-                tk.piv = h.piv.p + h.h_piv_off[i];
-                tk.T = h.T.p + h.h_T_off[i];
-                tk.skel = h.skel.p + (int64_t)i * h.ys_stride;
-                tk.rank = h.rank.p + i;
+                tk.piv = b.piv.p + b.h_piv_off[i];
+                tk.T = b.T.p + b.h_T_off[i];
+                tk.skel = b.skel.p + (int64_t)i * h.ys_stride;
+                tk.rank = b.rank.p + i;
                 tk.prm = h.prm;
                 tk.tol = h.tol_int;
                 tk.m = m;
                 tk.s = sy;
                 tk.d = h.d;
                 tk.kid = h.kid;
+                tk.swap = u.swap;
                 tasks.push_back(tk);
                 Moff.push_back(ws);
                 nuoff.push_back(no);
@@ -1310,33 +1334,34 @@ void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
             }
         }
         flush();
-        for (int p = 0; p < np; ++p) {
-            Handle& h = *hs[p];
-            const int L = lvl[p];
-            if (L < 1) continue;
-            const int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
-            std::vector<int> rk = read_vec(h.rank.p + lo, nl, s);
-            for (int q = 0; q < nl; ++q) h.h_rank[lo + q] = rk[q];
+        for (Unit& u : units) {
+            Handle& h = *u.h;
+            Basis& b = *u.b;
+            if (u.L < 1) continue;
+            const int lo = h.lvl_ptr[u.L], nl = h.lvl_ptr[u.L + 1] - lo;
+            std::vector<int> rk = read_vec(b.rank.p + lo, nl, s);
+            for (int q = 0; q < nl; ++q) b.h_rank[lo + q] = rk[q];
             if (prof_on)
                 for (int q = 0; q < nl; ++q) {
                     const int i = lo + q;
-                    const double f = id_flop_count(st[p].ys_cnt[i], h.h_mbar[i], rk[q]);
+                    const double f = id_flop_count((*u.ys_cnt)[i], b.h_mbar[i], rk[q]);
                     h.id_flops += f;
-                    if (h.h_mbar[i] > 64) h.id_wide_flops += f;
+                    if (b.h_mbar[i] > 64) h.id_wide_flops += f;
                 }
         }
     }
-    for (int p = 0; p < np; ++p) {
-        Handle& h = *hs[p];
+    for (Unit& u : units) {
+        Handle& h = *u.h;
+        Basis& b = *u.b;
         const int nn = h.nnode;
-        h.h_piv_off[nn] = st[p].piv_total;
-        h.h_T_off[nn] = st[p].T_total;
-        upload(h.mbar, h.h_mbar, s);
-        upload(h.piv_off, h.h_piv_off, s);
-        upload(h.T_off, h.h_T_off, s);
-        h.sum_rank = 0;
-        for (int i = 0; i < nn; ++i) h.sum_rank += h.h_rank[i];
-        h.bytes_T = st[p].T_total * (int64_t)sizeof(double);
+        b.h_piv_off[nn] = u.piv_total;
+        b.h_T_off[nn] = u.T_total;
+        upload(b.mbar, b.h_mbar, s);
+        upload(b.piv_off, b.h_piv_off, s);
+        upload(b.T_off, b.h_T_off, s);
+        b.sum_rank = 0;
+        for (int i = 0; i < nn; ++i) b.sum_rank += b.h_rank[i];
+        b.bytes_T = u.T_total * (int64_t)sizeof(double);
         h.id_ms = prof.ms_all;  // launches shared by all problems of the call
         h.id_wide_ms = prof.ms_wide;
     }

@@ -1,6 +1,7 @@
 // Coupling and nearfield blocks of Algorithm 2:
-//   B_ij = K(Xhat_i, Xhat_j)   for (i, j) in the interaction lists,
-//   D_ij = K(X_i, X_j)         for (i, j) in the near lists (leaf pairs).
+//   B_ij = K(Xhat_i^(row), Xhat_j^(col))   for (i, j) in the interaction lists,
+//   D_ij = K(X_i, X_j)                     for (i, j) in the near lists (leaf pairs);
+// the row and column skeletons coincide for a symmetric kernel.
 // Blocks are stored column-major (rank_i x rank_j, resp. count_i x count_j)
 // in CSR order of the lists; offsets come from a device scan over the block
 // sizes.  One workgroup per list row i.  These entries feed only the apply,
@@ -15,12 +16,13 @@ namespace {
 constexpr int TB = 256;
 
 __global__ __launch_bounds__(TB) void k_block_sizes(int nrow, const int* __restrict__ ptr, const int* __restrict__ col,
-                                                    const int* __restrict__ sz_node, int64_t* __restrict__ out)
+                                                    const int* __restrict__ sz_row, const int* __restrict__ sz_col,
+                                                    int64_t* __restrict__ out)
 {
     int i = blockIdx.x * TB + threadIdx.x;
     if (i >= nrow) return;
-    int64_t a = sz_node[i];
-    for (int e = ptr[i]; e < ptr[i + 1]; ++e) out[e] = a * sz_node[col[e]];
+    int64_t a = sz_row[i];
+    for (int e = ptr[i]; e < ptr[i + 1]; ++e) out[e] = a * sz_col[col[e]];
 }
 
 // Skeleton coordinates gathered into node order (SoA [d][sum k]) so that a
@@ -46,27 +48,38 @@ __global__ __launch_bounds__(TB) void k_entry_rows(int nrow, const int* __restri
     for (int e = ptr[i]; e < ptr[i + 1]; ++e) row[e] = i;
 }
 
+// Row and column point sets of the blocks: node i's points are cnt[i]
+// consecutive entries of the SoA array xs ([d][ld]) from xo[i].
+struct PtSet {
+    const double* xs;
+    int64_t ld;
+    const int64_t* xo;
+    const int* cnt;
+};
+
 // One wavefront per block (list entry e = (i, j)), four blocks per
-// workgroup.  Row points X_i (rows_i of them, contiguous in `xs` from xo[i])
-// and column points (cols_j from xo[j]) are loaded once, one per lane, and the
-// column point of each block column is broadcast with a lane shuffle.  The
-// block is column-major (entry (t,u) at u*rows_i + t); with rows_i <= 32 the
-// two half-waves fill two columns per pass.
-template <class OutT, bool COS>
+// workgroup.  Row points (rows_i of them, from the row set) and column points
+// (cols_j, from the column set) are loaded once, one per lane, and the column
+// point of each block column is broadcast with a lane shuffle.  The block is
+// column-major (entry (t,u) at u*rows_i + t); with rows_i <= 32 the two
+// half-waves fill two columns per pass.
+template <class OutT, int FAM>
 __global__ __launch_bounds__(TB) void k_blocks_eval(int64_t nent, const int* __restrict__ erow,
-                                                    const int* __restrict__ col, const int* __restrict__ cnt,
-                                                    const double* __restrict__ xs, int64_t ld,
-                                                    const int64_t* __restrict__ xo, int d, int kid, double prm,
-                                                    const int64_t* __restrict__ off, OutT* __restrict__ out)
+                                                    const int* __restrict__ col, PtSet rs, PtSet cs, int d, int kid,
+                                                    double prm, const int64_t* __restrict__ off,
+                                                    OutT* __restrict__ out)
 {
     const int64_t e = (int64_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6);
     if (e >= nent) return;
     const int lane = threadIdx.x & 63;
     const int i = erow[e], j = col[e];
-    const int ki = cnt[i], kj = cnt[j];
+    const int ki = rs.cnt[i], kj = cs.cnt[j];
     if (ki == 0 || kj == 0) return;
     OutT* o = out + off[e];
-    const int64_t bi = xo[i], bj = xo[j];
+    const int64_t bi = rs.xo[i], bj = cs.xo[j];
+    const double* xs = rs.xs;
+    const double* ys = cs.xs;
+    const int64_t ld = rs.ld, lc = cs.ld;
     for (int t0 = 0; t0 < ki; t0 += 64) {
         const bool half = ki - t0 <= 32;  // two columns per pass
         const int t = half ? t0 + (lane & 31) : t0 + lane;
@@ -82,9 +95,9 @@ __global__ __launch_bounds__(TB) void k_blocks_eval(int64_t nent, const int* __r
             const int uc = min(64, kj - u0);
             double y0 = 0.0, y1 = 0.0, y2 = 0.0;
             if (lane < uc) {
-                y0 = xs[bj + u0 + lane];
-                if (d > 1) y1 = xs[ld + bj + u0 + lane];
-                if (d > 2) y2 = xs[2 * ld + bj + u0 + lane];
+                y0 = ys[bj + u0 + lane];
+                if (d > 1) y1 = ys[lc + bj + u0 + lane];
+                if (d > 2) y2 = ys[2 * lc + bj + u0 + lane];
             }
             // wave-uniform trip count: every lane takes part in every shuffle
             for (int ub = 0; ub < uc; ub += su) {
@@ -94,7 +107,7 @@ __global__ __launch_bounds__(TB) void k_blocks_eval(int64_t nent, const int* __r
                 const double s1 = d > 1 ? __shfl(y1, src, 64) : 0.0;
                 const double s2 = d > 2 ? __shfl(y2, src, 64) : 0.0;
                 double r2 = 0.0, xy = 0.0;  // xy: the cosine kernel's inner product
-                if constexpr (COS) {
+                if constexpr (FAM == FAM_COSINE) {
                     xy = xi0 * s0;
                     if (d > 1) xy += xi1 * s1;
                     if (d > 2) xy += xi2 * s2;
@@ -110,22 +123,27 @@ __global__ __launch_bounds__(TB) void k_blocks_eval(int64_t nent, const int* __r
                         r2 += a2 * a2;
                     }
                 }
-                if (t < ki && uu < uc) o[(int64_t)(u0 + uu) * ki + t] = kappa_store<OutT, COS>(kid, prm, r2, xy);
+                if (t < ki && uu < uc) o[(int64_t)(u0 + uu) * ki + t] = kappa_store<OutT, FAM>(kid, prm, r2, xy, xi0 - s0);
             }
         }
     }
 }
 
-// The cosine kernel's blocks come from their own instance (see kappa_rx).
+// Each kernel family's blocks come from their own instance (see kappa_fam).
 template <class OutT>
-void launch_blocks_eval(int64_t nent, const int* erow, const int* col, const int* cnt, const double* xs, int64_t ld,
-                        const int64_t* xo, int d, int kid, double prm, const int64_t* off, OutT* out, hipStream_t s)
+void launch_blocks_eval(int64_t nent, const int* erow, const int* col, const PtSet& rs, const PtSet& cs, int d,
+                        int kid, double prm, const int64_t* off, OutT* out, hipStream_t s)
 {
     const unsigned nb = (unsigned)blocks_for(nent, TB / 64);
-    if (kid == H2_COSINE)
-        k_blocks_eval<OutT, true><<<nb, TB, 0, s>>>(nent, erow, col, cnt, xs, ld, xo, d, kid, prm, off, out);
-    else
-        k_blocks_eval<OutT, false><<<nb, TB, 0, s>>>(nent, erow, col, cnt, xs, ld, xo, d, kid, prm, off, out);
+    switch (kernel_family(kid)) {
+    case FAM_COSINE:
+        k_blocks_eval<OutT, FAM_COSINE><<<nb, TB, 0, s>>>(nent, erow, col, rs, cs, d, kid, prm, off, out);
+        break;
+    case FAM_ADVECTION:
+        k_blocks_eval<OutT, FAM_ADVECTION><<<nb, TB, 0, s>>>(nent, erow, col, rs, cs, d, kid, prm, off, out);
+        break;
+    default: k_blocks_eval<OutT, FAM_RADIAL><<<nb, TB, 0, s>>>(nent, erow, col, rs, cs, d, kid, prm, off, out);
+    }
     H2_LAUNCH_CHECK();
 }
 
@@ -142,19 +160,26 @@ void build_blocks(Handle& h)
     const int64_t nmax = std::max<int64_t>(std::max(h.nil, h.nnear), 1);
     sz.ensure((size_t)nmax, s);
     erow.ensure((size_t)nmax, s);
-    // skeleton coordinates in node order
-    std::vector<int64_t> xo((size_t)nn + 1, 0);
-    for (int i = 0; i < nn; ++i) xo[i + 1] = xo[i] + h.h_rank[i];
-    const int64_t sumk = std::max<int64_t>(xo[nn], 1);
-    DBuf<int64_t> d_xo;
-    d_xo.ensure(xo.size(), s);
-    H2_HIP(hipMemcpyAsync(d_xo.p, xo.data(), xo.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    DBuf<double> skc;
-    skc.ensure((size_t)h.d * sumk, s);
-    k_skel_coords<<<nn, TB, 0, s>>>(nn, h.pts.p, h.n, h.d, h.rank.p, h.skel.p, h.ys_stride, d_xo.p, sumk, skc.p);
-    H2_LAUNCH_CHECK();
+    // skeleton coordinates in node order: the row skeletons, and the column
+    // skeletons of a non-symmetric kernel
+    DBuf<int64_t> d_xo[2];
+    DBuf<double> skc[2];
+    auto skel_set = [&](const Basis& b, int w) -> PtSet {
+        std::vector<int64_t> xo((size_t)nn + 1, 0);
+        for (int i = 0; i < nn; ++i) xo[i + 1] = xo[i] + b.h_rank[i];
+        const int64_t sumk = std::max<int64_t>(xo[nn], 1);
+        d_xo[w].ensure(xo.size(), s);
+        H2_HIP(hipMemcpyAsync(d_xo[w].p, xo.data(), xo.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        skc[w].ensure((size_t)h.d * sumk, s);
+        k_skel_coords<<<nn, TB, 0, s>>>(nn, h.pts.p, h.n, h.d, b.rank.p, b.skel.p, h.ys_stride, d_xo[w].p, sumk,
+                                        skc[w].p);
+        H2_LAUNCH_CHECK();
+        return PtSet{skc[w].p, sumk, d_xo[w].p, b.rank.p};
+    };
+    const PtSet rs = skel_set(h.bu, 0);
+    const PtSet cs = h.nonsym ? skel_set(h.bv, 1) : rs;
     // coupling
-    k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, h.il_col.p, h.rank.p, sz.p);
+    k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, h.il_col.p, h.bu.rank.p, h.col().rank.p, sz.p);
     H2_LAUNCH_CHECK();
     scan_excl_i64(sz.p, h.B_off.p, h.nil, h.tmp_i64, s);
     int64_t nB = read_scalar(h.B_off.p + h.nil, s);
@@ -173,14 +198,12 @@ void build_blocks(Handle& h)
         k_entry_rows<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, erow.p);
         H2_LAUNCH_CHECK();
         if (f32)
-            launch_blocks_eval(h.nil, erow.p, h.il_col.p, h.rank.p, skc.p, sumk, d_xo.p, h.d, h.kid, h.prm,
-                               h.B_off.p, h.Bf.p, s);
+            launch_blocks_eval(h.nil, erow.p, h.il_col.p, rs, cs, h.d, h.kid, h.prm, h.B_off.p, h.Bf.p, s);
         else
-            launch_blocks_eval(h.nil, erow.p, h.il_col.p, h.rank.p, skc.p, sumk, d_xo.p, h.d, h.kid, h.prm,
-                               h.B_off.p, h.B.p, s);
+            launch_blocks_eval(h.nil, erow.p, h.il_col.p, rs, cs, h.d, h.kid, h.prm, h.B_off.p, h.B.p, s);
     }
     // nearfield: the leaves' points are contiguous in tree order
-    k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.nr_ptr.p, h.nr_col.p, h.count.p, sz.p);
+    k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.nr_ptr.p, h.nr_col.p, h.count.p, h.count.p, sz.p);
     H2_LAUNCH_CHECK();
     scan_excl_i64(sz.p, h.D_off.p, h.nnear, h.tmp_i64, s);
     int64_t nD = read_scalar(h.D_off.p + h.nnear, s);
@@ -199,12 +222,11 @@ void build_blocks(Handle& h)
         H2_HIP(hipMemcpyAsync(d_st.p, st.data(), st.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
         k_entry_rows<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.nr_ptr.p, erow.p);
         H2_LAUNCH_CHECK();
+        const PtSet ps{h.pts.p, h.n, d_st.p, h.count.p};
         if (f32)
-            launch_blocks_eval(h.nnear, erow.p, h.nr_col.p, h.count.p, h.pts.p, h.n, d_st.p, h.d, h.kid, h.prm,
-                               h.D_off.p, h.Df.p, s);
+            launch_blocks_eval(h.nnear, erow.p, h.nr_col.p, ps, ps, h.d, h.kid, h.prm, h.D_off.p, h.Df.p, s);
         else
-            launch_blocks_eval(h.nnear, erow.p, h.nr_col.p, h.count.p, h.pts.p, h.n, d_st.p, h.d, h.kid, h.prm,
-                               h.D_off.p, h.D.p, s);
+            launch_blocks_eval(h.nnear, erow.p, h.nr_col.p, ps, ps, h.d, h.kid, h.prm, h.D_off.p, h.D.p, s);
         H2_HIP(hipStreamSynchronize(s));
     }
     H2_HIP(hipStreamSynchronize(s));

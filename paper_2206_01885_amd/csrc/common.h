@@ -129,6 +129,24 @@ void scan_excl_i64(const int64_t* in, int64_t* out, int64_t cnt, DBuf<int64_t>& 
 // tile of the apply reads up to 15 elements past the end of a block column.
 constexpr int64_t BLK_PAD = 64;
 
+// One side of the nested bases of Algorithm 2: per node the rank k, the row
+// count m of its block (the points X_i of a leaf, else the children's
+// skeletons), the pivots and T of the ID (U_i = P [I; T^T]), the skeleton
+// points, and the offsets of the node's coefficients in xhat / yhat.
+struct Basis {
+    DBuf<int> rank, mbar;
+    std::vector<int> h_rank, h_mbar;
+    DBuf<int> skel;         // stride ys_stride: skeleton tree positions in pivot order
+    DBuf<int64_t> piv_off;  // per node offset into piv
+    DBuf<int> piv;          // per node m_i entries
+    DBuf<int64_t> T_off;    // per node offset into T (row-major k x (m-k))
+    DBuf<double> T;
+    DBuf<float> Tf;         // precision mode: T in FP32
+    std::vector<int64_t> h_piv_off, h_T_off;
+    DBuf<int64_t> xh_off;   // per node offset (in units of rank) into xhat / yhat
+    int64_t sum_rank = 0, bytes_T = 0;
+};
+
 struct Handle {
     // problem
     int64_t n = 0;
@@ -166,25 +184,20 @@ struct Handle {
     std::vector<int> calib_r;
     std::vector<double> calib_err;
 
-    // bases
-    DBuf<int> rank, mbar;
-    std::vector<int> h_rank, h_mbar;
-    DBuf<int> skel;         // stride ys_stride: skeleton tree positions in pivot order
-    DBuf<int64_t> piv_off;  // per node offset into piv
-    DBuf<int> piv;          // per node m_i entries
-    DBuf<int64_t> T_off;    // per node offset into T (row-major k x (m-k))
-    DBuf<double> T;
-    std::vector<int64_t> h_piv_off, h_T_off;
+    // bases: bu holds U and R (row side, the ID of K(Xbar_i, Y_i*)); for a
+    // non-symmetric kernel bv holds V and W (column side, the ID of
+    // K(Y_i*, Xbar_i)^T), otherwise V = U and bu serves both sides
+    bool nonsym = false;
+    Basis bu, bv;
+    Basis& col() { return nonsym ? bv : bu; }
 
     // coupling and nearfield blocks
     DBuf<int64_t> B_off;  // per IL entry (CSR order), size nil+1
     DBuf<double> B;
     DBuf<int64_t> D_off;  // per near entry, size nnear+1
     DBuf<double> D;
-    DBuf<float> Bf, Df, Tf;  // precision mode: FP32 blocks and interpolation matrices
-    DBuf<int64_t> xh_off;  // per node offset (in units of rank) into xhat/yhat
-    DBuf<int> leaves;      // leaf node ids
-    int64_t sum_rank = 0;
+    DBuf<float> Bf, Df;  // precision mode: FP32 blocks
+    DBuf<int> leaves;    // leaf node ids
 
     // apply task lists: (node, first row) of every 32-row chunk of a block
     // row, split by whether the chunk holds one or two 16-row tiles
@@ -216,7 +229,7 @@ struct Handle {
 
     // diagnostics
     double t_tree = 0, t_lists = 0, t_calib = 0, t_hidr = 0, t_basis = 0, t_blocks = 0;
-    int64_t bytes_B = 0, bytes_D = 0, bytes_T = 0;
+    int64_t bytes_B = 0, bytes_D = 0;
     // interpolative decompositions of the build (profile = 1): launch times
     // (ms) and the algorithmic floating-point operations of the IDs
     double id_ms = 0, id_wide_ms = 0, id_flops = 0, id_wide_flops = 0;
@@ -270,6 +283,7 @@ struct IdTask {
     int* rank = nullptr;         // 1 entry
     double prm = 1.0, tol = 0.0;
     int m = 0, s = 0, d = 0, kid = 0;
+    int swap = 0;    // 1: column side, entries kappa(y_r, x_c) instead of kappa(x_c, y_r)
     int folded = 0;  // set by batched_id: M holds the m x m R factor of the block
 };
 // HIP-event time (ms) of batched_id's launches: all classes, and the class of

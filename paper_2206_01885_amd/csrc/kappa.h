@@ -27,15 +27,35 @@ __device__ __forceinline__ double kappa_r2(int kid, double prm, double r2)
     }
 }
 
-// kappa from the squared distance r2 or the inner product xy = x.y.  The
-// cosine kernel (kappa_3 of Table 1) is the one that depends on xy; kernels
-// that evaluate it are compiled apart (COS = true), so that the radial
-// kernels' code does not carry the register cost of cos.
-template <bool COS>
-__device__ __forceinline__ double kappa_rx(int kid, double prm, double r2, double xy)
+// Kernel families.  The kernels that evaluate kappa are compiled once per
+// family, so that the radial kernels' code (functions of r2 = |x - y|^2)
+// carries neither the register cost of cos nor the drift term:
+//   FAM_RADIAL     Coulomb, Gaussian, exponential, Matern-3/2, bump
+//   FAM_COSINE     kappa_3 of Table 1, a function of xy = x.y
+//   FAM_ADVECTION  the advection-diffusion kernel, a function of r2 and of
+//                  d0 = (x - y)_0; not symmetric
+enum { FAM_RADIAL = 0, FAM_COSINE = 1, FAM_ADVECTION = 2 };
+inline int kernel_family(int kid)
 {
-    if constexpr (COS)
+    return kid == H2_COSINE ? FAM_COSINE : (kid == H2_ADVECTION ? FAM_ADVECTION : FAM_RADIAL);
+}
+
+// exp(a (d0 - r)) / r with r = sqrt(r2), 0 at r2 = 0 (a = prm): the Green's
+// function of steady advection-diffusion with the drift along axis 0.
+__device__ __forceinline__ double kappa_advection(double prm, double r2, double d0)
+{
+    if (!(r2 > 0.0)) return 0.0;
+    const double r = sqrt(r2);
+    return exp(prm * (d0 - r)) / r;
+}
+
+template <int FAM>
+__device__ __forceinline__ double kappa_fam(int kid, double prm, double r2, double xy, double d0)
+{
+    if constexpr (FAM == FAM_COSINE)
         return cos(prm * xy);
+    else if constexpr (FAM == FAM_ADVECTION)
+        return kappa_advection(prm, r2, d0);
     else
         return kappa_r2(kid, prm, r2);
 }
@@ -93,11 +113,11 @@ __device__ __forceinline__ float kappa_f32(int kid, float prm, double r2d)
     }
 }
 
-template <class T, bool COS>
-__device__ __forceinline__ T kappa_store(int kid, double prm, double r2, double xy)
+template <class T, int FAM>
+__device__ __forceinline__ T kappa_store(int kid, double prm, double r2, double xy, double d0)
 {
-    if constexpr (COS)
-        return (T)cos(prm * xy);
+    if constexpr (FAM != FAM_RADIAL)
+        return (T)kappa_fam<FAM>(kid, prm, r2, xy, d0);
     else if constexpr (std::is_same_v<T, float>)
         return kappa_f32(kid, (float)prm, r2);
     else

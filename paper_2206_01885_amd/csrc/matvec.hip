@@ -392,7 +392,7 @@ struct ApplyBufs<double> {
     static DBuf<double>& yh(Handle& h) { return h.yh; }
     static const double* B(Handle& h) { return h.B.p; }
     static const double* D(Handle& h) { return h.D.p; }
-    static const double* Tm(Handle& h) { return h.T.p; }
+    static const double* Tm(const Basis& b) { return b.T.p; }
 };
 template <>
 struct ApplyBufs<float> {
@@ -402,7 +402,7 @@ struct ApplyBufs<float> {
     static DBuf<float>& yh(Handle& h) { return h.yhf; }
     static const float* B(Handle& h) { return h.Bf.p; }
     static const float* D(Handle& h) { return h.Df.p; }
-    static const float* Tm(Handle& h) { return h.Tf.p; }
+    static const float* Tm(const Basis& b) { return b.Tf.p; }
 };
 
 template <class T>
@@ -415,15 +415,18 @@ void matvec_t(Handle& h, const T* x, T* y, int nrhs, hipStream_t s)
         H2_HIP(hipStreamSynchronize(s));
         AB::xt(h).ensure((size_t)n * ld, s);
         AB::yt(h).ensure((size_t)n * ld, s);
-        AB::xh(h).ensure((size_t)std::max<int64_t>(h.sum_rank, 1) * ld, s);
-        AB::yh(h).ensure((size_t)std::max<int64_t>(h.sum_rank, 1) * ld, s);
+        AB::xh(h).ensure((size_t)std::max<int64_t>(h.col().sum_rank, 1) * ld, s);
+        AB::yh(h).ensure((size_t)std::max<int64_t>(h.bu.sum_rank, 1) * ld, s);
         h.mv_ld = ld;
     }
     T* xt = AB::xt(h).p;
     T* yt = AB::yt(h).p;
     T* xh = AB::xh(h).p;
     T* yh = AB::yh(h).p;
-    const T* Tm = AB::Tm(h);
+    // upward through V, W (the column basis), downward through U, R
+    const Basis& bv = h.col();
+    const T* Tm = AB::Tm(h.bu);
+    const T* Tv = AB::Tm(bv);
     const T* zero = (const T*)h.zeros.p;
     const bool prof = h.profile != 0;
     auto mark = [&](int e) {
@@ -437,26 +440,26 @@ void matvec_t(Handle& h, const T* x, T* y, int nrhs, hipStream_t s)
     mark(1);
     for (int L = h.maxdepth; L >= 1; --L) {
         int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
-        k_upward<T><<<nl, TB, 0, s>>>(lo, nrhs, ld, h.nchild.p, h.first_child.p, h.start.p, h.rank.p, h.mbar.p,
-                                      h.piv_off.p, h.piv.p, h.T_off.p, Tm, h.xh_off.p, xt, xh);
+        k_upward<T><<<nl, TB, 0, s>>>(lo, nrhs, ld, h.nchild.p, h.first_child.p, h.start.p, bv.rank.p, bv.mbar.p,
+                                      bv.piv_off.p, bv.piv.p, bv.T_off.p, Tv, bv.xh_off.p, xt, xh);
         H2_LAUNCH_CHECK();
     }
     mark(2);
     // the precision mode adds each block product (one interaction) to the
     // row sums with compensation: FP32 recursion over the ~10^4 terms of an
     // interaction list would lose about sqrt(10^4) ulps
-    launch_sweep<T, sizeof(T) == 4>(h.cp, h.il_ptr.p, h.rank.p, h.B_off.p, AB::B(h), xh, h.xh_off.p, yh, ld, 0,
+    launch_sweep<T, sizeof(T) == 4>(h.cp, h.il_ptr.p, h.bu.rank.p, h.B_off.p, AB::B(h), xh, h.bu.xh_off.p, yh, ld, 0,
                                     zero, s);
     mark(3);
     for (int L = 1; L < h.maxdepth; ++L) {
         int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
-        k_downward<T><<<nl, TB, 0, s>>>(lo, nrhs, ld, h.nchild.p, h.first_child.p, h.rank.p, h.mbar.p,
-                                        h.piv_off.p, h.piv.p, h.T_off.p, Tm, h.xh_off.p, yh);
+        k_downward<T><<<nl, TB, 0, s>>>(lo, nrhs, ld, h.nchild.p, h.first_child.p, h.bu.rank.p, h.bu.mbar.p,
+                                        h.bu.piv_off.p, h.bu.piv.p, h.bu.T_off.p, Tm, h.bu.xh_off.p, yh);
         H2_LAUNCH_CHECK();
     }
     mark(4);
-    k_leaves_far<T><<<(unsigned)h.leaves.n, TB, 0, s>>>(nrhs, ld, h.leaves.p, h.start.p, h.count.p, h.rank.p,
-                                                        h.piv_off.p, h.piv.p, h.T_off.p, Tm, h.xh_off.p, yh, yt);
+    k_leaves_far<T><<<(unsigned)h.leaves.n, TB, 0, s>>>(nrhs, ld, h.leaves.p, h.start.p, h.count.p, h.bu.rank.p,
+                                                        h.bu.piv_off.p, h.bu.piv.p, h.bu.T_off.p, Tm, h.bu.xh_off.p, yh, yt);
     H2_LAUNCH_CHECK();
     launch_sweep<T, sizeof(T) == 4>(h.nr, h.nr_ptr.p, h.count.p, h.D_off.p, AB::D(h), xt, h.start64.p, yt, ld, 1,
                                     zero, s);
@@ -507,13 +510,15 @@ void prepare_apply(Handle& h)
     std::vector<int64_t> st(h.h_start.begin(), h.h_start.end());
     h.start64.ensure(std::max<size_t>(st.size(), 1), s);
     H2_HIP(hipMemcpyAsync(h.start64.p, st.data(), st.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    // coupling: every node with a basis writes its yhat (zero without IL)
-    make(h.h_rank, h.h_il_ptr, true, h.cp);
+    // coupling: every node with a basis writes its yhat (zero without IL);
+    // block rows follow the row ranks, block columns (and the xhat they
+    // read) the column ranks
+    make(h.bu.h_rank, h.h_il_ptr, true, h.cp);
     h.cp.ek.ensure(std::max<int64_t>(h.nil, 1), s);
     h.cp.ex.ensure(std::max<int64_t>(h.nil, 1), s);
     h.cp.steps.ensure(std::max(h.nnode, 1), s);
-    k_sweep_meta<<<blocks_for(h.nnode, TB), TB, 0, s>>>(h.nnode, h.il_ptr.p, h.il_col.p, h.rank.p, h.xh_off.p,
-                                                        h.cp.ek.p, h.cp.ex.p, h.cp.steps.p);
+    k_sweep_meta<<<blocks_for(h.nnode, TB), TB, 0, s>>>(h.nnode, h.il_ptr.p, h.il_col.p, h.col().rank.p,
+                                                        h.col().xh_off.p, h.cp.ek.p, h.cp.ex.p, h.cp.steps.p);
     H2_LAUNCH_CHECK();
     // nearfield: leaves with near entries (a leaf's own block is one)
     std::vector<int> leaf_rows(h.nnode, 0);
@@ -526,12 +531,14 @@ void prepare_apply(Handle& h)
     k_sweep_meta<<<blocks_for(h.nnode, TB), TB, 0, s>>>(h.nnode, h.nr_ptr.p, h.nr_col.p, h.count.p, h.start64.p,
                                                         h.nr.ek.p, h.nr.ex.p, h.nr.steps.p);
     H2_LAUNCH_CHECK();
-    if (h.precision == 32) {
-        const int64_t nt = std::max<int64_t>(h.h_T_off[h.nnode], 1);
-        h.Tf.ensure((size_t)nt, s);
-        k_to_f32<<<blocks_for(nt, TB), TB, 0, s>>>(h.T.p, nt, h.Tf.p);
-        H2_LAUNCH_CHECK();
-    }
+    if (h.precision == 32)
+        for (Basis* b : {&h.bu, &h.bv}) {
+            if (b == &h.bv && !h.nonsym) break;
+            const int64_t nt = std::max<int64_t>(b->h_T_off[h.nnode], 1);
+            b->Tf.ensure((size_t)nt, s);
+            k_to_f32<<<blocks_for(nt, TB), TB, 0, s>>>(b->T.p, nt, b->Tf.p);
+            H2_LAUNCH_CHECK();
+        }
     H2_HIP(hipStreamSynchronize(s));
 }
 

@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libh2.so")
 
 H2_OK, H2_EINVAL, H2_ENOMEM, H2_EDEVICE, H2_EUNSUPPORTED, H2_EINTERNAL = 0, -1, -2, -3, -4, -5
-KERNELS = {"coulomb": 0, "gaussian": 1, "exponential": 2, "matern32": 3, "bump": 4, "cosine": 5}
+KERNELS = {"coulomb": 0, "gaussian": 1, "exponential": 2, "matern32": 3, "bump": 4, "cosine": 5,
+           "advection": 6}
 
 EXPORTS = {"perm": (0, np.int32), "parent": (1, np.int32), "first_child": (2, np.int32),
            "nchild": (3, np.int32), "start": (4, np.int32), "count": (5, np.int32),
@@ -26,7 +27,9 @@ EXPORTS = {"perm": (0, np.int32), "parent": (1, np.int32), "first_child": (2, np
            "near_col": (12, np.int32), "xstar": (13, np.int32), "ystar": (14, np.int32),
            "rank": (15, np.int32), "mbar": (16, np.int32), "piv": (17, np.int32),
            "skel": (18, np.int32), "T": (19, np.float64), "points": (20, np.float64),
-           "B": (21, np.float64), "calib_r": (22, np.int32)}
+           "B": (21, np.float64), "calib_r": (22, np.int32),
+           "rank_v": (23, np.int32), "mbar_v": (24, np.int32), "piv_v": (25, np.int32),
+           "skel_v": (26, np.int32), "T_v": (27, np.float64)}
 
 
 class H2Error(RuntimeError):
@@ -52,7 +55,9 @@ class h2_info(C.Structure):
                 ("mv_coupling", C.c_double), ("mv_downward", C.c_double), ("mv_leaves", C.c_double),
                 ("mv_scatter", C.c_double), ("mv_nrhs", C.c_int), ("id_ms", C.c_double),
                 ("id_wide_ms", C.c_double), ("id_flops", C.c_double), ("id_wide_flops", C.c_double),
-                ("hidr_down_ms", C.c_double), ("hidr_down_bytes", C.c_double)]
+                ("hidr_down_ms", C.c_double), ("hidr_down_bytes", C.c_double),
+                ("nonsymmetric", C.c_int), ("max_rank_v", C.c_int), ("sum_rank_v", C.c_int64),
+                ("bytes_V", C.c_int64)]
 
 
 SYMBOLS = ["h2_options_default", "h2_build", "h2_build_ex", "h2_build_batched", "h2_rebuild", "h2_matvec",

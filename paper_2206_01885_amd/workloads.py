@@ -19,7 +19,8 @@ import math
 
 import numpy as np
 
-KERNEL_IDS = {"coulomb": 0, "gaussian": 1, "exponential": 2, "matern32": 3, "bump": 4, "cosine": 5}
+KERNEL_IDS = {"coulomb": 0, "gaussian": 1, "exponential": 2, "matern32": 3, "bump": 4, "cosine": 5,
+              "advection": 6}
 
 
 def cube(rng, n, d):

@@ -58,32 +58,38 @@ def _compare_structure(g, o):
     assert np.array_equal(pts, o.get("points"))
 
 
-def _compare_reduction_and_bases(g, o, t_rtol=None, tol=1e-6):
+def _compare_reduction_and_bases(g, o, t_rtol=None, tol=1e-6, sides=(0,)):
+    """X*, Y* and the nested bases against the oracle's: side 0 the row basis
+    U, R; side 1 the column basis V, W (a separate basis only for a
+    non-symmetric kernel)."""
     if t_rtol is None:
         t_rtol = 10.0 * U_ROUND / (0.5 * tol)
     gi, oi = g.info(), o.info()
     assert (gi["r1"], gi["r2"]) == (oi["r1"], oi["r2"])
     nn = oi["nnode"]
-    bad = {"xstar": 0, "ystar": 0, "rank": 0, "piv": 0, "skel": 0}
+    bad = {"xstar": 0, "ystar": 0}
     for i in range(1, nn):
         for name in ("xstar", "ystar"):
             if not np.array_equal(g.export(name, i), o.node_list(name, i)):
                 bad[name] += 1
-    grank, orank = g.export("rank"), o.get("rank")
-    bad["rank"] = int(np.sum(grank != orank))
-    assert np.array_equal(g.export("mbar"), o.get("mbar"))
     tmax = 0.0
-    for i in range(1, nn):
-        if grank[i] != orank[i]:
-            continue
-        if not np.array_equal(g.export("piv", i), o.node_list("piv", i)):
-            bad["piv"] += 1
-            continue
-        if not np.array_equal(g.export("skel", i), o.node_list("skel", i)):
-            bad["skel"] += 1
-        Tg, To = g.export("T", i), o.node_T(i).ravel()
-        if To.size:
-            tmax = max(tmax, np.max(np.abs(Tg - To)) / max(np.max(np.abs(To)), 1e-300))
+    for side in sides:
+        v = "_v" if side else ""
+        grank, orank = g.export("rank" + v), o.get("rank" + v)
+        bad["rank" + v] = int(np.sum(grank != orank))
+        bad["piv" + v] = bad["skel" + v] = 0
+        assert np.array_equal(g.export("mbar" + v), o.get("mbar" + v))
+        for i in range(1, nn):
+            if grank[i] != orank[i]:
+                continue
+            if not np.array_equal(g.export("piv" + v, i), o.node_list("piv" + v, i)):
+                bad["piv" + v] += 1
+                continue
+            if not np.array_equal(g.export("skel" + v, i), o.node_list("skel" + v, i)):
+                bad["skel" + v] += 1
+            Tg, To = g.export("T" + v, i), o.node_T(i, side=side).ravel()
+            if To.size:
+                tmax = max(tmax, np.max(np.abs(Tg - To)) / max(np.max(np.abs(To)), 1e-300))
     _say(f"mismatching nodes: {bad}, max rel |T diff| {tmax:.3e}")
     assert all(v == 0 for v in bad.values()), bad
     assert tmax <= t_rtol
@@ -171,6 +177,31 @@ def test_three_spheres_table1_kernels(H, kernel, prm, r):
         assert _rel(yg[r], ref[r]) <= 1e-6
 
 
+@pytest.mark.parametrize("d,prm,n,leaf,r", [(3, 2.0, 3000, 32, 216), (2, 0.5, 4000, 40, 100),
+                                            (3, 8.0, 2500, 64, 343), (1, 3.0, 2000, 32, 64)])
+def test_nonsymmetric_advection_parity(H, d, prm, n, leaf, r):
+    """The non-symmetric advection kernel: the build keeps a column basis V, W
+    of its own (Algorithm 2).  Structure, X*, Y* and both bases (ranks,
+    pivots, skeletons exactly; T to rounding) equal the oracle's, the product
+    is within 1e-10 of the oracle's and within the tolerance of the dense
+    product."""
+    rng = np.random.default_rng(900 + d)
+    P = rng.random((n, d)) ** 1.5
+    x = rng.standard_normal((2, n))
+    _say(f"advection a={prm} d{d} n{n} leaf{leaf} r{r}")
+    g, o = _build(H, P, "advection", prm, 1e-6, leaf, r=r)
+    info = g.info()
+    assert info["nonsymmetric"] == 1 and info["bytes_V"] > 0
+    _compare_structure(g, o)
+    _compare_reduction_and_bases(g, o, sides=(0, 1))
+    differ = sum(not np.array_equal(g.export("skel", i), g.export("skel_v", i)) for i in range(1, info["nnode"]))
+    _say(f"nodes whose column skeleton differs from the row skeleton: {differ} of {info['nnode'] - 1}")
+    yg = g.matvec(x).cpu().numpy()
+    assert _rel(yg, o.matvec(x)) <= 1e-10
+    ref = O.dense_rows(P, "advection", prm, x)
+    assert max(_rel(yg[k], ref[k]) for k in range(2)) <= 1e-6
+
+
 def test_exact_limit_against_dense(H):
     """r1 = r2 >= n and a rounding-level tolerance: the GPU H^2 product equals
     the dense product."""
@@ -233,9 +264,10 @@ def test_invalid_points_rejected(H):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("kernel,prm,d,n,leaf", [("coulomb", 1.0, 3, 4096, 64), ("gaussian", 0.1, 2, 20000, 128),
-                                                 ("matern32", 0.2, 3, 3000, 40)])
-def test_precision_mode_against_fp64_oracle(H, kernel, prm, d, n, leaf):
+@pytest.mark.parametrize("kernel,prm,d,n,leaf,r", [("coulomb", 1.0, 3, 4096, 64, 0), ("gaussian", 0.1, 2, 20000, 128, 0),
+                                                   ("matern32", 0.2, 3, 3000, 40, 0),
+                                                   ("advection", 2.0, 3, 3000, 32, 216)])
+def test_precision_mode_against_fp64_oracle(H, kernel, prm, d, n, leaf, r):
     """Precision mode (FP32 blocks, FP32 apply, compensated nearfield): the
     structure and the skeletons are the FP64 path's (the ID stays FP64), and
     the FP32 product is within 1e-6 of the FP64 oracle's (a few FP32 ulps
@@ -244,10 +276,10 @@ def test_precision_mode_against_fp64_oracle(H, kernel, prm, d, n, leaf):
     P = rng.random((n, d))
     x = rng.standard_normal((4, n))
     _say(f"precision32 {kernel}-d{d}-n{n}")
-    g = H.H2Matrix(P, kernel, prm, 1e-6, leaf, precision=32)
-    o = O.H2Oracle(P, kernel, prm, tol=1e-6, leaf=leaf)
+    g = H.H2Matrix(P, kernel, prm, 1e-6, leaf, precision=32, r1=r, r2=r)
+    o = O.H2Oracle(P, kernel, prm, tol=1e-6, leaf=leaf, r1=r, r2=r)
     assert g.info()["precision"] == 32
-    for name in ("perm", "il_col", "near_col", "rank"):
+    for name in ("perm", "il_col", "near_col", "rank", "rank_v"):
         assert np.array_equal(g.export(name), o.get(name)), name
     y = g.matvec(x.astype(np.float32)).cpu().numpy().astype(np.float64)
     yo = o.matvec(x)
@@ -338,19 +370,20 @@ def test_rebuild_reuses_representor_sets(H):
     n = 3000
     P = rng.random((n, 3))
     x = rng.standard_normal((2, n))
-    _say("rebuild: gaussian 0.1 -> exponential 0.2 -> gaussian 0.3")
+    _say("rebuild: gaussian 0.1 -> exponential 0.2 -> advection 1.0 -> gaussian 0.3")
     g = H.H2Matrix(P, "gaussian", 0.1, 1e-6, 64)
     r1, r2 = g.info()["r1"], g.info()["r2"]
     xs0 = [g.export("xstar", i) for i in range(len(g.export("parent")))]
-    for kern, prm, tol in (("exponential", 0.2, 1e-7), ("gaussian", 0.3, 1e-5)):
+    for kern, prm, tol in (("exponential", 0.2, 1e-7), ("advection", 1.0, 1e-6), ("gaussian", 0.3, 1e-5)):
         H.h2_rebuild(g.handle, kern, prm, tol)
         f = H.H2Matrix(P, kern, prm, tol, 64, r1=r1, r2=r2)
-        for name in ("perm", "il_col", "near_col", "rank", "mbar"):
+        assert g.info()["nonsymmetric"] == (kern == "advection")
+        for name in ("perm", "il_col", "near_col", "rank", "mbar", "rank_v", "mbar_v"):
             a, b = g.export(name), f.export(name)
             assert a.shape == b.shape and np.array_equal(a, b), name
         for i in range(len(f.export("parent"))):
             assert np.array_equal(g.export("xstar", i), xs0[i])
-            for name in ("piv", "skel", "T", "ystar"):
+            for name in ("piv", "skel", "T", "ystar", "piv_v", "skel_v", "T_v"):
                 a, b = g.export(name, i), f.export(name, i)
                 assert a.shape == b.shape and np.array_equal(a, b), (kern, name, i)
         yg = g.matvec(x).cpu().numpy()
