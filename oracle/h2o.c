@@ -217,6 +217,161 @@ int h2o_datareduct(int d, const double *pts, const int *list, int L, int k, int 
 }
 
 /* ------------------------------------------------------------------ */
+/* the other DataReduct methods of Section 3.3                         */
+/* ------------------------------------------------------------------ */
+enum { DR_VOLUME = 0, DR_FPS = 1, DR_SURFACE = 2 };
+
+/* Farthest point sampling: S starts with one point (silent which: the first
+ * of X in list order) and grows by the point of X farthest from S (largest
+ * squared distance to its nearest member, ties to the earliest position)
+ * until |S| = k, or until that largest distance is 0 (every point of X then
+ * coincides with a member of S).  |X| <= k: X unchanged.  S is written in
+ * selection order; returns |S|. */
+int h2o_datareduct_fps(int d, const double *pts, const int *list, int L, int k, int *out)
+{
+    if (L <= k) {
+        for (int p = 0; p < L; ++p)
+            out[p] = list[p];
+        return L;
+    }
+    double *md = (double *)malloc(sizeof(double) * (size_t)L);
+    for (int p = 0; p < L; ++p)
+        md[p] = INFINITY;
+    int cur = 0, cnt = 0;
+    for (;;) {
+        out[cnt++] = list[cur];
+        if (cnt == k) break;
+        const double *c = pts + (size_t)list[cur] * d;
+        int best = 0;
+        double bd = -1.0;
+        for (int p = 0; p < L; ++p) {
+            double dd = 0.0;
+            for (int a = 0; a < d; ++a) {
+                double e = pts[(size_t)list[p] * d + a] - c[a];
+                dd = dd + e * e;
+            }
+            if (dd < md[p]) md[p] = dd;
+            if (md[p] > bd) {
+                bd = md[p];
+                best = p;
+            }
+        }
+        if (!(bd > 0.0)) break;
+        cur = best;
+    }
+    free(md);
+    return cnt;
+}
+
+/* Unit direction j of m on the reference surfaces of the surface method
+ * (silent how the points are spread): 3-D the golden-angle spiral,
+ * z = 1 - (2j+1)/m, rho = sqrt(1 - z^2), phi = j pi (3 - sqrt 5),
+ * u = (rho cos phi, rho sin phi, z); 2-D the angles 2 pi (j + 1/2) / m;
+ * 1-D -1 then +1. */
+#define H2O_PI 3.14159265358979323846
+static void surface_dir(int d, int j, int m, double *u)
+{
+    if (d == 1) {
+        u[0] = j == 0 ? -1.0 : 1.0;
+    } else if (d == 2) {
+        double th = 2.0 * H2O_PI * ((double)j + 0.5) / (double)m;
+        u[0] = cos(th);
+        u[1] = sin(th);
+    } else {
+        double z = 1.0 - (double)(2 * j + 1) / (double)m;
+        double rho = sqrt(1.0 - z * z);
+        double phi = (double)j * (H2O_PI * (3.0 - sqrt(5.0)));
+        u[0] = rho * cos(phi);
+        u[1] = rho * sin(phi);
+        u[2] = z;
+    }
+}
+
+/* Surface-based DataReduct: the reference set is, for every non-empty
+ * segment (as in the volume method) with bounding box [lo, hi], widths
+ * w = hi - lo and centre c = lo + 0.5 w, points on the three ellipsoids
+ * centred at c with semi-axes gamma w, gamma = 0.3, 0.6, 1.2 (the values of
+ * Section 5.2): q = c + (gamma w) u_j for the m = max(1, floor(k/3))
+ * directions u_j of surface_dir (1-D: at most 2), in the order gamma, then j,
+ * the first k of them.  Nearest point, tie rule and output as in the volume
+ * method. */
+int h2o_datareduct_surface(int d, const double *pts, const int *list, int L, const int *seg, int nseg, int k,
+                           int *out)
+{
+    if (L <= k) {
+        for (int p = 0; p < L; ++p)
+            out[p] = list[p];
+        return L;
+    }
+    static const double gam[3] = {0.3, 0.6, 1.2};
+    int m = k / 3 > 1 ? k / 3 : 1;
+    if (d == 1 && m > 2) m = 2;
+    int nq1 = 3 * m < k ? 3 * m : k;
+    int *pick = (int *)malloc(sizeof(int) * (size_t)nq1 * (size_t)nseg);
+    int nq = 0;
+    for (int sg = 0; sg < nseg; ++sg) {
+        int b0 = seg[sg], b1 = seg[sg + 1];
+        if (b1 <= b0) continue;
+        double lo[3], hi[3];
+        for (int a = 0; a < d; ++a) {
+            lo[a] = pts[(size_t)list[b0] * d + a];
+            hi[a] = lo[a];
+        }
+        for (int p = b0 + 1; p < b1; ++p)
+            for (int a = 0; a < d; ++a) {
+                double v = pts[(size_t)list[p] * d + a];
+                if (v < lo[a]) lo[a] = v;
+                if (v > hi[a]) hi[a] = v;
+            }
+        for (int t = 0; t < nq1; ++t) {
+            double u[3], q[3];
+            surface_dir(d, t % m, m, u);
+            for (int a = 0; a < d; ++a) {
+                double w = hi[a] - lo[a];
+                double c = lo[a] + 0.5 * w;
+                q[a] = c + (gam[t / m] * w) * u[a];
+            }
+            int best = 0;
+            double bd = INFINITY;
+            for (int p = 0; p < L; ++p) {
+                double dd = 0.0;
+                for (int a = 0; a < d; ++a) {
+                    double e = q[a] - pts[(size_t)list[p] * d + a];
+                    dd = dd + e * e;
+                }
+                if (dd < bd) {
+                    bd = dd;
+                    best = p;
+                }
+            }
+            pick[nq++] = best;
+        }
+    }
+    int cnt = 0;
+    for (int t = 0; t < nq; ++t) {
+        int dup = 0;
+        for (int u = 0; u < t; ++u)
+            if (pick[u] == pick[t]) {
+                dup = 1;
+                break;
+            }
+        if (!dup) out[cnt++] = list[pick[t]];
+    }
+    free(pick);
+    return cnt;
+}
+
+/* DataReduct by method (0 volume, 1 FPS, 2 surface) of a list in segments;
+ * FPS takes the list whole. */
+int h2o_datareduct_method(int method, int d, const double *pts, const int *list, int L, const int *seg,
+                          int nseg, int k, int *out)
+{
+    if (method == DR_FPS) return h2o_datareduct_fps(d, pts, list, L, k, out);
+    if (method == DR_SURFACE) return h2o_datareduct_surface(d, pts, list, L, seg, nseg, k, out);
+    return h2o_datareduct_seg(d, pts, list, L, seg, nseg, k, out);
+}
+
+/* ------------------------------------------------------------------ */
 /* getBasis: interpolative decomposition by column-pivoted QR          */
 /* (Section 4.1, Eqs. SRRQR1-2)                                        */
 /* ------------------------------------------------------------------ */
@@ -397,6 +552,7 @@ typedef struct h2o {
     int *il_ptr, *il_col, *nr_ptr, *nr_col;
     /* HiDR */
     int r1, r2;
+    int dr; /* DataReduct method: 0 volume, 1 FPS, 2 surface */
     ilist *xs, *ys; /* X_i^*, Y_i^* as tree positions */
     /* bases: bu = U, R (row side); bv = V, W (column side), built only for a
      * non-symmetric kernel (otherwise V = U) */
@@ -669,7 +825,8 @@ static void run_hidr(h2o *h)
                         il_push(&S, h->xs[c].v[t]);
             }
             int *out = (int *)malloc(sizeof(int) * (size_t)(S.n > 0 ? S.n : 1));
-            int cnt = h2o_datareduct(h->d, h->P, S.v, S.n, h->r1, out);
+            int seg1[2] = {0, S.n};
+            int cnt = h2o_datareduct_method(h->dr, h->d, h->P, S.v, S.n, seg1, 1, h->r1, out);
             ilist X = {0};
             for (int t = 0; t < cnt; ++t)
                 il_push(&X, out[t]);
@@ -694,7 +851,7 @@ static void run_hidr(h2o *h)
             if (Tl.n > 0) {
                 int *out = (int *)malloc(sizeof(int) * (size_t)Tl.n);
                 int seg[3] = {0, h->ys[p].n, Tl.n};
-                int cnt = h2o_datareduct_seg(h->d, h->P, Tl.v, Tl.n, seg, 2, h->r2, out);
+                int cnt = h2o_datareduct_method(h->dr, h->d, h->P, Tl.v, Tl.n, seg, 2, h->r2, out);
                 for (int t = 0; t < cnt; ++t)
                     il_push(&Y, out[t]);
                 free(out);
@@ -918,10 +1075,13 @@ void h2o_free(h2o *h);
 
 /* Build the H^2 representation of K = [kappa(x_i, x_j)] for the points pts
  * ([n][d], row-major, original order).  r1/r2 <= 0 select calibration.
- * nthreads <= 0 keeps the OpenMP default.  Returns NULL on invalid input. */
-h2o *h2o_build(const double *pts, int n, int d, int kid, const double *prm, double tol, int q,
-               double tau, int r1, int r2, uint64_t seed, int nthreads)
+ * nthreads <= 0 keeps the OpenMP default.  dr selects the DataReduct method
+ * of HiDR (0 volume, 1 FPS, 2 surface); the calibration of r1, r2 uses the
+ * volume method whatever dr is.  Returns NULL on invalid input. */
+h2o *h2o_build_ex(const double *pts, int n, int d, int kid, const double *prm, double tol, int q,
+                  double tau, int r1, int r2, uint64_t seed, int nthreads, int dr)
 {
+    if (dr < 0 || dr > 2) return NULL;
     if (n < 1 || d < 1 || d > 3 || q < 1 || !(tol > 0.0 && tol < 1.0) || !(tau > 0.0 && tau < 1.0) ||
         kid < 0 || kid > 6)
         return NULL;
@@ -947,6 +1107,7 @@ h2o *h2o_build(const double *pts, int n, int d, int kid, const double *prm, doub
     h->q = q;
     h->r1 = r1;
     h->r2 = r2;
+    h->dr = dr;
     build_tree(h, pts);
     build_lists(h);
     calibrate(h, seed);
@@ -955,6 +1116,12 @@ h2o *h2o_build(const double *pts, int n, int d, int kid, const double *prm, doub
     build_bases(h, &h->bu, 0);
     if (h->nonsym) build_bases(h, &h->bv, 1);
     return h;
+}
+
+h2o *h2o_build(const double *pts, int n, int d, int kid, const double *prm, double tol, int q,
+               double tau, int r1, int r2, uint64_t seed, int nthreads)
+{
+    return h2o_build_ex(pts, n, d, kid, prm, tol, q, tau, r1, r2, seed, nthreads, DR_VOLUME);
 }
 
 /* Tree and lists only (for structural pins on inputs where HiDR is moot). */

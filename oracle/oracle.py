@@ -62,6 +62,11 @@ def lib():
         L.h2o_build.restype = C.c_void_p
         L.h2o_build.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp, C.c_double, C.c_int, C.c_double,
                                 C.c_int, C.c_int, C.c_uint64, C.c_int]
+        L.h2o_build_ex.restype = C.c_void_p
+        L.h2o_build_ex.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp, C.c_double, C.c_int, C.c_double,
+                                   C.c_int, C.c_int, C.c_uint64, C.c_int, C.c_int]
+        L.h2o_datareduct_method.restype = C.c_int
+        L.h2o_datareduct_method.argtypes = [C.c_int, C.c_int, dp, ip, C.c_int, ip, C.c_int, C.c_int, ip]
         L.h2o_build_tree_lists.restype = C.c_void_p
         L.h2o_build_tree_lists.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_double]
         L.h2o_free.argtypes = [C.c_void_p]
@@ -143,6 +148,21 @@ def datareduct_seg(pts, idx, seg, k) -> np.ndarray:
     return out[:cnt].copy()
 
 
+DATAREDUCT = {"volume": 0, "fps": 1, "surface": 2}
+
+
+def datareduct_method(method, pts, idx, k, seg=None) -> np.ndarray:
+    """DataReduct by method ("volume", "fps" or "surface"); seg as for
+    datareduct_seg (None: one segment)."""
+    pts = _f64(pts)
+    idx = _i32(idx)
+    seg = _i32([0, len(idx)] if seg is None else seg)
+    out = np.empty(max(1, len(idx)), dtype=np.int32)
+    cnt = lib().h2o_datareduct_method(DATAREDUCT[method], pts.shape[1], _d(pts), _i(idx), len(idx), _i(seg),
+                                      len(seg) - 1, int(k), _i(out))
+    return out[:cnt].copy()
+
+
 def cpqr_id(A, tol):
     """Interpolative decomposition of the rows of A (m x s).
 
@@ -203,7 +223,7 @@ class H2Oracle:
     """An oracle H^2 representation (Algorithm 2) built on the CPU."""
 
     def __init__(self, pts, kernel="coulomb", prm=1.0, tol=1e-6, leaf=64, tau=0.7, r1=0, r2=0,
-                 seed=0x5EED, nthreads=0, structure_only=False):
+                 seed=0x5EED, nthreads=0, structure_only=False, datareduct="volume"):
         pts = _f64(pts)
         self.n, self.d = pts.shape
         self.kid = kernel_id(kernel)
@@ -212,8 +232,8 @@ class H2Oracle:
         if structure_only:
             h = lib().h2o_build_tree_lists(_d(pts), self.n, self.d, leaf, tau)
         else:
-            h = lib().h2o_build(_d(pts), self.n, self.d, self.kid, _d(p), tol, leaf, tau, r1, r2,
-                                seed, nthreads)
+            h = lib().h2o_build_ex(_d(pts), self.n, self.d, self.kid, _d(p), tol, leaf, tau, r1, r2,
+                                   seed, nthreads, DATAREDUCT[datareduct])
         if not h:
             raise ValueError("oracle rejected the input")
         self._h = C.c_void_p(h)

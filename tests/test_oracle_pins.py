@@ -138,6 +138,81 @@ def test_nonsymmetric_bases():
     assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 1e-6
 
 
+def test_fps_greedy_and_covering():
+    """Farthest point sampling: the first pick is the first point; every
+    later pick is at the largest distance from the points picked before it
+    (scipy distances), the earliest such point on ties; no two picks are
+    closer than the covering radius the picks leave; on an evenly spaced
+    line from 0 the picks are 0, the far end, then the midpoint."""
+    rng = np.random.default_rng(21)
+    for d in (1, 2, 3):
+        X = rng.random((300, d))
+        idx = np.arange(300, dtype=np.int32)[::-1].copy()  # list order differs from index order
+        k = 40
+        S = O.datareduct_method("fps", X, idx, k)
+        assert len(S) == k and len(set(S.tolist())) == k and S[0] == idx[0]
+        pos = {int(v): p for p, v in enumerate(idx)}
+        for t in range(1, k):
+            dist = cdist(X[idx], X[S[:t]]).min(axis=1)
+            far = np.flatnonzero(dist == dist.max())
+            assert pos[int(S[t])] == far[0]
+        cover = cdist(X, X[S]).min(axis=1).max()
+        pair = cdist(X[S], X[S])
+        assert pair[~np.eye(k, dtype=bool)].min() >= cover
+    line = np.linspace(0.0, 1.0, 11)[:, None]
+    S = O.datareduct_method("fps", line, np.arange(11, dtype=np.int32), 3)
+    assert S.tolist() == [0, 10, 5]
+    same = np.zeros((20, 3))
+    assert O.datareduct_method("fps", same, np.arange(20, dtype=np.int32), 5).tolist() == [0]
+    assert O.datareduct_method("fps", X, idx[:30], 40).tolist() == idx[:30].tolist()
+
+
+def test_surface_reference_points():
+    """Surface-based DataReduct with k = 3 (one direction per ellipsoid): in
+    2-D the direction is (-1, 0), so on the grid over [-1, 1]^2 the reference
+    points (-0.6, 0), (-1.2, 0), (-2.4, 0) pick (-0.6, 0) and (-1, 0) (twice,
+    kept once); in 3-D the spiral's first direction (z = 0, phi = 0) is
+    (1, 0, 0): (0.6, 0, 0), (1.2, 0, 0), (2.4, 0, 0) pick (0.6, 0, 0) and the
+    face point (1, 0, 0).  On random points the outer ellipsoid's (gamma =
+    1.2) pick lies at the far side of the box; segments get reference sets
+    of their own."""
+    g = np.linspace(-1.0, 1.0, 11)
+    G2 = np.array([(a, b) for b in g for a in g])
+    S = O.datareduct_method("surface", G2, np.arange(len(G2), dtype=np.int32), 3)
+    np.testing.assert_allclose(G2[S], [[-0.6, 0.0], [-1.0, 0.0]], atol=1e-12)
+    G3 = np.array([(a, b, c) for c in g for b in g for a in g])
+    S = O.datareduct_method("surface", G3, np.arange(len(G3), dtype=np.int32), 3)
+    np.testing.assert_allclose(G3[S], [[0.6, 0.0, 0.0], [1.0, 0.0, 0.0]], atol=1e-12)
+    rng = np.random.default_rng(22)
+    X = rng.random((2000, 3))
+    idx = np.arange(2000, dtype=np.int32)
+    S = O.datareduct_method("surface", X, idx, 300)
+    assert 0 < len(S) <= 300 and len(set(S.tolist())) == len(S)
+    outer = O.datareduct_method("surface", X, idx, 3)[-1]  # gamma = 1.2 is the last reference point
+    assert X[outer, 0] >= np.quantile(X[:, 0], 0.99)
+    # two segments: reference points from each segment's box, picks from the whole list
+    Y = np.vstack([X[:1000] * 0.1, X[1000:] * 0.1 + 5.0])
+    S2 = O.datareduct_method("surface", Y, idx, 30, seg=[0, 1000, 2000])
+    assert np.any(S2 < 1000) and np.any(S2 >= 1000) and len(S2) <= 60
+
+
+@pytest.mark.parametrize("method", ["fps", "surface"])
+def test_hidr_variants_meet_tolerance(method):
+    """An H^2 build with the FPS or the surface DataReduct in HiDR meets the
+    tolerance against the dense product, as the volume method does; at
+    r >= n every method keeps every point and the product is exact."""
+    rng = np.random.default_rng(23)
+    n = 2500
+    P = rng.random((n, 3))
+    x = rng.standard_normal((2, n))
+    ref = x @ _dense(P, "coulomb", 1.0).T
+    h = O.H2Oracle(P, "coulomb", 1.0, tol=1e-6, leaf=32, r1=125, r2=125, datareduct=method)
+    assert np.linalg.norm(h.matvec(x) - ref) / np.linalg.norm(ref) < 1e-6
+    he = O.H2Oracle(P[:600], "exponential", 0.2, tol=1e-15, leaf=24, r1=600, r2=600, datareduct=method)
+    refe = x[:, :600] @ _dense(P[:600], "exponential", 0.2).T
+    assert np.linalg.norm(he.matvec(x[:, :600]) - refe) / np.linalg.norm(refe) < 1e-12
+
+
 def test_dense_rows_matches_library():
     rng = np.random.default_rng(1)
     P = rng.random((300, 3))
