@@ -87,7 +87,16 @@ typedef enum {
  *                  its stream, and the build around its launches of the
  *                  interpolative decompositions and of the top-down
  *                  DataReduct; h2_query then reports the last apply's and the
- *                  build's times                                            */
+ *                  build's times
+ *   datareduct     DataReduct method of HiDR (Section 3.3): H2_DR_VOLUME
+ *                  (default; the reference set is a tensor grid), H2_DR_FPS
+ *                  (farthest point sampling from the list's first point; a
+ *                  set gets at most r1 / r2 points) or H2_DR_SURFACE (the
+ *                  reference set lies on three ellipsoids around each part
+ *                  of the list, semi-axes 0.3, 0.6 and 1.2 times the part's
+ *                  bounding-box widths).  The choice of r1, r2 from the
+ *                  tolerance always uses the volume method.               */
+enum { H2_DR_VOLUME = 0, H2_DR_FPS = 1, H2_DR_SURFACE = 2 };
 typedef struct {
     double tau;
     int r1, r2;
@@ -96,6 +105,7 @@ typedef struct {
     uint64_t calib_seed;
     int profile;
     int r_min;
+    int datareduct;
 } h2_options;
 
 void h2_options_default(h2_options *opt);

@@ -69,6 +69,8 @@ h2_status check_and_init(h2::Handle& h, const double* points, int64_t n, int dim
         return set_err(H2_EINVAL, "r1, r2 must be in [0, 2048]");
     if (opt.precision != 64 && opt.precision != 32) return set_err(H2_EINVAL, "precision must be 64 or 32");
     if (opt.r_min < 0 || opt.r_min > 2048) return set_err(H2_EINVAL, "r_min must be in [0, 2048]");
+    if (opt.datareduct < H2_DR_VOLUME || opt.datareduct > H2_DR_SURFACE)
+        return set_err(H2_EINVAL, "unknown DataReduct method");
     if (opt.store_coupling != 1) return set_err(H2_EUNSUPPORTED, "only stored coupling blocks are implemented");
     if ((kernel_id == H2_COSINE || kernel_id == H2_ADVECTION) && (opt.r1 == 0 || opt.r2 == 0))
         return set_err(H2_EINVAL, "the cosine and advection kernels need options.r1 and options.r2 (no calibration)");
@@ -94,6 +96,7 @@ h2_status check_and_init(h2::Handle& h, const double* points, int64_t n, int dim
     h.calib_seed = opt.calib_seed;
     h.profile = opt.profile;
     h.r_min = opt.r_min;
+    h.dr = opt.datareduct;
     h.stream = s;
     return H2_OK;
 }
@@ -155,6 +158,7 @@ void h2_options_default(h2_options* opt)
     opt->calib_seed = 0x5EED;
     opt->profile = 0;
     opt->r_min = 0;
+    opt->datareduct = H2_DR_VOLUME;
 }
 
 const char* h2_last_error(void) { return g_last_error.c_str(); }

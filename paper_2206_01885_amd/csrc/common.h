@@ -157,6 +157,7 @@ struct Handle {
     double tau = 0.7;
     int q = 64;
     int r1 = 0, r2 = 0, r_min = 0;
+    int dr = H2_DR_VOLUME;  // DataReduct method of HiDR
     int precision = 64;
     int store_coupling = 1;
     uint64_t calib_seed = 0x5EED;
@@ -262,6 +263,12 @@ void matvec(Handle& h, const void* x, void* y, int nrhs, hipStream_t s);  // mat
 // reference set then holds one grid per non-empty part.
 void datareduct_lists(const double* pts, int64_t ld, int d, const int64_t* list_off, const int* list_idx,
                       const int* split, int nlist, int k, int* out, int out_stride, int* out_cnt, hipStream_t s);
+// The same with the DataReduct method of Section 3.3 (H2_DR_*): the volume
+// method as above, farthest point sampling (split ignored: the list is taken
+// whole) or the surface method (one reference set per part).
+void datareduct_lists_method(int method, const double* pts, int64_t ld, int d, const int64_t* list_off,
+                             const int* list_idx, const int* split, int nlist, int k, int* out, int out_stride,
+                             int* out_cnt, hipStream_t s);
 
 // Batched ID (basis.hip): one problem per entry.  Problem p has rows X
 // (m_p indices into pts) and columns Y (s_p indices into pts2); the kernel

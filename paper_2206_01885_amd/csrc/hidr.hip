@@ -1,5 +1,6 @@
 // Hierarchical data reduction (HiDR, Section 3.1 / Algorithm 1) with the
-// volume-based DataReduct of Section 3.3, on the device.
+// volume-based DataReduct of Section 3.3, on the device; the surface-based
+// method and farthest point sampling of the same section as options.
 //
 // DataReduct(X, k) reading (identical to the oracle's):
 //   |X| <= k            -> X unchanged;
@@ -27,6 +28,8 @@
 //
 // Compiled with -ffp-contract=off: distances round exactly as in the oracle,
 // so the picks are bit-identical.
+#include <cmath>
+
 #include "common.h"
 
 namespace h2 {
@@ -60,12 +63,18 @@ __device__ inline double block_max(double v, double* sh)
     return r;
 }
 
+// The surface method (method = H2_DR_SURFACE) differs only in its reference
+// set: per part, with box [lo, hi], widths w = hi - lo and centre
+// c = lo + 0.5 w, the points c + (gamma w) u_j on the ellipsoids gamma = 0.3,
+// 0.6, 1.2 for the mdir unit directions u_j of `dirs` ([mdir][d]), in the
+// order gamma, then j, the first k of them.
 template <int MAXQ>
 __global__ __launch_bounds__(TB) void k_datareduct(const double* __restrict__ pts, int64_t ld, int d,
                                                    const int64_t* __restrict__ list_off,
                                                    const int* __restrict__ list_idx,
                                                    const int* __restrict__ split, int k, int* __restrict__ out,
-                                                   int out_stride, int* __restrict__ out_cnt)
+                                                   int out_stride, int* __restrict__ out_cnt, int method,
+                                                   const double* __restrict__ dirs, int mdir)
 {
     __shared__ double sx[3][TB];
     __shared__ double red[TB];
@@ -109,6 +118,7 @@ __global__ __launch_bounds__(TB) void k_datareduct(const double* __restrict__ pt
             lo[sg][a] = block_min(mn, red);
             hi[sg][a] = block_max(mx, red);
         }
+    const bool surf = method == H2_DR_SURFACE;
     int g = 1;
     for (;;) {
         long long nx = 1;
@@ -118,6 +128,7 @@ __global__ __launch_bounds__(TB) void k_datareduct(const double* __restrict__ pt
     }
     int nq1 = 1;
     for (int a = 0; a < d; ++a) nq1 *= g;
+    if (surf) nq1 = min(k, 3 * mdir);
     const int nq = nq1 * nseg;
 
     // grid points owned by this lane: t = threadIdx.x + u*TB, in reference-set
@@ -133,11 +144,21 @@ __global__ __launch_bounds__(TB) void k_datareduct(const double* __restrict__ pt
         int sg = t / nq1;
         if (sg > nseg - 1) sg = nseg - 1;
         int rem = t - sg * nq1;
-        for (int a = 0; a < d; ++a) {
-            int ta = rem % g;
-            rem /= g;
-            double w = (double)(2 * ta + 1) / (double)(2 * g);
-            qx[u][a] = lo[sg][a] + (hi[sg][a] - lo[sg][a]) * w;
+        if (surf) {
+            const int e = rem / mdir, j = rem % mdir;
+            const double gm = e == 0 ? 0.3 : (e == 1 ? 0.6 : 1.2);
+            for (int a = 0; a < d; ++a) {
+                const double w = hi[sg][a] - lo[sg][a];
+                const double c = lo[sg][a] + 0.5 * w;
+                qx[u][a] = c + (gm * w) * dirs[j * d + a];
+            }
+        } else {
+            for (int a = 0; a < d; ++a) {
+                int ta = rem % g;
+                rem /= g;
+                double w = (double)(2 * ta + 1) / (double)(2 * g);
+                qx[u][a] = lo[sg][a] + (hi[sg][a] - lo[sg][a]) * w;
+            }
         }
     }
     const int nown = (nq - (int)threadIdx.x + TB - 1) / TB;  // reference points of this lane
@@ -241,6 +262,101 @@ __global__ __launch_bounds__(TB) void k_datareduct(const double* __restrict__ pt
     if (threadIdx.x == TB - 1) out_cnt[l] = scan_sh[TB - 1];
 }
 
+
+// Coordinates of the list entries in list order, SoA [d][tot].
+__global__ __launch_bounds__(TB) void k_list_coords(const double* __restrict__ pts, int64_t ld, int d,
+                                                    const int* __restrict__ list_idx, int64_t tot,
+                                                    double* __restrict__ cw)
+{
+    const int64_t p = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (p >= tot) return;
+    const int id = list_idx[p];
+    for (int a = 0; a < d; ++a) cw[a * tot + p] = pts[a * ld + id];
+}
+
+// Farthest point sampling of a list, one workgroup per list: S = {first
+// point}; then repeatedly every lane lowers the squared distance to S of its
+// points (md, in list order, distances in coordinate order as the oracle
+// forms them) by the last pick and the workgroup takes the largest, the
+// earliest position among equal ones, until |S| = k or the largest is 0.
+// |X| <= k: X unchanged.  The picks are written in selection order.
+__global__ __launch_bounds__(TB) void k_datareduct_fps(const double* __restrict__ cw, int64_t tot, int d,
+                                                       const int64_t* __restrict__ list_off,
+                                                       const int* __restrict__ list_idx, int k,
+                                                       int* __restrict__ out, int out_stride,
+                                                       int* __restrict__ out_cnt, double* __restrict__ md_ws)
+{
+    __shared__ double rv[TB];
+    __shared__ int rp[TB];
+    const int l = blockIdx.x;
+    const int64_t b0 = list_off[l];
+    const int L = (int)(list_off[l + 1] - b0);
+    const int* lst = list_idx + b0;
+    int* o = out + (int64_t)l * out_stride;
+    const int tid = threadIdx.x;
+    if (L <= k) {
+        for (int p = tid; p < L; p += TB) o[p] = lst[p];
+        if (tid == 0) out_cnt[l] = L;
+        return;
+    }
+    const double* x0 = cw + b0;
+    const double* x1 = cw + tot + b0;
+    const double* x2 = cw + 2 * tot + b0;
+    double* md = md_ws + b0;  // each entry read and written by its own lane only
+    for (int p = tid; p < L; p += TB) md[p] = INFINITY;
+    int cur = 0, cnt = 0;
+    for (;;) {
+        if (tid == 0) o[cnt] = lst[cur];
+        ++cnt;
+        if (cnt == k) break;
+        const double c0 = x0[cur];
+        const double c1 = d > 1 ? x1[cur] : 0.0;
+        const double c2 = d > 2 ? x2[cur] : 0.0;
+        double bv = -1.0;
+        int bp = 0x7fffffff;
+        for (int p = tid; p < L; p += TB) {
+            const double e0 = x0[p] - c0;
+            double dd = e0 * e0;
+            if (d > 1) {
+                const double e1 = x1[p] - c1;
+                dd = dd + e1 * e1;
+            }
+            if (d > 2) {
+                const double e2 = x2[p] - c2;
+                dd = dd + e2 * e2;
+            }
+            double mv = md[p];
+            if (dd < mv) {
+                mv = dd;
+                md[p] = mv;
+            }
+            if (mv > bv) {  // strict: a lane's earliest position among equal values
+                bv = mv;
+                bp = p;
+            }
+        }
+        rv[tid] = bv;
+        rp[tid] = bp;
+        __syncthreads();
+        for (int off = TB / 2; off > 0; off >>= 1) {
+            if (tid < off) {
+                const double v2 = rv[tid + off];
+                const int p2 = rp[tid + off];
+                if (v2 > rv[tid] || (v2 == rv[tid] && p2 < rp[tid])) {
+                    rv[tid] = v2;
+                    rp[tid] = p2;
+                }
+            }
+            __syncthreads();
+        }
+        const double best = rv[0];
+        const int bpos = rp[0];
+        __syncthreads();
+        if (!(best > 0.0)) break;
+        cur = bpos;
+    }
+    if (tid == 0) out_cnt[l] = cnt;
+}
 
 // Top-down DataReduct of T_i = Y_p^* ++ X_j^* (j in IL(i) ascending) without
 // materialising T_i.  Same reference set, distances, tie rule and output as
@@ -750,14 +866,75 @@ __global__ __launch_bounds__(TB) void k_xs_coords(const double* __restrict__ pts
 void datareduct_lists(const double* pts, int64_t ld, int d, const int64_t* list_off, const int* list_idx,
                       const int* split, int nlist, int k, int* out, int out_stride, int* out_cnt, hipStream_t s)
 {
+    datareduct_lists_method(H2_DR_VOLUME, pts, ld, d, list_off, list_idx, split, nlist, k, out, out_stride, out_cnt,
+                            s);
+}
+
+// Unit direction j of m on the reference surfaces of the surface method
+// (3-D: the golden-angle spiral z = 1 - (2j+1)/m, rho = sqrt(1 - z^2),
+// phi = j pi (3 - sqrt 5); 2-D: the angles 2 pi (j + 1/2) / m; 1-D: -1, +1).
+static void surface_dirs(int d, int m, std::vector<double>& u)
+{
+    const double pi = 3.14159265358979323846;
+    u.assign((size_t)m * d, 0.0);
+    for (int j = 0; j < m; ++j) {
+        double* v = u.data() + (size_t)j * d;
+        if (d == 1) {
+            v[0] = j == 0 ? -1.0 : 1.0;
+        } else if (d == 2) {
+            const double th = 2.0 * pi * ((double)j + 0.5) / (double)m;
+            v[0] = std::cos(th);
+            v[1] = std::sin(th);
+        } else {
+            const double z = 1.0 - (double)(2 * j + 1) / (double)m;
+            const double rho = std::sqrt(1.0 - z * z);
+            const double phi = (double)j * (pi * (3.0 - std::sqrt(5.0)));
+            v[0] = rho * std::cos(phi);
+            v[1] = rho * std::sin(phi);
+            v[2] = z;
+        }
+    }
+}
+
+void datareduct_lists_method(int method, const double* pts, int64_t ld, int d, const int64_t* list_off,
+                             const int* list_idx, const int* split, int nlist, int k, int* out, int out_stride,
+                             int* out_cnt, hipStream_t s)
+{
     if (nlist <= 0) return;
     if (k < 1 || k > MAXQ_ALL / 2) fail(H2_EUNSUPPORTED, "DataReduct size must be in [1, 2048]");
+    if (method == H2_DR_FPS) {
+        const int64_t tot = read_scalar(list_off + nlist, s);
+        if (tot > (int64_t)INT32_MAX) fail(H2_EUNSUPPORTED, "lists longer than 2^31 entries");
+        DBuf<double> md, cw;
+        md.ensure((size_t)std::max<int64_t>(tot, 1), s);
+        cw.ensure((size_t)std::max<int64_t>(tot, 1) * d, s);
+        if (tot > 0) {
+            k_list_coords<<<blocks_for(tot, TB), TB, 0, s>>>(pts, ld, d, list_idx, tot, cw.p);
+            H2_LAUNCH_CHECK();
+        }
+        k_datareduct_fps<<<nlist, TB, 0, s>>>(cw.p, tot, d, list_off, list_idx, k, out, out_stride, out_cnt, md.p);
+        H2_LAUNCH_CHECK();
+        H2_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    DBuf<double> dirs;
+    int mdir = 0;
+    if (method == H2_DR_SURFACE) {
+        mdir = std::max(1, k / 3);
+        if (d == 1) mdir = std::min(mdir, 2);
+        std::vector<double> u;
+        surface_dirs(d, mdir, u);
+        dirs.ensure(u.size(), s);
+        H2_HIP(hipMemcpyAsync(dirs.p, u.data(), u.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    }
     if (k <= 512)
-        k_datareduct<1024><<<nlist, TB, 0, s>>>(pts, ld, d, list_off, list_idx, split, k, out, out_stride, out_cnt);
+        k_datareduct<1024><<<nlist, TB, 0, s>>>(pts, ld, d, list_off, list_idx, split, k, out, out_stride, out_cnt,
+                                                method, dirs.p, mdir);
     else
-        k_datareduct<MAXQ_ALL>
-            <<<nlist, TB, 0, s>>>(pts, ld, d, list_off, list_idx, split, k, out, out_stride, out_cnt);
+        k_datareduct<MAXQ_ALL><<<nlist, TB, 0, s>>>(pts, ld, d, list_off, list_idx, split, k, out, out_stride,
+                                                    out_cnt, method, dirs.p, mdir);
     H2_LAUNCH_CHECK();
+    if (method == H2_DR_SURFACE) H2_HIP(hipStreamSynchronize(s));  // the direction table's lifetime
 }
 
 void run_hidr(Handle& h)
@@ -786,8 +963,8 @@ void run_hidr(Handle& h)
         k_up_fill<<<nl, TB, 0, s>>>(lo, h.nchild.p, h.first_child.p, h.start.p, h.count.p, h.xs_cnt.p, h.xs_idx.p,
                                     h.r1, off.p, list.p);
         H2_LAUNCH_CHECK();
-        datareduct_lists(h.pts.p, h.n, h.d, off.p, list.p, nullptr, nl, h.r1, h.xs_idx.p + (int64_t)lo * h.r1,
-                         h.r1, h.xs_cnt.p + lo, s);
+        datareduct_lists_method(h.dr, h.pts.p, h.n, h.d, off.p, list.p, nullptr, nl, h.r1,
+                                h.xs_idx.p + (int64_t)lo * h.r1, h.r1, h.xs_cnt.p + lo, s);
     }
     if (h.r2 < 1 || h.r2 > MAXQ_ALL / 2) fail(H2_EUNSUPPORTED, "r2 must be in [1, 2048]");
     DBuf<double> xs_pts;
@@ -803,12 +980,14 @@ void run_hidr(Handle& h)
     for (int L = 1; L <= h.maxdepth; ++L) {
         int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
         if (h.profile) H2_HIP(hipEventRecord(ev[2 * L], s));
-        launch_down(h, lo, nl, xs_pts.p, s);
+        // the box-pruned kernel serves the volume method; the other methods
+        // reduce every node's materialised T_i
+        if (h.dr == H2_DR_VOLUME) launch_down(h, lo, nl, xs_pts.p, s);
         if (h.profile) H2_HIP(hipEventRecord(ev[2 * L + 1], s));
         H2_LAUNCH_CHECK();
         std::vector<int> longn;
         for (int i = lo; i < lo + nl; ++i)
-            if (h.h_il_ptr[i + 1] - h.h_il_ptr[i] > ILCAP) longn.push_back(i);
+            if (h.dr != H2_DR_VOLUME || h.h_il_ptr[i + 1] - h.h_il_ptr[i] > ILCAP) longn.push_back(i);
         if (longn.empty()) continue;
         const int nlong = (int)longn.size();
         lnodes.ensure((size_t)nlong, s);
@@ -827,7 +1006,8 @@ void run_hidr(Handle& h)
         H2_LAUNCH_CHECK();
         tmp.ensure((size_t)nlong * h.ys_stride, s);
         tmp_cnt.ensure((size_t)nlong, s);
-        datareduct_lists(h.pts.p, h.n, h.d, off.p, list.p, split.p, nlong, h.r2, tmp.p, h.ys_stride, tmp_cnt.p, s);
+        datareduct_lists_method(h.dr, h.pts.p, h.n, h.d, off.p, list.p, split.p, nlong, h.r2, tmp.p, h.ys_stride,
+                                tmp_cnt.p, s);
         k_rows_scatter<<<nlong, TB, 0, s>>>(lnodes.p, tmp_cnt.p, tmp.p, h.ys_stride, h.ys_cnt.p, h.ys_idx.p);
         H2_LAUNCH_CHECK();
     }

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libh2.so")
 
 H2_OK, H2_EINVAL, H2_ENOMEM, H2_EDEVICE, H2_EUNSUPPORTED, H2_EINTERNAL = 0, -1, -2, -3, -4, -5
+DATAREDUCT = {"volume": 0, "fps": 1, "surface": 2}
 KERNELS = {"coulomb": 0, "gaussian": 1, "exponential": 2, "matern32": 3, "bump": 4, "cosine": 5,
            "advection": 6}
 
@@ -41,7 +42,7 @@ class H2Error(RuntimeError):
 class h2_options(C.Structure):
     _fields_ = [("tau", C.c_double), ("r1", C.c_int), ("r2", C.c_int), ("precision", C.c_int),
                 ("store_coupling", C.c_int), ("calib_seed", C.c_uint64), ("profile", C.c_int),
-                ("r_min", C.c_int)]
+                ("r_min", C.c_int), ("datareduct", C.c_int)]
 
 
 class h2_info(C.Structure):
@@ -191,7 +192,7 @@ class H2Matrix:
     """Owning wrapper: builds on construction, applies with matvec()."""
 
     def __init__(self, points, kernel="coulomb", prm=1.0, tol=1e-6, leaf=64, tau=0.7, r1=0, r2=0,
-                 seed=0x5EED, stream=None, precision=64, r_min=0):
+                 seed=0x5EED, stream=None, precision=64, r_min=0, datareduct="volume"):
         pts = torch.as_tensor(points, dtype=torch.float64)
         if not pts.is_cuda:
             pts = pts.cuda()
@@ -202,6 +203,7 @@ class H2Matrix:
         opt = h2_options_default()
         opt.tau, opt.r1, opt.r2, opt.calib_seed = tau, r1, r2, seed
         opt.precision, opt.r_min = precision, r_min
+        opt.datareduct = DATAREDUCT[datareduct]
         self.dtype = torch.float32 if precision == 32 else torch.float64
         self.stream = stream
         self.handle = h2_build(soa, kernel, prm, tol, leaf, opt, stream)

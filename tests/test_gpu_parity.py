@@ -40,9 +40,9 @@ def H():
     return h2
 
 
-def _build(H, P, kernel, prm, tol, leaf, r=0, oracle=True):
-    g = H.H2Matrix(P, kernel, prm, tol, leaf, r1=r, r2=r)
-    o = O.H2Oracle(P, kernel, prm, tol=tol, leaf=leaf, r1=r, r2=r) if oracle else None
+def _build(H, P, kernel, prm, tol, leaf, r=0, oracle=True, datareduct="volume"):
+    g = H.H2Matrix(P, kernel, prm, tol, leaf, r1=r, r2=r, datareduct=datareduct)
+    o = O.H2Oracle(P, kernel, prm, tol=tol, leaf=leaf, r1=r, r2=r, datareduct=datareduct) if oracle else None
     return g, o
 
 
@@ -200,6 +200,27 @@ def test_nonsymmetric_advection_parity(H, d, prm, n, leaf, r):
     assert _rel(yg, o.matvec(x)) <= 1e-10
     ref = O.dense_rows(P, "advection", prm, x)
     assert max(_rel(yg[k], ref[k]) for k in range(2)) <= 1e-6
+
+
+@pytest.mark.parametrize("method,d,kernel,prm,n,leaf,r", [
+    ("fps", 3, "coulomb", 1.0, 3000, 32, 125), ("fps", 2, "gaussian", 0.1, 5000, 50, 0),
+    ("fps", 1, "exponential", 0.3, 2000, 16, 16), ("surface", 3, "coulomb", 1.0, 3000, 32, 125),
+    ("surface", 2, "gaussian", 0.1, 5000, 50, 0), ("surface", 1, "exponential", 0.3, 2000, 16, 16),
+    ("surface", 3, "matern32", 0.2, 2500, 40, 600),
+])
+def test_datareduct_variants_parity(H, method, d, kernel, prm, n, leaf, r):
+    """HiDR with farthest point sampling or the surface-based DataReduct
+    (Section 3.3): X*, Y* (hence the bases) identical to the oracle's with
+    the same method, the product within 1e-10 of the oracle's."""
+    rng = np.random.default_rng(700 + d)
+    P = rng.random((n, d)) ** 1.5
+    x = rng.standard_normal((2, n))
+    _say(f"datareduct {method} {kernel}-d{d}-n{n} r{r}")
+    g, o = _build(H, P, kernel, prm, 1e-6, leaf, r=r, datareduct=method)
+    _compare_structure(g, o)
+    _compare_reduction_and_bases(g, o)
+    yg = g.matvec(x).cpu().numpy()
+    assert _rel(yg, o.matvec(x)) <= 1e-10
 
 
 def test_exact_limit_against_dense(H):
