@@ -509,6 +509,54 @@ int h2o_cpqr_id(const double *A, int m, int s, double tol, int *piv, double *T, 
     return k;
 }
 
+/* Strong rank-revealing swaps (Eq. SRRQR1 asks for an interpolation matrix
+ * G = T^T bounded entrywise by a prescribed constant f > 1).  With the rank
+ * k of the pivoted QR kept, while the largest |T_tu| exceeds f (the first in
+ * row-major order among equal ones) skeleton t and non-skeleton u trade
+ * places: in the basis of the skeleton columns this is a Gauss-Jordan pivot
+ * on p = T_tu (Cramer: it multiplies the volume det R11 of the projected
+ * block by p, so the iteration ends), with
+ *   new row t:        T_tu' <- T_tu' / p (u' != u),   T_tu <- 1 / p
+ *   other rows l:     T_lu' <- T_lu' - T_lu (T_tu' / p),   T_lu <- -T_lu / p
+ * and piv[t] <-> piv[k + u].  At most 8k swaps (a guard against cycling on
+ * rounding).  Returns the number of swaps. */
+int h2o_srrqr_swaps(int k, int m, double f, int *piv, double *T)
+{
+    int nr = m - k, nsw = 0;
+    if (k <= 0 || nr <= 0) return 0;
+    double *c = (double *)malloc(sizeof(double) * (size_t)k);
+    while (nsw < 8 * k) {
+        int bt = 0, bu = 0;
+        double bv = -1.0;
+        for (int t = 0; t < k; ++t)
+            for (int u = 0; u < nr; ++u) {
+                double a = fabs(T[(size_t)t * nr + u]);
+                if (a > bv) {
+                    bv = a;
+                    bt = t;
+                    bu = u;
+                }
+            }
+        if (!(bv > f)) break;
+        double p = T[(size_t)bt * nr + bu];
+        for (int l = 0; l < k; ++l)
+            c[l] = T[(size_t)l * nr + bu];
+        for (int u = 0; u < nr; ++u)
+            T[(size_t)bt * nr + u] = u == bu ? 1.0 / p : T[(size_t)bt * nr + u] / p;
+        for (int l = 0; l < k; ++l) {
+            if (l == bt) continue;
+            for (int u = 0; u < nr; ++u)
+                T[(size_t)l * nr + u] = u == bu ? -c[l] / p : T[(size_t)l * nr + u] - c[l] * T[(size_t)bt * nr + u];
+        }
+        int x = piv[bt];
+        piv[bt] = piv[k + bu];
+        piv[k + bu] = x;
+        ++nsw;
+    }
+    free(c);
+    return nsw;
+}
+
 /* ------------------------------------------------------------------ */
 /* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014), counter form       */
 /* ------------------------------------------------------------------ */
@@ -553,6 +601,7 @@ typedef struct h2o {
     /* HiDR */
     int r1, r2;
     int dr; /* DataReduct method: 0 volume, 1 FPS, 2 surface */
+    double srrqr_f; /* > 0: strong rank-revealing swaps bounding |T| by it */
     ilist *xs, *ys; /* X_i^*, Y_i^* as tree positions */
     /* bases: bu = U, R (row side); bv = V, W (column side), built only for a
      * non-symmetric kernel (otherwise V = U) */
@@ -1039,6 +1088,7 @@ static void build_bases(h2o *h, basis *b, int side)
                 double *Tt = (double *)malloc(sizeof(double) * (size_t)(kk > 0 ? kk : 1) * (size_t)m);
                 double *rd = (double *)malloc(sizeof(double) * (size_t)(kk > 0 ? kk : 1));
                 k = h2o_cpqr_id(A, m, s, h->tol, piv, Tt, rd);
+                if (h->srrqr_f > 0.0) h2o_srrqr_swaps(k, m, h->srrqr_f, piv, Tt);
                 T = Tt;
                 free(rd);
                 free(A);
@@ -1077,11 +1127,14 @@ void h2o_free(h2o *h);
  * ([n][d], row-major, original order).  r1/r2 <= 0 select calibration.
  * nthreads <= 0 keeps the OpenMP default.  dr selects the DataReduct method
  * of HiDR (0 volume, 1 FPS, 2 surface); the calibration of r1, r2 uses the
- * volume method whatever dr is.  Returns NULL on invalid input. */
+ * volume method whatever dr is.  srrqr_f > 1 adds the strong rank-revealing
+ * swaps to every getBasis (0: column-pivoted QR alone).  Returns NULL on
+ * invalid input. */
 h2o *h2o_build_ex(const double *pts, int n, int d, int kid, const double *prm, double tol, int q,
-                  double tau, int r1, int r2, uint64_t seed, int nthreads, int dr)
+                  double tau, int r1, int r2, uint64_t seed, int nthreads, int dr, double srrqr_f)
 {
     if (dr < 0 || dr > 2) return NULL;
+    if (srrqr_f != 0.0 && !(srrqr_f > 1.0)) return NULL;
     if (n < 1 || d < 1 || d > 3 || q < 1 || !(tol > 0.0 && tol < 1.0) || !(tau > 0.0 && tau < 1.0) ||
         kid < 0 || kid > 6)
         return NULL;
@@ -1108,6 +1161,7 @@ h2o *h2o_build_ex(const double *pts, int n, int d, int kid, const double *prm, d
     h->r1 = r1;
     h->r2 = r2;
     h->dr = dr;
+    h->srrqr_f = srrqr_f;
     build_tree(h, pts);
     build_lists(h);
     calibrate(h, seed);
@@ -1121,7 +1175,7 @@ h2o *h2o_build_ex(const double *pts, int n, int d, int kid, const double *prm, d
 h2o *h2o_build(const double *pts, int n, int d, int kid, const double *prm, double tol, int q,
                double tau, int r1, int r2, uint64_t seed, int nthreads)
 {
-    return h2o_build_ex(pts, n, d, kid, prm, tol, q, tau, r1, r2, seed, nthreads, DR_VOLUME);
+    return h2o_build_ex(pts, n, d, kid, prm, tol, q, tau, r1, r2, seed, nthreads, DR_VOLUME, 0.0);
 }
 
 /* Tree and lists only (for structural pins on inputs where HiDR is moot). */

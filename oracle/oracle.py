@@ -64,7 +64,9 @@ def lib():
                                 C.c_int, C.c_int, C.c_uint64, C.c_int]
         L.h2o_build_ex.restype = C.c_void_p
         L.h2o_build_ex.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp, C.c_double, C.c_int, C.c_double,
-                                   C.c_int, C.c_int, C.c_uint64, C.c_int, C.c_int]
+                                   C.c_int, C.c_int, C.c_uint64, C.c_int, C.c_int, C.c_double]
+        L.h2o_srrqr_swaps.restype = C.c_int
+        L.h2o_srrqr_swaps.argtypes = [C.c_int, C.c_int, C.c_double, ip, dp]
         L.h2o_datareduct_method.restype = C.c_int
         L.h2o_datareduct_method.argtypes = [C.c_int, C.c_int, dp, ip, C.c_int, ip, C.c_int, C.c_int, ip]
         L.h2o_build_tree_lists.restype = C.c_void_p
@@ -163,6 +165,16 @@ def datareduct_method(method, pts, idx, k, seg=None) -> np.ndarray:
     return out[:cnt].copy()
 
 
+def srrqr_swaps(k, piv, T, f):
+    """Strong rank-revealing swaps on an ID (k, piv, T) of cpqr_id: returns
+    (number of swaps, piv, T) with max |T| <= f."""
+    piv = _i32(piv).copy()
+    m = len(piv)
+    T = _f64(T).reshape(k, m - k).copy()
+    n = lib().h2o_srrqr_swaps(int(k), m, float(f), _i(piv), _d(T))
+    return n, piv, T
+
+
 def cpqr_id(A, tol):
     """Interpolative decomposition of the rows of A (m x s).
 
@@ -223,7 +235,7 @@ class H2Oracle:
     """An oracle H^2 representation (Algorithm 2) built on the CPU."""
 
     def __init__(self, pts, kernel="coulomb", prm=1.0, tol=1e-6, leaf=64, tau=0.7, r1=0, r2=0,
-                 seed=0x5EED, nthreads=0, structure_only=False, datareduct="volume"):
+                 seed=0x5EED, nthreads=0, structure_only=False, datareduct="volume", srrqr_f=0.0):
         pts = _f64(pts)
         self.n, self.d = pts.shape
         self.kid = kernel_id(kernel)
@@ -233,7 +245,7 @@ class H2Oracle:
             h = lib().h2o_build_tree_lists(_d(pts), self.n, self.d, leaf, tau)
         else:
             h = lib().h2o_build_ex(_d(pts), self.n, self.d, self.kid, _d(p), tol, leaf, tau, r1, r2,
-                                   seed, nthreads, DATAREDUCT[datareduct])
+                                   seed, nthreads, DATAREDUCT[datareduct], float(srrqr_f))
         if not h:
             raise ValueError("oracle rejected the input")
         self._h = C.c_void_p(h)

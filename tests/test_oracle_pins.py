@@ -213,6 +213,53 @@ def test_hidr_variants_meet_tolerance(method):
     assert np.linalg.norm(he.matvec(x[:, :600]) - refe) / np.linalg.norm(refe) < 1e-12
 
 
+def test_srrqr_swaps_on_kahan_matrix():
+    """Kahan's matrix defeats column pivoting: all columns have norm 1, the
+    pivoted QR keeps the natural order and at rank n - 1 its interpolation
+    matrix has entries near (1 + c)^(n-2).  The strong rank-revealing swaps
+    bound max |T| by f, keep a permutation, and the interpolation residual
+    of the non-skeleton row falls by orders of magnitude (a larger skeleton
+    volume).  An ID whose |T| is already within f is left bit for bit."""
+    n, c = 30, 0.285
+    s = np.sqrt(1.0 - c * c)
+    K = np.diag(s ** np.arange(n)) @ (np.eye(n) - c * np.triu(np.ones((n, n)), 1))
+    np.testing.assert_allclose(np.linalg.norm(K, axis=0), 1.0, rtol=1e-14)
+    A = K.T.copy()
+    k, piv, T, _ = O.cpqr_id(A, 0.3)
+    assert k == n - 1 and np.array_equal(piv, np.arange(n)) and np.abs(T).max() > 300
+    res0 = np.linalg.norm(A[piv[k:]] - T.T @ A[piv[:k]])
+    nsw, piv2, T2 = O.srrqr_swaps(k, piv, T, 2.0)
+    assert nsw >= 1 and np.abs(T2).max() <= 2.0
+    assert np.array_equal(np.sort(piv2), np.arange(n))
+    res1 = np.linalg.norm(A[piv2[k:]] - T2.T @ A[piv2[:k]])
+    assert res1 < 1e-2 * res0
+    rng = np.random.default_rng(24)
+    X, Y = rng.random((40, 3)), rng.random((120, 3)) + [2.0, 0.0, 0.0]
+    k, piv, T, _ = O.cpqr_id(1.0 / cdist(X, Y), 1e-8)
+    assert np.abs(T).max() <= 2.0
+    nsw, piv2, T2 = O.srrqr_swaps(k, piv, T, 2.0)
+    assert nsw == 0 and np.array_equal(piv2, piv) and np.array_equal(T2, T)
+
+
+def test_srrqr_build_bounds_interpolation():
+    """An H^2 build with the swaps (f = 1.05, close to 1 so that they occur)
+    has every node's max |T| within f and meets the tolerance."""
+    rng = np.random.default_rng(25)
+    n = 2500
+    P = rng.random((n, 3))
+    x = rng.standard_normal((2, n))
+    h = O.H2Oracle(P, "exponential", 0.2, tol=1e-6, leaf=32, r1=216, r2=216, srrqr_f=1.05)
+    h0 = O.H2Oracle(P, "exponential", 0.2, tol=1e-6, leaf=32, r1=216, r2=216)
+    nn = h.info()["nnode"]
+    tmax = max((np.abs(h.node_T(i)).max() for i in range(1, nn) if h.node_T(i).size), default=0.0)
+    tmax0 = max((np.abs(h0.node_T(i)).max() for i in range(1, nn) if h0.node_T(i).size), default=0.0)
+    assert tmax <= 1.05 < tmax0
+    ref = x @ _dense(P, "exponential", 0.2).T
+    assert np.linalg.norm(h.matvec(x) - ref) / np.linalg.norm(ref) < 1e-6
+    with pytest.raises(ValueError):
+        O.H2Oracle(P[:100], "coulomb", 1.0, tol=1e-6, leaf=32, srrqr_f=0.5)
+
+
 def test_dense_rows_matches_library():
     rng = np.random.default_rng(1)
     P = rng.random((300, 3))
