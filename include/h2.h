@@ -95,7 +95,11 @@ typedef enum {
  *                  reference set lies on three ellipsoids around each part
  *                  of the list, semi-axes 0.3, 0.6 and 1.2 times the part's
  *                  bounding-box widths).  The choice of r1, r2 from the
- *                  tolerance always uses the volume method.               */
+ *                  tolerance always uses the volume method.
+ *   srrqr_f        0 (default): getBasis is the column-pivoted QR alone;
+ *                  f > 1 (and <= 1e6): strong rank-revealing swaps follow it,
+ *                  so that the interpolation matrix G of Eq. (SRRQR1) has
+ *                  max |G| <= f (the rank stays the pivoted QR's)         */
 enum { H2_DR_VOLUME = 0, H2_DR_FPS = 1, H2_DR_SURFACE = 2 };
 typedef struct {
     double tau;
@@ -106,6 +110,7 @@ typedef struct {
     int profile;
     int r_min;
     int datareduct;
+    double srrqr_f;
 } h2_options;
 
 void h2_options_default(h2_options *opt);

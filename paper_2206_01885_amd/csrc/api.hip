@@ -71,6 +71,8 @@ h2_status check_and_init(h2::Handle& h, const double* points, int64_t n, int dim
     if (opt.r_min < 0 || opt.r_min > 2048) return set_err(H2_EINVAL, "r_min must be in [0, 2048]");
     if (opt.datareduct < H2_DR_VOLUME || opt.datareduct > H2_DR_SURFACE)
         return set_err(H2_EINVAL, "unknown DataReduct method");
+    if (opt.srrqr_f != 0.0 && !(opt.srrqr_f > 1.0 && opt.srrqr_f <= 1e6))
+        return set_err(H2_EINVAL, "srrqr_f must be 0 or in (1, 1e6]");
     if (opt.store_coupling != 1) return set_err(H2_EUNSUPPORTED, "only stored coupling blocks are implemented");
     if ((kernel_id == H2_COSINE || kernel_id == H2_ADVECTION) && (opt.r1 == 0 || opt.r2 == 0))
         return set_err(H2_EINVAL, "the cosine and advection kernels need options.r1 and options.r2 (no calibration)");
@@ -97,6 +99,7 @@ h2_status check_and_init(h2::Handle& h, const double* points, int64_t n, int dim
     h.profile = opt.profile;
     h.r_min = opt.r_min;
     h.dr = opt.datareduct;
+    h.srrqr_f = opt.srrqr_f;
     h.stream = s;
     return H2_OK;
 }
@@ -159,6 +162,7 @@ void h2_options_default(h2_options* opt)
     opt->profile = 0;
     opt->r_min = 0;
     opt->datareduct = H2_DR_VOLUME;
+    opt->srrqr_f = 0.0;
 }
 
 const char* h2_last_error(void) { return g_last_error.c_str(); }

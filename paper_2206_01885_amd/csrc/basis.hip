@@ -836,6 +836,83 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
     if (threadIdx.x == 0) *tk.rank = k;
 }
 
+// Strong rank-revealing swaps after the ID of a task with srrqr_f = f > 1
+// (Eq. SRRQR1 bounds the interpolation matrix by a constant), one workgroup
+// per task, T (k x (m-k), row-major) in place: while the largest |T_tu|
+// (the first in row-major order among equal ones) exceeds f, skeleton t and
+// non-skeleton u trade places by a Gauss-Jordan pivot on p = T_tu:
+//   row t:       T_tu' <- T_tu' / p,   T_tu <- 1 / p
+//   rows l != t: T_lu' <- T_lu' - T_lu (T_tu' / p),   T_lu <- -T_lu / p
+// and piv[t] <-> piv[k + u]; at most 8k swaps.  The skeleton is rewritten
+// from the final pivots.  Dynamic LDS: the pivot column (k doubles).
+__global__ __launch_bounds__(TB) void k_srrqr(const IdTask* __restrict__ tasks, int ntask)
+{
+    extern __shared__ double cbuf[];
+    __shared__ double rv[TB];
+    __shared__ int ri[TB];
+    if ((int)blockIdx.x >= ntask) return;
+    const IdTask& tk = tasks[blockIdx.x];
+    const double f = tk.srrqr_f;
+    const int m = tk.m;
+    const int k = *tk.rank;
+    const int nr = m - k;
+    const int tid = threadIdx.x;
+    if (!(f > 1.0) || k <= 0 || nr <= 0) return;
+    gdouble* T = (gdouble*)tk.T;
+    int* piv = tk.piv;
+    const int ne = k * nr;
+    for (int nsw = 0; nsw < 8 * k; ++nsw) {
+        double bv = -1.0;
+        int bi = 0x7fffffff;
+        for (int e = tid; e < ne; e += TB) {
+            const double a = fabs(T[e]);
+            if (a > bv) {
+                bv = a;
+                bi = e;
+            }
+        }
+        rv[tid] = bv;
+        ri[tid] = bi;
+        __syncthreads();
+        for (int off = TB / 2; off > 0; off >>= 1) {
+            if (tid < off) {
+                const double v2 = rv[tid + off];
+                const int i2 = ri[tid + off];
+                if (v2 > rv[tid] || (v2 == rv[tid] && i2 < ri[tid])) {
+                    rv[tid] = v2;
+                    ri[tid] = i2;
+                }
+            }
+            __syncthreads();
+        }
+        const double best = rv[0];
+        const int bidx = ri[0];
+        __syncthreads();
+        if (!(best > f)) break;
+        const int bt = bidx / nr, bu = bidx - bt * nr;
+        const double p = T[bidx];
+        for (int l = tid; l < k; l += TB) cbuf[l] = T[(int64_t)l * nr + bu];
+        __syncthreads();
+        for (int u = tid; u < nr; u += TB) {
+            const int64_t e = (int64_t)bt * nr + u;
+            T[e] = u == bu ? 1.0 / p : T[e] / p;
+        }
+        __syncthreads();
+        for (int e = tid; e < ne; e += TB) {
+            const int l = e / nr, u = e - l * nr;
+            if (l == bt) continue;
+            T[e] = u == bu ? -cbuf[l] / p : T[e] - cbuf[l] * T[(int64_t)bt * nr + u];
+        }
+        if (tid == 0) {
+            const int x = piv[bt];
+            piv[bt] = piv[k + bu];
+            piv[k + bu] = x;
+        }
+        __syncthreads();
+    }
+    for (int t = tid; t < k; t += TB) tk.skel[t] = tk.x_idx[piv[t]];
+}
+
 // Row set of every node of a level: the leaf's points, or the children's
 // skeletons concatenated in child order.
 __global__ __launch_bounds__(TB) void k_xbar_fill(int lo, const int* __restrict__ nchild,
@@ -1236,6 +1313,7 @@ void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
     DBuf<int> d_xidx;
     DBuf<int64_t> d_xoff;
     DBuf<double> Mws, nuws;
+    DBuf<IdTask> d_sw;
     for (int t = 0; t < maxd; ++t) {
         // units and levels of this round; grow piv / T first (the task
         // pointers must see the final buffers)
@@ -1294,6 +1372,21 @@ void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
                 tasks[q].nu = nuws.p + nuoff[q];
             }
             batched_id(tasks, s, prof_on ? &prof : nullptr);
+            // strong rank-revealing swaps where a problem asks for them
+            std::vector<IdTask> sw;
+            size_t kmax = 1;
+            for (const IdTask& t : tasks)
+                if (t.srrqr_f > 1.0) {
+                    sw.push_back(t);
+                    kmax = std::max(kmax, (size_t)std::min(t.m, t.s));
+                }
+            if (!sw.empty()) {
+                d_sw.ensure(sw.size(), s);
+                H2_HIP(hipMemcpyAsync(d_sw.p, sw.data(), sw.size() * sizeof(IdTask), hipMemcpyHostToDevice, s));
+                k_srrqr<<<(unsigned)sw.size(), TB, kmax * sizeof(double), s>>>(d_sw.p, (int)sw.size());
+                H2_LAUNCH_CHECK();
+                H2_HIP(hipStreamSynchronize(s));  // sw (host) is read by the copy
+            }
             tasks.clear();
             Moff.clear();
             nuoff.clear();
@@ -1325,6 +1418,7 @@ void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
                 tk.d = h.d;
                 tk.kid = h.kid;
                 tk.swap = u.swap;
+                tk.srrqr_f = h.srrqr_f;
                 tasks.push_back(tk);
                 Moff.push_back(ws);
                 nuoff.push_back(no);

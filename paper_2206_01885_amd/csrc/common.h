@@ -158,6 +158,7 @@ struct Handle {
     int q = 64;
     int r1 = 0, r2 = 0, r_min = 0;
     int dr = H2_DR_VOLUME;  // DataReduct method of HiDR
+    double srrqr_f = 0.0;   // > 1: strong rank-revealing swaps after every ID
     int precision = 64;
     int store_coupling = 1;
     uint64_t calib_seed = 0x5EED;
@@ -289,6 +290,7 @@ struct IdTask {
     int* skel = nullptr;         // k entries (x indices)
     int* rank = nullptr;         // 1 entry
     double prm = 1.0, tol = 0.0;
+    double srrqr_f = 0.0;  // > 1: swaps bounding max |T| by it after the ID
     int m = 0, s = 0, d = 0, kid = 0;
     int swap = 0;    // 1: column side, entries kappa(y_r, x_c) instead of kappa(x_c, y_r)
     int folded = 0;  // set by batched_id: M holds the m x m R factor of the block

@@ -42,7 +42,7 @@ class H2Error(RuntimeError):
 class h2_options(C.Structure):
     _fields_ = [("tau", C.c_double), ("r1", C.c_int), ("r2", C.c_int), ("precision", C.c_int),
                 ("store_coupling", C.c_int), ("calib_seed", C.c_uint64), ("profile", C.c_int),
-                ("r_min", C.c_int), ("datareduct", C.c_int)]
+                ("r_min", C.c_int), ("datareduct", C.c_int), ("srrqr_f", C.c_double)]
 
 
 class h2_info(C.Structure):
@@ -192,7 +192,7 @@ class H2Matrix:
     """Owning wrapper: builds on construction, applies with matvec()."""
 
     def __init__(self, points, kernel="coulomb", prm=1.0, tol=1e-6, leaf=64, tau=0.7, r1=0, r2=0,
-                 seed=0x5EED, stream=None, precision=64, r_min=0, datareduct="volume"):
+                 seed=0x5EED, stream=None, precision=64, r_min=0, datareduct="volume", srrqr_f=0.0):
         pts = torch.as_tensor(points, dtype=torch.float64)
         if not pts.is_cuda:
             pts = pts.cuda()
@@ -204,6 +204,7 @@ class H2Matrix:
         opt.tau, opt.r1, opt.r2, opt.calib_seed = tau, r1, r2, seed
         opt.precision, opt.r_min = precision, r_min
         opt.datareduct = DATAREDUCT[datareduct]
+        opt.srrqr_f = srrqr_f
         self.dtype = torch.float32 if precision == 32 else torch.float64
         self.stream = stream
         self.handle = h2_build(soa, kernel, prm, tol, leaf, opt, stream)

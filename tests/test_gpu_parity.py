@@ -223,6 +223,34 @@ def test_datareduct_variants_parity(H, method, d, kernel, prm, n, leaf, r):
     assert _rel(yg, o.matvec(x)) <= 1e-10
 
 
+@pytest.mark.parametrize("d,kernel,prm,n,leaf,r", [(3, "exponential", 0.2, 2500, 32, 216),
+                                                   (2, "gaussian", 0.1, 5000, 50, 0),
+                                                   (3, "advection", 2.0, 3000, 32, 216)])
+def test_srrqr_swaps_parity(H, d, kernel, prm, n, leaf, r):
+    """getBasis with the strong rank-revealing swaps (f = 1.05, close to 1
+    so that they occur): ranks, pivots and skeletons of every basis equal the
+    oracle's, T to rounding, max |T| within f where the pivoted QR alone
+    exceeds it, and the product within 1e-10 of the oracle's."""
+    rng = np.random.default_rng(800 + d)
+    P = rng.random((n, d)) ** 1.5
+    x = rng.standard_normal((2, n))
+    f = 1.05
+    _say(f"srrqr f={f} {kernel}-d{d}-n{n} r{r}")
+    g = H.H2Matrix(P, kernel, prm, 1e-6, leaf, r1=r, r2=r, srrqr_f=f)
+    o = O.H2Oracle(P, kernel, prm, tol=1e-6, leaf=leaf, r1=r, r2=r, srrqr_f=f)
+    sides = (0, 1) if kernel == "advection" else (0,)
+    _compare_structure(g, o)
+    _compare_reduction_and_bases(g, o, sides=sides)
+    nn = g.info()["nnode"]
+    tmax = max(np.abs(g.export("T", i)).max() for i in range(1, nn) if g.export("T", i).size)
+    g0 = H.H2Matrix(P, kernel, prm, 1e-6, leaf, r1=r, r2=r)
+    tmax0 = max(np.abs(g0.export("T", i)).max() for i in range(1, nn) if g0.export("T", i).size)
+    _say(f"max |T| {tmax0:.3f} -> {tmax:.3f}")
+    assert tmax <= f < tmax0
+    yg = g.matvec(x).cpu().numpy()
+    assert _rel(yg, o.matvec(x)) <= 1e-10
+
+
 def test_exact_limit_against_dense(H):
     """r1 = r2 >= n and a rounding-level tolerance: the GPU H^2 product equals
     the dense product."""
