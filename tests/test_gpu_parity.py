@@ -385,6 +385,50 @@ def test_batched_build_equals_solo(H):
             H.h2_destroy(hb)
 
 
+def test_batched_kernel_families_equal_solo(H):
+    """One h2_build_batched over problems of all three kernel families (radial,
+    cosine, non-symmetric advection; given r1 = r2, the FPS DataReduct and the
+    swap pass) gives every problem exactly its solo build: both bases, B and
+    the product bit for bit."""
+    import torch
+    rng = np.random.default_rng(2025)
+    specs = [(3000, "coulomb", 1.0), (2500, "cosine", 1.0), (2800, "advection", 2.0), (2000, "bump", 0.1)]
+    pts = [rng.random((n, 3)) for n, _, _ in specs]
+    soa = [torch.tensor(P.T.copy(), device="cuda") for P in pts]
+    opt = H.h2_options_default()
+    opt.r1 = opt.r2 = 150
+    opt.datareduct = H.DATAREDUCT["fps"]
+    opt.srrqr_f = 1.2
+    _say("batched build over kernel families")
+    hs = H.h2_build_batched(soa, [s[1] for s in specs], [s[2] for s in specs], [1e-6] * len(specs),
+                            [48] * len(specs), opt)
+    try:
+        for (n, k, prm), P, hb in zip(specs, pts, hs):
+            _say(f"batched vs solo {k} n{n}")
+            g = H.H2Matrix(P, k, prm, 1e-6, 48, r1=150, r2=150, datareduct="fps", srrqr_f=1.2)
+            assert H.h2_query(hb)["nonsymmetric"] == (k == "advection")
+            for name in ("perm", "il_col", "near_col", "rank", "mbar", "rank_v", "mbar_v"):
+                a, b = H.h2_export(hb, name), g.export(name)
+                assert a.shape == b.shape and np.array_equal(a, b), name
+            for i in range(len(g.export("parent"))):
+                for name in ("piv", "skel", "T", "piv_v", "skel_v", "T_v", "ystar"):
+                    a, b = H.h2_export(hb, name, i), g.export(name, i)
+                    assert a.shape == b.shape and np.array_equal(a, b), (name, i)
+            nil = len(g.export("il_col"))
+            for e in range(0, nil, max(1, nil // 100)):
+                assert np.array_equal(H.h2_export(hb, "B", e), g.export("B", e)), ("B", e)
+            x = torch.tensor(rng.standard_normal((2, n)), device="cuda")
+            yb = torch.empty_like(x)
+            H.h2_matvec(hb, x, yb, 2)
+            yg = g.matvec(x)
+            torch.cuda.synchronize()
+            assert torch.equal(yb, yg)
+            g.close()
+    finally:
+        for hb in hs:
+            H.h2_destroy(hb)
+
+
 def test_serving_mix_equals_solo(H):
     """The serving loop (admission, batched builds of the requests that are
     waiting, applies overlapped on a second stream) returns for every
