@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--rows", type=int, default=512, help="sampled rows for the dense accuracy check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=1 << 17, help="points of the oracle's bounded sample")
-    ap.add_argument("--workload", choices=["cube1m", "batched", "serving", "sphere3"], default="cube1m",
+    ap.add_argument("--workload", choices=["cube1m", "batched", "serving", "sphere3", "variants"], default="cube1m",
                     help="cube1m: the headline n=2^20 Coulomb step; batched: 256 independent problems; "
                          "serving: Poisson request stream")
     ap.add_argument("--nreq", type=int, default=64, help="requests of the serving workload")
@@ -170,6 +170,10 @@ def dense_rows_gpu(P, X, rows, chunk=64, kernel="coulomb", prm=1.0):
             K = torch.exp(-1.0 / (1.0 - prm * D2))
         elif kernel == "cosine":
             K = torch.cos(prm * (Pr @ P.T))
+        elif kernel == "advection":
+            D = D2.sqrt()
+            d0 = Pr[:, None, 0] - P[None, :, 0]
+            K = torch.where(D > 0, torch.exp(prm * (d0 - D)) / D, torch.zeros_like(D))
         else:
             raise ValueError(kernel)
         out.append(K @ X.T)  # [chunk, nrhs]
@@ -233,6 +237,54 @@ def bench_sphere3(args):
         "kernels": res,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_variants(args):
+    """The options of the build on the headline cube (n = 2^20, leaf 128,
+    tol 1e-6, r_min 343, 32 RHS): the volume DataReduct (reference), farthest
+    point sampling, the surface method, the strong rank-revealing swaps
+    (f = 1.05) and the non-symmetric advection kernel (a = 2, r1 = r2 = 343).
+    Per option one untimed build, then build + one apply timed; accuracy on
+    sampled rows against the dense product."""
+    import torch
+    from paper_2206_01885_amd import h2
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    n, nrhs = args.n, args.nrhs
+    rng = np.random.default_rng(1004)
+    P = torch.tensor(rng.random((n, 3)), device=dev)
+    Psoa = P.t().contiguous()
+    X = torch.tensor(rng.standard_normal((nrhs, n)), device=dev)
+    Y = torch.empty_like(X)
+    rows = torch.tensor(np.sort(rng.choice(n, args.rows, replace=False)), device=dev)
+    cases = [("volume", "coulomb", 1.0, "volume", 0.0, 0), ("fps", "coulomb", 1.0, "fps", 0.0, 0),
+             ("surface", "coulomb", 1.0, "surface", 0.0, 0), ("srrqr1.05", "coulomb", 1.0, "volume", 1.05, 0),
+             ("advection2", "advection", 2.0, "volume", 0.0, 343)]
+    res = {}
+    for name, kern, prm, dr, f, r in cases:
+        opt = h2.h2_options_default()
+        opt.r_min = args.r_min
+        opt.r1 = opt.r2 = r
+        opt.datareduct = h2.DATAREDUCT[dr]
+        opt.srrqr_f = f
+        for k in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hd = h2.h2_build(Psoa, kern, prm, 1e-6, 128, opt)
+            tb = time.perf_counter()
+            h2.h2_matvec(hd, X, Y, nrhs)
+            torch.cuda.synchronize()
+            te = time.perf_counter()
+            info = h2.h2_query(hd)
+            h2.h2_destroy(hd)
+            print(f"[bench] variants {name} build {tb - t0:.3f} s matvec {te - tb:.4f} s", file=sys.stderr,
+                  flush=True)
+        ref = dense_rows_gpu(P, X, rows, kernel=kern, prm=prm)
+        e = ((Y[:, rows] - ref).norm(dim=1) / ref.norm(dim=1)).max().item()
+        res[name] = {"build_s": tb - t0, "matvec_s": te - tb, "t_hidr": info["t_hidr"], "t_basis": info["t_basis"],
+                     "t_blocks": info["t_blocks"], "r1": info["r1"], "max_rank": info["max_rank"],
+                     "max_rank_v": info["max_rank_v"], "e_dense_sampled_rows_max_rhs": e}
+    print(json.dumps({"workload": f"cube3d-n{n}-options-nrhs{nrhs}", "cases": res}), flush=True)
 
 
 def cpu_baseline(n, nrhs):
@@ -347,6 +399,9 @@ def main():
         return
     if args.workload == "sphere3":
         bench_sphere3(args)
+        return
+    if args.workload == "variants":
+        bench_variants(args)
         return
     import torch
     from paper_2206_01885_amd import h2
