@@ -506,3 +506,67 @@ def test_long_interaction_lists(H):
         assert np.array_equal(g.export("ystar", int(i)), o.node_list("ystar", int(i))), i
     x = np.random.default_rng(1).standard_normal(30000)
     assert _rel(g.matvec(x).cpu().numpy(), o.matvec(x)) <= 1e-10
+
+
+def test_full_size_cube_sampled_parity(H):
+    """The headline configuration in the benchmark's launch form (n = 2^20
+    uniform in [0,1]^3, Coulomb, leaf 128, tol 1e-6, r_min 343, 32 RHS):
+    tree and lists equal the oracle's in full; for sampled nodes of every
+    level, X_i^* and Y_i^* equal the oracle's DataReduct of the inputs HiDR
+    gives them, and rank, pivots and skeleton equal the oracle's pivoted QR
+    of K(Xbar_i, Y_i^*) (T to rounding); 512 sampled rows of the product
+    are within the tolerance of the oracle's dense rows."""
+    import torch
+    rng = np.random.default_rng(1004)
+    n, nrhs = 1 << 20, 32
+    P = rng.random((n, 3))
+    X = rng.standard_normal((nrhs, n))
+    rows = np.sort(rng.choice(n, 512, replace=False))
+    _say("full size: build n=2^20")
+    g = H.H2Matrix(P, "coulomb", 1.0, 1e-6, 128, r_min=343)
+    o = O.H2Oracle(P, structure_only=True, leaf=128)
+    for name in ("perm", "parent", "nchild", "first_child", "start", "count", "il_ptr", "il_col", "near_ptr",
+                 "near_col"):
+        assert np.array_equal(g.export(name), o.get(name)), name
+    info = g.info()
+    r1, r2 = info["r1"], info["r2"]
+    pts = g.export("points").reshape(3, -1).T
+    parent, nch, fc = g.export("parent"), g.export("nchild"), g.export("first_child")
+    start, count, rank = g.export("start"), g.export("count"), g.export("rank")
+    il_ptr, il_col = g.export("il_ptr"), g.export("il_col")
+    depth = g.export("depth")
+    pick = np.random.default_rng(5)
+    nodes = []
+    for L in range(1, int(depth.max()) + 1):
+        at = np.flatnonzero(depth == L)
+        nodes += pick.choice(at, min(4, len(at)), replace=False).tolist()
+    t_rtol = 10.0 * U_ROUND / 0.5e-6
+    for i in nodes:
+        kids = range(fc[i], fc[i] + nch[i]) if nch[i] else []
+        S = (np.arange(start[i], start[i] + count[i], dtype=np.int32) if not nch[i]
+             else np.concatenate([g.export("xstar", c) for c in kids]).astype(np.int32))
+        assert np.array_equal(g.export("xstar", i), O.datareduct(pts, S, r1)), ("xstar", i)
+        yp = g.export("ystar", parent[i]) if parent[i] > 0 else np.zeros(0, np.int32)
+        Ti = np.concatenate([yp] + [g.export("xstar", j) for j in il_col[il_ptr[i]:il_ptr[i + 1]]]).astype(np.int32)
+        ys = g.export("ystar", i)
+        if len(Ti):
+            assert np.array_equal(ys, O.datareduct_seg(pts, Ti, [0, len(yp), len(Ti)], r2)), ("ystar", i)
+        Xbar = (np.arange(start[i], start[i] + count[i]) if not nch[i]
+                else np.concatenate([g.export("skel", c) for c in kids]))
+        if len(Xbar) == 0 or len(ys) == 0:
+            continue
+        A = O.kernel_matrix("coulomb", 1.0, pts[Xbar], pts[ys])
+        k, piv, T, _ = O.cpqr_id(A, 0.5e-6)
+        assert k == rank[i], ("rank", i)
+        assert np.array_equal(g.export("piv", i), piv), ("piv", i)
+        assert np.array_equal(g.export("skel", i), Xbar[piv[:k]]), ("skel", i)
+        if T.size:
+            Tg = g.export("T", i).reshape(T.shape)
+            assert np.max(np.abs(Tg - T)) <= t_rtol * np.max(np.abs(T)), ("T", i)
+    _say(f"full size: {len(nodes)} sampled nodes agree; product rows")
+    y = g.matvec(X).cpu().numpy()
+    ref = O.dense_rows(P, "coulomb", 1.0, X[:4], rows=rows)
+    e = max(_rel(y[r, rows], ref[r]) for r in range(4))
+    _say(f"full size: max e_dense over 4 RHS on 512 rows {e:.3e}")
+    assert e <= 1e-6
+    g.close()
