@@ -570,3 +570,51 @@ def test_full_size_cube_sampled_parity(H):
     _say(f"full size: max e_dense over 4 RHS on 512 rows {e:.3e}")
     assert e <= 1e-6
     g.close()
+
+
+def test_batched_full_config_sampled(H):
+    """The batched configuration in full (256 problems, n log-uniform in
+    [2048, 32768], cube or sphere, three kernels) in one h2_build_batched, as
+    the benchmark launches it: three sampled problems equal their solo builds
+    bit for bit and the oracle's product within 1e-10; every problem's
+    product against 64 dense rows stays within a few times the tolerance
+    (r1, r2 come from the calibration, whose well-separated cube pair is
+    optimistic for deep trees: up to 3.6e-6 here, as 4.6e-6 for the 2^20
+    cube at the calibrated r)."""
+    import torch
+    probs = W.config_batched(nprob=256)
+    soa = [torch.tensor(p["points"].T.copy(), device="cuda") for p in probs]
+    _say("batched full configuration: 256 problems")
+    hs = H.h2_build_batched(soa, [p["kernel"] for p in probs], [p["prm"] for p in probs],
+                            [p["tol"] for p in probs], [p["leaf"] for p in probs])
+    try:
+        rng = np.random.default_rng(9)
+        for q in rng.choice(len(probs), 3, replace=False):
+            p, hb = probs[q], hs[q]
+            _say(f"batched full: problem {q} {p['name']}")
+            g = H.H2Matrix(p["points"], p["kernel"], p["prm"], p["tol"], p["leaf"])
+            for name in ("perm", "il_col", "near_col", "rank", "mbar"):
+                assert np.array_equal(H.h2_export(hb, name), g.export(name)), name
+            x = torch.tensor(p["x"], device="cuda")
+            yb = torch.empty_like(x)
+            H.h2_matvec(hb, x, yb, 1)
+            yg = g.matvec(x)
+            torch.cuda.synchronize()
+            assert torch.equal(yb, yg)
+            o = O.H2Oracle(p["points"], p["kernel"], p["prm"], tol=p["tol"], leaf=p["leaf"])
+            assert _rel(yb.cpu().numpy()[0], o.matvec(p["x"])[0]) <= 1e-10
+            g.close()
+        worst = 0.0
+        for p, hb in zip(probs, hs):
+            n = p["points"].shape[0]
+            x = torch.tensor(p["x"], device="cuda")
+            y = torch.empty_like(x)
+            H.h2_matvec(hb, x, y, 1)
+            rows = np.linspace(0, n - 1, 64).astype(np.int64)
+            ref = O.dense_rows(p["points"], p["kernel"], p["prm"], p["x"], rows=rows)
+            worst = max(worst, _rel(y.cpu().numpy()[0, rows], ref[0]))
+        _say(f"batched full: max e_dense over 256 problems (64 rows each) {worst:.3e}")
+        assert worst <= 1e-5
+    finally:
+        for hb in hs:
+            H.h2_destroy(hb)
