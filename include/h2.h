@@ -208,9 +208,10 @@ typedef struct {
      * this handle's decompositions (pivoted QR to the rank found and the
      * solve for T); 0 otherwise */
     double id_ms, id_wide_ms, id_flops, id_wide_flops;
-    /* build with options.profile = 1: HIP-event time (ms) of the top-down
-     * DataReduct launches of HiDR, and the bytes of the candidate coordinates
-     * they reduce (each farfield list T_i counted once); 0 otherwise */
+    /* build with options.profile = 1 and the volume DataReduct: HIP-event
+     * time (ms) of the box-pruned top-down DataReduct launches of HiDR, and
+     * the bytes of the candidate coordinates they reduce (each farfield list
+     * T_i counted once); 0 otherwise */
     double hidr_down_ms, hidr_down_bytes;
     /* column basis V, W: 1 when the kernel is not symmetric and V, W are
      * built apart from U, R (max_rank, sum_rank and bytes_U describe U, R;
@@ -218,6 +219,10 @@ typedef struct {
      * bytes_V = 0 there) */
     int nonsymmetric, max_rank_v;
     int64_t sum_rank_v, bytes_V;
+    /* with hidr_down_ms: the squared distances the definition of the
+     * top-down DataReduct evaluates (every reference point against every
+     * candidate of T_i); the box-pruned search evaluates fewer */
+    double hidr_down_evals;
 } h2_info;
 
 h2_status h2_query(h2_handle h, h2_info *info);

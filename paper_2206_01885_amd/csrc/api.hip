@@ -427,6 +427,7 @@ h2_status h2_query(h2_handle hd, h2_info* info)
     info->id_wide_flops = h.id_wide_flops;
     info->hidr_down_ms = h.hidr_down_ms;
     info->hidr_down_bytes = h.hidr_down_bytes;
+    info->hidr_down_evals = h.hidr_down_evals;
     return H2_OK;
 }
 

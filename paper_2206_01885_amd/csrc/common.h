@@ -237,7 +237,7 @@ struct Handle {
     double id_ms = 0, id_wide_ms = 0, id_flops = 0, id_wide_flops = 0;
     // top-down DataReduct launches (profile = 1): time (ms) and the bytes of
     // the candidate coordinates they reduce (each T_i read once)
-    double hidr_down_ms = 0, hidr_down_bytes = 0;
+    double hidr_down_ms = 0, hidr_down_bytes = 0, hidr_down_evals = 0;
 
     // scratch
     DBuf<int> tmp_i32;

@@ -831,20 +831,27 @@ void launch_down(Handle& h, int lo, int nl, const double* xs_pts, hipStream_t s)
 }
 
 // |T_i| for the nodes the top-down kernel reduces (interaction lists of at
-// most ILCAP entries; 0 for the others), for the profile.
+// most ILCAP entries; 0 for the others), and the squared distances the
+// definition of DataReduct evaluates for them (every reference point against
+// every candidate: |T_i| times gd points per non-empty part when |T_i| > k),
+// for the profile.
 __global__ __launch_bounds__(TB) void k_down_len(int nn, const int* __restrict__ parent, const int* __restrict__ il_ptr,
                                                  const int* __restrict__ il_col, const int* __restrict__ xs_cnt,
-                                                 const int* __restrict__ ys_cnt, int64_t* __restrict__ len)
+                                                 const int* __restrict__ ys_cnt, int k, int gd,
+                                                 int64_t* __restrict__ len, int64_t* __restrict__ evals)
 {
     const int i = blockIdx.x * TB + threadIdx.x;
     if (i >= nn) return;
     const int e0 = il_ptr[i], ne = il_ptr[i + 1] - e0;
-    int64_t l = 0;
+    int64_t l = 0, lp = 0;
     if (i > 0 && ne <= ILCAP) {
-        l = parent[i] > 0 ? ys_cnt[parent[i]] : 0;
+        lp = parent[i] > 0 ? ys_cnt[parent[i]] : 0;
+        l = lp;
         for (int e = 0; e < ne; ++e) l += xs_cnt[il_col[e0 + e]];
     }
     len[i] = l;
+    const int nseg = (lp > 0) + (l > lp);
+    evals[i] = l > k ? l * nseg * gd : 0;
 }
 
 // Coordinates of every node's X_i^* in a contiguous copy,
@@ -1011,29 +1018,43 @@ void run_hidr(Handle& h)
         k_rows_scatter<<<nlong, TB, 0, s>>>(lnodes.p, tmp_cnt.p, tmp.p, h.ys_stride, h.ys_cnt.p, h.ys_idx.p);
         H2_LAUNCH_CHECK();
     }
-    if (h.profile) {
+    h.hidr_down_ms = h.hidr_down_bytes = h.hidr_down_evals = 0;
+    if (h.profile && h.dr == H2_DR_VOLUME) {
         // candidate bytes of the nodes the top-down kernel reduced:
         // |T_i| = |Y_p^*| + sum over IL(i) of |X_j^*| coordinates of d doubles
-        DBuf<int64_t> len;
+        int g = 1;
+        for (;;) {
+            long long nx = 1;
+            for (int a = 0; a < h.d; ++a) nx *= g + 1;
+            if (nx > h.r2) break;
+            ++g;
+        }
+        int gd = 1;
+        for (int a = 0; a < h.d; ++a) gd *= g;
+        DBuf<int64_t> len, ev_n;
         len.ensure((size_t)nn, s);
+        ev_n.ensure((size_t)nn, s);
         k_down_len<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.parent.p, h.il_ptr.p, h.il_col.p, h.xs_cnt.p, h.ys_cnt.p,
-                                                     len.p);
+                                                     h.r2, gd, len.p, ev_n.p);
         H2_LAUNCH_CHECK();
-        std::vector<int64_t> hl((size_t)nn);
+        std::vector<int64_t> hl((size_t)nn), he((size_t)nn);
         H2_HIP(hipMemcpyAsync(hl.data(), len.p, sizeof(int64_t) * nn, hipMemcpyDeviceToHost, s));
+        H2_HIP(hipMemcpyAsync(he.data(), ev_n.p, sizeof(int64_t) * nn, hipMemcpyDeviceToHost, s));
         H2_HIP(hipStreamSynchronize(s));
-        double tot = 0;
+        double tot = 0, tev = 0;
         for (int64_t v : hl) tot += (double)v;
+        for (int64_t v : he) tev += (double)v;
         h.hidr_down_bytes = tot * h.d * sizeof(double);
+        h.hidr_down_evals = tev;
         h.hidr_down_ms = 0;
         for (int L = 1; L <= h.maxdepth; ++L) {
             float ms = 0.f;
             H2_HIP(hipEventElapsedTime(&ms, ev[2 * L], ev[2 * L + 1]));
             h.hidr_down_ms += ms;
         }
-        for (auto& e : ev) H2_HIP(hipEventDestroy(e));
     }
     H2_HIP(hipStreamSynchronize(s));
+    for (auto& e : ev) H2_HIP(hipEventDestroy(e));
 }
 
 }  // namespace h2

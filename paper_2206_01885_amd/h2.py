@@ -58,7 +58,7 @@ class h2_info(C.Structure):
                 ("id_wide_ms", C.c_double), ("id_flops", C.c_double), ("id_wide_flops", C.c_double),
                 ("hidr_down_ms", C.c_double), ("hidr_down_bytes", C.c_double),
                 ("nonsymmetric", C.c_int), ("max_rank_v", C.c_int), ("sum_rank_v", C.c_int64),
-                ("bytes_V", C.c_int64)]
+                ("bytes_V", C.c_int64), ("hidr_down_evals", C.c_double)]
 
 
 SYMBOLS = ["h2_options_default", "h2_build", "h2_build_ex", "h2_build_batched", "h2_rebuild", "h2_matvec",
