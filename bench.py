@@ -513,6 +513,40 @@ def main():
     Y64 = Ysave
     del Y
 
+    # coupling blocks evaluated by the apply (store_coupling = 0): no B in
+    # memory, same representation otherwise
+    otf = None
+    if not args.no_f32:
+        opt0 = h2.h2_options_default()
+        opt0.r1 = opt0.r2 = args.r
+        opt0.r_min = args.r_min
+        opt0.store_coupling = 0
+        opt0.profile = 1
+        Y0 = torch.empty_like(X)
+        b0, m0 = [], []
+        for k in range(1 + args.steps):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            hd0 = h2.h2_build(Psoa, "coulomb", 1.0, 1e-6, 128, opt0)
+            tb = time.perf_counter()
+            h2.h2_matvec(hd0, X, Y0, nrhs)
+            torch.cuda.synchronize()
+            te = time.perf_counter()
+            if k > 0:
+                b0.append(tb - ts)
+                m0.append(te - tb)
+            i0 = h2.h2_query(hd0)
+            h2.h2_destroy(hd0)
+            print(f"[bench] store_coupling 0 step {k}: build {tb - ts:.3f} s matvec {te - tb:.4f} s",
+                  file=sys.stderr, flush=True)
+        e0 = ((Y0[:, ridx] - ref).norm(dim=1) / ref.norm(dim=1)).max().item()
+        e0_64 = ((Y0[:, ridx] - Y64).norm(dim=1) / Y64.norm(dim=1)).max().item()
+        otf = {"ms_per_step": 1e3 * (float(np.mean(b0)) + float(np.mean(m0))), "build_s": float(np.mean(b0)),
+               "matvec_s": float(np.mean(m0)), "mpts_per_s": n / (float(np.mean(b0)) + float(np.mean(m0))) / 1e6,
+               "mv_coupling_ms": i0["mv_coupling"], "bytes_B": i0["bytes_B"], "bytes_D": i0["bytes_D"],
+               "e_dense_sampled_rows_max_rhs": e0, "e_vs_stored_path_max_rhs": e0_64}
+        del Y0
+
     # precision mode: FP32 blocks and apply (compensated nearfield), same build otherwise
     f32 = None
     if not args.no_f32:
@@ -574,6 +608,7 @@ def main():
         "accuracy": {"e_dense_sampled_rows_max_rhs": e_rows, "e_dense_sampled_rows_mean_rhs": e_rows_mean,
                      "rows": int(args.rows)},
         "precision_f32": f32,
+        "store_coupling_0": otf,
         "roofline": roof_dr,
         "roofline_id_wide": roof_id,
         "roofline_id_all_classes": roof_id_all,

@@ -81,7 +81,12 @@ typedef enum {
  *                  compensated accumulation of the block products, FP64
  *                  interpolation sums); the tree, HiDR and the interpolative
  *                  decompositions stay FP64
- *   store_coupling 1: store the coupling and nearfield blocks (default)
+ *   store_coupling 1: store the coupling and nearfield blocks (default);
+ *                  0: store the nearfield blocks only; h2_matvec evaluates
+ *                  each coupling block entry where it multiplies (no B in
+ *                  memory: about 180 GB less at n = 2^20, at the cost of the
+ *                  kernel evaluations in every apply); precision 64 only
+ *                  (H2_EUNSUPPORTED otherwise)
  *   calib_seed     seed of the random points used to choose r1, r2
  *   profile        1: h2_matvec records HIP events around each of its sweeps on
  *                  its stream, and the build around its launches of the

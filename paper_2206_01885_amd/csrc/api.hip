@@ -73,7 +73,9 @@ h2_status check_and_init(h2::Handle& h, const double* points, int64_t n, int dim
         return set_err(H2_EINVAL, "unknown DataReduct method");
     if (opt.srrqr_f != 0.0 && !(opt.srrqr_f > 1.0 && opt.srrqr_f <= 1e6))
         return set_err(H2_EINVAL, "srrqr_f must be 0 or in (1, 1e6]");
-    if (opt.store_coupling != 1) return set_err(H2_EUNSUPPORTED, "only stored coupling blocks are implemented");
+    if (opt.store_coupling != 0 && opt.store_coupling != 1) return set_err(H2_EINVAL, "store_coupling must be 0 or 1");
+    if (opt.store_coupling == 0 && opt.precision != 64)
+        return set_err(H2_EUNSUPPORTED, "coupling blocks evaluated in the apply need precision 64");
     if ((kernel_id == H2_COSINE || kernel_id == H2_ADVECTION) && (opt.r1 == 0 || opt.r2 == 0))
         return set_err(H2_EINVAL, "the cosine and advection kernels need options.r1 and options.r2 (no calibration)");
     double prm = 1.0;
@@ -499,6 +501,7 @@ h2_status h2_export(h2_handle hd, int what, int node, void* host_buf, size_t byt
         case H2_EXP_B: {
             if (node < 0 || node >= h.nil) return set_err(H2_EINVAL, "IL entry out of range");
             if (h.precision != 64) return set_err(H2_EUNSUPPORTED, "B export needs precision 64");
+            if (h.store_coupling == 0) return set_err(H2_EUNSUPPORTED, "coupling blocks are not stored");
             int64_t o[2];
             H2_HIP(hipMemcpy(o, h.B_off.p + node, 2 * sizeof(int64_t), hipMemcpyDeviceToHost));
             cnt = o[1] - o[0];

@@ -147,62 +147,14 @@ void launch_blocks_eval(int64_t nent, const int* erow, const int* col, const PtS
     H2_LAUNCH_CHECK();
 }
 
-}  // namespace
-
-void build_blocks(Handle& h)
+// Nearfield blocks D_ij = K(X_i, X_j) of every near-list entry; sz and
+// erow are scratch of at least nnear entries.
+void near_blocks(Handle& h, DBuf<int64_t>& sz, DBuf<int>& erow)
 {
     hipStream_t s = h.stream;
     const int nn = h.nnode;
-    h.B_off.ensure((size_t)h.nil + 1, s);
-    h.D_off.ensure((size_t)h.nnear + 1, s);
-    DBuf<int64_t> sz;
-    DBuf<int> erow;
-    const int64_t nmax = std::max<int64_t>(std::max(h.nil, h.nnear), 1);
-    sz.ensure((size_t)nmax, s);
-    erow.ensure((size_t)nmax, s);
-    // skeleton coordinates in node order: the row skeletons, and the column
-    // skeletons of a non-symmetric kernel
-    DBuf<int64_t> d_xo[2];
-    DBuf<double> skc[2];
-    auto skel_set = [&](const Basis& b, int w) -> PtSet {
-        std::vector<int64_t> xo((size_t)nn + 1, 0);
-        for (int i = 0; i < nn; ++i) xo[i + 1] = xo[i] + b.h_rank[i];
-        const int64_t sumk = std::max<int64_t>(xo[nn], 1);
-        d_xo[w].ensure(xo.size(), s);
-        H2_HIP(hipMemcpyAsync(d_xo[w].p, xo.data(), xo.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        skc[w].ensure((size_t)h.d * sumk, s);
-        k_skel_coords<<<nn, TB, 0, s>>>(nn, h.pts.p, h.n, h.d, b.rank.p, b.skel.p, h.ys_stride, d_xo[w].p, sumk,
-                                        skc[w].p);
-        H2_LAUNCH_CHECK();
-        return PtSet{skc[w].p, sumk, d_xo[w].p, b.rank.p};
-    };
-    const PtSet rs = skel_set(h.bu, 0);
-    const PtSet cs = h.nonsym ? skel_set(h.bv, 1) : rs;
-    // coupling
-    k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, h.il_col.p, h.bu.rank.p, h.col().rank.p, sz.p);
-    H2_LAUNCH_CHECK();
-    scan_excl_i64(sz.p, h.B_off.p, h.nil, h.tmp_i64, s);
-    int64_t nB = read_scalar(h.B_off.p + h.nil, s);
     const bool f32 = h.precision == 32;
-    // BLK_PAD zeros after the last block (read by row tiles of the apply
-    // that run past a block's last row)
-    if (f32) {
-        h.Bf.ensure((size_t)(nB + BLK_PAD), s);
-        H2_HIP(hipMemsetAsync(h.Bf.p + nB, 0, BLK_PAD * sizeof(float), s));
-    } else {
-        h.B.ensure((size_t)(nB + BLK_PAD), s);
-        H2_HIP(hipMemsetAsync(h.B.p + nB, 0, BLK_PAD * sizeof(double), s));
-    }
-    h.bytes_B = nB * (int64_t)(f32 ? sizeof(float) : sizeof(double));
-    if (h.nil > 0) {
-        k_entry_rows<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, erow.p);
-        H2_LAUNCH_CHECK();
-        if (f32)
-            launch_blocks_eval(h.nil, erow.p, h.il_col.p, rs, cs, h.d, h.kid, h.prm, h.B_off.p, h.Bf.p, s);
-        else
-            launch_blocks_eval(h.nil, erow.p, h.il_col.p, rs, cs, h.d, h.kid, h.prm, h.B_off.p, h.B.p, s);
-    }
-    // nearfield: the leaves' points are contiguous in tree order
+    // the leaves' points are contiguous in tree order
     k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.nr_ptr.p, h.nr_col.p, h.count.p, h.count.p, sz.p);
     H2_LAUNCH_CHECK();
     scan_excl_i64(sz.p, h.D_off.p, h.nnear, h.tmp_i64, s);
@@ -230,6 +182,84 @@ void build_blocks(Handle& h)
         H2_HIP(hipStreamSynchronize(s));
     }
     H2_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+void build_blocks(Handle& h)
+{
+    hipStream_t s = h.stream;
+    const int nn = h.nnode;
+    h.B_off.ensure((size_t)h.nil + 1, s);
+    h.D_off.ensure((size_t)h.nnear + 1, s);
+    DBuf<int64_t> sz;
+    DBuf<int> erow;
+    const int64_t nmax = std::max<int64_t>(std::max(h.nil, h.nnear), 1);
+    sz.ensure((size_t)nmax, s);
+    erow.ensure((size_t)nmax, s);
+    // skeleton coordinates in node order: the row skeletons, and the column
+    // skeletons of a non-symmetric kernel (kept in the handle when the apply
+    // evaluates the coupling blocks itself)
+    DBuf<int64_t> d_xo[2];
+    DBuf<double> skc_local[2];
+    DBuf<double>* skc[2] = {&skc_local[0], &skc_local[1]};
+    if (h.store_coupling == 0) {
+        skc[0] = &h.skc_u;
+        skc[1] = &h.skc_v;
+    }
+    int64_t skc_ld[2] = {1, 1};
+    auto skel_set = [&](const Basis& b, int w) -> PtSet {
+        std::vector<int64_t> xo((size_t)nn + 1, 0);
+        for (int i = 0; i < nn; ++i) xo[i + 1] = xo[i] + b.h_rank[i];
+        const int64_t sumk = std::max<int64_t>(xo[nn], 1);
+        d_xo[w].ensure(xo.size(), s);
+        H2_HIP(hipMemcpyAsync(d_xo[w].p, xo.data(), xo.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        skc[w]->ensure((size_t)h.d * sumk, s);
+        k_skel_coords<<<nn, TB, 0, s>>>(nn, h.pts.p, h.n, h.d, b.rank.p, b.skel.p, h.ys_stride, d_xo[w].p, sumk,
+                                        skc[w]->p);
+        H2_LAUNCH_CHECK();
+        H2_HIP(hipStreamSynchronize(s));  // xo (host) is read by the copy
+        skc_ld[w] = sumk;
+        return PtSet{skc[w]->p, sumk, d_xo[w].p, b.rank.p};
+    };
+    const PtSet rs = skel_set(h.bu, 0);
+    const PtSet cs = h.nonsym ? skel_set(h.bv, 1) : rs;
+    h.skc_ld_u = skc_ld[0];
+    h.skc_ld_v = h.nonsym ? skc_ld[1] : skc_ld[0];
+    if (h.store_coupling == 0) {
+        // the coupling blocks are evaluated by the apply; only the nearfield
+        // blocks are stored
+        h.B.release();
+        h.Bf.release();
+        h.bytes_B = 0;
+        near_blocks(h, sz, erow);
+        return;
+    }
+    // coupling
+    k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, h.il_col.p, h.bu.rank.p, h.col().rank.p, sz.p);
+    H2_LAUNCH_CHECK();
+    scan_excl_i64(sz.p, h.B_off.p, h.nil, h.tmp_i64, s);
+    int64_t nB = read_scalar(h.B_off.p + h.nil, s);
+    const bool f32 = h.precision == 32;
+    // BLK_PAD zeros after the last block (read by row tiles of the apply
+    // that run past a block's last row)
+    if (f32) {
+        h.Bf.ensure((size_t)(nB + BLK_PAD), s);
+        H2_HIP(hipMemsetAsync(h.Bf.p + nB, 0, BLK_PAD * sizeof(float), s));
+    } else {
+        h.B.ensure((size_t)(nB + BLK_PAD), s);
+        H2_HIP(hipMemsetAsync(h.B.p + nB, 0, BLK_PAD * sizeof(double), s));
+    }
+    h.bytes_B = nB * (int64_t)(f32 ? sizeof(float) : sizeof(double));
+    if (h.nil > 0) {
+        k_entry_rows<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, erow.p);
+        H2_LAUNCH_CHECK();
+        if (f32)
+            launch_blocks_eval(h.nil, erow.p, h.il_col.p, rs, cs, h.d, h.kid, h.prm, h.B_off.p, h.Bf.p, s);
+        else
+            launch_blocks_eval(h.nil, erow.p, h.il_col.p, rs, cs, h.d, h.kid, h.prm, h.B_off.p, h.B.p, s);
+    }
+    near_blocks(h, sz, erow);
 }
 
 }  // namespace h2

@@ -199,6 +199,13 @@ struct Handle {
     DBuf<int64_t> D_off;  // per near entry, size nnear+1
     DBuf<double> D;
     DBuf<float> Bf, Df;  // precision mode: FP32 blocks
+    // skeleton coordinates (SoA [d][skc_ld], node offsets = the bases'
+    // xh_off) and the apply's tasks (node, first row) when the apply
+    // evaluates the coupling blocks itself (store_coupling = 0)
+    DBuf<double> skc_u, skc_v;
+    int64_t skc_ld_u = 1, skc_ld_v = 1;
+    DBuf<int> otf_node, otf_r0;
+    int n_otf = 0;
     DBuf<int> leaves;    // leaf node ids
 
     // apply task lists: (node, first row) of every 32-row chunk of a block

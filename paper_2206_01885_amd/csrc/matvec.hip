@@ -21,6 +21,7 @@
 //   scatter   y[perm] = y_t
 // Every output element has exactly one writer; there are no atomics.
 #include "common.h"
+#include "kappa.h"
 
 namespace h2 {
 namespace {
@@ -268,6 +269,94 @@ __global__ __launch_bounds__(64) void k_sweep(int ntask, const int* __restrict__
     }
 }
 
+// Coupling sweep without stored blocks (store_coupling = 0, FP64):
+// yhat_i = sum_{j in IL(i)} K(Xhat_i^(row), Xhat_j^(col)) xhat_j with every
+// block entry evaluated where it is used.  One wavefront per (node, 64-row
+// chunk): lane t holds skeleton point t of node i and 32 accumulators (one
+// 32-column slice of the right-hand sides at a time); the partner's
+// skeleton points and xhat rows are staged in LDS 32 columns at a time and
+// read as broadcasts (faster here than scalar-register operands read through
+// the scalar cache).  Entries are summed in list order, columns ascending.
+template <int FAM>
+__global__ __launch_bounds__(64) void k_coupling_otf(int ntask, const int* __restrict__ task_node,
+                                                     const int* __restrict__ task_r0, const int* __restrict__ ptr,
+                                                     const int* __restrict__ col, const int* __restrict__ krow,
+                                                     const int* __restrict__ kcol, const double* __restrict__ sr,
+                                                     int64_t ldr, const int64_t* __restrict__ offr,
+                                                     const double* __restrict__ sc, int64_t ldc,
+                                                     const int64_t* __restrict__ offc, int d, int kid, double prm,
+                                                     const double* __restrict__ X, double* __restrict__ Y, int ld)
+{
+    constexpr int UC = 32;
+    __shared__ double sy[3][UC];
+    __shared__ double sx[UC * 32];
+    const int per = (ntask + 7) / 8;
+    const int task = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (task >= ntask) return;
+    const int i = task_node[task], r0 = task_r0[task];
+    const int ki = krow[i];
+    const int lane = threadIdx.x;
+    const int t = r0 + lane;
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+    if (t < ki) {
+        x0 = sr[offr[i] + t];
+        if (d > 1) x1 = sr[ldr + offr[i] + t];
+        if (d > 2) x2 = sr[2 * ldr + offr[i] + t];
+    }
+    const int e0 = ptr[i], e1 = ptr[i + 1];
+    for (int c = 0; c < ld; c += 32) {
+        double acc[32];
+#pragma unroll
+        for (int r = 0; r < 32; ++r) acc[r] = 0.0;
+        for (int e = e0; e < e1; ++e) {
+            const int j = col[e];
+            const int kj = kcol[j];
+            const int64_t oj = offc[j];
+            for (int u0 = 0; u0 < kj; u0 += UC) {
+                const int uc = min(UC, kj - u0);
+                __syncthreads();  // the previous pass has read the slices
+                if (lane < uc) {
+                    sy[0][lane] = sc[oj + u0 + lane];
+                    if (d > 1) sy[1][lane] = sc[ldc + oj + u0 + lane];
+                    if (d > 2) sy[2][lane] = sc[2 * ldc + oj + u0 + lane];
+                }
+                for (int q = lane; q < uc * 32; q += 64) sx[q] = X[(oj + u0 + (q >> 5)) * (int64_t)ld + c + (q & 31)];
+                __syncthreads();
+                for (int u = 0; u < uc; ++u) {
+                    const double s0 = sy[0][u];
+                    const double s1 = d > 1 ? sy[1][u] : 0.0;
+                    const double s2 = d > 2 ? sy[2][u] : 0.0;
+                    double r2 = 0.0, xy = 0.0;
+                    if constexpr (FAM == FAM_COSINE) {
+                        xy = x0 * s0;
+                        if (d > 1) xy += x1 * s1;
+                        if (d > 2) xy += x2 * s2;
+                    } else {
+                        const double a0 = s0 - x0;
+                        r2 = a0 * a0;
+                        if (d > 1) {
+                            const double a1 = s1 - x1;
+                            r2 += a1 * a1;
+                        }
+                        if (d > 2) {
+                            const double a2 = s2 - x2;
+                            r2 += a2 * a2;
+                        }
+                    }
+                    const double kv = kappa_store<double, FAM>(kid, prm, r2, xy, x0 - s0);
+#pragma unroll
+                    for (int r = 0; r < 32; ++r) acc[r] += kv * sx[u * 32 + r];
+                }
+            }
+        }
+        if (t < ki) {
+            double* yr = Y + (offr[i] + t) * (int64_t)ld + c;
+#pragma unroll
+            for (int r = 0; r < 32; ++r) yr[r] = acc[r];
+        }
+    }
+}
+
 // Per-entry metadata of a list (columns, first input row) and per-node
 // step counts of the sweep (an entry without columns takes one step).
 __global__ __launch_bounds__(TB) void k_sweep_meta(int nrow, const int* __restrict__ ptr, const int* __restrict__ col,
@@ -448,8 +537,31 @@ void matvec_t(Handle& h, const T* x, T* y, int nrhs, hipStream_t s)
     // the precision mode adds each block product (one interaction) to the
     // row sums with compensation: FP32 recursion over the ~10^4 terms of an
     // interaction list would lose about sqrt(10^4) ulps
-    launch_sweep<T, sizeof(T) == 4>(h.cp, h.il_ptr.p, h.bu.rank.p, h.B_off.p, AB::B(h), xh, h.bu.xh_off.p, yh, ld, 0,
-                                    zero, s);
+    if (h.store_coupling == 0) {
+        if constexpr (std::is_same_v<T, double>) {
+            const Basis& bu = h.bu;
+            const unsigned grid = (unsigned)(8 * ((h.n_otf + 7) / 8));
+            auto go = [&](auto fam) {
+                constexpr int F = decltype(fam)::value;
+                if (h.n_otf > 0)
+                    k_coupling_otf<F><<<grid, 64, 0, s>>>(h.n_otf, h.otf_node.p, h.otf_r0.p, h.il_ptr.p, h.il_col.p,
+                                                          bu.rank.p, bv.rank.p, h.skc_u.p, h.skc_ld_u, bu.xh_off.p,
+                                                          h.nonsym ? h.skc_v.p : h.skc_u.p, h.skc_ld_v, bv.xh_off.p,
+                                                          h.d, h.kid, h.prm, xh, yh, ld);
+            };
+            switch (kernel_family(h.kid)) {
+            case FAM_COSINE: go(std::integral_constant<int, FAM_COSINE>()); break;
+            case FAM_ADVECTION: go(std::integral_constant<int, FAM_ADVECTION>()); break;
+            default: go(std::integral_constant<int, FAM_RADIAL>());
+            }
+            H2_LAUNCH_CHECK();
+        } else {
+            fail(H2_EINTERNAL, "coupling evaluated in the apply needs precision 64");
+        }
+    } else {
+        launch_sweep<T, sizeof(T) == 4>(h.cp, h.il_ptr.p, h.bu.rank.p, h.B_off.p, AB::B(h), xh, h.bu.xh_off.p, yh, ld,
+                                        0, zero, s);
+    }
     mark(3);
     for (int L = 1; L < h.maxdepth; ++L) {
         int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
@@ -510,6 +622,24 @@ void prepare_apply(Handle& h)
     std::vector<int64_t> st(h.h_start.begin(), h.h_start.end());
     h.start64.ensure(std::max<size_t>(st.size(), 1), s);
     H2_HIP(hipMemcpyAsync(h.start64.p, st.data(), st.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    // coupling evaluated in the apply: (node, first row) of every 64-row
+    // chunk of a node with a basis (zero yhat without IL)
+    if (h.store_coupling == 0) {
+        std::vector<int> nd, rr;
+        for (int i = 0; i < h.nnode; ++i)
+            for (int r0 = 0; r0 < h.bu.h_rank[i]; r0 += 64) {
+                nd.push_back(i);
+                rr.push_back(r0);
+            }
+        h.n_otf = (int)nd.size();
+        h.otf_node.ensure(std::max<size_t>(nd.size(), 1), s);
+        h.otf_r0.ensure(std::max<size_t>(rr.size(), 1), s);
+        if (!nd.empty()) {
+            H2_HIP(hipMemcpyAsync(h.otf_node.p, nd.data(), nd.size() * sizeof(int), hipMemcpyHostToDevice, s));
+            H2_HIP(hipMemcpyAsync(h.otf_r0.p, rr.data(), rr.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        }
+        H2_HIP(hipStreamSynchronize(s));
+    }
     // coupling: every node with a basis writes its yhat (zero without IL);
     // block rows follow the row ranks, block columns (and the xhat they
     // read) the column ranks

@@ -192,7 +192,8 @@ class H2Matrix:
     """Owning wrapper: builds on construction, applies with matvec()."""
 
     def __init__(self, points, kernel="coulomb", prm=1.0, tol=1e-6, leaf=64, tau=0.7, r1=0, r2=0,
-                 seed=0x5EED, stream=None, precision=64, r_min=0, datareduct="volume", srrqr_f=0.0):
+                 seed=0x5EED, stream=None, precision=64, r_min=0, datareduct="volume", srrqr_f=0.0,
+                 store_coupling=1):
         pts = torch.as_tensor(points, dtype=torch.float64)
         if not pts.is_cuda:
             pts = pts.cuda()
@@ -203,6 +204,7 @@ class H2Matrix:
         opt = h2_options_default()
         opt.tau, opt.r1, opt.r2, opt.calib_seed = tau, r1, r2, seed
         opt.precision, opt.r_min = precision, r_min
+        opt.store_coupling = store_coupling
         opt.datareduct = DATAREDUCT[datareduct]
         opt.srrqr_f = srrqr_f
         self.dtype = torch.float32 if precision == 32 else torch.float64

@@ -251,6 +251,41 @@ def test_srrqr_swaps_parity(H, d, kernel, prm, n, leaf, r):
     assert _rel(yg, o.matvec(x)) <= 1e-10
 
 
+@pytest.mark.parametrize("d,kernel,prm,n,leaf,r,nrhs", [(3, "coulomb", 1.0, 4000, 32, 216, 3),
+                                                        (2, "gaussian", 0.1, 5000, 50, 0, 40),
+                                                        (3, "advection", 2.0, 3000, 32, 216, 2),
+                                                        (3, "cosine", 1.0, 3000, 48, 128, 1)])
+def test_coupling_evaluated_in_apply(H, d, kernel, prm, n, leaf, r, nrhs):
+    """store_coupling = 0: the same representation without stored coupling
+    blocks (the apply evaluates them): structure and bases equal the stored
+    build's, no B is kept, the product matches the stored build's to
+    rounding (another summation order) and the oracle's within 1e-10; 40
+    right-hand sides cover two 32-column slices; h2_rebuild keeps the mode."""
+    rng = np.random.default_rng(600 + d)
+    P = rng.random((n, d)) ** 1.5
+    x = rng.standard_normal((nrhs, n))
+    _say(f"coupling in the apply {kernel}-d{d}-n{n} nrhs{nrhs}")
+    g0 = H.H2Matrix(P, kernel, prm, 1e-6, leaf, r1=r, r2=r, store_coupling=0)
+    g1 = H.H2Matrix(P, kernel, prm, 1e-6, leaf, r1=r, r2=r)
+    assert g0.info()["bytes_B"] == 0 and g1.info()["bytes_B"] > 0
+    for name in ("perm", "il_col", "near_col", "rank", "rank_v"):
+        assert np.array_equal(g0.export(name), g1.export(name)), name
+    with pytest.raises(H.H2Error):
+        g0.export("B", 0)
+    y0, y1 = g0.matvec(x).cpu().numpy(), g1.matvec(x).cpu().numpy()
+    assert _rel(y0, y1) <= 1e-12
+    o = O.H2Oracle(P, kernel, prm, tol=1e-6, leaf=leaf, r1=r, r2=r)
+    assert _rel(y0, o.matvec(x)) <= 1e-10
+    if kernel == "coulomb":
+        H.h2_rebuild(g0.handle, "exponential", 0.2, 1e-6)
+        f = H.H2Matrix(P, "exponential", 0.2, 1e-6, leaf, r1=r, r2=r)
+        assert g0.info()["bytes_B"] == 0
+        assert _rel(g0.matvec(x).cpu().numpy(), f.matvec(x).cpu().numpy()) <= 1e-12
+        f.close()
+    g0.close()
+    g1.close()
+
+
 def test_exact_limit_against_dense(H):
     """r1 = r2 >= n and a rounding-level tolerance: the GPU H^2 product equals
     the dense product."""

@@ -63,6 +63,12 @@ def test_validation_without_device_work():
     assert L.h2_build_ex(dummy, 10, 3, 0, prm, 1e-6, 64, C.byref(opt), None, C.byref(out)) == h2.H2_EINVAL
     opt.precision, opt.r_min = 32, -1
     assert L.h2_build_ex(dummy, 10, 3, 0, prm, 1e-6, 64, C.byref(opt), None, C.byref(out)) == h2.H2_EINVAL
+    opt = h2.h2_options_default()
+    assert opt.store_coupling == 1
+    opt.store_coupling = 2
+    assert L.h2_build_ex(dummy, 10, 3, 0, prm, 1e-6, 64, C.byref(opt), None, C.byref(out)) == h2.H2_EINVAL
+    opt.store_coupling, opt.precision = 0, 32  # the apply's own coupling evaluation is FP64 only
+    assert L.h2_build_ex(dummy, 10, 3, 0, prm, 1e-6, 64, C.byref(opt), None, C.byref(out)) == h2.H2_EUNSUPPORTED
     assert L.h2_matvec(None, dummy, dummy, 1) == h2.H2_EINVAL
     assert L.h2_destroy(None) == h2.H2_OK
 
