@@ -75,7 +75,8 @@ def parse():
     ap.add_argument("--rows", type=int, default=512, help="sampled rows for the dense accuracy check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=1 << 17, help="points of the oracle's bounded sample")
-    ap.add_argument("--workload", choices=["cube1m", "batched", "serving", "sphere3", "variants"], default="cube1m",
+    ap.add_argument("--workload", choices=["cube1m", "batched", "serving", "sphere3", "variants", "large"],
+                    default="cube1m",
                     help="cube1m: the headline n=2^20 Coulomb step; batched: 256 independent problems; "
                          "serving: Poisson request stream")
     ap.add_argument("--nreq", type=int, default=64, help="requests of the serving workload")
@@ -287,6 +288,51 @@ def bench_variants(args):
     print(json.dumps({"workload": f"cube3d-n{n}-options-nrhs{nrhs}", "cases": res}), flush=True)
 
 
+def bench_large(args):
+    """Beyond the stored-block limit: n = 2^22 uniform points in [0,1]^3
+    (--n overrides), Coulomb, leaf 128, tol 1e-6, r_min 343, 32 RHS, with
+    the coupling blocks evaluated in the apply (store_coupling = 0; stored,
+    they would take ~760 GB).  One untimed build + apply, then one timed;
+    accuracy on sampled rows against the dense product."""
+    import torch
+    from paper_2206_01885_amd import h2
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    n = args.n if args.n != 1 << 20 else 1 << 22
+    nrhs = args.nrhs
+    rng = np.random.default_rng(1004)
+    P = torch.tensor(rng.random((n, 3)), device=dev)
+    Psoa = P.t().contiguous()
+    X = torch.tensor(rng.standard_normal((nrhs, n)), device=dev)
+    Y = torch.empty_like(X)
+    rows = torch.tensor(np.sort(rng.choice(n, args.rows, replace=False)), device=dev)
+    opt = h2.h2_options_default()
+    opt.r_min = args.r_min
+    opt.store_coupling = 0
+    for k in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hd = h2.h2_build(Psoa, "coulomb", 1.0, 1e-6, 128, opt)
+        tb = time.perf_counter()
+        h2.h2_matvec(hd, X, Y, nrhs)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        info = h2.h2_query(hd)
+        h2.h2_destroy(hd)
+        print(f"[bench] large n={n} step {k}: build {tb - t0:.3f} s matvec {te - tb:.4f} s", file=sys.stderr,
+              flush=True)
+    ref = dense_rows_gpu(P, X, rows)
+    e = ((Y[:, rows] - ref).norm(dim=1) / ref.norm(dim=1)).max().item()
+    print(json.dumps({
+        "metric": "H2 build + matvec Mpts/s, coupling blocks evaluated in the apply",
+        "value": n / (te - t0) / 1e6, "unit": "Mpts/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1e3 * (te - t0), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"cube3d-coulomb-n{n}-leaf128-tol1e-6-nrhs{nrhs}-store_coupling0", "n": n},
+        "build_s": tb - t0, "matvec_s": te - tb, "nnode": info["nnode"], "r1": info["r1"],
+        "max_rank": info["max_rank"], "bytes_D": info["bytes_D"], "e_dense_sampled_rows_max_rhs": e}), flush=True)
+
+
 def cpu_baseline(n, nrhs):
     """The oracle as it stands on a bounded sample: n points of the same
     distribution, same kernel/leaf/tolerance; build + one apply with nrhs RHS."""
@@ -402,6 +448,9 @@ def main():
         return
     if args.workload == "variants":
         bench_variants(args)
+        return
+    if args.workload == "large":
+        bench_large(args)
         return
     import torch
     from paper_2206_01885_amd import h2
