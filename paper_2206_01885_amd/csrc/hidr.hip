@@ -280,6 +280,13 @@ __global__ __launch_bounds__(TB) void k_list_coords(const double* __restrict__ p
 // forms them) by the last pick and the workgroup takes the largest, the
 // earliest position among equal ones, until |S| = k or the largest is 0.
 // |X| <= k: X unchanged.  The picks are written in selection order.
+// Lists of up to FPS_TMAX tiles of TB consecutive entries keep per tile its
+// bounding box and the largest md with its earliest position; a pick leaves
+// a tile alone when the squared distance from the pick to the tile's box
+// (formed like the entries' distances, so by monotone rounding never above
+// any of them) is not below the tile's largest md, as no entry can then get
+// closer.  The picks are those of the full pass.
+constexpr int FPS_TMAX = 512;
 __global__ __launch_bounds__(TB) void k_datareduct_fps(const double* __restrict__ cw, int64_t tot, int d,
                                                        const int64_t* __restrict__ list_off,
                                                        const int* __restrict__ list_idx, int k,
@@ -288,6 +295,8 @@ __global__ __launch_bounds__(TB) void k_datareduct_fps(const double* __restrict_
 {
     __shared__ double rv[TB];
     __shared__ int rp[TB];
+    __shared__ double tlo[3][FPS_TMAX], thi[3][FPS_TMAX], tmx[FPS_TMAX];
+    __shared__ int tps[FPS_TMAX];
     const int l = blockIdx.x;
     const int64_t b0 = list_off[l];
     const int L = (int)(list_off[l + 1] - b0);
@@ -303,6 +312,129 @@ __global__ __launch_bounds__(TB) void k_datareduct_fps(const double* __restrict_
     const double* x1 = cw + tot + b0;
     const double* x2 = cw + 2 * tot + b0;
     double* md = md_ws + b0;  // each entry read and written by its own lane only
+    const int nt = (L + TB - 1) / TB;
+    if (nt <= FPS_TMAX) {
+        // wave w owns the tiles t = w mod 4, lane l the entries t TB + 64 q + l
+        constexpr int NW = TB / 64;
+        const int w = tid >> 6, lane = tid & 63;
+        for (int t = w; t < nt; t += NW) {
+            double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (int q = 0; q < NW; ++q) {
+                const int p = t * TB + 64 * q + lane;
+                if (p < L) {
+                    md[p] = INFINITY;
+                    const double v[3] = {x0[p], d > 1 ? x1[p] : 0.0, d > 2 ? x2[p] : 0.0};
+                    for (int a = 0; a < 3; ++a) {
+                        lo[a] = fmin(lo[a], v[a]);
+                        hi[a] = fmax(hi[a], v[a]);
+                    }
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1)
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = fmin(lo[a], __shfl_xor(lo[a], off, 64));
+                    hi[a] = fmax(hi[a], __shfl_xor(hi[a], off, 64));
+                }
+            if (lane == 0) {
+                for (int a = 0; a < 3; ++a) {
+                    tlo[a][t] = lo[a];
+                    thi[a][t] = hi[a];
+                }
+                tmx[t] = INFINITY;
+                tps[t] = t * TB;
+            }
+        }
+        __syncthreads();
+        int cur = 0, cnt = 0;
+        for (;;) {
+            if (tid == 0) o[cnt] = lst[cur];
+            ++cnt;
+            if (cnt == k) break;
+            const double c0 = x0[cur];
+            const double c1 = d > 1 ? x1[cur] : 0.0;
+            const double c2 = d > 2 ? x2[cur] : 0.0;
+            for (int t = w; t < nt; t += NW) {
+                double e = fmax(fmax(tlo[0][t] - c0, c0 - thi[0][t]), 0.0);
+                double lb = e * e;
+                if (d > 1) {
+                    e = fmax(fmax(tlo[1][t] - c1, c1 - thi[1][t]), 0.0);
+                    lb = lb + e * e;
+                }
+                if (d > 2) {
+                    e = fmax(fmax(tlo[2][t] - c2, c2 - thi[2][t]), 0.0);
+                    lb = lb + e * e;
+                }
+                if (!(lb < tmx[t])) continue;  // wave-uniform
+                double bv = -1.0;
+                int bp = 0x7fffffff;
+                for (int q = 0; q < NW; ++q) {
+                    const int p = t * TB + 64 * q + lane;
+                    if (p < L) {
+                        const double e0 = x0[p] - c0;
+                        double dd = e0 * e0;
+                        if (d > 1) {
+                            const double e1 = x1[p] - c1;
+                            dd = dd + e1 * e1;
+                        }
+                        if (d > 2) {
+                            const double e2 = x2[p] - c2;
+                            dd = dd + e2 * e2;
+                        }
+                        double mv = md[p];
+                        if (dd < mv) {
+                            mv = dd;
+                            md[p] = mv;
+                        }
+                        if (mv > bv) {
+                            bv = mv;
+                            bp = p;
+                        }
+                    }
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double v2 = __shfl_xor(bv, off, 64);
+                    const int p2 = __shfl_xor(bp, off, 64);
+                    if (v2 > bv || (v2 == bv && p2 < bp)) {
+                        bv = v2;
+                        bp = p2;
+                    }
+                }
+                if (lane == 0) {
+                    tmx[t] = bv;
+                    tps[t] = bp;
+                }
+            }
+            __syncthreads();
+            double bv = -1.0;
+            int bp = 0x7fffffff;
+            for (int t = tid; t < nt; t += TB)
+                if (tmx[t] > bv || (tmx[t] == bv && tps[t] < bp)) {
+                    bv = tmx[t];
+                    bp = tps[t];
+                }
+            rv[tid] = bv;
+            rp[tid] = bp;
+            __syncthreads();
+            for (int off = TB / 2; off > 0; off >>= 1) {
+                if (tid < off) {
+                    const double v2 = rv[tid + off];
+                    const int p2 = rp[tid + off];
+                    if (v2 > rv[tid] || (v2 == rv[tid] && p2 < rp[tid])) {
+                        rv[tid] = v2;
+                        rp[tid] = p2;
+                    }
+                }
+                __syncthreads();
+            }
+            const double best = rv[0];
+            const int bpos = rp[0];
+            __syncthreads();
+            if (!(best > 0.0)) break;
+            cur = bpos;
+        }
+        if (tid == 0) out_cnt[l] = cnt;
+        return;
+    }
     for (int p = tid; p < L; p += TB) md[p] = INFINITY;
     int cur = 0, cnt = 0;
     for (;;) {
