@@ -665,6 +665,22 @@ def main():
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                             "bytes_per_launch": coupling_bytes, "ms_per_launch": 1e3 * t_coup},
     }
+    # the HBM rate a plain device copy reaches here (1 GiB read + 1 GiB
+    # written per copy), beside the vendor peak
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    tc = time.perf_counter()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 8 / (time.perf_counter() - tc) / 1e9
+    del src, dst
+    out["hbm_copy_gbs"] = copy_gbs
+    for key in ("roofline", "roofline_matvec"):
+        if out[key]["unit"] == "GB/s":
+            out[key]["frac_of_measured_copy"] = out[key]["achieved"] / copy_gbs
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, nrhs)
