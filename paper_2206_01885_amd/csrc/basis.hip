@@ -1309,7 +1309,9 @@ void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
     bool prof_on = false;
     for (auto* h : hs) prof_on = prof_on || h->profile != 0;
     IdProf prof;
-    const int64_t WS_CAP = (int64_t)1 << 28;  // doubles of ID workspace per launch
+    // doubles of ID workspace per launch (8 GiB): a whole level of a 2^20-point
+    // problem fits, so each launch class fills the chip in one grid
+    const int64_t WS_CAP = (int64_t)1 << 30;
     DBuf<int> d_xidx;
     DBuf<int64_t> d_xoff;
     DBuf<double> Mws, nuws;
