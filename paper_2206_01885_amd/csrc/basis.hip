@@ -1365,10 +1365,17 @@ void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
         std::vector<IdTask> tasks;
         std::vector<int64_t> Moff, nuoff;
         int64_t ws = 0, no = 0;
+        // workspace sizes rounded up to a power of two, so that builds of
+        // different sizes reuse the same cached device blocks
+        auto pow2 = [](int64_t v) {
+            size_t c = 1;
+            while (c < (size_t)v) c <<= 1;
+            return c;
+        };
         auto flush = [&]() {
             if (tasks.empty()) return;
-            Mws.ensure((size_t)std::max<int64_t>(ws, 1), s);
-            nuws.ensure((size_t)std::max<int64_t>(no, 1), s);
+            Mws.ensure(pow2(ws), s);
+            nuws.ensure(pow2(no), s);
             for (size_t q = 0; q < tasks.size(); ++q) {
                 tasks[q].M = Mws.p + Moff[q];
                 tasks[q].nu = nuws.p + nuoff[q];
