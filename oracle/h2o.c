@@ -24,7 +24,9 @@
  *
  * All arithmetic is IEEE double, compiled with -ffp-contract=off; sums run
  * sequentially in index order.  OpenMP parallelises over independent nodes of
- * one tree level only, so results do not depend on the thread count.
+ * one tree level and over the rows of the calibration's residual (each row's
+ * sum kept apart and added in order), so results do not depend on the
+ * thread count.
  */
 #include <math.h>
 #include <stdint.h>
@@ -123,18 +125,22 @@ void h2o_kernel_matrix(int kid, const double *prm, int d, const double *X, int m
 /* ------------------------------------------------------------------ */
 /* DataReduct(X, k) -> X*: X is given as `L` indices into the point array
  * `pts` ([npts][d]), split into `nseg` consecutive segments seg[0..nseg]
- * (seg[0] = 0, seg[nseg] = L).  Reading of the silent details:
+ * (seg[0] = 0, seg[nseg] = L).  k is the maximum size of X* (Algorithm 1
+ * names r1 and r2 the maximum sizes of X_i^* and Y_i^*).  Reading of the
+ * silent details:
  *  - |X| <= k: X is returned unchanged (keeps every point);
  *  - the reference set Q is, for every non-empty segment in order, the
  *    tensor grid of cell centres of a g^d grid over that segment's bounding
- *    box (g the largest integer with g^d <= k, dimension 0 varying fastest);
- *    a list built from one set has one segment, the farfield list T_i of
- *    HiDR has two (the parent's Y_p^* and the interaction-list part);
+ *    box (g the largest integer with g^d <= k / nseg, at least 1, dimension 0
+ *    varying fastest), so |X*| <= k whenever k >= nseg; a list built from
+ *    one set has one segment, the farfield list T_i of HiDR has two (the
+ *    parent's Y_p^* and the interaction-list part), each sampled by a grid
+ *    of at most k/2 points over its own extent;
  *  - for each q in Q order the point of the whole X with the smallest squared
  *    distance is taken, ties going to the earliest position in X;
  *  - X* lists the distinct picks in Q order of first occurrence.
- * Writes the selected indices to out (capacity >= min(L, nseg*k)); returns
- * |X*|. */
+ * Writes the selected indices to out (capacity >= min(L, max(k, nseg)));
+ * returns |X*|. */
 int h2o_datareduct_seg(int d, const double *pts, const int *list, int L, const int *seg, int nseg, int k,
                        int *out)
 {
@@ -143,12 +149,13 @@ int h2o_datareduct_seg(int d, const double *pts, const int *list, int L, const i
             out[p] = list[p];
         return L;
     }
+    int kp = k / nseg > 1 ? k / nseg : 1; /* grid budget of one segment */
     int g = 1;
     for (;;) {
         long long nx = 1;
         for (int a = 0; a < d; ++a)
             nx *= (long long)(g + 1);
-        if (nx > k) break;
+        if (nx > kp) break;
         ++g;
     }
     int nq1 = 1;
@@ -291,9 +298,10 @@ static void surface_dir(int d, int j, int m, double *u)
  * segment (as in the volume method) with bounding box [lo, hi], widths
  * w = hi - lo and centre c = lo + 0.5 w, points on the three ellipsoids
  * centred at c with semi-axes gamma w, gamma = 0.3, 0.6, 1.2 (the values of
- * Section 5.2): q = c + (gamma w) u_j for the m = max(1, floor(k/3))
+ * Section 5.2): q = c + (gamma w) u_j for the m = max(1, floor(kp/3))
  * directions u_j of surface_dir (1-D: at most 2), in the order gamma, then j,
- * the first k of them.  Nearest point, tie rule and output as in the volume
+ * the first kp of them, kp = max(1, floor(k / nseg)) the segment's share of
+ * the size bound k.  Nearest point, tie rule and output as in the volume
  * method. */
 int h2o_datareduct_surface(int d, const double *pts, const int *list, int L, const int *seg, int nseg, int k,
                            int *out)
@@ -304,9 +312,10 @@ int h2o_datareduct_surface(int d, const double *pts, const int *list, int L, con
         return L;
     }
     static const double gam[3] = {0.3, 0.6, 1.2};
-    int m = k / 3 > 1 ? k / 3 : 1;
+    int kp = k / nseg > 1 ? k / nseg : 1;
+    int m = kp / 3 > 1 ? kp / 3 : 1;
     if (d == 1 && m > 2) m = 2;
-    int nq1 = 3 * m < k ? 3 * m : k;
+    int nq1 = 3 * m < kp ? 3 * m : kp;
     int *pick = (int *)malloc(sizeof(int) * (size_t)nq1 * (size_t)nseg);
     int nq = 0;
     for (int sg = 0; sg < nseg; ++sg) {
@@ -588,6 +597,7 @@ typedef struct h2o {
     int n, d, kid;
     double prm[4];
     double tol, tau;
+    double eps; /* the user's tolerance (tol = eps / 2 is the construction's) */
     int q;
     /* tree (Section 2.1); nodes in BFS order: depth, then parent, then child code */
     int nnode, cap, maxdepth;
@@ -855,8 +865,9 @@ static void build_lists(h2o *h)
  * X_j^* for j in IL(i) ascending (Y_root^* is empty); Y_i^* =
  * DataReduct(T_i, r2) when T_i is not empty, with the two parts of T_i as
  * the segments of the volume reference set, so each part is sampled on a
- * grid of its own extent and |Y_i^*| <= 2 r2.  (The text writes "union of
- * Y_p" once and Y_p^* in the algorithm and elsewhere; Y_p^* is taken.) */
+ * grid of at most r2/2 points over its own extent and |Y_i^*| <= r2.  (The
+ * text writes "union of Y_p" once and Y_p^* in the algorithm and elsewhere;
+ * Y_p^* is taken.) */
 static void run_hidr(h2o *h)
 {
     h->xs = (ilist *)calloc((size_t)h->nnode, sizeof(ilist));
@@ -915,47 +926,115 @@ static void run_hidr(h2o *h)
 /* r1, r2 from the tolerance (Section 4.2; Algorithm 2 step 2)         */
 /* ------------------------------------------------------------------ */
 /* The paper grows r1 = r2 from 1 until the ID built from the reduced set
- * approximates an artificial well-separated K_{Z1 Z2} to better than
- * 1e-2 eps.  Readings of what it leaves open: r steps over g^d (the sizes the
- * volume grid produces); Z1, Z2 hold 512 points each, uniform in cubes of
- * side s whose centres lie s sqrt(d)/tau apart along axis 0 (the closest
- * admissible placement); coordinates come from SplitMix64 values 0.. (Z1
- * first, then Z2, coordinate fastest); the ID inside uses tolerance 1e-3 eps,
- * a decade below the target, so that the sampling and not the truncation is
- * what the test measures;
- * the error is the relative Frobenius norm of K_{Z1Z2} - U K_{Zhat Z2}.
+ * approximates an artificial block K_{Z1 Z2} of well-separated point sets
+ * to better than 1e-2 eps.  Readings of what it leaves open:
+ *  - r steps over g^d, g = 1, 2, ... (the sizes the volume grid produces);
+ *    r1 = r and r2 = 2 r, since Y_i^* samples two parts of T_i with a grid
+ *    of r points each;
+ *  - Z1: 512 points uniform in the box [0, s)^d;
+ *  - Z2: 4096 points, each uniform in a box drawn uniformly from the
+ *    interaction list of Z1's box in the uniform tree of boxes of side s
+ *    (h2o_calib_shell): every box of Z2 is well separated from Z1's box,
+ *    and together they form the nearest farfield that the top-down
+ *    DataReduct of a node samples with one grid over its extent;
+ *  - coordinates are SplitMix64 values of the stream `seed`: value i d + a
+ *    is coordinate a of Z1 point i; for Z2 point j, value 512 d + j (d + 1)
+ *    picks its box (floor(u nb)) and the d values after it place the point
+ *    inside the box;
+ *  - the ID inside is built on Y* = DataReduct(Z2, r) with tolerance
+ *    1e-3 eps' (eps' = eps/2, the IDs' truncation tolerance of the
+ *    construction), so that the test measures the sampling more than the
+ *    truncation;
+ *  - the error is the relative Frobenius norm of K_{Z1Z2} - U K_{Zhat Z2}
+ *    over all of Z2; eps is the user's tolerance.
  * Returns the first r meeting the target, or r_cap if none does; *err gets
  * the error of the returned r. */
-#define H2O_NCAL 512
+#define H2O_NCAL1 512
+#define H2O_NCAL2 4096
+
+/* Cell offsets o (box [o s, (o + 1) s)) of the interaction list of the box
+ * [0, s)^d in the uniform tree of boxes of side s, by the pair rule: o is
+ * admissible to the box (Eq. separation with box diagonals and centres) and
+ * its parent cell floor(o / 2) (side 2 s) is not admissible to the box's
+ * parent [0, 2 s)^d.  Listed with dimension 0 varying fastest, every
+ * coordinate ascending; out ([count][d]) may be NULL.  Returns the count. */
+int h2o_calib_shell(int d, double tau, int *out)
+{
+    int R = (int)ceil(2.0 * sqrt((double)d) / tau) + 1;
+    int w = 2 * R + 1;
+    long long tot = 1;
+    for (int a = 0; a < d; ++a)
+        tot *= w;
+    int cnt = 0;
+    for (long long t = 0; t < tot; ++t) {
+        int o[3];
+        long long rem = t;
+        double dc = 0.0, dp = 0.0;
+        for (int a = 0; a < d; ++a) {
+            o[a] = (int)(rem % w) - R;
+            rem /= w;
+            int po = o[a] >= 0 ? o[a] / 2 : -((1 - o[a]) / 2); /* floor(o / 2) */
+            double ec = (double)o[a];           /* centre o + 1/2 against 1/2 */
+            double ep = 2.0 * (double)po;       /* centre 2 po + 1 against 1 */
+            dc = dc + ec * ec;
+            dp = dp + ep * ep;
+        }
+        int adm_c = (double)d * 4.0 <= 4.0 * tau * tau * dc;   /* sides 1 and 1 */
+        int adm_p = (double)d * 16.0 <= 4.0 * tau * tau * dp;  /* sides 2 and 2 */
+        if (adm_c && !adm_p) {
+            if (out)
+                for (int a = 0; a < d; ++a)
+                    out[(size_t)cnt * d + a] = o[a];
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+/* The calibration point sets of h2o_calibrate_one: Z1 [512][d], Z2
+ * [4096][d] (row-major). */
+void h2o_calib_points(int d, double s, double tau, uint64_t seed, double *Z1, double *Z2)
+{
+    int nb = h2o_calib_shell(d, tau, NULL);
+    int *sh = (int *)malloc(sizeof(int) * (size_t)(nb > 0 ? nb : 1) * d);
+    h2o_calib_shell(d, tau, sh);
+    for (int i = 0; i < H2O_NCAL1; ++i)
+        for (int a = 0; a < d; ++a)
+            Z1[(size_t)i * d + a] = s * h2o_splitmix_u01(seed, (uint64_t)i * d + a);
+    uint64_t base = (uint64_t)H2O_NCAL1 * d;
+    for (int j = 0; j < H2O_NCAL2; ++j) {
+        uint64_t c = base + (uint64_t)j * (d + 1);
+        int b = (int)(h2o_splitmix_u01(seed, c) * (double)nb);
+        if (b > nb - 1) b = nb - 1;
+        for (int a = 0; a < d; ++a)
+            Z2[(size_t)j * d + a] = s * ((double)sh[(size_t)b * d + a] + h2o_splitmix_u01(seed, c + 1 + a));
+    }
+    free(sh);
+}
+
 int h2o_calibrate_one(int kid, const double *prm, int d, double s, double tau, double eps,
                       uint64_t seed, int r_cap, double *err_out)
 {
-    int nz = H2O_NCAL;
-    double *Z1 = (double *)malloc(sizeof(double) * (size_t)nz * d);
-    double *Z2 = (double *)malloc(sizeof(double) * (size_t)nz * d);
-    double sep = s * sqrt((double)d) / tau;
-    for (int i = 0; i < nz; ++i)
-        for (int a = 0; a < d; ++a) {
-            double u1 = h2o_splitmix_u01(seed, (uint64_t)i * d + a);
-            double u2 = h2o_splitmix_u01(seed, (uint64_t)nz * d + (uint64_t)i * d + a);
-            Z1[(size_t)i * d + a] = s * (u1 - 0.5);
-            Z2[(size_t)i * d + a] = s * (u2 - 0.5) + (a == 0 ? sep : 0.0);
-        }
-    double *Kfull = (double *)malloc(sizeof(double) * (size_t)nz * nz);
-    h2o_kernel_matrix(kid, prm, d, Z1, nz, Z2, nz, Kfull);
+    int n1 = H2O_NCAL1, n2 = H2O_NCAL2;
+    double *Z1 = (double *)malloc(sizeof(double) * (size_t)n1 * d);
+    double *Z2 = (double *)malloc(sizeof(double) * (size_t)n2 * d);
+    h2o_calib_points(d, s, tau, seed, Z1, Z2);
+    double *Kfull = (double *)malloc(sizeof(double) * (size_t)n1 * n2);
+    h2o_kernel_matrix(kid, prm, d, Z1, n1, Z2, n2, Kfull);
     double fro = 0.0;
-    for (size_t e = 0; e < (size_t)nz * nz; ++e)
+    for (size_t e = 0; e < (size_t)n1 * n2; ++e)
         fro = fro + Kfull[e] * Kfull[e];
     fro = sqrt(fro);
-    int *all = (int *)malloc(sizeof(int) * (size_t)nz);
-    for (int i = 0; i < nz; ++i)
+    int *all = (int *)malloc(sizeof(int) * (size_t)n2);
+    for (int i = 0; i < n2; ++i)
         all[i] = i;
-    int *ysel = (int *)malloc(sizeof(int) * (size_t)nz);
-    double *Ysel = (double *)malloc(sizeof(double) * (size_t)nz * d);
-    double *A = (double *)malloc(sizeof(double) * (size_t)nz * nz);
-    int *piv = (int *)malloc(sizeof(int) * (size_t)nz);
-    double *T = (double *)malloc(sizeof(double) * (size_t)nz * nz);
-    double *rd = (double *)malloc(sizeof(double) * (size_t)nz);
+    int *ysel = (int *)malloc(sizeof(int) * (size_t)n2);
+    double *Ysel = (double *)malloc(sizeof(double) * (size_t)n2 * d);
+    double *A = (double *)malloc(sizeof(double) * (size_t)n1 * n2);
+    int *piv = (int *)malloc(sizeof(int) * (size_t)n1);
+    double *T = (double *)malloc(sizeof(double) * (size_t)n1 * n1);
+    double *rd = (double *)malloc(sizeof(double) * (size_t)n1);
+    double *rowres = (double *)malloc(sizeof(double) * (size_t)n1);
     int r_found = r_cap;
     double err = INFINITY;
     for (int g = 1;; ++g) {
@@ -963,25 +1042,36 @@ int h2o_calibrate_one(int kid, const double *prm, int d, double s, double tau, d
         for (int a = 0; a < d; ++a)
             rr *= g;
         int r = rr > r_cap ? r_cap : (int)rr;
-        int sy = h2o_datareduct(d, Z2, all, nz, r, ysel);
+        int sy = h2o_datareduct(d, Z2, all, n2, r, ysel);
         for (int t = 0; t < sy; ++t)
             for (int a = 0; a < d; ++a)
                 Ysel[(size_t)t * d + a] = Z2[(size_t)ysel[t] * d + a];
-        h2o_kernel_matrix(kid, prm, d, Z1, nz, Ysel, sy, A);
-        int k = h2o_cpqr_id(A, nz, sy, 1e-3 * eps, piv, T, rd);
-        /* residual K(rest,:) - T^T K(skel,:) over all of Z2 (skeleton rows are exact) */
-        int nr = nz - k;
-        double res = 0.0;
+        h2o_kernel_matrix(kid, prm, d, Z1, n1, Ysel, sy, A);
+        int k = h2o_cpqr_id(A, n1, sy, 1e-3 * (0.5 * eps), piv, T, rd);
+        /* residual K(rest,:) - T^T K(skel,:) over all of Z2 (skeleton rows
+         * are exact); each row's sum in a slot of its own, added in order */
+        int nr = n1 - k;
+#pragma omp parallel for schedule(dynamic, 4)
         for (int u = 0; u < nr; ++u) {
-            const double *xr = Z1 + (size_t)piv[k + u] * d;
-            for (int c = 0; c < nz; ++c) {
-                double approx = 0.0;
-                for (int t = 0; t < k; ++t)
-                    approx = approx + T[(size_t)t * nr + u] * Kfull[(size_t)piv[t] * nz + c];
-                double e = h2o_kappa(kid, prm, xr, Z2 + (size_t)c * d, d) - approx;
+            double *acc = (double *)calloc((size_t)n2, sizeof(double));
+            for (int t = 0; t < k; ++t) {
+                double tv = T[(size_t)t * nr + u];
+                const double *ks = Kfull + (size_t)piv[t] * n2;
+                for (int c = 0; c < n2; ++c)
+                    acc[c] = acc[c] + tv * ks[c];
+            }
+            const double *kr = Kfull + (size_t)piv[k + u] * n2;
+            double res = 0.0;
+            for (int c = 0; c < n2; ++c) {
+                double e = kr[c] - acc[c];
                 res = res + e * e;
             }
+            rowres[u] = res;
+            free(acc);
         }
+        double res = 0.0;
+        for (int u = 0; u < nr; ++u)
+            res = res + rowres[u];
         err = fro > 0.0 ? sqrt(res) / fro : 0.0;
         if (err < 1e-2 * eps) {
             r_found = r;
@@ -994,7 +1084,7 @@ int h2o_calibrate_one(int kid, const double *prm, int d, double s, double tau, d
     }
     if (err_out) *err_out = err;
     free(Z1); free(Z2); free(Kfull); free(all); free(ysel); free(Ysel);
-    free(A); free(piv); free(T); free(rd);
+    free(A); free(piv); free(T); free(rd); free(rowres);
     return r_found;
 }
 
@@ -1011,7 +1101,7 @@ static void calibrate(h2o *h, uint64_t seed)
     int cap = r_cap_for(h->d);
     if (h->kid == K_COULOMB) {
         double e;
-        int r = h2o_calibrate_one(h->kid, h->prm, h->d, 1.0, h->tau, h->tol, seed, cap, &e);
+        int r = h2o_calibrate_one(h->kid, h->prm, h->d, 1.0, h->tau, h->eps, seed, cap, &e);
         for (int L = 0; L <= h->maxdepth; ++L) {
             h->calib_r[L] = r;
             h->calib_err[L] = e;
@@ -1024,7 +1114,7 @@ static void calibrate(h2o *h, uint64_t seed)
                 if (h->il_ptr[i + 1] > h->il_ptr[i]) has = 1;
             if (!has) continue;
             double e;
-            int r = h2o_calibrate_one(h->kid, h->prm, h->d, h->side[h->lvl_ptr[L]], h->tau, h->tol,
+            int r = h2o_calibrate_one(h->kid, h->prm, h->d, h->side[h->lvl_ptr[L]], h->tau, h->eps,
                                       seed, cap, &e);
             h->calib_r[L] = r;
             h->calib_err[L] = e;
@@ -1032,7 +1122,7 @@ static void calibrate(h2o *h, uint64_t seed)
         }
     }
     if (h->r1 <= 0) h->r1 = rmax;
-    if (h->r2 <= 0) h->r2 = rmax;
+    if (h->r2 <= 0) h->r2 = 2 * rmax;
 }
 
 /* ------------------------------------------------------------------ */
@@ -1141,6 +1231,8 @@ h2o *h2o_build_ex(const double *pts, int n, int d, int kid, const double *prm, d
     /* the calibration places its boxes along one axis and assumes a kernel
      * of |x - y|: the cosine and advection kernels take given r1, r2 */
     if ((kid == K_COSINE || kid == K_ADVECTION) && (r1 <= 0 || r2 <= 0)) return NULL;
+    /* Y_i^* gets a grid of r2/2 points over each part of T_i */
+    if (r2 == 1) return NULL;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -1152,10 +1244,11 @@ h2o *h2o_build_ex(const double *pts, int n, int d, int kid, const double *prm, d
     h->kid = kid;
     h->prm[0] = prm ? prm[0] : 1.0;
     /* The paper leaves the split of the tolerance between sampling and
-     * truncation open; the construction runs at eps' = eps/2 (ID truncation
-     * and the calibration target), which keeps the end-to-end error against
+     * truncation open; the IDs truncate at eps' = eps/2 (the calibration
+     * targets 1e-2 eps as the paper states), which keeps the error against
      * the dense product within eps on the reference workloads. */
     h->tol = tol * 0.5;
+    h->eps = tol;
     h->tau = tau;
     h->q = q;
     h->r1 = r1;

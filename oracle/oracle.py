@@ -59,6 +59,9 @@ def lib():
         L.h2o_calibrate_one.restype = C.c_int
         L.h2o_calibrate_one.argtypes = [C.c_int, dp, C.c_int, C.c_double, C.c_double, C.c_double,
                                         C.c_uint64, C.c_int, dp]
+        L.h2o_calib_shell.restype = C.c_int
+        L.h2o_calib_shell.argtypes = [C.c_int, C.c_double, ip]
+        L.h2o_calib_points.argtypes = [C.c_int, C.c_double, C.c_double, C.c_uint64, dp, dp]
         L.h2o_build.restype = C.c_void_p
         L.h2o_build.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp, C.c_double, C.c_int, C.c_double,
                                 C.c_int, C.c_int, C.c_uint64, C.c_int]
@@ -191,6 +194,23 @@ def cpqr_id(A, tol):
 
 def splitmix_u01(seed, i) -> float:
     return lib().h2o_splitmix_u01(int(seed) & (2**64 - 1), int(i))
+
+
+def calib_shell(d, tau) -> np.ndarray:
+    """Cell offsets [nb, d] of the interaction list of the box [0, 1)^d in
+    the uniform tree of unit boxes (the calibration's Z2 boxes)."""
+    nb = lib().h2o_calib_shell(d, tau, None)
+    out = np.empty((max(nb, 1), d), dtype=np.int32)
+    lib().h2o_calib_shell(d, tau, _i(out))
+    return out[:nb].copy()
+
+
+def calib_points(d, side, tau, seed):
+    """The calibration's point sets (Z1 [512, d], Z2 [4096, d])."""
+    Z1 = np.empty((512, d))
+    Z2 = np.empty((4096, d))
+    lib().h2o_calib_points(d, side, tau, int(seed) & (2**64 - 1), _d(Z1), _d(Z2))
+    return Z1, Z2
 
 
 def calibrate_one(kid, prm, d, side, tau, eps, seed, r_cap):

@@ -123,13 +123,13 @@ def test_nonsymmetric_bases():
     n = 1500
     P = rng.random((n, 3))
     x = rng.standard_normal((2, n))
-    h0 = O.H2Oracle(P, "advection", 0.0, tol=1e-6, leaf=32, r1=216, r2=216)
+    h0 = O.H2Oracle(P, "advection", 0.0, tol=1e-6, leaf=32, r1=216, r2=432)
     for i in range(1, h0.info()["nnode"]):
         assert np.array_equal(h0.node_list("skel", i), h0.node_list("skel_v", i))
         assert np.array_equal(h0.node_T(i), h0.node_T(i, side=1))
-    hc = O.H2Oracle(P, "coulomb", 1.0, tol=1e-6, leaf=32, r1=216, r2=216)
+    hc = O.H2Oracle(P, "coulomb", 1.0, tol=1e-6, leaf=32, r1=216, r2=432)
     np.testing.assert_array_equal(h0.matvec(x), hc.matvec(x))
-    h1 = O.H2Oracle(P, "advection", 2.0, tol=1e-6, leaf=32, r1=216, r2=216)
+    h1 = O.H2Oracle(P, "advection", 2.0, tol=1e-6, leaf=32, r1=216, r2=432)
     nn = h1.info()["nnode"]
     differ = sum(not np.array_equal(h1.node_list("skel", i), h1.node_list("skel_v", i)) for i in range(1, nn))
     assert differ > nn // 4
@@ -193,7 +193,7 @@ def test_surface_reference_points():
     # two segments: reference points from each segment's box, picks from the whole list
     Y = np.vstack([X[:1000] * 0.1, X[1000:] * 0.1 + 5.0])
     S2 = O.datareduct_method("surface", Y, idx, 30, seg=[0, 1000, 2000])
-    assert np.any(S2 < 1000) and np.any(S2 >= 1000) and len(S2) <= 60
+    assert np.any(S2 < 1000) and np.any(S2 >= 1000) and len(S2) <= 30
 
 
 @pytest.mark.parametrize("method", ["fps", "surface"])
@@ -206,9 +206,9 @@ def test_hidr_variants_meet_tolerance(method):
     P = rng.random((n, 3))
     x = rng.standard_normal((2, n))
     ref = x @ _dense(P, "coulomb", 1.0).T
-    h = O.H2Oracle(P, "coulomb", 1.0, tol=1e-6, leaf=32, r1=125, r2=125, datareduct=method)
+    h = O.H2Oracle(P, "coulomb", 1.0, tol=1e-6, leaf=32, r1=125, r2=250, datareduct=method)
     assert np.linalg.norm(h.matvec(x) - ref) / np.linalg.norm(ref) < 1e-6
-    he = O.H2Oracle(P[:600], "exponential", 0.2, tol=1e-15, leaf=24, r1=600, r2=600, datareduct=method)
+    he = O.H2Oracle(P[:600], "exponential", 0.2, tol=1e-15, leaf=24, r1=600, r2=1200, datareduct=method)
     refe = x[:, :600] @ _dense(P[:600], "exponential", 0.2).T
     assert np.linalg.norm(he.matvec(x[:, :600]) - refe) / np.linalg.norm(refe) < 1e-12
 
@@ -248,8 +248,8 @@ def test_srrqr_build_bounds_interpolation():
     n = 2500
     P = rng.random((n, 3))
     x = rng.standard_normal((2, n))
-    h = O.H2Oracle(P, "exponential", 0.2, tol=1e-6, leaf=32, r1=216, r2=216, srrqr_f=1.05)
-    h0 = O.H2Oracle(P, "exponential", 0.2, tol=1e-6, leaf=32, r1=216, r2=216)
+    h = O.H2Oracle(P, "exponential", 0.2, tol=1e-6, leaf=32, r1=216, r2=432, srrqr_f=1.05)
+    h0 = O.H2Oracle(P, "exponential", 0.2, tol=1e-6, leaf=32, r1=216, r2=432)
     nn = h.info()["nnode"]
     tmax = max((np.abs(h.node_T(i)).max() for i in range(1, nn) if h.node_T(i).size), default=0.0)
     tmax0 = max((np.abs(h0.node_T(i)).max() for i in range(1, nn) if h0.node_T(i).size), default=0.0)
@@ -277,6 +277,96 @@ def test_splitmix64_published_value():
     """First output of SplitMix64 with seed 0 is 0xE220A8397B1DCDAF
     (Steele, Lea, Flood 2014 reference generator)."""
     assert O.splitmix_u01(0, 0) == (0xE220A8397B1DCDAF >> 11) * 2.0**-53
+
+
+# --------------------------------------------------------------- r1, r2
+def _splitmix_u01(seed, i):
+    """SplitMix64 (Steele, Lea, Flood 2014) value i of the stream `seed`, as
+    a double in [0, 1) from its top 53 bits; written out here from the
+    published generator, independently of the oracle's C."""
+    M = 2**64 - 1
+    z = (seed + (i + 1) * 0x9E3779B97F4A7C15) & M
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+    z ^= z >> 31
+    return (z >> 11) * 2.0**-53
+
+
+@pytest.mark.parametrize("d,per,cell", [(1, 32, 12), (2, 16, 6), (3, 16, 6)])
+def test_calib_shell_is_interaction_list(d, per, cell):
+    """The calibration's Z2 boxes are the interaction list of a box in a
+    uniform tree: on a lattice with one point per finest box, the offsets
+    (in box sides) of an interior lower-corner box's interaction list equal
+    the oracle's table, in its order (dimension 0 fastest, ascending)."""
+    P = _lattice(per, d)
+    h = O.H2Oracle(P, leaf=1, structure_only=True)
+    C, S, depth = h.get("center"), h.get("side"), h.get("depth")
+    ptr, col = h.get("il_ptr"), h.get("il_col")
+    lo = C[0] - S[0] / 2
+    i = [t for t in range(len(S))
+         if depth[t] == depth.max() and np.all(np.rint((C[t] - lo) / S[t] - 0.5) == cell)]
+    assert len(i) == 1
+    i = i[0]
+    off = np.rint((C[col[ptr[i]:ptr[i + 1]]] - C[i]) / S[i]).astype(int)
+    key = lambda o: tuple(o[::-1])  # dimension 0 fastest
+    off = np.array(sorted(off.tolist(), key=key))
+    sh = O.calib_shell(d, 0.7)
+    assert sh.shape == off.shape and np.array_equal(sh, off)
+    assert len(sh) == {1: 3, 2: 39, 3: 567}[d]
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_calib_points_recipe(d):
+    """Z1 and Z2 are the recipe's SplitMix64 values: Z1 point i uniform in
+    [0, s)^d from values i d + a; Z2 point j in the box of the shell drawn by
+    value 512 d + j (d + 1), placed by the d values after it."""
+    seed, side = 0x5EED, 0.375
+    Z1, Z2 = O.calib_points(d, side, 0.7, seed)
+    sh = O.calib_shell(d, 0.7)
+    nb = len(sh)
+    for i in (0, 1, 200, 511):
+        assert np.array_equal(Z1[i], [side * _splitmix_u01(seed, i * d + a) for a in range(d)])
+    for j in (0, 7, 1000, 4095):
+        c = 512 * d + j * (d + 1)
+        b = min(int(_splitmix_u01(seed, c) * nb), nb - 1)
+        want = [side * (sh[b][a] + _splitmix_u01(seed, c + 1 + a)) for a in range(d)]
+        assert np.array_equal(Z2[j], want)
+    # every Z2 point lies in a box well separated from Z1's box [0, s)^d
+    cz = (np.floor(Z2 / side) + 0.5) * side
+    dist2 = ((cz - side / 2) ** 2).sum(axis=1)
+    assert np.all(d * (2 * side) ** 2 <= 4 * 0.49 * dist2)
+
+
+@pytest.mark.parametrize("kern,prm,d,side,eps", [("coulomb", 1.0, 3, 1.0, 1e-6),
+                                                  ("exponential", 0.2, 3, 0.125, 1e-6),
+                                                  ("gaussian", 0.1, 2, 0.0625, 1e-8),
+                                                  ("coulomb", 1.0, 1, 1.0, 1e-6)])
+def test_calibrate_one_is_first_r_meeting_target(kern, prm, d, side, eps):
+    """h2o_calibrate_one returns the first r = g^d whose ID, built on
+    DataReduct(Z2, r) at tolerance 1e-3 eps/2, approximates K(Z1, Z2) to a
+    relative Frobenius error below 1e-2 eps: the error of every candidate is
+    recomputed here with U = P [I; T^T] formed explicitly, the returned r
+    meets the target and the candidate before it does not."""
+    cap = {1: 64, 2: 484, 3: 512}[d]
+    r, err = O.calibrate_one(kern, prm, d, side, 0.7, eps, 0x5EED, cap)
+    Z1, Z2 = O.calib_points(d, side, 0.7, 0x5EED)
+    K = O.kernel_matrix(kern, prm, Z1, Z2)
+
+    def cand_err(rr):
+        ys = O.datareduct(Z2, np.arange(len(Z2)), rr)
+        k, piv, T, _ = O.cpqr_id(O.kernel_matrix(kern, prm, Z1, Z2[ys]), 1e-3 * eps / 2)
+        U = np.zeros((len(Z1), k))
+        U[piv[:k], np.arange(k)] = 1.0
+        U[piv[k:], :] = T.T
+        return np.linalg.norm(K - U @ K[piv[:k]]) / np.linalg.norm(K)
+
+    assert round(r ** (1.0 / d)) ** d == r
+    e = cand_err(r)
+    assert abs(e - err) <= 1e-6 * err + 1e-14  # summation order differs
+    assert e < 1e-2 * eps
+    g = round(r ** (1.0 / d))
+    if g > 1:
+        assert cand_err((g - 1) ** d) >= 1e-2 * eps
 
 
 # --------------------------------------------------------------- tree
@@ -433,16 +523,19 @@ def test_datareduct_nearest_by_kdtree(d, k):
 
 def test_datareduct_segments_closed_form():
     """Two segments, each containing the cell centres of the g^d grid over its
-    own bounding box: every lattice point of both is picked, the first
-    segment's grid first, even though the second lies far away."""
+    own bounding box (size bound 2 g^d: g^d grid points per segment): every
+    lattice point of both is picked, the first segment's grid first, even
+    though the second lies far away."""
     g, d = 3, 2
     lat = _lattice(g, d)
     A = np.vstack([lat, np.zeros((1, d)), np.ones((1, d))])
     B = A * 0.25 + 7.0
     P = np.vstack([A, B])
     idx = np.arange(len(P))
-    out = O.datareduct_seg(P, idx, [0, len(A), len(P)], g**d)
+    out = O.datareduct_seg(P, idx, [0, len(A), len(P)], 2 * g**d)
     assert len(out) == 2 * g**d
+    # the size bound is shared: one more than an odd share rounds down
+    assert len(O.datareduct_seg(P, idx, [0, len(A), len(P)], 2 * g**d + 1)) == 2 * g**d
     assert np.all(out[:g**d] < len(A)) and np.all(out[g**d:] >= len(A))
     np.testing.assert_array_equal(np.sort(P[out[:g**d]], axis=0), np.sort(lat, axis=0))
     # one segment reproduces the plain DataReduct
@@ -459,7 +552,7 @@ def test_datareduct_segments_nearest_over_whole_list():
     idx = rng.permutation(len(P))
     cut = 250
     seg = [0, cut, len(P)]
-    k = 27
+    k = 54  # 27 grid points per segment
     out = O.datareduct_seg(P, idx, seg, k)
     tree = cKDTree(P[idx])
     want = []
@@ -537,13 +630,14 @@ def _ancestors(parent, i):
 
 @pytest.mark.parametrize("d,n,q,r", [(2, 3000, 20, 16), (3, 4000, 30, 27)])
 def test_hidr_bounds_and_farfield(d, n, q, r):
-    """Theorem 3.1 bounds |X_i^*| <= r1, |Y_i^*| <= 2 r2 (one reference grid for
-    each of the two parts of T_i); X_i^* lies in X_i;
+    """Algorithm 1's maximum sizes |X_i^*| <= r1, |Y_i^*| <= r2 (a reference
+    grid of r2/2 points for each of the two parts of T_i); Theorem 3.1's
+    |S_i| <= 2^d r1; X_i^* lies in X_i;
     every point of Y_i^* lies in a node admissible to i or to an ancestor of
     i (it belongs to the farfield)."""
     rng = np.random.default_rng(20 + d)
     P = rng.random((n, d))
-    h = O.H2Oracle(P, "coulomb", 1.0, tol=1e-6, leaf=q, r1=r, r2=r)
+    h = O.H2Oracle(P, "coulomb", 1.0, tol=1e-6, leaf=q, r1=r, r2=2 * r)
     start, count, parent = h.get("start"), h.get("count"), h.get("parent")
     nch, fc = h.get("nchild"), h.get("first_child")
     ptr, col = h.get("il_ptr"), h.get("il_col")
@@ -555,7 +649,7 @@ def test_hidr_bounds_and_farfield(d, n, q, r):
     for i in range(1, len(start)):
         xs = h.node_list("xstar", i)
         ys = h.node_list("ystar", i)
-        assert len(xs) <= r and len(ys) <= 2 * r  # two reference grids for T_i
+        assert len(xs) <= r and len(ys) <= 2 * r  # r2 = 2 r: two grids of r points
         assert np.all((xs >= start[i]) & (xs < start[i] + count[i]))
         if nch[i] > 0:
             S = sum(len(h.node_list("xstar", c)) for c in range(fc[i], fc[i] + nch[i]))
@@ -572,7 +666,7 @@ def test_hidr_is_kernel_independent():
     """DataReduct never touches the kernel (Section 3.3): X^*, Y^* agree
     across kernels for fixed r1, r2."""
     P = np.random.default_rng(30).random((1500, 3))
-    hs = [O.H2Oracle(P, k, p, tol=1e-6, leaf=24, r1=27, r2=27)
+    hs = [O.H2Oracle(P, k, p, tol=1e-6, leaf=24, r1=27, r2=54)
           for k, p in (("coulomb", 1.0), ("gaussian", 0.3), ("matern32", 0.2))]
     for i in range(hs[0].info()["nnode"]):
         for name in ("xstar", "ystar"):
