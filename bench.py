@@ -68,11 +68,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--nrhs", type=int, default=32)
-    ap.add_argument("--r", type=int, default=0, help="r1 = r2 override (0: chosen from the tolerance)")
-    ap.add_argument("--r-min", type=int, default=343,
-                    help="floor on the r chosen from the tolerance (343 = 7^3 meets 1e-6 at n=2^20)")
+    ap.add_argument("--r", type=int, default=0, help="r1 = r, r2 = 2 r override (0: chosen from the tolerance)")
+    ap.add_argument("--r-min", type=int, default=0, help="floor on the r chosen from the tolerance (0: none)")
     ap.add_argument("--no-f32", action="store_true", help="skip the precision-mode (FP32 apply) measurement")
-    ap.add_argument("--rows", type=int, default=512, help="sampled rows for the dense accuracy check")
+    ap.add_argument("--rows", type=int, default=4096, help="sampled rows for the accuracy checks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=1 << 17, help="points of the oracle's bounded sample")
     ap.add_argument("--workload", choices=["cube1m", "batched", "serving", "sphere3", "variants", "large"],
@@ -185,7 +184,7 @@ def bench_sphere3(args):
     """The paper's kernel-scaling workload: n points on three unit spheres
     (centres on a triangle of side 1), the Table-1 kernels kappa_4 (bump,
     a = 0.1), kappa_2 (Gaussian, h = 1) and kappa_3 (cosine, a = 1; given
-    r1 = r2 = 128, as it has no calibration), leaf 128, tol 1e-6, 32 RHS.  A
+    r1 = 128, r2 = 256, as it has no calibration), leaf 128, tol 1e-6, 32 RHS.  A
     step is one build + one apply per kernel; value = points per second over
     the three kernels' steps."""
     import torch
@@ -205,7 +204,7 @@ def bench_sphere3(args):
     total = 0.0
     kernels = (("bump", 0.1, 0), ("gaussian", 1.0, 0), ("cosine", 1.0, 128))
     for kern, prm, r in kernels:
-        opt.r1 = opt.r2 = r
+        opt.r1, opt.r2 = r, 2 * r
         times = []
         for k in range(args.warmup + args.steps):
             torch.cuda.synchronize()
@@ -242,9 +241,10 @@ def bench_sphere3(args):
 
 def bench_variants(args):
     """The options of the build on the headline cube (n = 2^20, leaf 128,
-    tol 1e-6, r_min 343, 32 RHS): the volume DataReduct (reference), farthest
-    point sampling, the surface method, the strong rank-revealing swaps
-    (f = 1.05) and the non-symmetric advection kernel (a = 2, r1 = r2 = 343).
+    tol 1e-6, r1 and r2 from the tolerance, 32 RHS): the volume DataReduct
+    (reference), farthest point sampling, the surface method, the strong
+    rank-revealing swaps (f = 1.05) and the non-symmetric advection kernel
+    (a = 2, r1 = 343, r2 = 686).
     Per option one untimed build, then build + one apply timed; accuracy on
     sampled rows against the dense product."""
     import torch
@@ -265,7 +265,7 @@ def bench_variants(args):
     for name, kern, prm, dr, f, r in cases:
         opt = h2.h2_options_default()
         opt.r_min = args.r_min
-        opt.r1 = opt.r2 = r
+        opt.r1, opt.r2 = r, 2 * r
         opt.datareduct = h2.DATAREDUCT[dr]
         opt.srrqr_f = f
         for k in range(2):
@@ -290,7 +290,8 @@ def bench_variants(args):
 
 def bench_large(args):
     """Beyond the stored-block limit: n = 2^22 uniform points in [0,1]^3
-    (--n overrides), Coulomb, leaf 128, tol 1e-6, r_min 343, 32 RHS, with
+    (--n overrides), Coulomb, leaf 128, tol 1e-6, r1 and r2 from the
+    tolerance, 32 RHS, with
     the coupling blocks evaluated in the apply (store_coupling = 0; stored,
     they would take ~760 GB).  One untimed build + apply, then one timed;
     accuracy on sampled rows against the dense product."""
@@ -333,9 +334,21 @@ def bench_large(args):
         "max_rank": info["max_rank"], "bytes_D": info["bytes_D"], "e_dense_sampled_rows_max_rhs": e}), flush=True)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n, nrhs):
     """The oracle as it stands on a bounded sample: n points of the same
-    distribution, same kernel/leaf/tolerance; build + one apply with nrhs RHS."""
+    distribution, same kernel/leaf/tolerance, r1 and r2 from the tolerance
+    (the Coulomb kernel is scale invariant, so the oracle's calibration picks
+    the r of the full-size GPU line); build + one apply with nrhs RHS."""
     from oracle import oracle as O
     rng = np.random.default_rng(4004)
     P = rng.random((n, 3))
@@ -346,10 +359,30 @@ def cpu_baseline(n, nrhs):
     h.matvec(X)
     t2 = time.perf_counter()
     cores = O.max_threads()
+    oi = h.info()
     return {"value": n / (t2 - t0) / 1e6, "unit": "Mpts/s", "cores": cores, "kind": "oracle",
-            "sample": f"n={n} uniform [0,1]^3 Coulomb leaf 128 tol 1e-6: build {t1 - t0:.2f} s + "
+            "sample": f"n={n} uniform [0,1]^3 Coulomb leaf 128 tol 1e-6, r1={oi['r1']} r2={oi['r2']}, "
+                      f"{cores} OpenMP threads on {cpu_model()}: build {t1 - t0:.2f} s + "
                       f"matvec {nrhs} RHS {t2 - t1:.2f} s",
-            "build_s": t1 - t0, "matvec_s": t2 - t1}
+            "build_s": t1 - t0, "matvec_s": t2 - t1, "r1": oi["r1"], "r2": oi["r2"], "cpu_model": cpu_model()}
+
+
+def cube_1m_golden():
+    """The oracle's H^2 product and dense product of the headline workload on
+    its 4096 sampled rows (right-hand sides 0 and 1), as written by
+    tests/golden/make_cube_1m_golden.py; None if the file is absent."""
+    path = os.path.join(ROOT, "tests", "golden", "cube_1m_oracle.txt")
+    if not os.path.exists(path):
+        return None
+    rows, vals = [], []
+    for line in open(path):
+        t = line.split()
+        if not t or t[0].startswith("#") or t[0] in ("r1", "r2", "nnode", "maxdepth", "level", "rows"):
+            continue
+        rows.append(int(t[0]))
+        vals.append([float(v) for v in t[1:]])
+    v = np.array(vals)
+    return {"rows": np.array(rows), "y_h2": v[:, :2].T.copy(), "y_dense": v[:, 2:].T.copy()}
 
 
 def bench_serving(args):
@@ -457,18 +490,20 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    from paper_2206_01885_amd import workloads
     n, nrhs = args.n, args.nrhs
-    rng = np.random.default_rng(1004)
-    P_np = rng.random((n, 3))
-    X_np = rng.standard_normal((nrhs, n))
-    rows = np.sort(rng.choice(n, args.rows, replace=False))
-    P = torch.tensor(P_np, device=dev)
+    cfg = workloads.config_cube_1m(n=n, nrhs=max(nrhs, 2), nrows=min(args.rows, n))
+    rows = np.asarray(cfg["rows"])
+    gold = cube_1m_golden() if (n == 1 << 20 and nrhs >= 2 and args.rows == 4096) else None
+    if gold is not None and not np.array_equal(gold["rows"], rows):
+        gold = None
+    P = torch.tensor(cfg["points"], device=dev)
     Psoa = P.t().contiguous()
-    X = torch.tensor(X_np, device=dev)
+    X = torch.tensor(cfg["x"][:nrhs], device=dev)
     Y = torch.empty_like(X)
-    del P_np, X_np
+    del cfg
     opt = h2.h2_options_default()
-    opt.r1 = opt.r2 = args.r
+    opt.r1, opt.r2 = args.r, 2 * args.r
     opt.r_min = args.r_min
     opt.profile = 1
     print(f"[bench] inputs resident: n={n} nrhs={nrhs}", file=sys.stderr, flush=True)
@@ -517,6 +552,20 @@ def main():
     e_per_rhs = (got - ref).norm(dim=1) / ref.norm(dim=1)
     e_rows = e_per_rhs.max().item()
     e_rows_mean = e_per_rhs.mean().item()
+
+    def vs_golden(Yrows):
+        """Per right-hand side 0, 1: error against the oracle's FP64 H^2
+        product and against the oracle's dense product on the 4096 rows."""
+        if gold is None:
+            return None
+        y = Yrows[:2].double().cpu().numpy()
+        return {"e_vs_fp64_oracle_h2": [float(np.linalg.norm(y[r] - gold["y_h2"][r]) /
+                                              np.linalg.norm(gold["y_h2"][r])) for r in range(2)],
+                "e_vs_oracle_dense": [float(np.linalg.norm(y[r] - gold["y_dense"][r]) /
+                                            np.linalg.norm(gold["y_dense"][r])) for r in range(2)],
+                "rows": int(len(gold["rows"])), "rhs": [0, 1]}
+
+    acc_oracle = vs_golden(got)
 
     # coupling-sweep roofline: algorithmic bytes = B blocks + xhat reads + yhat writes
     coupling_bytes = info["bytes_B"] + 2 * 8 * info["sum_rank"] * nrhs
@@ -567,7 +616,7 @@ def main():
     otf = None
     if not args.no_f32:
         opt0 = h2.h2_options_default()
-        opt0.r1 = opt0.r2 = args.r
+        opt0.r1, opt0.r2 = args.r, 2 * args.r
         opt0.r_min = args.r_min
         opt0.store_coupling = 0
         opt0.profile = 1
@@ -600,7 +649,7 @@ def main():
     f32 = None
     if not args.no_f32:
         opt32 = h2.h2_options_default()
-        opt32.r1 = opt32.r2 = args.r
+        opt32.r1, opt32.r2 = args.r, 2 * args.r
         opt32.r_min = args.r_min
         opt32.precision = 32
         opt32.profile = 1
@@ -627,11 +676,13 @@ def main():
         got32 = Y32[:, ridx].double()
         e32 = ((got32 - ref).norm(dim=1) / ref.norm(dim=1)).max().item()
         e32_64 = ((got32 - Y64).norm(dim=1) / Y64.norm(dim=1)).max().item()
+        acc32_oracle = vs_golden(got32)
         f32 = {"ms_per_step": 1e3 * (np.mean(b32) + np.mean(m32)), "build_s": float(np.mean(b32)),
                "matvec_s": float(np.mean(m32)), "matvec_phases_ms": {k: i32[k] for k in (
                    "mv_gather", "mv_upward", "mv_coupling", "mv_downward", "mv_leaves", "mv_scatter")},
                "bytes_B": i32["bytes_B"], "bytes_D": i32["bytes_D"],
-               "e_dense_sampled_rows_max_rhs": e32, "e_vs_fp64_path_max_rhs": e32_64}
+               "e_dense_sampled_rows_max_rhs": e32, "e_vs_fp64_path_max_rhs": e32_64,
+               "vs_oracle": acc32_oracle}
         del Y32, X32
 
     out = {
@@ -655,7 +706,8 @@ def main():
         "structure": {k: info[k] for k in ("nnode", "maxdepth", "nnz_il", "nnz_near", "max_rank", "sum_rank",
                                             "bytes_U", "bytes_B", "bytes_D")},
         "accuracy": {"e_dense_sampled_rows_max_rhs": e_rows, "e_dense_sampled_rows_mean_rhs": e_rows_mean,
-                     "rows": int(args.rows)},
+                     "rows": int(len(rows)), "dense_reference": "torch FP64 on the GPU, all RHS",
+                     "vs_oracle": acc_oracle},
         "precision_f32": f32,
         "store_coupling_0": otf,
         "roofline": roof_dr,

@@ -70,12 +70,16 @@ typedef enum {
 
 /* Build options (h2_options_default fills the defaults).
  *   tau            separation ratio of Eq. (separation), 0 < tau < 1; default 0.7
- *   r1, r2         grid sizes of the volume DataReduct (Algorithm 1; X_i^* has
- *                  at most r1 points, Y_i^* at most 2 r2: one reference grid for
- *                  each of the two parts of its input list); 0 = choose them
- *                  from the tolerance (Section 4.2); > 0 = use as given (<= 2048)
- *   r_min          0, or a lower bound applied to r1 and r2 after they were
- *                  chosen from the tolerance
+ *   r1, r2         the maximum sizes of X_i^* and Y_i^* (Algorithm 1).  The
+ *                  volume DataReduct samples X_i^*'s list with a grid of at
+ *                  most r1 points and each of the two parts of Y_i^*'s list
+ *                  (Y_p^* and the interaction-list part) with a grid of at
+ *                  most r2/2 points.  0 = choose them from the tolerance
+ *                  (Section 4.2: r1 = r, r2 = 2 r); > 0 = use as given
+ *                  (r1 <= 2048, 2 <= r2 <= 4096)
+ *   r_min          0, or a lower bound applied to the calibrated r (so r1 >=
+ *                  r_min and r2 >= 2 r_min when they are chosen from the
+ *                  tolerance)
  *   precision      64: FP64 throughout; 32: the coupling and nearfield blocks,
  *                  the apply and its vectors in FP32 (FP32 products per block,
  *                  compensated accumulation of the block products, FP64
@@ -179,8 +183,14 @@ h2_status h2_build_batched(int nprob, const double *const *points, const int64_t
  * the handle is left unusable for h2_matvec (h2_destroy still works).     */
 h2_status h2_rebuild(h2_handle h, int kernel_id, const double *params, double tol);
 
-/* h2_matvec: y = Ktilde x with the H^2 representation (upward, coupling,
- * downward and nearfield sweeps).
+/* h2_matvec: y = Ktilde x, the product of the H^2 representation with x
+ * (Section 2.1: the O(n) apply of a matrix with nested bases -- upward pass
+ * through the column bases and transfer matrices, coupling blocks of the
+ * interaction lists, downward pass through the row bases, dense nearfield
+ * blocks; Section 6 measures the construction by this product's error
+ * ||K z - Ktilde z|| / ||z||).
+ *   h      a built handle (h2_build*, h2_rebuild); H2_EINVAL if NULL or not
+ *          ready (a failed h2_rebuild)
  *   x, y   device, [nrhs][n] (x[r*n + i] is entry i of right-hand side r),
  *          original point order; FP64 (double) for a handle built with
  *          precision 64, FP32 (float) for precision 32; must not overlap
@@ -189,6 +199,7 @@ h2_status h2_rebuild(h2_handle h, int kernel_id, const double *params, double to
  * except on the first call with a larger nrhs (workspace allocation).    */
 h2_status h2_matvec(h2_handle h, const void *x, void *y, int nrhs);
 h2_status h2_matvec_ex(h2_handle h, const void *x, void *y, int nrhs, void *hip_stream);
+
 
 /* Summary of a built representation (all host values). */
 typedef struct {

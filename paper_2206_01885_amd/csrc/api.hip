@@ -30,14 +30,6 @@ double now_s()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-template <class T>
-void upload_vec(h2::DBuf<T>& dst, const std::vector<T>& src, hipStream_t s)
-{
-    dst.ensure(src.size(), s);
-    if (!src.empty())
-        H2_HIP(hipMemcpyAsync(dst.p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    H2_HIP(hipStreamSynchronize(s));
-}
 
 
 // Worker streams of the batched build: created once, kept for the life of
@@ -65,8 +57,8 @@ h2_status check_and_init(h2::Handle& h, const double* points, int64_t n, int dim
     if (!(tol > 0.0 && tol < 1.0)) return set_err(H2_EINVAL, "tol must be in (0, 1)");
     if (leaf_size < 1) return set_err(H2_EINVAL, "leaf_size must be >= 1");
     if (!(opt.tau > 0.0 && opt.tau < 1.0)) return set_err(H2_EINVAL, "tau must be in (0, 1)");
-    if (opt.r1 < 0 || opt.r2 < 0 || opt.r1 > 2048 || opt.r2 > 2048)
-        return set_err(H2_EINVAL, "r1, r2 must be in [0, 2048]");
+    if (opt.r1 < 0 || opt.r1 > 2048) return set_err(H2_EINVAL, "r1 must be in [0, 2048]");
+    if (opt.r2 < 0 || opt.r2 == 1 || opt.r2 > 4096) return set_err(H2_EINVAL, "r2 must be 0 or in [2, 4096]");
     if (opt.precision != 64 && opt.precision != 32) return set_err(H2_EINVAL, "precision must be 64 or 32");
     if (opt.r_min < 0 || opt.r_min > 2048) return set_err(H2_EINVAL, "r_min must be in [0, 2048]");
     if (opt.datareduct < H2_DR_VOLUME || opt.datareduct > H2_DR_SURFACE)

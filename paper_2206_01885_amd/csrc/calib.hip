@@ -1,15 +1,22 @@
 // Choice of r1, r2 from the tolerance (Section 4.2; Algorithm 2 step 2).
 //
 // The paper grows r1 = r2 from 1 until the ID built on the reduced set
-// approximates an artificial well-separated block K(Z1, Z2) to better than
-// 1e-2 eps.  Readings (identical to the oracle's): r steps over g^d, g = 1,
-// 2, ..., capped at 512 (3-D), 484 (2-D) or 64 (1-D); Z1, Z2 hold 512
-// points each, uniform in cubes of side s whose centres lie s sqrt(d)/tau
-// apart along axis 0; coordinates are SplitMix64 values (Z1 first, then Z2,
-// coordinate fastest); the ID inside uses tolerance 1e-3 eps; the error is the
-// relative Frobenius norm of K(Z1,Z2) - U K(Zhat, Z2).  The scale-invariant
-// Coulomb kernel is calibrated once (s = 1); the others at the box side of
-// every depth holding interaction-list pairs, taking r = the maximum.
+// approximates an artificial block K(Z1, Z2) of well-separated point sets to
+// better than 1e-2 eps.  Readings (identical to the oracle's): r steps over
+// g^d, g = 1, 2, ..., capped at 512 (3-D), 484 (2-D) or 64 (1-D), and gives
+// r1 = r, r2 = 2 r (Y_i^* samples the two parts of T_i with r points each);
+// Z1 holds 512 points uniform in the box [0, s)^d; Z2 holds 4096 points, each
+// uniform in a box drawn uniformly from the interaction list of Z1's box in
+// the uniform tree of boxes of side s (the pair rule: admissible to the box,
+// parent cell floor(o/2) not admissible to the parent [0, 2s)^d; listed with
+// dimension 0 fastest, coordinates ascending); coordinates are SplitMix64
+// values: i d + a for Z1, 512 d + j (d + 1) for the box of Z2 point j and the
+// d values after it for its place in the box; the ID inside is built on
+// DataReduct(Z2, r) with tolerance 1e-3 eps' (eps' = eps/2); the error is the
+// relative Frobenius norm of K(Z1,Z2) - U K(Zhat, Z2) over all of Z2.  The
+// scale-invariant Coulomb kernel is calibrated once (s = 1); the others at
+// the box side of every depth holding interaction-list pairs, taking r = the
+// maximum.
 //
 // Every candidate round runs on the device: point generation, DataReduct,
 // the batched ID and the error reduction; all still-open depths of a round
@@ -24,7 +31,9 @@ namespace h2 {
 namespace {
 
 constexpr int TB = 256;
-constexpr int NZ = 512;
+constexpr int NZ = 512;    // Z1: the candidate rows of the ID
+constexpr int NZ2 = 4096;  // Z2: the farfield sample
+constexpr int NS = NZ + NZ2;
 
 __device__ inline double splitmix_u01(uint64_t seed, uint64_t i)
 {
@@ -35,24 +44,27 @@ __device__ inline double splitmix_u01(uint64_t seed, uint64_t i)
     return (double)(z >> 11) * 0x1.0p-53;
 }
 
-// Sets are laid out as [Z1 (512) | Z2 (512)] per set, SoA with ld = nset*1024.
-__global__ __launch_bounds__(TB) void k_points(int nset, const double* __restrict__ sides, int d, double tau,
-                                               uint64_t seed, double* __restrict__ Z)
+// Sets are laid out as [Z1 (512) | Z2 (4096)] per set, SoA with
+// ld = nset * NS; shell ([nb][d]) holds the cell offsets of Z2's boxes.
+__global__ __launch_bounds__(TB) void k_points(int nset, const double* __restrict__ sides, int d,
+                                               const int* __restrict__ shell, int nb, uint64_t seed,
+                                               double* __restrict__ Z)
 {
-    int64_t ld = (int64_t)nset * 2 * NZ;
-    int64_t q = (int64_t)blockIdx.x * TB + threadIdx.x;
+    const int64_t ld = (int64_t)nset * NS;
+    const int64_t q = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (q >= ld) return;
-    int set = (int)(q / (2 * NZ));
-    int w = (int)(q - (int64_t)set * 2 * NZ);
-    double s = sides[set];
-    double sep = s * sqrt((double)d) / tau;
-    bool second = w >= NZ;
-    int i = second ? w - NZ : w;
-    for (int a = 0; a < d; ++a) {
-        uint64_t ctr = (second ? (uint64_t)NZ * d : 0) + (uint64_t)i * d + a;
-        double u = splitmix_u01(seed, ctr);
-        Z[a * ld + q] = second ? s * (u - 0.5) + (a == 0 ? sep : 0.0) : s * (u - 0.5);
+    const int set = (int)(q / NS);
+    const int w = (int)(q - (int64_t)set * NS);
+    const double s = sides[set];
+    if (w < NZ) {
+        for (int a = 0; a < d; ++a) Z[a * ld + q] = s * splitmix_u01(seed, (uint64_t)w * d + a);
+        return;
     }
+    const uint64_t c = (uint64_t)NZ * d + (uint64_t)(w - NZ) * (d + 1);
+    int b = (int)(splitmix_u01(seed, c) * (double)nb);
+    if (b > nb - 1) b = nb - 1;
+    for (int a = 0; a < d; ++a)
+        Z[a * ld + q] = s * ((double)shell[b * d + a] + splitmix_u01(seed, c + 1 + a));
 }
 
 __global__ void k_lists(int nprob, const int* __restrict__ set_of, int64_t* __restrict__ zoff,
@@ -60,17 +72,15 @@ __global__ void k_lists(int nprob, const int* __restrict__ set_of, int64_t* __re
                         int* __restrict__ mm)
 {
     int p = blockIdx.x;
-    int base = set_of[p] * 2 * NZ;
-    for (int i = threadIdx.x; i < NZ; i += blockDim.x) {
-        z2idx[(int64_t)p * NZ + i] = base + NZ + i;
-        z1idx[(int64_t)p * NZ + i] = base + i;
-    }
+    int base = set_of[p] * NS;
+    for (int i = threadIdx.x; i < NZ2; i += blockDim.x) z2idx[(int64_t)p * NZ2 + i] = base + NZ + i;
+    for (int i = threadIdx.x; i < NZ; i += blockDim.x) z1idx[(int64_t)p * NZ + i] = base + i;
     if (threadIdx.x == 0) {
-        zoff[p] = (int64_t)p * NZ;
+        zoff[p] = (int64_t)p * NZ2;
         xoff[p] = (int64_t)p * NZ;
         mm[p] = NZ;
         if (p == nprob - 1) {
-            zoff[nprob] = (int64_t)nprob * NZ;
+            zoff[nprob] = (int64_t)nprob * NZ2;
             xoff[nprob] = (int64_t)nprob * NZ;
         }
     }
@@ -79,10 +89,10 @@ __global__ void k_lists(int nprob, const int* __restrict__ set_of, int64_t* __re
 // Squared Frobenius norms for the calibration error, spread over the grid:
 // workgroup (p, cb) owns 8 columns c of Z2; it stages K(Zhat, c) in LDS and
 // each lane forms rows u of K(Z1 rest, c) - T^T K(Zhat, c).  Partial sums go
-// to part[(p*64 + cb)*2 + {0,1}] (residual, full norm) and are reduced in a
+// to part[(p*ECB + cb)*2 + {0,1}] (residual, full norm) and are reduced in a
 // fixed order by k_err_final, so the result does not depend on scheduling.
 constexpr int ECOLS = 8;
-constexpr int ECB = NZ / ECOLS;
+constexpr int ECB = NZ2 / ECOLS;
 __global__ __launch_bounds__(TB) void k_err_part(const double* __restrict__ Z, int64_t ld, int d,
                                                  const int* __restrict__ set_kid, const double* __restrict__ set_prm,
                                                  const int* __restrict__ set_of,
@@ -93,7 +103,7 @@ __global__ __launch_bounds__(TB) void k_err_part(const double* __restrict__ Z, i
     __shared__ double ks[NZ * ECOLS];  // K(Zhat_t, c) for t < k <= 512
     __shared__ double red_r[TB], red_f[TB];
     const int p = blockIdx.x / ECB, cb = blockIdx.x % ECB;
-    const int base = set_of[p] * 2 * NZ;
+    const int base = set_of[p] * NS;
     const int kid = set_kid[set_of[p]];
     const double prm = set_prm[set_of[p]];
     const int k = rank[p], nr = NZ - k;
@@ -147,6 +157,38 @@ __global__ void k_err_final(int np, const double* __restrict__ part, double* __r
 
 static int r_cap(int d) { return d == 3 ? 512 : (d == 2 ? 484 : 64); }
 
+// Cell offsets of the interaction list of the box [0, 1)^d in the uniform
+// tree of unit boxes (pair rule, Eq. separation with box diagonals and
+// centres): cell o is admissible to the box and its parent cell floor(o/2)
+// (side 2) is not admissible to the box's parent [0, 2)^d.  Dimension 0
+// varies fastest, coordinates ascending.
+static std::vector<int> shell_cells(int d, double tau)
+{
+    const int R = (int)std::ceil(2.0 * std::sqrt((double)d) / tau) + 1;  // |o_a| < 2 sqrt(d)/tau + 1
+    const int w = 2 * R + 1;
+    int64_t tot = 1;
+    for (int a = 0; a < d; ++a) tot *= w;
+    std::vector<int> out;
+    for (int64_t t = 0; t < tot; ++t) {
+        int o[3];
+        int64_t rem = t;
+        double dc = 0.0, dp = 0.0;
+        for (int a = 0; a < d; ++a) {
+            o[a] = (int)(rem % w) - R;
+            rem /= w;
+            const int po = (o[a] >= 0) ? o[a] / 2 : -((1 - o[a]) / 2);  // floor(o/2)
+            const double ec = (double)o[a], ep = 2.0 * (double)po;    // centre offsets
+            dc = dc + ec * ec;
+            dp = dp + ep * ep;
+        }
+        const bool adm = (double)d * 4.0 <= 4.0 * tau * tau * dc;
+        const bool adm_parent = (double)d * 16.0 <= 4.0 * tau * tau * dp;
+        if (adm && !adm_parent)
+            for (int a = 0; a < d; ++a) out.push_back(o[a]);
+    }
+    return out;
+}
+
 // Calibration of a list of sets that share d, tau and the seed; set t has
 // kernel kid[t] with parameter prm[t], box side side[t] and tolerance eps[t].
 // Returns, per set, the first r = g^d whose error is below 1e-2 eps (or the
@@ -168,9 +210,14 @@ static void calibrate_sets(int d, double tau, uint64_t seed, const std::vector<d
     H2_HIP(hipMemcpyAsync(dsides.p, sides.data(), sizeof(double) * nset, hipMemcpyHostToDevice, s));
     H2_HIP(hipMemcpyAsync(dprm.p, prms.data(), sizeof(double) * nset, hipMemcpyHostToDevice, s));
     H2_HIP(hipMemcpyAsync(dkid.p, kids.data(), sizeof(int) * nset, hipMemcpyHostToDevice, s));
-    const int64_t ld = (int64_t)nset * 2 * NZ;
+    const int64_t ld = (int64_t)nset * NS;
     Z.ensure((size_t)d * ld, s);
-    k_points<<<blocks_for(ld, TB), TB, 0, s>>>(nset, dsides.p, d, tau, seed, Z.p);
+    const std::vector<int> shell = shell_cells(d, tau);
+    const int nb = (int)shell.size() / d;
+    if (nb < 1) fail(H2_EINTERNAL, "calibration: empty interaction list");
+    DBuf<int> dshell;
+    upload_vec(dshell, shell, s);
+    k_points<<<blocks_for(ld, TB), TB, 0, s>>>(nset, dsides.p, d, dshell.p, nb, seed, Z.p);
     H2_LAUNCH_CHECK();
     std::vector<int> open(nset, 1);
     DBuf<int> set_of, z2idx, z1idx, mm, ycnt, yidx, rank, piv, skel;
@@ -187,14 +234,14 @@ static void calibrate_sets(int d, double tau, uint64_t seed, const std::vector<d
         const int np = (int)sets.size();
         set_of.ensure(np, s);
         H2_HIP(hipMemcpyAsync(set_of.p, sets.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
-        z2idx.ensure((size_t)np * NZ, s);
+        z2idx.ensure((size_t)np * NZ2, s);
         z1idx.ensure((size_t)np * NZ, s);
         zoff.ensure((size_t)np + 1, s);
         xoff.ensure((size_t)np + 1, s);
         mm.ensure(np, s);
         k_lists<<<np, TB, 0, s>>>(np, set_of.p, zoff.p, z2idx.p, z1idx.p, xoff.p, mm.p);
         H2_LAUNCH_CHECK();
-        const int rs = std::min(r, NZ);  // |Y*| <= min(r, 512)
+        const int rs = r;  // |Y*| <= r <= the cap (512)
         ycnt.ensure(np, s);
         yidx.ensure((size_t)np * rs, s);
         datareduct_lists(Z.p, ld, d, zoff.p, z2idx.p, nullptr, np, r, yidx.p, rs, ycnt.p, s);
@@ -220,7 +267,7 @@ static void calibrate_sets(int d, double tau, uint64_t seed, const std::vector<d
             t.skel = skel.p + (int64_t)p * rs;
             t.rank = rank.p + p;
             t.prm = prms[sets[p]];
-            t.tol = 1e-3 * epss[sets[p]];
+            t.tol = 1e-3 * (0.5 * epss[sets[p]]);  // 1e-3 eps'
             t.m = NZ;
             t.s = ys_h[p];
             t.d = d;
@@ -289,7 +336,7 @@ void run_calibration_multi(const std::vector<Handle*>& hs, hipStream_t s)
             }
         }
         for (auto& x : ds) {
-            Key k{h.d, h.kid, h.tau, h.kid == H2_COULOMB ? 1.0 : h.prm, x.second, h.tol_int, h.calib_seed};
+            Key k{h.d, h.kid, h.tau, h.kid == H2_COULOMB ? 1.0 : h.prm, x.second, h.tol, h.calib_seed};
             auto it = uniq.find(k);
             int id;
             if (it == uniq.end()) {
@@ -348,8 +395,9 @@ void run_calibration_multi(const std::vector<Handle*>& hs, hipStream_t s)
                 h.calib_err[u.first] = res_err[u.second];
             }
         }
-        if (h.r1 <= 0) h.r1 = std::max(rmax, h.r_min);
-        if (h.r2 <= 0) h.r2 = std::max(rmax, h.r_min);
+        const int r = std::max(rmax, h.r_min);
+        if (h.r1 <= 0) h.r1 = r;
+        if (h.r2 <= 0) h.r2 = 2 * r;
     }
 }
 

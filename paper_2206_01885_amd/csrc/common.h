@@ -116,6 +116,17 @@ inline std::vector<T> read_vec(const T* dptr, size_t cnt, hipStream_t s)
     return v;
 }
 
+// Host vector -> device buffer (resized as needed); synchronises s, so the
+// host vector may go out of scope on return.
+template <class T>
+inline void upload_vec(DBuf<T>& dst, const std::vector<T>& src, hipStream_t s)
+{
+    dst.ensure(src.size(), s);
+    if (!src.empty())
+        H2_HIP(hipMemcpyAsync(dst.p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    H2_HIP(hipStreamSynchronize(s));
+}
+
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // ------------------------------------------------------------------ scan (scan.hip)
@@ -181,7 +192,7 @@ struct Handle {
 
     // HiDR representor sets, fixed stride per node
     DBuf<int> xs_cnt, xs_idx;  // stride r1
-    DBuf<int> ys_cnt, ys_idx;  // stride ys_stride = 2*r2 (two reference grids)
+    DBuf<int> ys_cnt, ys_idx;  // stride ys_stride = r2 (the maximum size of Y_i^*)
     int ys_stride = 0;
     std::vector<int> calib_r;
     std::vector<double> calib_err;

@@ -2,7 +2,8 @@
 // volume-based DataReduct of Section 3.3, on the device; the surface-based
 // method and farthest point sampling of the same section as options.
 //
-// DataReduct(X, k) reading (identical to the oracle's):
+// DataReduct(X, k) reading (identical to the oracle's), k the maximum size
+// of X* (Algorithm 1's r1 for X_i^*, r2 for Y_i^*):
 //   |X| <= k            -> X unchanged;
 //   otherwise           -> Q = cell centres of the g^d tensor grid over the
 //                          bounding box of X (g the largest integer with
@@ -10,10 +11,11 @@
 //                          point of X at the smallest squared distance, ties to
 //                          the earliest position in X; X* = the distinct picks
 //                          in grid order of first occurrence.
-// A list may come in parts; the reference set then holds one such grid per
-// non-empty part (over that part's bounding box), each reference point taking
-// its nearest point of the whole list.  The farfield list T_i of HiDR has two
-// parts (Y_p^* and the interaction-list representors).
+// A list may come in two parts; the reference set then holds one such grid
+// per non-empty part (over that part's bounding box, g^d <= k/2), each
+// reference point taking its nearest point of the whole list, so |X*| <= k.
+// The farfield list T_i of HiDR has two parts (Y_p^* and the
+// interaction-list representors).
 // One workgroup reduces one list.  Each lane owns up to QPT reference points
 // and scans the list in LDS tiles of 256 points in list order, so the strict
 // `<` keeps the earliest position.  Duplicated picks are removed with a
@@ -36,7 +38,7 @@ namespace h2 {
 namespace {
 
 constexpr int TB = 256;
-constexpr int MAXQ_ALL = 4096;  // largest reference set: two grids of r <= 2048
+constexpr int MAXQ_ALL = 4096;  // largest reference set: r2 <= 4096 (two grids of r2/2)
 
 __device__ inline double block_min(double v, double* sh)
 {
@@ -67,7 +69,7 @@ __device__ inline double block_max(double v, double* sh)
 // set: per part, with box [lo, hi], widths w = hi - lo and centre
 // c = lo + 0.5 w, the points c + (gamma w) u_j on the ellipsoids gamma = 0.3,
 // 0.6, 1.2 for the mdir unit directions u_j of `dirs` ([mdir][d]), in the
-// order gamma, then j, the first k of them.
+// order gamma, then j, the first kp of them (kp = the part's share of k).
 template <int MAXQ>
 __global__ __launch_bounds__(TB) void k_datareduct(const double* __restrict__ pts, int64_t ld, int d,
                                                    const int64_t* __restrict__ list_off,
@@ -119,16 +121,17 @@ __global__ __launch_bounds__(TB) void k_datareduct(const double* __restrict__ pt
             hi[sg][a] = block_max(mx, red);
         }
     const bool surf = method == H2_DR_SURFACE;
+    const int kp = split ? max(1, k / 2) : k;  // grid budget of one part
     int g = 1;
     for (;;) {
         long long nx = 1;
         for (int a = 0; a < d; ++a) nx *= (long long)(g + 1);
-        if (nx > k) break;
+        if (nx > kp) break;
         ++g;
     }
     int nq1 = 1;
     for (int a = 0; a < d; ++a) nq1 *= g;
-    if (surf) nq1 = min(k, 3 * mdir);
+    if (surf) nq1 = min(kp, 3 * mdir);
     const int nq = nq1 * nseg;
 
     // grid points owned by this lane: t = threadIdx.x + u*TB, in reference-set
@@ -660,11 +663,12 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
         ++nseg;
     }
     __syncthreads();
+    const int kp = max(1, k / 2);  // grid budget of each part of T_i
     int g = 1;
     for (;;) {
         long long nx = 1;
         for (int a = 0; a < d; ++a) nx *= (long long)(g + 1);
-        if (nx > k) break;
+        if (nx > kp) break;
         ++g;
     }
     int nq1 = 1;
@@ -942,7 +946,7 @@ __global__ __launch_bounds__(TB) void k_up_fill(int lo, const int* __restrict__ 
 template <int D>
 void launch_down_d(Handle& h, int lo, int nl, const double* xs_pts, hipStream_t s)
 {
-    if (h.r2 <= 512)
+    if (h.r2 <= 1024)
         k_datareduct_down<D, 1024><<<nl, TB, 0, s>>>(lo, h.pts.p, h.n, h.parent.p, h.il_ptr.p, h.il_col.p,
                                                      h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, xs_pts, h.r1,
                                                      h.ys_cnt.p, h.ys_idx.p, h.ys_stride, h.r2);
@@ -966,7 +970,7 @@ void launch_down(Handle& h, int lo, int nl, const double* xs_pts, hipStream_t s)
 // most ILCAP entries; 0 for the others), and the squared distances the
 // definition of DataReduct evaluates for them (every reference point against
 // every candidate: |T_i| times gd points per non-empty part when |T_i| > k),
-// for the profile.
+// for the profile; gd is the grid size of one part.
 __global__ __launch_bounds__(TB) void k_down_len(int nn, const int* __restrict__ parent, const int* __restrict__ il_ptr,
                                                  const int* __restrict__ il_col, const int* __restrict__ xs_cnt,
                                                  const int* __restrict__ ys_cnt, int k, int gd,
@@ -1040,7 +1044,7 @@ void datareduct_lists_method(int method, const double* pts, int64_t ld, int d, c
                              int* out_cnt, hipStream_t s)
 {
     if (nlist <= 0) return;
-    if (k < 1 || k > MAXQ_ALL / 2) fail(H2_EUNSUPPORTED, "DataReduct size must be in [1, 2048]");
+    if (k < 1 || k > MAXQ_ALL) fail(H2_EUNSUPPORTED, "DataReduct size must be in [1, 4096]");
     if (method == H2_DR_FPS) {
         const int64_t tot = read_scalar(list_off + nlist, s);
         if (tot > (int64_t)INT32_MAX) fail(H2_EUNSUPPORTED, "lists longer than 2^31 entries");
@@ -1059,14 +1063,15 @@ void datareduct_lists_method(int method, const double* pts, int64_t ld, int d, c
     DBuf<double> dirs;
     int mdir = 0;
     if (method == H2_DR_SURFACE) {
-        mdir = std::max(1, k / 3);
+        const int kp = split ? std::max(1, k / 2) : k;
+        mdir = std::max(1, kp / 3);
         if (d == 1) mdir = std::min(mdir, 2);
         std::vector<double> u;
         surface_dirs(d, mdir, u);
         dirs.ensure(u.size(), s);
         H2_HIP(hipMemcpyAsync(dirs.p, u.data(), u.size() * sizeof(double), hipMemcpyHostToDevice, s));
     }
-    if (k <= 512)
+    if (k <= 1024)
         k_datareduct<1024><<<nlist, TB, 0, s>>>(pts, ld, d, list_off, list_idx, split, k, out, out_stride, out_cnt,
                                                 method, dirs.p, mdir);
     else
@@ -1083,7 +1088,7 @@ void run_hidr(Handle& h)
     h.xs_cnt.ensure((size_t)nn, s);
     h.ys_cnt.ensure((size_t)nn, s);
     h.xs_idx.ensure((size_t)nn * h.r1, s);
-    h.ys_stride = 2 * h.r2;
+    h.ys_stride = h.r2;
     h.ys_idx.ensure((size_t)nn * h.ys_stride, s);
     H2_HIP(hipMemsetAsync(h.xs_cnt.p, 0, sizeof(int) * nn, s));
     H2_HIP(hipMemsetAsync(h.ys_cnt.p, 0, sizeof(int) * nn, s));
@@ -1105,7 +1110,7 @@ void run_hidr(Handle& h)
         datareduct_lists_method(h.dr, h.pts.p, h.n, h.d, off.p, list.p, nullptr, nl, h.r1,
                                 h.xs_idx.p + (int64_t)lo * h.r1, h.r1, h.xs_cnt.p + lo, s);
     }
-    if (h.r2 < 1 || h.r2 > MAXQ_ALL / 2) fail(H2_EUNSUPPORTED, "r2 must be in [1, 2048]");
+    if (h.r2 < 2 || h.r2 > MAXQ_ALL) fail(H2_EUNSUPPORTED, "r2 must be in [2, 4096]");
     DBuf<double> xs_pts;
     xs_pts.ensure((size_t)nn * h.d * h.r1, s);
     k_xs_coords<<<nn, TB, 0, s>>>(h.pts.p, h.n, h.d, h.xs_cnt.p, h.xs_idx.p, h.r1, xs_pts.p);
@@ -1158,7 +1163,7 @@ void run_hidr(Handle& h)
         for (;;) {
             long long nx = 1;
             for (int a = 0; a < h.d; ++a) nx *= g + 1;
-            if (nx > h.r2) break;
+            if (nx > h.r2 / 2) break;
             ++g;
         }
         int gd = 1;
