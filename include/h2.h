@@ -200,6 +200,20 @@ h2_status h2_rebuild(h2_handle h, int kernel_id, const double *params, double to
 h2_status h2_matvec(h2_handle h, const void *x, void *y, int nrhs);
 h2_status h2_matvec_ex(h2_handle h, const void *x, void *y, int nrhs, void *hip_stream);
 
+/* h2_matvec_noalloc: h2_matvec_ex for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, same kernels and the same result bit
+ * for bit, but the apply's work vectors -- x and y in tree order and the
+ * node coefficients, (2 n + sum of ranks of both bases) * ceil(nrhs/32)*32
+ * values -- live in one array of H2_NOALLOC_SCRATCH_BYTES per GPU, which the
+ * library holds until the process ends; the call allocates nothing and
+ * records no profile events.  H2_EUNSUPPORTED if the work vectors do not
+ * fit (the message gives the bytes needed).  Every call on one GPU uses that
+ * GPU's array: calls that overlap on one GPU (other streams, other threads,
+ * other handles) race and must be ordered by the caller.  The device must be
+ * the handle's and current.                                              */
+#define H2_NOALLOC_SCRATCH_BYTES ((int64_t)1 << 28)
+h2_status h2_matvec_noalloc(h2_handle h, const void *x, void *y, int nrhs, void *hip_stream);
 
 /* Summary of a built representation (all host values). */
 typedef struct {

@@ -137,6 +137,8 @@ void build_back(h2::Handle& h)
         upload_vec(b->xh_off, xo, h.stream);
     }
     h2::prepare_apply(h);
+    // marks the end of the last apply (h2_destroy and h2_rebuild wait for it)
+    if (!h.mv_done) H2_HIP(hipEventCreateWithFlags(&h.mv_done, hipEventDisableTiming));
     h.t_blocks = t6 - t5;
 }
 
@@ -343,17 +345,42 @@ h2_status h2_matvec(h2_handle hd, const void* x, void* y, int nrhs)
     return h2_matvec_ex(hd, x, y, nrhs, hd ? (void*)hd->h.stream : nullptr);
 }
 
-h2_status h2_matvec_ex(h2_handle hd, const void* x, void* y, int nrhs, void* hip_stream)
+// Checks shared by the apply entry points.
+static h2_status check_apply(h2_handle hd, const void* x, const void* y, int nrhs)
 {
     if (!hd) return set_err(H2_EINVAL, "handle is NULL");
     if (!x || !y) return set_err(H2_EINVAL, "x or y is NULL");
     if (!hd->h.ready) return set_err(H2_EINVAL, "the handle holds no representation (a rebuild failed)");
     if (nrhs < 1 || nrhs > 256) return set_err(H2_EINVAL, "nrhs must be in [1, 256]");
-    h2::Handle& h = hd->h;
+    const h2::Handle& h = hd->h;
     const size_t bytes = (size_t)h.n * nrhs * (h.precision == 32 ? sizeof(float) : sizeof(double));
     const char* xb = (const char*)x;
     const char* yb = (const char*)y;
     if (!(xb + bytes <= yb || yb + bytes <= xb)) return set_err(H2_EINVAL, "x and y overlap");
+    return H2_OK;
+}
+
+h2_status h2_matvec_noalloc(h2_handle hd, const void* x, void* y, int nrhs, void* hip_stream)
+{
+    const h2_status st = check_apply(hd, x, y, nrhs);
+    if (st != H2_OK) return st;
+    h2::Handle& h = hd->h;
+    try {
+        hipStream_t ms = (hipStream_t)hip_stream;
+        h2::matvec_noalloc(h, x, y, nrhs, ms);
+        // created with the handle, so recording allocates nothing
+        if (h.mv_done) H2_HIP(hipEventRecord(h.mv_done, ms));
+    } catch (const h2::Error& e) {
+        return set_err(e.code, e.msg);
+    }
+    return H2_OK;
+}
+
+h2_status h2_matvec_ex(h2_handle hd, const void* x, void* y, int nrhs, void* hip_stream)
+{
+    const h2_status st = check_apply(hd, x, y, nrhs);
+    if (st != H2_OK) return st;
+    h2::Handle& h = hd->h;
     try {
         hipStream_t ms = (hipStream_t)hip_stream;
         h2::matvec(h, x, y, nrhs, ms);

@@ -273,6 +273,9 @@ void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s);  // basis
 void build_blocks(Handle& h);                                     // blocks.hip
 void prepare_apply(Handle& h);                                   // matvec.hip
 void matvec(Handle& h, const void* x, void* y, int nrhs, hipStream_t s);  // matvec.hip
+// The same apply on the library's per-device scratch array (no allocation;
+// H2_EUNSUPPORTED when the work vectors exceed H2_NOALLOC_SCRATCH_BYTES).
+void matvec_noalloc(Handle& h, const void* x, void* y, int nrhs, hipStream_t s);  // matvec.hip
 
 // DataReduct over materialised index lists (hidr.hip); used by HiDR and by
 // the calibration.  For each of `nlist` lists (indices into the SoA point

@@ -20,6 +20,9 @@
 //   leaves    y_t(X_i) = U_i yhat_i + sum_{j in near(i)} D_ij x_t(X_j)
 //   scatter   y[perm] = y_t
 // Every output element has exactly one writer; there are no atomics.
+#include <mutex>
+#include <string>
+
 #include "common.h"
 #include "kappa.h"
 
@@ -494,30 +497,30 @@ struct ApplyBufs<float> {
     static const float* Tm(const Basis& b) { return b.Tf.p; }
 };
 
+// The apply's work vectors: x and y in tree order ([n][ld]) and the node
+// coefficients xhat ([sum of column ranks][ld]) and yhat ([sum of row
+// ranks][ld]).
 template <class T>
-void matvec_t(Handle& h, const T* x, T* y, int nrhs, hipStream_t s)
+struct ApplyWork {
+    T *xt, *yt, *xh, *yh;
+};
+
+// One apply y = Ktilde x on work vectors w (column stride ld); prof: record
+// the sweeps' events (creates them on first use).
+template <class T>
+void apply_t(Handle& h, const T* x, T* y, int nrhs, int ld, const ApplyWork<T>& w, bool prof, hipStream_t s)
 {
     typedef ApplyBufs<T> AB;
     const int64_t n = h.n;
-    const int ld = (nrhs + 31) / 32 * 32;
-    if (ld > h.mv_ld) {
-        H2_HIP(hipStreamSynchronize(s));
-        AB::xt(h).ensure((size_t)n * ld, s);
-        AB::yt(h).ensure((size_t)n * ld, s);
-        AB::xh(h).ensure((size_t)std::max<int64_t>(h.col().sum_rank, 1) * ld, s);
-        AB::yh(h).ensure((size_t)std::max<int64_t>(h.bu.sum_rank, 1) * ld, s);
-        h.mv_ld = ld;
-    }
-    T* xt = AB::xt(h).p;
-    T* yt = AB::yt(h).p;
-    T* xh = AB::xh(h).p;
-    T* yh = AB::yh(h).p;
+    T* xt = w.xt;
+    T* yt = w.yt;
+    T* xh = w.xh;
+    T* yh = w.yh;
     // upward through V, W (the column basis), downward through U, R
     const Basis& bv = h.col();
     const T* Tm = AB::Tm(h.bu);
     const T* Tv = AB::Tm(bv);
     const T* zero = (const T*)h.zeros.p;
-    const bool prof = h.profile != 0;
     auto mark = [&](int e) {
         if (prof) H2_HIP(hipEventRecord(h.ev[e], s));
     };
@@ -583,6 +586,73 @@ void matvec_t(Handle& h, const T* x, T* y, int nrhs, hipStream_t s)
         h.prof_valid = true;
         h.prof_nrhs = nrhs;
     }
+}
+
+// The apply with the handle's work vectors, grown (after synchronising s) when
+// nrhs needs a wider column stride than any earlier apply.
+template <class T>
+void matvec_t(Handle& h, const T* x, T* y, int nrhs, hipStream_t s)
+{
+    typedef ApplyBufs<T> AB;
+    const int64_t n = h.n;
+    const int ld = (nrhs + 31) / 32 * 32;
+    if (ld > h.mv_ld) {
+        H2_HIP(hipStreamSynchronize(s));
+        AB::xt(h).ensure((size_t)n * ld, s);
+        AB::yt(h).ensure((size_t)n * ld, s);
+        AB::xh(h).ensure((size_t)std::max<int64_t>(h.col().sum_rank, 1) * ld, s);
+        AB::yh(h).ensure((size_t)std::max<int64_t>(h.bu.sum_rank, 1) * ld, s);
+        h.mv_ld = ld;
+    }
+    apply_t<T>(h, x, y, nrhs, ld, ApplyWork<T>{AB::xt(h).p, AB::yt(h).p, AB::xh(h).p, AB::yh(h).p}, h.profile != 0,
+               s);
+}
+
+// Work vectors of the apply that allocates nothing: one array per device,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in; kernels get the device address from hipGetSymbolAddress.
+constexpr int64_t SCRATCH_BYTES = H2_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+unsigned char* scratch_on_current_device()
+{
+    constexpr int MAXDEV = 64;
+    static std::mutex mu;
+    static unsigned char* ptr[MAXDEV] = {};
+    int dev = 0;
+    H2_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAXDEV) fail(H2_EDEVICE, "device index beyond the no-allocation apply's table");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            fail(H2_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        ptr[dev] = (unsigned char*)p;
+    }
+    return ptr[dev];
+}
+
+// The apply on work vectors carved from `scratch` (each start rounded up to
+// 256 bytes); no allocation, no events.
+template <class T>
+void matvec_noalloc_t(Handle& h, const T* x, T* y, int nrhs, hipStream_t s)
+{
+    const int ld = (nrhs + 31) / 32 * 32;
+    auto bytes = [](int64_t elems) { return (elems * (int64_t)sizeof(T) + 255) / 256 * 256; };
+    const int64_t bx = bytes(h.n * ld);
+    const int64_t bv = bytes(std::max<int64_t>(h.col().sum_rank, 1) * ld);
+    const int64_t bu = bytes(std::max<int64_t>(h.bu.sum_rank, 1) * ld);
+    const int64_t need = 2 * bx + bv + bu;
+    if (need > SCRATCH_BYTES)
+        fail(H2_EUNSUPPORTED, "h2_matvec_noalloc: this handle and nrhs need " + std::to_string(need) +
+                                  " bytes of work vectors, more than its " + std::to_string(SCRATCH_BYTES) +
+                                  "-byte scratch array");
+    unsigned char* base = scratch_on_current_device();
+    const ApplyWork<T> w{(T*)base, (T*)(base + bx), (T*)(base + 2 * bx), (T*)(base + 2 * bx + bv)};
+    apply_t<T>(h, x, y, nrhs, ld, w, false, s);
 }
 
 }  // namespace
@@ -678,6 +748,14 @@ void matvec(Handle& h, const void* x, void* y, int nrhs, hipStream_t s)
         matvec_t<float>(h, (const float*)x, (float*)y, nrhs, s);
     else
         matvec_t<double>(h, (const double*)x, (double*)y, nrhs, s);
+}
+
+void matvec_noalloc(Handle& h, const void* x, void* y, int nrhs, hipStream_t s)
+{
+    if (h.precision == 32)
+        matvec_noalloc_t<float>(h, (const float*)x, (float*)y, nrhs, s);
+    else
+        matvec_noalloc_t<double>(h, (const double*)x, (double*)y, nrhs, s);
 }
 
 }  // namespace h2

@@ -62,7 +62,7 @@ class h2_info(C.Structure):
 
 
 SYMBOLS = ["h2_options_default", "h2_build", "h2_build_ex", "h2_build_batched", "h2_rebuild", "h2_matvec",
-           "h2_matvec_ex", "h2_query", "h2_export", "h2_destroy", "h2_last_error"]
+           "h2_matvec_ex", "h2_matvec_noalloc", "h2_query", "h2_export", "h2_destroy", "h2_last_error"]
 
 _lib = None
 
@@ -92,6 +92,8 @@ def lib():
         L.h2_matvec.argtypes = [vp, vp, vp, C.c_int]
         L.h2_matvec_ex.restype = C.c_int
         L.h2_matvec_ex.argtypes = [vp, vp, vp, C.c_int, vp]
+        L.h2_matvec_noalloc.restype = C.c_int
+        L.h2_matvec_noalloc.argtypes = [vp, vp, vp, C.c_int, vp]
         L.h2_query.restype = C.c_int
         L.h2_query.argtypes = [vp, C.POINTER(h2_info)]
         L.h2_export.restype = C.c_int
@@ -166,6 +168,13 @@ def h2_matvec(handle, x: torch.Tensor, y: torch.Tensor, nrhs: int, stream=None):
     (precision 64) or float32 (precision 32)."""
     _check(lib().h2_matvec_ex(handle, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), int(nrhs),
                               _stream_ptr(stream)))
+
+
+def h2_matvec_noalloc(handle, x: torch.Tensor, y: torch.Tensor, nrhs: int, stream=None):
+    """C ABI h2_matvec_noalloc: as h2_matvec, on the library's per-device
+    scratch array (no allocation)."""
+    _check(lib().h2_matvec_noalloc(handle, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), int(nrhs),
+                                   _stream_ptr(stream)))
 
 
 def h2_query(handle) -> dict:

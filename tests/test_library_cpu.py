@@ -70,6 +70,7 @@ def test_validation_without_device_work():
     opt.store_coupling, opt.precision = 0, 32  # the apply's own coupling evaluation is FP64 only
     assert L.h2_build_ex(dummy, 10, 3, 0, prm, 1e-6, 64, C.byref(opt), None, C.byref(out)) == h2.H2_EUNSUPPORTED
     assert L.h2_matvec(None, dummy, dummy, 1) == h2.H2_EINVAL
+    assert L.h2_matvec_noalloc(None, dummy, dummy, 1, None) == h2.H2_EINVAL
     # r2 is the maximum size of Y_i^*: 1 cannot hold the two parts' grids
     opt = h2.h2_options_default()
     opt.r1, opt.r2 = 8, 1
