@@ -18,9 +18,10 @@
 // the box side of every depth holding interaction-list pairs, taking r = the
 // maximum.
 //
-// Every candidate round runs on the device: point generation, DataReduct,
-// the batched ID and the error reduction; all still-open depths of a round
-// share one launch of each.
+// Every step runs on the device: point generation, DataReduct, the batched
+// ID and the error reduction, for every candidate r of every set at once (one
+// launch of each, one read-back); each set then takes its first candidate
+// below the target, which is what trying them in turn would give.
 #include <map>
 #include <tuple>
 
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(TB) void k_err_part(const double* __restrict__ Z, i
                                                  const int* __restrict__ set_kid, const double* __restrict__ set_prm,
                                                  const int* __restrict__ set_of,
                                                  const int* __restrict__ rank, const int* __restrict__ piv,
-                                                 const double* __restrict__ T, int64_t T_stride,
+                                                 const double* __restrict__ T, const int64_t* __restrict__ T_off,
                                                  double* __restrict__ part)
 {
     __shared__ double ks[NZ * ECOLS];  // K(Zhat_t, c) for t < k <= 512
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(TB) void k_err_part(const double* __restrict__ Z, i
     const double prm = set_prm[set_of[p]];
     const int k = rank[p], nr = NZ - k;
     const int* pv = piv + (int64_t)p * NZ;
-    const double* Tp = T + (int64_t)p * T_stride;
+    const double* Tp = T + T_off[p];
     const int cl = threadIdx.x % ECOLS, ul = threadIdx.x / ECOLS;  // 8 columns x 32 row lanes
     const int c = cb * ECOLS + cl;
     for (int t = ul; t < k; t += TB / ECOLS)
@@ -219,80 +220,89 @@ static void calibrate_sets(int d, double tau, uint64_t seed, const std::vector<d
     upload_vec(dshell, shell, s);
     k_points<<<blocks_for(ld, TB), TB, 0, s>>>(nset, dsides.p, d, dshell.p, nb, seed, Z.p);
     H2_LAUNCH_CHECK();
-    std::vector<int> open(nset, 1);
-    DBuf<int> set_of, z2idx, z1idx, mm, ycnt, yidx, rank, piv, skel;
-    DBuf<int64_t> zoff, xoff;
-    DBuf<double> M, nu, T, err, part;
+    // every candidate r = g^d (g = 1, 2, ... up to the cap) of every set in
+    // one round: task p is (set, g); the result of a set is its first
+    // candidate below the target, as if the candidates were tried in turn
+    std::vector<int> rs_of;  // candidate sizes
     for (int g = 1;; ++g) {
         long long rr = 1;
         for (int a = 0; a < d; ++a) rr *= g;
-        const int r = rr > cap ? cap : (int)rr;
-        std::vector<int> sets;
-        for (int t = 0; t < nset; ++t)
-            if (open[t]) sets.push_back(t);
-        if (sets.empty()) break;
-        const int np = (int)sets.size();
-        set_of.ensure(np, s);
-        H2_HIP(hipMemcpyAsync(set_of.p, sets.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
-        z2idx.ensure((size_t)np * NZ2, s);
-        z1idx.ensure((size_t)np * NZ, s);
-        zoff.ensure((size_t)np + 1, s);
-        xoff.ensure((size_t)np + 1, s);
-        mm.ensure(np, s);
-        k_lists<<<np, TB, 0, s>>>(np, set_of.p, zoff.p, z2idx.p, z1idx.p, xoff.p, mm.p);
-        H2_LAUNCH_CHECK();
-        const int rs = r;  // |Y*| <= r <= the cap (512)
-        ycnt.ensure(np, s);
-        yidx.ensure((size_t)np * rs, s);
-        datareduct_lists(Z.p, ld, d, zoff.p, z2idx.p, nullptr, np, r, yidx.p, rs, ycnt.p, s);
-        M.ensure((size_t)np * rs * NZ, s);
-        nu.ensure((size_t)np * 3 * NZ, s);
-        T.ensure((size_t)np * rs * NZ, s);
-        rank.ensure(np, s);
-        piv.ensure((size_t)np * NZ, s);
-        skel.ensure((size_t)np * rs, s);
-        err.ensure(np, s);
-        std::vector<int> ys_h = read_vec(ycnt.p, np, s);
-        std::vector<IdTask> tasks(np);
-        for (int p = 0; p < np; ++p) {
-            IdTask& t = tasks[p];
-            t.pts = Z.p;
-            t.ld = ld;
-            t.x_idx = z1idx.p + (int64_t)p * NZ;
-            t.y_idx = yidx.p + (int64_t)p * rs;
-            t.M = M.p + (int64_t)p * rs * NZ;
-            t.nu = nu.p + (int64_t)p * 3 * NZ;
-            t.piv = piv.p + (int64_t)p * NZ;
-            t.T = T.p + (int64_t)p * rs * NZ;
-            t.skel = skel.p + (int64_t)p * rs;
-            t.rank = rank.p + p;
-            t.prm = prms[sets[p]];
-            t.tol = 1e-3 * (0.5 * epss[sets[p]]);  // 1e-3 eps'
-            t.m = NZ;
-            t.s = ys_h[p];
-            t.d = d;
-            t.kid = kids[sets[p]];
+        rs_of.push_back(rr > cap ? cap : (int)rr);
+        if (rr >= cap) break;
+    }
+    const int ng = (int)rs_of.size();
+    const int np = nset * ng;
+    std::vector<int> sets(np);
+    std::vector<int64_t> y_off(np + 1, 0), mt_off(np + 1, 0);
+    for (int g = 0; g < ng; ++g)
+        for (int t = 0; t < nset; ++t) {
+            const int p = g * nset + t;  // tasks grouped by candidate size
+            sets[p] = t;
+            y_off[p + 1] = y_off[p] + rs_of[g];
+            mt_off[p + 1] = mt_off[p] + (int64_t)rs_of[g] * NZ;
         }
-        batched_id(tasks, s);
-        part.ensure((size_t)np * ECB * 2, s);
-        k_err_part<<<np * ECB, TB, 0, s>>>(Z.p, ld, d, dkid.p, dprm.p, set_of.p, rank.p, piv.p, T.p,
-                                           (int64_t)rs * NZ, part.p);
-        H2_LAUNCH_CHECK();
-        k_err_final<<<blocks_for(np, 64), 64, 0, s>>>(np, part.p, err.p);
-        H2_LAUNCH_CHECK();
-        std::vector<double> e = read_vec(err.p, np, s);
-        for (int p = 0; p < np; ++p) {
-            int t = sets[p];
-            if (e[p] < 1e-2 * epss[t]) {
-                result[t] = r;
-                result_err[t] = e[p];
-                open[t] = 0;
-            } else if (r >= cap) {
-                result[t] = cap;
-                result_err[t] = e[p];
-                open[t] = 0;
+    DBuf<int> set_of, z2idx, z1idx, mm, ycnt, yidx, rank, piv, skel;
+    DBuf<int64_t> zoff, xoff, d_mt_off;
+    DBuf<double> M, nu, T, err, part;
+    upload_vec(set_of, sets, s);
+    upload_vec(d_mt_off, mt_off, s);
+    z2idx.ensure((size_t)np * NZ2, s);
+    z1idx.ensure((size_t)np * NZ, s);
+    zoff.ensure((size_t)np + 1, s);
+    xoff.ensure((size_t)np + 1, s);
+    mm.ensure(np, s);
+    k_lists<<<np, TB, 0, s>>>(np, set_of.p, zoff.p, z2idx.p, z1idx.p, xoff.p, mm.p);
+    H2_LAUNCH_CHECK();
+    ycnt.ensure(np, s);
+    yidx.ensure((size_t)y_off[np], s);
+    for (int g = 0; g < ng; ++g)  // |Y*| <= r <= the cap (512)
+        datareduct_lists(Z.p, ld, d, zoff.p + (int64_t)g * nset, z2idx.p, nullptr, nset, rs_of[g],
+                         yidx.p + y_off[(size_t)g * nset], rs_of[g], ycnt.p + (int64_t)g * nset, s);
+    M.ensure((size_t)mt_off[np], s);
+    nu.ensure((size_t)np * 3 * NZ, s);
+    T.ensure((size_t)mt_off[np], s);
+    rank.ensure(np, s);
+    piv.ensure((size_t)np * NZ, s);
+    skel.ensure((size_t)y_off[np], s);
+    err.ensure(np, s);
+    std::vector<int> ys_h = read_vec(ycnt.p, np, s);
+    std::vector<IdTask> tasks(np);
+    for (int p = 0; p < np; ++p) {
+        IdTask& t = tasks[p];
+        t.pts = Z.p;
+        t.ld = ld;
+        t.x_idx = z1idx.p + (int64_t)p * NZ;
+        t.y_idx = yidx.p + y_off[p];
+        t.M = M.p + mt_off[p];
+        t.nu = nu.p + (int64_t)p * 3 * NZ;
+        t.piv = piv.p + (int64_t)p * NZ;
+        t.T = T.p + mt_off[p];
+        t.skel = skel.p + y_off[p];
+        t.rank = rank.p + p;
+        t.prm = prms[sets[p]];
+        t.tol = 1e-3 * (0.5 * epss[sets[p]]);  // 1e-3 eps'
+        t.m = NZ;
+        t.s = ys_h[p];
+        t.d = d;
+        t.kid = kids[sets[p]];
+    }
+    batched_id(tasks, s);
+    part.ensure((size_t)np * ECB * 2, s);
+    k_err_part<<<np * ECB, TB, 0, s>>>(Z.p, ld, d, dkid.p, dprm.p, set_of.p, rank.p, piv.p, T.p, d_mt_off.p,
+                                       part.p);
+    H2_LAUNCH_CHECK();
+    k_err_final<<<blocks_for(np, 64), 64, 0, s>>>(np, part.p, err.p);
+    H2_LAUNCH_CHECK();
+    const std::vector<double> e = read_vec(err.p, np, s);
+    for (int t = 0; t < nset; ++t) {
+        result[t] = cap;
+        result_err[t] = e[(size_t)(ng - 1) * nset + t];
+        for (int g = 0; g < ng; ++g)
+            if (e[(size_t)g * nset + t] < 1e-2 * epss[t]) {
+                result[t] = rs_of[g];
+                result_err[t] = e[(size_t)g * nset + t];
+                break;
             }
-        }
     }
 }
 
