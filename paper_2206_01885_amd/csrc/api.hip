@@ -1,6 +1,7 @@
 // C ABI (include/h2.h): argument checks, the build pipeline of Algorithm 2
 // (tree -> lists -> r1/r2 -> HiDR -> nested bases -> coupling/near blocks),
 // the apply, queries and exports.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -521,12 +522,31 @@ h2_status h2_export(h2_handle hd, int what, int node, void* host_buf, size_t byt
             if (node < 0 || node >= h.nil) return set_err(H2_EINVAL, "IL entry out of range");
             if (h.precision != 64) return set_err(H2_EUNSUPPORTED, "B export needs precision 64");
             if (h.store_coupling == 0) return set_err(H2_EUNSUPPORTED, "coupling blocks are not stored");
-            int64_t o[2];
-            H2_HIP(hipMemcpy(o, h.B_off.p + node, 2 * sizeof(int64_t), hipMemcpyDeviceToHost));
-            cnt = o[1] - o[0];
-            src = h.B.p + o[0];
-            esz = 8;
-            break;
+            // B_ij of entry e = (i, j), rank_i x rank_j column-major; an entry
+            // j < i of a symmetric kernel reads the stored B_ji transposed
+            const int i = (int)(std::upper_bound(h.h_il_ptr.begin(), h.h_il_ptr.end(), (int)node) -
+                                h.h_il_ptr.begin()) - 1;
+            int j = 0;
+            int64_t o = 0;
+            H2_HIP(hipMemcpy(&j, h.il_col.p + node, sizeof(int), hipMemcpyDeviceToHost));
+            H2_HIP(hipMemcpy(&o, h.B_off.p + node, sizeof(int64_t), hipMemcpyDeviceToHost));
+            const int ki = h.bu.h_rank[i], kj = h.col().h_rank[j];
+            cnt = (int64_t)ki * kj;
+            if (count) *count = cnt;
+            if (!host_buf) return H2_OK;
+            if (bytes < (size_t)cnt * 8) return set_err(H2_EINVAL, "buffer too small");
+            if (cnt == 0) return H2_OK;
+            H2_HIP(hipStreamSynchronize(s));
+            std::vector<double> blk((size_t)cnt);
+            H2_HIP(hipMemcpy(blk.data(), h.B.p + o, (size_t)cnt * 8, hipMemcpyDeviceToHost));
+            double* outp = (double*)host_buf;
+            if (h.B_upper && j < i) {
+                for (int u = 0; u < kj; ++u)
+                    for (int t = 0; t < ki; ++t) outp[(size_t)u * ki + t] = blk[(size_t)t * kj + u];
+            } else {
+                std::memcpy(outp, blk.data(), (size_t)cnt * 8);
+            }
+            return H2_OK;
         }
         case H2_EXP_CALIB_R:
             cnt = (int64_t)h.calib_r.size();

@@ -4,9 +4,12 @@
 // the row and column skeletons coincide for a symmetric kernel.
 // Blocks are stored column-major (rank_i x rank_j, resp. count_i x count_j)
 // in CSR order of the lists; offsets come from a device scan over the block
-// sizes.  One workgroup per list row i.  These entries feed only the apply,
-// so they use the fast kernel evaluation (an ulp or two from the correctly
-// rounded form that the ID uses).
+// sizes.  For a symmetric kernel (V = U, so B_ji = B_ij^T) only the blocks of
+// the entries with j > i are stored -- the interaction lists are symmetric,
+// so every unordered pair once -- and the offset of an entry with j < i
+// points at the stored B_ji, which the apply reads transposed.  These
+// entries feed only the apply, so they use the fast kernel evaluation (an ulp
+// or two from the correctly rounded form that the ID uses).
 #include "common.h"
 #include "kappa.h"
 
@@ -15,14 +18,55 @@ namespace {
 
 constexpr int TB = 256;
 
+// Block sizes per list entry; with `upper` set only the entries with j > i
+// get a block (the others 0).
 __global__ __launch_bounds__(TB) void k_block_sizes(int nrow, const int* __restrict__ ptr, const int* __restrict__ col,
                                                     const int* __restrict__ sz_row, const int* __restrict__ sz_col,
-                                                    int64_t* __restrict__ out)
+                                                    int upper, int64_t* __restrict__ out)
 {
     int i = blockIdx.x * TB + threadIdx.x;
     if (i >= nrow) return;
     int64_t a = sz_row[i];
-    for (int e = ptr[i]; e < ptr[i + 1]; ++e) out[e] = a * sz_col[col[e]];
+    for (int e = ptr[i]; e < ptr[i + 1]; ++e) out[e] = (upper && col[e] < i) ? 0 : a * sz_col[col[e]];
+}
+
+// First entry of every row with column > i (rows sorted ascending; an
+// interaction list never holds i itself).
+__global__ __launch_bounds__(TB) void k_row_split(int nrow, const int* __restrict__ ptr, const int* __restrict__ col,
+                                                  int* __restrict__ split)
+{
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= nrow) return;
+    int lo = ptr[i], hi = ptr[i + 1];
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (col[mid] < i)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    split[i] = lo;
+}
+
+// Entries (i, j) with j < i take the offset of the stored block of (j, i),
+// found by a binary search in row j's upper part.
+__global__ __launch_bounds__(TB) void k_lower_offsets(int nrow, const int* __restrict__ ptr, const int* __restrict__ col,
+                                                      const int* __restrict__ split, int64_t* __restrict__ off)
+{
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= nrow) return;
+    for (int e = ptr[i]; e < split[i]; ++e) {
+        const int j = col[e];
+        int lo = split[j], hi = ptr[j + 1] - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (col[mid] < i)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        off[e] = off[lo];
+    }
 }
 
 // Skeleton coordinates gathered into node order (SoA [d][sum k]) so that a
@@ -66,13 +110,14 @@ struct PtSet {
 template <class OutT, int FAM>
 __global__ __launch_bounds__(TB) void k_blocks_eval(int64_t nent, const int* __restrict__ erow,
                                                     const int* __restrict__ col, PtSet rs, PtSet cs, int d, int kid,
-                                                    double prm, const int64_t* __restrict__ off,
+                                                    double prm, const int64_t* __restrict__ off, int upper,
                                                     OutT* __restrict__ out)
 {
     const int64_t e = (int64_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6);
     if (e >= nent) return;
     const int lane = threadIdx.x & 63;
     const int i = erow[e], j = col[e];
+    if (upper && j < i) return;  // stored with the entry (j, i)
     const int ki = rs.cnt[i], kj = cs.cnt[j];
     if (ki == 0 || kj == 0) return;
     OutT* o = out + off[e];
@@ -132,17 +177,18 @@ __global__ __launch_bounds__(TB) void k_blocks_eval(int64_t nent, const int* __r
 // Each kernel family's blocks come from their own instance (see kappa_fam).
 template <class OutT>
 void launch_blocks_eval(int64_t nent, const int* erow, const int* col, const PtSet& rs, const PtSet& cs, int d,
-                        int kid, double prm, const int64_t* off, OutT* out, hipStream_t s)
+                        int kid, double prm, const int64_t* off, int upper, OutT* out, hipStream_t s)
 {
     const unsigned nb = (unsigned)blocks_for(nent, TB / 64);
     switch (kernel_family(kid)) {
     case FAM_COSINE:
-        k_blocks_eval<OutT, FAM_COSINE><<<nb, TB, 0, s>>>(nent, erow, col, rs, cs, d, kid, prm, off, out);
+        k_blocks_eval<OutT, FAM_COSINE><<<nb, TB, 0, s>>>(nent, erow, col, rs, cs, d, kid, prm, off, upper, out);
         break;
     case FAM_ADVECTION:
-        k_blocks_eval<OutT, FAM_ADVECTION><<<nb, TB, 0, s>>>(nent, erow, col, rs, cs, d, kid, prm, off, out);
+        k_blocks_eval<OutT, FAM_ADVECTION><<<nb, TB, 0, s>>>(nent, erow, col, rs, cs, d, kid, prm, off, upper, out);
         break;
-    default: k_blocks_eval<OutT, FAM_RADIAL><<<nb, TB, 0, s>>>(nent, erow, col, rs, cs, d, kid, prm, off, out);
+    default:
+        k_blocks_eval<OutT, FAM_RADIAL><<<nb, TB, 0, s>>>(nent, erow, col, rs, cs, d, kid, prm, off, upper, out);
     }
     H2_LAUNCH_CHECK();
 }
@@ -155,7 +201,7 @@ void near_blocks(Handle& h, DBuf<int64_t>& sz, DBuf<int>& erow)
     const int nn = h.nnode;
     const bool f32 = h.precision == 32;
     // the leaves' points are contiguous in tree order
-    k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.nr_ptr.p, h.nr_col.p, h.count.p, h.count.p, sz.p);
+    k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.nr_ptr.p, h.nr_col.p, h.count.p, h.count.p, 0, sz.p);
     H2_LAUNCH_CHECK();
     scan_excl_i64(sz.p, h.D_off.p, h.nnear, h.tmp_i64, s);
     int64_t nD = read_scalar(h.D_off.p + h.nnear, s);
@@ -176,9 +222,9 @@ void near_blocks(Handle& h, DBuf<int64_t>& sz, DBuf<int>& erow)
         H2_LAUNCH_CHECK();
         const PtSet ps{h.pts.p, h.n, d_st.p, h.count.p};
         if (f32)
-            launch_blocks_eval(h.nnear, erow.p, h.nr_col.p, ps, ps, h.d, h.kid, h.prm, h.D_off.p, h.Df.p, s);
+            launch_blocks_eval(h.nnear, erow.p, h.nr_col.p, ps, ps, h.d, h.kid, h.prm, h.D_off.p, 0, h.Df.p, s);
         else
-            launch_blocks_eval(h.nnear, erow.p, h.nr_col.p, ps, ps, h.d, h.kid, h.prm, h.D_off.p, h.D.p, s);
+            launch_blocks_eval(h.nnear, erow.p, h.nr_col.p, ps, ps, h.d, h.kid, h.prm, h.D_off.p, 0, h.D.p, s);
         H2_HIP(hipStreamSynchronize(s));
     }
     H2_HIP(hipStreamSynchronize(s));
@@ -190,6 +236,7 @@ void build_blocks(Handle& h)
 {
     hipStream_t s = h.stream;
     const int nn = h.nnode;
+    h.B_upper = false;
     h.B_off.ensure((size_t)h.nil + 1, s);
     h.D_off.ensure((size_t)h.nnear + 1, s);
     DBuf<int64_t> sz;
@@ -235,11 +282,22 @@ void build_blocks(Handle& h)
         near_blocks(h, sz, erow);
         return;
     }
-    // coupling
-    k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, h.il_col.p, h.bu.rank.p, h.col().rank.p, sz.p);
+    // coupling: for a symmetric kernel the blocks of the entries j > i only
+    const int upper = h.nonsym ? 0 : 1;
+    h.B_upper = upper != 0;
+    h.il_split.ensure((size_t)std::max(nn, 1), s);
+    k_row_split<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, h.il_col.p, h.il_split.p);
+    H2_LAUNCH_CHECK();
+    k_block_sizes<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, h.il_col.p, h.bu.rank.p, h.col().rank.p, upper,
+                                                    sz.p);
     H2_LAUNCH_CHECK();
     scan_excl_i64(sz.p, h.B_off.p, h.nil, h.tmp_i64, s);
     int64_t nB = read_scalar(h.B_off.p + h.nil, s);
+    if (upper) {
+        k_lower_offsets<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, h.il_col.p, h.il_split.p, h.B_off.p);
+        H2_LAUNCH_CHECK();
+    }
+    h.h_il_split = read_vec(h.il_split.p, (size_t)nn, s);
     const bool f32 = h.precision == 32;
     // BLK_PAD zeros after the last block (read by row tiles of the apply
     // that run past a block's last row)
@@ -255,9 +313,9 @@ void build_blocks(Handle& h)
         k_entry_rows<<<blocks_for(nn, TB), TB, 0, s>>>(nn, h.il_ptr.p, erow.p);
         H2_LAUNCH_CHECK();
         if (f32)
-            launch_blocks_eval(h.nil, erow.p, h.il_col.p, rs, cs, h.d, h.kid, h.prm, h.B_off.p, h.Bf.p, s);
+            launch_blocks_eval(h.nil, erow.p, h.il_col.p, rs, cs, h.d, h.kid, h.prm, h.B_off.p, upper, h.Bf.p, s);
         else
-            launch_blocks_eval(h.nil, erow.p, h.il_col.p, rs, cs, h.d, h.kid, h.prm, h.B_off.p, h.B.p, s);
+            launch_blocks_eval(h.nil, erow.p, h.il_col.p, rs, cs, h.d, h.kid, h.prm, h.B_off.p, upper, h.B.p, s);
     }
     near_blocks(h, sz, erow);
 }

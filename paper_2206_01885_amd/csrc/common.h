@@ -206,6 +206,12 @@ struct Handle {
 
     // coupling and nearfield blocks
     DBuf<int64_t> B_off;  // per IL entry (CSR order), size nil+1
+    // B_upper (symmetric kernel): blocks stored for the entries j > i only;
+    // B_off of an entry j < i points at the stored B_ji (read transposed).
+    // il_split[i]: first entry of row i with column > i.
+    bool B_upper = false;
+    DBuf<int> il_split;
+    std::vector<int> h_il_split;
     DBuf<double> B;
     DBuf<int64_t> D_off;  // per near entry, size nnear+1
     DBuf<double> D;
@@ -231,6 +237,7 @@ struct Handle {
         DBuf<int> steps;    // per node: sum over its entries of max(1, ceil(columns / 4))
     };
     Sweep cp, nr;
+    Sweep cpt;  // B_upper: the transposed (j < i) coupling entries
     DBuf<double> zeros;     // 64 zeros, read by masked lanes of the sweeps
     DBuf<int64_t> start64;  // start[] widened, row offsets of the leaves in x_t / y_t
 

@@ -122,6 +122,7 @@ __global__ __launch_bounds__(TB) void k_upward(int lo, int nrhs, int ld, const i
 // blocks together are one rows_i x (sum of columns) column-major matrix and
 // the sweep over a row is one long K loop.
 //
+// Row i's entries are [ptr_b[i], ptr_e[i]).
 // One wavefront per task (node i, rows r0 .. r0 + 16 MT - 1, 32 columns of
 // X per pass): MT 16-row tiles x 2 16-column tiles of 16x16x4 matrix-core
 // steps, four columns of the row matrix (four rows of X) per step.  The
@@ -142,7 +143,8 @@ __global__ __launch_bounds__(TB) void k_upward(int lo, int nrhs, int ld, const i
 // sum with Kahan compensation (precision mode).
 template <int MT, class T, bool COMP, int P>
 __global__ __launch_bounds__(64) void k_sweep(int ntask, const int* __restrict__ task_node,
-                                              const int* __restrict__ task_r0, const int* __restrict__ ptr,
+                                              const int* __restrict__ task_r0, const int* __restrict__ ptr_b,
+                                              const int* __restrict__ ptr_e,
                                               const int* __restrict__ ek, const int64_t* __restrict__ ex,
                                               const int* __restrict__ nsteps, const int* __restrict__ krow,
                                               const int64_t* __restrict__ blk_off, const T* __restrict__ blk,
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(64) void k_sweep(int ntask, const int* __restrict__
     const int i = task_node[task], r0 = task_r0[task];
     const int ki = krow[i];
     const int lane = threadIdx.x, q = lane & 15, g = lane >> 4;
-    const int e0 = ptr[i], e1 = ptr[i + 1];
+    const int e0 = ptr_b[i], e1 = ptr_e[i];
     const int S = nsteps[i];
     const int SP = (S + P - 1) / P * P;
     // lane bases: column g of the row matrix at row r0 + MT q; row g of X
@@ -360,6 +362,187 @@ __global__ __launch_bounds__(64) void k_coupling_otf(int ntask, const int* __res
     }
 }
 
+// Transposed coupling sweep of a symmetric kernel's stored blocks:
+// Y[rows of i] += sum_{e in [ptr_b[i], ptr_e[i])} B_e^T X[rows of j_e],
+// where B_e (blk + blk_off[e]) is the stored k_j x k_i block B_ji,
+// column-major with leading dimension k_j, so row a of B_ij = B_ji^T is its
+// column a, k_j contiguous values.  Same task and tile layout as k_sweep
+// (lane (q, g), rows r0 + MT q + mt, columns 2q + nt of a 32-column pass),
+// but the K loop goes 16 columns of B_ij at a time: lane group g takes
+// columns 16 b + 4 g .. 16 b + 4 g + 3, one vector load per row tile, and the
+// four matrix-core steps of the block pair them with X rows 16 b + 4 g + t
+// (t = 0..3) -- a reordering of the sum over the block's columns.  X rows
+// past k_j read zeros, so the A values loaded past a column's end (the next
+// column's first entries, or the zero padding after the last block) add
+// nothing; rows past k_i read zeros.  Loads run P blocks ahead through a
+// register ring, across entries.  COMP: Kahan accumulation of the block
+// products, as in k_sweep.
+template <int MT, class T, bool COMP, int P>
+__global__ __launch_bounds__(64) void k_sweep_t(int ntask, const int* __restrict__ task_node,
+                                                const int* __restrict__ task_r0, const int* __restrict__ ptr_b,
+                                                const int* __restrict__ ptr_e, const int* __restrict__ ek,
+                                                const int64_t* __restrict__ ex, const int* __restrict__ nblk,
+                                                const int* __restrict__ krow, const int64_t* __restrict__ blk_off,
+                                                const T* __restrict__ blk, const T* __restrict__ X,
+                                                const int64_t* __restrict__ out_off, T* __restrict__ Y, int nchunk,
+                                                int ld, const T* __restrict__ zero)
+{
+    typedef typename Mfma<T>::V V;
+    const int per = (ntask + 7) / 8;
+    const int task = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (task >= ntask) return;
+    const int i = task_node[task], r0 = task_r0[task];
+    const int ki = krow[i];
+    const int lane = threadIdx.x, q = lane & 15, g = lane >> 4;
+    const int e0 = ptr_b[i], e1 = ptr_e[i];
+    const int S = nblk[i];
+    const int SP = (S + P - 1) / P * P;
+    bool rv[MT];  // rows of this lane inside the block
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) rv[mt] = r0 + MT * q + mt < ki;
+    for (int c = 0; c < nchunk; ++c) {
+        const T* baseX = X + 32 * c + 2 * q;
+        V acc[MT][2], cmp[MT][2], bacc[MT][2];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                acc[mt][nt] = (V){0, 0, 0, 0};
+                cmp[mt][nt] = (V){0, 0, 0, 0};
+                bacc[mt][nt] = (V){0, 0, 0, 0};
+            }
+        // loader state (wave-uniform): entry le, first column lu of the next
+        // 16-column block, the entry's columns lk, first input row lx and
+        // block offset lo; nk, nx, no: the same for entry le + 1 (read one
+        // entry ahead); an entry without columns takes one all-zero block
+        int le = e0, lu = 0, lk = 0, nk = 0;
+        int64_t lx = 0, lo = 0, nx = 0, no = 0;
+        if (e0 < e1) {
+            lk = ek[e0];
+            lx = ex[e0];
+            lo = blk_off[e0];
+        }
+        if (e0 + 1 < e1) {
+            nk = ek[e0 + 1];
+            nx = ex[e0 + 1];
+            no = blk_off[e0 + 1];
+        }
+        Vec<T, 4> av[P][MT];
+        Vec<T, 2> xv[P][4];
+        bool last[P];
+        auto load = [&](Vec<T, 4>* a, Vec<T, 2>* x, bool& lst) {
+            const int k0 = lu + 4 * g;
+            const bool kv = le < e1 && k0 < lk;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const T* pa = blk + lo + (int64_t)(r0 + MT * q + mt) * lk + k0;
+                a[mt] = vload<T, 4>(kv && rv[mt] ? pa : zero);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const T* px = baseX + (lx + k0 + t) * ld;
+                x[t] = vload<T, 2>(le < e1 && k0 + t < lk ? px : zero);
+            }
+            lu += 16;
+            lst = le < e1 && lu >= lk;
+            if (lst) {
+                lu = 0;
+                ++le;
+                lk = nk;
+                lx = nx;
+                lo = no;
+                if (le + 1 < e1) {
+                    nk = ek[le + 1];
+                    nx = ex[le + 1];
+                    no = blk_off[le + 1];
+                } else {
+                    nk = 0;
+                }
+            }
+        };
+#pragma unroll
+        for (int p = 0; p < P; ++p) load(av[p], xv[p], last[p]);
+        for (int s0 = 0; s0 < SP; s0 += P) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int nt = 0; nt < 2; ++nt) {
+                            if (COMP)
+                                bacc[mt][nt] = Mfma<T>::step(av[p][mt].v[t], xv[p][t].v[nt], bacc[mt][nt]);
+                            else
+                                acc[mt][nt] = Mfma<T>::step(av[p][mt].v[t], xv[p][t].v[nt], acc[mt][nt]);
+                        }
+                const bool lst = last[p];
+                load(av[p], xv[p], last[p]);
+                if (COMP && lst) {
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int nt = 0; nt < 2; ++nt) {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                T yk = bacc[mt][nt][r] - cmp[mt][nt][r];
+                                T tk = acc[mt][nt][r] + yk;
+                                cmp[mt][nt][r] = (tk - acc[mt][nt][r]) - yk;
+                                acc[mt][nt][r] = tk;
+                            }
+                            bacc[mt][nt] = (V){0, 0, 0, 0};
+                        }
+                }
+            }
+        }
+        // added to the rows the upper sweep wrote
+        T* Yi = Y + out_off[i] * ld + 32 * c + 2 * q;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + MT * Mfma<T>::row(r, g) + mt;
+                if (row < ki) {
+                    T* dst = Yi + (int64_t)row * ld;
+                    Vec<T, 2> v = vload<T, 2>(dst);
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt) v.v[nt] += COMP ? acc[mt][nt][r] - cmp[mt][nt][r] : acc[mt][nt][r];
+                    __builtin_memcpy(dst, &v, sizeof(v));
+                }
+            }
+    }
+}
+
+// Per-entry metadata of a list (columns, first input row), for every entry.
+__global__ __launch_bounds__(TB) void k_entry_meta(int nrow, const int* __restrict__ ptr, const int* __restrict__ col,
+                                                   const int* __restrict__ kcol, const int64_t* __restrict__ in_off,
+                                                   int* __restrict__ ek, int64_t* __restrict__ ex)
+{
+    const int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= nrow) return;
+    for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+        const int j = col[e];
+        ek[e] = kcol[j];
+        ex[e] = in_off[j];
+    }
+}
+
+// Per-node counts of the K-loop units over entries [ptr_b[i], ptr_e[i]):
+// units of `width` columns, at least one per entry.
+__global__ __launch_bounds__(TB) void k_range_units(int nrow, const int* __restrict__ ptr_b,
+                                                    const int* __restrict__ ptr_e, const int* __restrict__ ek, int width,
+                                                    int* __restrict__ units)
+{
+    const int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= nrow) return;
+    int st = 0;
+    for (int e = ptr_b[i]; e < ptr_e[i]; ++e) {
+        const int k = ek[e];
+        st += k > 0 ? (k + width - 1) / width : 1;
+    }
+    units[i] = st;
+}
+
 // Per-entry metadata of a list (columns, first input row) and per-node
 // step counts of the sweep (an entry without columns takes one step).
 __global__ __launch_bounds__(TB) void k_sweep_meta(int nrow, const int* __restrict__ ptr, const int* __restrict__ col,
@@ -451,27 +634,57 @@ __global__ __launch_bounds__(TB) void k_to_f32(const double* __restrict__ a, int
 }
 
 template <int MT, class T, bool COMP>
-void launch_sweep_mt(const Handle::Sweep& w, const int* ptr, const int* krow, const int64_t* blk_off, const T* blk,
-                     const T* X, const int64_t* out_off, T* Y, int ld, int accumulate, const T* zero, hipStream_t s)
+void launch_sweep_mt(const Handle::Sweep& w, const int* ptr_b, const int* ptr_e, const int* krow,
+                     const int64_t* blk_off, const T* blk, const T* X, const int64_t* out_off, T* Y, int ld,
+                     int accumulate, const T* zero, hipStream_t s)
 {
     const int nt = w.n[MT - 1];
     if (nt == 0) return;
     constexpr int P = MT <= 2 ? 4 : 3;
     const unsigned grid = (unsigned)(8 * ((nt + 7) / 8));
-    k_sweep<MT, T, COMP, P><<<grid, 64, 0, s>>>(nt, w.node[MT - 1].p, w.r0[MT - 1].p, ptr, w.ek.p, w.ex.p,
+    k_sweep<MT, T, COMP, P><<<grid, 64, 0, s>>>(nt, w.node[MT - 1].p, w.r0[MT - 1].p, ptr_b, ptr_e, w.ek.p, w.ex.p,
                                                 w.steps.p, krow, blk_off, blk, X, out_off, Y, ld / 32, ld,
                                                 accumulate, zero);
     H2_LAUNCH_CHECK();
 }
 
+// Row i's entries are [ptr_b[i], ptr_e[i]) (a CSR list: ptr_e = ptr_b + 1).
 template <class T, bool COMP>
-void launch_sweep(const Handle::Sweep& w, const int* ptr, const int* krow, const int64_t* blk_off, const T* blk,
-                  const T* X, const int64_t* out_off, T* Y, int ld, int accumulate, const T* zero, hipStream_t s)
+void launch_sweep(const Handle::Sweep& w, const int* ptr_b, const int* ptr_e, const int* krow,
+                  const int64_t* blk_off, const T* blk, const T* X, const int64_t* out_off, T* Y, int ld,
+                  int accumulate, const T* zero, hipStream_t s)
 {
-    launch_sweep_mt<4, T, COMP>(w, ptr, krow, blk_off, blk, X, out_off, Y, ld, accumulate, zero, s);
-    launch_sweep_mt<3, T, COMP>(w, ptr, krow, blk_off, blk, X, out_off, Y, ld, accumulate, zero, s);
-    launch_sweep_mt<2, T, COMP>(w, ptr, krow, blk_off, blk, X, out_off, Y, ld, accumulate, zero, s);
-    launch_sweep_mt<1, T, COMP>(w, ptr, krow, blk_off, blk, X, out_off, Y, ld, accumulate, zero, s);
+    launch_sweep_mt<4, T, COMP>(w, ptr_b, ptr_e, krow, blk_off, blk, X, out_off, Y, ld, accumulate, zero, s);
+    launch_sweep_mt<3, T, COMP>(w, ptr_b, ptr_e, krow, blk_off, blk, X, out_off, Y, ld, accumulate, zero, s);
+    launch_sweep_mt<2, T, COMP>(w, ptr_b, ptr_e, krow, blk_off, blk, X, out_off, Y, ld, accumulate, zero, s);
+    launch_sweep_mt<1, T, COMP>(w, ptr_b, ptr_e, krow, blk_off, blk, X, out_off, Y, ld, accumulate, zero, s);
+}
+
+// tasks and block counts from w, entry metadata (ek, ex) shared with the
+// upper sweep
+template <int MT, class T, bool COMP>
+void launch_sweep_t_mt(const Handle::Sweep& w, const int* ek, const int64_t* ex, const int* ptr_b, const int* ptr_e,
+                       const int* krow, const int64_t* blk_off, const T* blk, const T* X, const int64_t* out_off,
+                       T* Y, int ld, const T* zero, hipStream_t s)
+{
+    const int nt = w.n[MT - 1];
+    if (nt == 0) return;
+    constexpr int P = 2;
+    const unsigned grid = (unsigned)(8 * ((nt + 7) / 8));
+    k_sweep_t<MT, T, COMP, P><<<grid, 64, 0, s>>>(nt, w.node[MT - 1].p, w.r0[MT - 1].p, ptr_b, ptr_e, ek, ex,
+                                                  w.steps.p, krow, blk_off, blk, X, out_off, Y, ld / 32, ld, zero);
+    H2_LAUNCH_CHECK();
+}
+
+template <class T, bool COMP>
+void launch_sweep_t(const Handle::Sweep& w, const int* ek, const int64_t* ex, const int* ptr_b, const int* ptr_e,
+                    const int* krow, const int64_t* blk_off, const T* blk, const T* X, const int64_t* out_off, T* Y,
+                    int ld, const T* zero, hipStream_t s)
+{
+    launch_sweep_t_mt<4, T, COMP>(w, ek, ex, ptr_b, ptr_e, krow, blk_off, blk, X, out_off, Y, ld, zero, s);
+    launch_sweep_t_mt<3, T, COMP>(w, ek, ex, ptr_b, ptr_e, krow, blk_off, blk, X, out_off, Y, ld, zero, s);
+    launch_sweep_t_mt<2, T, COMP>(w, ek, ex, ptr_b, ptr_e, krow, blk_off, blk, X, out_off, Y, ld, zero, s);
+    launch_sweep_t_mt<1, T, COMP>(w, ek, ex, ptr_b, ptr_e, krow, blk_off, blk, X, out_off, Y, ld, zero, s);
 }
 
 template <class T>
@@ -561,9 +774,16 @@ void apply_t(Handle& h, const T* x, T* y, int nrhs, int ld, const ApplyWork<T>& 
         } else {
             fail(H2_EINTERNAL, "coupling evaluated in the apply needs precision 64");
         }
+    } else if (h.B_upper) {
+        // the stored blocks of the entries j > i, then those of j < i read
+        // transposed (added to the rows the first sweep wrote)
+        launch_sweep<T, sizeof(T) == 4>(h.cp, h.il_split.p, h.il_ptr.p + 1, h.bu.rank.p, h.B_off.p, AB::B(h), xh,
+                                        h.bu.xh_off.p, yh, ld, 0, zero, s);
+        launch_sweep_t<T, sizeof(T) == 4>(h.cpt, h.cp.ek.p, h.cp.ex.p, h.il_ptr.p, h.il_split.p, h.bu.rank.p,
+                                          h.B_off.p, AB::B(h), xh, h.bu.xh_off.p, yh, ld, zero, s);
     } else {
-        launch_sweep<T, sizeof(T) == 4>(h.cp, h.il_ptr.p, h.bu.rank.p, h.B_off.p, AB::B(h), xh, h.bu.xh_off.p, yh, ld,
-                                        0, zero, s);
+        launch_sweep<T, sizeof(T) == 4>(h.cp, h.il_ptr.p, h.il_ptr.p + 1, h.bu.rank.p, h.B_off.p, AB::B(h), xh,
+                                        h.bu.xh_off.p, yh, ld, 0, zero, s);
     }
     mark(3);
     for (int L = 1; L < h.maxdepth; ++L) {
@@ -576,8 +796,8 @@ void apply_t(Handle& h, const T* x, T* y, int nrhs, int ld, const ApplyWork<T>& 
     k_leaves_far<T><<<(unsigned)h.leaves.n, TB, 0, s>>>(nrhs, ld, h.leaves.p, h.start.p, h.count.p, h.bu.rank.p,
                                                         h.bu.piv_off.p, h.bu.piv.p, h.bu.T_off.p, Tm, h.bu.xh_off.p, yh, yt);
     H2_LAUNCH_CHECK();
-    launch_sweep<T, sizeof(T) == 4>(h.nr, h.nr_ptr.p, h.count.p, h.D_off.p, AB::D(h), xt, h.start64.p, yt, ld, 1,
-                                    zero, s);
+    launch_sweep<T, sizeof(T) == 4>(h.nr, h.nr_ptr.p, h.nr_ptr.p + 1, h.count.p, h.D_off.p, AB::D(h), xt,
+                                    h.start64.p, yt, ld, 1, zero, s);
     mark(5);
     k_scatter<T><<<blocks_for(n * nrhs, TB), TB, 0, s>>>(yt, n, nrhs, ld, h.perm.p, y);
     H2_LAUNCH_CHECK();
@@ -717,9 +937,28 @@ void prepare_apply(Handle& h)
     h.cp.ek.ensure(std::max<int64_t>(h.nil, 1), s);
     h.cp.ex.ensure(std::max<int64_t>(h.nil, 1), s);
     h.cp.steps.ensure(std::max(h.nnode, 1), s);
-    k_sweep_meta<<<blocks_for(h.nnode, TB), TB, 0, s>>>(h.nnode, h.il_ptr.p, h.il_col.p, h.col().rank.p,
-                                                        h.col().xh_off.p, h.cp.ek.p, h.cp.ex.p, h.cp.steps.p);
-    H2_LAUNCH_CHECK();
+    if (h.B_upper) {
+        // the stored (j > i) entries in steps of 4 columns; the transposed
+        // (j < i) entries in blocks of 16, for the nodes that have them
+        k_entry_meta<<<blocks_for(h.nnode, TB), TB, 0, s>>>(h.nnode, h.il_ptr.p, h.il_col.p, h.col().rank.p,
+                                                            h.col().xh_off.p, h.cp.ek.p, h.cp.ex.p);
+        H2_LAUNCH_CHECK();
+        k_range_units<<<blocks_for(h.nnode, TB), TB, 0, s>>>(h.nnode, h.il_split.p, h.il_ptr.p + 1, h.cp.ek.p, 4,
+                                                             h.cp.steps.p);
+        H2_LAUNCH_CHECK();
+        std::vector<int> rows_l(h.nnode, 0);
+        for (int i = 0; i < h.nnode; ++i)
+            if (h.h_il_split[i] > h.h_il_ptr[i]) rows_l[i] = h.bu.h_rank[i];
+        make(rows_l, h.h_il_ptr, true, h.cpt);
+        h.cpt.steps.ensure(std::max(h.nnode, 1), s);
+        k_range_units<<<blocks_for(h.nnode, TB), TB, 0, s>>>(h.nnode, h.il_ptr.p, h.il_split.p, h.cp.ek.p, 16,
+                                                             h.cpt.steps.p);
+        H2_LAUNCH_CHECK();
+    } else {
+        k_sweep_meta<<<blocks_for(h.nnode, TB), TB, 0, s>>>(h.nnode, h.il_ptr.p, h.il_col.p, h.col().rank.p,
+                                                            h.col().xh_off.p, h.cp.ek.p, h.cp.ex.p, h.cp.steps.p);
+        H2_LAUNCH_CHECK();
+    }
     // nearfield: leaves with near entries (a leaf's own block is one)
     std::vector<int> leaf_rows(h.nnode, 0);
     for (int i = 0; i < h.nnode; ++i)

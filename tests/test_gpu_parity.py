@@ -287,6 +287,50 @@ def test_coupling_evaluated_in_apply(H, d, kernel, prm, n, leaf, r, nrhs):
     g1.close()
 
 
+@pytest.mark.parametrize("kernel,prm,r", [("coulomb", 1.0, 0), ("advection", 2.0, 125)])
+def test_coupling_blocks_one_per_unordered_pair(H, kernel, prm, r):
+    """A symmetric kernel (V = U, so B_ji = B_ij^T, Algorithm 2) stores one
+    coupling block per unordered interaction pair: bytes_B is the sum of
+    k_i k_j over the entries with j > i, and the block exported for (j, i)
+    is the transpose of the one for (i, j), bit for bit, and equals
+    K(Xhat_i, Xhat_j) evaluated here; a non-symmetric kernel stores every
+    ordered pair.  The product agrees with the oracle's within 1e-10 in FP64
+    and within the tolerance in the precision mode."""
+    rng = np.random.default_rng(4242)
+    n = 5000
+    P = rng.random((n, 3))
+    x = rng.standard_normal((3, n))
+    _say(f"coupling storage {kernel}")
+    g = H.H2Matrix(P, kernel, prm, 1e-6, 40, r1=r, r2=2 * r)
+    ptr, col = g.export("il_ptr"), g.export("il_col")
+    rank, rank_v = g.export("rank"), g.export("rank_v")
+    rows = np.repeat(np.arange(len(ptr) - 1), np.diff(ptr))
+    full = int(np.sum(rank[rows].astype(np.int64) * rank_v[col]))
+    upper = int(np.sum((rank[rows].astype(np.int64) * rank_v[col])[col > rows]))
+    sym = kernel != "advection"
+    assert g.info()["bytes_B"] == 8 * (upper if sym else full)
+    pts = g.export("points").reshape(3, -1).T
+    pick = np.random.default_rng(3).choice(len(col), 40, replace=False)
+    for e in pick:
+        i, j = int(rows[e]), int(col[e])
+        f = int(np.flatnonzero((rows == j) & (col == i))[0])
+        Bij = g.export("B", int(e)).reshape(rank_v[j], rank[i]).T
+        Bji = g.export("B", f).reshape(rank_v[i], rank[j]).T
+        if sym:
+            assert np.array_equal(Bij, Bji.T), (i, j)
+        si, sj = g.export("skel", i), g.export("skel_v", j)
+        np.testing.assert_allclose(Bij, O.kernel_matrix(kernel, prm, pts[si], pts[sj]), rtol=1e-13, atol=0)
+    o = O.H2Oracle(P, kernel, prm, tol=1e-6, leaf=40, r1=r, r2=2 * r)
+    yo = o.matvec(x)
+    assert _rel(g.matvec(x).cpu().numpy(), yo) <= 1e-10
+    g.close()
+    g32 = H.H2Matrix(P, kernel, prm, 1e-6, 40, r1=r, r2=2 * r, precision=32)
+    assert g32.info()["bytes_B"] == 4 * (upper if sym else full)
+    y32 = g32.matvec(x.astype(np.float32)).cpu().numpy().astype(np.float64)
+    assert _rel(y32, yo) <= 1e-6
+    g32.close()
+
+
 def test_exact_limit_against_dense(H):
     """r1 = r2 >= n and a rounding-level tolerance: the GPU H^2 product equals
     the dense product."""
