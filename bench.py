@@ -723,7 +723,9 @@ def main():
         "roofline_id_all_classes": roof_id_all,
         "roofline_matvec": {"kernel": "k_sweep + k_sweep_t (coupling sweeps of the apply)", "bound": "hbm",
                             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                            "frac": achieved / HBM_PEAK_GBS,
+                            "traffic": recorded_traffic("k_sweep_coupling_cube3d-coulomb-n1048576-nrhs32_hbm-counters.md",
+                                                        "paper_2206_01885_amd/csrc/matvec.hip"),
                             "bytes_per_launch": coupling_bytes, "stored_block_bytes": info["bytes_B"],
                             "blocks_streamed_per_apply": 2 if sym_B else 1, "ms_per_launch": 1e3 * t_coup},
     }
