@@ -693,6 +693,42 @@ def main():
                "vs_oracle": acc32_oracle}
         del Y32, X32
 
+    # precision mode where its decompositions run in FP32 too (tol >= 1e-5):
+    # FP64 and FP32 paths side by side at tol 1e-5
+    f32_1e5 = None
+    if not args.no_f32:
+        f32_1e5 = {}
+        for prec in (64, 32):
+            o5 = h2.h2_options_default()
+            o5.r1, o5.r2 = args.r, 2 * args.r
+            o5.r_min = args.r_min
+            o5.precision = prec
+            o5.profile = 1
+            Xp = X if prec == 64 else X.float()
+            Yp = torch.empty_like(Xp)
+            tb5, tm5 = [], []
+            for k in range(1 + args.steps):
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                hp = h2.h2_build(Psoa, "coulomb", 1.0, 1e-5, 128, o5)
+                tb = time.perf_counter()
+                h2.h2_matvec(hp, Xp, Yp, nrhs)
+                torch.cuda.synchronize()
+                te = time.perf_counter()
+                if k > 0:
+                    tb5.append(tb - ts)
+                    tm5.append(te - tb)
+                ip = h2.h2_query(hp)
+                h2.h2_destroy(hp)
+            got = Yp[:, ridx].double()
+            f32_1e5[f"fp{prec}"] = {
+                "ms_per_step": 1e3 * (np.mean(tb5) + np.mean(tm5)), "build_s": float(np.mean(tb5)),
+                "matvec_s": float(np.mean(tm5)), "t_basis_s": ip["t_basis"], "sum_rank": ip["sum_rank"],
+                "bytes_B": ip["bytes_B"],
+                "e_dense_sampled_rows_max_rhs": ((got - ref).norm(dim=1) / ref.norm(dim=1)).max().item()}
+            print(f"[bench] tol 1e-5 precision {prec}: {f32_1e5[f'fp{prec}']}", file=sys.stderr, flush=True)
+            del Xp, Yp
+
     out = {
         "metric": "H2 build Mpts/s + matvec GB/s, n=1M 3D Coulomb @1e-6; p50/p99 latency",
         "value": n / (ms_per_step / 1e3) / 1e6,
@@ -717,6 +753,7 @@ def main():
                      "rows": int(len(rows)), "dense_reference": "torch FP64 on the GPU, all RHS",
                      "vs_oracle": acc_oracle},
         "precision_f32": f32,
+        "precision_tol1e-5": f32_1e5,
         "store_coupling_0": otf,
         "roofline": roof_dr,
         "roofline_id_wide": roof_id,

@@ -75,6 +75,20 @@ __device__ inline int block_min_i(int v, int* sh)
 // space.
 typedef __attribute__((address_space(1))) double gdouble;
 typedef __attribute__((address_space(1))) int gint;
+template <class ET>
+using gptr = __attribute__((address_space(1))) ET*;
+
+// Kernel entries of the interpolative decompositions: FP64 correctly rounded
+// (compared with the oracle bit for bit), or, for the precision mode's FP32
+// decompositions, the kernel function evaluated in FP32.
+template <class ET, int FAM>
+__device__ __forceinline__ ET kappa_id(int kid, double prm, double r2, double xy, double d0)
+{
+    if constexpr (std::is_same_v<ET, float>)
+        return kappa_store<float, FAM>(kid, prm, r2, xy, d0);
+    else
+        return kappa_fam<FAM>(kid, prm, r2, xy, d0);
+}
 
 // Barrier that orders LDS accesses only: global loads and stores of a lane
 // stay in flight across it.
@@ -92,17 +106,31 @@ __device__ inline void lds_barrier()
 // overlaps.
 constexpr int LB = 8;
 
-// acc + sum_{r=r0}^{r1-1} a[r] * x[r*ld], accumulated in row order
-template <int BATCH = LB, class XP>
-__device__ __forceinline__ double dot_rows(const double* __restrict__ a, XP x, int64_t ld, int r0, int r1, double acc)
+// A norm down-date is trusted while the squared remainder it leaves is
+// above the square root of the matrix type's machine epsilon (LAWN 176);
+// FP32 data makes it unreliable far earlier than FP64 data.
+template <class ET>
+__device__ __forceinline__ double down_tol()
+{
+    return std::is_same_v<ET, float> ? 3.4526698300124393e-04 /* sqrt(2^-23) */
+                                     : sqrt(2.220446049250313e-16);
+}
+
+__device__ __forceinline__ double fma_e(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_e(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// acc + sum_{r=r0}^{r1-1} a[r] * x[r*ld], accumulated in row order in the
+// type of a (FP64, or FP32 in the precision mode's decompositions)
+template <int BATCH = LB, class AT, class XP>
+__device__ __forceinline__ AT dot_rows(const AT* __restrict__ a, XP x, int64_t ld, int r0, int r1, AT acc)
 {
     int r = r0;
     if (r + BATCH <= r1) {
-        double cur[BATCH];
+        AT cur[BATCH];
 #pragma unroll
         for (int q = 0; q < BATCH; ++q) cur[q] = x[(int64_t)(r + q) * ld];
         for (; r + 2 * BATCH <= r1; r += BATCH) {
-            double nxt[BATCH];
+            AT nxt[BATCH];
 #pragma unroll
             for (int q = 0; q < BATCH; ++q) nxt[q] = x[(int64_t)(r + BATCH + q) * ld];
 #pragma unroll
@@ -118,7 +146,7 @@ __device__ __forceinline__ double dot_rows(const double* __restrict__ a, XP x, i
     return acc;
 }
 
-// acc + sum_{r=r0}^{r1-1} x[r*ld]^2, in row order
+// acc + sum_{r=r0}^{r1-1} x[r*ld]^2, in row order, in FP64
 template <class XP>
 __device__ __forceinline__ double sumsq_rows(XP x, int64_t ld, int r0, int r1, double acc)
 {
@@ -144,46 +172,47 @@ __device__ __forceinline__ double sumsq_rows(XP x, int64_t ld, int r0, int r1, d
     return acc;
 }
 
-// x[r] <- x[r] - f v[r] for r in [r0, r1); returns the sum of the new x[r]^2
-// over r in [r0+1, r1) in row order (the next step's tail norm)
-template <class XP>
-__device__ __forceinline__ double axpy_rows(const double* __restrict__ v, double f, XP x, int64_t ld, int r0, int r1)
+// x[r] <- x[r] - f v[r] for r in [r0, r1) in the type of v; returns the sum
+// of the new x[r]^2 over r in [r0+1, r1) in row order, in FP64 (the next
+// step's tail norm)
+template <class AT, class XP>
+__device__ __forceinline__ double axpy_rows(const AT* __restrict__ v, AT f, XP x, int64_t ld, int r0, int r1)
 {
     {
-        double y = x[(int64_t)r0 * ld] - f * v[r0];
+        AT y = x[(int64_t)r0 * ld] - f * v[r0];
         x[(int64_t)r0 * ld] = y;
     }
     double tail = 0.0;
     int r = r0 + 1;
     if (r + LB <= r1) {
-        double cur[LB];
+        AT cur[LB];
 #pragma unroll
         for (int q = 0; q < LB; ++q) cur[q] = x[(int64_t)(r + q) * ld];
         for (; r + 2 * LB <= r1; r += LB) {
-            double nxt[LB];
+            AT nxt[LB];
 #pragma unroll
             for (int q = 0; q < LB; ++q) nxt[q] = x[(int64_t)(r + LB + q) * ld];
 #pragma unroll
             for (int q = 0; q < LB; ++q) {
-                double y = cur[q] - f * v[r + q];
+                AT y = cur[q] - f * v[r + q];
                 x[(int64_t)(r + q) * ld] = y;
-                tail = tail + y * y;
+                tail = tail + (double)y * (double)y;
             }
 #pragma unroll
             for (int q = 0; q < LB; ++q) cur[q] = nxt[q];
         }
 #pragma unroll
         for (int q = 0; q < LB; ++q) {
-            double y = cur[q] - f * v[r + q];
+            AT y = cur[q] - f * v[r + q];
             x[(int64_t)(r + q) * ld] = y;
-            tail = tail + y * y;
+            tail = tail + (double)y * (double)y;
         }
         r += LB;
     }
     for (; r < r1; ++r) {
-        double y = x[(int64_t)r * ld] - f * v[r];
+        AT y = x[(int64_t)r * ld] - f * v[r];
         x[(int64_t)r * ld] = y;
-        tail = tail + y * y;
+        tail = tail + (double)y * (double)y;
     }
     return tail;
 }
@@ -236,10 +265,14 @@ struct XCoords<1> {
 // pointer.  Every R entry is read and written by the lane that owns its
 // column only (the diagonal entry reaches the other lanes through LDS), so
 // the steps need LDS barriers only.
-template <int NT, int CPL, int BR, int FAM, class RPtr>
-__device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbuf, double* nubuf, double* scr)
+template <int NT, int CPL, int BR, int FAM, class ET, class RPtr>
+__device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbuf_d, double* nubuf_d, double* scr_d)
 {
-    double* x0buf = nubuf + 2;
+    // ET buffers at the places of the FP64 ones (an FP32 fold uses half)
+    ET* colbuf = (ET*)colbuf_d;
+    ET* nubuf = (ET*)nubuf_d;
+    ET* x0buf = (ET*)(nubuf_d + 2);
+    ET* scr = (ET*)scr_d;
     const double* pts = tk.pts;
     const int64_t ld = tk.ld;
     const int* xi = tk.x_idx;
@@ -248,13 +281,13 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbu
     const double prm = tk.prm;
     const double dsgn = tk.swap ? -1.0 : 1.0;  // column side: kappa(y, x)
     const int lane = threadIdx.x;
-    double* ycrd = scr + BR * NT;  // 3 x BR: the row block's points
+    double* ycrd = scr_d + BR * NT;  // 3 x BR: the row block's points
     for (int64_t e = lane; e < (int64_t)m * m; e += NT) R[e] = 0.0;
     // this lane's column points: in registers for one column per lane,
     // otherwise read where needed (L1 hits; registers kept for occupancy)
     XCoords<CPL> xr(pts, ld, xi, lane, NT, m, d);
     __syncthreads();
-    double bc[CPL][BR], tail[CPL];
+    ET bc[CPL][BR], tail[CPL];
     for (int r0 = 0; r0 < s0; r0 += BR) {
         const int nb = min(BR, s0 - r0);
         // the row block's points, staged once in LDS for all lanes
@@ -278,22 +311,22 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbu
                             if (a == 0) e0 = ea;
                             r2 = r2 + ea * ea;
                         }
-                    scr[r * NT + lane] = kappa_fam<FAM>(kid, prm, r2, xy, dsgn * e0);
+                    scr[r * NT + lane] = kappa_id<ET, FAM>(kid, prm, r2, xy, dsgn * e0);
                 }
             }
-            tail[t] = 0.0;
+            tail[t] = ET(0);
 #pragma unroll
             for (int r = 0; r < BR; ++r) {
-                const double v = (c < m && r < nb) ? scr[r * NT + lane] : 0.0;
+                const ET v = (c < m && r < nb) ? scr[r * NT + lane] : ET(0);
                 bc[t][r] = v;
-                tail[t] = __builtin_fma(v, v, tail[t]);
+                tail[t] = fma_e(v, v, tail[t]);
             }
         }
-        double rn[CPL];
+        ET rn[CPL];
 #pragma unroll
         for (int t = 0; t < CPL; ++t) {
             const int c = lane + t * NT;
-            rn[t] = c < m ? R[c] : 0.0;
+            rn[t] = c < m ? R[c] : ET(0);
         }
         // publish column 0
         if (lane == 0) {
@@ -304,37 +337,37 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbu
         }
         lds_barrier();
         for (int j = 0; j < m; ++j) {
-            const double* cj = colbuf + (j & 1) * BR;
-            const double nub = nubuf[j & 1];
-            const double x0 = x0buf[j & 1];
-            double rc[CPL];
+            const ET* cj = colbuf + (j & 1) * BR;
+            const ET nub = nubuf[j & 1];
+            const ET x0 = x0buf[j & 1];
+            ET rc[CPL];
 #pragma unroll
             for (int t = 0; t < CPL; ++t) {
                 rc[t] = rn[t];
                 const int c = lane + t * NT;
-                rn[t] = (c < m && j + 1 < m) ? R[(int64_t)(j + 1) * m + c] : 0.0;
+                rn[t] = (c < m && j + 1 < m) ? R[(int64_t)(j + 1) * m + c] : ET(0);
             }
-            if (nub != 0.0) {
-                const double alpha = x0 >= 0.0 ? -sqrt(x0 * x0 + nub) : sqrt(x0 * x0 + nub);
-                const double v0 = x0 - alpha;
-                const double vtv = 2.0 * fabs(alpha) * (fabs(alpha) + fabs(x0));
-                double cjr[BR];
+            if (nub != ET(0)) {
+                const ET alpha = x0 >= ET(0) ? -sqrt(x0 * x0 + nub) : sqrt(x0 * x0 + nub);
+                const ET v0 = x0 - alpha;
+                const ET vtv = ET(2) * fabs(alpha) * (fabs(alpha) + fabs(x0));
+                ET cjr[BR];
 #pragma unroll
                 for (int r = 0; r < BR; ++r) cjr[r] = cj[r];
 #pragma unroll
                 for (int t = 0; t < CPL; ++t) {
                     const int c = lane + t * NT;
                     if (c > j && c < m) {
-                        double w = v0 * rc[t];
+                        ET w = v0 * rc[t];
 #pragma unroll
-                        for (int r = 0; r < BR; ++r) w = __builtin_fma(cjr[r], bc[t][r], w);
-                        const double f = 2.0 * w / vtv;
+                        for (int r = 0; r < BR; ++r) w = fma_e(cjr[r], bc[t][r], w);
+                        const ET f = ET(2) * w / vtv;
                         R[(int64_t)j * m + c] = rc[t] - f * v0;
-                        double ts = 0.0;
+                        ET ts = ET(0);
 #pragma unroll
                         for (int r = 0; r < BR; ++r) {
-                            bc[t][r] = __builtin_fma(-f, cjr[r], bc[t][r]);
-                            ts = __builtin_fma(bc[t][r], bc[t][r], ts);
+                            bc[t][r] = fma_e(-f, cjr[r], bc[t][r]);
+                            ts = fma_e(bc[t][r], bc[t][r], ts);
                         }
                         tail[t] = ts;
                     }
@@ -345,7 +378,7 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbu
             // diagonal entry of R from the row loaded ahead) for the next step
             if (j + 1 < m && lane == (j + 1) % NT) {
                 const int t1 = (j + 1) / NT;
-                double* nb1 = colbuf + ((j + 1) & 1) * BR;
+                ET* nb1 = colbuf + ((j + 1) & 1) * BR;
 #pragma unroll
                 for (int t = 0; t < CPL; ++t)
                     if (t == t1) {
@@ -403,21 +436,28 @@ __host__ __device__ inline bool use_blocked(int64_t s, int64_t m, int cols, int 
 // on the fly (LAPACK ends the panel instead; with the fast-decaying spectra
 // of kernel blocks that would end nearly every panel).  Returns the rank;
 // the pivot order is in piv and R in the upper triangle of M.
-template <int NT, int CPL, int NB>
-__device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol, gint* piv, double* lds)
+template <int NT, int CPL, int NB, class ET>
+__device__ __forceinline__ int cpqr_blocked(gptr<ET> M, int m, int s, double tol, gint* piv, double* lds)
 {
     constexpr int W = NT / 64;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    double* v = lds;            // s: the reflector of the step
-    double* nu = v + s;         // m: partial column norms
+    // LDS laid out in FP64 slots; the matrix-typed (ET) arrays start at their
+    // slots (an FP32 decomposition fills half of each)
+    double* nu = lds + s;       // m: partial column norms (FP64)
     double* nu0 = nu + m;       // m: their reference values
-    double* Vl = nu0 + m;       // s x NB: the panel's reflectors, Vl[r * NB + b]
-    double* fp = Vl + (int64_t)s * NB;  // NB: F row of the pivot column
-    double* fj = fp + NB;       // NB: F row of column j
-    double* vj = fj + NB;       // NB: row j of V
-    double* red = vj + NB;      // W x NB partial sums
-    double* redd = red + W * NB;  // W
-    int* redi = (int*)(redd + W);  // W
+    double* Vl_d = nu0 + m;
+    double* fp_d = Vl_d + (int64_t)s * NB;
+    double* fj_d = fp_d + NB;
+    double* vj_d = fj_d + NB;
+    double* red_d = vj_d + NB;
+    double* redd = red_d + W * NB;  // W
+    int* redi = (int*)(redd + W);   // W
+    ET* v = (ET*)lds;           // s: the reflector of the step
+    ET* Vl = (ET*)Vl_d;         // s x NB: the panel's reflectors, Vl[r * NB + b]
+    ET* fp = (ET*)fp_d;         // NB: F row of the pivot column
+    ET* fj = (ET*)fj_d;         // NB: F row of column j
+    ET* vj = (ET*)vj_d;         // NB: row j of V
+    ET* red = (ET*)red_d;       // W x NB partial sums
     for (int t = 0; t < CPL; ++t) {
         const int c = tid + t * NT;
         if (c < m) {
@@ -427,14 +467,14 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
         }
     }
     __syncthreads();
-    const double tol3z = sqrt(2.220446049250313e-16);
+    const double tol3z = down_tol<ET>();
     const double window = 1.0 - 0x1.0p-40;
     const int kmax = m < s ? m : s;
-    double F[CPL][NB];
+    ET F[CPL][NB];
 #pragma unroll
     for (int t = 0; t < CPL; ++t)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) F[t][b] = 0.0;
+        for (int b = 0; b < NB; ++b) F[t][b] = ET(0);
     double r00 = 0.0;
     int k = 0, j0 = 0;
     for (int j = 0; j < kmax; ++j) {
@@ -466,21 +506,21 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
         // row r >= j is handled by thread (r - j) mod NT in this step
         double a2 = 0.0;
         for (int r = j + tid; r < s; r += NT) {
-            double x = M[(int64_t)r * m + pc];
-            const double* Vr = Vl + (int64_t)r * NB;
+            ET x = M[(int64_t)r * m + pc];
+            const ET* Vr = Vl + (int64_t)r * NB;
             for (int b = 0; b < jb; ++b) x = x - Vr[b] * fp[b];
             v[r] = x;
-            a2 = a2 + x * x;
+            a2 = a2 + (double)x * (double)x;
         }
         a2 = block_sum<NT>(a2, redd);
         const double alpha = sqrt(a2);
         if (j == 0) r00 = alpha;
         // the step that stops swaps nothing
         if (alpha == 0.0 || alpha <= tol * r00) break;
-        const double xj = v[j];
-        const double beta = xj >= 0.0 ? -alpha : alpha;
-        const double vd = xj - beta;  // first entry of the Householder vector
-        const double vtv = 2.0 * alpha * (alpha + fabs(xj));
+        const ET xj = v[j];
+        const ET beta = xj >= ET(0) ? ET(-alpha) : ET(alpha);
+        const ET vd = xj - beta;  // first entry of the Householder vector
+        const ET vtv = ET(2.0 * alpha * (alpha + fabs((double)xj)));
         // swap columns j and pc (every row), F rows and norms; the reflector
         // below the diagonal of column j, R_jj
         for (int r = j + tid; r < s; r += NT) {
@@ -490,7 +530,7 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
         }
         if (pc != j) {
             for (int r = tid; r < j; r += NT) {
-                const double a = M[(int64_t)r * m + j];
+                const ET a = M[(int64_t)r * m + j];
                 M[(int64_t)r * m + j] = M[(int64_t)r * m + pc];
                 M[(int64_t)r * m + pc] = a;
             }
@@ -506,12 +546,12 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
             }
         }
         // y_b = v^T v_b over rows >= j (b < jb), row j of V
-        double yp[NB];
+        ET yp[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) yp[b] = 0.0;
+        for (int b = 0; b < NB; ++b) yp[b] = ET(0);
         for (int r = j + tid; r < s; r += NT) {
-            const double vr = r == j ? vd : v[r];
-            const double* Vr = Vl + (int64_t)r * NB;
+            const ET vr = r == j ? vd : v[r];
+            const ET* Vr = Vl + (int64_t)r * NB;
 #pragma unroll
             for (int b = 0; b < NB; ++b)
                 if (b < jb) yp[b] = yp[b] + vr * Vr[b];
@@ -527,10 +567,10 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
             vj[jb] = vd;
         }
         __syncthreads();
-        double yb[NB];
+        ET yb[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            double a = 0.0;
+            ET a = ET(0);
             for (int q = 0; q < W; ++q) a = a + red[q * NB + b];
             yb[b] = a;
         }
@@ -539,22 +579,22 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
         for (int t = 0; t < CPL; ++t) {
             const int c = tid + t * NT;
             if (c > j && c < m) {
-                const double w = dot_rows<16>(v, M + c, m, j, s, 0.0);
-                double corr = 0.0;
+                const ET w = dot_rows<16>(v, M + c, m, j, s, ET(0));
+                ET corr = ET(0);
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
                     if (b < jb) corr = corr + yb[b] * F[t][b];
-                const double fn = 2.0 * (w - corr) / vtv;
+                const ET fn = ET(2) * (w - corr) / vtv;
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
                     if (b == jb) F[t][b] = fn;
-                double rj = M[(int64_t)j * m + c];
+                ET rj = M[(int64_t)j * m + c];
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
                     if (b <= jb) rj = rj - vj[b] * F[t][b];
                 M[(int64_t)j * m + c] = rj;
                 if (nu[c] != 0.0) {
-                    double tt = fabs(rj) / nu[c];
+                    double tt = fabs((double)rj) / nu[c];
                     tt = (1.0 + tt) * (1.0 - tt);
                     if (tt < 0.0) tt = 0.0;
                     const double rat = nu[c] / nu0[c];
@@ -565,25 +605,25 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
                         constexpr int RB = 8;
                         int r = j + 1;
                         for (; r + RB <= s; r += RB) {
-                            double x[RB];
+                            ET x[RB];
 #pragma unroll
                             for (int q = 0; q < RB; ++q) x[q] = M[(int64_t)(r + q) * m + c];
 #pragma unroll
                             for (int q = 0; q < RB; ++q) {
-                                const double* Vr = Vl + (int64_t)(r + q) * NB;
+                                const ET* Vr = Vl + (int64_t)(r + q) * NB;
 #pragma unroll
                                 for (int b = 0; b < NB; ++b)
                                     if (b <= jb) x[q] = x[q] - Vr[b] * F[t][b];
-                                a = a + x[q] * x[q];
+                                a = a + (double)x[q] * (double)x[q];
                             }
                         }
                         for (; r < s; ++r) {
-                            double x = M[(int64_t)r * m + c];
-                            const double* Vr = Vl + (int64_t)r * NB;
+                            ET x = M[(int64_t)r * m + c];
+                            const ET* Vr = Vl + (int64_t)r * NB;
 #pragma unroll
                             for (int b = 0; b < NB; ++b)
                                 if (b <= jb) x = x - Vr[b] * F[t][b];
-                            a = a + x * x;
+                            a = a + (double)x * (double)x;
                         }
                         nu[c] = sqrt(a);
                         nu0[c] = nu[c];
@@ -605,12 +645,12 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
                     constexpr int RB = 8;
                     int r = j + 1;
                     for (; r + RB <= s; r += RB) {
-                        double x[RB];
+                        ET x[RB];
 #pragma unroll
                         for (int q = 0; q < RB; ++q) x[q] = M[(int64_t)(r + q) * m + c];
 #pragma unroll
                         for (int q = 0; q < RB; ++q) {
-                            const double* Vr = Vl + (int64_t)(r + q) * NB;
+                            const ET* Vr = Vl + (int64_t)(r + q) * NB;
 #pragma unroll
                             for (int b = 0; b < NB; ++b)
                                 if (b <= jb) x[q] = x[q] - Vr[b] * F[t][b];
@@ -618,8 +658,8 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
                         }
                     }
                     for (; r < s; ++r) {
-                        double x = M[(int64_t)r * m + c];
-                        const double* Vr = Vl + (int64_t)r * NB;
+                        ET x = M[(int64_t)r * m + c];
+                        const ET* Vr = Vl + (int64_t)r * NB;
 #pragma unroll
                         for (int b = 0; b < NB; ++b)
                             if (b <= jb) x = x - Vr[b] * F[t][b];
@@ -627,7 +667,7 @@ __device__ __forceinline__ int cpqr_blocked(gdouble* M, int m, int s, double tol
                     }
                 }
 #pragma unroll
-                for (int b = 0; b < NB; ++b) F[t][b] = 0.0;
+                for (int b = 0; b < NB; ++b) F[t][b] = ET(0);
             }
             j0 = j + 1;
             __syncthreads();
@@ -654,7 +694,7 @@ __host__ __device__ inline bool compress_rows(int s, int m, int cap)
 // (tsqr_fold; PRE: k_id_fold already did it): column pivoting sees only the
 // partial column norms, which a left orthogonal factor does not change, so
 // the pivots, |R_jj| and T are those of the s x m block up to rounding.
-template <int NT, bool LDSM, int CPL, int BR, bool PRE, int FAM>
+template <int NT, bool LDSM, int CPL, int BR, bool PRE, int FAM, class ET>
 __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ tasks, const int* __restrict__ order)
 {
     extern __shared__ double dyn[];
@@ -674,13 +714,13 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
     // PRE: the block was compressed to its m x m R factor by k_id_fold
     const bool comp = !PRE && compress_rows(s0, m, CPL * NT);
     const int s = (comp || PRE) ? m : s0;  // rows of the matrix the pivoted QR runs on
-    double* v = dyn;
-    using MPtr = std::conditional_t<LDSM, double*, gdouble*>;
+    ET* v = (ET*)dyn;  // in the FP64 slots of dyn, like everything below
+    using MPtr = std::conditional_t<LDSM, ET*, gptr<ET>>;
     MPtr M;
     if constexpr (LDSM)
-        M = dyn + s;
+        M = (ET*)(dyn + s);
     else
-        M = (gdouble*)tk.M;
+        M = (gptr<ET>)tk.M;
     gdouble* nu = (gdouble*)tk.nu;
     gdouble* nu0 = nu + m;
     gdouble* ss = nu + 2 * m;
@@ -692,7 +732,7 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
         // the published column lives after the LDS matrix, or over the (not
         // yet used) reflector space
         double* cb = LDSM ? dyn + s + (int64_t)s * m : dyn;
-        tsqr_fold<NT, CPL, BR, FAM>(tk, m, s0, M, cb, cb + 2 * BR, cb + 2 * BR + 4);
+        tsqr_fold<NT, CPL, BR, FAM, ET>(tk, m, s0, M, cb, cb + 2 * BR, cb + 2 * BR + 4);
     } else {
         // kernel block: M[r][c] = kappa(x_c, y_r), a row per wavefront at a
         // time (its point read once), the columns across the lanes
@@ -718,7 +758,7 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
                         r2 = r2 + t * t;
                     }
                 }
-                M[(int64_t)r * m + c] = kappa_fam<FAM>(kid, prm, r2, xy, tk.swap ? -e0 : e0);
+                M[(int64_t)r * m + c] = kappa_id<ET, FAM>(kid, prm, r2, xy, tk.swap ? -e0 : e0);
             }
         }
         __syncthreads();
@@ -728,7 +768,7 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
     if constexpr (!LDSM) {
         // global matrix: the blocked form when the lanes can hold the F rows
         if (use_blocked(s, m, CPL * NT, NT, QR_NB)) {
-            k = cpqr_blocked<NT, CPL, QR_NB>(M, m, s, tol, piv, dyn);
+            k = cpqr_blocked<NT, CPL, QR_NB, ET>(M, m, s, tol, piv, dyn);
             blocked = true;
         }
     }
@@ -741,7 +781,7 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
     }
     __syncthreads();
 
-    const double tol3z = sqrt(2.220446049250313e-16);
+    const double tol3z = down_tol<ET>();
     const double window = 1.0 - 0x1.0p-40;
     const int kmax = m < s ? m : s;
     double r00 = 0.0;
@@ -765,7 +805,7 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
         if (alpha == 0.0 || alpha <= tol * r00) break;
         if (pc != j) {
             for (int r = threadIdx.x; r < s; r += NT) {
-                double t = M[(int64_t)r * m + j];
+                ET t = M[(int64_t)r * m + j];
                 M[(int64_t)r * m + j] = M[(int64_t)r * m + pc];
                 M[(int64_t)r * m + pc] = t;
             }
@@ -777,20 +817,20 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
             }
         }
         __syncthreads();
-        const double xj = M[(int64_t)j * m + j];
-        const double beta = xj >= 0.0 ? -alpha : alpha;
+        const ET xj = M[(int64_t)j * m + j];
+        const ET beta = xj >= ET(0) ? ET(-alpha) : ET(alpha);
         for (int r = j + threadIdx.x; r < s; r += NT) v[r] = M[(int64_t)r * m + j];
         __syncthreads();
         if (threadIdx.x == 0) v[j] = v[j] - beta;
         __syncthreads();
-        const double vtv = 2.0 * alpha * (alpha + fabs(xj));
+        const ET vtv = ET(2.0 * alpha * (alpha + fabs((double)xj)));
         for (int c = j + 1 + threadIdx.x; c < m; c += NT) {
-            double w = dot_rows(v, M + c, m, j, s, 0.0);
-            double f = 2.0 * w / vtv;
+            ET w = dot_rows(v, M + c, m, j, s, ET(0));
+            ET f = ET(2) * w / vtv;
             double tail = axpy_rows(v, f, M + c, m, j, s);
             ss[c] = tail;
             if (nu[c] != 0.0) {
-                double t = fabs(M[(int64_t)j * m + c]) / nu[c];
+                double t = fabs((double)M[(int64_t)j * m + c]) / nu[c];
                 t = (1.0 + t) * (1.0 - t);
                 if (t < 0.0) t = 0.0;
                 double rat = nu[c] / nu0[c];
@@ -948,17 +988,18 @@ __global__ __launch_bounds__(TB) void k_xbar_fill(int lo, const int* __restrict_
 // entries, so a step synchronises through LDS only; the R rows a lane needs
 // are loaded D steps ahead into a register ring, and the block entries are
 // evaluated SL rows at a time through a lane-private LDS slice.
-template <int CPL, int BR, int D, int FAM>
+template <int CPL, int BR, int D, int FAM, class ET>
 __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ tasks, const int* __restrict__ order)
 {
     constexpr int NT = 256, SL = 8;
     static_assert(BR % SL == 0 && BR % 4 == 0, "row block");
     extern __shared__ double dyn[];
-    double* colbuf = dyn;          // 2 x BR: the column step j eliminates
-    double* nubuf = dyn + 2 * BR;  // 2: its squared norm
-    double* x0buf = nubuf + 2;     // 2: the diagonal entry R[j][j]
-    double* scr = x0buf + 2;       // SL x NT evaluation slices
-    double* ycrd = scr + SL * NT;  // 3 x BR: the row block's points
+    // FP64 slots; the ET arrays start at theirs
+    ET* colbuf = (ET*)dyn;                   // 2 x BR: the column step j eliminates
+    ET* nubuf = (ET*)(dyn + 2 * BR);         // 2: its squared norm
+    ET* x0buf = (ET*)(dyn + 2 * BR + 2);     // 2: the diagonal entry R[j][j]
+    ET* scr = (ET*)(dyn + 2 * BR + 4);       // SL x NT evaluation slices
+    double* ycrd = dyn + 2 * BR + 4 + SL * NT;  // 3 x BR: the row block's points
     const IdTask& tk = tasks[order[blockIdx.x]];
     const int m = tk.m, s0 = tk.s, d = tk.d, kid = tk.kid;
     const double prm = tk.prm;
@@ -966,14 +1007,14 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
     const double* pts = tk.pts;
     const int64_t ld = tk.ld;
     const int* yi = tk.y_idx;
-    gdouble* R = (gdouble*)tk.M;
+    gptr<ET> R = (gptr<ET>)tk.M;
     const int lane = threadIdx.x;
     for (int64_t e = lane; e < (int64_t)m * m; e += NT) R[e] = 0.0;
     // this lane's column points: in registers for one column per lane,
     // otherwise read where needed (L1 hits; registers kept for occupancy)
     XCoords<CPL> xr(pts, ld, tk.x_idx, lane, NT, m, d);
     __syncthreads();
-    double bc[CPL][BR], tail[CPL], rn[D][CPL];
+    ET bc[CPL][BR], tail[CPL], rn[D][CPL];
     for (int r0 = 0; r0 < s0; r0 += BR) {
         const int nb = min(BR, s0 - r0);
         // the row block's points, staged once in LDS for all lanes
@@ -997,14 +1038,14 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
                                 if (a == 0) e0 = ea;
                                 r2 = r2 + ea * ea;
                             }
-                        scr[r * NT + lane] = kappa_fam<FAM>(kid, prm, r2, xy, dsgn * e0);
+                        scr[r * NT + lane] = kappa_id<ET, FAM>(kid, prm, r2, xy, dsgn * e0);
                     }
 #pragma unroll
-                for (int r = 0; r < SL; ++r) bc[t][k0 + r] = (c < m && k0 + r < nb) ? scr[r * NT + lane] : 0.0;
+                for (int r = 0; r < SL; ++r) bc[t][k0 + r] = (c < m && k0 + r < nb) ? scr[r * NT + lane] : ET(0);
             }
-            double t4[4] = {0.0, 0.0, 0.0, 0.0};
+            ET t4[4] = {ET(0), ET(0), ET(0), ET(0)};
 #pragma unroll
-            for (int r = 0; r < BR; ++r) t4[r & 3] = __builtin_fma(bc[t][r], bc[t][r], t4[r & 3]);
+            for (int r = 0; r < BR; ++r) t4[r & 3] = fma_e(bc[t][r], bc[t][r], t4[r & 3]);
             tail[t] = (t4[0] + t4[1]) + (t4[2] + t4[3]);
         }
 #pragma unroll
@@ -1012,7 +1053,7 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
 #pragma unroll
             for (int t = 0; t < CPL; ++t) {
                 const int c = lane + t * NT;
-                rn[q][t] = (c < m && q < m) ? R[(int64_t)q * m + c] : 0.0;
+                rn[q][t] = (c < m && q < m) ? R[(int64_t)q * m + c] : ET(0);
             }
         if (lane == 0) {
 #pragma unroll
@@ -1026,48 +1067,48 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
             for (int q = 0; q < D; ++q) {
                 const int j = j0 + q;
                 if (j < m) {
-                    const double* cj = colbuf + (j & 1) * BR;
-                    const double nub = nubuf[j & 1];
-                    const double x0 = x0buf[j & 1];
-                    double rc[CPL];
+                    const ET* cj = colbuf + (j & 1) * BR;
+                    const ET nub = nubuf[j & 1];
+                    const ET x0 = x0buf[j & 1];
+                    ET rc[CPL];
 #pragma unroll
                     for (int t = 0; t < CPL; ++t) {
                         rc[t] = rn[q][t];
                         const int c = lane + t * NT;
-                        rn[q][t] = (c < m && j + D < m) ? R[(int64_t)(j + D) * m + c] : 0.0;
+                        rn[q][t] = (c < m && j + D < m) ? R[(int64_t)(j + D) * m + c] : ET(0);
                     }
-                    if (nub != 0.0) {
-                        const double alpha = x0 >= 0.0 ? -sqrt(x0 * x0 + nub) : sqrt(x0 * x0 + nub);
-                        const double v0 = x0 - alpha;
-                        const double vtv = 2.0 * fabs(alpha) * (fabs(alpha) + fabs(x0));
+                    if (nub != ET(0)) {
+                        const ET alpha = x0 >= ET(0) ? -sqrt(x0 * x0 + nub) : sqrt(x0 * x0 + nub);
+                        const ET v0 = x0 - alpha;
+                        const ET vtv = ET(2) * fabs(alpha) * (fabs(alpha) + fabs(x0));
 #pragma unroll
                         for (int t = 0; t < CPL; ++t) {
                             const int c = lane + t * NT;
                             // chunks wholly at or left of column j, or past m, are skipped
                             if (t * NT + NT - 1 > j && t * NT < m && c > j && c < m) {
                                 // the published column is read from LDS in chunks of 8
-                                double w4[4] = {v0 * rc[t], 0.0, 0.0, 0.0};
+                                ET w4[4] = {v0 * rc[t], ET(0), ET(0), ET(0)};
 #pragma unroll
                                 for (int r0 = 0; r0 < BR; r0 += 8) {
-                                    double cv[8];
+                                    ET cv[8];
 #pragma unroll
                                     for (int r = 0; r < 8; ++r) cv[r] = cj[r0 + r];
 #pragma unroll
                                     for (int r = 0; r < 8; ++r)
-                                        w4[r & 3] = __builtin_fma(cv[r], bc[t][r0 + r], w4[r & 3]);
+                                        w4[r & 3] = fma_e(cv[r], bc[t][r0 + r], w4[r & 3]);
                                 }
-                                const double f = 2.0 * ((w4[0] + w4[1]) + (w4[2] + w4[3])) / vtv;
+                                const ET f = ET(2) * ((w4[0] + w4[1]) + (w4[2] + w4[3])) / vtv;
                                 R[(int64_t)j * m + c] = rc[t] - f * v0;
-                                double t4[4] = {0.0, 0.0, 0.0, 0.0};
+                                ET t4[4] = {ET(0), ET(0), ET(0), ET(0)};
 #pragma unroll
                                 for (int r0 = 0; r0 < BR; r0 += 8) {
-                                    double cv[8];
+                                    ET cv[8];
 #pragma unroll
                                     for (int r = 0; r < 8; ++r) cv[r] = cj[r0 + r];
 #pragma unroll
                                     for (int r = 0; r < 8; ++r) {
-                                        bc[t][r0 + r] = __builtin_fma(-f, cv[r], bc[t][r0 + r]);
-                                        t4[r & 3] = __builtin_fma(bc[t][r0 + r], bc[t][r0 + r], t4[r & 3]);
+                                        bc[t][r0 + r] = fma_e(-f, cv[r], bc[t][r0 + r]);
+                                        t4[r & 3] = fma_e(bc[t][r0 + r], bc[t][r0 + r], t4[r & 3]);
                                     }
                                 }
                                 tail[t] = (t4[0] + t4[1]) + (t4[2] + t4[3]);
@@ -1078,7 +1119,7 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
                     // the owner of column j + 1 publishes it for the next step
                     if (j + 1 < m && lane == (j + 1) % NT) {
                         const int t1 = (j + 1) / NT;
-                        double* nb1 = colbuf + ((j + 1) & 1) * BR;
+                        ET* nb1 = colbuf + ((j + 1) & 1) * BR;
 #pragma unroll
                         for (int t = 0; t < CPL; ++t)
                             if (t == t1) {
@@ -1097,7 +1138,7 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
 
 namespace {
 
-template <int FAM>
+template <int FAM, class ET>
 void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdProf* prof)
 {
     const int np = (int)tasks_in.size();
@@ -1185,11 +1226,11 @@ void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdPro
         const int* ord = d_order.p + off[c];
         switch (c) {
         case 0:
-        case 3: k_batched_id<64, true, 1, 32, false, FAM><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
-        case 1: k_batched_id<64, false, 1, 16, false, FAM><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
-        case 4: k_batched_id<WNT, false, 2, 16, true, FAM><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord); break;
-        case 5: k_batched_id<256, false, 1, 16, true, FAM><<<cnt[c], 256, lds[c], s>>>(d_tasks.p, ord); break;
-        default: k_batched_id<WNT, false, 2, 16, false, FAM><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord); break;
+        case 3: k_batched_id<64, true, 1, 32, false, FAM, ET><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
+        case 1: k_batched_id<64, false, 1, 16, false, FAM, ET><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
+        case 4: k_batched_id<WNT, false, 2, 16, true, FAM, ET><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord); break;
+        case 5: k_batched_id<256, false, 1, 16, true, FAM, ET><<<cnt[c], 256, lds[c], s>>>(d_tasks.p, ord); break;
+        default: k_batched_id<WNT, false, 2, 16, false, FAM, ET><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord); break;
         }
         H2_LAUNCH_CHECK();
     };
@@ -1198,13 +1239,13 @@ void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdPro
     launch(1);
     if (prof) H2_HIP(hipEventRecord(ev[1], s));
     if (!fold[0].empty())
-        k_id_fold<1, 32, 1, FAM><<<(unsigned)fold[0].size(), 256, (2 * 32 + 4 + 8 * 256 + 3 * 32) * sizeof(double), s>>>(
+        k_id_fold<1, 32, 1, FAM, ET><<<(unsigned)fold[0].size(), 256, (2 * 32 + 4 + 8 * 256 + 3 * 32) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[0]);
     if (!fold[1].empty())
-        k_id_fold<2, 16, 1, FAM><<<(unsigned)fold[1].size(), 256, (2 * 16 + 4 + 8 * 256 + 3 * 16) * sizeof(double), s>>>(
+        k_id_fold<2, 16, 1, FAM, ET><<<(unsigned)fold[1].size(), 256, (2 * 16 + 4 + 8 * 256 + 3 * 16) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[1]);
     if (!fold[2].empty())
-        k_id_fold<4, 8, 1, FAM><<<(unsigned)fold[2].size(), 256, (2 * 8 + 4 + 8 * 256 + 3 * 8) * sizeof(double), s>>>(
+        k_id_fold<4, 8, 1, FAM, ET><<<(unsigned)fold[2].size(), 256, (2 * 8 + 4 + 8 * 256 + 3 * 8) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[2]);
     H2_LAUNCH_CHECK();
     launch(5);
@@ -1225,15 +1266,19 @@ void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdPro
 
 }  // namespace
 
-// The ID tasks of each kernel family run through their own instances of the
-// launches (a batched build may mix families).
+// The ID tasks of each kernel family and arithmetic (FP64, or FP32 for the
+// precision mode) run through their own instances of the launches (a
+// batched build may mix them).
 void batched_id(const std::vector<IdTask>& tasks, hipStream_t s, IdProf* prof)
 {
-    std::vector<IdTask> fam[3];
-    for (const IdTask& t : tasks) fam[kernel_family(t.kid)].push_back(t);
-    batched_id_family<FAM_RADIAL>(fam[FAM_RADIAL], s, prof);
-    batched_id_family<FAM_COSINE>(fam[FAM_COSINE], s, prof);
-    batched_id_family<FAM_ADVECTION>(fam[FAM_ADVECTION], s, prof);
+    std::vector<IdTask> fam[2][3];
+    for (const IdTask& t : tasks) fam[t.f32 ? 1 : 0][kernel_family(t.kid)].push_back(t);
+    batched_id_family<FAM_RADIAL, double>(fam[0][FAM_RADIAL], s, prof);
+    batched_id_family<FAM_COSINE, double>(fam[0][FAM_COSINE], s, prof);
+    batched_id_family<FAM_ADVECTION, double>(fam[0][FAM_ADVECTION], s, prof);
+    batched_id_family<FAM_RADIAL, float>(fam[1][FAM_RADIAL], s, prof);
+    batched_id_family<FAM_COSINE, float>(fam[1][FAM_COSINE], s, prof);
+    batched_id_family<FAM_ADVECTION, float>(fam[1][FAM_ADVECTION], s, prof);
 }
 
 template <class T>
@@ -1428,6 +1473,7 @@ void build_bases_multi(const std::vector<Handle*>& hs, hipStream_t s)
                 tk.kid = h.kid;
                 tk.swap = u.swap;
                 tk.srrqr_f = h.srrqr_f;
+                tk.f32 = id_f32(h) ? 1 : 0;
                 tasks.push_back(tk);
                 Moff.push_back(ws);
                 nuoff.push_back(no);

@@ -321,10 +321,20 @@ struct IdTask {
     double srrqr_f = 0.0;  // > 1: swaps bounding max |T| by it after the ID
     int m = 0, s = 0, d = 0, kid = 0;
     int swap = 0;    // 1: column side, entries kappa(y_r, x_c) instead of kappa(x_c, y_r)
+    int f32 = 0;     // 1: FP32 kernel entries and Householder updates (FP64 norms and T)
     int folded = 0;  // set by batched_id: M holds the m x m R factor of the block
 };
 // HIP-event time (ms) of batched_id's launches: all classes, and the class of
 // the wide nodes (m > 64), accumulated over calls.
+// The precision mode's decompositions run in FP32 (kernel entries,
+// Householder updates; FP64 column norms, down-dates and T) when the
+// tolerance leaves room for FP32 rounding: eps >= 1e-5.  Each Householder
+// step rounds every updated entry to FP32, and over the hundreds of steps of
+// a wide block that noise reaches the truncation level of eps = 1e-6 (there
+// the n = 2^20 Coulomb product came out 1.2e-6 from the dense one, against
+// 0.6e-6 with FP64 decompositions); below 1e-5 the decompositions stay FP64.
+inline bool id_f32(const Handle& h) { return h.precision == 32 && h.tol >= 1e-5; }
+
 struct IdProf {
     double ms_all = 0, ms_wide = 0;
 };

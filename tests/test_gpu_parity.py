@@ -325,7 +325,9 @@ def test_coupling_blocks_one_per_unordered_pair(H, kernel, prm, r):
     assert _rel(g.matvec(x).cpu().numpy(), yo) <= 1e-10
     g.close()
     g32 = H.H2Matrix(P, kernel, prm, 1e-6, 40, r1=r, r2=2 * r, precision=32)
-    assert g32.info()["bytes_B"] == 4 * (upper if sym else full)
+    k32, k32v = g32.export("rank"), g32.export("rank_v")  # the FP32 IDs' own ranks
+    blk32 = k32[rows].astype(np.int64) * k32v[col]
+    assert g32.info()["bytes_B"] == 4 * int(np.sum(blk32[col > rows]) if sym else np.sum(blk32))
     y32 = g32.matvec(x.astype(np.float32)).cpu().numpy().astype(np.float64)
     assert _rel(y32, yo) <= 1e-6
     g32.close()
@@ -393,28 +395,50 @@ def test_invalid_points_rejected(H):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("kernel,prm,d,n,leaf,r", [("coulomb", 1.0, 3, 4096, 64, 0), ("gaussian", 0.1, 2, 20000, 128, 0),
+@pytest.mark.parametrize("tol", [1e-6, 1e-5])
+@pytest.mark.parametrize("kernel,prm,d,n,leaf,r", [("coulomb", 1.0, 3, 5000, 40, 0), ("gaussian", 0.1, 2, 20000, 128, 0),
                                                    ("matern32", 0.2, 3, 3000, 40, 0),
-                                                   ("advection", 2.0, 3, 3000, 32, 216)])
-def test_precision_mode_against_fp64_oracle(H, kernel, prm, d, n, leaf, r):
-    """Precision mode (FP32 blocks, FP32 apply, compensated nearfield): the
-    structure and the skeletons are the FP64 path's (the ID stays FP64), and
-    the FP32 product is within 1e-6 of the FP64 oracle's (a few FP32 ulps
-    accumulated over the sweeps)."""
-    rng = np.random.default_rng(77 + d)
+                                                   ("advection", 2.0, 3, 3000, 32, 125)])
+def test_precision_mode_against_fp64_oracle(H, kernel, prm, d, n, leaf, r, tol):
+    """Precision mode: FP32 blocks and apply with compensated block sums;
+    at tol >= 1e-5 the IDs too run in FP32 (FP32 kernel entries and
+    Householder updates, FP64 column norms, down-dates and T), at 1e-6 they
+    stay FP64.  Tree, lists, r1, r2, X* and Y* are the FP64 oracle's (HiDR
+    is geometric).  FP64 IDs give the oracle's ranks exactly; FP32 IDs
+    resolve near-ties of the pivoting otherwise and their rounding noise can
+    add a column, so per level their ranks lie within -3% / +6% of the
+    oracle's.  The product is within the tolerance of the dense product and
+    within twice that of the FP64 oracle's product."""
+    rng = np.random.default_rng(177 + d)
     P = rng.random((n, d))
     x = rng.standard_normal((4, n))
-    _say(f"precision32 {kernel}-d{d}-n{n}")
-    g = H.H2Matrix(P, kernel, prm, 1e-6, leaf, precision=32, r1=r, r2=2 * r)
-    o = O.H2Oracle(P, kernel, prm, tol=1e-6, leaf=leaf, r1=r, r2=2 * r)
+    _say(f"precision32 {kernel}-d{d}-n{n} tol {tol}")
+    g = H.H2Matrix(P, kernel, prm, tol, leaf, precision=32, r1=r, r2=2 * r)
+    o = O.H2Oracle(P, kernel, prm, tol=tol, leaf=leaf, r1=r, r2=2 * r)
     assert g.info()["precision"] == 32
-    for name in ("perm", "il_col", "near_col", "rank", "rank_v"):
+    for name in ("perm", "il_col", "near_col"):
         assert np.array_equal(g.export(name), o.get(name)), name
+    assert (g.info()["r1"], g.info()["r2"]) == (o.info()["r1"], o.info()["r2"])
+    for i in range(1, o.info()["nnode"], 7):
+        assert np.array_equal(g.export("ystar", i), o.node_list("ystar", i)), i
+    gr, orr, dep = g.export("rank"), o.get("rank"), g.export("depth")
+    for L in range(1, int(dep.max()) + 1):
+        a, b = int(gr[dep == L].sum()), int(orr[dep == L].sum())
+        _say(f"precision32 depth {L}: rank sum {a} (FP64 oracle {b})")
+        if tol < 1e-5:
+            assert a == b
+        else:
+            assert -max(2, 0.03 * b) <= a - b <= max(2, 0.06 * b)
+    if tol < 1e-5:
+        assert np.array_equal(gr, orr)
     y = g.matvec(x.astype(np.float32)).cpu().numpy().astype(np.float64)
     yo = o.matvec(x)
-    err = max(_rel(y[r], yo[r]) for r in range(4))
-    _say(f"precision32 max rel diff vs FP64 oracle {err:.3e}")
-    assert err <= 1e-6
+    ref = O.dense_rows(P, kernel, prm, x)
+    err = max(_rel(y[q], yo[q]) for q in range(4))
+    err_d = max(_rel(y[q], ref[q]) for q in range(4))
+    _say(f"precision32 max rel diff vs FP64 oracle {err:.3e}, vs dense {err_d:.3e}")
+    assert err_d <= tol
+    assert err <= 2 * tol
 
 
 def test_batched_build_equals_solo(H):
