@@ -533,7 +533,7 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     const int* __restrict__ il_ptr, const int* __restrict__ il_col, const double* __restrict__ center,
     const double* __restrict__ side, const int* __restrict__ xs_cnt, const int* __restrict__ xs_idx,
     const double* __restrict__ xs_pts, int r1, int* __restrict__ ys_cnt, int* __restrict__ ys_idx, int ys_stride,
-    int k)
+    int k, int nl)
 {
     __shared__ double red[TB];
     __shared__ int scan_sh[TB];
@@ -554,7 +554,13 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     constexpr int QPT = MAXQ / TB;
     constexpr int d = D;
 
-    const int i = lo_node + blockIdx.x;
+    // workgroup ids go round-robin over the 8 XCDs: each XCD takes a
+    // contiguous range of the level's nodes, so that the boxes shared by
+    // neighbouring nodes' interaction lists are read through one L2
+    const int xper = (nl + 7) / 8;
+    const int t = (int)(blockIdx.x % 8) * xper + (int)(blockIdx.x / 8);
+    if (t >= nl) return;
+    const int i = lo_node + t;
     const int p = parent[i];
     const int np_ = p > 0 ? ys_cnt[p] : 0;
     const int* yp = ys_idx + (int64_t)(p > 0 ? p : 0) * ys_stride;
@@ -946,14 +952,15 @@ __global__ __launch_bounds__(TB) void k_up_fill(int lo, const int* __restrict__ 
 template <int D>
 void launch_down_d(Handle& h, int lo, int nl, const double* xs_pts, hipStream_t s)
 {
+    const unsigned grid = 8u * (unsigned)((nl + 7) / 8);
     if (h.r2 <= 1024)
-        k_datareduct_down<D, 1024><<<nl, TB, 0, s>>>(lo, h.pts.p, h.n, h.parent.p, h.il_ptr.p, h.il_col.p,
-                                                     h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, xs_pts, h.r1,
-                                                     h.ys_cnt.p, h.ys_idx.p, h.ys_stride, h.r2);
+        k_datareduct_down<D, 1024><<<grid, TB, 0, s>>>(lo, h.pts.p, h.n, h.parent.p, h.il_ptr.p, h.il_col.p,
+                                                       h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, xs_pts, h.r1,
+                                                       h.ys_cnt.p, h.ys_idx.p, h.ys_stride, h.r2, nl);
     else
-        k_datareduct_down<D, MAXQ_ALL><<<nl, TB, 0, s>>>(lo, h.pts.p, h.n, h.parent.p, h.il_ptr.p, h.il_col.p,
-                                                         h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, xs_pts, h.r1,
-                                                         h.ys_cnt.p, h.ys_idx.p, h.ys_stride, h.r2);
+        k_datareduct_down<D, MAXQ_ALL><<<grid, TB, 0, s>>>(lo, h.pts.p, h.n, h.parent.p, h.il_ptr.p, h.il_col.p,
+                                                           h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, xs_pts,
+                                                           h.r1, h.ys_cnt.p, h.ys_idx.p, h.ys_stride, h.r2, nl);
 }
 
 void launch_down(Handle& h, int lo, int nl, const double* xs_pts, hipStream_t s)

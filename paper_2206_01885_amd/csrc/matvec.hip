@@ -25,32 +25,12 @@
 
 #include "common.h"
 #include "kappa.h"
+#include "mfma.h"
 
 namespace h2 {
 namespace {
 
 constexpr int TB = 256;
-
-typedef double double4_t __attribute__((ext_vector_type(4)));
-typedef float float4_t __attribute__((ext_vector_type(4)));
-
-// 16x16x4 matrix-core step per value type.  Operand layout (both types):
-// A lane l = A[l%16][l/16], B lane l = B[l/16][l%16].  Result register r of
-// lane l holds row 4r + l/16 (FP64) or 4(l/16) + r (FP32) of column l%16.
-template <class T>
-struct Mfma;
-template <>
-struct Mfma<double> {
-    typedef double4_t V;
-    __device__ static V step(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-    __device__ static int row(int r, int k4) { return 4 * r + k4; }
-};
-template <>
-struct Mfma<float> {
-    typedef float4_t V;
-    __device__ static V step(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-    __device__ static int row(int r, int k4) { return 4 * k4 + r; }
-};
 
 // n contiguous values loaded as one (unaligned) vector access
 template <class T, int N>

@@ -89,6 +89,7 @@ def _compare_reduction_and_bases(g, o, t_rtol=None, tol=1e-6, sides=(0,)):
                 bad["skel" + v] += 1
             Tg, To = g.export("T" + v, i), o.node_T(i, side=side).ravel()
             if To.size:
+                assert np.all(np.isfinite(Tg)), ("T not finite", i)
                 tmax = max(tmax, np.max(np.abs(Tg - To)) / max(np.max(np.abs(To)), 1e-300))
     _say(f"mismatching nodes: {bad}, max rel |T diff| {tmax:.3e}")
     assert all(v == 0 for v in bad.values()), bad
