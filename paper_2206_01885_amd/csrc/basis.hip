@@ -281,45 +281,52 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbu
     const double prm = tk.prm;
     const double dsgn = tk.swap ? -1.0 : 1.0;  // column side: kappa(y, x)
     const int lane = threadIdx.x;
-    double* ycrd = scr_d + BR * NT;  // 3 x BR: the row block's points
+    constexpr int SL = 8;              // rows per evaluation slice
+    static_assert(BR % SL == 0, "row block");
+    double* ycrd = scr_d + SL * NT;  // 3 x BR: the row block's points
     for (int64_t e = lane; e < (int64_t)m * m; e += NT) R[e] = 0.0;
     // this lane's column points: in registers for one column per lane,
     // otherwise read where needed (L1 hits; registers kept for occupancy)
     XCoords<CPL> xr(pts, ld, xi, lane, NT, m, d);
     __syncthreads();
-    ET bc[CPL][BR], tail[CPL];
+    ET bc[CPL][BR];
+    // squared norm of a column's block part, in row order (formed by the
+    // column's owner when it publishes the column)
+    auto sumsq = [](const ET* b) {
+        ET ts = ET(0);
+#pragma unroll
+        for (int r = 0; r < BR; ++r) ts = fma_e(b[r], b[r], ts);
+        return ts;
+    };
     for (int r0 = 0; r0 < s0; r0 += BR) {
         const int nb = min(BR, s0 - r0);
         // the row block's points, staged once in LDS for all lanes
         if (lane < nb)
             for (int a = 0; a < d; ++a) ycrd[a * BR + lane] = pts[a * ld + yi[r0 + lane]];
         lds_barrier();
-        // this lane's block entries (evaluated through a lane-private LDS
-        // slice, scr[r * NT + lane]; squared distances accumulated in
-        // coordinate order as dist2 does) and their squared sums
+        // this lane's block entries (evaluated SL rows at a time through a
+        // lane-private LDS slice, scr[r * NT + lane]; squared distances
+        // accumulated in coordinate order as dist2 does)
 #pragma unroll
         for (int t = 0; t < CPL; ++t) {
             const int c = lane + t * NT;
-            if (c < m) {
-                for (int r = 0; r < nb; ++r) {
-                    double r2 = 0.0, xy = 0.0, e0 = 0.0;
-                    if constexpr (FAM == FAM_COSINE)
-                        for (int a = 0; a < d; ++a) xy = xy + xr.get(t, a) * ycrd[a * BR + r];
-                    else
-                        for (int a = 0; a < d; ++a) {
-                            const double ea = xr.get(t, a) - ycrd[a * BR + r];
-                            if (a == 0) e0 = ea;
-                            r2 = r2 + ea * ea;
-                        }
-                    scr[r * NT + lane] = kappa_id<ET, FAM>(kid, prm, r2, xy, dsgn * e0);
-                }
-            }
-            tail[t] = ET(0);
 #pragma unroll
-            for (int r = 0; r < BR; ++r) {
-                const ET v = (c < m && r < nb) ? scr[r * NT + lane] : ET(0);
-                bc[t][r] = v;
-                tail[t] = fma_e(v, v, tail[t]);
+            for (int k0 = 0; k0 < BR; k0 += SL) {
+                if (c < m)
+                    for (int r = 0; r < SL && k0 + r < nb; ++r) {
+                        double r2 = 0.0, xy = 0.0, e0 = 0.0;
+                        if constexpr (FAM == FAM_COSINE)
+                            for (int a = 0; a < d; ++a) xy = xy + xr.get(t, a) * ycrd[a * BR + k0 + r];
+                        else
+                            for (int a = 0; a < d; ++a) {
+                                const double ea = xr.get(t, a) - ycrd[a * BR + k0 + r];
+                                if (a == 0) e0 = ea;
+                                r2 = r2 + ea * ea;
+                            }
+                        scr[r * NT + lane] = kappa_id<ET, FAM>(kid, prm, r2, xy, dsgn * e0);
+                    }
+#pragma unroll
+                for (int r = 0; r < SL; ++r) bc[t][k0 + r] = (c < m && k0 + r < nb) ? scr[r * NT + lane] : ET(0);
             }
         }
         ET rn[CPL];
@@ -332,7 +339,7 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbu
         if (lane == 0) {
 #pragma unroll
             for (int r = 0; r < BR; ++r) colbuf[r] = bc[0][r];
-            nubuf[0] = tail[0];
+            nubuf[0] = sumsq(bc[0]);
             x0buf[0] = rn[0];
         }
         lds_barrier();
@@ -351,25 +358,34 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbu
                 const ET alpha = x0 >= ET(0) ? -sqrt(x0 * x0 + nub) : sqrt(x0 * x0 + nub);
                 const ET v0 = x0 - alpha;
                 const ET vtv = ET(2) * fabs(alpha) * (fabs(alpha) + fabs(x0));
-                ET cjr[BR];
-#pragma unroll
-                for (int r = 0; r < BR; ++r) cjr[r] = cj[r];
 #pragma unroll
                 for (int t = 0; t < CPL; ++t) {
                     const int c = lane + t * NT;
                     if (c > j && c < m) {
+                        // the published column is read from LDS (broadcast)
+                        // in chunks of 8, once for the dot product and once
+                        // for the update: holding it in registers between
+                        // them would cost 2 BR registers and occupancy
                         ET w = v0 * rc[t];
 #pragma unroll
-                        for (int r = 0; r < BR; ++r) w = fma_e(cjr[r], bc[t][r], w);
+                        for (int r0 = 0; r0 < BR; r0 += 8) {
+                            ET cv[8];
+#pragma unroll
+                            for (int r = 0; r < 8; ++r) cv[r] = cj[r0 + r];
+#pragma unroll
+                            for (int r = 0; r < 8; ++r) w = fma_e(cv[r], bc[t][r0 + r], w);
+                        }
                         const ET f = ET(2) * w / vtv;
                         R[(int64_t)j * m + c] = rc[t] - f * v0;
-                        ET ts = ET(0);
+                        __asm__ __volatile__("" ::: "memory");  // re-read, do not keep
 #pragma unroll
-                        for (int r = 0; r < BR; ++r) {
-                            bc[t][r] = fma_e(-f, cjr[r], bc[t][r]);
-                            ts = fma_e(bc[t][r], bc[t][r], ts);
+                        for (int r0 = 0; r0 < BR; r0 += 8) {
+                            ET cv[8];
+#pragma unroll
+                            for (int r = 0; r < 8; ++r) cv[r] = cj[r0 + r];
+#pragma unroll
+                            for (int r = 0; r < 8; ++r) bc[t][r0 + r] = fma_e(-f, cv[r], bc[t][r0 + r]);
                         }
-                        tail[t] = ts;
                     }
                 }
                 if (lane == j % NT) R[(int64_t)j * m + j] = alpha;
@@ -384,7 +400,7 @@ __device__ void tsqr_fold(const IdTask& tk, int m, int s0, RPtr R, double* colbu
                     if (t == t1) {
 #pragma unroll
                         for (int r = 0; r < BR; ++r) nb1[r] = bc[t][r];
-                        nubuf[(j + 1) & 1] = tail[t];
+                        nubuf[(j + 1) & 1] = sumsq(bc[t]);
                         x0buf[(j + 1) & 1] = rn[t];
                     }
             }
@@ -1014,7 +1030,15 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
     // otherwise read where needed (L1 hits; registers kept for occupancy)
     XCoords<CPL> xr(pts, ld, tk.x_idx, lane, NT, m, d);
     __syncthreads();
-    ET bc[CPL][BR], tail[CPL], rn[D][CPL];
+    ET bc[CPL][BR], rn[D][CPL];
+    // squared norm of a column's block part (formed by the column's owner
+    // when it publishes the column)
+    auto sumsq = [](const ET* b) {
+        ET t4[4] = {ET(0), ET(0), ET(0), ET(0)};
+#pragma unroll
+        for (int r = 0; r < BR; ++r) t4[r & 3] = fma_e(b[r], b[r], t4[r & 3]);
+        return (t4[0] + t4[1]) + (t4[2] + t4[3]);
+    };
     for (int r0 = 0; r0 < s0; r0 += BR) {
         const int nb = min(BR, s0 - r0);
         // the row block's points, staged once in LDS for all lanes
@@ -1043,10 +1067,6 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
 #pragma unroll
                 for (int r = 0; r < SL; ++r) bc[t][k0 + r] = (c < m && k0 + r < nb) ? scr[r * NT + lane] : ET(0);
             }
-            ET t4[4] = {ET(0), ET(0), ET(0), ET(0)};
-#pragma unroll
-            for (int r = 0; r < BR; ++r) t4[r & 3] = fma_e(bc[t][r], bc[t][r], t4[r & 3]);
-            tail[t] = (t4[0] + t4[1]) + (t4[2] + t4[3]);
         }
 #pragma unroll
         for (int q = 0; q < D; ++q)
@@ -1058,7 +1078,7 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
         if (lane == 0) {
 #pragma unroll
             for (int r = 0; r < BR; ++r) colbuf[r] = bc[0][r];
-            nubuf[0] = tail[0];
+            nubuf[0] = sumsq(bc[0]);
             x0buf[0] = rn[0][0];
         }
         lds_barrier();
@@ -1099,19 +1119,14 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
                                 }
                                 const ET f = ET(2) * ((w4[0] + w4[1]) + (w4[2] + w4[3])) / vtv;
                                 R[(int64_t)j * m + c] = rc[t] - f * v0;
-                                ET t4[4] = {ET(0), ET(0), ET(0), ET(0)};
 #pragma unroll
                                 for (int r0 = 0; r0 < BR; r0 += 8) {
                                     ET cv[8];
 #pragma unroll
                                     for (int r = 0; r < 8; ++r) cv[r] = cj[r0 + r];
 #pragma unroll
-                                    for (int r = 0; r < 8; ++r) {
-                                        bc[t][r0 + r] = fma_e(-f, cv[r], bc[t][r0 + r]);
-                                        t4[r & 3] = fma_e(bc[t][r0 + r], bc[t][r0 + r], t4[r & 3]);
-                                    }
+                                    for (int r = 0; r < 8; ++r) bc[t][r0 + r] = fma_e(-f, cv[r], bc[t][r0 + r]);
                                 }
-                                tail[t] = (t4[0] + t4[1]) + (t4[2] + t4[3]);
                             }
                         }
                         if (lane == j % NT) R[(int64_t)j * m + j] = alpha;
@@ -1125,7 +1140,7 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
                             if (t == t1) {
 #pragma unroll
                                 for (int r = 0; r < BR; ++r) nb1[r] = bc[t][r];
-                                nubuf[(j + 1) & 1] = tail[t];
+                                nubuf[(j + 1) & 1] = sumsq(bc[t]);
                                 x0buf[(j + 1) & 1] = rn[(q + 1) % D][t];
                             }
                     }
@@ -1146,8 +1161,7 @@ void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdPro
     std::vector<IdTask> tasks(tasks_in);
     // Launch classes (lanes per task, where the matrix lives, columns per lane
     // and rows per block of the compression):
-    //   0 / 3  64 lanes, matrix in LDS, m <= 64 (split at 32 KiB of LDS so that
-    //          small problems are not limited to the occupancy of the largest)
+    //   0      64 lanes, matrix in LDS, m <= 64 (one launch per LDS bin)
     //   1      64 lanes, global matrix, m <= 64
     //   4 / 5  64 < m <= 1024 and s > 1.5 m: compression by k_id_fold (many
     //          tasks per CU), then the blocked pivoted QR of the m x m
@@ -1156,7 +1170,7 @@ void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdPro
     struct Cls {
         int nt, cpl, br;
     };
-    const Cls CL[6] = {{64, 1, 32}, {64, 1, 16}, {WNT, 2, 16}, {64, 1, 32}, {WNT, 2, 16}, {256, 1, 16}};
+    const Cls CL[6] = {{64, 1, 32}, {64, 1, 16}, {WNT, 2, 16}, {64, 1, 32}, {WNT, 2, 16}, {256, 1, 16}};  // 3: unused
     const size_t LDS_CAP = 80 * 1024;     // bytes per workgroup
     auto lds_need = [&](const IdTask& t, int c) -> size_t {
         const Cls& k = CL[c];
@@ -1167,11 +1181,18 @@ void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdPro
         if (c == 4 || c == 5) return std::max((size_t)sr, qr) * sizeof(double);
         // published column (2 x BR), its norms and diagonal entries (2 x 2),
         // the lanes' evaluation slices, the row block's points (3 x BR)
-        const size_t pub = comp ? 2 * k.br + 4 + (size_t)k.br * k.nt + 3 * k.br : 0;
+        const size_t pub = comp ? 2 * k.br + 4 + (size_t)8 * k.nt + 3 * k.br : 0;
         if (c == 0 || c == 3) return ((size_t)sr + (size_t)sr * t.m + pub) * sizeof(double);
         return std::max(std::max((size_t)sr, qr), pub) * sizeof(double);
     };
-    std::vector<int> cls(np);
+    // The narrow nodes in LDS go out in one launch per size bin of their LDS
+    // need (a launch reserves its largest need for every workgroup), so that
+    // the bulk of the leaves is not held to the occupancy of the largest.
+    constexpr int NBIN = 12;
+    const size_t BIN_CAP[NBIN] = {12 << 10, 14 << 10, 16 << 10, 18 << 10, 20 << 10, 24 << 10,
+                                  28 << 10, 32 << 10, 40 << 10, 48 << 10, 64 << 10, 80 << 10};
+    static_assert(80 << 10 == LDS_CAP, "last bin");
+    std::vector<int> cls(np), bin(np, -1);
     for (int p = 0; p < np; ++p) {
         const IdTask& t = tasks[p];
         if (t.m > 64) {
@@ -1180,13 +1201,28 @@ void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdPro
             tasks[p].folded = comp ? 1 : 0;
         } else {
             const size_t need = lds_need(t, 0);
-            cls[p] = need <= 32 * 1024 ? 0 : (need <= LDS_CAP ? 3 : 1);
+            cls[p] = need <= LDS_CAP ? 0 : 1;
+            if (cls[p] == 0)
+                for (int b = NBIN - 1; b >= 0 && need <= BIN_CAP[b]; --b) bin[p] = b;
         }
     }
-    // narrow classes first, then the wide ones (timed together)
-    const int ORD[6] = {0, 3, 1, 5, 4, 2};
+    // narrow classes first (the LDS bins, then the global one), then the
+    // wide ones (timed together)
     std::vector<int> order;
     order.reserve(np);
+    int bcnt[NBIN] = {}, boff[NBIN] = {};
+    size_t blds[NBIN] = {};
+    for (int b = 0; b < NBIN; ++b) {
+        boff[b] = (int)order.size();
+        blds[b] = 8;
+        for (int p = 0; p < np; ++p)
+            if (bin[p] == b) {
+                order.push_back(p);
+                ++bcnt[b];
+                blds[b] = std::max(blds[b], lds_need(tasks[p], 0));
+            }
+    }
+    const int ORD[4] = {1, 5, 4, 2};
     int cnt[6] = {0, 0, 0, 0, 0, 0}, off[6] = {0, 0, 0, 0, 0, 0};
     size_t lds[6] = {8, 8, 8, 8, 8, 8};
     for (int c : ORD) {
@@ -1225,8 +1261,6 @@ void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdPro
         if (cnt[c] == 0) return;
         const int* ord = d_order.p + off[c];
         switch (c) {
-        case 0:
-        case 3: k_batched_id<64, true, 1, 32, false, FAM, ET><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
         case 1: k_batched_id<64, false, 1, 16, false, FAM, ET><<<cnt[c], 64, lds[c], s>>>(d_tasks.p, ord); break;
         case 4: k_batched_id<WNT, false, 2, 16, true, FAM, ET><<<cnt[c], WNT, lds[c], s>>>(d_tasks.p, ord); break;
         case 5: k_batched_id<256, false, 1, 16, true, FAM, ET><<<cnt[c], 256, lds[c], s>>>(d_tasks.p, ord); break;
@@ -1234,8 +1268,11 @@ void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdPro
         }
         H2_LAUNCH_CHECK();
     };
-    launch(0);
-    launch(3);
+    for (int b = 0; b < NBIN; ++b)
+        if (bcnt[b] > 0) {
+            k_batched_id<64, true, 1, 32, false, FAM, ET><<<bcnt[b], 64, blds[b], s>>>(d_tasks.p, d_order.p + boff[b]);
+            H2_LAUNCH_CHECK();
+        }
     launch(1);
     if (prof) H2_HIP(hipEventRecord(ev[1], s));
     if (!fold[0].empty())
