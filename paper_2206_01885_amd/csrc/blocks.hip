@@ -106,10 +106,64 @@ struct PtSet {
 // (cols_j, from the column set) are loaded once, one per lane, and the column
 // point of each block column is broadcast with a lane shuffle.  The block is
 // column-major (entry (t,u) at u*rows_i + t); with rows_i <= 32 the two
-// half-waves fill two columns per pass.
-template <class OutT, int FAM>
+// half-waves fill two columns per pass.  The dimension D and the kernel id
+// KID are compile-time constants of the loop (the kernel's switch over the
+// kernel id sits outside it), so an entry costs its distance, the kernel
+// function and one store.
+template <class OutT, int FAM, int D, int KID>
+__device__ __forceinline__ void blocks_eval_one(int lane, int ki, int kj, const double* __restrict__ xs, int64_t ld,
+                                                int64_t bi, const double* __restrict__ ys, int64_t lc, int64_t bj,
+                                                double prm, OutT* __restrict__ o)
+{
+    for (int t0 = 0; t0 < ki; t0 += 64) {
+        const bool half = ki - t0 <= 32;  // two columns per pass
+        const int t = half ? t0 + (lane & 31) : t0 + lane;
+        const int du = half ? (lane >> 5) : 0;
+        const int su = half ? 2 : 1;
+        double xi[3] = {0.0, 0.0, 0.0};
+        if (t < ki)
+#pragma unroll
+            for (int a = 0; a < D; ++a) xi[a] = xs[a * ld + bi + t];
+        for (int u0 = 0; u0 < kj; u0 += 64) {
+            const int uc = min(64, kj - u0);
+            double y[3] = {0.0, 0.0, 0.0};
+            if (lane < uc)
+#pragma unroll
+                for (int a = 0; a < D; ++a) y[a] = ys[a * lc + bj + u0 + lane];
+            OutT* op = o + (int64_t)(u0 + du) * ki + t;
+            const int64_t step = (int64_t)su * ki;
+            // wave-uniform trip count: every lane takes part in every shuffle
+            for (int ub = 0; ub < uc; ub += su, op += step) {
+                const int uu = ub + du;
+                const int src = uu < uc ? uu : uc - 1;
+                double sc[3];
+#pragma unroll
+                for (int a = 0; a < D; ++a) sc[a] = __shfl(y[a], src, 64);
+                double r2 = 0.0, xy = 0.0;  // xy: the cosine kernel's inner product
+                // (fused multiply-adds written out, as in the apply's
+                // evaluation of the same entries)
+                if constexpr (FAM == FAM_COSINE) {
+                    xy = xi[0] * sc[0];
+#pragma unroll
+                    for (int a = 1; a < D; ++a) xy = __builtin_fma(xi[a], sc[a], xy);
+                } else {
+                    const double a0 = sc[0] - xi[0];
+                    r2 = a0 * a0;
+#pragma unroll
+                    for (int a = 1; a < D; ++a) {
+                        const double aa = sc[a] - xi[a];
+                        r2 = __builtin_fma(aa, aa, r2);
+                    }
+                }
+                if (t < ki && uu < uc) *op = kappa_store<OutT, FAM>(KID, prm, r2, xy, xi[0] - sc[0]);
+            }
+        }
+    }
+}
+
+template <class OutT, int FAM, int D>
 __global__ __launch_bounds__(TB) void k_blocks_eval(int64_t nent, const int* __restrict__ erow,
-                                                    const int* __restrict__ col, PtSet rs, PtSet cs, int d, int kid,
+                                                    const int* __restrict__ col, PtSet rs, PtSet cs, int kid,
                                                     double prm, const int64_t* __restrict__ off, int upper,
                                                     OutT* __restrict__ out)
 {
@@ -122,59 +176,42 @@ __global__ __launch_bounds__(TB) void k_blocks_eval(int64_t nent, const int* __r
     if (ki == 0 || kj == 0) return;
     OutT* o = out + off[e];
     const int64_t bi = rs.xo[i], bj = cs.xo[j];
-    const double* xs = rs.xs;
-    const double* ys = cs.xs;
-    const int64_t ld = rs.ld, lc = cs.ld;
-    for (int t0 = 0; t0 < ki; t0 += 64) {
-        const bool half = ki - t0 <= 32;  // two columns per pass
-        const int t = half ? t0 + (lane & 31) : t0 + lane;
-        const int du = half ? (lane >> 5) : 0;
-        const int su = half ? 2 : 1;
-        double xi0 = 0.0, xi1 = 0.0, xi2 = 0.0;
-        if (t < ki) {
-            xi0 = xs[bi + t];
-            if (d > 1) xi1 = xs[ld + bi + t];
-            if (d > 2) xi2 = xs[2 * ld + bi + t];
+    if constexpr (FAM == FAM_RADIAL) {
+        switch (kid) {
+        case H2_COULOMB:
+            blocks_eval_one<OutT, FAM, D, H2_COULOMB>(lane, ki, kj, rs.xs, rs.ld, bi, cs.xs, cs.ld, bj, prm, o);
+            break;
+        case H2_GAUSSIAN:
+            blocks_eval_one<OutT, FAM, D, H2_GAUSSIAN>(lane, ki, kj, rs.xs, rs.ld, bi, cs.xs, cs.ld, bj, prm, o);
+            break;
+        case H2_EXPONENTIAL:
+            blocks_eval_one<OutT, FAM, D, H2_EXPONENTIAL>(lane, ki, kj, rs.xs, rs.ld, bi, cs.xs, cs.ld, bj, prm, o);
+            break;
+        case H2_BUMP:
+            blocks_eval_one<OutT, FAM, D, H2_BUMP>(lane, ki, kj, rs.xs, rs.ld, bi, cs.xs, cs.ld, bj, prm, o);
+            break;
+        default:
+            blocks_eval_one<OutT, FAM, D, H2_MATERN32>(lane, ki, kj, rs.xs, rs.ld, bi, cs.xs, cs.ld, bj, prm, o);
         }
-        for (int u0 = 0; u0 < kj; u0 += 64) {
-            const int uc = min(64, kj - u0);
-            double y0 = 0.0, y1 = 0.0, y2 = 0.0;
-            if (lane < uc) {
-                y0 = ys[bj + u0 + lane];
-                if (d > 1) y1 = ys[lc + bj + u0 + lane];
-                if (d > 2) y2 = ys[2 * lc + bj + u0 + lane];
-            }
-            // wave-uniform trip count: every lane takes part in every shuffle
-            for (int ub = 0; ub < uc; ub += su) {
-                const int uu = ub + du;
-                const int src = uu < uc ? uu : uc - 1;
-                const double s0 = __shfl(y0, src, 64);
-                const double s1 = d > 1 ? __shfl(y1, src, 64) : 0.0;
-                const double s2 = d > 2 ? __shfl(y2, src, 64) : 0.0;
-                double r2 = 0.0, xy = 0.0;  // xy: the cosine kernel's inner product
-                if constexpr (FAM == FAM_COSINE) {
-                    xy = xi0 * s0;
-                    if (d > 1) xy += xi1 * s1;
-                    if (d > 2) xy += xi2 * s2;
-                } else {
-                    const double a0 = s0 - xi0;
-                    r2 = a0 * a0;
-                    if (d > 1) {
-                        const double a1 = s1 - xi1;
-                        r2 += a1 * a1;
-                    }
-                    if (d > 2) {
-                        const double a2 = s2 - xi2;
-                        r2 += a2 * a2;
-                    }
-                }
-                if (t < ki && uu < uc) o[(int64_t)(u0 + uu) * ki + t] = kappa_store<OutT, FAM>(kid, prm, r2, xy, xi0 - s0);
-            }
-        }
+    } else {
+        blocks_eval_one<OutT, FAM, D, 0>(lane, ki, kj, rs.xs, rs.ld, bi, cs.xs, cs.ld, bj, prm, o);
     }
 }
 
-// Each kernel family's blocks come from their own instance (see kappa_fam).
+// Each kernel family's blocks come from their own instance (see kappa_fam),
+// one per dimension.
+template <class OutT, int FAM>
+void launch_blocks_eval_d(unsigned nb, int64_t nent, const int* erow, const int* col, const PtSet& rs,
+                          const PtSet& cs, int d, int kid, double prm, const int64_t* off, int upper, OutT* out,
+                          hipStream_t s)
+{
+    switch (d) {
+    case 1: k_blocks_eval<OutT, FAM, 1><<<nb, TB, 0, s>>>(nent, erow, col, rs, cs, kid, prm, off, upper, out); break;
+    case 2: k_blocks_eval<OutT, FAM, 2><<<nb, TB, 0, s>>>(nent, erow, col, rs, cs, kid, prm, off, upper, out); break;
+    default: k_blocks_eval<OutT, FAM, 3><<<nb, TB, 0, s>>>(nent, erow, col, rs, cs, kid, prm, off, upper, out);
+    }
+}
+
 template <class OutT>
 void launch_blocks_eval(int64_t nent, const int* erow, const int* col, const PtSet& rs, const PtSet& cs, int d,
                         int kid, double prm, const int64_t* off, int upper, OutT* out, hipStream_t s)
@@ -182,13 +219,13 @@ void launch_blocks_eval(int64_t nent, const int* erow, const int* col, const PtS
     const unsigned nb = (unsigned)blocks_for(nent, TB / 64);
     switch (kernel_family(kid)) {
     case FAM_COSINE:
-        k_blocks_eval<OutT, FAM_COSINE><<<nb, TB, 0, s>>>(nent, erow, col, rs, cs, d, kid, prm, off, upper, out);
+        launch_blocks_eval_d<OutT, FAM_COSINE>(nb, nent, erow, col, rs, cs, d, kid, prm, off, upper, out, s);
         break;
     case FAM_ADVECTION:
-        k_blocks_eval<OutT, FAM_ADVECTION><<<nb, TB, 0, s>>>(nent, erow, col, rs, cs, d, kid, prm, off, upper, out);
+        launch_blocks_eval_d<OutT, FAM_ADVECTION>(nb, nent, erow, col, rs, cs, d, kid, prm, off, upper, out, s);
         break;
     default:
-        k_blocks_eval<OutT, FAM_RADIAL><<<nb, TB, 0, s>>>(nent, erow, col, rs, cs, d, kid, prm, off, upper, out);
+        launch_blocks_eval_d<OutT, FAM_RADIAL>(nb, nent, erow, col, rs, cs, d, kid, prm, off, upper, out, s);
     }
     H2_LAUNCH_CHECK();
 }

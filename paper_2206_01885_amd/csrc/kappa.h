@@ -62,12 +62,14 @@ __device__ __forceinline__ double kappa_fam(int kid, double prm, double r2, doub
 
 // 1/sqrt(r2) for r2 > 0: the hardware estimate refined by two Newton steps
 // y <- y (3 - r2 y^2) / 2 (each roughly doubles the correct bits).
+// (Fused multiply-adds written out, so that every kernel that evaluates
+// entries forms them alike, whatever the contraction mode of its file.)
 __device__ __forceinline__ double rsqrt_nr(double r2)
 {
     double y = __builtin_amdgcn_rsq(r2);
-    double h = 0.5 * r2;
-    y = y * (1.5 - h * y * y);
-    y = y * (1.5 - h * y * y);
+    const double h = 0.5 * r2;
+    y = y * __builtin_fma(-(h * y), y, 1.5);
+    y = y * __builtin_fma(-(h * y), y, 1.5);
     return y;
 }
 

@@ -312,20 +312,22 @@ __global__ __launch_bounds__(64) void k_coupling_otf(int ntask, const int* __res
                     const double s1 = d > 1 ? sy[1][u] : 0.0;
                     const double s2 = d > 2 ? sy[2][u] : 0.0;
                     double r2 = 0.0, xy = 0.0;
+                    // (fused multiply-adds written out, as in the block
+                    // evaluation of the stored path)
                     if constexpr (FAM == FAM_COSINE) {
                         xy = x0 * s0;
-                        if (d > 1) xy += x1 * s1;
-                        if (d > 2) xy += x2 * s2;
+                        if (d > 1) xy = __builtin_fma(x1, s1, xy);
+                        if (d > 2) xy = __builtin_fma(x2, s2, xy);
                     } else {
                         const double a0 = s0 - x0;
                         r2 = a0 * a0;
                         if (d > 1) {
                             const double a1 = s1 - x1;
-                            r2 += a1 * a1;
+                            r2 = __builtin_fma(a1, a1, r2);
                         }
                         if (d > 2) {
                             const double a2 = s2 - x2;
-                            r2 += a2 * a2;
+                            r2 = __builtin_fma(a2, a2, r2);
                         }
                     }
                     const double kv = kappa_store<double, FAM>(kid, prm, r2, xy, x0 - s0);
