@@ -166,6 +166,8 @@ def dense_rows_gpu(P, X, rows, chunk=64, kernel="coulomb", prm=1.0):
             K = torch.where(D > 0, 1.0 / D, torch.zeros_like(D))
         elif kernel == "gaussian":
             K = torch.exp(-D2 / (prm * prm))
+        elif kernel == "exponential":
+            K = torch.exp(-D2.sqrt() / prm)
         elif kernel == "bump":
             K = torch.exp(-1.0 / (1.0 - prm * D2))
         elif kernel == "cosine":
@@ -438,6 +440,22 @@ def bench_serving(args):
     wall_p = time.perf_counter() - t0
     poi = serving.summarize(reqs, wall_p)
     print(f"[bench] poisson {wall_p:.2f} s", file=sys.stderr, flush=True)
+    # accuracy of every request: an untimed pass that keeps the outputs, 256
+    # sampled rows per request against dense rows (torch FP64 on the GPU)
+    reqs = fresh()
+    serving.Server(keep_outputs=True).run(reqs)
+    rng_rows = np.random.default_rng(1006)
+    errs = []
+    for c, r in zip(cfg, reqs):
+        n = int(c["points"].shape[0])
+        rows = np.sort(rng_rows.choice(n, min(256, n), replace=False))
+        P = torch.tensor(c["points"], device="cuda")
+        X = torch.tensor(c["x"], device="cuda")
+        ref = dense_rows_gpu(P, X, torch.tensor(rows, device="cuda"), kernel=c["kernel"], prm=c["prm"])
+        got = torch.tensor(np.asarray(r.y)[:, rows], device="cuda", dtype=torch.float64)
+        errs.append(((got - ref).norm(dim=1) / ref.norm(dim=1)).max().item())
+        del P, X, ref, got
+    print(f"[bench] serving accuracy: max {max(errs):.2e} over {len(errs)} requests", file=sys.stderr, flush=True)
     nrhs = sum(int(c["x"].shape[0]) for c in cfg)
     out = {
         "metric": "H2 serving: p50/p99 request latency and solves/s (build + 8-RHS apply per request)",
@@ -450,6 +468,9 @@ def bench_serving(args):
                             "p99_s": float(np.percentile(lat_plain, 99))},
         "saturation": sat,
         "poisson": dict(poi, offered_load=args.load, offered_requests_per_s=rate),
+        "accuracy": {"rows_per_request": 256, "dense_reference": "torch FP64 on the GPU, all 8 RHS",
+                     "e_dense_max": max(errs), "e_dense_p50": float(np.percentile(errs, 50)),
+                     "e_dense_per_request": errs, "tol": 1e-6},
     }
     print(json.dumps(out), flush=True)
 

@@ -506,6 +506,9 @@ __device__ __forceinline__ int cpqr_blocked(gptr<ET> M, int m, int s, double tol
                 break;
             }
         const int pc = block_min_i<NT>(cand, redi);
+        // no admissible pivot (non-finite norms, e.g. a kernel that
+        // overflowed): stop, as at the rank threshold
+        if (pc >= m) break;
         // F rows of the pivot column and of column j (their owners)
 #pragma unroll
         for (int t = 0; t < CPL; ++t) {
@@ -813,6 +816,9 @@ __global__ __launch_bounds__(NT) void k_batched_id(const IdTask* __restrict__ ta
                 break;
             }
         int pc = block_min_i<NT>(cand, redi);
+        // no admissible pivot (non-finite norms, e.g. a kernel that
+        // overflowed): stop, as at the rank threshold
+        if (pc >= m) break;
         // |R_jj| of the candidate; the step that stops swaps nothing
         if (threadIdx.x == 0) sh_alpha = sqrt(ss[pc]);
         __syncthreads();
