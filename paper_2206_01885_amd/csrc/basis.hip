@@ -1010,7 +1010,7 @@ __global__ __launch_bounds__(TB) void k_xbar_fill(int lo, const int* __restrict_
 // entries, so a step synchronises through LDS only; the R rows a lane needs
 // are loaded D steps ahead into a register ring, and the block entries are
 // evaluated SL rows at a time through a lane-private LDS slice.
-template <int CPL, int BR, int D, int FAM, class ET>
+template <int CPL, int BR, int D, int FAM, class ET, bool REREAD = false>
 __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ tasks, const int* __restrict__ order)
 {
     constexpr int NT = 256, SL = 8;
@@ -1125,6 +1125,9 @@ __global__ __launch_bounds__(256) void k_id_fold(const IdTask* __restrict__ task
                                 }
                                 const ET f = ET(2) * ((w4[0] + w4[1]) + (w4[2] + w4[3])) / vtv;
                                 R[(int64_t)j * m + c] = rc[t] - f * v0;
+                                // REREAD: the published column is read again for the
+                                // update instead of being held (2 BR registers)
+                                if constexpr (REREAD) __asm__ __volatile__("" ::: "memory");
 #pragma unroll
                                 for (int r0 = 0; r0 < BR; r0 += 8) {
                                     ET cv[8];
@@ -1285,7 +1288,7 @@ void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdPro
         k_id_fold<1, 32, 1, FAM, ET><<<(unsigned)fold[0].size(), 256, (2 * 32 + 4 + 8 * 256 + 3 * 32) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[0]);
     if (!fold[1].empty())
-        k_id_fold<2, 16, 1, FAM, ET><<<(unsigned)fold[1].size(), 256, (2 * 16 + 4 + 8 * 256 + 3 * 16) * sizeof(double), s>>>(
+        k_id_fold<2, 32, 1, FAM, ET, true><<<(unsigned)fold[1].size(), 256, (2 * 32 + 4 + 8 * 256 + 3 * 32) * sizeof(double), s>>>(
             d_tasks.p, d_order.p + foff[1]);
     if (!fold[2].empty())
         k_id_fold<4, 8, 1, FAM, ET><<<(unsigned)fold[2].size(), 256, (2 * 8 + 4 + 8 * 256 + 3 * 8) * sizeof(double), s>>>(
