@@ -31,6 +31,7 @@
 // Compiled with -ffp-contract=off: distances round exactly as in the oracle,
 // so the picks are bit-identical.
 #include <cmath>
+#include <type_traits>
 
 #include "common.h"
 
@@ -39,12 +40,14 @@ namespace {
 
 constexpr int TB = 256;
 constexpr int MAXQ_ALL = 4096;  // largest reference set: r2 <= 4096 (two grids of r2/2)
+constexpr int MAXR1 = 2048;     // largest r1 (the options are checked against it)
 
+template <int NTH = TB>
 __device__ inline double block_min(double v, double* sh)
 {
     sh[threadIdx.x] = v;
     __syncthreads();
-    for (int off = TB / 2; off > 0; off >>= 1) {
+    for (int off = NTH / 2; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + off]);
         __syncthreads();
     }
@@ -52,11 +55,12 @@ __device__ inline double block_min(double v, double* sh)
     __syncthreads();
     return r;
 }
+template <int NTH = TB>
 __device__ inline double block_max(double v, double* sh)
 {
     sh[threadIdx.x] = v;
     __syncthreads();
-    for (int off = TB / 2; off > 0; off >>= 1) {
+    for (int off = NTH / 2; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
         __syncthreads();
     }
@@ -512,6 +516,7 @@ __global__ __launch_bounds__(TB) void k_datareduct_fps(const double* __restrict_
 constexpr int ILCAP = 640;  // interaction-list entries staged per node
 constexpr int YCAP = 768;   // Y_p^* points staged per node
 constexpr int PB = 8;       // candidate loads issued ahead
+constexpr int NCO = 9;      // child offsets per node in the grouped copy of X_i^* (2^d + 1)
 
 __device__ __forceinline__ int seg_of(const int* __restrict__ off, int n, int p)
 {
@@ -527,16 +532,17 @@ __device__ __forceinline__ int seg_of(const int* __restrict__ off, int n, int p)
     return lo;
 }
 
-template <int D, int MAXQ>
-__global__ __launch_bounds__(TB) void k_datareduct_down(
+template <int D, int MAXQ, int NTH>
+__global__ __launch_bounds__(NTH) void k_datareduct_down(
     int lo_node, const double* __restrict__ pts, int64_t ld, const int* __restrict__ parent,
     const int* __restrict__ il_ptr, const int* __restrict__ il_col, const double* __restrict__ center,
     const double* __restrict__ side, const int* __restrict__ xs_cnt, const int* __restrict__ xs_idx,
-    const double* __restrict__ xs_pts, int r1, int* __restrict__ ys_cnt, int* __restrict__ ys_idx, int ys_stride,
-    int k, int nl)
+    const double* __restrict__ xs_pts, const int* __restrict__ xs_pos, const int* __restrict__ xs_coff,
+    const int* __restrict__ nchild, const int* __restrict__ first_child, int r1, int* __restrict__ ys_cnt,
+    int* __restrict__ ys_idx, int ys_stride, int k, int nl)
 {
-    __shared__ double red[TB];
-    __shared__ int scan_sh[TB];
+    __shared__ double red[NTH];
+    __shared__ int scan_sh[NTH];
     // box table in FP32, rounded outward (centre to nearest, half side up by
     // the centre's rounding and one more ulp): every box it describes contains
     // the true box, so its distance stays a lower bound and the pruning exact
@@ -551,7 +557,7 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     __shared__ int pick_own[ALIAS ? 1 : MAXQ];
     long long* keys = ALIAS ? (long long*)&yc[0][0] : keys_own;
     int* pick = ALIAS ? (int*)((long long*)&yc[0][0] + MAXQ) : pick_own;
-    constexpr int QPT = MAXQ / TB;
+    constexpr int QPT = MAXQ / NTH;
     constexpr int d = D;
 
     // workgroup ids go round-robin over the 8 XCDs: each XCD takes a
@@ -569,7 +575,7 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     int* o = ys_idx + (int64_t)i * ys_stride;
 
     // interaction-list table and its exclusive prefix of counts
-    for (int e = threadIdx.x; e < ne; e += TB) {
+    for (int e = threadIdx.x; e < ne; e += NTH) {
         const int j = il_col[e0 + e];
         bj[e] = j;
         bcnt[e] = xs_cnt[j];
@@ -587,18 +593,18 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     }
     const bool stage_y = np_ <= YCAP;
     if (stage_y)
-        for (int q = threadIdx.x; q < np_; q += TB)
+        for (int q = threadIdx.x; q < np_; q += NTH)
             for (int a = 0; a < d; ++a) yc[a][q] = pts[a * ld + yp[q]];
     __syncthreads();
     {
         // block scan over ne <= ILCAP counts: each lane sums a run of entries
-        const int per = (ne + TB - 1) / TB;
+        const int per = (ne + NTH - 1) / NTH;
         const int q0 = threadIdx.x * per;
         int c = 0;
         for (int e = q0; e < min(ne, q0 + per); ++e) c += bcnt[e];
         scan_sh[threadIdx.x] = c;
         __syncthreads();
-        for (int off = 1; off < TB; off <<= 1) {
+        for (int off = 1; off < NTH; off <<= 1) {
             int a = (int)threadIdx.x >= off ? scan_sh[threadIdx.x - off] : 0;
             __syncthreads();
             scan_sh[threadIdx.x] += a;
@@ -609,7 +615,7 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
             boff[e] = w;
             w += bcnt[e];
         }
-        if (threadIdx.x == TB - 1) boff[ne] = scan_sh[TB - 1];
+        if (threadIdx.x == NTH - 1) boff[ne] = scan_sh[NTH - 1];
         __syncthreads();
     }
     const int Lil = boff[ne];
@@ -619,8 +625,8 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
         return;
     }
     if (L <= k) {
-        for (int q = threadIdx.x; q < np_; q += TB) o[q] = yp[q];
-        for (int q = threadIdx.x; q < Lil; q += TB) {
+        for (int q = threadIdx.x; q < np_; q += NTH) o[q] = yp[q];
+        for (int q = threadIdx.x; q < Lil; q += NTH) {
             const int e = seg_of(boff, ne, q);
             o[np_ + q] = xs_idx[(int64_t)bj[e] * r1 + (q - boff[e])];
         }
@@ -635,12 +641,12 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     if (np_ > 0) {
         for (int a = 0; a < d; ++a) {
             double mn = INFINITY, mx = -INFINITY;
-            for (int q = threadIdx.x; q < np_; q += TB) {
+            for (int q = threadIdx.x; q < np_; q += NTH) {
                 const double v = stage_y ? yc[a][q] : pts[a * ld + yp[q]];
                 mn = fmin(mn, v);
                 mx = fmax(mx, v);
             }
-            const double l0 = block_min(mn, red), h0 = block_max(mx, red);
+            const double l0 = block_min<NTH>(mn, red), h0 = block_max<NTH>(mx, red);
             if (threadIdx.x == 0) {
                 lo[nseg][a] = l0;
                 hi[nseg][a] = h0;
@@ -650,7 +656,7 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     }
     if (Lil > 0) {
         double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-        for (int q = threadIdx.x; q < Lil; q += TB) {
+        for (int q = threadIdx.x; q < Lil; q += NTH) {
             const int e = seg_of(boff, ne, q);
             const int id = xs_idx[(int64_t)bj[e] * r1 + (q - boff[e])];
             for (int a = 0; a < d; ++a) {
@@ -660,7 +666,7 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
             }
         }
         for (int a = 0; a < d; ++a) {
-            const double l0 = block_min(mn[a], red), h0 = block_max(mx[a], red);
+            const double l0 = block_min<NTH>(mn[a], red), h0 = block_max<NTH>(mx[a], red);
             if (threadIdx.x == 0) {
                 lo[nseg][a] = l0;
                 hi[nseg][a] = h0;
@@ -681,7 +687,7 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     for (int a = 0; a < d; ++a) nq1 *= g;
     const int nq = nq1 * nseg;
 
-    // A lane's reference points (t = lane + TB u) go through every phase
+    // A lane's reference points (t = lane + NTH u) go through every phase
     // together, so each candidate and each box is read once per lane.
     double qv[QPT][D];
     double best[QPT];
@@ -689,7 +695,7 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     bool act[QPT];
 #pragma unroll
     for (int u = 0; u < QPT; ++u) {
-        const int t = threadIdx.x + u * TB;
+        const int t = threadIdx.x + u * NTH;
         act[u] = t < nq;
         const int tq = act[u] ? t : 0;
         const int sg = tq / nq1;
@@ -730,32 +736,39 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
         }
         return lb;
     };
-    // box e for the reference points in mask (bit u); X_j^* coordinates are
-    // read from their contiguous per-node copy
-    auto scan_box = [&](int e, unsigned mask) {
-        const int c = bcnt[e];
+    // grouped positions m0 .. m1 - 1 of box e for the reference points in
+    // mask (bit u); X_j^* coordinates are read from their contiguous per-node
+    // copy (grouped by child), each with its position in X_j^* (the grouped
+    // order of a leaf's X_j^* is its own: ID = true reads no positions)
+    auto scan_range = [&](auto id_order, int e, int m0, int m1, unsigned mask) {
+        constexpr bool ID = decltype(id_order)::value;
         const double* xj = xs_pts + (int64_t)bj[e] * D * r1;
+        const int* pj = xs_pos + (int64_t)bj[e] * r1;
         const int pos0 = np_ + boff[e];
-        int m = 0;
-        for (; m + PB <= c; m += PB) {
+        int m = m0;
+        for (; m + PB <= m1; m += PB) {
             double cx[PB][D];
+            int pz[PB];
 #pragma unroll
-            for (int z = 0; z < PB; ++z)
+            for (int z = 0; z < PB; ++z) {
 #pragma unroll
                 for (int a = 0; a < D; ++a) cx[z][a] = xj[a * r1 + m + z];
+                pz[z] = pos0 + (ID ? m + z : pj[m + z]);
+            }
 #pragma unroll
             for (int u = 0; u < QPT; ++u)
                 if (mask & (1u << u))
 #pragma unroll
-                    for (int z = 0; z < PB; ++z) consider(u, dist(u, cx[z]), pos0 + m + z);
+                    for (int z = 0; z < PB; ++z) consider(u, dist(u, cx[z]), pz[z]);
         }
-        for (; m < c; ++m) {
+        for (; m < m1; ++m) {
             double cx[D];
 #pragma unroll
             for (int a = 0; a < D; ++a) cx[a] = xj[a * r1 + m];
+            const int pz = pos0 + (ID ? m : pj[m]);
 #pragma unroll
             for (int u = 0; u < QPT; ++u)
-                if (mask & (1u << u)) consider(u, dist(u, cx), pos0 + m);
+                if (mask & (1u << u)) consider(u, dist(u, cx), pz);
         }
     };
     // Y_p^*
@@ -792,7 +805,8 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     }
 #pragma unroll
     for (int u = 0; u < QPT; ++u)
-        if (act[u] && e_first[u] >= 0 && lb_first[u] * (1.0 - 1e-12) <= best[u]) scan_box(e_first[u], 1u << u);
+        if (act[u] && e_first[u] >= 0 && lb_first[u] * (1.0 - 1e-12) <= best[u])
+            scan_range(std::false_type(), e_first[u], 0, bcnt[e_first[u]], 1u << u);
     for (int e = 0; e < ne; ++e) {
         double bc[D];
 #pragma unroll
@@ -802,13 +816,43 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
 #pragma unroll
         for (int u = 0; u < QPT; ++u)
             if (act[u] && e != e_first[u] && box_lb(u, bc, h) * (1.0 - 1e-12) <= best[u]) mask |= 1u << u;
-        if (mask) scan_box(e, mask);
+        if (!mask) continue;
+        // an admitted box is searched child by child: the points of X_j^* in
+        // child c lie in c's box (its half side padded by 1e-13 of its
+        // extent for the rounding of the tree's centres), whose distance
+        // bounds them from below in the same way
+        const int j = bj[e];
+        const int nc = nchild[j];
+        if (nc == 0) {
+            scan_range(std::true_type(), e, 0, bcnt[e], mask);
+            continue;
+        }
+        const int* co = xs_coff + (int64_t)j * NCO;
+        const int fc = first_child[j];
+        for (int kc = 0; kc < nc; ++kc) {
+            const int m0 = co[kc], m1 = co[kc + 1];
+            if (m0 == m1) continue;
+            double cc[D];
+            double cm = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                cc[a] = center[(int64_t)(fc + kc) * D + a];
+                cm = fmax(cm, fabs(cc[a]));
+            }
+            const double sc = side[fc + kc];
+            const double hc = 0.5 * sc + 1e-13 * (cm + sc);
+            unsigned cmask = 0;
+#pragma unroll
+            for (int u = 0; u < QPT; ++u)
+                if ((mask & (1u << u)) && box_lb(u, cc, hc) * (1.0 - 1e-12) <= best[u]) cmask |= 1u << u;
+            if (cmask) scan_range(std::false_type(), e, m0, m1, cmask);
+        }
     }
     __syncthreads();  // every lane is done with Y_p^* (keys and picks reuse it)
 #pragma unroll
     for (int u = 0; u < QPT; ++u) {
         if (!act[u]) continue;
-        const int t = threadIdx.x + u * TB;
+        const int t = threadIdx.x + u * NTH;
         int bidx;
         if (bpos[u] < np_) {
             bidx = yp[bpos[u]];
@@ -822,11 +866,11 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     }
     int P = 1;
     while (P < nq) P <<= 1;
-    for (int t = nq + threadIdx.x; t < P; t += TB) keys[t] = 0x7fffffffffffffffLL;
+    for (int t = nq + threadIdx.x; t < P; t += NTH) keys[t] = 0x7fffffffffffffffLL;
     __syncthreads();
     for (int kk = 2; kk <= P; kk <<= 1)
         for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            for (int x = threadIdx.x; x < P; x += TB) {
+            for (int x = threadIdx.x; x < P; x += NTH) {
                 int y = x ^ jj;
                 if (y > x) {
                     bool up = (x & kk) == 0;
@@ -839,19 +883,19 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
             }
             __syncthreads();
         }
-    for (int x = threadIdx.x; x < nq; x += TB) {
+    for (int x = threadIdx.x; x < nq; x += NTH) {
         bool first = x == 0 || (keys[x - 1] >> 13) != (keys[x] >> 13);
         int t = (int)(keys[x] & 8191);
         if (!first) pick[t] = -1;
     }
     __syncthreads();
-    const int per = (nq + TB - 1) / TB;
+    const int per = (nq + NTH - 1) / NTH;
     const int t0 = threadIdx.x * per;
     int c = 0;
     for (int t = t0; t < min(nq, t0 + per); ++t) c += pick[t] >= 0;
     scan_sh[threadIdx.x] = c;
     __syncthreads();
-    for (int off = 1; off < TB; off <<= 1) {
+    for (int off = 1; off < NTH; off <<= 1) {
         int a = (int)threadIdx.x >= off ? scan_sh[threadIdx.x - off] : 0;
         __syncthreads();
         scan_sh[threadIdx.x] += a;
@@ -860,7 +904,7 @@ __global__ __launch_bounds__(TB) void k_datareduct_down(
     int w = scan_sh[threadIdx.x] - c;
     for (int t = t0; t < min(nq, t0 + per); ++t)
         if (pick[t] >= 0) o[w++] = pick[t];
-    if (threadIdx.x == TB - 1) ys_cnt[i] = scan_sh[TB - 1];
+    if (threadIdx.x == NTH - 1) ys_cnt[i] = scan_sh[NTH - 1];
 }
 
 // ---- T_i = Y_p^* ++ X_j^* (j in IL(i)) materialised for the nodes with long
@@ -949,28 +993,48 @@ __global__ __launch_bounds__(TB) void k_up_fill(int lo, const int* __restrict__ 
     }
 }
 
-template <int D>
-void launch_down_d(Handle& h, int lo, int nl, const double* xs_pts, hipStream_t s)
+// Levels with few nodes run 1024 lanes per node (one reference point per
+// lane): the 4x more wavefronts hide the latency of the searches where a
+// level has too few nodes to fill the CUs.  The result does not depend on
+// the workgroup size.
+constexpr int DOWN_NODES_WIDE = 2048;
+
+// the grouped copy of every node's X_i^* (k_xs_grouped)
+struct XsGrouped {
+    const double* pts;
+    const int* pos;
+    const int* coff;
+};
+
+template <int D, int MAXQ, int NTH>
+void launch_down_k(Handle& h, int lo, int nl, const XsGrouped& xg, hipStream_t s)
 {
     const unsigned grid = 8u * (unsigned)((nl + 7) / 8);
-    if (h.r2 <= 1024)
-        k_datareduct_down<D, 1024><<<grid, TB, 0, s>>>(lo, h.pts.p, h.n, h.parent.p, h.il_ptr.p, h.il_col.p,
-                                                       h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, xs_pts, h.r1,
-                                                       h.ys_cnt.p, h.ys_idx.p, h.ys_stride, h.r2, nl);
-    else
-        k_datareduct_down<D, MAXQ_ALL><<<grid, TB, 0, s>>>(lo, h.pts.p, h.n, h.parent.p, h.il_ptr.p, h.il_col.p,
-                                                           h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, xs_pts,
-                                                           h.r1, h.ys_cnt.p, h.ys_idx.p, h.ys_stride, h.r2, nl);
+    k_datareduct_down<D, MAXQ, NTH><<<grid, NTH, 0, s>>>(lo, h.pts.p, h.n, h.parent.p, h.il_ptr.p, h.il_col.p,
+                                                         h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, xg.pts,
+                                                         xg.pos, xg.coff, h.nchild.p, h.first_child.p, h.r1,
+                                                         h.ys_cnt.p, h.ys_idx.p, h.ys_stride, h.r2, nl);
 }
 
-void launch_down(Handle& h, int lo, int nl, const double* xs_pts, hipStream_t s)
+template <int D>
+void launch_down_d(Handle& h, int lo, int nl, const XsGrouped& xg, hipStream_t s)
+{
+    if (h.r2 > 1024)
+        launch_down_k<D, MAXQ_ALL, TB>(h, lo, nl, xg, s);
+    else if (nl < DOWN_NODES_WIDE)
+        launch_down_k<D, 1024, 1024>(h, lo, nl, xg, s);
+    else
+        launch_down_k<D, 1024, TB>(h, lo, nl, xg, s);
+}
+
+void launch_down(Handle& h, int lo, int nl, const XsGrouped& xg, hipStream_t s)
 {
     if (h.d == 1)
-        launch_down_d<1>(h, lo, nl, xs_pts, s);
+        launch_down_d<1>(h, lo, nl, xg, s);
     else if (h.d == 2)
-        launch_down_d<2>(h, lo, nl, xs_pts, s);
+        launch_down_d<2>(h, lo, nl, xg, s);
     else
-        launch_down_d<3>(h, lo, nl, xs_pts, s);
+        launch_down_d<3>(h, lo, nl, xg, s);
 }
 
 // |T_i| for the nodes the top-down kernel reduces (interaction lists of at
@@ -997,17 +1061,57 @@ __global__ __launch_bounds__(TB) void k_down_len(int nn, const int* __restrict__
     evals[i] = l > k ? l * nseg * gd : 0;
 }
 
-// Coordinates of every node's X_i^* in a contiguous copy,
-// xs_pts[(i * d + a) * r1 + m] = coordinate a of point xs_idx[i * r1 + m].
-__global__ __launch_bounds__(TB) void k_xs_coords(const double* __restrict__ pts, int64_t ld, int d,
-                                                  const int* __restrict__ xs_cnt, const int* __restrict__ xs_idx,
-                                                  int r1, double* __restrict__ xs_pts)
+// Coordinates of every node's X_i^* in a contiguous copy grouped by the child
+// of i whose point range holds each point (a leaf: one group), in order of
+// position within a group: xs_pts[(i * d + a) * r1 + m'] is coordinate a of
+// the point at grouped position m', xs_pos[i * r1 + m'] its position in
+// X_i^*, and grouped positions xs_coff[i * NCO + k] .. xs_coff[i * NCO + k + 1]
+// - 1 belong to child k.
+__global__ __launch_bounds__(TB) void k_xs_grouped(const double* __restrict__ pts, int64_t ld, int d,
+                                                   const int* __restrict__ xs_cnt, const int* __restrict__ xs_idx,
+                                                   int r1, const int* __restrict__ nchild,
+                                                   const int* __restrict__ first_child, const int* __restrict__ start,
+                                                   const int* __restrict__ count, double* __restrict__ xs_pts,
+                                                   int* __restrict__ xs_pos, int* __restrict__ xs_coff)
 {
+    __shared__ unsigned char grp[MAXR1];
+    __shared__ int gcnt[NCO];
     const int i = blockIdx.x;
     const int c = xs_cnt[i];
+    const int nc = nchild[i], fc = first_child[i];
+    const int ng = nc > 0 ? nc : 1;
     for (int m = threadIdx.x; m < c; m += TB) {
+        int g = 0;
+        if (nc > 0) {
+            const int id = xs_idx[(int64_t)i * r1 + m];
+            for (int k = 0; k < nc; ++k)
+                if (id >= start[fc + k] && id < start[fc + k] + count[fc + k]) g = k;
+        }
+        grp[m] = (unsigned char)g;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < ng) {
+        int w = 0;
+        for (int m = 0; m < c; ++m) w += grp[m] == (int)threadIdx.x;
+        gcnt[threadIdx.x] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int w = 0;
+        for (int k = 0; k < ng; ++k) {
+            xs_coff[(int64_t)i * NCO + k] = w;
+            w += gcnt[k];
+        }
+        xs_coff[(int64_t)i * NCO + ng] = w;
+    }
+    for (int m = threadIdx.x; m < c; m += TB) {
+        const int g = grp[m];
+        int w = 0;
+        for (int k = 0; k < g; ++k) w += gcnt[k];
+        for (int q = 0; q < m; ++q) w += grp[q] == g;
         const int id = xs_idx[(int64_t)i * r1 + m];
-        for (int a = 0; a < d; ++a) xs_pts[((int64_t)i * d + a) * r1 + m] = pts[a * ld + id];
+        xs_pos[(int64_t)i * r1 + w] = m;
+        for (int a = 0; a < d; ++a) xs_pts[((int64_t)i * d + a) * r1 + w] = pts[a * ld + id];
     }
 }
 
@@ -1119,8 +1223,13 @@ void run_hidr(Handle& h)
     }
     if (h.r2 < 2 || h.r2 > MAXQ_ALL) fail(H2_EUNSUPPORTED, "r2 must be in [2, 4096]");
     DBuf<double> xs_pts;
+    DBuf<int> xs_pos, xs_coff;
     xs_pts.ensure((size_t)nn * h.d * h.r1, s);
-    k_xs_coords<<<nn, TB, 0, s>>>(h.pts.p, h.n, h.d, h.xs_cnt.p, h.xs_idx.p, h.r1, xs_pts.p);
+    xs_pos.ensure((size_t)nn * h.r1, s);
+    xs_coff.ensure((size_t)nn * NCO, s);
+    k_xs_grouped<<<nn, TB, 0, s>>>(h.pts.p, h.n, h.d, h.xs_cnt.p, h.xs_idx.p, h.r1, h.nchild.p, h.first_child.p,
+                                   h.start.p, h.count.p, xs_pts.p, xs_pos.p, xs_coff.p);
+    const XsGrouped xg{xs_pts.p, xs_pos.p, xs_coff.p};
     H2_LAUNCH_CHECK();
     DBuf<int> lnodes, split, tmp, tmp_cnt;
     std::vector<hipEvent_t> ev;  // around each level's launch (profile)
@@ -1133,7 +1242,7 @@ void run_hidr(Handle& h)
         if (h.profile) H2_HIP(hipEventRecord(ev[2 * L], s));
         // the box-pruned kernel serves the volume method; the other methods
         // reduce every node's materialised T_i
-        if (h.dr == H2_DR_VOLUME) launch_down(h, lo, nl, xs_pts.p, s);
+        if (h.dr == H2_DR_VOLUME) launch_down(h, lo, nl, xg, s);
         if (h.profile) H2_HIP(hipEventRecord(ev[2 * L + 1], s));
         H2_LAUNCH_CHECK();
         std::vector<int> longn;
