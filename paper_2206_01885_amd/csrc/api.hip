@@ -278,7 +278,10 @@ h2_status h2_build_batched(int nprob, const double* const* points, const int64_t
     try {
         const hipStream_t us = (hipStream_t)hip_stream;
         std::vector<h2::Handle*> hv(nprob);
-        for (int p = 0; p < nprob; ++p) hv[p] = &hs[p]->h;
+        for (int p = 0; p < nprob; ++p) {
+            hv[p] = &hs[p]->h;
+            hv[p]->down_wide_nodes = 0;
+        }
         // the per-problem steps (many small launches and read-backs each) run
         // concurrently: problem p on worker p % W, each worker with its own
         // stream, ordered after the caller's stream; the shared steps run on

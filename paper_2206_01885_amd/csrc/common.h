@@ -173,6 +173,10 @@ struct Handle {
     int precision = 64;
     int store_coupling = 1;
     uint64_t calib_seed = 0x5EED;
+    // top-down DataReduct: levels with fewer nodes than this take 1024 lanes
+    // per node (a build alone); 0 in a batched build, whose problems fill
+    // the device together
+    int down_wide_nodes = 2048;
     hipStream_t stream = nullptr;
 
     // tree: nodes in BFS order (depth, parent, child code)

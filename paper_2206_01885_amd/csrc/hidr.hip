@@ -517,6 +517,7 @@ constexpr int ILCAP = 640;  // interaction-list entries staged per node
 constexpr int YCAP = 768;   // Y_p^* points staged per node
 constexpr int PB = 8;       // candidate loads issued ahead
 constexpr int NCO = 9;      // child offsets per node in the grouped copy of X_i^* (2^d + 1)
+constexpr int SPLIT_MIN = 64;  // boxes with more candidates are searched child by child
 
 __device__ __forceinline__ int seg_of(const int* __restrict__ off, int n, int p)
 {
@@ -817,14 +818,19 @@ __global__ __launch_bounds__(NTH) void k_datareduct_down(
         for (int u = 0; u < QPT; ++u)
             if (act[u] && e != e_first[u] && box_lb(u, bc, h) * (1.0 - 1e-12) <= best[u]) mask |= 1u << u;
         if (!mask) continue;
-        // an admitted box is searched child by child: the points of X_j^* in
-        // child c lie in c's box (its half side padded by 1e-13 of its
-        // extent for the rounding of the tree's centres), whose distance
-        // bounds them from below in the same way
+        // an admitted box with more than SPLIT_MIN candidates is searched
+        // child by child: the points of X_j^* in child c lie in c's box (its
+        // half side padded by 1e-13 of its extent for the rounding of the
+        // tree's centres), whose distance bounds them from below in the same
+        // way
         const int j = bj[e];
         const int nc = nchild[j];
         if (nc == 0) {
             scan_range(std::true_type(), e, 0, bcnt[e], mask);
+            continue;
+        }
+        if (bcnt[e] <= SPLIT_MIN) {
+            scan_range(std::false_type(), e, 0, bcnt[e], mask);
             continue;
         }
         const int* co = xs_coff + (int64_t)j * NCO;
@@ -993,11 +999,10 @@ __global__ __launch_bounds__(TB) void k_up_fill(int lo, const int* __restrict__ 
     }
 }
 
-// Levels with few nodes run 1024 lanes per node (one reference point per
-// lane): the 4x more wavefronts hide the latency of the searches where a
-// level has too few nodes to fill the CUs.  The result does not depend on
-// the workgroup size.
-constexpr int DOWN_NODES_WIDE = 2048;
+// Levels with fewer than h.down_wide_nodes nodes run 1024 lanes per node (one
+// reference point per lane): the 4x more wavefronts hide the latency of the
+// searches where a level has too few nodes to fill the CUs.  The result does
+// not depend on the workgroup size.
 
 // the grouped copy of every node's X_i^* (k_xs_grouped)
 struct XsGrouped {
@@ -1021,7 +1026,7 @@ void launch_down_d(Handle& h, int lo, int nl, const XsGrouped& xg, hipStream_t s
 {
     if (h.r2 > 1024)
         launch_down_k<D, MAXQ_ALL, TB>(h, lo, nl, xg, s);
-    else if (nl < DOWN_NODES_WIDE)
+    else if (nl < h.down_wide_nodes)
         launch_down_k<D, 1024, 1024>(h, lo, nl, xg, s);
     else
         launch_down_k<D, 1024, TB>(h, lo, nl, xg, s);
