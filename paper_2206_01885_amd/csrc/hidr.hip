@@ -508,6 +508,8 @@ __global__ __launch_bounds__(TB) void k_datareduct_fps(const double* __restrict_
 // sequential scan's answer -- smallest distance, earliest position among
 // equal ones -- whatever the scan order; the box nearest to q is scanned
 // first so that the bound prunes well.
+// The staged Y_p^* is searched the same way, by runs of YCH points with
+// their bounding boxes, after the nearest box has set a first bound.
 // The interaction-list table (box centre, half side, count, list offset) and
 // (up to YCAP points) the coordinates of Y_p^* are staged in LDS; nodes with
 // more than ILCAP interaction-list entries are skipped here and reduced from
@@ -518,6 +520,7 @@ constexpr int YCAP = 768;   // Y_p^* points staged per node
 constexpr int PB = 8;       // candidate loads issued ahead
 constexpr int NCO = 9;      // child offsets per node in the grouped copy of X_i^* (2^d + 1)
 constexpr int SPLIT_MIN = 64;  // boxes with more candidates are searched child by child
+constexpr int YCH = 16;        // staged Y_p^* points per bounding box of the search
 
 __device__ __forceinline__ int seg_of(const int* __restrict__ off, int n, int p)
 {
@@ -597,6 +600,23 @@ __global__ __launch_bounds__(NTH) void k_datareduct_down(
         for (int q = threadIdx.x; q < np_; q += NTH)
             for (int a = 0; a < d; ++a) yc[a][q] = pts[a * ld + yp[q]];
     __syncthreads();
+    // bounding boxes of the staged Y_p^* in runs of YCH points, in FP32
+    // rounded outward (they contain every point of their run)
+    __shared__ float ylo[3][YCAP / YCH], yhi[3][YCAP / YCH];
+    const int nych = stage_y ? (np_ + YCH - 1) / YCH : 0;
+    for (int w = threadIdx.x; w < nych * D; w += NTH) {
+        const int ch = w / D, a = w - ch * D;
+        double mn = INFINITY, mx = -INFINITY;
+        for (int q = ch * YCH; q < min(np_, ch * YCH + YCH); ++q) {
+            mn = fmin(mn, yc[a][q]);
+            mx = fmax(mx, yc[a][q]);
+        }
+        float fl = (float)mn, fh = (float)mx;
+        if ((double)fl > mn) fl = nextafterf(fl, -INFINITY);
+        if ((double)fh < mx) fh = nextafterf(fh, INFINITY);
+        ylo[a][ch] = fl;
+        yhi[a][ch] = fh;
+    }
     {
         // block scan over ne <= ILCAP counts: each lane sums a run of entries
         const int per = (ne + NTH - 1) / NTH;
@@ -772,15 +792,6 @@ __global__ __launch_bounds__(NTH) void k_datareduct_down(
                 if (mask & (1u << u)) consider(u, dist(u, cx), pz);
         }
     };
-    // Y_p^*
-    for (int c = 0; c < np_; ++c) {
-        double cy[D];
-#pragma unroll
-        for (int a = 0; a < D; ++a) cy[a] = stage_y ? yc[a][c] : pts[a * ld + yp[c]];
-#pragma unroll
-        for (int u = 0; u < QPT; ++u)
-            if (act[u]) consider(u, dist(u, cy), c);
-    }
     // each reference point's nearest box first (it prunes best), then every
     // box its bound admits
     int e_first[QPT];
@@ -808,6 +819,39 @@ __global__ __launch_bounds__(NTH) void k_datareduct_down(
     for (int u = 0; u < QPT; ++u)
         if (act[u] && e_first[u] >= 0 && lb_first[u] * (1.0 - 1e-12) <= best[u])
             scan_range(std::false_type(), e_first[u], 0, bcnt[e_first[u]], 1u << u);
+    // Y_p^*, run by run where staged (a run whose box bound exceeds a
+    // reference point's best distance cannot hold its nearest point)
+    auto scan_y = [&](int c0, int c1, unsigned mask) {
+        for (int c = c0; c < c1; ++c) {
+            double cy[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) cy[a] = stage_y ? yc[a][c] : pts[a * ld + yp[c]];
+#pragma unroll
+            for (int u = 0; u < QPT; ++u)
+                if (mask & (1u << u)) consider(u, dist(u, cy), c);
+        }
+    };
+    if (!stage_y) {
+        unsigned am = 0;
+#pragma unroll
+        for (int u = 0; u < QPT; ++u)
+            if (act[u]) am |= 1u << u;
+        scan_y(0, np_, am);
+    }
+    for (int ch = 0; ch < nych; ++ch) {
+        unsigned mask = 0;
+#pragma unroll
+        for (int u = 0; u < QPT; ++u) {
+            double lb = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const double ex = fmax((double)ylo[a][ch] - qv[u][a], qv[u][a] - (double)yhi[a][ch]);
+                if (ex > 0.0) lb = lb + ex * ex;
+            }
+            if (act[u] && lb * (1.0 - 1e-12) <= best[u]) mask |= 1u << u;
+        }
+        if (mask) scan_y(ch * YCH, min(np_, ch * YCH + YCH), mask);
+    }
     for (int e = 0; e < ne; ++e) {
         double bc[D];
 #pragma unroll
