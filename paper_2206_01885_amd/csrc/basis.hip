@@ -22,6 +22,8 @@
 // whenever the kernel entries do.  Compiled with -ffp-contract=off.
 #include <type_traits>
 
+#include <algorithm>
+
 #include "common.h"
 #include "kappa.h"
 
@@ -1215,21 +1217,47 @@ void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdPro
                 for (int b = NBIN - 1; b >= 0 && need <= BIN_CAP[b]; --b) bin[p] = b;
         }
     }
+    // A bin of fewer than BIN_MIN tasks joins the next smaller non-empty bin
+    // (whose launch then reserves the larger need): a launch of a few
+    // workgroups lasts a whole task, which the larger launch hides.  A launch
+    // starts its tasks of the largest bins first.
+    constexpr int BIN_MIN = 256;
+    std::vector<int> bin0(bin);
+    {
+        int nb[NBIN] = {};
+        for (int p = 0; p < np; ++p)
+            if (bin[p] >= 0) ++nb[bin[p]];
+        for (int b = NBIN - 1; b > 0; --b) {
+            if (nb[b] == 0 || nb[b] >= BIN_MIN) continue;
+            int to = b - 1;
+            while (to >= 0 && nb[to] == 0) --to;
+            if (to < 0) break;
+            for (int p = 0; p < np; ++p)
+                if (bin[p] == b) bin[p] = to;
+            nb[to] += nb[b];
+            nb[b] = 0;
+        }
+    }
     // narrow classes first (the LDS bins, then the global one), then the
     // wide ones (timed together)
     std::vector<int> order;
     order.reserve(np);
     int bcnt[NBIN] = {}, boff[NBIN] = {};
     size_t blds[NBIN] = {};
-    for (int b = 0; b < NBIN; ++b) {
-        boff[b] = (int)order.size();
-        blds[b] = 8;
+    {
+        std::vector<int> nar;
         for (int p = 0; p < np; ++p)
-            if (bin[p] == b) {
-                order.push_back(p);
-                ++bcnt[b];
-                blds[b] = std::max(blds[b], lds_need(tasks[p], 0));
-            }
+            if (bin[p] >= 0) nar.push_back(p);
+        std::stable_sort(nar.begin(), nar.end(),
+                         [&](int x, int y) { return bin[x] != bin[y] ? bin[x] < bin[y] : bin0[x] > bin0[y]; });
+        for (int b = 0; b < NBIN; ++b) blds[b] = 8;
+        for (int p : nar) {
+            const int b = bin[p];
+            if (bcnt[b] == 0) boff[b] = (int)order.size();
+            order.push_back(p);
+            ++bcnt[b];
+            blds[b] = std::max(blds[b], lds_need(tasks[p], 0));
+        }
     }
     const int ORD[4] = {1, 5, 4, 2};
     int cnt[6] = {0, 0, 0, 0, 0, 0}, off[6] = {0, 0, 0, 0, 0, 0};
