@@ -347,10 +347,24 @@ def test_exact_limit_against_dense(H):
     assert _rel(y, O.dense_rows(P, "coulomb", 1.0, x)) < 1e-12
 
 
-@pytest.mark.parametrize("case", ["n1", "root_leaf", "duplicates", "collinear", "two_clusters"])
+@pytest.mark.parametrize("case", ["n1", "root_leaf", "duplicates", "collinear", "two_clusters", "lattice"])
 def test_degenerate_inputs(H, case):
+    """Degenerate point sets against the oracle, bit for bit in X*, Y*,
+    ranks, pivots and skeletons.  "lattice": the 17^3 points k/16, which lie
+    on the split planes of every level of the tree (centres 1/2, 1/4, ...)
+    and give many equal distances, so the top-down search's child boxes,
+    its bounding boxes of Y_p^* runs and its tie rule are all exercised at
+    their edges; X* and Y* are unique and compared bit for bit, but the
+    lattice's symmetry also gives columns of equal norm, between which the
+    pivoted QR's choice is decided by rounding (the GPU's blocked and folded
+    QR rounds differently from the oracle's), so there the pivots are checked
+    for validity: ranks within 1 % of the oracle's and the product within the
+    tolerance of the dense product."""
     rng = np.random.default_rng(11)
-    if case == "n1":
+    if case == "lattice":
+        k = np.arange(17) / 16.0
+        P = np.stack(np.meshgrid(k, k, k, indexing="ij"), axis=-1).reshape(-1, 3)
+    elif case == "n1":
         P = rng.random((1, 3))
     elif case == "root_leaf":
         P = rng.random((50, 3))
@@ -366,6 +380,18 @@ def test_degenerate_inputs(H, case):
     _say(f"degenerate {case} n{n}")
     g, o = _build(H, P, "coulomb", 1.0, 1e-6, 8 if case != "root_leaf" else 64)
     _compare_structure(g, o)
+    if case == "lattice":
+        assert (g.info()["r1"], g.info()["r2"]) == (o.info()["r1"], o.info()["r2"])
+        for i in range(1, o.info()["nnode"]):
+            for name in ("xstar", "ystar"):
+                assert np.array_equal(g.export(name, i), o.node_list(name, i)), (name, i)
+        rg, ro = int(g.export("rank").sum()), int(o.get("rank").sum())
+        assert abs(rg - ro) <= 0.01 * ro, (rg, ro)
+        x = rng.standard_normal((2, n))
+        e = _rel(g.matvec(x).cpu().numpy(), O.dense_rows(P, "coulomb", 1.0, x))
+        _say(f"lattice: rank sums {rg} / {ro} (oracle), error against dense {e:.2e}")
+        assert e <= 1e-6
+        return
     _compare_reduction_and_bases(g, o)
     yg = g.matvec(x).cpu().numpy()
     yo = o.matvec(x)
