@@ -280,7 +280,9 @@ h2_status h2_build_batched(int nprob, const double* const* points, const int64_t
         std::vector<h2::Handle*> hv(nprob);
         for (int p = 0; p < nprob; ++p) {
             hv[p] = &hs[p]->h;
-            hv[p]->down_wide_nodes = 0;
+            // small problems fill the device together: their top-down
+            // DataReduct keeps 256 lanes per node at every level
+            if (n[p] < (int64_t)1 << 18) hv[p]->down_wide_nodes = 0;
         }
         // the per-problem steps (many small launches and read-backs each) run
         // concurrently: problem p on worker p % W, each worker with its own

@@ -174,8 +174,8 @@ struct Handle {
     int store_coupling = 1;
     uint64_t calib_seed = 0x5EED;
     // top-down DataReduct: levels with fewer nodes than this take 1024 lanes
-    // per node (a build alone); 0 in a batched build, whose problems fill
-    // the device together
+    // per node; 0 for the problems below 2^18 points of a batched build,
+    // which fill the device together
     int down_wide_nodes = 2048;
     hipStream_t stream = nullptr;
 
