@@ -90,6 +90,8 @@ __global__ __launch_bounds__(TB) void k_upward(int lo, int nrhs, int ld, const i
         int t = q / nrhs, r = q - t * nrhs;
         double acc = z[(int64_t)pv[t] * ld + r];
         const T* Tr = Ti + (int64_t)t * nr;
+        // unrolled so that the loads run ahead of the (in-order) sum
+#pragma unroll 8
         for (int u = 0; u < nr; ++u) acc += (double)Tr[u] * (double)z[(int64_t)pv[k + u] * ld + r];
         o[(int64_t)t * ld + r] = (T)acc;
     }
@@ -553,6 +555,7 @@ __device__ inline T u_times(int pos, int k, int nr, int r, int ld, const T* __re
     if (pos < k) return yhat[(int64_t)pos * ld + r];
     int u = pos - k;
     double acc = 0;
+#pragma unroll 8
     for (int t = 0; t < k; ++t) acc += (double)Ti[(int64_t)t * nr + u] * (double)yhat[(int64_t)t * ld + r];
     return (T)acc;
 }
