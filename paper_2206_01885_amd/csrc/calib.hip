@@ -19,9 +19,10 @@
 // maximum.
 //
 // Every step runs on the device: point generation, DataReduct, the batched
-// ID and the error reduction, for every candidate r of every set at once (one
-// launch of each, one read-back); each set then takes its first candidate
-// below the target, which is what trying them in turn would give.
+// ID and the error reduction, for every candidate r below the cap of every
+// set at once (one launch of each, one read-back), then for the cap only for
+// the sets none of those met; each set takes its first candidate below the
+// target, which is what trying them in turn would give.
 #include <map>
 #include <tuple>
 
@@ -220,10 +221,8 @@ static void calibrate_sets(int d, double tau, uint64_t seed, const std::vector<d
     upload_vec(dshell, shell, s);
     k_points<<<blocks_for(ld, TB), TB, 0, s>>>(nset, dsides.p, d, dshell.p, nb, seed, Z.p);
     H2_LAUNCH_CHECK();
-    // every candidate r = g^d (g = 1, 2, ... up to the cap) of every set in
-    // one round: task p is (set, g); the result of a set is its first
-    // candidate below the target, as if the candidates were tried in turn
-    std::vector<int> rs_of;  // candidate sizes
+    // candidate sizes r = g^d (g = 1, 2, ... up to the cap)
+    std::vector<int> rs_of;
     for (int g = 1;; ++g) {
         long long rr = 1;
         for (int a = 0; a < d; ++a) rr *= g;
@@ -231,78 +230,104 @@ static void calibrate_sets(int d, double tau, uint64_t seed, const std::vector<d
         if (rr >= cap) break;
     }
     const int ng = (int)rs_of.size();
-    const int np = nset * ng;
-    std::vector<int> sets(np);
-    std::vector<int64_t> y_off(np + 1, 0), mt_off(np + 1, 0);
-    for (int g = 0; g < ng; ++g)
-        for (int t = 0; t < nset; ++t) {
-            const int p = g * nset + t;  // tasks grouped by candidate size
-            sets[p] = t;
-            y_off[p + 1] = y_off[p] + rs_of[g];
-            mt_off[p + 1] = mt_off[p] + (int64_t)rs_of[g] * NZ;
-        }
-    DBuf<int> set_of, z2idx, z1idx, mm, ycnt, yidx, rank, piv, skel;
-    DBuf<int64_t> zoff, xoff, d_mt_off;
-    DBuf<double> M, nu, T, err, part;
-    upload_vec(set_of, sets, s);
-    upload_vec(d_mt_off, mt_off, s);
-    z2idx.ensure((size_t)np * NZ2, s);
-    z1idx.ensure((size_t)np * NZ, s);
-    zoff.ensure((size_t)np + 1, s);
-    xoff.ensure((size_t)np + 1, s);
-    mm.ensure(np, s);
-    k_lists<<<np, TB, 0, s>>>(np, set_of.p, zoff.p, z2idx.p, z1idx.p, xoff.p, mm.p);
-    H2_LAUNCH_CHECK();
-    ycnt.ensure(np, s);
-    yidx.ensure((size_t)y_off[np], s);
-    for (int g = 0; g < ng; ++g)  // |Y*| <= r <= the cap (512)
-        datareduct_lists(Z.p, ld, d, zoff.p + (int64_t)g * nset, z2idx.p, nullptr, nset, rs_of[g],
-                         yidx.p + y_off[(size_t)g * nset], rs_of[g], ycnt.p + (int64_t)g * nset, s);
-    M.ensure((size_t)mt_off[np], s);
-    nu.ensure((size_t)np * 3 * NZ, s);
-    T.ensure((size_t)mt_off[np], s);
-    rank.ensure(np, s);
-    piv.ensure((size_t)np * NZ, s);
-    skel.ensure((size_t)y_off[np], s);
-    err.ensure(np, s);
-    std::vector<int> ys_h = read_vec(ycnt.p, np, s);
-    std::vector<IdTask> tasks(np);
-    for (int p = 0; p < np; ++p) {
-        IdTask& t = tasks[p];
-        t.pts = Z.p;
-        t.ld = ld;
-        t.x_idx = z1idx.p + (int64_t)p * NZ;
-        t.y_idx = yidx.p + y_off[p];
-        t.M = M.p + mt_off[p];
-        t.nu = nu.p + (int64_t)p * 3 * NZ;
-        t.piv = piv.p + (int64_t)p * NZ;
-        t.T = T.p + mt_off[p];
-        t.skel = skel.p + y_off[p];
-        t.rank = rank.p + p;
-        t.prm = prms[sets[p]];
-        t.tol = 1e-3 * (0.5 * epss[sets[p]]);  // 1e-3 eps'
-        t.m = NZ;
-        t.s = ys_h[p];
-        t.d = d;
-        t.kid = kids[sets[p]];
-    }
-    batched_id(tasks, s);
-    part.ensure((size_t)np * ECB * 2, s);
-    k_err_part<<<np * ECB, TB, 0, s>>>(Z.p, ld, d, dkid.p, dprm.p, set_of.p, rank.p, piv.p, T.p, d_mt_off.p,
-                                       part.p);
-    H2_LAUNCH_CHECK();
-    k_err_final<<<blocks_for(np, 64), 64, 0, s>>>(np, part.p, err.p);
-    H2_LAUNCH_CHECK();
-    const std::vector<double> e = read_vec(err.p, np, s);
-    for (int t = 0; t < nset; ++t) {
-        result[t] = cap;
-        result_err[t] = e[(size_t)(ng - 1) * nset + t];
-        for (int g = 0; g < ng; ++g)
-            if (e[(size_t)g * nset + t] < 1e-2 * epss[t]) {
-                result[t] = rs_of[g];
-                result_err[t] = e[(size_t)g * nset + t];
-                break;
+    // The errors of candidates G (indices into rs_of) of sets S, all in one
+    // round: task p = (G[gi], S[si]), p = gi |S| + si (tasks grouped by
+    // candidate size); returns e[p].
+    auto run = [&](const std::vector<int>& G, const std::vector<int>& S) {
+        const int nS = (int)S.size(), np = (int)G.size() * nS;
+        std::vector<int> sets(np);
+        std::vector<int64_t> y_off(np + 1, 0), mt_off(np + 1, 0);
+        for (int gi = 0; gi < (int)G.size(); ++gi)
+            for (int si = 0; si < nS; ++si) {
+                const int p = gi * nS + si;
+                sets[p] = S[si];
+                y_off[p + 1] = y_off[p] + rs_of[G[gi]];
+                mt_off[p + 1] = mt_off[p] + (int64_t)rs_of[G[gi]] * NZ;
             }
+        DBuf<int> set_of, z2idx, z1idx, mm, ycnt, yidx, rank, piv, skel;
+        DBuf<int64_t> zoff, xoff, d_mt_off;
+        DBuf<double> M, nu, T, err, part;
+        upload_vec(set_of, sets, s);
+        upload_vec(d_mt_off, mt_off, s);
+        z2idx.ensure((size_t)np * NZ2, s);
+        z1idx.ensure((size_t)np * NZ, s);
+        zoff.ensure((size_t)np + 1, s);
+        xoff.ensure((size_t)np + 1, s);
+        mm.ensure(np, s);
+        k_lists<<<np, TB, 0, s>>>(np, set_of.p, zoff.p, z2idx.p, z1idx.p, xoff.p, mm.p);
+        H2_LAUNCH_CHECK();
+        ycnt.ensure(np, s);
+        yidx.ensure((size_t)y_off[np], s);
+        for (int gi = 0; gi < (int)G.size(); ++gi) {  // |Y*| <= r <= the cap (512)
+            const int r = rs_of[G[gi]];
+            datareduct_lists(Z.p, ld, d, zoff.p + (int64_t)gi * nS, z2idx.p, nullptr, nS, r,
+                             yidx.p + y_off[(size_t)gi * nS], r, ycnt.p + (int64_t)gi * nS, s);
+        }
+        M.ensure((size_t)mt_off[np], s);
+        nu.ensure((size_t)np * 3 * NZ, s);
+        T.ensure((size_t)mt_off[np], s);
+        rank.ensure(np, s);
+        piv.ensure((size_t)np * NZ, s);
+        skel.ensure((size_t)y_off[np], s);
+        err.ensure(np, s);
+        std::vector<int> ys_h = read_vec(ycnt.p, np, s);
+        std::vector<IdTask> tasks(np);
+        for (int p = 0; p < np; ++p) {
+            IdTask& t = tasks[p];
+            t.pts = Z.p;
+            t.ld = ld;
+            t.x_idx = z1idx.p + (int64_t)p * NZ;
+            t.y_idx = yidx.p + y_off[p];
+            t.M = M.p + mt_off[p];
+            t.nu = nu.p + (int64_t)p * 3 * NZ;
+            t.piv = piv.p + (int64_t)p * NZ;
+            t.T = T.p + mt_off[p];
+            t.skel = skel.p + y_off[p];
+            t.rank = rank.p + p;
+            t.prm = prms[sets[p]];
+            t.tol = 1e-3 * (0.5 * epss[sets[p]]);  // 1e-3 eps'
+            t.m = NZ;
+            t.s = ys_h[p];
+            t.d = d;
+            t.kid = kids[sets[p]];
+        }
+        batched_id(tasks, s);
+        part.ensure((size_t)np * ECB * 2, s);
+        k_err_part<<<np * ECB, TB, 0, s>>>(Z.p, ld, d, dkid.p, dprm.p, set_of.p, rank.p, piv.p, T.p, d_mt_off.p,
+                                           part.p);
+        H2_LAUNCH_CHECK();
+        k_err_final<<<blocks_for(np, 64), 64, 0, s>>>(np, part.p, err.p);
+        H2_LAUNCH_CHECK();
+        return read_vec(err.p, np, s);
+    };
+    // Each set takes its first candidate below the target, as if they were
+    // tried in turn.  The candidates below the cap run together; the cap (the
+    // largest and slowest ID) only for the sets none of them satisfied.
+    std::vector<int> all(nset), G1;
+    for (int t = 0; t < nset; ++t) all[t] = t;
+    for (int g = 0; g + 1 < ng; ++g) G1.push_back(g);
+    std::vector<int> rest;
+    if (!G1.empty()) {
+        const std::vector<double> e = run(G1, all);
+        for (int t = 0; t < nset; ++t) {
+            bool found = false;
+            for (int gi = 0; gi < (int)G1.size() && !found; ++gi)
+                if (e[(size_t)gi * nset + t] < 1e-2 * epss[t]) {
+                    result[t] = rs_of[G1[gi]];
+                    result_err[t] = e[(size_t)gi * nset + t];
+                    found = true;
+                }
+            if (!found) rest.push_back(t);
+        }
+    } else {
+        rest = all;
+    }
+    if (!rest.empty()) {
+        const std::vector<double> e = run({ng - 1}, rest);
+        for (size_t q = 0; q < rest.size(); ++q) {
+            result[rest[q]] = rs_of[ng - 1];  // the cap, met or not
+            result_err[rest[q]] = e[q];
+        }
     }
 }
 
