@@ -478,8 +478,8 @@ def bench_serving(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part "
-              "of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library runs on one GPU "
+              "and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         import torch

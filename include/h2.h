@@ -33,7 +33,7 @@ typedef enum {
     H2_EINVAL = -1,       /* invalid argument (sizes, tolerance, non-finite points, ...) */
     H2_ENOMEM = -2,       /* device memory exhausted */
     H2_EDEVICE = -3,      /* HIP runtime error */
-    H2_EUNSUPPORTED = -4, /* valid request outside what this build implements */
+    H2_EUNSUPPORTED = -4, /* valid request outside what the library implements */
     H2_EINTERNAL = -5     /* internal consistency check failed */
 } h2_status;
 
