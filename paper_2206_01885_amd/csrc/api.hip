@@ -187,12 +187,56 @@ h2_status h2_build_ex(const double* points, int64_t n, int dim, int kernel_id, c
         return st;
     }
     try {
-        build_tree_lists(h, points);
-        double t0 = now_s();
-        h2::run_calibration(h);
-        h.t_calib = now_s() - t0;
+        // The scale-invariant Coulomb kernel is calibrated at side 1 whatever
+        // the points: that calibration runs from a second host thread on a
+        // worker stream while the tree and the lists are built.
+        if (h.kid == H2_COULOMB && !(h.r1 > 0 && h.r2 > 0)) {
+            h2::Handle c;
+            c.d = h.d;
+            c.kid = h.kid;
+            c.prm = h.prm;
+            c.tol = h.tol;
+            c.tol_int = h.tol_int;
+            c.tau = h.tau;
+            c.r1 = h.r1;
+            c.r2 = h.r2;
+            c.r_min = h.r_min;
+            c.calib_seed = h.calib_seed;
+            int dev = 0;
+            H2_HIP(hipGetDevice(&dev));
+            std::exception_ptr cerr;
+            double tc = 0.0;
+            std::thread th([&]() {
+                try {
+                    H2_HIP(hipSetDevice(dev));
+                    const double t0 = now_s();
+                    h2::run_calibration_multi({&c}, worker_stream(0));
+                    tc = now_s() - t0;
+                } catch (...) {
+                    cerr = std::current_exception();
+                }
+            });
+            try {
+                build_tree_lists(h, points);
+            } catch (...) {
+                th.join();
+                throw;
+            }
+            th.join();
+            if (cerr) std::rethrow_exception(cerr);
+            h.calib_r.assign((size_t)h.maxdepth + 1, c.calib_r[0]);
+            h.calib_err.assign((size_t)h.maxdepth + 1, c.calib_err[0]);
+            h.r1 = c.r1;
+            h.r2 = c.r2;
+            h.t_calib = tc;
+        } else {
+            build_tree_lists(h, points);
+            double t0 = now_s();
+            h2::run_calibration(h);
+            h.t_calib = now_s() - t0;
+        }
         build_hidr(h);
-        t0 = now_s();
+        const double t0 = now_s();
         h2::build_bases(h);
         h.t_basis = now_s() - t0;
         build_back(h);
