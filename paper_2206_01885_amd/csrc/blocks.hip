@@ -161,21 +161,102 @@ __device__ __forceinline__ void blocks_eval_one(int lane, int ki, int kj, const 
     }
 }
 
+// Blocks with at most FLAT_MAX rows and columns: the row and column points
+// are staged in the wavefront's LDS slice sp ([2][3][FLAT_MAX]: rows, then
+// columns) and lane l forms entries l, l + 64, ... of the column-major block,
+// so that every store is 64 consecutive entries whatever k_i (the entries
+// and their arithmetic are those of blocks_eval_one).
+constexpr int FLAT_MAX = 128;
+template <class OutT, int FAM, int D, int KID>
+__device__ __forceinline__ void blocks_eval_flat(int lane, int ki, int kj, const double (*sp)[3][FLAT_MAX],
+                                                 double prm, OutT* __restrict__ o)
+{
+    const int64_t tot = (int64_t)ki * kj;
+    int t = lane % ki, u = lane / ki;
+    const int dt = 64 % ki, du = 64 / ki;
+    for (int64_t e0 = 0; e0 < tot; e0 += 64) {
+        if (e0 + lane < tot) {
+            double xi[3], sc[3];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                xi[a] = sp[0][a][t];
+                sc[a] = sp[1][a][u];
+            }
+            double r2 = 0.0, xy = 0.0;
+            if constexpr (FAM == FAM_COSINE) {
+                xy = xi[0] * sc[0];
+#pragma unroll
+                for (int a = 1; a < D; ++a) xy = __builtin_fma(xi[a], sc[a], xy);
+            } else {
+                const double a0 = sc[0] - xi[0];
+                r2 = a0 * a0;
+#pragma unroll
+                for (int a = 1; a < D; ++a) {
+                    const double aa = sc[a] - xi[a];
+                    r2 = __builtin_fma(aa, aa, r2);
+                }
+            }
+            o[e0 + lane] = kappa_store<OutT, FAM>(KID, prm, r2, xy, xi[0] - sc[0]);
+        }
+        t += dt;
+        u += du;
+        if (t >= ki) {
+            t -= ki;
+            ++u;
+        }
+    }
+}
+
 template <class OutT, int FAM, int D>
 __global__ __launch_bounds__(TB) void k_blocks_eval(int64_t nent, const int* __restrict__ erow,
                                                     const int* __restrict__ col, PtSet rs, PtSet cs, int kid,
                                                     double prm, const int64_t* __restrict__ off, int upper,
                                                     OutT* __restrict__ out)
 {
+    __shared__ double sp[TB / 64][2][3][FLAT_MAX];
     const int64_t e = (int64_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6);
-    if (e >= nent) return;
-    const int lane = threadIdx.x & 63;
-    const int i = erow[e], j = col[e];
-    if (upper && j < i) return;  // stored with the entry (j, i)
-    const int ki = rs.cnt[i], kj = cs.cnt[j];
-    if (ki == 0 || kj == 0) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    bool run = e < nent;
+    int i = 0, j = 0, ki = 0, kj = 0;
+    if (run) {
+        i = erow[e];
+        j = col[e];
+        if (upper && j < i) run = false;  // stored with the entry (j, i)
+    }
+    if (run) {
+        ki = rs.cnt[i];
+        kj = cs.cnt[j];
+        run = ki > 0 && kj > 0;
+    }
+    const int64_t bi = run ? rs.xo[i] : 0, bj = run ? cs.xo[j] : 0;
+    const bool flat = run && ki <= FLAT_MAX && kj <= FLAT_MAX;
+    if (flat) {
+        for (int q = lane; q < ki; q += 64)
+#pragma unroll
+            for (int a = 0; a < D; ++a) sp[wv][0][a][q] = rs.xs[a * rs.ld + bi + q];
+        for (int q = lane; q < kj; q += 64)
+#pragma unroll
+            for (int a = 0; a < D; ++a) sp[wv][1][a][q] = cs.xs[a * cs.ld + bj + q];
+    }
+    __syncthreads();  // every wavefront of the workgroup reaches it once
+    if (!run) return;
     OutT* o = out + off[e];
-    const int64_t bi = rs.xo[i], bj = cs.xo[j];
+    if (flat) {
+        if constexpr (FAM == FAM_RADIAL) {
+            switch (kid) {
+            case H2_COULOMB: blocks_eval_flat<OutT, FAM, D, H2_COULOMB>(lane, ki, kj, sp[wv], prm, o); break;
+            case H2_GAUSSIAN: blocks_eval_flat<OutT, FAM, D, H2_GAUSSIAN>(lane, ki, kj, sp[wv], prm, o); break;
+            case H2_EXPONENTIAL:
+                blocks_eval_flat<OutT, FAM, D, H2_EXPONENTIAL>(lane, ki, kj, sp[wv], prm, o);
+                break;
+            case H2_BUMP: blocks_eval_flat<OutT, FAM, D, H2_BUMP>(lane, ki, kj, sp[wv], prm, o); break;
+            default: blocks_eval_flat<OutT, FAM, D, H2_MATERN32>(lane, ki, kj, sp[wv], prm, o);
+            }
+        } else {
+            blocks_eval_flat<OutT, FAM, D, 0>(lane, ki, kj, sp[wv], prm, o);
+        }
+        return;
+    }
     if constexpr (FAM == FAM_RADIAL) {
         switch (kid) {
         case H2_COULOMB:
