@@ -187,6 +187,7 @@ struct Handle {
     DBuf<double> side;
     DBuf<double> pts;  // [d][n] SoA, tree order
     DBuf<int> perm;    // tree position -> original index
+    DBuf<int> iperm;   // original index -> tree position (the apply's gather and scatter)
     std::vector<int> h_nchild, h_first_child, h_start, h_count, h_parent;  // host mirrors (small)
 
     // lists (CSR, columns ascending)

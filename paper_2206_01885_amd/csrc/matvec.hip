@@ -45,26 +45,48 @@ __device__ __forceinline__ Vec<T, N> vload(const T* p)
     return r;
 }
 
+// Caller order (x, y: nrhs rows of n) <-> tree order (xt, yt: ld values per
+// point), through a tile of 64 consecutive caller-order points x 32 RHS in
+// LDS: a row of x / y is read / written as 64 contiguous values and a
+// point's RHS as one contiguous run; iperm[j] is the tree position of the
+// caller's point j.  Grid (ceil(n / 64), ceil(nrhs / 32)), TB threads.
 template <class T>
 __global__ __launch_bounds__(TB) void k_gather(const T* __restrict__ x, int64_t n, int nrhs, int ld,
-                                               const int* __restrict__ perm, T* __restrict__ xt)
+                                               const int* __restrict__ iperm, T* __restrict__ xt)
 {
-    int64_t q = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (q >= n * nrhs) return;
-    int64_t i = q / nrhs;
-    int r = (int)(q - i * nrhs);
-    xt[i * ld + r] = x[(int64_t)r * n + perm[i]];
+    __shared__ T tile[64][33];
+    const int64_t j0 = (int64_t)blockIdx.x * 64;
+    const int c0 = blockIdx.y * 32, nr = min(32, nrhs - c0);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (j0 + lane < n)
+        for (int r = wv; r < nr; r += TB / 64) tile[lane][r] = x[(int64_t)(c0 + r) * n + j0 + lane];
+    __syncthreads();
+    const int rr = threadIdx.x & 31;
+    for (int p = threadIdx.x >> 5; p < 64; p += TB / 32)
+        if (j0 + p < n && rr < nr) xt[(int64_t)iperm[j0 + p] * ld + c0 + rr] = tile[p][rr];
 }
 
 template <class T>
 __global__ __launch_bounds__(TB) void k_scatter(const T* __restrict__ yt, int64_t n, int nrhs, int ld,
-                                                const int* __restrict__ perm, T* __restrict__ y)
+                                                const int* __restrict__ iperm, T* __restrict__ y)
 {
-    int64_t q = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (q >= n * nrhs) return;
-    int64_t i = q / nrhs;
-    int r = (int)(q - i * nrhs);
-    y[(int64_t)r * n + perm[i]] = yt[i * ld + r];
+    __shared__ T tile[64][33];
+    const int64_t j0 = (int64_t)blockIdx.x * 64;
+    const int c0 = blockIdx.y * 32, nr = min(32, nrhs - c0);
+    const int rr = threadIdx.x & 31;
+    for (int p = threadIdx.x >> 5; p < 64; p += TB / 32)
+        if (j0 + p < n && rr < nr) tile[p][rr] = yt[(int64_t)iperm[j0 + p] * ld + c0 + rr];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (j0 + lane < n)
+        for (int r = wv; r < nr; r += TB / 64) y[(int64_t)(c0 + r) * n + j0 + lane] = tile[lane][r];
+}
+
+// Inverse of the tree permutation: iperm[perm[i]] = i.
+__global__ __launch_bounds__(TB) void k_invert_perm(int64_t n, const int* __restrict__ perm, int* __restrict__ iperm)
+{
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i < n) iperm[perm[i]] = (int)i;
 }
 
 // The interpolation sums (up to a few hundred terms) accumulate in FP64 in
@@ -725,7 +747,8 @@ void apply_t(Handle& h, const T* x, T* y, int nrhs, int ld, const ApplyWork<T>& 
     if (prof && !h.ev[0])
         for (auto& e : h.ev) H2_HIP(hipEventCreate(&e));
     mark(0);
-    k_gather<T><<<blocks_for(n * nrhs, TB), TB, 0, s>>>(x, n, nrhs, ld, h.perm.p, xt);
+    const dim3 tiles((unsigned)((n + 63) / 64), (unsigned)((nrhs + 31) / 32));
+    k_gather<T><<<tiles, TB, 0, s>>>(x, n, nrhs, ld, h.iperm.p, xt);
     H2_LAUNCH_CHECK();
     mark(1);
     for (int L = h.maxdepth; L >= 1; --L) {
@@ -784,7 +807,7 @@ void apply_t(Handle& h, const T* x, T* y, int nrhs, int ld, const ApplyWork<T>& 
     launch_sweep<T, sizeof(T) == 4>(h.nr, h.nr_ptr.p, h.nr_ptr.p + 1, h.count.p, h.D_off.p, AB::D(h), xt,
                                     h.start64.p, yt, ld, 1, zero, s);
     mark(5);
-    k_scatter<T><<<blocks_for(n * nrhs, TB), TB, 0, s>>>(yt, n, nrhs, ld, h.perm.p, y);
+    k_scatter<T><<<tiles, TB, 0, s>>>(yt, n, nrhs, ld, h.iperm.p, y);
     H2_LAUNCH_CHECK();
     mark(6);
     if (prof) {
@@ -897,6 +920,9 @@ void prepare_apply(Handle& h)
     std::vector<int64_t> st(h.h_start.begin(), h.h_start.end());
     h.start64.ensure(std::max<size_t>(st.size(), 1), s);
     H2_HIP(hipMemcpyAsync(h.start64.p, st.data(), st.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    h.iperm.ensure((size_t)std::max<int64_t>(h.n, 1), s);
+    k_invert_perm<<<blocks_for(h.n, TB), TB, 0, s>>>(h.n, h.perm.p, h.iperm.p);
+    H2_LAUNCH_CHECK();
     // coupling evaluated in the apply: (node, first row) of every 64-row
     // chunk of a node with a basis (zero yhat without IL)
     if (h.store_coupling == 0) {
