@@ -800,6 +800,9 @@ def main():
     copy_gbs = 5 * 2 * src.numel() * 8 / (time.perf_counter() - tc) / 1e9
     del src, dst
     out["hbm_copy_gbs"] = copy_gbs
+    # the launch parameters the library was built with (autotune.py)
+    from paper_2206_01885_amd import autotune
+    out["tuning"] = {"params": autotune.current(), "source": "paper_2206_01885_amd/tuning.json"}
     for key in ("roofline", "roofline_matvec"):
         if out[key]["unit"] == "GB/s":
             out[key]["frac_of_measured_copy"] = out[key]["achieved"] / copy_gbs

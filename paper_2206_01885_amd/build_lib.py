@@ -1,6 +1,7 @@
 """Build the HIP shared library libh2.so for gfx950 (in-tree)."""
 from __future__ import annotations
 
+import json
 import os
 import subprocess
 import sys
@@ -10,6 +11,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libh2.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# Launch parameters measured by autotune.py (csrc/tuning.h holds the
+# defaults and their meaning); absent file: the defaults.
+TUNING = os.path.join(HERE, "tuning.json")
+
+
+def tuning_params(path: str = TUNING) -> dict:
+    """The H2_TUNE_* values of tuning.json ({} when there is none)."""
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return {k: int(v) for k, v in json.load(f)["params"].items()}
 
 # Sources whose arithmetic must round exactly as written (geometry,
 # DataReduct, the ID and its calibration) are compiled without FMA
@@ -26,9 +38,9 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
           "-I" + os.path.join(HERE, "..", "include")]
 
 
-def _compile(src: str, outdir: str) -> str:
+def _compile(src: str, outdir: str, params: dict) -> str:
     obj = os.path.join(outdir, src.replace(".hip", ".o"))
-    flags = list(COMMON)
+    flags = list(COMMON) + [f"-D{k}={v}" for k, v in sorted(params.items())]
     flags.append("-ffp-contract=off" if src in EXACT else "-ffp-contract=fast")
     if src in MFMA_VGPR:
         flags += ["-mllvm", "-amdgpu-mfma-vgpr-form"]
@@ -40,16 +52,20 @@ def _compile(src: str, outdir: str) -> str:
     return obj
 
 
-def build(jobs: int = 8) -> str:
-    outdir = os.path.join(HERE, "_build")
+def build(jobs: int = 8, out: str = LIB, params: dict | None = None) -> str:
+    """Compile every source and link `out`; params: H2_TUNE_* values (default:
+    tuning.json)."""
+    if params is None:
+        params = tuning_params()
+    outdir = os.path.join(HERE, "_build", os.path.basename(out).replace(".so", ""))
     os.makedirs(outdir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, outdir), SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, outdir, params), SOURCES))
+    tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

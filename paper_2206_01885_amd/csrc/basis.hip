@@ -1221,7 +1221,7 @@ void batched_id_family(const std::vector<IdTask>& tasks_in, hipStream_t s, IdPro
     // (whose launch then reserves the larger need): a launch of a few
     // workgroups lasts a whole task, which the larger launch hides.  A launch
     // starts its tasks of the largest bins first.
-    constexpr int BIN_MIN = 256;
+    constexpr int BIN_MIN = H2_TUNE_BIN_MIN;
     std::vector<int> bin0(bin);
     {
         int nb[NBIN] = {};

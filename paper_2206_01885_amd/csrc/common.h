@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/h2.h"
+#include "tuning.h"
 
 namespace h2 {
 
@@ -176,7 +177,7 @@ struct Handle {
     // top-down DataReduct: levels with fewer nodes than this take 1024 lanes
     // per node; 0 for the problems below 2^18 points of a batched build,
     // which fill the device together
-    int down_wide_nodes = 2048;
+    int down_wide_nodes = H2_TUNE_DOWN_WIDE;
     hipStream_t stream = nullptr;
 
     // tree: nodes in BFS order (depth, parent, child code)

@@ -519,7 +519,7 @@ constexpr int ILCAP = 640;  // interaction-list entries staged per node
 constexpr int YCAP = 768;   // Y_p^* points staged per node
 constexpr int PB = 8;       // candidate loads issued ahead
 constexpr int NCO = 9;      // child offsets per node in the grouped copy of X_i^* (2^d + 1)
-constexpr int SPLIT_MIN = 64;  // boxes with more candidates are searched child by child
+constexpr int SPLIT_MIN = H2_TUNE_SPLIT_MIN;  // boxes with more candidates are searched child by child
 constexpr int YCH = 16;        // staged Y_p^* points per bounding box of the search
 
 __device__ __forceinline__ int seg_of(const int* __restrict__ off, int n, int p)

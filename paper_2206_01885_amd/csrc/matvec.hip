@@ -676,7 +676,7 @@ void launch_sweep_t_mt(const Handle::Sweep& w, const int* ek, const int64_t* ex,
 {
     const int nt = w.n[MT - 1];
     if (nt == 0) return;
-    constexpr int P = 3;  // blocks of 16 columns loaded ahead (2: 1.5 ms slower at n = 2^20, 4: 0.9 ms)
+    constexpr int P = H2_TUNE_SWEEP_T_P;  // blocks of 16 columns loaded ahead
     const unsigned grid = (unsigned)(8 * ((nt + 7) / 8));
     k_sweep_t<MT, T, COMP, P><<<grid, 64, 0, s>>>(nt, w.node[MT - 1].p, w.r0[MT - 1].p, ptr_b, ptr_e, ek, ex,
                                                   w.steps.p, krow, blk_off, blk, X, out_off, Y, ld / 32, ld, zero);

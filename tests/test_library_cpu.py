@@ -116,3 +116,26 @@ def test_rebuild_validation_without_device_work():
     assert L.h2_rebuild(dummy, 1, None, 1e-6) == h2.H2_EINVAL
     prm[0] = float("nan")
     assert L.h2_rebuild(dummy, 1, prm, 1e-6) == h2.H2_EINVAL
+
+
+def test_autotune_plan_and_tuning_file():
+    """The autotuner's one-at-a-time plan covers every candidate value once
+    around the base setting, and the committed tuning.json names only the
+    parameters that csrc/tuning.h defines."""
+    from paper_2206_01885_amd import autotune, build_lib
+    base = autotune.current()
+    plan = autotune.variants(base)
+    assert plan[0] == ("base", base)
+    names = [n for n, _ in plan[1:]]
+    assert len(names) == len(set(names))
+    for k, vals in autotune.CANDIDATES.items():
+        assert base[k] in vals
+        got = sorted(p[k] for n, p in plan[1:] if n.startswith(k + "="))
+        assert got == sorted(v for v in vals if v != base[k])
+        for n, p in plan[1:]:
+            if not n.startswith(k + "="):
+                assert p[k] == base[k]
+    header = open(os.path.join(os.path.dirname(build_lib.HERE), "paper_2206_01885_amd", "csrc", "tuning.h")).read()
+    for k, v in build_lib.tuning_params().items():
+        assert f"#define {k} " in header, k
+        assert v in autotune.CANDIDATES[k]
