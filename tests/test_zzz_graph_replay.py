@@ -1,7 +1,7 @@
 """h2_matvec_noalloc captured in a HIP graph and replayed, the use it exists
 for (a caller that cannot allocate, e.g. a serving loop under graph
-capture): the apply records only kernel launches (no memory set or copy
-nodes), and each of several replays, with new inputs and eager work on the
+capture): the apply records kernel launches and its completion event (no
+memory set or copy nodes), and each of several replays, with new inputs and eager work on the
 device between them, equals the eager h2_matvec of the same input bit for
 bit."""
 import sys
