@@ -31,7 +31,8 @@ typedef struct h2_handle_s *h2_handle;
 typedef enum {
     H2_OK = 0,
     H2_EINVAL = -1,       /* invalid argument (sizes, tolerance, non-finite points, ...) */
-    H2_ENOMEM = -2,       /* device memory exhausted */
+    H2_ENOMEM = -2,       /* device memory exhausted (H2_DEVICE_MEMORY_CAP=<bytes> in the
+                             environment caps what the library takes, to test this) */
     H2_EDEVICE = -3,      /* HIP runtime error */
     H2_EUNSUPPORTED = -4, /* valid request outside what the library implements */
     H2_EINTERNAL = -5     /* internal consistency check failed */

@@ -6,8 +6,13 @@
 // it was freed; reusing it on another stream makes that stream wait for the
 // event (no host synchronisation, no device-wide hipFree on the hot path).
 // When hipMalloc fails the cache is released (after each block's event) and
-// the allocation retried.
+// the allocation retried.  The environment variable H2_DEVICE_MEMORY_CAP
+// (bytes) caps what the library holds from hipMalloc, cache included: an
+// allocation beyond it fails as hipMalloc would (a test of the H2_ENOMEM
+// path).
+#include <cstdlib>
 #include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -28,6 +33,18 @@ struct Block {
 std::mutex g_mu;
 std::vector<Block> g_cache;
 std::vector<hipEvent_t> g_events;
+std::mutex g_raw_mu;
+size_t g_raw_bytes = 0;                       // held from hipMalloc
+std::unordered_map<void*, size_t> g_raw_size;  // its blocks (under a cap)
+
+size_t memory_cap()
+{
+    static const size_t cap = [] {
+        const char* v = std::getenv("H2_DEVICE_MEMORY_CAP");
+        return v ? (size_t)std::strtoull(v, nullptr, 10) : (size_t)0;
+    }();
+    return cap;
+}
 
 size_t class_bytes(size_t bytes)
 {
@@ -39,10 +56,17 @@ size_t class_bytes(size_t bytes)
 
 void* raw_alloc(size_t bytes)
 {
+    std::lock_guard<std::mutex> lk(g_raw_mu);
+    const size_t cap = memory_cap();
+    if (cap && g_raw_bytes + bytes > cap) return nullptr;
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return nullptr;
+    }
+    if (cap) {
+        g_raw_bytes += bytes;
+        g_raw_size[p] = bytes;
     }
     return p;
 }
@@ -132,6 +156,12 @@ void dev_cache_trim()
             g_events.push_back(b.ev);
         }
         (void)hipFree(b.p);
+        std::lock_guard<std::mutex> lk2(g_raw_mu);
+        auto it = g_raw_size.find(b.p);
+        if (it != g_raw_size.end()) {
+            g_raw_bytes -= it->second;
+            g_raw_size.erase(it);
+        }
     }
     (void)hipGetLastError();
     g_cache.clear();

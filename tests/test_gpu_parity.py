@@ -807,3 +807,39 @@ def test_batched_full_config_sampled(H):
     finally:
         for hb in hs:
             H.h2_destroy(hb)
+
+
+def test_device_memory_cap_gives_enomem(H):
+    """With H2_DEVICE_MEMORY_CAP set below what a build needs, h2_build
+    returns H2_ENOMEM (no fault, no partial handle), and the same process
+    then builds and applies a problem that fits, matching the oracle; run in
+    a process of its own so that the cap stays there."""
+    import os
+    import subprocess
+    code = r'''
+import sys, numpy as np, torch
+sys.path.insert(0, %r)
+from paper_2206_01885_amd import h2 as H
+from oracle import oracle as O
+rng = np.random.default_rng(8)
+P = rng.random((20000, 3))
+try:
+    H.H2Matrix(P, "coulomb", 1.0, 1e-6, 64)
+    print("no error")
+except H.H2Error as e:
+    print("status", e.status)
+Q = rng.random((400, 3))
+g = H.H2Matrix(Q, "coulomb", 1.0, 1e-6, 32, r1=27, r2=54)
+x = rng.standard_normal((1, 400))
+y = g.matvec(x).cpu().numpy()
+o = O.H2Oracle(Q, "coulomb", 1.0, tol=1e-6, leaf=32, r1=27, r2=54)
+print("rel", float(np.linalg.norm(y - o.matvec(x)) / np.linalg.norm(o.matvec(x))))
+''' % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, H2_DEVICE_MEMORY_CAP=str(24 << 20))
+    _say("device memory cap 24 MiB: a 20000-point build, then a 400-point one")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0, r.stderr[-3000:]
+    out = r.stdout.split("\n")
+    assert f"status {H.H2_ENOMEM}" in out, r.stdout
+    rel = float(next(l for l in out if l.startswith("rel")).split()[1])
+    assert rel <= 1e-10, rel
