@@ -543,7 +543,7 @@ __global__ __launch_bounds__(NTH) void k_datareduct_down(
     const double* __restrict__ side, const int* __restrict__ xs_cnt, const int* __restrict__ xs_idx,
     const double* __restrict__ xs_pts, const int* __restrict__ xs_pos, const int* __restrict__ xs_coff,
     const int* __restrict__ nchild, const int* __restrict__ first_child, int r1, int* __restrict__ ys_cnt,
-    int* __restrict__ ys_idx, int ys_stride, int k, int nl)
+    int* __restrict__ ys_idx, int ys_stride, int k, int nl, int method, const double* __restrict__ dirs, int mdir)
 {
     __shared__ double red[NTH];
     __shared__ int scan_sh[NTH];
@@ -706,6 +706,10 @@ __global__ __launch_bounds__(NTH) void k_datareduct_down(
     }
     int nq1 = 1;
     for (int a = 0; a < d; ++a) nq1 *= g;
+    // the surface method's reference set (k_datareduct's): per part, the
+    // points c + (gamma w) u_j on the ellipsoids gamma = 0.3, 0.6, 1.2
+    const bool surf = method == H2_DR_SURFACE;
+    if (surf) nq1 = min(kp, 3 * mdir);
     const int nq = nq1 * nseg;
 
     // A lane's reference points (t = lane + NTH u) go through every phase
@@ -721,12 +725,23 @@ __global__ __launch_bounds__(NTH) void k_datareduct_down(
         const int tq = act[u] ? t : 0;
         const int sg = tq / nq1;
         int rem = tq - sg * nq1;
+        if (surf) {
+            const int e = rem / mdir, j = rem % mdir;
+            const double gm = e == 0 ? 0.3 : (e == 1 ? 0.6 : 1.2);
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-            int ta = rem % g;
-            rem /= g;
-            double w = (double)(2 * ta + 1) / (double)(2 * g);
-            qv[u][a] = lo[sg][a] + (hi[sg][a] - lo[sg][a]) * w;
+            for (int a = 0; a < D; ++a) {
+                const double w = hi[sg][a] - lo[sg][a];
+                const double c = lo[sg][a] + 0.5 * w;
+                qv[u][a] = c + (gm * w) * dirs[j * D + a];
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                int ta = rem % g;
+                rem /= g;
+                double w = (double)(2 * ta + 1) / (double)(2 * g);
+                qv[u][a] = lo[sg][a] + (hi[sg][a] - lo[sg][a]) * w;
+            }
         }
         best[u] = INFINITY;
         bpos[u] = 0x7fffffff;
@@ -1053,6 +1068,8 @@ struct XsGrouped {
     const double* pts;
     const int* pos;
     const int* coff;
+    const double* dirs;  // the surface method's directions (mdir of them)
+    int mdir;
 };
 
 template <int D, int MAXQ, int NTH>
@@ -1062,7 +1079,8 @@ void launch_down_k(Handle& h, int lo, int nl, const XsGrouped& xg, hipStream_t s
     k_datareduct_down<D, MAXQ, NTH><<<grid, NTH, 0, s>>>(lo, h.pts.p, h.n, h.parent.p, h.il_ptr.p, h.il_col.p,
                                                          h.center.p, h.side.p, h.xs_cnt.p, h.xs_idx.p, xg.pts,
                                                          xg.pos, xg.coff, h.nchild.p, h.first_child.p, h.r1,
-                                                         h.ys_cnt.p, h.ys_idx.p, h.ys_stride, h.r2, nl);
+                                                         h.ys_cnt.p, h.ys_idx.p, h.ys_stride, h.r2, nl, h.dr, xg.dirs,
+                                                         xg.mdir);
 }
 
 template <int D>
@@ -1278,7 +1296,19 @@ void run_hidr(Handle& h)
     xs_coff.ensure((size_t)nn * NCO, s);
     k_xs_grouped<<<nn, TB, 0, s>>>(h.pts.p, h.n, h.d, h.xs_cnt.p, h.xs_idx.p, h.r1, h.nchild.p, h.first_child.p,
                                    h.start.p, h.count.p, xs_pts.p, xs_pos.p, xs_coff.p);
-    const XsGrouped xg{xs_pts.p, xs_pos.p, xs_coff.p};
+    // the surface method's directions, as datareduct_lists_method forms them
+    // for a two-part T_i
+    DBuf<double> dirs;
+    std::vector<double> dir_h;
+    int mdir = 0;
+    if (h.dr == H2_DR_SURFACE) {
+        mdir = std::max(1, std::max(1, h.r2 / 2) / 3);
+        if (h.d == 1) mdir = std::min(mdir, 2);
+        surface_dirs(h.d, mdir, dir_h);
+        dirs.ensure(dir_h.size(), s);
+        H2_HIP(hipMemcpyAsync(dirs.p, dir_h.data(), dir_h.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    const XsGrouped xg{xs_pts.p, xs_pos.p, xs_coff.p, dirs.p, mdir};
     H2_LAUNCH_CHECK();
     DBuf<int> lnodes, split, tmp, tmp_cnt;
     std::vector<hipEvent_t> ev;  // around each level's launch (profile)
@@ -1289,14 +1319,15 @@ void run_hidr(Handle& h)
     for (int L = 1; L <= h.maxdepth; ++L) {
         int lo = h.lvl_ptr[L], nl = h.lvl_ptr[L + 1] - lo;
         if (h.profile) H2_HIP(hipEventRecord(ev[2 * L], s));
-        // the box-pruned kernel serves the volume method; the other methods
-        // reduce every node's materialised T_i
-        if (h.dr == H2_DR_VOLUME) launch_down(h, lo, nl, xg, s);
+        // the box-pruned kernel serves the volume and surface methods; FPS
+        // reduces every node's materialised T_i
+        const bool pruned = h.dr == H2_DR_VOLUME || h.dr == H2_DR_SURFACE;
+        if (pruned) launch_down(h, lo, nl, xg, s);
         if (h.profile) H2_HIP(hipEventRecord(ev[2 * L + 1], s));
         H2_LAUNCH_CHECK();
         std::vector<int> longn;
         for (int i = lo; i < lo + nl; ++i)
-            if (h.dr != H2_DR_VOLUME || h.h_il_ptr[i + 1] - h.h_il_ptr[i] > ILCAP) longn.push_back(i);
+            if (!pruned || h.h_il_ptr[i + 1] - h.h_il_ptr[i] > ILCAP) longn.push_back(i);
         if (longn.empty()) continue;
         const int nlong = (int)longn.size();
         lnodes.ensure((size_t)nlong, s);
